@@ -1,0 +1,263 @@
+"""Plain CPU FP64 oracle for the ring-polymer BAOAB + PILE-L step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
+(``paper_2602_13553_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``pimd_oracle.c`` (plain C, ``-O2 -ffp-contract=off``);
+this module only marshals numpy arrays through ctypes.  Every array is FP64 in
+the oracle's own layout ``[P][N][3]`` (bead, atom, Cartesian dim).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "pimd_oracle.c")
+
+POT_NONE, POT_HARMONIC, POT_PAIR = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile ``liboracle.so`` with gcc (OpenMP on, FMA contraction off)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                          os.path.getmtime(os.path.join(_HERE, "pimd_oracle.h")))
+    ):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _System(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("n_beads", C.c_int32), ("nve", C.c_int32), ("pot", C.c_int32),
+        ("temp", C.c_double), ("kB", C.c_double), ("hbar", C.c_double), ("mvv2e", C.c_double),
+        ("dt", C.c_double), ("tau", C.c_double), ("tau_scale", C.c_double),
+        ("box", C.c_double * 3), ("seed", C.c_uint64), ("omega", C.c_double),
+        ("lj_eps", C.c_double), ("lj_sigma", C.c_double), ("lj_rc", C.c_double),
+        ("bond_k", C.c_double), ("bond_r0", C.c_double),
+        ("mass", C.POINTER(C.c_double)), ("lj_active", C.POINTER(C.c_int32)),
+        ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32)),
+    ]
+
+
+class _Est(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        d = C.POINTER(C.c_double)
+        u64 = C.POINTER(C.c_uint64)
+        S = C.POINTER(_System)
+        sig = {
+            "orc_nm_matrix": (None, [C.c_int32, d]),
+            "orc_mode_lambda": (None, [C.c_int32, d]),
+            "orc_to_normal": (None, [C.c_int32, C.c_int32, d, d, d]),
+            "orc_from_normal": (None, [C.c_int32, C.c_int32, d, d, d]),
+            "orc_philox4x64_10": (None, [u64, u64, u64]),
+            "orc_gaussians": (None, [C.c_uint64] * 5 + [d]),
+            "orc_free_rp_matrix": (None, [S, C.c_int32, C.c_double, d]),
+            "orc_pile_coeffs": (None, [S, C.c_int32, d, d]),
+            "orc_forces_bead": (C.c_double, [S, d, d]),
+            "orc_forces": (None, [S, d, d, d]),
+            "orc_step": (None, [S, d, d, d, d, u64, C.c_int32]),
+            "orc_estimators": (None, [S, d, d, d, d, C.POINTER(_Est)]),
+            "orc_spring_energy_nm": (C.c_double, [S, d]),
+            "orc_kcv_nm": (C.c_double, [S, d, d]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def nm_matrix(P: int) -> np.ndarray:
+    M = np.zeros((P, P))
+    lib().orc_nm_matrix(P, _dp(M))
+    return M
+
+
+def mode_lambda(P: int) -> np.ndarray:
+    lam = np.zeros(P)
+    lib().orc_mode_lambda(P, _dp(lam))
+    return lam
+
+
+def to_normal(a: np.ndarray) -> np.ndarray:
+    P, N, _ = a.shape
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.zeros_like(a)
+    lib().orc_to_normal(P, N, _dp(nm_matrix(P)), _dp(a), _dp(out))
+    return out
+
+
+def from_normal(at: np.ndarray) -> np.ndarray:
+    P, N, _ = at.shape
+    at = np.ascontiguousarray(at, dtype=np.float64)
+    out = np.zeros_like(at)
+    lib().orc_from_normal(P, N, _dp(nm_matrix(P)), _dp(at), _dp(out))
+    return out
+
+
+def philox4x64_10(ctr, key) -> list[int]:
+    c = (C.c_uint64 * 4)(*[int(v) & (2**64 - 1) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
+    o = (C.c_uint64 * 4)()
+    lib().orc_philox4x64_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def gaussians(seed: int, tag: int, i: int, k: int, s: int) -> np.ndarray:
+    z = np.zeros(3)
+    lib().orc_gaussians(seed, tag, i, k, s, _dp(z))
+    return z
+
+
+@dataclass
+class System:
+    """Physical parameters of one ring-polymer system (oracle side)."""
+    n_atoms: int
+    n_beads: int
+    mass: np.ndarray
+    temp: float
+    kB: float = 1.0
+    hbar: float = 1.0
+    mvv2e: float = 1.0
+    dt: float = 0.01
+    tau: float = 1.0
+    tau_scale: float = 1.0
+    nve: bool = False
+    pot: int = POT_NONE
+    box: tuple = (0.0, 0.0, 0.0)
+    seed: int = 0
+    omega: float = 0.0
+    lj_eps: float = 0.0
+    lj_sigma: float = 1.0
+    lj_rc: float = 2.5
+    bond_k: float = 0.0
+    bond_r0: float = 0.0
+    lj_active: np.ndarray | None = None
+    bonds: np.ndarray | None = None
+    _c: _System = field(default=None, init=False, repr=False)
+
+    def cstruct(self) -> _System:
+        self._mass = np.ascontiguousarray(self.mass, dtype=np.float64)
+        s = _System()
+        s.n_atoms, s.n_beads, s.nve, s.pot = self.n_atoms, self.n_beads, int(self.nve), self.pot
+        s.temp, s.kB, s.hbar, s.mvv2e = self.temp, self.kB, self.hbar, self.mvv2e
+        s.dt, s.tau, s.tau_scale = self.dt, self.tau, self.tau_scale
+        s.box = (C.c_double * 3)(*self.box)
+        s.seed = int(self.seed) & (2**64 - 1)
+        s.omega = self.omega
+        s.lj_eps, s.lj_sigma, s.lj_rc = self.lj_eps, self.lj_sigma, self.lj_rc
+        s.bond_k, s.bond_r0 = self.bond_k, self.bond_r0
+        s.mass = _dp(self._mass)
+        if self.lj_active is not None:
+            self._act = np.ascontiguousarray(self.lj_active, dtype=np.int32)
+            s.lj_active = self._act.ctypes.data_as(C.POINTER(C.c_int32))
+        if self.bonds is not None and len(self.bonds):
+            self._bonds = np.ascontiguousarray(self.bonds, dtype=np.int32).reshape(-1, 2)
+            s.n_bonds = self._bonds.shape[0]
+            s.bonds = self._bonds.ctypes.data_as(C.POINTER(C.c_int32))
+        self._c = s
+        return s
+
+    @classmethod
+    def from_spec(cls, spec) -> "System":
+        """Build from any object with the workload-spec attributes (duck-typed,
+        so this package imports nothing from the product package)."""
+        pot = {0: POT_NONE, 1: POT_HARMONIC, 2: POT_PAIR, 3: POT_PAIR}[int(spec.potential)]
+        return cls(n_atoms=spec.n_atoms, n_beads=spec.n_beads, mass=np.asarray(spec.mass),
+                   temp=spec.temp, kB=spec.kB, hbar=spec.hbar, mvv2e=spec.mvv2e, dt=spec.dt,
+                   tau=spec.tau, tau_scale=spec.tau_scale, nve=bool(spec.ensemble == 1),
+                   pot=pot, box=tuple(spec.box), seed=spec.seed, omega=spec.omega,
+                   lj_eps=spec.lj_eps, lj_sigma=spec.lj_sigma, lj_rc=spec.lj_rc,
+                   bond_k=spec.bond_k, bond_r0=spec.bond_r0, lj_active=spec.lj_active,
+                   bonds=spec.bonds)
+
+    # --- per-function wrappers -------------------------------------------
+    def free_rp_matrix(self, k: int, h: float) -> np.ndarray:
+        A = np.zeros(4)
+        lib().orc_free_rp_matrix(C.byref(self.cstruct()), k, h, _dp(A))
+        return A.reshape(2, 2)
+
+    def pile_coeffs(self, k: int) -> tuple[float, float]:
+        c1, c2 = C.c_double(), C.c_double()
+        lib().orc_pile_coeffs(C.byref(self.cstruct()), k, C.byref(c1), C.byref(c2))
+        return c1.value, c2.value
+
+    def forces(self, x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        f = np.zeros_like(x)
+        U = np.zeros(self.n_beads)
+        lib().orc_forces(C.byref(self.cstruct()), _dp(x), _dp(f), _dp(U))
+        return f, U
+
+    def spring_energy_nm(self, x: np.ndarray) -> float:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_spring_energy_nm(C.byref(self.cstruct()), _dp(x))
+
+    def kcv_nm(self, x: np.ndarray, f: np.ndarray) -> float:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        return lib().orc_kcv_nm(C.byref(self.cstruct()), _dp(x), _dp(f))
+
+
+ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
+
+
+class State:
+    """Oracle integrator state: Cartesian x, normal-mode v~, forces f, step s."""
+
+    @classmethod
+    def from_spec(cls, spec, step: int = 0) -> "State":
+        return cls(System.from_spec(spec), spec.x0, spec.v0, step)
+
+    def __init__(self, system: System, x: np.ndarray, v: np.ndarray, step: int = 0):
+        self.sys = system
+        self.x = np.ascontiguousarray(x, dtype=np.float64).copy()
+        self.vt = to_normal(np.ascontiguousarray(v, dtype=np.float64))
+        self.f, self.U = system.forces(self.x)
+        self.step_count = np.array([step], dtype=np.uint64)
+
+    @property
+    def v(self) -> np.ndarray:
+        """Cartesian bead velocities M^T v~."""
+        return from_normal(self.vt)
+
+    @property
+    def p(self) -> np.ndarray:
+        return self.v * self.sys.mass[None, :, None]
+
+    def step(self, n: int = 1) -> None:
+        s = self.sys.cstruct()
+        lib().orc_step(C.byref(s), _dp(self.x), _dp(self.vt), _dp(self.f), _dp(self.U),
+                       self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)), int(n))
+
+    def estimators(self) -> dict:
+        e = _Est()
+        lib().orc_estimators(C.byref(self.sys.cstruct()), _dp(self.x), _dp(self.vt), _dp(self.f),
+                             _dp(self.U), C.byref(e))
+        return {n: getattr(e, n) for n in ESTIMATOR_NAMES}

@@ -1,0 +1,472 @@
+/*
+ * pimd_oracle.c -- plain CPU FP64 reference for the ring-polymer BAOAB step
+ * with the PILE-L thermostat (arXiv:2602.13553).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.
+ *
+ * Built with -O2 -ffp-contract=off (no FMA contraction, no fast-math).  The
+ * force loops carry an OpenMP pragma so the CPU baseline can use the host's
+ * cores; every reduction is done serially afterwards in a fixed order, so the
+ * result does not depend on the thread count.
+ */
+#include "pimd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------
+ * Normal-mode matrix, App. B Eq. (B1).  Row i is the mode, column j the bead.
+ *   i = 0                 : 1/sqrt(P)
+ *   i = P/2 (P even)      : (-1)^j / sqrt(P)
+ *   1 <= i <= floor(P/2)  : sqrt(2/P) cos(2 pi i j / P)
+ *   floor(P/2) < i < P    : sqrt(2/P) sin(2 pi i j / P)
+ * For P even the row i = P/2 matches both the second and third case; the
+ * second (normalized) one is taken.  The angle's integer part (i*j mod P) is
+ * reduced before the trigonometric call; this changes only rounding.
+ * Pinned: orthogonality, M A M^T = diag(lambda), equality with the real-DFT
+ * form built from numpy.fft, and the hand values for P = 1, 2.
+ * --------------------------------------------------------------------- */
+void orc_nm_matrix(int32_t P, double *M)
+{
+    const double inv_sqrt_p = 1.0 / sqrt((double)P);
+    const double sqrt_2_p = sqrt(2.0 / (double)P);
+    for (int32_t i = 0; i < P; ++i) {
+        for (int32_t j = 0; j < P; ++j) {
+            double v;
+            long long ij = ((long long)i * (long long)j) % P;
+            double ang = 2.0 * PI * (double)ij / (double)P;
+            if (i == 0)
+                v = inv_sqrt_p;
+            else if ((P % 2 == 0) && (i == P / 2))
+                v = (j % 2 == 0) ? inv_sqrt_p : -inv_sqrt_p;
+            else if (i <= P / 2)
+                v = sqrt_2_p * cos(ang);
+            else
+                v = sqrt_2_p * sin(ang);
+            M[(size_t)i * P + j] = v;
+        }
+    }
+}
+
+/* Eq. (B2): lambda_k = 4 sin^2(k pi / P), attached to row k of M.  These are
+ * the eigenvalues of the circulant ring Laplacian that M diagonalizes. */
+void orc_mode_lambda(int32_t P, double *lam)
+{
+    for (int32_t k = 0; k < P; ++k) {
+        double s = sin(PI * (double)k / (double)P);
+        lam[k] = 4.0 * s * s;
+    }
+}
+
+void orc_to_normal(int32_t P, int32_t N, const double *M, const double *a, double *at)
+{
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t d = 0; d < 3; ++d)
+            for (int32_t k = 0; k < P; ++k) {
+                double s = 0.0;
+                for (int32_t j = 0; j < P; ++j)
+                    s += M[(size_t)k * P + j] * a[((size_t)j * N + i) * 3 + d];
+                at[((size_t)k * N + i) * 3 + d] = s;
+            }
+}
+
+/* Eq. (B3): the inverse is the transpose. */
+void orc_from_normal(int32_t P, int32_t N, const double *M, const double *at, double *a)
+{
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t d = 0; d < 3; ++d)
+            for (int32_t j = 0; j < P; ++j) {
+                double s = 0.0;
+                for (int32_t k = 0; k < P; ++k)
+                    s += M[(size_t)k * P + j] * at[((size_t)k * N + i) * 3 + d];
+                a[((size_t)j * N + i) * 3 + d] = s;
+            }
+}
+
+/* ------------------------------------------------------------------------
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+ *   (hi0, lo0) = M0 * c0, (hi1, lo1) = M1 * c2,
+ *   c <- (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0),
+ * with the key bumped by the Weyl constants between rounds.
+ * Pinned against numpy.random.Philox (known answers).
+ * --------------------------------------------------------------------- */
+static void mul_hilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *lo = (uint64_t)p;
+    *hi = (uint64_t)(p >> 64);
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_hilo64(M0, c0, &hi0, &lo0);
+        mul_hilo64(M1, c2, &hi1, &lo1);
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform on (0, 1]: the top 53 bits plus one, times 2^-53. */
+static double u01_open0(uint64_t w)
+{
+    return ((double)(w >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+}
+
+/* Box-Muller on the four words: (z0, z1) from (u0, u1), z2 from (u2, u3).
+ * The paper leaves the generator unspecified (App. D only asks for
+ * independent N(0,1) numbers); this keyed, counter-based stream is this
+ * implementation's reading.  Pinned by moment tests. */
+void orc_gaussians(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s,
+                   double z[3])
+{
+    uint64_t ctr[4] = {i, k, s, 0};
+    uint64_t key[2] = {seed, tag};
+    uint64_t w[4];
+    orc_philox4x64_10(ctr, key, w);
+    double u0 = u01_open0(w[0]), u1 = u01_open0(w[1]);
+    double u2 = u01_open0(w[2]), u3 = u01_open0(w[3]);
+    double r0 = sqrt(-2.0 * log(u0));
+    double r2 = sqrt(-2.0 * log(u2));
+    z[0] = r0 * cos(2.0 * PI * u1);
+    z[1] = r0 * sin(2.0 * PI * u1);
+    z[2] = r2 * cos(2.0 * PI * u3);
+}
+
+/* ------------------------------------------------------------------------
+ * Free ring polymer in normal modes.  With physical masses (fmmode
+ * physical) the spring part of Eq. 1 is sum_k 1/2 m omega_k^2 x~_k^2 with
+ * omega_k = sqrt(lambda_k) omega_n and omega_n = P kB T / hbar (Eq. 2).  The
+ * paper does not print the position update; the A step is read as the exact
+ * flow of that quadratic Hamiltonian over a time h.
+ * Pinned: det A = 1, A(h)A(h) = A(2h), energy conservation of the free ring
+ * polymer at zero friction.
+ * --------------------------------------------------------------------- */
+static double omega_n(const orc_system *sys)
+{
+    return (double)sys->n_beads * sys->kB * sys->temp / sys->hbar;
+}
+
+static double omega_k(const orc_system *sys, int32_t k)
+{
+    double s = sin(PI * (double)k / (double)sys->n_beads);
+    return 2.0 * omega_n(sys) * fabs(s);
+}
+
+void orc_free_rp_matrix(const orc_system *sys, int32_t k, double h, double A[4])
+{
+    double w = (k == 0) ? 0.0 : omega_k(sys, k);
+    if (w == 0.0) {
+        A[0] = 1.0; A[1] = h; A[2] = 0.0; A[3] = 1.0;
+    } else {
+        double c = cos(w * h), s = sin(w * h);
+        A[0] = c; A[1] = s / w; A[2] = -w * s; A[3] = c;
+    }
+}
+
+/* App. D, Eqs. (D1)-(D2): tau_0 = tau; tau_k = scale / (2 omega_k) for k >= 1;
+ * c1 = exp(-dt/tau_k), c2 = sqrt(1 - c1^2).  The O step spans one full dt. */
+void orc_pile_coeffs(const orc_system *sys, int32_t k, double *c1, double *c2)
+{
+    if (sys->nve) { *c1 = 1.0; *c2 = 0.0; return; }
+    double tau_k = (k == 0) ? sys->tau : sys->tau_scale / (2.0 * omega_k(sys, k));
+    double a = exp(-sys->dt / tau_k);
+    *c1 = a;
+    *c2 = sqrt(1.0 - a * a);
+}
+
+/* ------------------------------------------------------------------------
+ * Forces.  Every bead is an independent copy of the physical system (the
+ * U(r^(k)) term of Eq. 1).  Pair potential: Lennard-Jones among lj_active
+ * atoms, truncated at rc with the energy shifted so that u(rc) = 0 and the
+ * force left unshifted, summed over all periodic images with
+ * |r_ij + n L| < rc (i = j only for n != 0).  Bonds: U = K (r - r0)^2 with the
+ * minimum-image bond vector.  Harmonic trap: U = 1/2 m omega^2 |r|^2.
+ * Pinned: finite differences of U, Newton's third law, image sum = minimum
+ * image for large boxes, small box = replicated large box.
+ * --------------------------------------------------------------------- */
+static void lj_pair(double eps, double sig, double rc2, double ushift, double r2,
+                    double *u, double *fr)
+{
+    /* u(r) and fr = -(du/dr)/r, for r2 < rc2 */
+    (void)rc2;
+    double sr2 = sig * sig / r2;
+    double sr6 = sr2 * sr2 * sr2;
+    double sr12 = sr6 * sr6;
+    *u = 4.0 * eps * (sr12 - sr6) - ushift;
+    *fr = 24.0 * eps * (2.0 * sr12 - sr6) / r2;
+}
+
+double orc_forces_bead(const orc_system *sys, const double *xk, double *fk)
+{
+    const int32_t N = sys->n_atoms;
+    double *eat = (double *)calloc((size_t)N, sizeof(double));
+    memset(fk, 0, sizeof(double) * 3 * (size_t)N);
+
+    if (sys->pot == ORC_POT_HARMONIC) {
+        for (int32_t i = 0; i < N; ++i) {
+            double kk = sys->mass[i] * sys->omega * sys->omega * sys->mvv2e;
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                fk[3 * i + d] = -kk * xk[3 * i + d];
+                r2 += xk[3 * i + d] * xk[3 * i + d];
+            }
+            eat[i] = 0.5 * kk * r2;
+        }
+    } else if (sys->pot == ORC_POT_PAIR) {
+        const double L0 = sys->box[0], L1 = sys->box[1], L2 = sys->box[2];
+        const double rc = sys->lj_rc, rc2 = rc * rc;
+        const double eps = sys->lj_eps, sig = sys->lj_sigma;
+        double src2 = sig * sig / rc2, src6 = src2 * src2 * src2;
+        const double ushift = 4.0 * eps * (src6 * src6 - src6);
+        const int minimg = (L0 >= 2.0 * rc) && (L1 >= 2.0 * rc) && (L2 >= 2.0 * rc);
+        const int n0 = (int)ceil(rc / L0) + 1, n1 = (int)ceil(rc / L1) + 1,
+                  n2 = (int)ceil(rc / L2) + 1;
+        if (eps != 0.0) {
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int32_t i = 0; i < N; ++i) {
+                if (sys->lj_active && !sys->lj_active[i]) continue;
+                double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+                for (int32_t j = 0; j < N; ++j) {
+                    if (sys->lj_active && !sys->lj_active[j]) continue;
+                    double dx = xk[3 * i] - xk[3 * j];
+                    double dy = xk[3 * i + 1] - xk[3 * j + 1];
+                    double dz = xk[3 * i + 2] - xk[3 * j + 2];
+                    if (minimg) {
+                        if (j == i) continue;
+                        dx -= L0 * nearbyint(dx / L0);
+                        dy -= L1 * nearbyint(dy / L1);
+                        dz -= L2 * nearbyint(dz / L2);
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < rc2) {
+                            double u, fr;
+                            lj_pair(eps, sig, rc2, ushift, r2, &u, &fr);
+                            e += 0.5 * u;
+                            fx += fr * dx; fy += fr * dy; fz += fr * dz;
+                        }
+                    } else {
+                        for (int a = -n0; a <= n0; ++a)
+                            for (int b = -n1; b <= n1; ++b)
+                                for (int c = -n2; c <= n2; ++c) {
+                                    if (j == i && a == 0 && b == 0 && c == 0) continue;
+                                    double ex = dx + a * L0, ey = dy + b * L1, ez = dz + c * L2;
+                                    double r2 = ex * ex + ey * ey + ez * ez;
+                                    if (r2 < rc2) {
+                                        double u, fr;
+                                        lj_pair(eps, sig, rc2, ushift, r2, &u, &fr);
+                                        e += 0.5 * u;
+                                        fx += fr * ex; fy += fr * ey; fz += fr * ez;
+                                    }
+                                }
+                    }
+                }
+                fk[3 * i] = fx; fk[3 * i + 1] = fy; fk[3 * i + 2] = fz;
+                eat[i] = e;
+            }
+        }
+        /* bonds: serial, in the given order */
+        for (int32_t b = 0; b < sys->n_bonds; ++b) {
+            int32_t i = sys->bonds[2 * b], j = sys->bonds[2 * b + 1];
+            double d[3];
+            for (int a = 0; a < 3; ++a) {
+                d[a] = xk[3 * i + a] - xk[3 * j + a];
+                if (sys->box[a] > 0.0) d[a] -= sys->box[a] * nearbyint(d[a] / sys->box[a]);
+            }
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double dr = r - sys->bond_r0;
+            double u = sys->bond_k * dr * dr;
+            double fr = -2.0 * sys->bond_k * dr / r;
+            for (int a = 0; a < 3; ++a) {
+                fk[3 * i + a] += fr * d[a];
+                fk[3 * j + a] -= fr * d[a];
+            }
+            eat[i] += 0.5 * u;
+            eat[j] += 0.5 * u;
+        }
+    }
+    double U = 0.0;
+    for (int32_t i = 0; i < N; ++i) U += eat[i];
+    free(eat);
+    return U;
+}
+
+void orc_forces(const orc_system *sys, const double *x, double *f, double *U)
+{
+    const size_t stride = 3 * (size_t)sys->n_atoms;
+    for (int32_t k = 0; k < sys->n_beads; ++k)
+        U[k] = orc_forces_bead(sys, x + k * stride, f + k * stride);
+}
+
+/* ------------------------------------------------------------------------
+ * One BAOAB step in normal modes (Sec. IV.A; Sec. III.C lists BAOAB):
+ *   B  v~ += (dt/2) f~/m        with f~ = M f
+ *   A  (x~, v~) <- A(dt/2)       with x~ = M x
+ *   O  v~ <- c1 v~ + c2 sqrt(P kB T / m) eta     (Eq. D2, thermostat at P T)
+ *   A  (x~, v~) <- A(dt/2)
+ *      x = M^T x~, f = F(x)
+ *   B  v~ += (dt/2) f~/m        with f~ = M f
+ * The noise eta for mode k, atom i, dim a at step s is orc_gaussians(seed, 0,
+ * i, k, s)[a].
+ * --------------------------------------------------------------------- */
+void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U,
+              uint64_t *step, int32_t nsteps)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double h = 0.5 * sys->dt;
+    const double ftm2v = 1.0 / sys->mvv2e;
+    double *M = (double *)malloc(sizeof(double) * (size_t)P * P);
+    double *xt = (double *)malloc(sizeof(double) * n);
+    double *ft = (double *)malloc(sizeof(double) * n);
+    double *Ah = (double *)malloc(sizeof(double) * 4 * (size_t)P);
+    double *c1 = (double *)malloc(sizeof(double) * (size_t)P);
+    double *c2 = (double *)malloc(sizeof(double) * (size_t)P);
+    orc_nm_matrix(P, M);
+    for (int32_t k = 0; k < P; ++k) {
+        orc_free_rp_matrix(sys, k, h, Ah + 4 * k);
+        orc_pile_coeffs(sys, k, c1 + k, c2 + k);
+    }
+
+    for (int32_t it = 0; it < nsteps; ++it) {
+        const uint64_t s = *step;
+        /* B */
+        orc_to_normal(P, N, M, f, ft);
+        for (int32_t k = 0; k < P; ++k)
+            for (int32_t i = 0; i < N; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    size_t e = ((size_t)k * N + i) * 3 + d;
+                    vt[e] += h * ft[e] * ftm2v / sys->mass[i];
+                }
+        /* A, O, A */
+        orc_to_normal(P, N, M, x, xt);
+        for (int32_t k = 0; k < P; ++k) {
+            const double *A = Ah + 4 * k;
+            for (int32_t i = 0; i < N; ++i) {
+                double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
+                double z[3] = {0.0, 0.0, 0.0};
+                if (!sys->nve) orc_gaussians(sys->seed, 0, (uint64_t)i, (uint64_t)k, s, z);
+                for (int d = 0; d < 3; ++d) {
+                    size_t e = ((size_t)k * N + i) * 3 + d;
+                    double q = xt[e], p = vt[e];
+                    double q1 = A[0] * q + A[1] * p;
+                    double p1 = A[2] * q + A[3] * p;
+                    if (!sys->nve) p1 = c1[k] * p1 + c2[k] * sigma * z[d];
+                    xt[e] = A[0] * q1 + A[1] * p1;
+                    vt[e] = A[2] * q1 + A[3] * p1;
+                }
+            }
+        }
+        orc_from_normal(P, N, M, xt, x);
+        /* forces at the new positions, then B */
+        orc_forces(sys, x, f, U);
+        orc_to_normal(P, N, M, f, ft);
+        for (int32_t k = 0; k < P; ++k)
+            for (int32_t i = 0; i < N; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    size_t e = ((size_t)k * N + i) * 3 + d;
+                    vt[e] += h * ft[e] * ftm2v / sys->mass[i];
+                }
+        *step = s + 1;
+    }
+    free(M); free(xt); free(ft); free(Ah); free(c1); free(c2);
+}
+
+/* ------------------------------------------------------------------------
+ * Estimators, App. A.  Read with omega_n^2 wherever the printed formulas
+ * show omega_n (dimensional analysis), and with the 1/P on the spring sum of
+ * K_PR (Eq. A5), which the printed formula lacks.
+ *   K    = sum_k sum_i 1/2 m |v~_i^k|^2
+ *   S    = sum_k sum_i 1/2 m omega_n^2 |r_i^k - r_i^(k+1)|^2   (bead form)
+ *   K_PR = 3 P N kB T / 2 - S / P
+ *   K_CV = 3 N kB T / 2 - (1/2P) sum_k sum_i (r_i^k - r_i^c) . F_i^k
+ *   temp = 2 K / (3 N P^2 kB)
+ * --------------------------------------------------------------------- */
+void orc_estimators(const orc_system *sys, const double *x, const double *vt,
+                    const double *f, const double *U, orc_est *out)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const double wn = omega_n(sys);
+    const double kT = sys->kB * sys->temp;
+    double ekin = 0.0, espring = 0.0, epot = 0.0, vir = 0.0;
+    for (int32_t k = 0; k < P; ++k) {
+        int32_t kp = (k + 1) % P;
+        for (int32_t i = 0; i < N; ++i) {
+            double m = sys->mass[i];
+            for (int d = 0; d < 3; ++d) {
+                double v = vt[((size_t)k * N + i) * 3 + d];
+                ekin += 0.5 * m * sys->mvv2e * v * v;
+                double dr = x[((size_t)k * N + i) * 3 + d] - x[((size_t)kp * N + i) * 3 + d];
+                espring += 0.5 * m * sys->mvv2e * wn * wn * dr * dr;
+            }
+        }
+        epot += U[k];
+    }
+    for (int32_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double c = 0.0;
+            for (int32_t k = 0; k < P; ++k) c += x[((size_t)k * N + i) * 3 + d];
+            c /= (double)P;
+            for (int32_t k = 0; k < P; ++k) {
+                size_t e = ((size_t)k * N + i) * 3 + d;
+                vir += (x[e] - c) * f[e];
+            }
+        }
+    out->ekin = ekin;
+    out->espring = espring;
+    out->epot = epot;
+    out->etot = ekin + espring + epot;
+    out->kprim = 1.5 * (double)P * (double)N * kT - espring / (double)P;
+    out->kcv = 1.5 * (double)N * kT - vir / (2.0 * (double)P);
+    out->temp = 2.0 * ekin / (3.0 * (double)N * (double)P * (double)P * sys->kB);
+}
+
+double orc_spring_energy_nm(const orc_system *sys, const double *x)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double wn = omega_n(sys);
+    double *M = (double *)malloc(sizeof(double) * (size_t)P * P);
+    double *lam = (double *)malloc(sizeof(double) * (size_t)P);
+    double *xt = (double *)malloc(sizeof(double) * n);
+    orc_nm_matrix(P, M);
+    orc_mode_lambda(P, lam);
+    orc_to_normal(P, N, M, x, xt);
+    double s = 0.0;
+    for (int32_t k = 0; k < P; ++k)
+        for (int32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double q = xt[((size_t)k * N + i) * 3 + d];
+                s += 0.5 * sys->mass[i] * sys->mvv2e * wn * wn * lam[k] * q * q;
+            }
+    free(M); free(lam); free(xt);
+    return s;
+}
+
+double orc_kcv_nm(const orc_system *sys, const double *x, const double *f)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    double *M = (double *)malloc(sizeof(double) * (size_t)P * P);
+    double *xt = (double *)malloc(sizeof(double) * n);
+    double *ft = (double *)malloc(sizeof(double) * n);
+    orc_nm_matrix(P, M);
+    orc_to_normal(P, N, M, x, xt);
+    orc_to_normal(P, N, M, f, ft);
+    double vir = 0.0;
+    for (int32_t k = 1; k < P; ++k)
+        for (size_t e = (size_t)k * N * 3; e < (size_t)(k + 1) * N * 3; ++e) vir += xt[e] * ft[e];
+    free(M); free(xt); free(ft);
+    return 1.5 * (double)N * sys->kB * sys->temp - vir / (2.0 * (double)P);
+}

@@ -1,0 +1,115 @@
+/*
+ * pimd_oracle.h -- plain CPU FP64 reference ("oracle") for the ring-polymer
+ * BAOAB step with the PILE-L Langevin thermostat, as described in
+ * Li et al., "fix pimd/langevin: An Efficient Implementation of Path Integral
+ * Molecular Dynamics in LAMMPS" (arXiv:2602.13553).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The GPU library shares
+ * no code, header, table or helper with it.
+ *
+ * Everything is FP64, written for clarity and checked against the physics
+ * (orthogonality, energy conservation, closed forms), not for speed.
+ *
+ * Layout: every per-bead array is [P][N][3] (bead k, atom i, Cartesian dim a),
+ * i.e. element r_i^(k)_a lives at ((k*N)+i)*3+a.  Velocities in the state are
+ * normal-mode velocities v~ (the paper keeps positions Cartesian and
+ * velocities in normal-mode form, Sec. III.A).
+ *
+ * Units: the caller chooses a consistent unit system.  kB*temp is an energy,
+ * hbar is energy*time, and mvv2e converts mass*velocity^2 to energy (1 in
+ * reduced LJ units; 1/4.184e-4 for amu, Angstrom, fs, kcal/mol).
+ *
+ * Parity pins: see the per-function comments; every function here is pinned
+ * by a test against a closed form, an invariant, a library routine or brute
+ * force, except where a comment says "parity unpinned".
+ */
+#ifndef PIMD_ORACLE_H
+#define PIMD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_POT_NONE = 0, ORC_POT_HARMONIC = 1, ORC_POT_PAIR = 2 };
+
+typedef struct orc_system {
+    int32_t n_atoms;        /* N */
+    int32_t n_beads;        /* P (the paper's n) */
+    int32_t nve;            /* 1: no thermostat (c1 = 1, c2 = 0) */
+    int32_t pot;            /* ORC_POT_* */
+    double temp;            /* T */
+    double kB;              /* Boltzmann constant, energy per temperature */
+    double hbar;            /* reduced Planck constant (already scaled by sp) */
+    double mvv2e;           /* energy = mvv2e * mass * velocity^2 */
+    double dt;              /* time step */
+    double tau;             /* centroid damping time tau_0 */
+    double tau_scale;       /* multiplies the non-centroid damping times */
+    double box[3];          /* periodic box lengths (pair potentials only) */
+    uint64_t seed;          /* thermostat seed */
+    double omega;           /* harmonic trap frequency (ORC_POT_HARMONIC) */
+    double lj_eps, lj_sigma, lj_rc;   /* Lennard-Jones among lj_active atoms */
+    double bond_k, bond_r0;           /* U = bond_k (r - r0)^2 per bond */
+    const double *mass;     /* [N] */
+    const int32_t *lj_active; /* [N] 0/1, or NULL = every atom */
+    int32_t n_bonds;
+    const int32_t *bonds;   /* [n_bonds][2] atom pairs */
+} orc_system;
+
+typedef struct orc_est {
+    double ekin;    /* sum_k K^(k), App. A item 1 (normal-mode form) */
+    double espring; /* sum_k S^(k), Eq. 1 spring term (read with omega_n^2) */
+    double epot;    /* sum_k U^(k), App. A item 3 */
+    double etot;    /* H, Eq. A4 */
+    double kprim;   /* K_PR, Eq. A5 (read with 1/n and omega_n^2) */
+    double kcv;     /* K_CV, Eq. A7 */
+    double temp;    /* ring-polymer temperature divided by P (Sec. III.A) */
+} orc_est;
+
+/* --- normal modes (App. B) --------------------------------------------- */
+void orc_nm_matrix(int32_t P, double *M /* [P][P], row = mode */);
+void orc_mode_lambda(int32_t P, double *lam /* [P] */);
+/* a~ = M a for every atom and dim; a, at are [P][N][3] */
+void orc_to_normal(int32_t P, int32_t N, const double *M, const double *a, double *at);
+/* a = M^T a~ */
+void orc_from_normal(int32_t P, int32_t N, const double *M, const double *at, double *a);
+
+/* --- random numbers (App. D noise) ------------------------------------- */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+/* three standard normal deviates for (seed, tag) and counter (i, k, s, 0) */
+void orc_gaussians(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s,
+                   double z[3]);
+
+/* --- free ring-polymer propagator and thermostat coefficients ---------- */
+/* A(h) for mode k: [[a00, a01], [a10, a11]] acting on (x~, v~) */
+void orc_free_rp_matrix(const orc_system *sys, int32_t k, double h, double A[4]);
+void orc_pile_coeffs(const orc_system *sys, int32_t k, double *c1, double *c2);
+
+/* --- forces, per bead independently ----------------------------------- */
+/* x, f: [N][3] of one bead; returns U^(k) */
+double orc_forces_bead(const orc_system *sys, const double *xk, double *fk);
+/* x, f: [P][N][3]; U: [P] */
+void orc_forces(const orc_system *sys, const double *x, double *f, double *U);
+
+/* --- the integrator ---------------------------------------------------- */
+/* Advances (x, v~, f) by nsteps BAOAB steps.  step is the thermostat step
+ * counter s used in the noise counter; it is incremented once per step. */
+void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U,
+              uint64_t *step, int32_t nsteps);
+
+/* --- estimators (App. A) ----------------------------------------------- */
+/* At a synchronized state.  U is [P] from orc_forces. */
+void orc_estimators(const orc_system *sys, const double *x, const double *vt,
+                    const double *f, const double *U, orc_est *out);
+/* Spring energy in the normal-mode form of App. A item 2 (for the pin that
+ * it equals the bead form of Eq. 1). */
+double orc_spring_energy_nm(const orc_system *sys, const double *x);
+/* K_CV written through normal modes: 3NkT/2 - (1/2P) sum_{k>=1} x~.f~ */
+double orc_kcv_nm(const orc_system *sys, const double *x, const double *f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,361 @@
+"""Pins for the CPU oracle: each check ties it to something other than itself
+(closed forms, invariants, library routines, textbook special cases, brute
+force), chosen so that a dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails at least one of them."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2602_13553_amd import inputs
+
+
+# ---------------------------------------------------------------- normal modes
+def test_nm_matrix_hand_values():
+    assert np.allclose(oracle.nm_matrix(1), [[1.0]], atol=0, rtol=0)
+    s = 1 / math.sqrt(2)
+    assert np.allclose(oracle.nm_matrix(2), [[s, s], [s, -s]], atol=1e-16)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5, 6, 7, 8, 9, 16, 32, 64, 96, 128])
+def test_nm_matrix_orthogonal_and_diagonalizes_ring(P):
+    M = oracle.nm_matrix(P)
+    assert np.abs(M @ M.T - np.eye(P)).max() <= 1e-13
+    # circulant ring Laplacian: 2 on the diagonal, -1 on the ring neighbours
+    A = 2 * np.eye(P)
+    for j in range(P):
+        A[j, (j + 1) % P] -= 1
+        A[j, (j - 1) % P] -= 1
+    if P == 1:
+        A = np.zeros((1, 1))
+    if P == 2:
+        A = np.array([[2.0, -2.0], [-2.0, 2.0]])
+    lam = oracle.mode_lambda(P)
+    D = M @ A @ M.T
+    assert np.abs(D - np.diag(lam)).max() <= 1e-12 * max(1.0, np.abs(A).max())
+    # the eigenvalues themselves, from LAPACK
+    assert np.allclose(np.sort(lam), np.linalg.eigvalsh(A), atol=1e-12)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5, 8, 12, 32, 64])
+def test_nm_matrix_equals_real_dft(P):
+    """Rows of M from numpy.fft: X = DFT(e_j) with exp(-2 pi i q j / P)."""
+    X = np.fft.fft(np.eye(P), axis=0)        # column j = DFT of unit vector e_j
+    ref = np.zeros((P, P))
+    ref[0] = X[0].real / math.sqrt(P)
+    for q in range(1, P):
+        if P % 2 == 0 and q == P // 2:
+            ref[q] = X[q].real / math.sqrt(P)
+        elif q <= P // 2:
+            ref[q] = math.sqrt(2 / P) * X[q].real
+        else:
+            ref[q] = math.sqrt(2 / P) * X[P - q].imag
+    assert np.abs(oracle.nm_matrix(P) - ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("P", [1, 4, 7, 32, 64])
+def test_nm_round_trip(P):
+    rng = np.random.default_rng(P)
+    x = rng.standard_normal((P, 13, 3)) * 5 + 3
+    xt = oracle.to_normal(x)
+    back = oracle.from_normal(xt)
+    assert np.abs(back - x).max() <= 1e-13 * np.abs(x).max()
+    # the centroid mode is sqrt(P) times the centroid
+    assert np.allclose(xt[0] / math.sqrt(P), x.mean(axis=0), rtol=0, atol=1e-13 * np.abs(x).max())
+
+
+# ---------------------------------------------------------------- random numbers
+def test_philox_known_answers_numpy():
+    """numpy.random.Philox(counter=c, key=k).random_raw(4) returns
+    Philox4x64-10(c + 1, k), the counter incrementing from word 0 upward."""
+    rng = np.random.default_rng(1)
+    cases = [((0, 0), (0, 0, 0, 0)), ((2**64 - 1, 2**64 - 1), (2**64 - 1,) * 3 + (2**64 - 2,))]
+    for _ in range(20):
+        cases.append((tuple(int(v) for v in rng.integers(0, 2**63, 2)),
+                      tuple(int(v) for v in rng.integers(0, 2**63, 4))))
+    for key, ctr in cases:
+        g = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                             counter=np.array(ctr, dtype=np.uint64))
+        ref = [int(v) for v in g.random_raw(4)]
+        c = sum(int(ctr[i]) << (64 * i) for i in range(4)) + 1
+        c1 = [(c >> (64 * i)) & (2**64 - 1) for i in range(4)]
+        assert oracle.philox4x64_10(c1, key) == ref
+
+
+def test_gaussian_moments_and_independence():
+    n = 60000
+    z = np.array([oracle.gaussians(12345, 0, i % 300, i // 300, 7) for i in range(n)])
+    se = 1 / math.sqrt(n)
+    for d in range(3):
+        assert abs(z[:, d].mean()) < 5 * se
+        assert abs(z[:, d].var() - 1) < 5 * math.sqrt(2) * se
+        kurt = ((z[:, d] - z[:, d].mean()) ** 4).mean() / z[:, d].var() ** 2
+        assert abs(kurt - 3) < 5 * math.sqrt(24) * se
+    c = np.corrcoef(z.T)
+    assert np.abs(c - np.eye(3)).max() < 5 * se
+    # independence beyond correlation: E[z_a^2 z_b^2] = 1 for a != b
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        q = z[:, a] ** 2 * z[:, b] ** 2
+        assert abs(q.mean() - 1) < 5 * q.std() / math.sqrt(n)
+    # distinct keys, steps and modes give uncorrelated streams
+    z2 = np.array([oracle.gaussians(12346, 0, i % 300, i // 300, 7) for i in range(n)])
+    z3 = np.array([oracle.gaussians(12345, 0, i % 300, i // 300, 8) for i in range(n)])
+    assert abs(np.corrcoef(z[:, 0], z2[:, 0])[0, 1]) < 5 * se
+    assert abs(np.corrcoef(z[:, 0], z3[:, 0])[0, 1]) < 5 * se
+
+
+# ---------------------------------------------------------------- propagators
+def _sys(P=8, kT=0.7, hbar=0.1, dt=0.002, **kw):
+    return oracle.System(n_atoms=1, n_beads=P, mass=np.ones(1), temp=kT, hbar=hbar, dt=dt, **kw)
+
+
+@pytest.mark.parametrize("P", [1, 2, 5, 8, 32])
+def test_free_rp_matrix_is_exact_flow(P):
+    s = _sys(P=P)
+    wn = P * s.kB * s.temp / s.hbar
+    h = 0.5 * s.dt
+    for k in range(P):
+        A = s.free_rp_matrix(k, h)
+        wk = 2 * wn * abs(math.sin(math.pi * k / P))
+        # generator of x' = v, v' = -w^2 x, exponentiated by scipy
+        G = np.array([[0.0, 1.0], [-wk * wk, 0.0]])
+        assert np.allclose(A, scipy.linalg.expm(G * h), rtol=1e-13, atol=1e-15)
+        assert abs(np.linalg.det(A) - 1) < 1e-13
+        assert np.allclose(A @ A, s.free_rp_matrix(k, 2 * h), rtol=1e-12, atol=1e-14)
+
+
+def test_pile_coefficients():
+    s = _sys(P=8, tau=0.5, tau_scale=1.0)
+    wn = 8 * 0.7 / 0.1
+    for k in range(8):
+        c1, c2 = s.pile_coeffs(k)
+        assert abs(c1 * c1 + c2 * c2 - 1) < 1e-15
+        gamma = 1 / 0.5 if k == 0 else 2 * (2 * wn * math.sin(math.pi * k / 8))
+        assert abs(c1 - math.exp(-gamma * s.dt)) < 1e-15
+    s2 = _sys(P=8, tau=0.5, tau_scale=3.0)
+    c1, _ = s2.pile_coeffs(3)
+    assert abs(c1 - math.exp(-2 * 2 * wn * math.sin(3 * math.pi / 8) * s.dt / 3.0)) < 1e-15
+    s3 = _sys(P=8, nve=True)
+    assert s3.pile_coeffs(0) == (1.0, 0.0) and s3.pile_coeffs(5) == (1.0, 0.0)
+
+
+# ---------------------------------------------------------------- forces
+def _lj_box(N=24, L=6.0, seed=3, rc=2.5, P=1):
+    rng = np.random.default_rng(seed)
+    # jittered grid so that no two atoms overlap
+    g = int(math.ceil(N ** (1 / 3)))
+    pts = np.stack(np.meshgrid(*[np.arange(g)] * 3, indexing="ij"), -1).reshape(-1, 3)[:N]
+    x = (pts + 0.5) * (L / g) + rng.uniform(-0.15, 0.15, (N, 3)) * (L / g)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, pot=oracle.POT_PAIR,
+                      box=(L, L, L), lj_eps=1.0, lj_sigma=1.0, lj_rc=rc)
+    return s, x
+
+
+def _fd_check(s, x1, h=1e-6, tol=1e-6):
+    f, U = s.forces(x1[None])
+    f = f[0]
+    num = np.zeros_like(x1)
+    for i in range(x1.shape[0]):
+        for d in range(3):
+            xp = x1.copy(); xp[i, d] += h
+            xm = x1.copy(); xm[i, d] -= h
+            num[i, d] = -(s.forces(xp[None])[1][0] - s.forces(xm[None])[1][0]) / (2 * h)
+    assert np.abs(num - f).max() <= tol * max(1.0, np.abs(f).max())
+    return f
+
+
+def test_lj_force_is_minus_gradient_and_newton3():
+    s, x = _lj_box(N=20, L=6.5)
+    f = _fd_check(s, x)
+    assert np.abs(f.sum(axis=0)).max() < 1e-11 * np.abs(f).max()
+
+
+def test_lj_small_box_equals_replicated_box():
+    """A box with L < 2 rc (image sum) against its 3x3x3 replica (minimum image)."""
+    s, x = _lj_box(N=8, L=3.4, seed=5)
+    f, U = s.forces(x[None])
+    L = 3.4
+    shifts = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3) * L
+    xs = (x[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
+    big = oracle.System(n_atoms=xs.shape[0], n_beads=1, mass=np.ones(xs.shape[0]), temp=1.0,
+                        pot=oracle.POT_PAIR, box=(3 * L,) * 3, lj_eps=1.0, lj_sigma=1.0, lj_rc=2.5)
+    fb, Ub = big.forces(xs[None])
+    assert np.abs(fb[0, :8] - f[0]).max() <= 1e-12 * np.abs(f).max()
+    assert abs(Ub[0] / 27 - U[0]) <= 1e-12 * abs(U[0])
+    _fd_check(s, x)
+
+
+def test_lj_pair_special_values():
+    rc = 2.5
+    urc = 4 * (rc ** -12 - rc ** -6)
+    for r, u_ref, f_ref in [(2 ** (1 / 6), -1.0 - urc, 0.0), (1.0, -urc, 24.0),
+                            (2.6, 0.0, 0.0)]:
+        s = oracle.System(n_atoms=2, n_beads=1, mass=np.ones(2), temp=1.0, pot=oracle.POT_PAIR,
+                          box=(20.0,) * 3, lj_eps=1.0, lj_sigma=1.0, lj_rc=rc)
+        x = np.array([[[1.0, 1.0, 1.0], [1.0 + r, 1.0, 1.0]]])
+        f, U = s.forces(x)
+        assert abs(U[0] - u_ref) < 1e-14
+        assert abs(f[0, 0, 0] + f_ref) < 1e-12 and abs(f[0, 1, 0] - f_ref) < 1e-12
+
+
+def test_bond_and_masked_lj():
+    """Water-shaped terms: U = K (r - r0)^2 per bond; LJ only among active atoms."""
+    spec = inputs.water(n_atoms=24, n_beads=1, seed=1)
+    s = oracle.System.from_spec(spec)
+    x = spec.x0[0]
+    # stretch one bond by 0.1: bond energy K * 0.01
+    s_b = oracle.System.from_spec(spec)
+    s_b.lj_eps = 0.0
+    f, U = s_b.forces(x[None])
+    r = np.linalg.norm(x[spec.bonds[:, 0]] - x[spec.bonds[:, 1]], axis=1)
+    assert abs(U[0] - (450.0 * (r - 0.96) ** 2).sum()) < 1e-12
+    # forces vanish on H atoms' LJ (inactive) -> only bond force on H
+    _fd_check(s, x, h=1e-6, tol=1e-6)
+    act = spec.lj_active.astype(bool)
+    s_nb = oracle.System.from_spec(spec)
+    s_nb.bond_k = 0.0
+    f2, _ = s_nb.forces(x[None])
+    assert np.all(f2[0][~act] == 0.0)
+
+
+def test_harmonic_force_exact():
+    spec = inputs.harmonic_tiny(n_atoms=5, n_beads=3)
+    s = oracle.System.from_spec(spec)
+    f, U = s.forces(spec.x0)
+    assert np.array_equal(f, -spec.x0)
+    assert np.allclose(U, 0.5 * (spec.x0 ** 2).sum(axis=(1, 2)), rtol=1e-15)
+
+
+# ---------------------------------------------------------------- whole step
+def test_p1_is_velocity_verlet():
+    """P = 1, NVE: the step is textbook velocity Verlet on the classical system."""
+    s, x = _lj_box(N=16, L=5.5, seed=9)
+    s.n_beads, s.nve, s.dt = 1, True, 0.002
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal((1, 16, 3))
+    st = oracle.State(s, x[None], v)
+    st.step(50)
+    xv, vv = x.copy(), v[0].copy()
+    a = s.forces(xv[None])[0][0]
+    for _ in range(50):
+        xv = xv + s.dt * vv + 0.5 * s.dt * s.dt * a
+        a2 = s.forces(xv[None])[0][0]
+        vv = vv + 0.5 * s.dt * (a + a2)
+        a = a2
+    assert np.abs(st.x[0] - xv).max() < 1e-11
+    assert np.abs(st.v[0] - vv).max() < 1e-11
+
+
+def test_free_ring_polymer_nve_conserves_h():
+    spec = inputs.free_ring_polymer(n_atoms=6, n_beads=8, dt=0.05)
+    st = oracle.State.from_spec(spec)
+    h0 = st.estimators()["etot"]
+    st.step(10000)
+    assert abs(st.estimators()["etot"] - h0) <= 1e-12 * abs(h0)
+
+
+def test_harmonic_nve_h_bounded_no_drift():
+    spec = inputs.harmonic_tiny(n_atoms=4, n_beads=4, ensemble=inputs.NVE)
+    st = oracle.State.from_spec(spec)
+    h = []
+    for _ in range(200):
+        st.step(100)
+        h.append(st.estimators()["etot"])
+    h = np.array(h)
+    h0 = h[0]
+    # O((omega dt)^2) fluctuation, no secular drift
+    assert np.abs(h - h0).max() < 5e-3 * abs(h0)
+    assert abs(h[100:].mean() - h[:100].mean()) < 1e-3 * abs(h0)
+
+
+def test_estimators_nm_forms_equal_bead_forms():
+    spec = inputs.lj_liquid(n_atoms=32, n_beads=6, seed=4)
+    st = oracle.State.from_spec(spec)
+    st.step(3)
+    e = st.estimators()
+    assert abs(st.sys.spring_energy_nm(st.x) - e["espring"]) <= 1e-13 * abs(e["espring"])
+    assert abs(st.sys.kcv_nm(st.x, st.f) - e["kcv"]) <= 1e-12 * abs(e["kcv"])
+    assert abs(e["etot"] - (e["ekin"] + e["espring"] + e["epot"])) <= 1e-14 * abs(e["etot"])
+
+
+def test_estimators_p1_classical():
+    spec = inputs.lj_liquid(n_atoms=32, n_beads=1, seed=4)
+    st = oracle.State.from_spec(spec)
+    e = st.estimators()
+    assert e["espring"] == 0.0
+    assert e["kprim"] == pytest.approx(1.5 * 32 * 0.7, rel=1e-15)
+    assert e["kcv"] == pytest.approx(1.5 * 32 * 0.7, rel=1e-15)
+
+
+def _block_mean(a, nb=20):
+    a = np.asarray(a)
+    b = a[: len(a) // nb * nb].reshape(nb, -1).mean(axis=1)
+    return b.mean(), b.std(ddof=1) / math.sqrt(nb)
+
+
+def harmonic_x2_closed_form(P, beta, m=1.0, w=1.0, hbar=1.0):
+    """Finite-P harmonic oscillator: <x^2> = (1/(beta m)) sum_k 1/(w^2 + w_k^2),
+    w_k = 2 (P / (beta hbar)) sin(pi k / P)."""
+    wn = P / (beta * hbar)
+    return sum(1.0 / (w * w + (2 * wn * math.sin(math.pi * k / P)) ** 2) for k in range(P)) / (beta * m)
+
+
+def test_closed_form_value():
+    assert harmonic_x2_closed_form(4, 4.0) == pytest.approx(7 / 15, rel=1e-15)
+    # quantum limit 1/(2 tanh(beta/2)) for P -> infinity; classical limit 1/beta at P = 1
+    assert harmonic_x2_closed_form(4000, 4.0) == pytest.approx(0.5 / math.tanh(2.0), rel=1e-5)
+    assert harmonic_x2_closed_form(1, 4.0) == pytest.approx(0.25, rel=1e-15)
+
+
+@pytest.mark.slow
+def test_harmonic_config_x2_matches_closed_form():
+    """N=64, P=4, kT=0.25, dt=0.05, tau=1, 2000 steps: <x^2> per dim = 7/15,
+    <K_PR> = <K_CV> = (3/2) m w^2 <x^2> = 0.7 per atom, Var K_CV < Var K_PR."""
+    spec = inputs.harmonic_tiny(seed=20260213)
+    st = oracle.State.from_spec(spec)
+    x2, kpr, kcv, temp = [], [], [], []
+    for s in range(spec.nsteps):
+        st.step(1)
+        if s >= 400:
+            x2.append((st.x ** 2).mean())
+            e = st.estimators()
+            kpr.append(e["kprim"] / 64)
+            kcv.append(e["kcv"] / 64)
+            temp.append(e["temp"])
+    m, se = _block_mean(x2)
+    assert abs(m - 7 / 15) < 3.5 * se, (m, se)
+    assert abs(m - 0.518657) > 3 * se and abs(m - 0.25) > 3 * se
+    for series in (kpr, kcv):
+        mm, ss = _block_mean(series)
+        assert abs(mm - 0.7) < 3.5 * ss, (mm, ss)
+    assert np.var(kcv) < np.var(kpr)
+    mt, st_ = _block_mean(temp)
+    assert abs(mt - 0.25) < 3.5 * st_ + 0.25 * 2e-3
+
+
+@pytest.mark.slow
+def test_free_rp_nvt_mode_variances_exact():
+    """U = 0 with the thermostat: A and O are exact, so <v~_k^2> = P kT/m and
+    <x~_k^2> = P kT / (m w_k^2) (k >= 1) hold for any dt."""
+    P, kT = 8, 1.0
+    spec = inputs.free_ring_polymer(n_atoms=64, n_beads=P, dt=0.05, ensemble=inputs.NVT, kT=kT)
+    spec.mass = np.ones(64)
+    spec.v0 = spec.v0 * 0 + np.random.default_rng(2).standard_normal(spec.v0.shape) * math.sqrt(P)
+    st = oracle.State.from_spec(spec)
+    wn = P * kT / spec.hbar
+    st.step(300)
+    xs, vs = [], []
+    for _ in range(1500):
+        st.step(1)
+        xs.append(oracle.to_normal(st.x))
+        vs.append(st.vt.copy())
+    xs, vs = np.array(xs), np.array(vs)
+    for k in range(1, P):
+        wk = 2 * wn * math.sin(math.pi * k / P)
+        m, se = _block_mean((xs[:, k] ** 2).mean(axis=(1, 2)))
+        assert abs(m - P * kT / wk ** 2) < 4 * se, (k, m, P * kT / wk ** 2, se)
+    for k in range(P):
+        m, se = _block_mean((vs[:, k] ** 2).mean(axis=(1, 2)))
+        assert abs(m - P * kT) < 4 * se, (k, m, se)
