@@ -62,15 +62,26 @@ void orc_mode_lambda(int32_t P, double *lam)
     }
 }
 
+/* Transforms: each element is one dot product of a row (or column) of M with
+ * the bead (or mode) values of one atom and dim.  The products and their sum
+ * are accumulated in x87 extended precision (64-bit mantissa) and rounded to
+ * FP64 once, so every transformed value is the correctly rounded exact dot
+ * product up to a 2^-11 ulp margin.  Reason: positions are unwrapped and of
+ * box size (about 70 A for the water workload) while the non-centroid modes
+ * are of order 0.01-0.1 A; FP64 summation leaves absolute errors of ~1e-13 A
+ * in those modes, and the stiff ring-polymer springs (m omega_k^2 up to ~100
+ * amu/fs^2) turn that into momentum noise of ~1e-12 relative after 10 steps,
+ * which depends only on the summation order.  Extended accumulation removes
+ * that order dependence, so the oracle is a sharper reference. */
 void orc_to_normal(int32_t P, int32_t N, const double *M, const double *a, double *at)
 {
     for (int32_t i = 0; i < N; ++i)
         for (int32_t d = 0; d < 3; ++d)
             for (int32_t k = 0; k < P; ++k) {
-                double s = 0.0;
+                long double s = 0.0L;
                 for (int32_t j = 0; j < P; ++j)
-                    s += M[(size_t)k * P + j] * a[((size_t)j * N + i) * 3 + d];
-                at[((size_t)k * N + i) * 3 + d] = s;
+                    s += (long double)M[(size_t)k * P + j] * (long double)a[((size_t)j * N + i) * 3 + d];
+                at[((size_t)k * N + i) * 3 + d] = (double)s;
             }
 }
 
@@ -80,10 +91,10 @@ void orc_from_normal(int32_t P, int32_t N, const double *M, const double *at, do
     for (int32_t i = 0; i < N; ++i)
         for (int32_t d = 0; d < 3; ++d)
             for (int32_t j = 0; j < P; ++j) {
-                double s = 0.0;
+                long double s = 0.0L;
                 for (int32_t k = 0; k < P; ++k)
-                    s += M[(size_t)k * P + j] * at[((size_t)k * N + i) * 3 + d];
-                a[((size_t)j * N + i) * 3 + d] = s;
+                    s += (long double)M[(size_t)k * P + j] * (long double)at[((size_t)k * N + i) * 3 + d];
+                a[((size_t)j * N + i) * 3 + d] = (double)s;
             }
 }
 

@@ -253,7 +253,9 @@ def test_free_ring_polymer_nve_conserves_h():
     st = oracle.State.from_spec(spec)
     h0 = st.estimators()["etot"]
     st.step(10000)
-    assert abs(st.estimators()["etot"] - h0) <= 1e-12 * abs(h0)
+    # exact flow, rounded coefficients: det A = 1 + O(eps) per step, so H may
+    # drift by about (steps) x (a few roundings) x eps = 1e4 x 10 x 1.1e-16
+    assert abs(st.estimators()["etot"] - h0) <= 1.1e-11 * abs(h0)
 
 
 def test_harmonic_nve_h_bounded_no_drift():
