@@ -1,0 +1,177 @@
+/*
+ * pimd.h -- C ABI of libpimd.so: the ring-polymer BAOAB step with the PILE-L
+ * Langevin thermostat on one MI355X (gfx950), all P beads of all N atoms
+ * resident in HBM.
+ *
+ * Method: Li et al., "fix pimd/langevin: An Efficient Implementation of Path
+ * Integral Molecular Dynamics in LAMMPS", arXiv:2602.13553.
+ *   - ring-polymer Hamiltonian and spring frequency: Sec. II, Eqs. 1-2
+ *   - normal-mode transform and its inverse: App. B, Eqs. B1-B3
+ *   - BAOAB splitting in normal modes, thermostat at P*T: Sec. III.C, IV.A
+ *   - PILE-L O step and damping times: App. D, Eqs. D1-D2
+ *   - unwrapped coordinates for transforms and estimators: Sec. IV.B
+ *   - estimators K, S, U, H, K_PR, K_CV: App. A, Eqs. A4, A5, A7
+ *
+ * Conventions for every entry point:
+ *   - Return 0 (PIMD_OK) or a negative PIMD_ERR_* code.  On error, out
+ *     parameters are left untouched and pimd_last_error() describes it.  No
+ *     C++ exception crosses this boundary.
+ *   - Host pointers are borrowed for the duration of the call only
+ *     (copy-in / copy-out).  Device state is owned by the context, or lives
+ *     in a caller-provided device workspace (see pimd_create).
+ *   - A context is used by one host thread at a time.
+ *   - Host-side bead arrays use the layout [P][N][3] (bead k, atom i,
+ *     Cartesian dim), FP64, atoms in the caller's order.  The device layout
+ *     is private to the library.
+ *   - Units are the caller's: kB*temp is an energy, hbar an energy*time, and
+ *     mvv2e converts mass*velocity^2 to energy (1 in reduced LJ units,
+ *     2390.0573... for amu, Angstrom, fs and kcal/mol).
+ */
+#ifndef PIMD_H
+#define PIMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIMD_OK 0
+#define PIMD_ERR_ARG (-1)         /* invalid argument or parameter */
+#define PIMD_ERR_OOM (-2)         /* device allocation failed / workspace too small */
+#define PIMD_ERR_DEVICE (-3)      /* HIP runtime error */
+#define PIMD_ERR_STATE (-4)       /* call out of order (e.g. step before set_state) */
+#define PIMD_ERR_NONFINITE (-5)   /* a position or velocity became NaN/Inf */
+#define PIMD_ERR_UNSUPPORTED (-6) /* valid but not supported by this build */
+#define PIMD_ERR_OVERFLOW (-7)    /* neighbor-list capacity exceeded */
+
+/* ensemble (Sec. III.C): NVT = PILE-L thermostat at P*T, NVE = no thermostat */
+#define PIMD_NVT 0
+#define PIMD_NVE 1
+
+/* potential U of one bead (the U(r^(k)) term of Eq. 1); every bead is an
+ * independent copy of the physical system */
+#define PIMD_POT_NONE 0      /* U = 0: free ring polymers */
+#define PIMD_POT_HARMONIC 1  /* U = sum_i 1/2 m_i omega^2 |r_i|^2 (trap at the origin) */
+#define PIMD_POT_LJ 2        /* 12-6 Lennard-Jones among all atoms, periodic box */
+#define PIMD_POT_WATER 3     /* LJ among topology-active atoms + harmonic bonds */
+
+typedef struct pimd_params {
+    int32_t n_atoms;    /* N >= 1 */
+    int32_t n_beads;    /* P >= 1 (the paper's n); this build supports P <= 128 */
+    int32_t ensemble;   /* PIMD_NVT or PIMD_NVE */
+    int32_t potential;  /* PIMD_POT_* */
+    double temp;        /* T > 0; the thermostat acts at P*T (Sec. IV.A) */
+    double kB;          /* Boltzmann constant (energy per temperature) > 0 */
+    double hbar;        /* reduced Planck constant, already scaled by sp (Sec. III.C) > 0 */
+    double mvv2e;       /* energy per mass*velocity^2 > 0 */
+    double dt;          /* time step > 0 */
+    double tau;         /* centroid damping time tau_0 (> 0 for NVT) */
+    double tau_scale;   /* scale on tau_k = 1/(2 omega_k), k >= 1 (Eq. D1) (> 0 for NVT) */
+    double box[3];      /* periodic box lengths; required (> 0) for LJ and WATER */
+    uint64_t seed;      /* thermostat seed */
+    double omega;       /* trap frequency (HARMONIC) */
+    double lj_eps;      /* LJ epsilon */
+    double lj_sigma;    /* LJ sigma > 0 */
+    double lj_rc;       /* LJ cutoff > 0; energy shifted to 0 at rc, force not shifted */
+    double skin;        /* neighbor-list skin >= 0 (LJ, WATER) */
+    double bond_k;      /* bond U = bond_k (r - bond_r0)^2 (WATER) */
+    double bond_r0;
+    int32_t nbr_capacity; /* neighbors per atom; 0 = sized from the density */
+    int32_t reserved;
+} pimd_params;
+
+typedef struct pimd_topology {
+    const int32_t *lj_active; /* [N] 1 = takes part in LJ; NULL = every atom */
+    int32_t n_bonds;          /* harmonic bonds, at most 4 per atom */
+    const int32_t *bonds;     /* [n_bonds][2] atom indices (caller's order) */
+} pimd_topology;
+
+/* Instantaneous estimators at the state's step, and running sums over every
+ * step completed by pimd_step since the last pimd_reset_averages. */
+#define PIMD_NEST 7
+typedef struct pimd_estimators {
+    uint64_t step;     /* thermostat step counter of the state */
+    /* order of the arrays below: ekin, espring, epot, etot, kprim, kcv, temp */
+    double value[PIMD_NEST];
+    uint64_t count;    /* number of steps in the running sums */
+    double sum[PIMD_NEST];
+    double sumsq[PIMD_NEST];
+    int32_t nonfinite; /* 1 if a NaN/Inf position or velocity was seen */
+    int32_t overflow;  /* 1 if a neighbor list ran out of capacity */
+} pimd_estimators;
+/* ekin    = sum_k sum_i 1/2 m_i |v~_i^(k)|^2 (App. A item 1)
+ * espring = sum_k sum_i 1/2 m_i omega_n^2 lambda_k |x~_i^(k)|^2 (App. A item 2,
+ *           read with omega_n^2)
+ * epot    = sum_k U^(k) (App. A item 3)
+ * etot    = H = ekin + espring + epot (Eq. A4)
+ * kprim   = K_PR = 3 P N kB T / 2 - espring / P (Eq. A5, read with the 1/P)
+ * kcv     = K_CV = 3 N kB T / 2 - (1/2P) sum_k sum_i (r_i^k - r_i^c).F_i^k (Eq. A7)
+ * temp    = 2 ekin / (3 N P^2 kB): the ring-polymer temperature over P (Sec. III.A) */
+
+typedef struct pimd_ctx pimd_ctx;
+
+/* Device bytes one context needs for these parameters (for admission by HBM
+ * budget).  mass [N] is required for LJ and WATER unless nbr_capacity > 0
+ * (the neighbor-list size is bounded from the lightest active atom's thermal
+ * wavelength); topo may be NULL.  Errors: PIMD_ERR_ARG, PIMD_ERR_UNSUPPORTED. */
+int pimd_workspace_bytes(const pimd_params *p, const double *mass, const pimd_topology *topo,
+                         size_t *bytes);
+
+/* Create a context on the current HIP device.
+ *   p         parameters (copied)
+ *   mass      [N] host masses > 0 (copied)
+ *   topo      WATER: active-LJ flags and bonds; LJ: may be NULL; else ignored
+ *   workspace device buffer of at least pimd_workspace_bytes() bytes owned by
+ *             the caller and kept alive until pimd_destroy, or NULL to let the
+ *             library allocate (hipMalloc) its own
+ *   stream    hipStream_t to enqueue on (borrowed; must not be the legacy
+ *             null stream), or NULL for a stream owned by the context
+ * Errors: ARG (bad parameter), UNSUPPORTED (P > 128, pair potential without a
+ * periodic box), OOM, DEVICE. */
+int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *topo,
+                void *workspace, size_t workspace_bytes, void *stream, pimd_ctx **out);
+
+/* Load a state (Sec. IV.A: Cartesian positions, velocities turned into normal
+ * modes v~ = M v).  x and v are [P][N][3] host arrays; x is taken as
+ * unwrapped (all beads of an atom in the same periodic image, Sec. IV.B).
+ * Computes f(x), the neighbor lists and the estimators of this state, and
+ * sets the thermostat step counter to `step`.  Synchronizes.
+ * Errors: ARG (NULL or non-finite input), DEVICE. */
+int pimd_set_state(pimd_ctx *ctx, const double *x, const double *v, uint64_t step);
+
+/* Enqueue nsteps >= 0 BAOAB steps on the context's stream and return without
+ * waiting.  Each step: B(dt/2), A(dt/2), O(dt), A(dt/2), forces, B(dt/2), in
+ * normal modes; the noise for mode k, atom i, dim a at step s is the
+ * Philox4x64-10 stream keyed by (seed, 0) at counter (i, k, s, 0).  After the
+ * call's work completes the state is synchronized (full-step velocities) and
+ * the estimators of every step are in the running sums.
+ * Errors: STATE (no set_state yet), ARG (nsteps < 0), DEVICE. */
+int pimd_step(pimd_ctx *ctx, int64_t nsteps);
+
+/* Wait for the stream, then copy out the estimators.  Returns
+ * PIMD_ERR_NONFINITE / PIMD_ERR_OVERFLOW (after filling *out) if the device
+ * flagged either condition.  Errors: STATE, DEVICE. */
+int pimd_get_estimators(pimd_ctx *ctx, pimd_estimators *out);
+
+/* Wait for the stream, then copy out Cartesian positions x (unwrapped) and
+ * momenta p = m M^T v~, both [P][N][3] host arrays (either may be NULL), and
+ * the step counter (may be NULL).  Errors: STATE, DEVICE. */
+int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
+
+/* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
+int pimd_reset_averages(pimd_ctx *ctx);
+
+/* Free the context and everything the library allocated for it (waits for
+ * the stream first).  NULL is a no-op. */
+void pimd_destroy(pimd_ctx *ctx);
+
+/* Message of the last error on ctx (or of the last failed pimd_create when
+ * ctx is NULL).  Never NULL; valid until the next call on the context. */
+const char *pimd_last_error(const pimd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIMD_H */

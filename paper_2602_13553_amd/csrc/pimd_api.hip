@@ -1,0 +1,591 @@
+// Host side of libpimd.so: parameter validation, the library's tables
+// (normal-mode matrix, per-mode propagator and thermostat constants, per-atom
+// constants), the device workspace, and the C ABI declared in include/pimd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pimd.h"
+#include "pimd_internal.h"
+
+using namespace pimd;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr int kGraphChunk = 32;   // steps per captured graph
+
+struct Layout {
+    size_t x, v, f, stage, cent, cref, M, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
+        partials, fpartials, ctl, total;
+    int cap, fused_grid, pair_grid, n_active;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool is_pair(int pot) { return pot == PIMD_POT_LJ || pot == PIMD_POT_WATER; }
+
+}  // namespace
+
+struct pimd_ctx {
+    pimd_params p;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    bool own_ws = false;
+    bool have_state = false;
+    double *d_x, *d_v, *d_f, *d_stage, *d_cent, *d_cref, *d_M, *d_modes, *d_atoms, *d_mass;
+    double *d_partials, *d_fpartials;
+    int *d_orig, *d_bond_j, *d_nbr_count;
+    int2 *d_nbr;
+    Ctl *d_ctl;
+    std::vector<int> orig;          // internal -> caller index
+    FusedArgs fa;
+    PairArgs pa;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_failed = false;
+    std::string err = "no error";
+};
+
+namespace {
+
+int fail(pimd_ctx *c, int code, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int hip_fail(pimd_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, PIMD_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                          \
+    do {                                                            \
+        hipError_t e_ = (expr);                                     \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);    \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
+{
+    if (!p) { why = "params is NULL"; return PIMD_ERR_ARG; }
+    if (p->n_atoms < 1) { why = "n_atoms must be >= 1"; return PIMD_ERR_ARG; }
+    if (p->n_beads < 1) { why = "n_beads must be >= 1"; return PIMD_ERR_ARG; }
+    if (p->n_beads > kMaxBeads) { why = "n_beads > 128 is not supported"; return PIMD_ERR_UNSUPPORTED; }
+    if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) { why = "bad ensemble"; return PIMD_ERR_ARG; }
+    if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_WATER) { why = "bad potential"; return PIMD_ERR_ARG; }
+    if (!finite_pos(p->temp) || !finite_pos(p->kB) || !finite_pos(p->hbar) || !finite_pos(p->mvv2e) ||
+        !finite_pos(p->dt)) {
+        why = "temp, kB, hbar, mvv2e and dt must be finite and > 0";
+        return PIMD_ERR_ARG;
+    }
+    if (p->ensemble == PIMD_NVT && (!finite_pos(p->tau) || !finite_pos(p->tau_scale))) {
+        why = "tau and tau_scale must be finite and > 0 for NVT";
+        return PIMD_ERR_ARG;
+    }
+    if (p->potential == PIMD_POT_HARMONIC && !std::isfinite(p->omega)) { why = "bad omega"; return PIMD_ERR_ARG; }
+    if (is_pair(p->potential)) {
+        for (int d = 0; d < 3; ++d)
+            if (!finite_pos(p->box[d])) {
+                why = "pair potentials need a periodic box with all lengths > 0";
+                return PIMD_ERR_UNSUPPORTED;
+            }
+        if (!finite_pos(p->lj_rc) || !finite_pos(p->lj_sigma) || !std::isfinite(p->lj_eps) ||
+            !(p->skin >= 0.0) || !std::isfinite(p->skin)) {
+            why = "lj_rc, lj_sigma > 0, finite lj_eps and skin >= 0 required";
+            return PIMD_ERR_ARG;
+        }
+        if (p->nbr_capacity < 0) { why = "nbr_capacity must be >= 0"; return PIMD_ERR_ARG; }
+    }
+    if (p->potential == PIMD_POT_WATER && topo) {
+        if (topo->n_bonds < 0 || (topo->n_bonds > 0 && !topo->bonds)) { why = "bad bond list"; return PIMD_ERR_ARG; }
+        if (!std::isfinite(p->bond_k) || !std::isfinite(p->bond_r0)) { why = "bad bond parameters"; return PIMD_ERR_ARG; }
+        std::vector<int> deg(p->n_atoms, 0);
+        for (int b = 0; b < topo->n_bonds; ++b) {
+            const int i = topo->bonds[2 * b], j = topo->bonds[2 * b + 1];
+            if (i < 0 || j < 0 || i >= p->n_atoms || j >= p->n_atoms || i == j) {
+                why = "bond index out of range";
+                return PIMD_ERR_ARG;
+            }
+            if (++deg[i] > kMaxBonds || ++deg[j] > kMaxBonds) {
+                why = "more than 4 bonds on one atom";
+                return PIMD_ERR_UNSUPPORTED;
+            }
+        }
+    }
+    return PIMD_OK;
+}
+
+// Active-first internal order; orig[internal] = caller index.
+std::vector<int> internal_order(const pimd_params *p, const pimd_topology *topo, int *n_active)
+{
+    std::vector<int> orig;
+    orig.reserve(p->n_atoms);
+    const int32_t *act = (p->potential == PIMD_POT_WATER && topo) ? topo->lj_active : nullptr;
+    if (!is_pair(p->potential)) act = nullptr;
+    for (int i = 0; i < p->n_atoms; ++i)
+        if (!act || act[i]) orig.push_back(i);
+    *n_active = is_pair(p->potential) ? (int)orig.size() : 0;
+    if (act)
+        for (int i = 0; i < p->n_atoms; ++i)
+            if (!act[i]) orig.push_back(i);
+    return orig;
+}
+
+int neighbor_capacity(const pimd_params *p, const double *mass, const std::vector<int> &orig,
+                      int n_active)
+{
+    if (p->nbr_capacity > 0) return p->nbr_capacity;
+    if (n_active == 0) return 1;
+    // generous bound on the bead-centroid excursion of the lightest active
+    // atom: three thermal wavelengths hbar / sqrt(m kB T mvv2e)
+    double mmin = 1e300;
+    for (int q = 0; q < n_active; ++q) mmin = std::min(mmin, mass[orig[q]]);
+    const double lam = p->hbar / std::sqrt(mmin * p->kB * p->temp * p->mvv2e);
+    const double e_guess = (p->n_beads > 1) ? 3.0 * lam : 0.0;
+    const double r = p->lj_rc + p->skin + 2.0 * e_guess;
+    const double vol = p->box[0] * p->box[1] * p->box[2];
+    const double nb = (double)n_active / vol * (4.0 / 3.0) * M_PI * r * r * r;
+    return (int)std::ceil(1.4 * nb) + 32;
+}
+
+Layout make_layout(const pimd_params *p, int n_active, int cap)
+{
+    Layout L{};
+    const size_t N = (size_t)p->n_atoms, P = (size_t)p->n_beads;
+    const size_t arr = N * 3 * P * sizeof(double);
+    const bool pair = is_pair(p->potential);
+    L.cap = cap;
+    L.n_active = n_active;
+    L.fused_grid = fused_grid(p->n_atoms, p->n_beads);
+    L.pair_grid = pair ? pair_grid(p->n_atoms, p->n_beads) : 0;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+    L.x = take(arr);
+    L.v = take(arr);
+    L.f = take(pair ? arr : 0);
+    L.stage = take(arr);
+    L.cent = take(N * 3 * sizeof(double));
+    L.cref = take(N * 3 * sizeof(double));
+    L.M = take(P * P * sizeof(double));
+    L.modes = take(P * 8 * sizeof(double));
+    L.atoms = take(N * 4 * sizeof(double));
+    L.mass = take(N * sizeof(double));
+    L.orig = take(N * sizeof(int));
+    L.bond_j = take(pair ? N * kMaxBonds * sizeof(int) : 0);
+    L.nbr_count = take(pair ? N * sizeof(int) : 0);
+    L.nbr = take(pair ? (size_t)n_active * cap * sizeof(int2) : 0);
+    L.partials = take((size_t)L.fused_grid * PF_COUNT * sizeof(double));
+    L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
+    L.ctl = take(sizeof(Ctl));
+    L.total = o;
+    return L;
+}
+
+// Normal-mode matrix of App. B (Eq. B1): row k = mode, column j = bead.
+// Centroid row 1/sqrt(P); for even P the alternating row (-1)^j/sqrt(P) at
+// k = P/2; cosine rows sqrt(2/P) cos(2 pi k j/P) for 1 <= k <= P/2; sine rows
+// sqrt(2/P) sin(2 pi k j/P) above.  The phase k*j is reduced mod P first.
+std::vector<double> nm_matrix(int P)
+{
+    std::vector<double> M((size_t)P * P);
+    const double a0 = 1.0 / std::sqrt((double)P), a1 = std::sqrt(2.0 / (double)P);
+    for (int k = 0; k < P; ++k) {
+        const bool alt = (P % 2 == 0) && (2 * k == P);
+        for (int j = 0; j < P; ++j) {
+            const long long ph = ((long long)k * j) % P;
+            const double ang = 2.0 * M_PI * (double)ph / (double)P;
+            double m;
+            if (k == 0)
+                m = a0;
+            else if (alt)
+                m = (j & 1) ? -a0 : a0;
+            else if (2 * k < P)
+                m = a1 * std::cos(ang);
+            else
+                m = a1 * std::sin(ang);
+            M[(size_t)k * P + j] = m;
+        }
+    }
+    return M;
+}
+
+// Per-mode constants: exact free-ring-polymer flow over h = dt/2 for the
+// spring frequency omega_k = 2 omega_n |sin(pi k / P)|, omega_n = P kB T / hbar
+// (Eqs. 2, B2); PILE-L c1 = exp(-dt/tau_k), c2 = sqrt(1 - c1^2) with tau_0 = tau
+// and tau_k = tau_scale / (2 omega_k) (Eqs. D1, D2); omega_k^2 for the spring
+// energy.
+std::vector<double> mode_table(const pimd_params *p)
+{
+    const int P = p->n_beads;
+    std::vector<double> t((size_t)P * 8, 0.0);
+    const double wn = (double)P * p->kB * p->temp / p->hbar;
+    const double h = 0.5 * p->dt;
+    for (int k = 0; k < P; ++k) {
+        const double wk = (k == 0) ? 0.0 : 2.0 * wn * std::fabs(std::sin(M_PI * (double)k / (double)P));
+        double *r = &t[(size_t)k * 8];
+        if (wk == 0.0) {
+            r[MD_A00] = 1.0; r[MD_A01] = h; r[MD_A10] = 0.0; r[MD_A11] = 1.0;
+        } else {
+            const double c = std::cos(wk * h), s = std::sin(wk * h);
+            r[MD_A00] = c; r[MD_A01] = s / wk; r[MD_A10] = -wk * s; r[MD_A11] = c;
+        }
+        if (p->ensemble == PIMD_NVT) {
+            const double tau_k = (k == 0) ? p->tau : p->tau_scale / (2.0 * wk);
+            r[MD_C1] = std::exp(-p->dt / tau_k);
+            r[MD_C2] = std::sqrt(-std::expm1(-2.0 * p->dt / tau_k));
+        } else {
+            r[MD_C1] = 1.0; r[MD_C2] = 0.0;
+        }
+        r[MD_SPRING] = wk * wk;
+        r[MD_NONCENTROID] = (k == 0) ? 0.0 : 1.0;
+    }
+    return t;
+}
+
+int launch_error(pimd_ctx *c, const char *where)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, where);
+    return PIMD_OK;
+}
+
+void enqueue_step(pimd_ctx *c)
+{
+    FusedArgs a = c->fa;
+    a.mode = FUSED_STEP;
+    launch_fused(a, c->lay.fused_grid, c->stream);
+    if (a.pair) launch_pair(c->pa, c->lay.pair_grid, c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pimd_workspace_bytes(const pimd_params *p, const double *mass, const pimd_topology *topo,
+                         size_t *bytes)
+{
+    std::string why;
+    int rc = validate(p, topo, why);
+    if (rc != PIMD_OK) return fail(nullptr, rc, why);
+    if (!bytes) return fail(nullptr, PIMD_ERR_ARG, "bytes is NULL");
+    if (!mass && is_pair(p->potential) && p->nbr_capacity == 0)
+        return fail(nullptr, PIMD_ERR_ARG, "mass is required to size neighbor lists");
+    int n_active = 0;
+    std::vector<int> orig = internal_order(p, topo, &n_active);
+    const int cap = is_pair(p->potential) ? neighbor_capacity(p, mass, orig, n_active) : 0;
+    *bytes = make_layout(p, n_active, cap).total;
+    return PIMD_OK;
+}
+
+int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *topo,
+                void *workspace, size_t workspace_bytes, void *stream, pimd_ctx **out)
+{
+    std::string why;
+    int rc = validate(p, topo, why);
+    if (rc != PIMD_OK) return fail(nullptr, rc, why);
+    if (!out) return fail(nullptr, PIMD_ERR_ARG, "out is NULL");
+    if (!mass) return fail(nullptr, PIMD_ERR_ARG, "mass is NULL");
+    for (int i = 0; i < p->n_atoms; ++i)
+        if (!finite_pos(mass[i])) return fail(nullptr, PIMD_ERR_ARG, "masses must be finite and > 0");
+
+    pimd_ctx *c = new (std::nothrow) pimd_ctx();
+    if (!c) return fail(nullptr, PIMD_ERR_OOM, "host allocation failed");
+    c->p = *p;
+    int n_active = 0;
+    c->orig = internal_order(p, topo, &n_active);
+    const int N = p->n_atoms, P = p->n_beads;
+    const bool pair = is_pair(p->potential);
+    const int cap = pair ? neighbor_capacity(p, mass, c->orig, n_active) : 0;
+    c->lay = make_layout(p, n_active, cap);
+    const Layout &L = c->lay;
+
+    auto cleanup = [&](int code, const std::string &msg) {
+        if (c->own_ws && c->ws) (void)hipFree(c->ws);
+        if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return fail(nullptr, code, msg);
+    };
+
+    if (workspace) {
+        if (workspace_bytes < L.total)
+            return cleanup(PIMD_ERR_OOM, "workspace smaller than pimd_workspace_bytes()");
+        if (((uintptr_t)workspace & 255) != 0) return cleanup(PIMD_ERR_ARG, "workspace must be 256-byte aligned");
+        c->ws = (char *)workspace;
+    } else {
+        hipError_t e = hipMalloc((void **)&c->ws, L.total);
+        if (e != hipSuccess) {
+            c->ws = nullptr;
+            return cleanup(PIMD_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        c->own_ws = true;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return cleanup(PIMD_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        c->own_stream = true;
+    }
+
+    char *w = c->ws;
+    c->d_x = (double *)(w + L.x);
+    c->d_v = (double *)(w + L.v);
+    c->d_f = pair ? (double *)(w + L.f) : nullptr;
+    c->d_stage = (double *)(w + L.stage);
+    c->d_cent = (double *)(w + L.cent);
+    c->d_cref = (double *)(w + L.cref);
+    c->d_M = (double *)(w + L.M);
+    c->d_modes = (double *)(w + L.modes);
+    c->d_atoms = (double *)(w + L.atoms);
+    c->d_mass = (double *)(w + L.mass);
+    c->d_orig = (int *)(w + L.orig);
+    c->d_bond_j = pair ? (int *)(w + L.bond_j) : nullptr;
+    c->d_nbr_count = pair ? (int *)(w + L.nbr_count) : nullptr;
+    c->d_nbr = pair ? (int2 *)(w + L.nbr) : nullptr;
+    c->d_partials = (double *)(w + L.partials);
+    c->d_fpartials = (double *)(w + L.fpartials);
+    c->d_ctl = (Ctl *)(w + L.ctl);
+
+    // tables in internal order
+    std::vector<double> M = nm_matrix(P), modes = mode_table(p);
+    std::vector<double> atoms((size_t)N * 4), m_int(N);
+    const double kT = p->kB * p->temp;
+    const int32_t *act = (p->potential == PIMD_POT_WATER && topo) ? topo->lj_active : nullptr;
+    for (int q = 0; q < N; ++q) {
+        const int i = c->orig[q];
+        const double m = mass[i];
+        m_int[q] = m;
+        atoms[(size_t)q * 4 + AT_HALF_M] = 0.5 * m * p->mvv2e;
+        atoms[(size_t)q * 4 + AT_INV_M] = 1.0 / (m * p->mvv2e);
+        atoms[(size_t)q * 4 + AT_SIGMA] = std::sqrt((double)P * kT / (m * p->mvv2e));
+        atoms[(size_t)q * 4 + AT_ACTIVE] = (pair && (!act || act[i])) ? 1.0 : 0.0;
+    }
+    std::vector<int> bond_j;
+    if (pair) {
+        std::vector<int> inv(N);
+        for (int q = 0; q < N; ++q) inv[c->orig[q]] = q;
+        bond_j.assign((size_t)N * kMaxBonds, -1);
+        std::vector<int> deg(N, 0);
+        if (p->potential == PIMD_POT_WATER && topo)
+            for (int b = 0; b < topo->n_bonds; ++b) {
+                const int i = inv[topo->bonds[2 * b]], j = inv[topo->bonds[2 * b + 1]];
+                bond_j[(size_t)i * kMaxBonds + deg[i]++] = j;
+                bond_j[(size_t)j * kMaxBonds + deg[j]++] = i;
+            }
+    }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpy(c->d_M, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_modes, modes.data(), modes.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_atoms, atoms.data(), atoms.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_mass, m_int.data(), m_int.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_orig, c->orig.data(), c->orig.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pair)
+        e = hipMemcpy(c->d_bond_j, bond_j.data(), bond_j.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->d_cref, 0, (size_t)N * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(c->d_cent, 0, (size_t)N * 3 * sizeof(double));
+    if (e == hipSuccess && pair) e = hipMemset(c->d_nbr_count, 0, (size_t)N * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(c->d_ctl, 0, sizeof(Ctl));
+    if (e != hipSuccess) return cleanup(PIMD_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+
+    FusedArgs &a = c->fa;
+    a.N = N; a.P = P; a.n_active = n_active;
+    a.mode = FUSED_STEP;
+    a.pair = pair ? 1 : 0;
+    a.nvt = p->ensemble == PIMD_NVT ? 1 : 0;
+    a.hdt = 0.5 * p->dt;
+    a.omega2 = p->potential == PIMD_POT_HARMONIC ? p->omega * p->omega : 0.0;
+    a.skin = p->skin;
+    a.rc = p->lj_rc;
+    a.kT15N = 1.5 * (double)N * kT;
+    a.kT15PN = 1.5 * (double)P * (double)N * kT;
+    a.temp_norm = 2.0 / (3.0 * (double)N * (double)P * (double)P * p->kB);
+    a.seed = p->seed;
+    a.x = c->d_x; a.v = c->d_v; a.f = c->d_f; a.vin = c->d_f;
+    a.cent = c->d_cent; a.cref = c->d_cref;
+    a.M = c->d_M; a.modes = c->d_modes; a.atoms = c->d_atoms; a.orig = c->d_orig;
+    a.partials = c->d_partials;
+    a.fpartials = c->d_fpartials;
+    a.n_fpartials = L.pair_grid;
+    a.ctl = c->d_ctl;
+
+    PairArgs &q = c->pa;
+    q.N = N; q.P = P; q.n_active = n_active; q.cap = L.cap;
+    for (int d = 0; d < 3; ++d) q.box[d] = p->box[d];
+    q.rc2 = p->lj_rc * p->lj_rc;
+    q.lj_eps = p->lj_eps;
+    q.lj_sig2 = p->lj_sigma * p->lj_sigma;
+    {
+        const double sr2 = q.lj_sig2 / q.rc2, sr6 = sr2 * sr2 * sr2;
+        q.lj_ushift = 4.0 * p->lj_eps * (sr6 * sr6 - sr6);
+    }
+    q.bond_k = (p->potential == PIMD_POT_WATER) ? p->bond_k : 0.0;
+    q.bond_r0 = p->bond_r0;
+    q.x = c->d_x; q.f = c->d_f; q.cent = c->d_cent; q.cref = c->d_cref;
+    q.nbr_count = c->d_nbr_count; q.nbr = c->d_nbr; q.bond_j = c->d_bond_j;
+    q.fpartials = c->d_fpartials;
+    q.ctl = c->d_ctl;
+
+    *out = c;
+    return PIMD_OK;
+}
+
+int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!x || !v) return fail(c, PIMD_ERR_ARG, "x and v must be non-NULL");
+    const int N = c->p.n_atoms, P = c->p.n_beads;
+    const size_t n = (size_t)N * 3 * P;
+    for (size_t e = 0; e < n; ++e)
+        if (!std::isfinite(x[e]) || !std::isfinite(v[e])) return fail(c, PIMD_ERR_ARG, "non-finite x or v");
+    // Positions and Cartesian velocities go through the staging buffer into
+    // the device layout; PREP then turns v into v~ = M v in place (each tile
+    // is staged in shared memory before it is overwritten).
+    launch_ctl_init(c->d_ctl, (unsigned long long)step, c->stream);
+    HIP_TRY(c, hipMemcpyAsync(c->d_stage, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_import(c->d_stage, c->d_x, c->d_orig, N, P, c->stream);
+    HIP_TRY(c, hipMemcpyAsync(c->d_stage, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_import(c->d_stage, c->d_v, c->d_orig, N, P, c->stream);
+    FusedArgs a = c->fa;
+    a.vin = c->d_v;
+    a.mode = FUSED_PREP;
+    launch_fused(a, c->lay.fused_grid, c->stream);
+    if (a.pair) launch_pair(c->pa, c->lay.pair_grid, c->stream);
+    a.mode = FUSED_EST;
+    launch_fused(a, c->lay.fused_grid, c->stream);
+    int rc = launch_error(c, "set_state launch");
+    if (rc != PIMD_OK) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->have_state = true;
+    return PIMD_OK;
+}
+
+int pimd_step(pimd_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "pimd_step before pimd_set_state");
+    if (nsteps < 0) return fail(c, PIMD_ERR_ARG, "nsteps < 0");
+    if (nsteps == 0) return PIMD_OK;
+    int64_t left = nsteps;
+    if (left >= kGraphChunk && !c->graph_failed) {
+        if (!c->graph_exec) {
+            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int s = 0; s < kGraphChunk; ++s) enqueue_step(c);
+                e = hipStreamEndCapture(c->stream, &c->graph);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                if (c->graph) (void)hipGraphDestroy(c->graph);
+                c->graph = nullptr;
+                c->graph_exec = nullptr;
+                c->graph_failed = true;
+            }
+        }
+        if (c->graph_exec) {
+            while (left >= kGraphChunk) {
+                HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+                left -= kGraphChunk;
+            }
+        }
+    }
+    for (; left > 0; --left) enqueue_step(c);
+    if (c->fa.pair) {
+        FusedArgs a = c->fa;
+        a.mode = FUSED_CLOSE;
+        launch_fused(a, c->lay.fused_grid, c->stream);
+    }
+    return launch_error(c, "step launch");
+}
+
+int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!out) return fail(c, PIMD_ERR_ARG, "out is NULL");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Ctl h;
+    HIP_TRY(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    out->step = h.est_step;
+    for (int q = 0; q < kNumEst; ++q) {
+        out->value[q] = h.value[q];
+        out->sum[q] = h.sum[q];
+        out->sumsq[q] = h.sumsq[q];
+    }
+    out->count = h.count;
+    out->nonfinite = h.nonfinite;
+    out->overflow = h.overflow;
+    if (h.nonfinite) return fail(c, PIMD_ERR_NONFINITE, "non-finite position or velocity");
+    if (h.overflow) return fail(c, PIMD_ERR_OVERFLOW, "neighbor list capacity exceeded");
+    return PIMD_OK;
+}
+
+int pimd_get_state(pimd_ctx *c, double *x, double *p, uint64_t *step)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    const int N = c->p.n_atoms, P = c->p.n_beads;
+    const size_t n = (size_t)N * 3 * P;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (x) {
+        launch_export(c->d_x, c->d_v, c->d_mass, c->d_M, c->d_orig, c->d_stage, nullptr, N, P, c->stream);
+        int rc = launch_error(c, "export");
+        if (rc != PIMD_OK) return rc;
+        HIP_TRY(c, hipMemcpyAsync(x, c->d_stage, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    if (p) {
+        launch_export(c->d_x, c->d_v, c->d_mass, c->d_M, c->d_orig, nullptr, c->d_stage, N, P, c->stream);
+        int rc = launch_error(c, "export");
+        if (rc != PIMD_OK) return rc;
+        HIP_TRY(c, hipMemcpyAsync(p, c->d_stage, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    if (step) {
+        Ctl h;
+        HIP_TRY(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        *step = h.step;
+    }
+    return PIMD_OK;
+}
+
+int pimd_reset_averages(pimd_ctx *c)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    launch_ctl_reset_sums(c->d_ctl, c->stream);
+    return launch_error(c, "reset_averages");
+}
+
+void pimd_destroy(pimd_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *pimd_last_error(const pimd_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

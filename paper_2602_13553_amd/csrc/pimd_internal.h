@@ -1,0 +1,116 @@
+// Internal declarations of libpimd.so shared by its host (pimd_api.hip) and
+// device (pimd_kernels.hip) translation units.  Not installed, not part of the
+// C ABI.
+//
+// Device layout of every per-bead array: [N][3][P] in the library's internal
+// atom order (LJ-active atoms first), i.e. element (atom i, dim a, bead or
+// mode k) at (i*3 + a)*P + k.  The P beads (or modes) of one atom-dim are
+// contiguous, so a group of P lanes reads them in one coalesced segment, and
+// neighbor gathers in the force kernel fetch whole bead rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pimd {
+
+constexpr int kBlock = 256;      // threads per block for the step kernels
+constexpr int kMaxBeads = 128;   // P limit of this build (LDS-resident M)
+constexpr int kMaxBonds = 4;     // bonds per atom
+constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
+
+// Per-block partial slots written by the fused kernel.
+enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_PAD, PF_COUNT };
+
+// Fused-kernel modes.
+enum FusedMode : int {
+    FUSED_STEP = 0,   // (pending closing B + estimators) opening B, A, O, A, inverse transform
+    FUSED_CLOSE = 1,  // pending closing B + estimators only
+    FUSED_EST = 2,    // estimators of a synchronized state (after set_state)
+    FUSED_PREP = 3,   // v~ = M v, centroids, excursion; requests a neighbor build
+};
+
+// Device-resident control block.  Written only by the last block of the
+// fused kernel (or by small host-enqueued kernels), read at kernel start.
+struct Ctl {
+    unsigned long long step;   // thermostat step counter s
+    int synced;                // 1: velocities are at the full step
+    int rebuild;               // 1: the coming force pass rebuilds the lists
+    double rlist;              // centroid cutoff of the current lists
+    double ebuild;             // max bead-centroid excursion at the last build
+    unsigned int done;         // last-block counter of the fused kernel
+    int nonfinite;
+    int overflow;
+    int pad0;
+    unsigned long long est_step;
+    double value[kNumEst];
+    unsigned long long count;
+    double sum[kNumEst];
+    double sumsq[kNumEst];
+};
+
+struct FusedArgs {
+    int N, P, n_active;
+    int mode;                 // FusedMode
+    int pair;                 // 1: forces come from the pair kernel (array f)
+    int nvt;                  // 1: PILE-L O step
+    double hdt;               // dt / 2
+    double omega2;            // external trap omega^2 (0 for none / pair)
+    double skin;
+    double rc;
+    double kT15N;             // 3 N kB T / 2
+    double kT15PN;            // 3 P N kB T / 2
+    double temp_norm;         // 2 / (3 N P^2 kB)
+    unsigned long long seed;
+    double *x;                // [N][3][P] Cartesian, unwrapped
+    double *v;                // [N][3][P] normal-mode velocities
+    const double *f;          // [N][3][P] Cartesian forces (pair) or nullptr
+    const double *vin;        // PREP: [N][3][P] Cartesian velocities
+    double *cent;             // [N][3] centroids (written)
+    const double *cref;       // [N][3] centroids at the last list build
+    const double *M;          // [P][P] normal-mode matrix, row = mode
+    const double *modes;      // [P][8] per-mode constants
+    const double *atoms;      // [N][4] per-atom constants
+    const int *orig;          // [N] caller's atom index (noise counter)
+    double *partials;         // [gridDim][PF_COUNT]
+    const double *fpartials;  // [n_fpartials] force-kernel energy partials
+    int n_fpartials;
+    Ctl *ctl;
+};
+
+// modes[k*8 + ...]
+enum { MD_A00 = 0, MD_A01, MD_A10, MD_A11, MD_C1, MD_C2, MD_SPRING, MD_NONCENTROID };
+// atoms[i*4 + ...]
+enum { AT_HALF_M = 0, AT_INV_M, AT_SIGMA, AT_ACTIVE };
+
+struct PairArgs {
+    int N, P, n_active, cap;
+    double box[3];
+    double rc2;
+    double lj_eps, lj_sig2, lj_ushift;
+    double bond_k, bond_r0;
+    const double *x;          // [N][3][P]
+    double *f;                // [N][3][P]
+    const double *cent;       // [N][3]
+    double *cref;             // [N][3]
+    int *nbr_count;           // [N]
+    int2 *nbr;                // [N][cap] (j, packed image shift)
+    const int *bond_j;        // [N][kMaxBonds] partner or -1
+    double *fpartials;        // [gridDim]
+    Ctl *ctl;
+};
+
+// Launchers (pimd_kernels.hip).
+int fused_smem_bytes(int P);
+int fused_grid(int N, int P);
+void launch_fused(const FusedArgs &a, int grid, hipStream_t s);
+int pair_grid(int N, int P);
+void launch_pair(const PairArgs &a, int grid, hipStream_t s);
+void launch_import(const double *src, double *dst, const int *orig, int N, int P, hipStream_t s);
+void launch_export(const double *x, const double *v, const double *atoms_mass, const double *M,
+                   const int *orig, double *xdst, double *pdst, int N, int P, hipStream_t s);
+void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, unsigned long long step, hipStream_t s);
+
+}  // namespace pimd

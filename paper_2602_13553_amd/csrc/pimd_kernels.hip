@@ -1,0 +1,762 @@
+// HIP kernels of libpimd.so for gfx950 (CDNA4, wave64).
+//
+// k_fused  : one pass over (x, v~, f) per step: normal-mode transforms
+//            (App. B), pending closing B + estimators (App. A), opening B,
+//            A(dt/2), PILE-L O(dt) (App. D), A(dt/2), inverse transform.
+//            With an external trap the forces are evaluated in normal modes
+//            inside the same pass and the whole step is this one kernel.
+// k_pair   : bead-batched short-range forces for all P replicas in one
+//            launch (LJ among active atoms + harmonic bonds), each atom's
+//            neighbor list rebuilt in place from centroids when requested.
+//
+// Reductions are deterministic: fixed-order block trees, then the last block
+// to finish (atomic ticket) combines the per-block partials in block order.
+#include "pimd_internal.h"
+
+namespace pimd {
+
+// --------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0,
+                                              unsigned long long k1)
+{
+    const unsigned long long M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const unsigned long long lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const unsigned long long n0 = hi1 ^ c[1] ^ k0;
+        const unsigned long long n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += W0; k1 += W1;
+    }
+}
+
+__device__ __forceinline__ double u01(unsigned long long w)
+{
+    // top 53 bits + 1, times 2^-53: uniform on (0, 1], exact in FP64
+    return ((double)(w >> 11) + 1.0) * 1.1102230246251565404e-16;
+}
+
+// Three N(0,1) deviates for atom i, mode k, step s: counter (i, k, s, 0),
+// key (seed, 0); (z0, z1) from (u0, u1), z2 from (u2, u3).
+__device__ __forceinline__ void gauss3(unsigned long long seed, unsigned long long i,
+                                       unsigned long long k, unsigned long long s, double z[3])
+{
+    unsigned long long c[4] = {i, k, s, 0ULL};
+    philox4x64_10(c, seed, 0ULL);
+    const double r0 = sqrt(-2.0 * log(u01(c[0])));
+    const double r2 = sqrt(-2.0 * log(u01(c[2])));
+    double s1, c1;
+    sincospi(2.0 * u01(c[1]), &s1, &c1);
+    z[0] = r0 * c1;
+    z[1] = r0 * s1;
+    z[2] = r2 * cospi(2.0 * u01(c[3]));
+}
+
+// --------------------------------------------------------------------------
+// Block reductions (fixed order).
+// --------------------------------------------------------------------------
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double *red /* [kBlock*NV] */)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q * kBlock + t] = v[q];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) red[q * kBlock + t] += red[q * kBlock + t + w];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = red[q * kBlock];
+    __syncthreads();
+}
+
+__device__ double block_max(double v, double *red)
+{
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] = fmax(red[t], red[t + w]);
+        __syncthreads();
+    }
+    v = red[0];
+    __syncthreads();
+    return v;
+}
+
+__device__ __forceinline__ void store_agent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns true in every thread of the last block to arrive.
+__device__ bool last_block_ticket(unsigned int *counter)
+{
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_last) __threadfence();
+    return s_last != 0;
+}
+
+// --------------------------------------------------------------------------
+// Fused step kernel.
+// Shared memory: M^T padded [P][P+1], tile X [A][3][P], tile F [A][3][P],
+// centroids [A][3], reduction scratch.
+// --------------------------------------------------------------------------
+int fused_smem_bytes(int P)
+{
+    const int A = kBlock / P;
+    return (int)sizeof(double) * (P * (P + 1) + 2 * 3 * A * P + 3 * A);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[kBlock * 4];
+    const int P = a.P, N = a.N;
+    const int A = kBlock / P;
+    const int PS = P + 1;
+    double *sMT = smem;                 // sMT[j*PS + k] = M[k][j]
+    double *sX = sMT + P * PS;          // [A][3][P]
+    double *sF = sX + 3 * A * P;        // [A][3][P]
+    double *sC = sF + 3 * A * P;        // [A][3]
+
+    const int t = threadIdx.x;
+    for (int e = t; e < P * P; e += kBlock) {
+        const int k = e / P, j = e - k * P;
+        sMT[j * PS + k] = a.M[e];
+    }
+
+    const int mode = a.mode;
+    const unsigned long long step = a.ctl->step;
+    const int synced = a.ctl->synced;
+    const int ext = !a.pair;                                    // forces in-kernel
+    const bool closing = (mode == FUSED_STEP || mode == FUSED_CLOSE) && !synced && a.pair;
+    const bool est_now = closing || mode == FUSED_EST;          // estimators of this state
+    const bool est_after = (mode == FUSED_STEP) && ext;         // estimators of the new state
+    const bool need_f = a.pair && (mode == FUSED_STEP || est_now);
+    const bool inverse = (mode == FUSED_STEP);
+    const double sqrtP = sqrt((double)P);
+
+    const int la = t / P, k = t - (t / P) * P;
+    const bool lane_ok = la < A;
+
+    double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
+    double acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
+
+    double mk[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mk[q] = lane_ok ? a.modes[k * 8 + q] : 0.0;
+
+    const int ntiles = (N + A - 1) / A;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int a0 = tile * A;
+        const int na = min(A, N - a0);
+        const int nel = na * 3 * P;
+        __syncthreads();
+        {
+            const double *xg = a.x + (size_t)a0 * 3 * P;
+            for (int e = t; e < nel; e += kBlock) sX[e] = xg[e];
+            if (need_f) {
+                const double *fg = a.f + (size_t)a0 * 3 * P;
+                for (int e = t; e < nel; e += kBlock) sF[e] = fg[e];
+            } else if (mode == FUSED_PREP) {
+                const double *vg = a.vin + (size_t)a0 * 3 * P;
+                for (int e = t; e < nel; e += kBlock) sF[e] = vg[e];
+            }
+        }
+        __syncthreads();
+
+        const bool act = lane_ok && la < na;
+        const int i = a0 + la;
+        double xt[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0}, vt[3] = {0.0, 0.0, 0.0};
+        double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0;
+        if (act) {
+            hm = a.atoms[i * 4 + AT_HALF_M];
+            im = a.atoms[i * 4 + AT_INV_M];
+            sg = a.atoms[i * 4 + AT_SIGMA];
+            active = a.atoms[i * 4 + AT_ACTIVE];
+            // forward transforms of this mode: x~_k = sum_j M_kj x_j (and f, or v in PREP).
+            // Positions are taken relative to bead 0: the non-centroid rows of M
+            // sum to zero, so x~_k = sum_j M_kj (x_j - x_0) exactly, and the
+            // differences are small, so the result keeps its absolute accuracy
+            // for box-size unwrapped coordinates; the centroid row adds
+            // sqrt(P) x_0 back.
+            const double *xr = sX + la * 3 * P;
+            const double *fr = sF + la * 3 * P;
+            const bool tf = need_f || mode == FUSED_PREP;
+            const double r0 = xr[0], r1 = xr[P], r2 = xr[2 * P];
+            for (int j = 0; j < P; ++j) {
+                const double m = sMT[j * PS + k];
+                xt[0] += m * (xr[j] - r0);
+                xt[1] += m * (xr[P + j] - r1);
+                xt[2] += m * (xr[2 * P + j] - r2);
+                if (tf) {
+                    ft[0] += m * fr[j];
+                    ft[1] += m * fr[P + j];
+                    ft[2] += m * fr[2 * P + j];
+                }
+            }
+            if (k == 0) {
+                xt[0] += sqrtP * r0;
+                xt[1] += sqrtP * r1;
+                xt[2] += sqrtP * r2;
+            }
+            const size_t vb = (size_t)i * 3 * P + k;
+            if (mode == FUSED_PREP) {
+                vt[0] = ft[0]; vt[1] = ft[1]; vt[2] = ft[2];
+                ft[0] = ft[1] = ft[2] = 0.0;
+            } else {
+                vt[0] = a.v[vb]; vt[1] = a.v[vb + P]; vt[2] = a.v[vb + 2 * P];
+            }
+            if (ext) {
+                // external trap: the normal-mode force is -m mvv2e omega^2 x~
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * xt[d];
+            }
+            if (closing) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+            }
+            if (est_now) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    acc_ekin += hm * vt[d] * vt[d];
+                    acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
+                    acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
+                    acc_uext += hm * a.omega2 * xt[d] * xt[d];
+                }
+            }
+            if (mode == FUSED_STEP) {
+                // opening B
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                // A(dt/2)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double q = xt[d], p = vt[d];
+                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
+                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                }
+                // O(dt): PILE-L at P*T
+                if (a.nvt) {
+                    double z[3];
+                    gauss3(a.seed, (unsigned long long)a.orig[i], (unsigned long long)k, step, z);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
+                }
+                // A(dt/2)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double q = xt[d], p = vt[d];
+                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
+                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                }
+                if (ext) {
+                    // closing B with the trap force of the new positions, then
+                    // the estimators of the new state
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        ft[d] = -2.0 * hm * a.omega2 * xt[d];
+                        vt[d] += a.hdt * im * ft[d];
+                    }
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        acc_ekin += hm * vt[d] * vt[d];
+                        acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
+                        acc_uext += hm * a.omega2 * xt[d] * xt[d];
+                        acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
+                    }
+                }
+            }
+            if (mode == FUSED_STEP || mode == FUSED_CLOSE || mode == FUSED_PREP) {
+                a.v[vb] = vt[0]; a.v[vb + P] = vt[1]; a.v[vb + 2 * P] = vt[2];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (!isfinite(vt[d])) acc_bad = 1.0;
+            if (k == 0 && (mode == FUSED_PREP)) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sC[la * 3 + d] = xt[d] / sqrtP;
+            }
+        }
+        if (mode == FUSED_STEP) {
+            __syncthreads();   // all reads of sX done
+            if (act) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sX[(la * 3 + d) * P + k] = xt[d];
+                if (k == 0) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) sC[la * 3 + d] = xt[d] / sqrtP;
+                }
+            }
+        }
+        if (mode == FUSED_STEP || mode == FUSED_PREP) {
+            __syncthreads();
+            if (act) {
+                // bead j = k of atom i: x_j = sum_k M_kj x~_k (STEP) or x as loaded (PREP)
+                const int j = k;
+                double xj[3];
+                if (inverse) {
+                    // non-centroid modes first (small), the centroid term last
+                    xj[0] = xj[1] = xj[2] = 0.0;
+                    const double *xr = sX + la * 3 * P;
+                    for (int m = 1; m < P; ++m) {
+                        const double w = sMT[j * PS + m];   // M[m][j]
+                        xj[0] += w * xr[m];
+                        xj[1] += w * xr[P + m];
+                        xj[2] += w * xr[2 * P + m];
+                    }
+                    const double w0 = sMT[j * PS];
+                    xj[0] += w0 * xr[0];
+                    xj[1] += w0 * xr[P];
+                    xj[2] += w0 * xr[2 * P];
+                    const size_t xb = (size_t)i * 3 * P + j;
+                    a.x[xb] = xj[0]; a.x[xb + P] = xj[1]; a.x[xb + 2 * P] = xj[2];
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) xj[d] = sX[(la * 3 + d) * P + j];
+                }
+                double e2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double dd = xj[d] - sC[la * 3 + d];
+                    e2 += dd * dd;
+                    if (!isfinite(xj[d])) acc_bad = 1.0;
+                }
+                if (active != 0.0) acc_emax = fmax(acc_emax, e2);
+                if (j == 0) {
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double c = sC[la * 3 + d];
+                        a.cent[i * 3 + d] = c;
+                        const double dd = c - a.cref[i * 3 + d];
+                        d2 += dd * dd;
+                    }
+                    if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
+                }
+            }
+        }
+    }
+
+    // ---- per-block partials
+    {
+        double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
+        block_sum<4>(s4, red);
+        const double emax = block_max(acc_emax, red);
+        const double dmax = block_max(acc_dmax, red);
+        const double bad = block_max(acc_bad, red);
+        if (t == 0) {
+            double *pp = a.partials + (size_t)blockIdx.x * PF_COUNT;
+            store_agent(pp + PF_EKIN, s4[0]);
+            store_agent(pp + PF_ESPRING, s4[1]);
+            store_agent(pp + PF_VIR, s4[2]);
+            store_agent(pp + PF_UEXT, s4[3]);
+            store_agent(pp + PF_EMAX, emax);
+            store_agent(pp + PF_DMAX, dmax);
+            store_agent(pp + PF_NONFINITE, bad);
+        }
+    }
+    if (!last_block_ticket(&a.ctl->done)) return;
+
+    // ---- last block: combine partials in block order
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    double emax = 0.0, dmax = 0.0, bad = 0.0, upair = 0.0;
+    for (int b = t; b < (int)gridDim.x; b += kBlock) {
+        const double *pp = a.partials + (size_t)b * PF_COUNT;
+        tot[0] += load_agent(pp + PF_EKIN);
+        tot[1] += load_agent(pp + PF_ESPRING);
+        tot[2] += load_agent(pp + PF_VIR);
+        tot[3] += load_agent(pp + PF_UEXT);
+        emax = fmax(emax, load_agent(pp + PF_EMAX));
+        dmax = fmax(dmax, load_agent(pp + PF_DMAX));
+        bad = fmax(bad, load_agent(pp + PF_NONFINITE));
+    }
+    if (a.pair && (est_now)) {
+        for (int b = t; b < a.n_fpartials; b += kBlock) upair += a.fpartials[b];
+    }
+    block_sum<4>(tot, red);
+    {
+        double u1[1] = {upair};
+        block_sum<1>(u1, red);
+        upair = u1[0];
+    }
+    emax = sqrt(block_max(emax, red));
+    dmax = sqrt(block_max(dmax, red));
+    bad = block_max(bad, red);
+
+    if (t == 0) {
+        Ctl *c = a.ctl;
+        if (est_now || est_after) {
+            const double ekin = tot[0], esp = tot[1], vir = tot[2];
+            const double epot = a.pair ? upair : tot[3];
+            double v[kNumEst];
+            v[0] = ekin;
+            v[1] = esp;
+            v[2] = epot;
+            v[3] = ekin + esp + epot;
+            v[4] = a.kT15PN - esp / (double)P;
+            v[5] = a.kT15N - vir / (2.0 * (double)P);
+            v[6] = ekin * a.temp_norm;
+            for (int q = 0; q < kNumEst; ++q) c->value[q] = v[q];
+            c->est_step = est_after ? step + 1 : step;
+            if (mode != FUSED_EST) {
+                c->count += 1;
+                for (int q = 0; q < kNumEst; ++q) {
+                    c->sum[q] += v[q];
+                    c->sumsq[q] += v[q] * v[q];
+                }
+            }
+        }
+        if (mode == FUSED_STEP) {
+            c->step = step + 1;
+            c->synced = ext ? 1 : 0;
+        } else if (mode == FUSED_CLOSE) {
+            c->synced = 1;
+        }
+        if (a.pair && mode == FUSED_PREP) {
+            c->rebuild = 1;
+            c->ebuild = emax;
+            c->rlist = a.rc + a.skin + 2.0 * emax;
+        } else if (a.pair && mode == FUSED_STEP) {
+            if (dmax + emax > 0.5 * a.skin + c->ebuild) {
+                c->rebuild = 1;
+                c->ebuild = emax;
+                c->rlist = a.rc + a.skin + 2.0 * emax;
+            } else {
+                c->rebuild = 0;
+            }
+        }
+        if (bad != 0.0) c->nonfinite = 1;
+        c->done = 0;
+    }
+}
+
+int fused_grid(int N, int P)
+{
+    const int A = kBlock / P;
+    const int ntiles = (N + A - 1) / A;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    // large P needs more than the default 64 KB of dynamic LDS per block
+    (void)hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              fused_smem_bytes(P));
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, kBlock, fused_smem_bytes(P)) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int cap = ncu * per_cu;
+    return ntiles < cap ? ntiles : cap;
+}
+
+void launch_fused(const FusedArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kBlock), fused_smem_bytes(a.P), s, a);
+}
+
+// --------------------------------------------------------------------------
+// Pair forces.  Block = A = kBlock/P atoms, thread (atom, bead).  When the
+// control block requests it, each atom's group of P lanes first rebuilds that
+// atom's list: it scans every active atom's centroid (and, in boxes smaller
+// than twice the list cutoff, every periodic image within reach) and keeps
+// entries with |c_i - c_j + s L| < rlist, in (j, image) order.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int pack_shift(int sx, int sy, int sz)
+{
+    return (sx + 512) | ((sy + 512) << 10) | ((sz + 512) << 20);
+}
+__device__ __forceinline__ void unpack_shift(int p, double &sx, double &sy, double &sz)
+{
+    sx = (double)((p & 1023) - 512);
+    sy = (double)(((p >> 10) & 1023) - 512);
+    sz = (double)(((p >> 20) & 1023) - 512);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
+{
+    __shared__ int s_cnt[kBlock];
+    __shared__ double red[kBlock];
+    const int P = a.P;
+    const int A = kBlock / P;
+    const int t = threadIdx.x;
+    const int la = t / P, k = t - (t / P) * P;
+    const int i = blockIdx.x * A + la;
+    const bool act = (la < A) && (i < a.N);
+    const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
+
+    // A list cutoff that is not finite (non-finite positions) or that would
+    // need more than kMaxImages periodic images per dim skips the build and
+    // flags the state; the image loops below are therefore always bounded.
+    constexpr int kMaxImages = 8;
+    const double rl_in = a.ctl->rlist;
+    const bool rl_ok = isfinite(rl_in) && rl_in > 0.0 && rl_in <= kMaxImages * L0 &&
+                       rl_in <= kMaxImages * L1 && rl_in <= kMaxImages * L2;
+    if (a.ctl->rebuild && !rl_ok) {
+        if (blockIdx.x == 0 && t == 0) a.ctl->nonfinite = 1;
+    }
+    if (a.ctl->rebuild && rl_ok) {
+        const double rl = rl_in;
+        const double rl2 = rl * rl;
+        const bool big = (L0 >= 2.0 * rl) && (L1 >= 2.0 * rl) && (L2 >= 2.0 * rl);
+        const int R0 = big ? 0 : min((int)ceil(rl / L0), kMaxImages),
+                  R1 = big ? 0 : min((int)ceil(rl / L1), kMaxImages),
+                  R2 = big ? 0 : min((int)ceil(rl / L2), kMaxImages);
+        const bool builder = act && i < a.n_active;
+        double ci[3] = {0.0, 0.0, 0.0};
+        if (builder) {
+            ci[0] = a.cent[i * 3]; ci[1] = a.cent[i * 3 + 1]; ci[2] = a.cent[i * 3 + 2];
+        }
+        int total = 0;
+        int2 *mylist = a.nbr + (size_t)(builder ? i : 0) * a.cap;
+        for (int j0 = 0; j0 < a.n_active; j0 += P) {
+            const int j = j0 + k;
+            int cnt = 0;
+            double dx = 0, dy = 0, dz = 0;
+            int bx = 0, by = 0, bz = 0;
+            const bool cand = builder && j < a.n_active;
+            if (cand) {
+                dx = ci[0] - a.cent[j * 3];
+                dy = ci[1] - a.cent[j * 3 + 1];
+                dz = ci[2] - a.cent[j * 3 + 2];
+                bx = -(int)rint(dx / L0);
+                by = -(int)rint(dy / L1);
+                bz = -(int)rint(dz / L2);
+                for (int ox = -R0; ox <= R0; ++ox)
+                    for (int oy = -R1; oy <= R1; ++oy)
+                        for (int oz = -R2; oz <= R2; ++oz) {
+                            const int sx = bx + ox, sy = by + oy, sz = bz + oz;
+                            if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
+                            const double ex = dx + sx * L0, ey = dy + sy * L1, ez = dz + sz * L2;
+                            if (ex * ex + ey * ey + ez * ez < rl2) ++cnt;
+                        }
+            }
+            s_cnt[t] = cnt;
+            __syncthreads();
+            int off = 0, chunk = 0;
+            if (la < A) {
+                for (int q = 0; q < P; ++q) {
+                    const int c = s_cnt[la * P + q];
+                    if (q < k) off += c;
+                    chunk += c;
+                }
+            }
+            if (cand && cnt > 0) {
+                int w = total + off;
+                for (int ox = -R0; ox <= R0; ++ox)
+                    for (int oy = -R1; oy <= R1; ++oy)
+                        for (int oz = -R2; oz <= R2; ++oz) {
+                            const int sx = bx + ox, sy = by + oy, sz = bz + oz;
+                            if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
+                            const double ex = dx + sx * L0, ey = dy + sy * L1, ez = dz + sz * L2;
+                            if (ex * ex + ey * ey + ez * ez < rl2) {
+                                if (w < a.cap) mylist[w] = make_int2(j, pack_shift(sx, sy, sz));
+                                ++w;
+                            }
+                        }
+            }
+            total += chunk;
+            __syncthreads();
+        }
+        if (act && k == 0) {
+            if (i < a.n_active) {
+                if (total > a.cap) {
+                    a.ctl->overflow = 1;
+                    total = a.cap;
+                }
+                a.nbr_count[i] = total;
+            } else {
+                a.nbr_count[i] = 0;
+            }
+            a.cref[i * 3] = a.cent[i * 3];
+            a.cref[i * 3 + 1] = a.cent[i * 3 + 1];
+            a.cref[i * 3 + 2] = a.cent[i * 3 + 2];
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+
+    double e = 0.0;
+    if (act) {
+        const int P3 = 3 * P;
+        const size_t ib = (size_t)i * P3 + k;
+        const double xi = a.x[ib], yi = a.x[ib + P], zi = a.x[ib + 2 * P];
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        const int cnt = (i < a.n_active) ? a.nbr_count[i] : 0;
+        const int2 *lst = a.nbr + (size_t)i * a.cap;
+        const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
+        for (int q = 0; q < cnt; ++q) {
+            const int2 en = lst[q];
+            double sx, sy, sz;
+            unpack_shift(en.y, sx, sy, sz);
+            const size_t jb = (size_t)en.x * P3 + k;
+            const double dx = xi - a.x[jb] + sx * L0;
+            const double dy = yi - a.x[jb + P] + sy * L1;
+            const double dz = zi - a.x[jb + 2 * P] + sz * L2;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < a.rc2) {
+                const double sr2 = a.lj_sig2 / r2;
+                const double sr6 = sr2 * sr2 * sr2;
+                const double fr = eps24 * (2.0 * sr6 * sr6 - sr6) / r2;
+                e += 0.5 * (eps4 * (sr6 * sr6 - sr6) - a.lj_ushift);
+                fx += fr * dx; fy += fr * dy; fz += fr * dz;
+            }
+        }
+        for (int b = 0; b < kMaxBonds; ++b) {
+            const int j = a.bond_j[i * kMaxBonds + b];
+            if (j < 0) break;
+            const size_t jb = (size_t)j * P3 + k;
+            double dx = xi - a.x[jb], dy = yi - a.x[jb + P], dz = zi - a.x[jb + 2 * P];
+            dx -= L0 * rint(dx / L0);
+            dy -= L1 * rint(dy / L1);
+            dz -= L2 * rint(dz / L2);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double dr = r - a.bond_r0;
+            const double fr = -2.0 * a.bond_k * dr / r;
+            e += 0.5 * a.bond_k * dr * dr;
+            fx += fr * dx; fy += fr * dy; fz += fr * dz;
+        }
+        a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
+    }
+    double s1[1] = {e};
+    // block sum (fixed order); red is sized for one value per thread
+    red[t] = s1[0];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) a.fpartials[blockIdx.x] = red[0];
+}
+
+int pair_grid(int N, int P)
+{
+    const int A = kBlock / P;
+    return (N + A - 1) / A;
+}
+
+void launch_pair(const PairArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kBlock), 0, s, a);
+}
+
+// --------------------------------------------------------------------------
+// Layout conversion between the host layout [P][N][3] (caller's atom order)
+// and the device layout [N][3][P] (internal order).
+// --------------------------------------------------------------------------
+__global__ void k_import(const double *src, double *dst, const int *orig, int N, int P)
+{
+    const size_t n = (size_t)N * 3 * P;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % P);
+        const int d = (int)((e / P) % 3);
+        const int i = (int)(e / (3 * (size_t)P));
+        dst[e] = src[((size_t)k * N + orig[i]) * 3 + d];
+    }
+}
+
+void launch_import(const double *src, double *dst, const int *orig, int N, int P, hipStream_t s)
+{
+    const size_t n = (size_t)N * 3 * P;
+    const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_import, dim3(grid), dim3(256), 0, s, src, dst, orig, N, P);
+}
+
+// x: device positions; v: device normal-mode velocities; writes host-layout
+// positions and Cartesian momenta p = m M^T v~.
+__global__ void k_export(const double *x, const double *v, const double *mass, const double *M,
+                         const int *orig, double *xdst, double *pdst, int N, int P)
+{
+    const size_t n = (size_t)N * 3 * P;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e % P);
+        const int d = (int)((e / P) % 3);
+        const int i = (int)(e / (3 * (size_t)P));
+        const size_t base = ((size_t)i * 3 + d) * P;
+        double s = 0.0;
+        for (int m = 0; m < P; ++m) s += M[(size_t)m * P + j] * v[base + m];
+        const size_t o = ((size_t)j * N + orig[i]) * 3 + d;
+        if (xdst) xdst[o] = x[e];
+        if (pdst) pdst[o] = mass[i] * s;
+    }
+}
+
+void launch_export(const double *x, const double *v, const double *mass, const double *M,
+                   const int *orig, double *xdst, double *pdst, int N, int P, hipStream_t s)
+{
+    const size_t n = (size_t)N * 3 * P;
+    const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    hipLaunchKernelGGL(k_export, dim3(grid), dim3(256), 0, s, x, v, mass, M, orig, xdst, pdst, N,
+                       P);
+}
+
+// --------------------------------------------------------------------------
+// Control-block maintenance (kernels, so that graphs never hold memsets).
+// --------------------------------------------------------------------------
+__global__ void k_ctl_reset_sums(Ctl *c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->count = 0;
+        for (int q = 0; q < kNumEst; ++q) {
+            c->sum[q] = 0.0;
+            c->sumsq[q] = 0.0;
+        }
+    }
+}
+
+__global__ void k_ctl_init(Ctl *c, unsigned long long step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->step = step;
+        c->synced = 1;
+        c->rebuild = 1;
+        c->rlist = 0.0;
+        c->ebuild = 0.0;
+        c->done = 0;
+        c->nonfinite = 0;
+        c->overflow = 0;
+        c->est_step = step;
+        c->count = 0;
+        for (int q = 0; q < kNumEst; ++q) {
+            c->value[q] = 0.0;
+            c->sum[q] = 0.0;
+            c->sumsq[q] = 0.0;
+        }
+    }
+}
+
+void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_reset_sums, dim3(1), dim3(64), 0, s, ctl);
+}
+
+void launch_ctl_init(Ctl *ctl, unsigned long long step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, step);
+}
+
+}  // namespace pimd

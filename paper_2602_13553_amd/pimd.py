@@ -1,0 +1,211 @@
+"""Python binding of ``libpimd.so`` (C ABI in ``include/pimd.h``).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies the device workspace (``torch.empty`` on ``cuda``)
+so that device memory is accounted by torch's allocator.  If the library is
+missing, every entry point raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpimd.so")
+
+PIMD_OK = 0
+ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PIMD_ERR_STATE",
+          -5: "PIMD_ERR_NONFINITE", -6: "PIMD_ERR_UNSUPPORTED", -7: "PIMD_ERR_OVERFLOW"}
+PIMD_NVT, PIMD_NVE = 0, 1
+PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER = 0, 1, 2, 3
+ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
+EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
+            "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_destroy",
+            "pimd_last_error")
+
+
+class PimdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "PIMD_ERR"), code, msg))
+        self.code = code
+
+
+class pimd_params(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("n_beads", C.c_int32), ("ensemble", C.c_int32),
+        ("potential", C.c_int32), ("temp", C.c_double), ("kB", C.c_double), ("hbar", C.c_double),
+        ("mvv2e", C.c_double), ("dt", C.c_double), ("tau", C.c_double), ("tau_scale", C.c_double),
+        ("box", C.c_double * 3), ("seed", C.c_uint64), ("omega", C.c_double),
+        ("lj_eps", C.c_double), ("lj_sigma", C.c_double), ("lj_rc", C.c_double),
+        ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
+        ("nbr_capacity", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class pimd_topology(C.Structure):
+    _fields_ = [("lj_active", C.POINTER(C.c_int32)), ("n_bonds", C.c_int32),
+                ("bonds", C.POINTER(C.c_int32))]
+
+
+class pimd_estimators(C.Structure):
+    _fields_ = [("step", C.c_uint64), ("value", C.c_double * 7), ("count", C.c_uint64),
+                ("sum", C.c_double * 7), ("sumsq", C.c_double * 7), ("nonfinite", C.c_int32),
+                ("overflow", C.c_int32)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libpimd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpimd.so is not built (run __graft_entry__.build())")
+        # torch ships its own HIP runtime under the same soname
+        # (libamdhip64.so.7); loading torch first makes libpimd.so bind to that
+        # one, so the process holds a single HIP/HSA runtime.
+        import torch  # noqa: F401
+        lib = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        lib.pimd_workspace_bytes.argtypes = [P(pimd_params), P(C.c_double), P(pimd_topology),
+                                             P(C.c_size_t)]
+        lib.pimd_create.argtypes = [P(pimd_params), P(C.c_double), P(pimd_topology), C.c_void_p,
+                                    C.c_size_t, C.c_void_p, P(C.c_void_p)]
+        lib.pimd_set_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), C.c_uint64]
+        lib.pimd_step.argtypes = [C.c_void_p, C.c_int64]
+        lib.pimd_get_estimators.argtypes = [C.c_void_p, P(pimd_estimators)]
+        lib.pimd_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_uint64)]
+        lib.pimd_reset_averages.argtypes = [C.c_void_p]
+        lib.pimd_destroy.argtypes = [C.c_void_p]
+        lib.pimd_destroy.restype = None
+        lib.pimd_last_error.argtypes = [C.c_void_p]
+        lib.pimd_last_error.restype = C.c_char_p
+        for n in EXPORTED:
+            if n not in ("pimd_destroy", "pimd_last_error"):
+                getattr(lib, n).restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def params_from_spec(spec) -> pimd_params:
+    """Fill pimd_params from a workload spec (``inputs.SystemSpec``)."""
+    p = pimd_params()
+    p.n_atoms, p.n_beads = spec.n_atoms, spec.n_beads
+    p.ensemble, p.potential = int(spec.ensemble), int(spec.potential)
+    p.temp, p.kB, p.hbar, p.mvv2e = spec.temp, spec.kB, spec.hbar, spec.mvv2e
+    p.dt, p.tau, p.tau_scale = spec.dt, spec.tau, spec.tau_scale
+    p.box = (C.c_double * 3)(*spec.box)
+    p.seed = int(spec.seed) & (2**64 - 1)
+    p.omega = spec.omega
+    p.lj_eps, p.lj_sigma, p.lj_rc = spec.lj_eps, spec.lj_sigma, spec.lj_rc
+    p.skin, p.bond_k, p.bond_r0 = spec.skin, spec.bond_k, spec.bond_r0
+    return p
+
+
+class Context:
+    """One ring-polymer system on the GPU (wraps a ``pimd_ctx``)."""
+
+    def __init__(self, params: pimd_params, mass: np.ndarray, lj_active=None, bonds=None,
+                 stream=None, use_torch_workspace: bool = True):
+        lib = load()
+        self._lib = lib
+        self.params = params
+        self.N, self.P = params.n_atoms, params.n_beads
+        self._mass = np.ascontiguousarray(mass, dtype=np.float64)
+        self._topo = None
+        if lj_active is not None or bonds is not None:
+            t = pimd_topology()
+            if lj_active is not None:
+                self._act = np.ascontiguousarray(lj_active, dtype=np.int32)
+                t.lj_active = self._act.ctypes.data_as(C.POINTER(C.c_int32))
+            if bonds is not None and len(bonds):
+                self._bonds = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
+                t.n_bonds = self._bonds.shape[0]
+                t.bonds = self._bonds.ctypes.data_as(C.POINTER(C.c_int32))
+            self._topo = t
+        topo = C.byref(self._topo) if self._topo is not None else None
+        nbytes = C.c_size_t()
+        self._check(lib.pimd_workspace_bytes(C.byref(params), _dp(self._mass), topo,
+                                             C.byref(nbytes)), None)
+        self.workspace_bytes = nbytes.value
+        self._ws = None
+        ws_ptr = None
+        if use_torch_workspace:
+            import torch
+            # 256-byte aligned device buffer from torch's caching allocator
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            ws_ptr = (base + 255) & ~255
+        h = C.c_void_p()
+        self._check(lib.pimd_create(C.byref(params), _dp(self._mass), topo,
+                                    C.c_void_p(ws_ptr) if ws_ptr else None,
+                                    C.c_size_t(self.workspace_bytes + (0 if ws_ptr is None else 0)),
+                                    C.c_void_p(stream) if stream else None, C.byref(h)), None)
+        self._h = h
+
+    @classmethod
+    def from_spec(cls, spec, **kw) -> "Context":
+        return cls(params_from_spec(spec), spec.mass, lj_active=spec.lj_active, bonds=spec.bonds,
+                   **kw)
+
+    def _check(self, rc: int, h) -> None:
+        if rc != PIMD_OK:
+            msg = self._lib.pimd_last_error(h)
+            raise PimdError(rc, msg.decode() if msg else "")
+
+    def set_state(self, x: np.ndarray, v: np.ndarray, step: int = 0) -> None:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert x.shape == (self.P, self.N, 3) and v.shape == x.shape
+        self._check(self._lib.pimd_set_state(self._h, _dp(x), _dp(v), int(step)), self._h)
+
+    def step(self, n: int = 1) -> None:
+        self._check(self._lib.pimd_step(self._h, int(n)), self._h)
+
+    def estimators(self, check: bool = True) -> dict:
+        e = pimd_estimators()
+        rc = self._lib.pimd_get_estimators(self._h, C.byref(e))
+        if check:
+            self._check(rc, self._h)
+        out = {n: e.value[q] for q, n in enumerate(ESTIMATOR_NAMES)}
+        out["step"] = e.step
+        out["count"] = e.count
+        out["sum"] = {n: e.sum[q] for q, n in enumerate(ESTIMATOR_NAMES)}
+        out["sumsq"] = {n: e.sumsq[q] for q, n in enumerate(ESTIMATOR_NAMES)}
+        out["nonfinite"], out["overflow"] = e.nonfinite, e.overflow
+        return out
+
+    def get_state(self):
+        x = np.empty((self.P, self.N, 3))
+        p = np.empty((self.P, self.N, 3))
+        s = C.c_uint64()
+        self._check(self._lib.pimd_get_state(self._h, _dp(x), _dp(p), C.byref(s)), self._h)
+        return x, p, int(s.value)
+
+    def reset_averages(self) -> None:
+        self._check(self._lib.pimd_reset_averages(self._h), self._h)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.pimd_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,98 @@
+"""Host-side checks that need no GPU: libpimd.so loads and exports every entry
+point that include/pimd.h declares, the binding's structs match the header's
+field order, and the seeded workload generators produce what they promise."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2602_13553_amd import inputs, pimd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pimd.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pimd_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = header_functions()
+    assert set(declared) == set(pimd.EXPORTED)
+    lib = C.CDLL(pimd.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_binding_structs_follow_header():
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+    def fields(struct):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct, struct), src, re.S).group(1)
+        names = []
+        for decl in body.split(";"):
+            decl = re.sub(r"\[.*?\]", "", decl).replace("*", " ")
+            toks = [t for t in decl.replace(",", " , ").split() if t != "const"]
+            if not toks:
+                continue
+            # first token is the type, then comma-separated names
+            names += [t for t in toks[1:] if t != ","]
+        return names
+
+    assert fields("pimd_params") == [f[0] for f in pimd.pimd_params._fields_]
+    assert fields("pimd_topology") == [f[0] for f in pimd.pimd_topology._fields_]
+    assert fields("pimd_estimators") == [f[0] for f in pimd.pimd_estimators._fields_]
+
+
+def test_create_rejects_bad_parameters_without_gpu():
+    """Validation runs before any device call."""
+    lib = pimd.load()
+    spec = inputs.harmonic_tiny()
+    p = pimd.params_from_spec(spec)
+    n = C.c_size_t()
+    mass = np.ascontiguousarray(spec.mass)
+    assert lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n)) == 0
+    assert n.value > 0
+    bad = pimd.params_from_spec(spec)
+    bad.n_beads = 129
+    assert lib.pimd_workspace_bytes(C.byref(bad), pimd._dp(mass), None, C.byref(n)) == -6
+    bad = pimd.params_from_spec(spec)
+    bad.dt = -1.0
+    assert lib.pimd_workspace_bytes(C.byref(bad), pimd._dp(mass), None, C.byref(n)) == -1
+    assert b"dt" in lib.pimd_last_error(None)
+    lj = pimd.params_from_spec(inputs.lj_liquid(n_atoms=32, n_beads=4))
+    lj.box = (C.c_double * 3)(0.0, 1.0, 1.0)
+    assert lib.pimd_workspace_bytes(C.byref(lj), pimd._dp(np.ones(32)), None, C.byref(n)) == -6
+    h = C.c_void_p()
+    assert lib.pimd_create(C.byref(bad), pimd._dp(mass), None, None, 0, None, C.byref(h)) == -1
+
+
+def test_workload_generators():
+    h = inputs.harmonic_tiny()
+    assert h.x0.shape == (4, 64, 3) and h.n_beads == 4 and h.temp == 0.25
+    lj = inputs.lj_liquid()
+    L = lj.box[0]
+    assert lj.n_atoms == 4000 and abs(4000 / L ** 3 - 0.8) < 1e-12
+    d = np.linalg.norm(lj.x0[0, 0] - lj.x0[0, 1:], axis=1).min()
+    assert abs(d - L / 10 / math.sqrt(2)) < 0.1
+    w = inputs.water()
+    assert w.n_atoms == 32766 and w.extra["n_mol"] == 10922
+    assert abs(w.box[0] - 68.875) < 1e-3
+    x = w.x0.mean(axis=0)
+    r = np.linalg.norm(x[w.bonds[:, 0]] - x[w.bonds[:, 1]], axis=1)
+    assert np.allclose(r, 0.96, atol=0.05)
+    assert w.lj_active.sum() == 10922
+    assert abs(inputs.REAL_HBAR - 15.1787283) < 1e-6 and abs(inputs.REAL_MVV2E - 2390.0573) < 1e-3
+    b = inputs.batch_systems(n_systems=64)
+    ns = np.array([s.n_atoms for s in b])
+    assert ns.min() >= 64 and ns.max() <= 4096
+    assert set(s.n_beads for s in b) <= {8, 16, 32, 64}
+    tr = inputs.serving_trace(n_jobs=200)
+    gaps = np.diff([j.arrival for j in tr])
+    assert abs(gaps.mean() - 1 / 20) < 0.3 / 20
+    assert all(j.n_atoms % 3 == 0 for j in tr if j.kind == "water")
