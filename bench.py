@@ -1,0 +1,191 @@
+"""Throughput of the ring-polymer BAOAB + PILE-L step on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: normal-mode
+transforms, B/A/O/A/B, PILE-L noise, bead-batched forces, estimators.  The
+headline workload is the LJ quantum liquid (N=4000 atoms, P=32 beads, reduced
+density 0.8, kT=0.7, hbar=0.1, rc=2.5, dt=0.002, tau=0.5, FCC start).
+
+Prints ONE JSON line: bead*atom*steps/s over exactly --steps timed steps
+(after --warmup untimed ones), the roofline of the dominant kernel from HIP
+events on the library's stream, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2602_13553_amd import inputs  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
+LJ_FLOPS_PER_PAIR = 23         # per ordered bead pair inside rc (full neighbor list)
+FUSED_BYTES_PAIR = 120         # per bead*atom: read x, v~, f; write x, v~ (FP64 x 3 dims)
+FUSED_BYTES_EXT = 96           # per bead*atom with in-kernel trap forces (no f array)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pairs_inside_cutoff(x, box, rc, active=None):
+    """Ordered bead pairs (i, j), i != j, of the same bead with |r_ij| < rc under
+    the minimum image (scipy cKDTree with periodic box), summed over beads."""
+    from scipy.spatial import cKDTree
+    L = np.asarray(box)
+    tot = 0
+    for k in range(x.shape[0]):
+        pts = x[k] if active is None else x[k][active]
+        tree = cKDTree(np.mod(pts, L), boxsize=L)
+        tot += 2 * len(tree.query_pairs(rc, output_type="ndarray"))
+    return tot
+
+
+def sync(ctx):
+    import torch
+    torch.cuda.synchronize()
+    return ctx.estimators()
+
+
+def run_gpu(spec, steps, warmup, profile_steps):
+    from paper_2602_13553_amd import pimd
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    ctx.step(warmup)
+    sync(ctx)
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    est = sync(ctx)
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    # profiled region: same workload, per-kernel HIP events on the library stream
+    ctx.profile_begin()
+    t2 = time.perf_counter()
+    ctx.step(profile_steps)
+    prof = ctx.profile_end()
+    t3 = time.perf_counter()
+    x, p, s = ctx.get_state()
+    ctx.close()
+    return ms_step, est, prof, (t3 - t2) * 1e3 / profile_steps, x
+
+
+def kernel_avgs(prof):
+    return {k: (ms / n if n else 0.0, n) for k, (n, ms) in prof.items()}
+
+
+def cpu_baseline(spec, max_seconds=25.0):
+    """The oracle as it stands on the host cores, on a bounded sample of the
+    same workload (a few steps from the same initial state)."""
+    import oracle
+    st = oracle.State.from_spec(spec)
+    st.step(1)                      # first-touch / thread start-up outside the timing
+    n, t = 0, 0.0
+    while t < max_seconds and n < 200:
+        t0 = time.perf_counter()
+        st.step(1)
+        t += time.perf_counter() - t0
+        n += 1
+        if n >= 3 and t * (n + 1) / n > max_seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": spec.bead_atoms * n / t, "unit": "bead*atom*steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d steps of the same workload (N=%d, P=%d) from its initial state, %.1f s"
+                      % (n, spec.n_atoms, spec.n_beads, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    spec = inputs.lj_liquid()
+    log("workload %s: %d warmup + %d timed steps" % (spec.name, args.warmup, args.steps))
+    ms_step, est, prof, ms_prof, x = run_gpu(spec, args.steps, args.warmup, args.profile_steps)
+    ba = spec.bead_atoms
+    value = ba * 1e3 / ms_step
+    avgs = kernel_avgs(prof)
+    log("ms/step %.4f (profiled %.4f); kernels %s" % (ms_step, ms_prof, avgs))
+
+    # dominant kernel of the workload and its roofline
+    dom = max(("fused", "pair"), key=lambda k: avgs[k][0] * avgs[k][1])
+    if dom == "pair":
+        npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc)
+        flops = LJ_FLOPS_PER_PAIR * npairs
+        ach = flops / (avgs["pair"][0] * 1e-3) / 1e12
+        roof = {"kernel": "k_pair", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                "work_per_launch": "%d ordered bead pairs inside rc x %d flops"
+                                   % (npairs, LJ_FLOPS_PER_PAIR)}
+    else:
+        byts = FUSED_BYTES_PAIR * ba
+        ach = byts / (avgs["fused"][0] * 1e-3) / 1e9
+        roof = {"kernel": "k_fused", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    fused_gbs = FUSED_BYTES_PAIR * ba / (avgs["fused"][0] * 1e-3) / 1e9
+
+    out = {
+        "metric": "ring-polymer bead*atom*steps/s",
+        "value": value,
+        "unit": "bead*atom*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded FCC LJ liquid, Maxwell-Boltzmann bead velocities at P*T)",
+        "config": {"workload": "LJ quantum liquid", "n_atoms": spec.n_atoms,
+                   "n_beads": spec.n_beads, "bead_atoms": ba, "rho": 0.8, "kT": spec.temp,
+                   "hbar": spec.hbar, "rc": spec.lj_rc, "dt": spec.dt, "tau": spec.tau,
+                   "ensemble": "NVT PILE-L", "integrator": "BAOAB"},
+        "roofline": roof,
+        "kernels_ms": {k: v[0] for k, v in avgs.items()},
+        "fused_in_cache_gbs": fused_gbs,
+        "estimators": {"kcv_per_atom": est["kcv"] / spec.n_atoms,
+                       "kprim_per_atom": est["kprim"] / spec.n_atoms, "temp": est["temp"]},
+    }
+
+    if not args.no_hbm_probe:
+        # the fused pass on a working set larger than the 256 MB Infinity Cache:
+        # the water-shaped workload at P=64 (N=32766, 2.1e6 bead*atoms, 252 MB/step)
+        w = inputs.water(n_beads=64)
+        log("hbm probe %s" % w.name)
+        ms_w, _, prof_w, _, _ = run_gpu(w, 50, 10, 50)
+        aw = kernel_avgs(prof_w)
+        gbs = FUSED_BYTES_PAIR * w.bead_atoms / (aw["fused"][0] * 1e-3) / 1e9
+        out["fused_roofline"] = {"kernel": "k_fused", "workload": w.name, "bound": "hbm",
+                                 "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                                 "bytes_per_launch": FUSED_BYTES_PAIR * w.bead_atoms}
+        out["water_p64"] = {"bead_atom_steps_per_s": w.bead_atoms * 1e3 / ms_w,
+                            "ms_per_step": ms_w, "kernels_ms": {k: v[0] for k, v in aw.items()}}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

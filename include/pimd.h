@@ -163,6 +163,26 @@ int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);
 
+/* Per-kernel timing.  Between pimd_profile_begin and pimd_profile_end,
+ * pimd_step launches its kernels directly (no graph) and brackets each one
+ * with HIP events on the context's stream; pimd_profile_end waits for the
+ * stream and returns, per kernel kind, the number of launches and the summed
+ * event-measured durations.  Kinds: PIMD_KERNEL_FUSED (the step pass),
+ * PIMD_KERNEL_PAIR (forces), PIMD_KERNEL_CLOSE (closing B at the end of a
+ * pimd_step call), PIMD_KERNEL_FINALIZE (the one-block reduction after each
+ * fused or closing pass).  Errors: STATE (end without begin), DEVICE. */
+#define PIMD_NKERNEL 4
+#define PIMD_KERNEL_FUSED 0
+#define PIMD_KERNEL_PAIR 1
+#define PIMD_KERNEL_CLOSE 2
+#define PIMD_KERNEL_FINALIZE 3
+typedef struct pimd_profile {
+    uint64_t launches[PIMD_NKERNEL];
+    double ms[PIMD_NKERNEL];
+} pimd_profile;
+int pimd_profile_begin(pimd_ctx *ctx);
+int pimd_profile_end(pimd_ctx *ctx, pimd_profile *out);
+
 /* Free the context and everything the library allocated for it (waits for
  * the stream first).  NULL is a no-op. */
 void pimd_destroy(pimd_ctx *ctx);

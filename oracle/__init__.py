@@ -68,8 +68,8 @@ def lib():
         sig = {
             "orc_nm_matrix": (None, [C.c_int32, d]),
             "orc_mode_lambda": (None, [C.c_int32, d]),
-            "orc_to_normal": (None, [C.c_int32, C.c_int32, d, d, d]),
-            "orc_from_normal": (None, [C.c_int32, C.c_int32, d, d, d]),
+            "orc_to_normal": (None, [C.c_int32, C.c_int32, d, d]),
+            "orc_from_normal": (None, [C.c_int32, C.c_int32, d, d]),
             "orc_philox4x64_10": (None, [u64, u64, u64]),
             "orc_gaussians": (None, [C.c_uint64] * 5 + [d]),
             "orc_free_rp_matrix": (None, [S, C.c_int32, C.c_double, d]),
@@ -109,7 +109,7 @@ def to_normal(a: np.ndarray) -> np.ndarray:
     P, N, _ = a.shape
     a = np.ascontiguousarray(a, dtype=np.float64)
     out = np.zeros_like(a)
-    lib().orc_to_normal(P, N, _dp(nm_matrix(P)), _dp(a), _dp(out))
+    lib().orc_to_normal(P, N, _dp(a), _dp(out))
     return out
 
 
@@ -117,7 +117,7 @@ def from_normal(at: np.ndarray) -> np.ndarray:
     P, N, _ = at.shape
     at = np.ascontiguousarray(at, dtype=np.float64)
     out = np.zeros_like(at)
-    lib().orc_from_normal(P, N, _dp(nm_matrix(P)), _dp(at), _dp(out))
+    lib().orc_from_normal(P, N, _dp(at), _dp(out))
     return out
 
 

@@ -62,40 +62,70 @@ void orc_mode_lambda(int32_t P, double *lam)
     }
 }
 
-/* Transforms: each element is one dot product of a row (or column) of M with
- * the bead (or mode) values of one atom and dim.  The products and their sum
- * are accumulated in x87 extended precision (64-bit mantissa) and rounded to
- * FP64 once, so every transformed value is the correctly rounded exact dot
- * product up to a 2^-11 ulp margin.  Reason: positions are unwrapped and of
- * box size (about 70 A for the water workload) while the non-centroid modes
- * are of order 0.01-0.1 A; FP64 summation leaves absolute errors of ~1e-13 A
- * in those modes, and the stiff ring-polymer springs (m omega_k^2 up to ~100
- * amu/fs^2) turn that into momentum noise of ~1e-12 relative after 10 steps,
- * which depends only on the summation order.  Extended accumulation removes
- * that order dependence, so the oracle is a sharper reference. */
-void orc_to_normal(int32_t P, int32_t N, const double *M, const double *a, double *at)
+/* Eq. B1 evaluated in x87 extended precision (64-bit mantissa), used by the
+ * transforms below.  Same definition as orc_nm_matrix, higher precision. */
+static void nm_matrix_ext(int32_t P, long double *M)
 {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double inv_sqrt_p = 1.0L / sqrtl((long double)P);
+    const long double sqrt_2_p = sqrtl(2.0L / (long double)P);
+    for (int32_t i = 0; i < P; ++i)
+        for (int32_t j = 0; j < P; ++j) {
+            long long ij = ((long long)i * (long long)j) % P;
+            long double ang = 2.0L * pi * (long double)ij / (long double)P;
+            long double v;
+            if (i == 0)
+                v = inv_sqrt_p;
+            else if ((P % 2 == 0) && (i == P / 2))
+                v = (j % 2 == 0) ? inv_sqrt_p : -inv_sqrt_p;
+            else if (i <= P / 2)
+                v = sqrt_2_p * cosl(ang);
+            else
+                v = sqrt_2_p * sinl(ang);
+            M[(size_t)i * P + j] = v;
+        }
+}
+
+/* Transforms: each element is one dot product of a row (or column) of M with
+ * the bead (or mode) values of one atom and dim.  Both M and the sum are
+ * carried in x87 extended precision and the result is rounded to FP64 once,
+ * so every transformed value is the correctly rounded exact value up to a
+ * 2^-11 ulp margin.  Reason: positions are unwrapped and of box size (about
+ * 70 A for the water workload) while the non-centroid modes are 0.01-0.1 A.
+ * In FP64, (i) the rounded entries of a non-centroid row do not sum to zero
+ * exactly, which adds a spurious x * 5e-16 to that mode, and (ii) the
+ * summation leaves ~1e-13 A; the stiff ring-polymer springs (m omega_k^2 up
+ * to ~100 amu/fs^2) turn either into ~1e-12 relative momentum error within
+ * 10 steps.  Extended precision removes both. */
+void orc_to_normal(int32_t P, int32_t N, const double *a, double *at)
+{
+    long double *M = (long double *)malloc(sizeof(long double) * (size_t)P * P);
+    nm_matrix_ext(P, M);
     for (int32_t i = 0; i < N; ++i)
         for (int32_t d = 0; d < 3; ++d)
             for (int32_t k = 0; k < P; ++k) {
                 long double s = 0.0L;
                 for (int32_t j = 0; j < P; ++j)
-                    s += (long double)M[(size_t)k * P + j] * (long double)a[((size_t)j * N + i) * 3 + d];
+                    s += M[(size_t)k * P + j] * (long double)a[((size_t)j * N + i) * 3 + d];
                 at[((size_t)k * N + i) * 3 + d] = (double)s;
             }
+    free(M);
 }
 
 /* Eq. (B3): the inverse is the transpose. */
-void orc_from_normal(int32_t P, int32_t N, const double *M, const double *at, double *a)
+void orc_from_normal(int32_t P, int32_t N, const double *at, double *a)
 {
+    long double *M = (long double *)malloc(sizeof(long double) * (size_t)P * P);
+    nm_matrix_ext(P, M);
     for (int32_t i = 0; i < N; ++i)
         for (int32_t d = 0; d < 3; ++d)
             for (int32_t j = 0; j < P; ++j) {
                 long double s = 0.0L;
                 for (int32_t k = 0; k < P; ++k)
-                    s += (long double)M[(size_t)k * P + j] * (long double)at[((size_t)k * N + i) * 3 + d];
+                    s += M[(size_t)k * P + j] * (long double)at[((size_t)k * N + i) * 3 + d];
                 a[((size_t)j * N + i) * 3 + d] = (double)s;
             }
+    free(M);
 }
 
 /* ------------------------------------------------------------------------
@@ -338,13 +368,11 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
     const size_t n = (size_t)P * N * 3;
     const double h = 0.5 * sys->dt;
     const double ftm2v = 1.0 / sys->mvv2e;
-    double *M = (double *)malloc(sizeof(double) * (size_t)P * P);
     double *xt = (double *)malloc(sizeof(double) * n);
     double *ft = (double *)malloc(sizeof(double) * n);
     double *Ah = (double *)malloc(sizeof(double) * 4 * (size_t)P);
     double *c1 = (double *)malloc(sizeof(double) * (size_t)P);
     double *c2 = (double *)malloc(sizeof(double) * (size_t)P);
-    orc_nm_matrix(P, M);
     for (int32_t k = 0; k < P; ++k) {
         orc_free_rp_matrix(sys, k, h, Ah + 4 * k);
         orc_pile_coeffs(sys, k, c1 + k, c2 + k);
@@ -353,7 +381,7 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
     for (int32_t it = 0; it < nsteps; ++it) {
         const uint64_t s = *step;
         /* B */
-        orc_to_normal(P, N, M, f, ft);
+        orc_to_normal(P, N, f, ft);
         for (int32_t k = 0; k < P; ++k)
             for (int32_t i = 0; i < N; ++i)
                 for (int d = 0; d < 3; ++d) {
@@ -361,7 +389,7 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
                     vt[e] += h * ft[e] * ftm2v / sys->mass[i];
                 }
         /* A, O, A */
-        orc_to_normal(P, N, M, x, xt);
+        orc_to_normal(P, N, x, xt);
         for (int32_t k = 0; k < P; ++k) {
             const double *A = Ah + 4 * k;
             for (int32_t i = 0; i < N; ++i) {
@@ -379,10 +407,10 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
                 }
             }
         }
-        orc_from_normal(P, N, M, xt, x);
+        orc_from_normal(P, N, xt, x);
         /* forces at the new positions, then B */
         orc_forces(sys, x, f, U);
-        orc_to_normal(P, N, M, f, ft);
+        orc_to_normal(P, N, f, ft);
         for (int32_t k = 0; k < P; ++k)
             for (int32_t i = 0; i < N; ++i)
                 for (int d = 0; d < 3; ++d) {
@@ -391,7 +419,7 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
                 }
         *step = s + 1;
     }
-    free(M); free(xt); free(ft); free(Ah); free(c1); free(c2);
+    free(xt); free(ft); free(Ah); free(c1); free(c2);
 }
 
 /* ------------------------------------------------------------------------
@@ -448,12 +476,10 @@ double orc_spring_energy_nm(const orc_system *sys, const double *x)
     const int32_t P = sys->n_beads, N = sys->n_atoms;
     const size_t n = (size_t)P * N * 3;
     const double wn = omega_n(sys);
-    double *M = (double *)malloc(sizeof(double) * (size_t)P * P);
     double *lam = (double *)malloc(sizeof(double) * (size_t)P);
     double *xt = (double *)malloc(sizeof(double) * n);
-    orc_nm_matrix(P, M);
     orc_mode_lambda(P, lam);
-    orc_to_normal(P, N, M, x, xt);
+    orc_to_normal(P, N, x, xt);
     double s = 0.0;
     for (int32_t k = 0; k < P; ++k)
         for (int32_t i = 0; i < N; ++i)
@@ -461,7 +487,7 @@ double orc_spring_energy_nm(const orc_system *sys, const double *x)
                 double q = xt[((size_t)k * N + i) * 3 + d];
                 s += 0.5 * sys->mass[i] * sys->mvv2e * wn * wn * lam[k] * q * q;
             }
-    free(M); free(lam); free(xt);
+    free(lam); free(xt);
     return s;
 }
 
@@ -469,15 +495,13 @@ double orc_kcv_nm(const orc_system *sys, const double *x, const double *f)
 {
     const int32_t P = sys->n_beads, N = sys->n_atoms;
     const size_t n = (size_t)P * N * 3;
-    double *M = (double *)malloc(sizeof(double) * (size_t)P * P);
     double *xt = (double *)malloc(sizeof(double) * n);
     double *ft = (double *)malloc(sizeof(double) * n);
-    orc_nm_matrix(P, M);
-    orc_to_normal(P, N, M, x, xt);
-    orc_to_normal(P, N, M, f, ft);
+    orc_to_normal(P, N, x, xt);
+    orc_to_normal(P, N, f, ft);
     double vir = 0.0;
     for (int32_t k = 1; k < P; ++k)
         for (size_t e = (size_t)k * N * 3; e < (size_t)(k + 1) * N * 3; ++e) vir += xt[e] * ft[e];
-    free(M); free(xt); free(ft);
+    free(xt); free(ft);
     return 1.5 * (double)N * sys->kB * sys->temp - vir / (2.0 * (double)P);
 }

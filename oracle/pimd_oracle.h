@@ -71,10 +71,11 @@ typedef struct orc_est {
 /* --- normal modes (App. B) --------------------------------------------- */
 void orc_nm_matrix(int32_t P, double *M /* [P][P], row = mode */);
 void orc_mode_lambda(int32_t P, double *lam /* [P] */);
-/* a~ = M a for every atom and dim; a, at are [P][N][3] */
-void orc_to_normal(int32_t P, int32_t N, const double *M, const double *a, double *at);
+/* a~ = M a for every atom and dim; a, at are [P][N][3].  M and the dot
+ * products are evaluated in extended precision and rounded once. */
+void orc_to_normal(int32_t P, int32_t N, const double *a, double *at);
 /* a = M^T a~ */
-void orc_from_normal(int32_t P, int32_t N, const double *M, const double *at, double *a);
+void orc_from_normal(int32_t P, int32_t N, const double *at, double *a);
 
 /* --- random numbers (App. D noise) ------------------------------------- */
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

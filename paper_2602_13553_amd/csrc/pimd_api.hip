@@ -53,6 +53,10 @@ struct pimd_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_failed = false;
+    // profiling: event pairs around every launch while enabled
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, size_t>> ev_used;   // (kernel kind, first event index)
     std::string err = "no error";
 };
 
@@ -264,12 +268,46 @@ int launch_error(pimd_ctx *c, const char *where)
     return PIMD_OK;
 }
 
-void enqueue_step(pimd_ctx *c)
+// Event pair around a launch when profiling (events are pooled and reused).
+size_t prof_begin(pimd_ctx *c, int kind)
+{
+    if (!c->profiling) return 0;
+    size_t first = c->ev_used.empty() ? 0 : c->ev_used.back().second + 2;
+    while (c->ev_pool.size() < first + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return 0;
+        c->ev_pool.push_back(e);
+    }
+    c->ev_used.push_back({kind, first});
+    (void)hipEventRecord(c->ev_pool[first], c->stream);
+    return first;
+}
+
+void prof_end(pimd_ctx *c, size_t first)
+{
+    if (c->profiling) (void)hipEventRecord(c->ev_pool[first + 1], c->stream);
+}
+
+void enqueue_fused(pimd_ctx *c, int mode, int kind)
 {
     FusedArgs a = c->fa;
-    a.mode = FUSED_STEP;
+    a.mode = mode;
+    size_t e = prof_begin(c, kind);
     launch_fused(a, c->lay.fused_grid, c->stream);
-    if (a.pair) launch_pair(c->pa, c->lay.pair_grid, c->stream);
+    prof_end(c, e);
+    e = prof_begin(c, PIMD_KERNEL_FINALIZE);
+    launch_finalize(a, c->lay.fused_grid, c->stream);
+    prof_end(c, e);
+}
+
+void enqueue_step(pimd_ctx *c)
+{
+    enqueue_fused(c, FUSED_STEP, PIMD_KERNEL_FUSED);
+    if (c->fa.pair) {
+        size_t e = prof_begin(c, PIMD_KERNEL_PAIR);
+        launch_pair(c->pa, c->lay.pair_grid, c->stream);
+        prof_end(c, e);
+    }
 }
 
 }  // namespace
@@ -464,9 +502,11 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     a.vin = c->d_v;
     a.mode = FUSED_PREP;
     launch_fused(a, c->lay.fused_grid, c->stream);
+    launch_finalize(a, c->lay.fused_grid, c->stream);
     if (a.pair) launch_pair(c->pa, c->lay.pair_grid, c->stream);
     a.mode = FUSED_EST;
     launch_fused(a, c->lay.fused_grid, c->stream);
+    launch_finalize(a, c->lay.fused_grid, c->stream);
     int rc = launch_error(c, "set_state launch");
     if (rc != PIMD_OK) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -481,7 +521,7 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
     if (nsteps < 0) return fail(c, PIMD_ERR_ARG, "nsteps < 0");
     if (nsteps == 0) return PIMD_OK;
     int64_t left = nsteps;
-    if (left >= kGraphChunk && !c->graph_failed) {
+    if (left >= kGraphChunk && !c->graph_failed && !c->profiling) {
         if (!c->graph_exec) {
             hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
@@ -492,6 +532,7 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
                 c->graph = nullptr;
                 c->graph_exec = nullptr;
                 c->graph_failed = true;
@@ -505,12 +546,35 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
         }
     }
     for (; left > 0; --left) enqueue_step(c);
-    if (c->fa.pair) {
-        FusedArgs a = c->fa;
-        a.mode = FUSED_CLOSE;
-        launch_fused(a, c->lay.fused_grid, c->stream);
-    }
+    if (c->fa.pair) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
     return launch_error(c, "step launch");
+}
+
+int pimd_profile_begin(pimd_ctx *c)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    c->profiling = true;
+    c->ev_used.clear();
+    return PIMD_OK;
+}
+
+int pimd_profile_end(pimd_ctx *c, pimd_profile *out)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!c->profiling) return fail(c, PIMD_ERR_STATE, "pimd_profile_end without pimd_profile_begin");
+    c->profiling = false;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    pimd_profile r;
+    for (int q = 0; q < PIMD_NKERNEL; ++q) { r.launches[q] = 0; r.ms[q] = 0.0; }
+    for (const auto &u : c->ev_used) {
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
+        r.launches[u.first] += 1;
+        r.ms[u.first] += ms;
+    }
+    c->ev_used.clear();
+    if (out) *out = r;
+    return PIMD_OK;
 }
 
 int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
@@ -578,6 +642,7 @@ void pimd_destroy(pimd_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

@@ -31,15 +31,15 @@ enum FusedMode : int {
     FUSED_PREP = 3,   // v~ = M v, centroids, excursion; requests a neighbor build
 };
 
-// Device-resident control block.  Written only by the last block of the
-// fused kernel (or by small host-enqueued kernels), read at kernel start.
+// Device-resident control block.  Written by k_finalize (one block, after
+// each fused pass) and by small host-enqueued kernels; read at kernel start.
 struct Ctl {
     unsigned long long step;   // thermostat step counter s
     int synced;                // 1: velocities are at the full step
     int rebuild;               // 1: the coming force pass rebuilds the lists
     double rlist;              // centroid cutoff of the current lists
     double ebuild;             // max bead-centroid excursion at the last build
-    unsigned int done;         // last-block counter of the fused kernel
+    unsigned int done;         // unused (kept for layout)
     int nonfinite;
     int overflow;
     int pad0;
@@ -105,6 +105,7 @@ struct PairArgs {
 int fused_smem_bytes(int P);
 int fused_grid(int N, int P);
 void launch_fused(const FusedArgs &a, int grid, hipStream_t s);
+void launch_finalize(const FusedArgs &a, int fused_blocks, hipStream_t s);
 int pair_grid(int N, int P);
 void launch_pair(const PairArgs &a, int grid, hipStream_t s);
 void launch_import(const double *src, double *dst, const int *orig, int N, int P, hipStream_t s);

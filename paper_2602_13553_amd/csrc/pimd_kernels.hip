@@ -9,8 +9,9 @@
 //            launch (LJ among active atoms + harmonic bonds), each atom's
 //            neighbor list rebuilt in place from centroids when requested.
 //
-// Reductions are deterministic: fixed-order block trees, then the last block
-// to finish (atomic ticket) combines the per-block partials in block order.
+// k_finalize: one block after k_fused; combines the per-block partials in
+//            block order (deterministic), records estimators and running
+//            sums, advances the step counter, decides list rebuilds.
 #include "pimd_internal.h"
 
 namespace pimd {
@@ -92,31 +93,6 @@ __device__ double block_max(double v, double *red)
     return v;
 }
 
-__device__ __forceinline__ void store_agent(double *p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true in every thread of the last block to arrive.
-__device__ bool last_block_ticket(unsigned int *counter)
-{
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last != 0;
-}
-
 // --------------------------------------------------------------------------
 // Fused step kernel.
 // Shared memory: M^T padded [P][P+1], tile X [A][3][P], tile F [A][3][P],
@@ -125,7 +101,7 @@ __device__ bool last_block_ticket(unsigned int *counter)
 int fused_smem_bytes(int P)
 {
     const int A = kBlock / P;
-    return (int)sizeof(double) * (P * (P + 1) + 2 * 3 * A * P + 3 * A);
+    return (int)sizeof(double) * (P * (P + 1) + 2 * 3 * A * P + 6 * A);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
@@ -138,7 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     double *sMT = smem;                 // sMT[j*PS + k] = M[k][j]
     double *sX = sMT + P * PS;          // [A][3][P]
     double *sF = sX + 3 * A * P;        // [A][3][P]
-    double *sC = sF + 3 * A * P;        // [A][3]
+    double *sC = sF + 3 * A * P;        // [A][3] centroids
+    double *sR = sC + 3 * A;            // [A][3] bead-0 reference positions
 
     const int t = threadIdx.x;
     for (int e = t; e < P * P; e += kBlock) {
@@ -152,7 +129,6 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     const int ext = !a.pair;                                    // forces in-kernel
     const bool closing = (mode == FUSED_STEP || mode == FUSED_CLOSE) && !synced && a.pair;
     const bool est_now = closing || mode == FUSED_EST;          // estimators of this state
-    const bool est_after = (mode == FUSED_STEP) && ext;         // estimators of the new state
     const bool need_f = a.pair && (mode == FUSED_STEP || est_now);
     const bool inverse = (mode == FUSED_STEP);
     const double sqrtP = sqrt((double)P);
@@ -189,18 +165,19 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
         const bool act = lane_ok && la < na;
         const int i = a0 + la;
         double xt[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0}, vt[3] = {0.0, 0.0, 0.0};
+        double ref[3] = {0.0, 0.0, 0.0};
         double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0;
         if (act) {
             hm = a.atoms[i * 4 + AT_HALF_M];
             im = a.atoms[i * 4 + AT_INV_M];
             sg = a.atoms[i * 4 + AT_SIGMA];
             active = a.atoms[i * 4 + AT_ACTIVE];
-            // forward transforms of this mode: x~_k = sum_j M_kj x_j (and f, or v in PREP).
-            // Positions are taken relative to bead 0: the non-centroid rows of M
-            // sum to zero, so x~_k = sum_j M_kj (x_j - x_0) exactly, and the
-            // differences are small, so the result keeps its absolute accuracy
-            // for box-size unwrapped coordinates; the centroid row adds
-            // sqrt(P) x_0 back.
+            // Forward transforms of this mode.  Positions are carried relative
+            // to the atom's bead 0 for the whole step: y_j = x_j - x_0 (exact),
+            // y~ = M y.  Since the non-centroid rows of M sum to zero,
+            // y~_k = x~_k for k >= 1 and y~_0 = x~_0 - sqrt(P) x_0; the small
+            // relative values keep full absolute accuracy for box-size
+            // unwrapped coordinates.  Forces (and v in PREP) have no offset.
             const double *xr = sX + la * 3 * P;
             const double *fr = sF + la * 3 * P;
             const bool tf = need_f || mode == FUSED_PREP;
@@ -216,11 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                     ft[2] += m * fr[2 * P + j];
                 }
             }
-            if (k == 0) {
-                xt[0] += sqrtP * r0;
-                xt[1] += sqrtP * r1;
-                xt[2] += sqrtP * r2;
-            }
+            ref[0] = r0; ref[1] = r1; ref[2] = r2;
             const size_t vb = (size_t)i * 3 * P + k;
             if (mode == FUSED_PREP) {
                 vt[0] = ft[0]; vt[1] = ft[1]; vt[2] = ft[2];
@@ -228,10 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
             } else {
                 vt[0] = a.v[vb]; vt[1] = a.v[vb + P]; vt[2] = a.v[vb + 2 * P];
             }
+            // absolute mode coordinate x~_k (differs from y~_k only for k = 0)
+            const double off = (k == 0) ? sqrtP : 0.0;
             if (ext) {
                 // external trap: the normal-mode force is -m mvv2e omega^2 x~
 #pragma unroll
-                for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * xt[d];
+                for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * ref[d]);
             }
             if (closing) {
 #pragma unroll
@@ -243,7 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                     acc_ekin += hm * vt[d] * vt[d];
                     acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
                     acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
-                    acc_uext += hm * a.omega2 * xt[d] * xt[d];
+                    const double xa = xt[d] + off * ref[d];
+                    acc_uext += hm * a.omega2 * xa * xa;
                 }
             }
             if (mode == FUSED_STEP) {
@@ -276,14 +252,15 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                     // the estimators of the new state
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        ft[d] = -2.0 * hm * a.omega2 * xt[d];
+                        ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * ref[d]);
                         vt[d] += a.hdt * im * ft[d];
                     }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
+                        const double xa = xt[d] + off * ref[d];
                         acc_ekin += hm * vt[d] * vt[d];
                         acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
-                        acc_uext += hm * a.omega2 * xt[d] * xt[d];
+                        acc_uext += hm * a.omega2 * xa * xa;
                         acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
                     }
                 }
@@ -296,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                 if (!isfinite(vt[d])) acc_bad = 1.0;
             if (k == 0 && (mode == FUSED_PREP)) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) sC[la * 3 + d] = xt[d] / sqrtP;
+                for (int d = 0; d < 3; ++d) sC[la * 3 + d] = ref[d] + xt[d] / sqrtP;
             }
         }
         if (mode == FUSED_STEP) {
@@ -306,7 +283,10 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                 for (int d = 0; d < 3; ++d) sX[(la * 3 + d) * P + k] = xt[d];
                 if (k == 0) {
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) sC[la * 3 + d] = xt[d] / sqrtP;
+                    for (int d = 0; d < 3; ++d) {
+                        sC[la * 3 + d] = ref[d] + xt[d] / sqrtP;
+                        sR[la * 3 + d] = ref[d];
+                    }
                 }
             }
         }
@@ -317,19 +297,17 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                 const int j = k;
                 double xj[3];
                 if (inverse) {
-                    // non-centroid modes first (small), the centroid term last
+                    // y_j = sum_k M_kj y~_k (all small), then x_j = x_0 + y_j
                     xj[0] = xj[1] = xj[2] = 0.0;
                     const double *xr = sX + la * 3 * P;
-                    for (int m = 1; m < P; ++m) {
+                    for (int m = 0; m < P; ++m) {
                         const double w = sMT[j * PS + m];   // M[m][j]
                         xj[0] += w * xr[m];
                         xj[1] += w * xr[P + m];
                         xj[2] += w * xr[2 * P + m];
                     }
-                    const double w0 = sMT[j * PS];
-                    xj[0] += w0 * xr[0];
-                    xj[1] += w0 * xr[P];
-                    xj[2] += w0 * xr[2 * P];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) xj[d] += sR[la * 3 + d];
                     const size_t xb = (size_t)i * 3 * P + j;
                     a.x[xb] = xj[0]; a.x[xb + P] = xj[1]; a.x[xb + 2 * P] = xj[2];
                 } else {
@@ -359,7 +337,8 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
         }
     }
 
-    // ---- per-block partials
+    // ---- per-block partials (plain stores; k_finalize runs after this
+    // kernel, so the kernel boundary makes them visible)
     {
         double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
         block_sum<4>(s4, red);
@@ -368,31 +347,50 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
         const double bad = block_max(acc_bad, red);
         if (t == 0) {
             double *pp = a.partials + (size_t)blockIdx.x * PF_COUNT;
-            store_agent(pp + PF_EKIN, s4[0]);
-            store_agent(pp + PF_ESPRING, s4[1]);
-            store_agent(pp + PF_VIR, s4[2]);
-            store_agent(pp + PF_UEXT, s4[3]);
-            store_agent(pp + PF_EMAX, emax);
-            store_agent(pp + PF_DMAX, dmax);
-            store_agent(pp + PF_NONFINITE, bad);
+            pp[PF_EKIN] = s4[0];
+            pp[PF_ESPRING] = s4[1];
+            pp[PF_VIR] = s4[2];
+            pp[PF_UEXT] = s4[3];
+            pp[PF_EMAX] = emax;
+            pp[PF_DMAX] = dmax;
+            pp[PF_NONFINITE] = bad;
         }
     }
-    if (!last_block_ticket(&a.ctl->done)) return;
+}
 
-    // ---- last block: combine partials in block order
+// --------------------------------------------------------------------------
+// One block, after k_fused: combines its per-block partials (and the force
+// kernel's energy partials) in block order, records the estimators and the
+// running sums, advances the step counter and decides the neighbor-list
+// rebuild for the coming force pass.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
+{
+    __shared__ double red[kBlock * 4];
+    const int t = threadIdx.x;
+    const int P = a.P;
+    const int mode = a.mode;
+    Ctl *c = a.ctl;
+    const unsigned long long step = c->step;
+    const int synced = c->synced;
+    const int ext = !a.pair;
+    const bool closing = (mode == FUSED_STEP || mode == FUSED_CLOSE) && !synced && a.pair;
+    const bool est_now = closing || mode == FUSED_EST;
+    const bool est_after = (mode == FUSED_STEP) && ext;
+
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
     double emax = 0.0, dmax = 0.0, bad = 0.0, upair = 0.0;
-    for (int b = t; b < (int)gridDim.x; b += kBlock) {
+    for (int b = t; b < nblocks; b += kBlock) {
         const double *pp = a.partials + (size_t)b * PF_COUNT;
-        tot[0] += load_agent(pp + PF_EKIN);
-        tot[1] += load_agent(pp + PF_ESPRING);
-        tot[2] += load_agent(pp + PF_VIR);
-        tot[3] += load_agent(pp + PF_UEXT);
-        emax = fmax(emax, load_agent(pp + PF_EMAX));
-        dmax = fmax(dmax, load_agent(pp + PF_DMAX));
-        bad = fmax(bad, load_agent(pp + PF_NONFINITE));
+        tot[0] += pp[PF_EKIN];
+        tot[1] += pp[PF_ESPRING];
+        tot[2] += pp[PF_VIR];
+        tot[3] += pp[PF_UEXT];
+        emax = fmax(emax, pp[PF_EMAX]);
+        dmax = fmax(dmax, pp[PF_DMAX]);
+        bad = fmax(bad, pp[PF_NONFINITE]);
     }
-    if (a.pair && (est_now)) {
+    if (a.pair && est_now) {
         for (int b = t; b < a.n_fpartials; b += kBlock) upair += a.fpartials[b];
     }
     block_sum<4>(tot, red);
@@ -406,7 +404,6 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     bad = block_max(bad, red);
 
     if (t == 0) {
-        Ctl *c = a.ctl;
         if (est_now || est_after) {
             const double ekin = tot[0], esp = tot[1], vir = tot[2];
             const double epot = a.pair ? upair : tot[3];
@@ -448,7 +445,6 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
             }
         }
         if (bad != 0.0) c->nonfinite = 1;
-        c->done = 0;
     }
 }
 
@@ -475,6 +471,11 @@ int fused_grid(int N, int P)
 void launch_fused(const FusedArgs &a, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kBlock), fused_smem_bytes(a.P), s, a);
+}
+
+void launch_finalize(const FusedArgs &a, int fused_blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, a, fused_blocks);
 }
 
 // --------------------------------------------------------------------------

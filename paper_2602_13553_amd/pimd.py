@@ -23,7 +23,8 @@ PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER = 0, 1, 2, 3
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_destroy",
-            "pimd_last_error")
+            "pimd_last_error", "pimd_profile_begin", "pimd_profile_end")
+KERNEL_NAMES = ("fused", "pair", "close", "finalize")
 
 
 class PimdError(RuntimeError):
@@ -55,6 +56,10 @@ class pimd_estimators(C.Structure):
                 ("overflow", C.c_int32)]
 
 
+class pimd_profile(C.Structure):
+    _fields_ = [("launches", C.c_uint64 * 4), ("ms", C.c_double * 4)]
+
+
 _lib = None
 
 
@@ -81,6 +86,8 @@ def load() -> C.CDLL:
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_destroy.argtypes = [C.c_void_p]
         lib.pimd_destroy.restype = None
+        lib.pimd_profile_begin.argtypes = [C.c_void_p]
+        lib.pimd_profile_end.argtypes = [C.c_void_p, P(pimd_profile)]
         lib.pimd_last_error.argtypes = [C.c_void_p]
         lib.pimd_last_error.restype = C.c_char_p
         for n in EXPORTED:
@@ -188,6 +195,15 @@ class Context:
         s = C.c_uint64()
         self._check(self._lib.pimd_get_state(self._h, _dp(x), _dp(p), C.byref(s)), self._h)
         return x, p, int(s.value)
+
+    def profile_begin(self) -> None:
+        self._check(self._lib.pimd_profile_begin(self._h), self._h)
+
+    def profile_end(self) -> dict:
+        """{kernel: (launches, summed ms)} of the steps enqueued since profile_begin."""
+        r = pimd_profile()
+        self._check(self._lib.pimd_profile_end(self._h, C.byref(r)), self._h)
+        return {n: (int(r.launches[q]), float(r.ms[q])) for q, n in enumerate(KERNEL_NAMES)}
 
     def reset_averages(self) -> None:
         self._check(self._lib.pimd_reset_averages(self._h), self._h)

@@ -47,6 +47,7 @@ def test_binding_structs_follow_header():
     assert fields("pimd_params") == [f[0] for f in pimd.pimd_params._fields_]
     assert fields("pimd_topology") == [f[0] for f in pimd.pimd_topology._fields_]
     assert fields("pimd_estimators") == [f[0] for f in pimd.pimd_estimators._fields_]
+    assert fields("pimd_profile") == [f[0] for f in pimd.pimd_profile._fields_]
 
 
 def test_create_rejects_bad_parameters_without_gpu():
