@@ -56,9 +56,9 @@ def sync(ctx):
     return ctx.estimators()
 
 
-def run_gpu(spec, steps, warmup, profile_steps):
+def run_gpu(spec, steps, warmup, profile_steps, flags=0):
     from paper_2602_13553_amd import pimd
-    ctx = pimd.Context.from_spec(spec)
+    ctx = pimd.Context.from_spec(spec, flags=flags)
     ctx.set_state(spec.x0, spec.v0, 0)
     ctx.step(warmup)
     sync(ctx)
@@ -103,6 +103,63 @@ def cpu_baseline(spec, max_seconds=25.0):
                       % (n, spec.n_atoms, spec.n_beads, t)}
 
 
+def bench_batched(n_systems, steps, seed=20260213):
+    """256 independent LJ systems (N log-uniform in [64, 4096], P from
+    {8, 16, 32, 64}, kT in [0.5, 1]) stepped together in one batch, against the
+    same systems stepped one at a time with their own contexts."""
+    import torch
+    from paper_2602_13553_amd import pimd
+    specs = inputs.batch_systems(n_systems=n_systems, seed=seed, nsteps=steps)
+    work = sum(s.bead_atoms for s in specs) * steps
+    b = pimd.Batch()
+    ids = [b.add(s) for s in specs]
+    for i, s in zip(ids, specs):
+        b.set_state(i, s.x0, s.v0, 0)
+    b.step(2)                       # plan, graph capture and first-touch outside the timing
+    torch.cuda.synchronize()
+    b.estimators(ids[0])
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.estimators(ids[0])            # waits for the batch stream
+    tb = time.perf_counter() - t0
+    b.close()
+    # one at a time
+    ctxs = []
+    for s in specs:
+        c = pimd.Context.from_spec(s, use_torch_workspace=False)
+        c.set_state(s.x0, s.v0, 0)
+        c.step(2)
+        c.estimators()
+        ctxs.append(c)
+    t0 = time.perf_counter()
+    for c in ctxs:
+        c.step(steps)
+        c.estimators()
+    ts = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    return {"workload": "%d LJ systems, N log-uniform [64,4096], P in {8,16,32,64}" % n_systems,
+            "steps": steps, "bead_atoms": sum(s.bead_atoms for s in specs),
+            "batched_bead_atom_steps_per_s": work / tb, "batched_s": tb,
+            "one_at_a_time_bead_atom_steps_per_s": work / ts, "one_at_a_time_s": ts,
+            "speedup": ts / tb}
+
+
+def bench_serving(n_jobs, seed=20260213):
+    """Poisson arrivals at 20 jobs/s (harmonic, LJ or water-shaped; N
+    log-uniform in [256, 32768]; P from {8..64}; 200-5000 steps), admitted under
+    a 200 GB budget and stepped together, against one job at a time."""
+    from paper_2602_13553_amd import serve
+    tr = inputs.serving_trace(n_jobs=n_jobs, seed=seed)
+    rep = serve.serve(tr, hbm_budget=200e9, max_active=64, tick=32).summary()
+    seq = serve.serve_sequential(tr).summary()
+    offered = sum(j.n_atoms * j.n_beads * j.nsteps for j in tr) / max(tr[-1].arrival, 1e-9)
+    return {"workload": "%d jobs, Poisson 20/s, harmonic/LJ/water, N in [256,32768], "
+                        "P in {8,16,32,64}, 200-5000 steps" % n_jobs,
+            "offered_bead_atom_steps_per_s": offered,
+            "continuous_batching": rep, "one_at_a_time": seq}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +168,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-probe", action="store_true")
+    ap.add_argument("--batch-systems", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--serve-jobs", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -164,6 +226,8 @@ def main():
         "fused_in_cache_gbs": fused_gbs,
         "estimators": {"kcv_per_atom": est["kcv"] / spec.n_atoms,
                        "kprim_per_atom": est["kprim"] / spec.n_atoms, "temp": est["temp"]},
+        "neighbor_lists": {"rlist": est["rlist"], "builds": est["n_rebuilds"],
+                           "steps": args.warmup + args.steps},
     }
 
     if not args.no_hbm_probe:
@@ -180,7 +244,19 @@ def main():
                                  "bytes_per_launch": FUSED_BYTES_PAIR * w.bead_atoms}
         out["water_p64"] = {"bead_atom_steps_per_s": w.bead_atoms * 1e3 / ms_w,
                             "ms_per_step": ms_w, "kernels_ms": {k: v[0] for k, v in aw.items()}}
+        # the same pass with the transforms on the FP64 vector ALUs instead of MFMA
+        from paper_2602_13553_amd import pimd as _p
+        ms_v, _, prof_v, _, _ = run_gpu(w, 50, 10, 50, flags=_p.PIMD_FLAG_VALU_TRANSFORMS)
+        av = kernel_avgs(prof_v)
+        out["transform_variants_water_p64_fused_ms"] = {"mfma": aw["fused"][0],
+                                                         "valu": av["fused"][0]}
 
+    if not args.no_batch:
+        log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))
+        out["batched"] = bench_batched(args.batch_systems, args.batch_steps)
+    if not args.no_serve:
+        log("serving: %d jobs" % args.serve_jobs)
+        out["serving"] = bench_serving(args.serve_jobs)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(spec)

@@ -79,8 +79,12 @@ typedef struct pimd_params {
     double bond_k;      /* bond U = bond_k (r - bond_r0)^2 (WATER) */
     double bond_r0;
     int32_t nbr_capacity; /* neighbors per atom; 0 = sized from the density */
-    int32_t reserved;
+    int32_t flags;        /* PIMD_FLAG_* (0 = defaults) */
 } pimd_params;
+
+/* flags: force the FP64 vector-ALU transforms instead of the FP64 matrix-core
+ * (MFMA) ones that the step pass uses for P = 16, 32 and 64 */
+#define PIMD_FLAG_VALU_TRANSFORMS 1
 
 typedef struct pimd_topology {
     const int32_t *lj_active; /* [N] 1 = takes part in LJ; NULL = every atom */
@@ -100,6 +104,8 @@ typedef struct pimd_estimators {
     double sumsq[PIMD_NEST];
     int32_t nonfinite; /* 1 if a NaN/Inf position or velocity was seen */
     int32_t overflow;  /* 1 if a neighbor list ran out of capacity */
+    uint64_t n_rebuilds; /* neighbor-list builds since set_state (LJ, WATER) */
+    double rlist;        /* centroid cutoff of the current neighbor lists */
 } pimd_estimators;
 /* ekin    = sum_k sum_i 1/2 m_i |v~_i^(k)|^2 (App. A item 1)
  * espring = sum_k sum_i 1/2 m_i omega_n^2 lambda_k |x~_i^(k)|^2 (App. A item 2,
@@ -182,6 +188,60 @@ typedef struct pimd_profile {
 } pimd_profile;
 int pimd_profile_begin(pimd_ctx *ctx);
 int pimd_profile_end(pimd_ctx *ctx, pimd_profile *out);
+
+/* ---- Batched execution ------------------------------------------------
+ * Many independent systems (each with its own N, P, T, potential, seed, ...)
+ * advanced together: one step of the whole batch is a fixed handful of
+ * launches (the fused pass per bead-count group, one finalize pass with a
+ * block per system, one force pass), whatever the number of systems, and
+ * chunks of steps are captured in a hipGraph.  Every system behaves exactly
+ * as a pimd_ctx with the same parameters (same kernels, same noise stream);
+ * its arithmetic does not depend on the other systems in the batch.
+ * A system id stays valid until pimd_batch_remove.  Batch calls are made by
+ * one host thread at a time. */
+typedef struct pimd_batch pimd_batch;
+
+/* Empty batch on the current device.  stream: hipStream_t (borrowed, not the
+ * legacy null stream) or NULL for a stream owned by the batch.
+ * Errors: ARG, DEVICE. */
+int pimd_batch_create(void *stream, pimd_batch **out);
+
+/* Add a system (arguments as in pimd_create; the library allocates its
+ * device memory, pimd_workspace_bytes() of it).  The system takes part in
+ * pimd_batch_step once pimd_batch_set_state has been called for it.
+ * Errors: ARG, UNSUPPORTED, OOM, DEVICE. */
+int pimd_batch_add(pimd_batch *b, const pimd_params *p, const double *mass,
+                   const pimd_topology *topo, int32_t *sys);
+
+/* Remove a system and free its device memory (waits for the stream).
+ * Errors: ARG (unknown id). */
+int pimd_batch_remove(pimd_batch *b, int32_t sys);
+
+/* As pimd_set_state for one system of the batch; activates it.  Its step
+ * budget becomes unlimited.  Errors: ARG, DEVICE. */
+int pimd_batch_set_state(pimd_batch *b, int32_t sys, const double *x, const double *v,
+                         uint64_t step);
+
+/* Let the system take at most `steps` more steps (-1 = unlimited).  Systems
+ * whose budget is spent sit out the remaining steps of a pimd_batch_step call
+ * (their state is synchronized at the end of the call).  Enqueued on the
+ * stream.  Errors: ARG, STATE (no state yet). */
+int pimd_batch_set_budget(pimd_batch *b, int32_t sys, int64_t steps);
+
+/* Enqueue nsteps steps for every active system with budget left, then the
+ * closing B; returns without waiting.  Errors: ARG, DEVICE. */
+int pimd_batch_step(pimd_batch *b, int64_t nsteps);
+
+/* As pimd_get_estimators / pimd_get_state for one system (wait for the
+ * stream).  Errors: ARG, STATE, NONFINITE, OVERFLOW, DEVICE. */
+int pimd_batch_get_estimators(pimd_batch *b, int32_t sys, pimd_estimators *out);
+int pimd_batch_get_state(pimd_batch *b, int32_t sys, double *x, double *p, uint64_t *step);
+
+/* Wait for the stream, free every system and the batch.  NULL is a no-op. */
+void pimd_batch_destroy(pimd_batch *b);
+
+/* Message of the last error on the batch (never NULL). */
+const char *pimd_batch_last_error(const pimd_batch *b);
 
 /* Free the context and everything the library allocated for it (waits for
  * the stream first).  NULL is a no-op. */

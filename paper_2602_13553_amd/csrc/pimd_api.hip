@@ -25,7 +25,8 @@ constexpr int kGraphChunk = 32;   // steps per captured graph
 struct Layout {
     size_t x, v, f, stage, cent, cref, M, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
         partials, fpartials, ctl, total;
-    int cap, fused_grid, pair_grid, n_active;
+    int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
+    int valu_tiles, mfma_tiles;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -176,7 +177,12 @@ Layout make_layout(const pimd_params *p, int n_active, int cap)
     L.cap = cap;
     L.n_active = n_active;
     L.fused_grid = fused_grid(p->n_atoms, p->n_beads);
-    L.pair_grid = pair ? pair_grid(p->n_atoms, p->n_beads) : 0;
+    L.mfma_grid = (!(p->flags & PIMD_FLAG_VALU_TRANSFORMS) && fused_mfma_supported(p->n_beads))
+                      ? fused_mfma_grid(p->n_atoms, p->n_beads)
+                      : 0;
+    L.pair_S = pair ? pair_subgroups(p->n_atoms, p->n_beads) : 1;
+    L.pair_grid = pair ? pair_grid(p->n_atoms, p->n_beads, L.pair_S) : 0;
+    L.pair_active_tiles = pair ? pair_active_tiles(n_active, p->n_beads, L.pair_S) : 0;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
     L.x = take(arr);
@@ -193,7 +199,11 @@ Layout make_layout(const pimd_params *p, int n_active, int cap)
     L.bond_j = take(pair ? N * kMaxBonds * sizeof(int) : 0);
     L.nbr_count = take(pair ? N * sizeof(int) : 0);
     L.nbr = take(pair ? (size_t)n_active * cap * sizeof(int2) : 0);
-    L.partials = take((size_t)L.fused_grid * PF_COUNT * sizeof(double));
+    // partials: per block (single system) or per tile (batched execution)
+    L.valu_tiles = (p->n_atoms + (kBlock / p->n_beads) - 1) / (kBlock / p->n_beads);
+    L.mfma_tiles = fused_mfma_supported(p->n_beads) ? mfma_block_tiles(p->n_atoms) : 0;
+    const int nparts = std::max(std::max(L.fused_grid, L.mfma_grid), std::max(L.valu_tiles, L.mfma_tiles));
+    L.partials = take((size_t)nparts * PF_COUNT * sizeof(double));
     L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
     L.ctl = take(sizeof(Ctl));
     L.total = o;
@@ -292,11 +302,17 @@ void enqueue_fused(pimd_ctx *c, int mode, int kind)
 {
     FusedArgs a = c->fa;
     a.mode = mode;
+    // the step pass uses the matrix-core transforms where available
+    const bool mfma = (mode == FUSED_STEP) && c->lay.mfma_grid > 0;
+    const int blocks = mfma ? c->lay.mfma_grid : c->lay.fused_grid;
     size_t e = prof_begin(c, kind);
-    launch_fused(a, c->lay.fused_grid, c->stream);
+    if (mfma)
+        launch_fused_mfma(a, blocks, c->stream);
+    else
+        launch_fused(a, blocks, c->stream);
     prof_end(c, e);
     e = prof_begin(c, PIMD_KERNEL_FINALIZE);
-    launch_finalize(a, c->lay.fused_grid, c->stream);
+    launch_finalize(a, blocks, c->stream);
     prof_end(c, e);
 }
 
@@ -463,6 +479,8 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
 
     PairArgs &q = c->pa;
     q.N = N; q.P = P; q.n_active = n_active; q.cap = L.cap;
+    q.S = L.pair_S;
+    q.n_active_tiles = L.pair_active_tiles;
     for (int d = 0; d < 3; ++d) q.box[d] = p->box[d];
     q.rc2 = p->lj_rc * p->lj_rc;
     q.lj_eps = p->lj_eps;
@@ -594,6 +612,8 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
     out->count = h.count;
     out->nonfinite = h.nonfinite;
     out->overflow = h.overflow;
+    out->n_rebuilds = h.n_rebuilds;
+    out->rlist = h.rlist;
     if (h.nonfinite) return fail(c, PIMD_ERR_NONFINITE, "non-finite position or velocity");
     if (h.overflow) return fail(c, PIMD_ERR_OVERFLOW, "neighbor list capacity exceeded");
     return PIMD_OK;
@@ -651,6 +671,347 @@ void pimd_destroy(pimd_ctx *c)
 const char *pimd_last_error(const pimd_ctx *c)
 {
     return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched execution
+// ===========================================================================
+struct pimd_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<pimd_ctx *> sys;     // nullptr: removed
+    std::vector<char> active;        // has a state
+    // device plan
+    FusedArgs *d_fa = nullptr;
+    PairArgs *d_pa = nullptr;
+    int *d_nparts = nullptr;         // [2][n]: step pass, closing pass
+    int2 *d_items = nullptr;
+    size_t cap_sys = 0, cap_items = 0;
+    struct Group {
+        int P;        // bead count (MFMA groups) or 0 (vector-ALU group)
+        int off, n;   // items [off, off + n)
+    };
+    std::vector<Group> step_groups;
+    int pair_off = 0, pair_n = 0, close_off = 0, close_n = 0, n_sys_plan = 0;
+    int smem_valu = 0;   // dynamic LDS of the batched vector-ALU pass: max over its systems
+    int ncu = 256;
+    bool dirty = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
+    std::string err = "no error";
+};
+
+namespace {
+
+constexpr int kBatchGraphChunk = 16;
+
+int bfail(pimd_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define BHIP_TRY(b, expr)                                                             \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return bfail((b), PIMD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool valid_sys(const pimd_batch *b, int32_t s)
+{
+    return b && s >= 0 && (size_t)s < b->sys.size() && b->sys[s] != nullptr;
+}
+
+void drop_graph(pimd_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+int grow(pimd_batch *b, void **ptr, size_t *cap, size_t need, size_t elem)
+{
+    if (need <= *cap && *ptr) return PIMD_OK;
+    size_t n = std::max<size_t>(need, 2 * *cap);
+    if (n == 0) n = 1;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    BHIP_TRY(b, hipMalloc(ptr, n * elem));
+    *cap = n;
+    return PIMD_OK;
+}
+
+int cu_count()
+{
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    return ncu;
+}
+
+// Rebuild the device tables and work lists from the active systems.
+int rebuild_plan(pimd_batch *b)
+{
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    const int n = (int)b->sys.size();
+    std::vector<FusedArgs> fa(std::max(n, 1));
+    std::vector<PairArgs> pa(std::max(n, 1));
+    std::vector<int> nparts(2 * std::max(n, 1), 0);
+    std::vector<int2> items;
+    b->step_groups.clear();
+    b->smem_valu = 0;
+    for (int s = 0; s < n; ++s) {
+        if (b->sys[s]) {
+            fa[s] = b->sys[s]->fa;
+            pa[s] = b->sys[s]->pa;
+        }
+    }
+    // MFMA groups by bead count, then the vector-ALU group
+    for (int P : {16, 32, 64}) {
+        pimd_batch::Group g{P, (int)items.size(), 0};
+        for (int s = 0; s < n; ++s) {
+            pimd_ctx *c = b->sys[s];
+            if (!c || !b->active[s] || c->p.n_beads != P || c->lay.mfma_grid == 0) continue;
+            for (int t = 0; t < c->lay.mfma_tiles; ++t) items.push_back(make_int2(s, t));
+            nparts[s] = c->lay.mfma_tiles;
+        }
+        g.n = (int)items.size() - g.off;
+        if (g.n) b->step_groups.push_back(g);
+    }
+    {
+        pimd_batch::Group g{0, (int)items.size(), 0};
+        for (int s = 0; s < n; ++s) {
+            pimd_ctx *c = b->sys[s];
+            if (!c || !b->active[s] || c->lay.mfma_grid != 0) continue;
+            for (int t = 0; t < c->lay.valu_tiles; ++t) items.push_back(make_int2(s, t));
+            nparts[s] = c->lay.valu_tiles;
+            b->smem_valu = std::max(b->smem_valu, fused_smem_bytes(c->p.n_beads));
+        }
+        g.n = (int)items.size() - g.off;
+        if (g.n) b->step_groups.push_back(g);
+    }
+    b->pair_off = (int)items.size();
+    for (int s = 0; s < n; ++s) {
+        pimd_ctx *c = b->sys[s];
+        if (!c || !b->active[s] || !c->fa.pair) continue;
+        for (int t = 0; t < c->lay.pair_grid; ++t) items.push_back(make_int2(s, t));
+    }
+    b->pair_n = (int)items.size() - b->pair_off;
+    b->close_off = (int)items.size();
+    for (int s = 0; s < n; ++s) {
+        pimd_ctx *c = b->sys[s];
+        if (!c || !b->active[s] || !c->fa.pair) continue;
+        for (int t = 0; t < c->lay.valu_tiles; ++t) items.push_back(make_int2(s, t));
+        nparts[n + s] = c->lay.valu_tiles;
+        b->smem_valu = std::max(b->smem_valu, fused_smem_bytes(c->p.n_beads));
+    }
+    b->close_n = (int)items.size() - b->close_off;
+    b->n_sys_plan = n;
+    int rc;
+    if (!b->d_fa || fa.size() > b->cap_sys) {
+        // the three per-system tables always share one capacity
+        const size_t cap = std::max(fa.size(), 2 * b->cap_sys);
+        if (b->d_fa) (void)hipFree(b->d_fa);
+        if (b->d_pa) (void)hipFree(b->d_pa);
+        if (b->d_nparts) (void)hipFree(b->d_nparts);
+        b->d_fa = nullptr; b->d_pa = nullptr; b->d_nparts = nullptr; b->cap_sys = 0;
+        BHIP_TRY(b, hipMalloc((void **)&b->d_fa, cap * sizeof(FusedArgs)));
+        BHIP_TRY(b, hipMalloc((void **)&b->d_pa, cap * sizeof(PairArgs)));
+        BHIP_TRY(b, hipMalloc((void **)&b->d_nparts, 2 * cap * sizeof(int)));
+        b->cap_sys = cap;
+    }
+    if ((rc = grow(b, (void **)&b->d_items, &b->cap_items, std::max<size_t>(items.size(), 1), sizeof(int2))) != PIMD_OK)
+        return rc;
+    BHIP_TRY(b, hipMemcpy(b->d_fa, fa.data(), fa.size() * sizeof(FusedArgs), hipMemcpyHostToDevice));
+    BHIP_TRY(b, hipMemcpy(b->d_pa, pa.data(), pa.size() * sizeof(PairArgs), hipMemcpyHostToDevice));
+    BHIP_TRY(b, hipMemcpy(b->d_nparts, nparts.data(), nparts.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!items.empty())
+        BHIP_TRY(b, hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+    set_batch_smem(b->smem_valu);
+    set_mfma_batch_smem();
+    b->ncu = cu_count();
+    b->dirty = false;
+    return PIMD_OK;
+}
+
+void enqueue_batch_step(pimd_batch *b)
+{
+    const int ncu = b->ncu;
+    for (const auto &g : b->step_groups) {
+        if (g.P)
+            launch_fused_mfma_batch(g.P, b->d_fa, b->d_items + g.off, g.n, std::min(g.n, 2 * ncu), b->stream);
+        else
+            launch_fused_batch(b->d_fa, b->d_items + g.off, g.n, FUSED_STEP, b->smem_valu,
+                               std::min(g.n, 2 * ncu), b->stream);
+    }
+    launch_finalize_batch(b->d_fa, b->d_nparts, b->n_sys_plan, FUSED_STEP, b->stream);
+    if (b->pair_n)
+        launch_pair_batch(b->d_pa, b->d_items + b->pair_off, b->pair_n, std::min(b->pair_n, 8 * ncu),
+                          b->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pimd_batch_create(void *stream, pimd_batch **out)
+{
+    if (!out) return bfail(nullptr, PIMD_ERR_ARG, "out is NULL");
+    pimd_batch *b = new (std::nothrow) pimd_batch();
+    if (!b) return bfail(nullptr, PIMD_ERR_OOM, "host allocation failed");
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete b;
+            return bfail(nullptr, PIMD_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        b->own_stream = true;
+    }
+    *out = b;
+    return PIMD_OK;
+}
+
+int pimd_batch_add(pimd_batch *b, const pimd_params *p, const double *mass, const pimd_topology *topo,
+                   int32_t *sys)
+{
+    if (!b || !sys) return bfail(b, PIMD_ERR_ARG, "NULL argument");
+    pimd_ctx *c = nullptr;
+    int rc = pimd_create(p, mass, topo, nullptr, 0, (void *)b->stream, &c);
+    if (rc != PIMD_OK) return bfail(b, rc, pimd_last_error(nullptr));
+    int id = -1;
+    for (size_t s = 0; s < b->sys.size(); ++s)
+        if (!b->sys[s]) { id = (int)s; break; }
+    if (id < 0) {
+        id = (int)b->sys.size();
+        b->sys.push_back(nullptr);
+        b->active.push_back(0);
+    }
+    b->sys[id] = c;
+    b->active[id] = 0;
+    b->dirty = true;
+    *sys = id;
+    return PIMD_OK;
+}
+
+int pimd_batch_remove(pimd_batch *b, int32_t s)
+{
+    if (!valid_sys(b, s)) return bfail(b, PIMD_ERR_ARG, "unknown system id");
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    pimd_destroy(b->sys[s]);
+    b->sys[s] = nullptr;
+    b->active[s] = 0;
+    b->dirty = true;
+    return PIMD_OK;
+}
+
+int pimd_batch_set_state(pimd_batch *b, int32_t s, const double *x, const double *v, uint64_t step)
+{
+    if (!valid_sys(b, s)) return bfail(b, PIMD_ERR_ARG, "unknown system id");
+    int rc = pimd_set_state(b->sys[s], x, v, step);
+    if (rc != PIMD_OK) return bfail(b, rc, b->sys[s]->err);
+    if (!b->active[s]) b->dirty = true;
+    b->active[s] = 1;
+    return PIMD_OK;
+}
+
+int pimd_batch_set_budget(pimd_batch *b, int32_t s, int64_t steps)
+{
+    if (!valid_sys(b, s)) return bfail(b, PIMD_ERR_ARG, "unknown system id");
+    if (!b->active[s]) return bfail(b, PIMD_ERR_STATE, "system has no state");
+    if (steps < -1) return bfail(b, PIMD_ERR_ARG, "budget must be >= -1");
+    launch_ctl_set_budget(b->sys[s]->d_ctl, (long long)steps, b->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, PIMD_ERR_DEVICE, hipGetErrorString(e));
+    return PIMD_OK;
+}
+
+int pimd_batch_step(pimd_batch *b, int64_t nsteps)
+{
+    if (!b) return bfail(nullptr, PIMD_ERR_ARG, "batch is NULL");
+    if (nsteps < 0) return bfail(b, PIMD_ERR_ARG, "nsteps < 0");
+    if (nsteps == 0) return PIMD_OK;
+    if (b->dirty) {
+        int rc = rebuild_plan(b);
+        if (rc != PIMD_OK) return rc;
+    }
+    if (b->step_groups.empty()) return PIMD_OK;
+    int64_t left = nsteps;
+    if (left >= kBatchGraphChunk && !b->graph_failed) {
+        if (!b->gexec) {
+            hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int s = 0; s < kBatchGraphChunk; ++s) enqueue_batch_step(b);
+                e = hipStreamEndCapture(b->stream, &b->graph);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                drop_graph(b);
+                b->graph_failed = true;
+            }
+        }
+        if (b->gexec) {
+            while (left >= kBatchGraphChunk) {
+                BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+                left -= kBatchGraphChunk;
+            }
+        }
+    }
+    for (; left > 0; --left) enqueue_batch_step(b);
+    if (b->close_n) {
+        launch_fused_batch(b->d_fa, b->d_items + b->close_off, b->close_n, FUSED_CLOSE, b->smem_valu,
+                           std::min(b->close_n, 2 * b->ncu), b->stream);
+        launch_finalize_batch(b->d_fa, b->d_nparts + b->n_sys_plan, b->n_sys_plan, FUSED_CLOSE, b->stream);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, PIMD_ERR_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
+    return PIMD_OK;
+}
+
+int pimd_batch_get_estimators(pimd_batch *b, int32_t s, pimd_estimators *out)
+{
+    if (!valid_sys(b, s)) return bfail(b, PIMD_ERR_ARG, "unknown system id");
+    int rc = pimd_get_estimators(b->sys[s], out);
+    if (rc != PIMD_OK) return bfail(b, rc, b->sys[s]->err);
+    return PIMD_OK;
+}
+
+int pimd_batch_get_state(pimd_batch *b, int32_t s, double *x, double *p, uint64_t *step)
+{
+    if (!valid_sys(b, s)) return bfail(b, PIMD_ERR_ARG, "unknown system id");
+    int rc = pimd_get_state(b->sys[s], x, p, step);
+    if (rc != PIMD_OK) return bfail(b, rc, b->sys[s]->err);
+    return PIMD_OK;
+}
+
+void pimd_batch_destroy(pimd_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (pimd_ctx *c : b->sys) pimd_destroy(c);
+    if (b->d_fa) (void)hipFree(b->d_fa);
+    if (b->d_pa) (void)hipFree(b->d_pa);
+    if (b->d_nparts) (void)hipFree(b->d_nparts);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char *pimd_batch_last_error(const pimd_batch *b)
+{
+    return b ? b->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

@@ -39,10 +39,12 @@ struct Ctl {
     int rebuild;               // 1: the coming force pass rebuilds the lists
     double rlist;              // centroid cutoff of the current lists
     double ebuild;             // max bead-centroid excursion at the last build
-    unsigned int done;         // unused (kept for layout)
     int nonfinite;
     int overflow;
-    int pad0;
+    unsigned long long n_rebuilds;
+    long long budget;          // steps this system may still take (-1 = unlimited)
+    int ran;                   // 1: the last fused pass did work (the force pass follows it)
+    int pad1;
     unsigned long long est_step;
     double value[kNumEst];
     unsigned long long count;
@@ -86,6 +88,8 @@ enum { AT_HALF_M = 0, AT_INV_M, AT_SIGMA, AT_ACTIVE };
 
 struct PairArgs {
     int N, P, n_active, cap;
+    int S;                    // sub-groups of lanes sharing one atom's list
+    int n_active_tiles;       // tiles that hold LJ-active atoms (they come first)
     double box[3];
     double rc2;
     double lj_eps, lj_sig2, lj_ushift;
@@ -106,12 +110,30 @@ int fused_smem_bytes(int P);
 int fused_grid(int N, int P);
 void launch_fused(const FusedArgs &a, int grid, hipStream_t s);
 void launch_finalize(const FusedArgs &a, int fused_blocks, hipStream_t s);
-int pair_grid(int N, int P);
+bool fused_mfma_supported(int P);
+int fused_mfma_grid(int N, int P);
+void launch_fused_mfma(const FusedArgs &a, int grid, hipStream_t s);
+// batched launches: items are (system index, tile) pairs grouped by system
+int mfma_block_tiles(int N);
+void set_mfma_batch_smem();
+void launch_fused_mfma_batch(int P, const FusedArgs *table, const int2 *items, int n_items,
+                             int grid, hipStream_t s);
+void launch_fused_batch(const FusedArgs *table, const int2 *items, int n_items, int mode,
+                        int smem_bytes, int grid, hipStream_t s);
+void set_batch_smem(int smem_bytes);
+void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys, int mode,
+                           hipStream_t s);
+void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
+                       hipStream_t s);
+int pair_subgroups(int N, int P);
+int pair_grid(int N, int P, int S);
+int pair_active_tiles(int n_active, int P, int S);
 void launch_pair(const PairArgs &a, int grid, hipStream_t s);
 void launch_import(const double *src, double *dst, const int *orig, int N, int P, hipStream_t s);
 void launch_export(const double *x, const double *v, const double *atoms_mass, const double *M,
                    const int *orig, double *xdst, double *pdst, int N, int P, hipStream_t s);
 void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, unsigned long long step, hipStream_t s);
+void launch_ctl_set_budget(Ctl *ctl, long long budget, hipStream_t s);
 
 }  // namespace pimd

@@ -12,86 +12,10 @@
 // k_finalize: one block after k_fused; combines the per-block partials in
 //            block order (deterministic), records estimators and running
 //            sums, advances the step counter, decides list rebuilds.
+#include "pimd_device.h"
 #include "pimd_internal.h"
 
 namespace pimd {
-
-// --------------------------------------------------------------------------
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
-// --------------------------------------------------------------------------
-__device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0,
-                                              unsigned long long k1)
-{
-    const unsigned long long M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const unsigned long long lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const unsigned long long lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-        const unsigned long long n0 = hi1 ^ c[1] ^ k0;
-        const unsigned long long n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-        k0 += W0; k1 += W1;
-    }
-}
-
-__device__ __forceinline__ double u01(unsigned long long w)
-{
-    // top 53 bits + 1, times 2^-53: uniform on (0, 1], exact in FP64
-    return ((double)(w >> 11) + 1.0) * 1.1102230246251565404e-16;
-}
-
-// Three N(0,1) deviates for atom i, mode k, step s: counter (i, k, s, 0),
-// key (seed, 0); (z0, z1) from (u0, u1), z2 from (u2, u3).
-__device__ __forceinline__ void gauss3(unsigned long long seed, unsigned long long i,
-                                       unsigned long long k, unsigned long long s, double z[3])
-{
-    unsigned long long c[4] = {i, k, s, 0ULL};
-    philox4x64_10(c, seed, 0ULL);
-    const double r0 = sqrt(-2.0 * log(u01(c[0])));
-    const double r2 = sqrt(-2.0 * log(u01(c[2])));
-    double s1, c1;
-    sincospi(2.0 * u01(c[1]), &s1, &c1);
-    z[0] = r0 * c1;
-    z[1] = r0 * s1;
-    z[2] = r2 * cospi(2.0 * u01(c[3]));
-}
-
-// --------------------------------------------------------------------------
-// Block reductions (fixed order).
-// --------------------------------------------------------------------------
-template <int NV>
-__device__ void block_sum(double (&v)[NV], double *red /* [kBlock*NV] */)
-{
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) red[q * kBlock + t] = v[q];
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (t < w) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) red[q * kBlock + t] += red[q * kBlock + t + w];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = red[q * kBlock];
-    __syncthreads();
-}
-
-__device__ double block_max(double v, double *red)
-{
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] = fmax(red[t], red[t + w]);
-        __syncthreads();
-    }
-    v = red[0];
-    __syncthreads();
-    return v;
-}
 
 // --------------------------------------------------------------------------
 // Fused step kernel.
@@ -104,10 +28,14 @@ int fused_smem_bytes(int P)
     return (int)sizeof(double) * (P * (P + 1) + 2 * 3 * A * P + 6 * A);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
+// Processes tiles t0, t0 + tstride, ... of one system and writes one set of
+// partials.  stage_m = false keeps the matrix already staged in shared
+// memory (same system or same P as the previous call of this block).
+__device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *smem, double *red,
+                           double *partial_out, bool stage_m)
 {
-    extern __shared__ double smem[];
-    __shared__ double red[kBlock * 4];
+    // a system whose step budget is spent takes no step (uniform per block)
+    if (a.mode == FUSED_STEP && a.ctl->budget == 0) return;
     const int P = a.P, N = a.N;
     const int A = kBlock / P;
     const int PS = P + 1;
@@ -118,9 +46,12 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     double *sR = sC + 3 * A;            // [A][3] bead-0 reference positions
 
     const int t = threadIdx.x;
-    for (int e = t; e < P * P; e += kBlock) {
-        const int k = e / P, j = e - k * P;
-        sMT[j * PS + k] = a.M[e];
+    __syncthreads();   // the previous call's shared-memory reads are done
+    if (stage_m) {
+        for (int e = t; e < P * P; e += kBlock) {
+            const int k = e / P, j = e - k * P;
+            sMT[j * PS + k] = a.M[e];
+        }
     }
 
     const int mode = a.mode;
@@ -144,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     for (int q = 0; q < 8; ++q) mk[q] = lane_ok ? a.modes[k * 8 + q] : 0.0;
 
     const int ntiles = (N + A - 1) / A;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int tile = t0; tile < ntiles; tile += tstride) {
         const int a0 = tile * A;
         const int na = min(A, N - a0);
         const int nel = na * 3 * P;
@@ -346,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
         const double dmax = block_max(acc_dmax, red);
         const double bad = block_max(acc_bad, red);
         if (t == 0) {
-            double *pp = a.partials + (size_t)blockIdx.x * PF_COUNT;
+            double *pp = partial_out;
             pp[PF_EKIN] = s4[0];
             pp[PF_ESPRING] = s4[1];
             pp[PF_VIR] = s4[2];
@@ -358,19 +289,50 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[kBlock * 4];
+    fused_tiles(a, blockIdx.x, gridDim.x, smem, red, a.partials + (size_t)blockIdx.x * PF_COUNT,
+                true);
+}
+
+// Batched: item (system, tile); the system's arguments come from the table and
+// its partials are per tile.  Items are grouped by system, so the matrix is
+// restaged only when the system changes.
+__global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *table, const int2 *items,
+                                                        int n_items, int mode)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[kBlock * 4];
+    int prev = -1;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = items[it];
+        FusedArgs a = table[item.x];
+        a.mode = mode;
+        fused_tiles(a, item.y, 1 << 30, smem, red, a.partials + (size_t)item.y * PF_COUNT,
+                    item.x != prev);
+        prev = item.x;
+    }
+}
+
 // --------------------------------------------------------------------------
 // One block, after k_fused: combines its per-block partials (and the force
 // kernel's energy partials) in block order, records the estimators and the
 // running sums, advances the step counter and decides the neighbor-list
 // rebuild for the coming force pass.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
+__device__ void finalize_system(const FusedArgs &a, int nblocks, double *red)
 {
-    __shared__ double red[kBlock * 4];
     const int t = threadIdx.x;
     const int P = a.P;
     const int mode = a.mode;
     Ctl *c = a.ctl;
+    if (mode == FUSED_STEP && c->budget == 0) {
+        // no step was taken: nothing to combine, and no force pass follows
+        if (t == 0) c->ran = 0;
+        return;
+    }
     const unsigned long long step = c->step;
     const int synced = c->synced;
     const int ext = !a.pair;
@@ -428,23 +390,46 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
         if (mode == FUSED_STEP) {
             c->step = step + 1;
             c->synced = ext ? 1 : 0;
+            if (c->budget > 0) c->budget -= 1;
         } else if (mode == FUSED_CLOSE) {
             c->synced = 1;
         }
+        c->ran = 1;
         if (a.pair && mode == FUSED_PREP) {
             c->rebuild = 1;
             c->ebuild = emax;
             c->rlist = a.rc + a.skin + 2.0 * emax;
+            c->n_rebuilds += 1;
         } else if (a.pair && mode == FUSED_STEP) {
             if (dmax + emax > 0.5 * a.skin + c->ebuild) {
                 c->rebuild = 1;
                 c->ebuild = emax;
                 c->rlist = a.rc + a.skin + 2.0 * emax;
+                c->n_rebuilds += 1;
             } else {
                 c->rebuild = 0;
             }
         }
         if (bad != 0.0) c->nonfinite = 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
+{
+    __shared__ double red[kBlock * 4];
+    finalize_system(a, nblocks, red);
+}
+
+// Batched: block s finalizes system s from its per-tile partials.
+__global__ __launch_bounds__(kBlock) void k_finalize_batch(const FusedArgs *table,
+                                                           const int *nparts, int n_sys, int mode)
+{
+    __shared__ double red[kBlock * 4];
+    for (int sidx = blockIdx.x; sidx < n_sys; sidx += gridDim.x) {
+        FusedArgs a = table[sidx];
+        a.mode = mode;
+        if (nparts[sidx] > 0) finalize_system(a, nparts[sidx], red);
+        __syncthreads();
     }
 }
 
@@ -496,17 +481,49 @@ __device__ __forceinline__ void unpack_shift(int p, double &sx, double &sy, doub
     sz = (double)(((p >> 20) & 1023) - 512);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
+// Blocks are dispatched round-robin over the 8 XCDs; map them so that each
+// XCD gets a contiguous range of tiles (neighboring atoms, hence a shared
+// neighborhood in that XCD's L2).  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_tile(int b, int nb)
 {
-    __shared__ int s_cnt[kBlock];
-    __shared__ double red[kBlock];
-    const int P = a.P;
-    const int A = kBlock / P;
+    constexpr int kXcd = 8;
+    const int q = nb / kXcd, r = nb % kXcd;
+    const int xcd = b % kXcd, idx = b / kXcd;
+    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+__device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, double rc2,
+                                              double sig2, double eps4, double eps24,
+                                              double ushift, double &fx, double &fy,
+                                              double &fz, double &e)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rc2) {
+        const double ir2 = 1.0 / r2;
+        const double sr2 = sig2 * ir2;
+        const double sr6 = sr2 * sr2 * sr2;
+        const double fr = eps24 * (2.0 * sr6 * sr6 - sr6) * ir2;
+        e += 0.5 * (eps4 * (sr6 * sr6 - sr6) - ushift);
+        fx += fr * dx; fy += fr * dy; fz += fr * dz;
+    }
+}
+
+// Thread = (atom, sub-group s, bead k).  The S sub-groups of an atom share
+// its neighbor list (entry q goes to sub-group q mod S) and their partial
+// forces are combined in sub-group order through shared memory; S > 1 only
+// when the system alone would leave the GPU with few waves to hide latency.
+__device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, double *s_f)
+{
+    const int P = a.P, S = a.S;
+    const int G = S * P;                    // lanes per atom
+    const int A = kBlock / G;               // atoms per block
     const int t = threadIdx.x;
-    const int la = t / P, k = t - (t / P) * P;
-    const int i = blockIdx.x * A + la;
+    const int la = t / G, g = t - la * G;   // atom slot, lane within the atom's group
+    const int sg = g / P, k = g - sg * P;   // sub-group, bead
+    const int i = tile * A + la;
     const bool act = (la < A) && (i < a.N);
     const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
+    if (!a.ctl->ran) return;   // the system took no step (uniform per block)
 
     // A list cutoff that is not finite (non-finite positions) or that would
     // need more than kMaxImages periodic images per dim skips the build and
@@ -516,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
     const bool rl_ok = isfinite(rl_in) && rl_in > 0.0 && rl_in <= kMaxImages * L0 &&
                        rl_in <= kMaxImages * L1 && rl_in <= kMaxImages * L2;
     if (a.ctl->rebuild && !rl_ok) {
-        if (blockIdx.x == 0 && t == 0) a.ctl->nonfinite = 1;
+        if (tile == 0 && t == 0) a.ctl->nonfinite = 1;
     }
     if (a.ctl->rebuild && rl_ok) {
         const double rl = rl_in;
@@ -532,8 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
         }
         int total = 0;
         int2 *mylist = a.nbr + (size_t)(builder ? i : 0) * a.cap;
-        for (int j0 = 0; j0 < a.n_active; j0 += P) {
-            const int j = j0 + k;
+        for (int j0 = 0; j0 < a.n_active; j0 += G) {
+            const int j = j0 + g;
             int cnt = 0;
             double dx = 0, dy = 0, dz = 0;
             int bx = 0, by = 0, bz = 0;
@@ -558,9 +575,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
             __syncthreads();
             int off = 0, chunk = 0;
             if (la < A) {
-                for (int q = 0; q < P; ++q) {
-                    const int c = s_cnt[la * P + q];
-                    if (q < k) off += c;
+                for (int q = 0; q < G; ++q) {
+                    const int c = s_cnt[la * G + q];
+                    if (q < g) off += c;
                     chunk += c;
                 }
             }
@@ -581,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
             total += chunk;
             __syncthreads();
         }
-        if (act && k == 0) {
+        if (act && g == 0) {
             if (i < a.n_active) {
                 if (total > a.cap) {
                     a.ctl->overflow = 1;
@@ -600,62 +617,161 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
     }
 
     double e = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    const int P3 = 3 * P;
+    const size_t ib = (size_t)i * P3 + k;
     if (act) {
-        const int P3 = 3 * P;
-        const size_t ib = (size_t)i * P3 + k;
-        const double xi = a.x[ib], yi = a.x[ib + P], zi = a.x[ib + 2 * P];
-        double fx = 0.0, fy = 0.0, fz = 0.0;
+        const double *__restrict__ X = a.x;
+        const double xi = X[ib], yi = X[ib + P], zi = X[ib + 2 * P];
         const int cnt = (i < a.n_active) ? a.nbr_count[i] : 0;
-        const int2 *lst = a.nbr + (size_t)i * a.cap;
+        const int2 *__restrict__ lst = a.nbr + (size_t)i * a.cap;
         const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
-        for (int q = 0; q < cnt; ++q) {
+        const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
+        int q = sg;
+        // four entries per iteration: all gathers issued before any use
+        for (; q + 3 * S < cnt; q += 4 * S) {
+            int2 en[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) en[u] = lst[q + u * S];
+            double xj[4], yj[4], zj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t jb = (size_t)en[u].x * P3 + k;
+                xj[u] = X[jb]; yj[u] = X[jb + P]; zj[u] = X[jb + 2 * P];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double sx, sy, sz;
+                unpack_shift(en[u].y, sx, sy, sz);
+                lj_accumulate(xi - xj[u] + sx * L0, yi - yj[u] + sy * L1, zi - zj[u] + sz * L2,
+                              rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
+            }
+        }
+        for (; q < cnt; q += S) {
             const int2 en = lst[q];
             double sx, sy, sz;
             unpack_shift(en.y, sx, sy, sz);
             const size_t jb = (size_t)en.x * P3 + k;
-            const double dx = xi - a.x[jb] + sx * L0;
-            const double dy = yi - a.x[jb + P] + sy * L1;
-            const double dz = zi - a.x[jb + 2 * P] + sz * L2;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < a.rc2) {
-                const double sr2 = a.lj_sig2 / r2;
-                const double sr6 = sr2 * sr2 * sr2;
-                const double fr = eps24 * (2.0 * sr6 * sr6 - sr6) / r2;
-                e += 0.5 * (eps4 * (sr6 * sr6 - sr6) - a.lj_ushift);
+            lj_accumulate(xi - X[jb] + sx * L0, yi - X[jb + P] + sy * L1, zi - X[jb + 2 * P] + sz * L2,
+                          rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
+        }
+        if (sg == 0) {
+            for (int bb = 0; bb < kMaxBonds; ++bb) {
+                const int j = a.bond_j[i * kMaxBonds + bb];
+                if (j < 0) break;
+                const size_t jb = (size_t)j * P3 + k;
+                double dx = xi - X[jb], dy = yi - X[jb + P], dz = zi - X[jb + 2 * P];
+                dx -= L0 * rint(dx / L0);
+                dy -= L1 * rint(dy / L1);
+                dz -= L2 * rint(dz / L2);
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double dr = r - a.bond_r0;
+                const double fr = -2.0 * a.bond_k * dr / r;
+                e += 0.5 * a.bond_k * dr * dr;
                 fx += fr * dx; fy += fr * dy; fz += fr * dz;
             }
         }
-        for (int b = 0; b < kMaxBonds; ++b) {
-            const int j = a.bond_j[i * kMaxBonds + b];
-            if (j < 0) break;
-            const size_t jb = (size_t)j * P3 + k;
-            double dx = xi - a.x[jb], dy = yi - a.x[jb + P], dz = zi - a.x[jb + 2 * P];
-            dx -= L0 * rint(dx / L0);
-            dy -= L1 * rint(dy / L1);
-            dz -= L2 * rint(dz / L2);
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            const double dr = r - a.bond_r0;
-            const double fr = -2.0 * a.bond_k * dr / r;
-            e += 0.5 * a.bond_k * dr * dr;
-            fx += fr * dx; fy += fr * dy; fz += fr * dz;
+    }
+    if (S > 1) {
+        s_f[t * 3] = fx; s_f[t * 3 + 1] = fy; s_f[t * 3 + 2] = fz;
+        __syncthreads();
+        if (act && sg == 0) {
+            for (int u = 1; u < S; ++u) {
+                const int o = (la * G + u * P + k) * 3;
+                fx += s_f[o]; fy += s_f[o + 1]; fz += s_f[o + 2];
+            }
         }
+    }
+    if (act && sg == 0) {
         a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
     }
-    double s1[1] = {e};
-    // block sum (fixed order); red is sized for one value per thread
-    red[t] = s1[0];
+    // block sum (fixed order)
+    red[t] = e;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (t == 0) a.fpartials[blockIdx.x] = red[0];
+    if (t == 0) a.fpartials[tile] = red[0];
+    __syncthreads();
 }
 
-int pair_grid(int N, int P)
+__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
 {
-    const int A = kBlock / P;
+    __shared__ int s_cnt[kBlock];
+    __shared__ double red[kBlock];
+    __shared__ double s_f[kBlock * 3];
+    // Tiles holding LJ-active atoms come first.  Each of the two tile ranges
+    // is laid out contiguously per XCD, so both are spread over all XCDs.
+    const int b = blockIdx.x, nA = a.n_active_tiles;
+    const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
+    pair_tile(a, tile, s_cnt, red, s_f);
+}
+
+// Batched: one (system, tile) item per block iteration.
+__global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *table, const int2 *items,
+                                                       int n_items)
+{
+    __shared__ int s_cnt[kBlock];
+    __shared__ double red[kBlock];
+    __shared__ double s_f[kBlock * 3];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = items[it];
+        const PairArgs a = table[item.x];
+        pair_tile(a, item.y, s_cnt, red, s_f);
+    }
+}
+
+int pair_subgroups(int N, int P)
+{
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    }
+    // aim for at least 16 waves per CU
+    const long long target = 16LL * 64 * ncu;
+    int S = 1;
+    while (2 * S * P <= kBlock && (long long)N * P * S < target) S *= 2;
+    return S;
+}
+
+int pair_grid(int N, int P, int S)
+{
+    const int A = kBlock / (S * P);
     return (N + A - 1) / A;
+}
+
+int pair_active_tiles(int n_active, int P, int S)
+{
+    const int A = kBlock / (S * P);
+    return (n_active + A - 1) / A;
+}
+
+void launch_fused_batch(const FusedArgs *table, const int2 *items, int n_items, int mode,
+                        int smem_bytes, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fused_batch, dim3(grid), dim3(kBlock), smem_bytes, s, table, items,
+                       n_items, mode);
+}
+
+void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys, int mode,
+                           hipStream_t s)
+{
+    const int grid = n_sys < 1024 ? n_sys : 1024;
+    hipLaunchKernelGGL(k_finalize_batch, dim3(grid), dim3(kBlock), 0, s, table, nparts, n_sys, mode);
+}
+
+void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pair_batch, dim3(grid), dim3(kBlock), 0, s, table, items, n_items);
+}
+
+void set_batch_smem(int smem_bytes)
+{
+    (void)hipFuncSetAttribute((const void *)k_fused_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              smem_bytes);
 }
 
 void launch_pair(const PairArgs &a, int grid, hipStream_t s)
@@ -737,9 +853,11 @@ __global__ void k_ctl_init(Ctl *c, unsigned long long step)
         c->rebuild = 1;
         c->rlist = 0.0;
         c->ebuild = 0.0;
-        c->done = 0;
         c->nonfinite = 0;
         c->overflow = 0;
+        c->n_rebuilds = 0;
+        c->budget = -1;
+        c->ran = 1;
         c->est_step = step;
         c->count = 0;
         for (int q = 0; q < kNumEst; ++q) {
@@ -748,6 +866,16 @@ __global__ void k_ctl_init(Ctl *c, unsigned long long step)
             c->sumsq[q] = 0.0;
         }
     }
+}
+
+__global__ void k_ctl_set_budget(Ctl *c, long long budget)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->budget = budget;
+}
+
+void launch_ctl_set_budget(Ctl *ctl, long long budget, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_set_budget, dim3(1), dim3(64), 0, s, ctl, budget);
 }
 
 void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s)

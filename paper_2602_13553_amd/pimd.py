@@ -20,10 +20,14 @@ ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PI
           -5: "PIMD_ERR_NONFINITE", -6: "PIMD_ERR_UNSUPPORTED", -7: "PIMD_ERR_OVERFLOW"}
 PIMD_NVT, PIMD_NVE = 0, 1
 PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER = 0, 1, 2, 3
+PIMD_FLAG_VALU_TRANSFORMS = 1
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_destroy",
-            "pimd_last_error", "pimd_profile_begin", "pimd_profile_end")
+            "pimd_last_error", "pimd_profile_begin", "pimd_profile_end",
+            "pimd_batch_create", "pimd_batch_add", "pimd_batch_remove", "pimd_batch_set_state",
+            "pimd_batch_set_budget", "pimd_batch_step", "pimd_batch_get_estimators",
+            "pimd_batch_get_state", "pimd_batch_destroy", "pimd_batch_last_error")
 KERNEL_NAMES = ("fused", "pair", "close", "finalize")
 
 
@@ -41,7 +45,7 @@ class pimd_params(C.Structure):
         ("box", C.c_double * 3), ("seed", C.c_uint64), ("omega", C.c_double),
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double), ("lj_rc", C.c_double),
         ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
-        ("nbr_capacity", C.c_int32), ("reserved", C.c_int32),
+        ("nbr_capacity", C.c_int32), ("flags", C.c_int32),
     ]
 
 
@@ -53,7 +57,7 @@ class pimd_topology(C.Structure):
 class pimd_estimators(C.Structure):
     _fields_ = [("step", C.c_uint64), ("value", C.c_double * 7), ("count", C.c_uint64),
                 ("sum", C.c_double * 7), ("sumsq", C.c_double * 7), ("nonfinite", C.c_int32),
-                ("overflow", C.c_int32)]
+                ("overflow", C.c_int32), ("n_rebuilds", C.c_uint64), ("rlist", C.c_double)]
 
 
 class pimd_profile(C.Structure):
@@ -90,8 +94,24 @@ def load() -> C.CDLL:
         lib.pimd_profile_end.argtypes = [C.c_void_p, P(pimd_profile)]
         lib.pimd_last_error.argtypes = [C.c_void_p]
         lib.pimd_last_error.restype = C.c_char_p
+        lib.pimd_batch_create.argtypes = [C.c_void_p, P(C.c_void_p)]
+        lib.pimd_batch_add.argtypes = [C.c_void_p, P(pimd_params), P(C.c_double), P(pimd_topology),
+                                       P(C.c_int32)]
+        lib.pimd_batch_remove.argtypes = [C.c_void_p, C.c_int32]
+        lib.pimd_batch_set_state.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
+                                             C.c_uint64]
+        lib.pimd_batch_set_budget.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+        lib.pimd_batch_step.argtypes = [C.c_void_p, C.c_int64]
+        lib.pimd_batch_get_estimators.argtypes = [C.c_void_p, C.c_int32, P(pimd_estimators)]
+        lib.pimd_batch_get_state.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
+                                             P(C.c_uint64)]
+        lib.pimd_batch_destroy.argtypes = [C.c_void_p]
+        lib.pimd_batch_destroy.restype = None
+        lib.pimd_batch_last_error.argtypes = [C.c_void_p]
+        lib.pimd_batch_last_error.restype = C.c_char_p
         for n in EXPORTED:
-            if n not in ("pimd_destroy", "pimd_last_error"):
+            if n not in ("pimd_destroy", "pimd_last_error", "pimd_batch_destroy",
+                         "pimd_batch_last_error"):
                 getattr(lib, n).restype = C.c_int
         _lib = lib
     return _lib
@@ -101,9 +121,38 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
 
 
-def params_from_spec(spec) -> pimd_params:
+def _estimators_dict(e) -> dict:
+    out = {n: e.value[q] for q, n in enumerate(ESTIMATOR_NAMES)}
+    out["step"] = e.step
+    out["count"] = e.count
+    out["sum"] = {n: e.sum[q] for q, n in enumerate(ESTIMATOR_NAMES)}
+    out["sumsq"] = {n: e.sumsq[q] for q, n in enumerate(ESTIMATOR_NAMES)}
+    out["nonfinite"], out["overflow"] = e.nonfinite, e.overflow
+    out["n_rebuilds"], out["rlist"] = int(e.n_rebuilds), float(e.rlist)
+    return out
+
+
+def _topology(lj_active, bonds, keep: list):
+    if lj_active is None and bonds is None:
+        return None
+    t = pimd_topology()
+    if lj_active is not None:
+        act = np.ascontiguousarray(lj_active, dtype=np.int32)
+        keep.append(act)
+        t.lj_active = act.ctypes.data_as(C.POINTER(C.c_int32))
+    if bonds is not None and len(bonds):
+        bd = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
+        keep.append(bd)
+        t.n_bonds = bd.shape[0]
+        t.bonds = bd.ctypes.data_as(C.POINTER(C.c_int32))
+    keep.append(t)
+    return t
+
+
+def params_from_spec(spec, flags: int = 0) -> pimd_params:
     """Fill pimd_params from a workload spec (``inputs.SystemSpec``)."""
     p = pimd_params()
+    p.flags = int(flags)
     p.n_atoms, p.n_beads = spec.n_atoms, spec.n_beads
     p.ensemble, p.potential = int(spec.ensemble), int(spec.potential)
     p.temp, p.kB, p.hbar, p.mvv2e = spec.temp, spec.kB, spec.hbar, spec.mvv2e
@@ -158,9 +207,9 @@ class Context:
         self._h = h
 
     @classmethod
-    def from_spec(cls, spec, **kw) -> "Context":
-        return cls(params_from_spec(spec), spec.mass, lj_active=spec.lj_active, bonds=spec.bonds,
-                   **kw)
+    def from_spec(cls, spec, flags: int = 0, **kw) -> "Context":
+        return cls(params_from_spec(spec, flags), spec.mass, lj_active=spec.lj_active,
+                   bonds=spec.bonds, **kw)
 
     def _check(self, rc: int, h) -> None:
         if rc != PIMD_OK:
@@ -181,13 +230,7 @@ class Context:
         rc = self._lib.pimd_get_estimators(self._h, C.byref(e))
         if check:
             self._check(rc, self._h)
-        out = {n: e.value[q] for q, n in enumerate(ESTIMATOR_NAMES)}
-        out["step"] = e.step
-        out["count"] = e.count
-        out["sum"] = {n: e.sum[q] for q, n in enumerate(ESTIMATOR_NAMES)}
-        out["sumsq"] = {n: e.sumsq[q] for q, n in enumerate(ESTIMATOR_NAMES)}
-        out["nonfinite"], out["overflow"] = e.nonfinite, e.overflow
-        return out
+        return _estimators_dict(e)
 
     def get_state(self):
         x = np.empty((self.P, self.N, 3))
@@ -225,3 +268,76 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Many independent systems stepped together (wraps a ``pimd_batch``)."""
+
+    def __init__(self, stream=None):
+        self._lib = load()
+        h = C.c_void_p()
+        self._check(self._lib.pimd_batch_create(C.c_void_p(stream) if stream else None,
+                                                C.byref(h)), None)
+        self._h = h
+        self.shapes = {}
+
+    def _check(self, rc: int, h) -> None:
+        if rc != PIMD_OK:
+            msg = self._lib.pimd_batch_last_error(h)
+            raise PimdError(rc, msg.decode() if msg else "")
+
+    def add(self, spec, flags: int = 0) -> int:
+        keep = []
+        p = params_from_spec(spec, flags)
+        mass = np.ascontiguousarray(spec.mass, dtype=np.float64)
+        topo = _topology(spec.lj_active, spec.bonds, keep)
+        sid = C.c_int32()
+        self._check(self._lib.pimd_batch_add(self._h, C.byref(p), _dp(mass),
+                                             C.byref(topo) if topo is not None else None,
+                                             C.byref(sid)), self._h)
+        self.shapes[sid.value] = (spec.n_beads, spec.n_atoms)
+        return sid.value
+
+    def remove(self, sid: int) -> None:
+        self._check(self._lib.pimd_batch_remove(self._h, sid), self._h)
+        self.shapes.pop(sid, None)
+
+    def set_state(self, sid: int, x, v, step: int = 0) -> None:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert x.shape == self.shapes[sid] + (3,) and v.shape == x.shape
+        self._check(self._lib.pimd_batch_set_state(self._h, sid, _dp(x), _dp(v), int(step)),
+                    self._h)
+
+    def set_budget(self, sid: int, steps: int) -> None:
+        self._check(self._lib.pimd_batch_set_budget(self._h, sid, int(steps)), self._h)
+
+    def step(self, n: int = 1) -> None:
+        self._check(self._lib.pimd_batch_step(self._h, int(n)), self._h)
+
+    def estimators(self, sid: int, check: bool = True) -> dict:
+        e = pimd_estimators()
+        rc = self._lib.pimd_batch_get_estimators(self._h, sid, C.byref(e))
+        if check:
+            self._check(rc, self._h)
+        return _estimators_dict(e)
+
+    def get_state(self, sid: int):
+        P, N = self.shapes[sid]
+        x = np.empty((P, N, 3))
+        p = np.empty((P, N, 3))
+        s = C.c_uint64()
+        self._check(self._lib.pimd_batch_get_state(self._h, sid, _dp(x), _dp(p), C.byref(s)),
+                    self._h)
+        return x, p, int(s.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.pimd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
