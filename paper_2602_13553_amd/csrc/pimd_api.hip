@@ -23,7 +23,7 @@ thread_local std::string g_create_error = "no error";
 constexpr int kGraphChunk = 32;   // steps per captured graph
 
 struct Layout {
-    size_t x, v, f, stage, cent, cref, M, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
+    size_t x, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
         partials, fpartials, ctl, total;
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
     int valu_tiles, mfma_tiles;
@@ -43,7 +43,7 @@ struct pimd_ctx {
     char *ws = nullptr;
     bool own_ws = false;
     bool have_state = false;
-    double *d_x, *d_v, *d_f, *d_stage, *d_cent, *d_cref, *d_M, *d_modes, *d_atoms, *d_mass;
+    double *d_x, *d_v, *d_f, *d_stage, *d_cent, *d_cref, *d_M, *d_MT, *d_modes, *d_atoms, *d_mass;
     double *d_partials, *d_fpartials;
     int *d_orig, *d_bond_j, *d_nbr_count;
     int2 *d_nbr;
@@ -192,6 +192,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap)
     L.cent = take(N * 3 * sizeof(double));
     L.cref = take(N * 3 * sizeof(double));
     L.M = take(P * P * sizeof(double));
+    L.MT = take(P * P * sizeof(double));
     L.modes = take(P * 8 * sizeof(double));
     L.atoms = take(N * 4 * sizeof(double));
     L.mass = take(N * sizeof(double));
@@ -201,7 +202,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap)
     L.nbr = take(pair ? (size_t)n_active * cap * sizeof(int2) : 0);
     // partials: per block (single system) or per tile (batched execution)
     L.valu_tiles = (p->n_atoms + (kBlock / p->n_beads) - 1) / (kBlock / p->n_beads);
-    L.mfma_tiles = fused_mfma_supported(p->n_beads) ? mfma_block_tiles(p->n_atoms) : 0;
+    L.mfma_tiles = fused_mfma_supported(p->n_beads) ? mfma_block_tiles(p->n_atoms, p->n_beads) : 0;
     const int nparts = std::max(std::max(L.fused_grid, L.mfma_grid), std::max(L.valu_tiles, L.mfma_tiles));
     L.partials = take((size_t)nparts * PF_COUNT * sizeof(double));
     L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
@@ -404,6 +405,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     c->d_cent = (double *)(w + L.cent);
     c->d_cref = (double *)(w + L.cref);
     c->d_M = (double *)(w + L.M);
+    c->d_MT = (double *)(w + L.MT);
     c->d_modes = (double *)(w + L.modes);
     c->d_atoms = (double *)(w + L.atoms);
     c->d_mass = (double *)(w + L.mass);
@@ -417,6 +419,9 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
 
     // tables in internal order
     std::vector<double> M = nm_matrix(P), modes = mode_table(p);
+    std::vector<double> MT((size_t)P * P);
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j) MT[(size_t)j * P + k] = M[(size_t)k * P + j];
     std::vector<double> atoms((size_t)N * 4), m_int(N);
     const double kT = p->kB * p->temp;
     const int32_t *act = (p->potential == PIMD_POT_WATER && topo) ? topo->lj_active : nullptr;
@@ -444,6 +449,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpy(c->d_M, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_MT, MT.data(), MT.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_modes, modes.data(), modes.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_atoms, atoms.data(), atoms.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_mass, m_int.data(), m_int.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -471,7 +477,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.seed = p->seed;
     a.x = c->d_x; a.v = c->d_v; a.f = c->d_f; a.vin = c->d_f;
     a.cent = c->d_cent; a.cref = c->d_cref;
-    a.M = c->d_M; a.modes = c->d_modes; a.atoms = c->d_atoms; a.orig = c->d_orig;
+    a.M = c->d_M; a.MT = c->d_MT; a.modes = c->d_modes; a.atoms = c->d_atoms; a.orig = c->d_orig;
     a.partials = c->d_partials;
     a.fpartials = c->d_fpartials;
     a.n_fpartials = L.pair_grid;

@@ -1,17 +1,23 @@
 // Fused BAOAB step pass with the normal-mode transforms on the FP64 matrix
 // cores (v_mfma_f64_16x16x4f64), for P in {16, 32, 64}.
 //
-// Each wave owns a tile of 16 atoms and forms, per Cartesian dim d,
+// A block works on T = 64/P tiles of 16 atoms at once.  The x and f values of
+// those atoms are loaded into LDS with coalesced reads (atom rows padded to
+// 3P+1 doubles, which makes the operand reads conflict-free); each tile is
+// shared by P/16 waves, wave w taking mode block (and, in the inverse, bead
+// block) w % (P/16).  Per dim d the wave forms
 //   y~^T[atom][mode] = sum_bead (x - x_0)^T[atom][bead] M^T[bead][mode]
+//   f~^T[atom][mode] = sum_bead f^T[atom][bead] M^T[bead][mode]
 //   x^T[atom][bead]  = x_0 + sum_mode y~^T[atom][mode] M[mode][bead]
-// (App. B, Eqs. B1, B3; positions carried relative to bead 0, exact because
-// the non-centroid rows of M sum to zero).  The f~ = M f product is formed
-// the same way.  M is staged once per block in LDS with a padded stride.
+// (App. B, Eqs. B1, B3; positions relative to bead 0, exact because the
+// non-centroid rows of M sum to zero).  The wave's slices of M live in
+// registers; the new y~ goes to LDS (over the f values, no longer needed) for
+// the inverse.
 //
 // Operand layout of the instruction (checked on the device): A[i][k] in lane
 // i + 16k, B[k][j] in lane j + 16k, and accumulator register r of lane l
-// holds D[4r + l/16][l%16].  With atoms as rows, lane l therefore holds, for
-// one mode (column l%16 of a 16-mode block), the four atoms 4r + l/16: the
+// holds D[4r + l/16][l%16].  With atoms as rows, lane l holds, for one mode
+// (column l%16 of the wave's mode block), the four atoms 4r + l/16: the
 // per-(atom, mode) work (B, A, O with one Philox call for the three dims, A)
 // runs in registers, and v~ is read and written as 128-byte segments.
 #include "pimd_device.h"
@@ -30,52 +36,44 @@ __device__ __forceinline__ d4 mfma4(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Order this wave's LDS writes before its later LDS reads by other lanes.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int P>
 struct Lds {
-    static constexpr int PS = P + 1;              // padded row stride (conflict-free)
-    static constexpr int M_ELEMS = P * PS;        // M[mode][bead]
-    static constexpr int Y_ELEMS = 3 * 16 * PS;   // per wave: y~[d][atom][mode]
-    static constexpr int R_ELEMS = 16 * 4;        // per wave: [atom][d] bead-0 refs, centroids
-    static constexpr int bytes = 8 * (M_ELEMS + kWaves * (Y_ELEMS + 2 * R_ELEMS));
+    static constexpr int NMB = P / 16;            // mode blocks = waves per atom tile
+    static constexpr int T = kWaves / NMB;        // atom tiles per block
+    static constexpr int XS = 3 * P + 1;          // padded atom row of a tile
+    static constexpr int PS = P + 1;              // padded row of the y~ staging
+    static constexpr int X_ELEMS = 16 * XS;
+    static constexpr int Y_ELEMS = 3 * 16 * PS;
+    static constexpr int C_ELEMS = 16 * 4;        // centroids [atom][d]
+    static constexpr int TILE = 2 * X_ELEMS + Y_ELEMS + C_ELEMS;
+    static constexpr int bytes = 8 * T * TILE;
 };
 
 }  // namespace
 
-// Processes wave tiles first, first + stride, ... (per wave) of one system and
-// writes one set of partials for the block.
+// Processes block tiles first, first + stride, ... (T*16 atoms each) of one
+// system and writes one set of partials for the block.
 template <int P>
 __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *smem, double *red,
-                           double *partial_out, bool stage_m)
+                           double *partial_out)
 {
     // a system whose step budget is spent takes no step (uniform per block)
     if (a.ctl->budget == 0) return;
     using L = Lds<P>;
-    constexpr int PS = L::PS;
-    constexpr int NB16 = P / 16;      // 16-wide mode (or bead) blocks
+    constexpr int NMB = L::NMB, T = L::T, XS = L::XS, PS = L::PS;
     constexpr int NK4 = P / 4;        // k-steps of 4
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int lr = l & 15, lq = l >> 4;
-    double *sM = smem;
-    double *sY = smem + L::M_ELEMS + w * L::Y_ELEMS;
-    double *sR = smem + L::M_ELEMS + kWaves * L::Y_ELEMS + w * 2 * L::R_ELEMS;
-    double *sC = sR + L::R_ELEMS;
-
-    __syncthreads();   // the previous call's shared-memory reads are done
-    if (stage_m) {
-        for (int e = t; e < P * P; e += kBlock) {
-            const int m = e / P, j = e - m * P;
-            sM[m * PS + j] = a.M[e];
-        }
-    }
-    __syncthreads();
+    const int tt = w / NMB;           // this wave's atom tile within the block
+    const int mb = w - tt * NMB;      // this wave's mode block (and bead block)
+    double *sX = smem + tt * L::TILE;             // [16][XS]: x of the tile's atoms
+    double *sF = sX + L::X_ELEMS;                 // [16][XS]: f
+    double *sY = sF + L::X_ELEMS;                 // [3][16][PS]: new y~
+    double *sC = sY + L::Y_ELEMS;                 // [16][4]: centroids
+    // B operands: forward M^T[4kb + lq][mb*16 + lr], inverse M[4kb + lq][mb*16 + lr];
+    // both are 4 rows x 16 consecutive columns per instruction (coalesced)
+    const double *bmT = a.MT + lq * P + mb * 16 + lr;
+    const double *bmM = a.M + lq * P + mb * 16 + lr;
 
     const int N = a.N;
     const unsigned long long step = a.ctl->step;
@@ -84,173 +82,175 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const bool closing = a.pair && !synced;
     const bool need_f = a.pair != 0;
     const double sqrtP = sqrt((double)P);
+    const int m = mb * 16 + lr;       // this lane's mode
+    double mk[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mk[q] = a.modes[m * 8 + q];
+    const double off = (m == 0) ? sqrtP : 0.0;
 
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
     double acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
 
-    const int ntw = (N + 15) / 16;
-    for (int tw = first + w; tw < ntw; tw += stride) {
-        const int a0 = tw * 16;
-        wave_lds_sync();   // the previous tile's LDS reads are done
-        // operand-row atom of this lane (A[row = lr][k])
-        const int ia_op = a0 + lr;
-        const bool ok_op = ia_op < N;
-        const size_t base_op = (size_t)(ok_op ? ia_op : 0) * 3 * P;
-        double x0op[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) x0op[d] = ok_op ? a.x[base_op + d * P] : 0.0;
-        if (lq == 0) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) sR[lr * 4 + d] = x0op[d];
+    const int nbt = (N + 16 * T - 1) / (16 * T);
+    for (int bt = first; bt < nbt; bt += stride) {
+        const int b0 = bt * 16 * T;                    // first atom of the block tile
+        __syncthreads();                               // previous tile's LDS use is done
+        {
+            // coalesced load of x (and f) of the block's atoms into the tiles
+            const int nat = min(16 * T, N - b0);
+            const int nel = nat * 3 * P;
+            const double *xg = a.x + (size_t)b0 * 3 * P;
+            const double *fg = need_f ? a.f + (size_t)b0 * 3 * P : nullptr;
+            for (int e = t; e < nel; e += kBlock) {
+                const int at = e / (3 * P), r = e - at * (3 * P);
+                const int tile = at >> 4, row = at & 15;
+                double *dst = smem + tile * L::TILE + row * XS + r;
+                dst[0] = xg[e];
+                if (need_f) dst[L::X_ELEMS] = fg[e];
+            }
         }
-        wave_lds_sync();
+        __syncthreads();
 
-        for (int mb = 0; mb < NB16; ++mb) {
-            d4 ay[3], af[3];
+        const int a0 = b0 + tt * 16;
+        const bool ok_op = (a0 + lr) < N;
+        d4 ay[3], af[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ay[d] = d4{0.0, 0.0, 0.0, 0.0};
+            af[d] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+        const double *xr = sX + lr * XS;
+        const double *fr = sF + lr * XS;
+#pragma unroll 4
+        for (int kb = 0; kb < NK4; ++kb) {
+            const int bead = 4 * kb + lq;
+            const double bm = bmT[4 * kb * P];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                ay[d] = d4{0.0, 0.0, 0.0, 0.0};
-                af[d] = d4{0.0, 0.0, 0.0, 0.0};
-            }
-#pragma unroll 4
-            for (int kb = 0; kb < NK4; ++kb) {
-                const int bead = kb * 4 + lq;
-                const double bm = sM[(mb * 16 + lr) * PS + bead];   // M[mode][bead]
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double xv = ok_op ? a.x[base_op + d * P + bead] - x0op[d] : 0.0;
-                    ay[d] = mfma4(xv, bm, ay[d]);
-                    if (need_f) {
-                        const double fv = ok_op ? a.f[base_op + d * P + bead] : 0.0;
-                        af[d] = mfma4(fv, bm, af[d]);
-                    }
-                }
-            }
-            // lane l, register r: atom 4r + lq, mode mb*16 + lr
-            const int m = mb * 16 + lr;
-            double mk[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) mk[q] = a.modes[m * 8 + q];
-            const double off = (m == 0) ? sqrtP : 0.0;
-            // one atom at a time keeps a single Philox chain live
-#pragma unroll 1
-            for (int r = 0; r < 4; ++r) {
-                const int ra = 4 * r + lq;
-                const int ia = a0 + ra;
-                if (ia >= N) continue;
-                const double hm = a.atoms[ia * 4 + AT_HALF_M];
-                const double im = a.atoms[ia * 4 + AT_INV_M];
-                const double sg = a.atoms[ia * 4 + AT_SIGMA];
-                const double active = a.atoms[ia * 4 + AT_ACTIVE];
-                double xt[3], ft[3], vt[3], x0[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    xt[d] = ay[d][r];
-                    ft[d] = af[d][r];
-                    x0[d] = sR[ra * 4 + d];
-                }
-                const size_t vb = (size_t)ia * 3 * P + m;
-                vt[0] = a.v[vb]; vt[1] = a.v[vb + P]; vt[2] = a.v[vb + 2 * P];
-                if (ext) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * x0[d]);
-                }
-                if (closing) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        vt[d] += a.hdt * im * ft[d];
-                        acc_ekin += hm * vt[d] * vt[d];
-                        acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
-                        acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
-                    }
-                }
-                // opening B, A(dt/2), O(dt), A(dt/2)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double q = xt[d], p = vt[d];
-                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
-                }
-                if (a.nvt) {
-                    double z[3];
-                    gauss3(a.seed, (unsigned long long)a.orig[ia], (unsigned long long)m, step, z);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double q = xt[d], p = vt[d];
-                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
-                }
-                if (ext) {
-                    // closing B with the trap force of the new positions, and
-                    // the estimators of the new state
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double xa = xt[d] + off * x0[d];
-                        ft[d] = -2.0 * hm * a.omega2 * xa;
-                        vt[d] += a.hdt * im * ft[d];
-                        acc_ekin += hm * vt[d] * vt[d];
-                        acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
-                        acc_uext += hm * a.omega2 * xa * xa;
-                        acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
-                    }
-                }
-                a.v[vb] = vt[0]; a.v[vb + P] = vt[1]; a.v[vb + 2 * P] = vt[2];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    if (!isfinite(vt[d])) acc_bad = 1.0;
-                    sY[(d * 16 + ra) * PS + m] = xt[d];
-                }
-                if (m == 0) {
-                    double d2 = 0.0;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double c = x0[d] + xt[d] / sqrtP;
-                        sC[ra * 4 + d] = c;
-                        a.cent[ia * 3 + d] = c;
-                        const double dd = c - a.cref[ia * 3 + d];
-                        d2 += dd * dd;
-                    }
-                    if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
+                const double xv = ok_op ? xr[d * P + bead] - xr[d * P] : 0.0;
+                ay[d] = mfma4(xv, bm, ay[d]);
+                if (need_f) {
+                    const double fv = ok_op ? fr[d * P + bead] : 0.0;
+                    af[d] = mfma4(fv, bm, af[d]);
                 }
             }
         }
-        wave_lds_sync();
-
-        // inverse: x^T[atom][bead] = x_0 + sum_mode y~^T[atom][mode] M[mode][bead]
-        for (int jb = 0; jb < NB16; ++jb) {
-            d4 ax[3];
+        // lane l, register r: atom a0 + 4r + lq, mode m
+#pragma unroll 1
+        for (int r = 0; r < 4; ++r) {
+            const int ra = 4 * r + lq;
+            const int ia = a0 + ra;
+            if (ia >= N) continue;
+            const double hm = a.atoms[ia * 4 + AT_HALF_M];
+            const double im = a.atoms[ia * 4 + AT_INV_M];
+            const double sg = a.atoms[ia * 4 + AT_SIGMA];
+            const double active = a.atoms[ia * 4 + AT_ACTIVE];
+            double xt[3], ft[3], vt[3], x0[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ax[d] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-            for (int kb = 0; kb < NK4; ++kb) {
-                const int m = kb * 4 + lq;
-                const double bm = sM[m * PS + jb * 16 + lr];   // M[mode][bead]
-#pragma unroll
-                for (int d = 0; d < 3; ++d) ax[d] = mfma4(sY[(d * 16 + lr) * PS + m], bm, ax[d]);
+            for (int d = 0; d < 3; ++d) {
+                xt[d] = ay[d][r];
+                ft[d] = af[d][r];
+                x0[d] = sX[ra * XS + d * P];
             }
-            const int bead = jb * 16 + lr;
+            const size_t vb = (size_t)ia * 3 * P + m;
+            vt[0] = a.v[vb]; vt[1] = a.v[vb + P]; vt[2] = a.v[vb + 2 * P];
+            if (ext) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ra = 4 * r + lq;
-                const int ia = a0 + ra;
-                if (ia >= N) continue;
-                const size_t xb = (size_t)ia * 3 * P + bead;
-                double e2 = 0.0;
+                for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * x0[d]);
+            }
+            if (closing) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double xj = sR[ra * 4 + d] + ax[d][r];
-                    a.x[xb + d * P] = xj;
-                    const double dd = xj - sC[ra * 4 + d];
-                    e2 += dd * dd;
-                    if (!isfinite(xj)) acc_bad = 1.0;
+                    vt[d] += a.hdt * im * ft[d];
+                    acc_ekin += hm * vt[d] * vt[d];
+                    acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
+                    acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
                 }
-                if (a.atoms[ia * 4 + AT_ACTIVE] != 0.0) acc_emax = fmax(acc_emax, e2);
             }
+            // opening B, A(dt/2), O(dt), A(dt/2)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double q = xt[d], p = vt[d];
+                xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
+                vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+            }
+            if (a.nvt) {
+                double z[3];
+                gauss3(a.seed, (unsigned long long)a.orig[ia], (unsigned long long)m, step, z);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double q = xt[d], p = vt[d];
+                xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
+                vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+            }
+            if (ext) {
+                // closing B with the trap force of the new positions, and
+                // the estimators of the new state
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double xa = xt[d] + off * x0[d];
+                    ft[d] = -2.0 * hm * a.omega2 * xa;
+                    vt[d] += a.hdt * im * ft[d];
+                    acc_ekin += hm * vt[d] * vt[d];
+                    acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
+                    acc_uext += hm * a.omega2 * xa * xa;
+                    acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
+                }
+            }
+            a.v[vb] = vt[0]; a.v[vb + P] = vt[1]; a.v[vb + 2 * P] = vt[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (!isfinite(vt[d])) acc_bad = 1.0;
+                sY[(d * 16 + ra) * PS + m] = xt[d];
+            }
+            if (m == 0) {
+                double d2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double c = x0[d] + xt[d] / sqrtP;
+                    sC[ra * 4 + d] = c;
+                    a.cent[ia * 3 + d] = c;
+                    const double dd = c - a.cref[ia * 3 + d];
+                    d2 += dd * dd;
+                }
+                if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
+            }
+        }
+        __syncthreads();   // the tile's y~ (all modes) and centroids are in LDS
+
+        // inverse for bead block mb: x^T = x_0 + sum_mode y~^T M
+        d4 ax[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ax[d] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int kb = 0; kb < NK4; ++kb) {
+            const int mm = 4 * kb + lq;
+            const double bm = bmM[4 * kb * P];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ax[d] = mfma4(sY[(d * 16 + lr) * PS + mm], bm, ax[d]);
+        }
+        const int bead = mb * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ra = 4 * r + lq;
+            const int ia = a0 + ra;
+            if (ia >= N) continue;
+            const size_t xb = (size_t)ia * 3 * P + bead;
+            double e2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double xj = sX[ra * XS + d * P] + ax[d][r];
+                a.x[xb + d * P] = xj;
+                const double dd = xj - sC[ra * 4 + d];
+                e2 += dd * dd;
+                if (!isfinite(xj)) acc_bad = 1.0;
+            }
+            if (a.atoms[ia * 4 + AT_ACTIVE] != 0.0) acc_emax = fmax(acc_emax, e2);
         }
     }
 
@@ -273,29 +273,25 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_fused_mfma(FusedArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma(FusedArgs a)
 {
     extern __shared__ double smem[];
     __shared__ double red[kBlock * 4];
-    mfma_tiles<P>(a, blockIdx.x * kWaves, gridDim.x * kWaves, smem, red,
-                  a.partials + (size_t)blockIdx.x * PF_COUNT, true);
+    mfma_tiles<P>(a, blockIdx.x, gridDim.x, smem, red, a.partials + (size_t)blockIdx.x * PF_COUNT);
 }
 
-// Batched: item (system, block tile of 4 x 16 atoms) for systems with this P.
+// Batched: item (system, block tile of T x 16 atoms) for systems with this P.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_fused_mfma_batch(const FusedArgs *table,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma_batch(const FusedArgs *table,
                                                              const int2 *items, int n_items)
 {
     extern __shared__ double smem[];
     __shared__ double red[kBlock * 4];
-    int prev = -1;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
         FusedArgs a = table[item.x];
         a.mode = FUSED_STEP;
-        mfma_tiles<P>(a, item.y * kWaves, 1 << 30, smem, red,
-                      a.partials + (size_t)item.y * PF_COUNT, item.x != prev);
-        prev = item.x;
+        mfma_tiles<P>(a, item.y, 1 << 30, smem, red, a.partials + (size_t)item.y * PF_COUNT);
     }
 }
 
@@ -316,8 +312,7 @@ int grid_for(int N)
                                                      Lds<P>::bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    const int ntiles = (N + 15) / 16;
-    const int want = (ntiles + kWaves - 1) / kWaves;
+    const int want = (N + 16 * Lds<P>::T - 1) / (16 * Lds<P>::T);
     const int cap = ncu * per_cu;
     return want < cap ? want : cap;
 }
@@ -353,7 +348,11 @@ void launch_fused_mfma(const FusedArgs &a, int grid, hipStream_t s)
     }
 }
 
-int mfma_block_tiles(int N) { return (N + 16 * kWaves - 1) / (16 * kWaves); }
+int mfma_block_tiles(int N, int P)
+{
+    const int T = kWaves / (P / 16);
+    return (N + 16 * T - 1) / (16 * T);
+}
 
 void set_mfma_batch_smem()
 {

@@ -72,6 +72,7 @@ struct FusedArgs {
     double *cent;             // [N][3] centroids (written)
     const double *cref;       // [N][3] centroids at the last list build
     const double *M;          // [P][P] normal-mode matrix, row = mode
+    const double *MT;         // [P][P] its transpose, row = bead
     const double *modes;      // [P][8] per-mode constants
     const double *atoms;      // [N][4] per-atom constants
     const int *orig;          // [N] caller's atom index (noise counter)
@@ -114,7 +115,7 @@ bool fused_mfma_supported(int P);
 int fused_mfma_grid(int N, int P);
 void launch_fused_mfma(const FusedArgs &a, int grid, hipStream_t s);
 // batched launches: items are (system index, tile) pairs grouped by system
-int mfma_block_tiles(int N);
+int mfma_block_tiles(int N, int P);
 void set_mfma_batch_smem();
 void launch_fused_mfma_batch(int P, const FusedArgs *table, const int2 *items, int n_items,
                              int grid, hipStream_t s);
