@@ -33,6 +33,18 @@ FUSED_BYTES_PAIR = 120         # per bead*atom: read x, v~, f; write x, v~ (FP64
 FUSED_BYTES_EXT = 96           # per bead*atom with in-kernel trap forces (no f array)
 
 
+WORKLOADS = {
+    "lj": ("LJ quantum liquid, N=4000, P=32, rho=0.8", inputs.lj_liquid,
+           "synthetic (seeded FCC LJ liquid, Maxwell-Boltzmann bead velocities at P*T)"),
+    "water32": ("water-shaped, N=32766, P=32", lambda: inputs.water(n_beads=32),
+                "synthetic (seeded water-shaped O/H lattice, Maxwell-Boltzmann bead velocities at P*T)"),
+    "water64": ("water-shaped, N=32766, P=64", lambda: inputs.water(n_beads=64),
+                "synthetic (seeded water-shaped O/H lattice, Maxwell-Boltzmann bead velocities at P*T)"),
+    "harmonic": ("harmonic oscillators, N=64, P=4", inputs.harmonic_tiny,
+                 "synthetic (seeded Gaussian positions, Maxwell-Boltzmann bead velocities at P*T)"),
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -44,7 +56,7 @@ def pairs_inside_cutoff(x, box, rc, active=None):
     L = np.asarray(box)
     tot = 0
     for k in range(x.shape[0]):
-        pts = x[k] if active is None else x[k][active]
+        pts = x[k] if active is None else x[k][np.asarray(active).astype(bool)]
         tree = cKDTree(np.mod(pts, L), boxsize=L)
         tot += 2 * len(tree.query_pairs(rc, output_type="ndarray"))
     return tot
@@ -173,15 +185,25 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="lj",
+                    help="workload of the timed steps (default: the LJ quantum liquid)")
+    ap.add_argument("--transforms", choices=("auto", "valu"), default="auto",
+                    help="valu: normal-mode transforms on the FP64 vector ALUs only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    spec = inputs.lj_liquid()
+    title, make, data = WORKLOADS[args.workload]
+    spec = make()
+    flags = 0
+    if args.transforms == "valu":
+        from paper_2602_13553_amd import pimd as _p
+        flags = _p.PIMD_FLAG_VALU_TRANSFORMS
     log("workload %s: %d warmup + %d timed steps" % (spec.name, args.warmup, args.steps))
-    ms_step, est, prof, ms_prof, x = run_gpu(spec, args.steps, args.warmup, args.profile_steps)
+    ms_step, est, prof, ms_prof, x = run_gpu(spec, args.steps, args.warmup, args.profile_steps,
+                                             flags)
     ba = spec.bead_atoms
     value = ba * 1e3 / ms_step
     avgs = kernel_avgs(prof)
@@ -190,7 +212,7 @@ def main():
     # dominant kernel of the workload and its roofline
     dom = max(("fused", "pair"), key=lambda k: avgs[k][0] * avgs[k][1])
     if dom == "pair":
-        npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc)
+        npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc, spec.lj_active)
         flops = LJ_FLOPS_PER_PAIR * npairs
         ach = flops / (avgs["pair"][0] * 1e-3) / 1e12
         roof = {"kernel": "k_pair", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
@@ -198,7 +220,7 @@ def main():
                 "work_per_launch": "%d ordered bead pairs inside rc x %d flops"
                                    % (npairs, LJ_FLOPS_PER_PAIR)}
     else:
-        byts = FUSED_BYTES_PAIR * ba
+        byts = (FUSED_BYTES_PAIR if spec.potential != inputs.POT_HARMONIC else FUSED_BYTES_EXT) * ba
         ach = byts / (avgs["fused"][0] * 1e-3) / 1e9
         roof = {"kernel": "k_fused", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
@@ -216,11 +238,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded FCC LJ liquid, Maxwell-Boltzmann bead velocities at P*T)",
-        "config": {"workload": "LJ quantum liquid", "n_atoms": spec.n_atoms,
-                   "n_beads": spec.n_beads, "bead_atoms": ba, "rho": 0.8, "kT": spec.temp,
+        "data": data,
+        "config": {"workload": title, "n_atoms": spec.n_atoms,
+                   "n_beads": spec.n_beads, "bead_atoms": ba, "kT": spec.temp,
                    "hbar": spec.hbar, "rc": spec.lj_rc, "dt": spec.dt, "tau": spec.tau,
-                   "ensemble": "NVT PILE-L", "integrator": "BAOAB"},
+                   "ensemble": "NVT PILE-L", "integrator": "BAOAB",
+                   "transforms": args.transforms},
         "roofline": roof,
         "kernels_ms": {k: v[0] for k, v in avgs.items()},
         "fused_in_cache_gbs": fused_gbs,

@@ -854,7 +854,7 @@ void enqueue_batch_step(pimd_batch *b)
     const int ncu = b->ncu;
     for (const auto &g : b->step_groups) {
         if (g.P)
-            launch_fused_mfma_batch(g.P, b->d_fa, b->d_items + g.off, g.n, std::min(g.n, 2 * ncu), b->stream);
+            launch_fused_mfma_batch(g.P, b->d_fa, b->d_items + g.off, g.n, g.n, b->stream);
         else
             launch_fused_batch(b->d_fa, b->d_items + g.off, g.n, FUSED_STEP, b->smem_valu,
                                std::min(g.n, 2 * ncu), b->stream);

@@ -42,34 +42,51 @@ struct Lds {
     static constexpr int T = kWaves / NMB;        // atom tiles per block
     static constexpr int XS = 3 * P + 1;          // padded atom row of a tile
     static constexpr int PS = P + 1;              // padded row of the y~ staging
-    static constexpr int X_ELEMS = 16 * XS;
-    static constexpr int Y_ELEMS = 3 * 16 * PS;
+    static constexpr int XY_ELEMS = 3 * 16 * PS;  // x [16][XS], later y~ [3][16][PS]
+    static constexpr int F_ELEMS = 16 * XS;       // f [16][XS]
+    static constexpr int AT_W = 12;               // per-atom row of the atom table
+    static constexpr int AT_ELEMS = 16 * AT_W;
     static constexpr int C_ELEMS = 16 * 4;        // centroids [atom][d]
-    static constexpr int TILE = 2 * X_ELEMS + Y_ELEMS + C_ELEMS;
-    static constexpr int bytes = 8 * T * TILE;
+    static constexpr int TILE = XY_ELEMS + F_ELEMS + AT_ELEMS + C_ELEMS;
+    static constexpr int MK_ELEMS = 8 * P;        // the per-mode table, shared by the block
+    static constexpr int bytes = 8 * (T * TILE + MK_ELEMS);
+    static constexpr int NLD = 16 * T * 3 * P / kBlock;   // tile elements per thread
+    static_assert(16 * XS <= XY_ELEMS, "x tile must fit the y~ region");
+    static_assert(16 * T * 3 * P == NLD * kBlock, "tile elements split evenly");
+    static_assert(16 * T <= kBlock, "one thread per atom of the block tile");
 };
+
+// atom-table columns (per atom of a tile)
+enum { TA_X0 = 0, TA_HM = 3, TA_IM = 4, TA_SG = 5, TA_ACT = 6, TA_ORIG = 7, TA_CREF = 8 };
 
 }  // namespace
 
 // Processes block tiles first, first + stride, ... (T*16 atoms each) of one
 // system and writes one set of partials for the block.
+//
+// Per block tile: every global read of the tile (x, f, this lane's v~, the
+// per-atom table) is issued at once into registers, before the barrier that
+// releases the previous tile's LDS; the forward products read x and f from
+// LDS; after a barrier the y~ of the update overwrite the x region; a last
+// barrier precedes the inverse products.
 template <int P>
-__device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *smem, double *red,
+__device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *smem,
                            double *partial_out)
 {
     // a system whose step budget is spent takes no step (uniform per block)
     if (a.ctl->budget == 0) return;
     using L = Lds<P>;
-    constexpr int NMB = L::NMB, T = L::T, XS = L::XS, PS = L::PS;
+    constexpr int NMB = L::NMB, T = L::T, XS = L::XS, PS = L::PS, NLD = L::NLD, AW = L::AT_W;
     constexpr int NK4 = P / 4;        // k-steps of 4
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int lr = l & 15, lq = l >> 4;
     const int tt = w / NMB;           // this wave's atom tile within the block
     const int mb = w - tt * NMB;      // this wave's mode block (and bead block)
-    double *sX = smem + tt * L::TILE;             // [16][XS]: x of the tile's atoms
-    double *sF = sX + L::X_ELEMS;                 // [16][XS]: f
-    double *sY = sF + L::X_ELEMS;                 // [3][16][PS]: new y~
-    double *sC = sY + L::Y_ELEMS;                 // [16][4]: centroids
+    double *sX = smem + tt * L::TILE;             // [16][XS] x, then y~ [3][16][PS]
+    double *sY = sX;
+    double *sF = sX + L::XY_ELEMS;                // [16][XS]: f
+    double *sA = sF + L::F_ELEMS;                 // [16][AW]: atom table
+    double *sC = sA + L::AT_ELEMS;                // [16][4]: centroids
     // B operands: forward M^T[4kb + lq][mb*16 + lr], inverse M[4kb + lq][mb*16 + lr];
     // both are 4 rows x 16 consecutive columns per instruction (coalesced)
     const double *bmT = a.MT + lq * P + mb * 16 + lr;
@@ -83,9 +100,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const bool need_f = a.pair != 0;
     const double sqrtP = sqrt((double)P);
     const int m = mb * 16 + lr;       // this lane's mode
-    double mk[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) mk[q] = a.modes[m * 8 + q];
+    double *sMk = smem + T * L::TILE;             // [P][8]: per-mode coefficients
+    for (int e = t; e < 8 * P; e += kBlock) sMk[e] = a.modes[e];
+    const double *mk = sMk + m * 8;
     const double off = (m == 0) ? sqrtP : 0.0;
 
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
@@ -94,24 +111,64 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const int nbt = (N + 16 * T - 1) / (16 * T);
     for (int bt = first; bt < nbt; bt += stride) {
         const int b0 = bt * 16 * T;                    // first atom of the block tile
-        __syncthreads();                               // previous tile's LDS use is done
+        const int nat = min(16 * T, N - b0);
+        const int nel = nat * 3 * P;
+        const int a0 = b0 + tt * 16;                   // first atom of this wave's tile
+
+        // ---- all global reads of the tile, in flight together
+        double rx[NLD], rf[NLD];
         {
-            // coalesced load of x (and f) of the block's atoms into the tiles
-            const int nat = min(16 * T, N - b0);
-            const int nel = nat * 3 * P;
             const double *xg = a.x + (size_t)b0 * 3 * P;
-            const double *fg = need_f ? a.f + (size_t)b0 * 3 * P : nullptr;
-            for (int e = t; e < nel; e += kBlock) {
-                const int at = e / (3 * P), r = e - at * (3 * P);
-                const int tile = at >> 4, row = at & 15;
-                double *dst = smem + tile * L::TILE + row * XS + r;
-                dst[0] = xg[e];
-                if (need_f) dst[L::X_ELEMS] = fg[e];
+            const double *fg = a.f + (size_t)b0 * 3 * P;
+#pragma unroll
+            for (int q = 0; q < NLD; ++q) {
+                const int e = t + q * kBlock;
+                rx[q] = e < nel ? xg[e] : 0.0;
+                rf[q] = (need_f && e < nel) ? fg[e] : 0.0;
             }
+        }
+        double rv[4][3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ia = a0 + 4 * r + lq;
+            const size_t vb = (size_t)ia * 3 * P + m;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) rv[r][d] = ia < N ? a.v[vb + d * P] : 0.0;
+        }
+        double ratom[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (t < nat) {
+            const int ia = b0 + t;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ratom[q] = a.atoms[ia * 4 + q];
+            ratom[4] = (double)a.orig[ia];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ratom[5 + d] = a.cref[ia * 3 + d];
+        }
+
+        __syncthreads();                               // previous tile's LDS use is done
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = t + q * kBlock;
+            const int at = e / (3 * P), rr = e - at * (3 * P);
+            double *dst = smem + (at >> 4) * L::TILE + (at & 15) * XS + rr;
+            dst[0] = rx[q];
+            dst[L::XY_ELEMS] = rf[q];
+            if (rr % P == 0) smem[(at >> 4) * L::TILE + L::XY_ELEMS + L::F_ELEMS +
+                                 (at & 15) * AW + TA_X0 + rr / P] = rx[q];
+        }
+        if (t < 16 * T) {
+            double *ar = smem + (t >> 4) * L::TILE + L::XY_ELEMS + L::F_ELEMS + (t & 15) * AW;
+            ar[TA_HM] = ratom[AT_HALF_M];
+            ar[TA_IM] = ratom[AT_INV_M];
+            ar[TA_SG] = ratom[AT_SIGMA];
+            ar[TA_ACT] = ratom[AT_ACTIVE];
+            ar[TA_ORIG] = ratom[4];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ar[TA_CREF + d] = ratom[5 + d];
         }
         __syncthreads();
 
-        const int a0 = b0 + tt * 16;
+        // ---- forward products: y~ and f~ of mode block mb for the tile's 16 atoms
         const bool ok_op = (a0 + lr) < N;
         d4 ay[3], af[3];
 #pragma unroll
@@ -135,25 +192,24 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 }
             }
         }
-        // lane l, register r: atom a0 + 4r + lq, mode m
-#pragma unroll 1
+        __syncthreads();   // every wave is done with the x tile before y~ replaces it
+
+        // ---- per (atom, mode) update: lane l, register r: atom a0 + 4r + lq, mode m
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ra = 4 * r + lq;
             const int ia = a0 + ra;
             if (ia >= N) continue;
-            const double hm = a.atoms[ia * 4 + AT_HALF_M];
-            const double im = a.atoms[ia * 4 + AT_INV_M];
-            const double sg = a.atoms[ia * 4 + AT_SIGMA];
-            const double active = a.atoms[ia * 4 + AT_ACTIVE];
+            const double *ar = sA + ra * AW;
+            const double hm = ar[TA_HM], im = ar[TA_IM], sg = ar[TA_SG];
             double xt[3], ft[3], vt[3], x0[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 xt[d] = ay[d][r];
                 ft[d] = af[d][r];
-                x0[d] = sX[ra * XS + d * P];
+                x0[d] = ar[TA_X0 + d];
+                vt[d] = rv[r][d];
             }
-            const size_t vb = (size_t)ia * 3 * P + m;
-            vt[0] = a.v[vb]; vt[1] = a.v[vb + P]; vt[2] = a.v[vb + 2 * P];
             if (ext) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * x0[d]);
@@ -178,7 +234,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             }
             if (a.nvt) {
                 double z[3];
-                gauss3(a.seed, (unsigned long long)a.orig[ia], (unsigned long long)m, step, z);
+                gauss3(a.seed, (unsigned long long)ar[TA_ORIG], (unsigned long long)m, step, z);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
             }
@@ -202,6 +258,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                     acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
                 }
             }
+            const size_t vb = (size_t)ia * 3 * P + m;
             a.v[vb] = vt[0]; a.v[vb + P] = vt[1]; a.v[vb + 2 * P] = vt[2];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -215,15 +272,15 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                     const double c = x0[d] + xt[d] / sqrtP;
                     sC[ra * 4 + d] = c;
                     a.cent[ia * 3 + d] = c;
-                    const double dd = c - a.cref[ia * 3 + d];
+                    const double dd = c - ar[TA_CREF + d];
                     d2 += dd * dd;
                 }
-                if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
+                if (ar[TA_ACT] != 0.0) acc_dmax = fmax(acc_dmax, d2);
             }
         }
         __syncthreads();   // the tile's y~ (all modes) and centroids are in LDS
 
-        // inverse for bead block mb: x^T = x_0 + sum_mode y~^T M
+        // ---- inverse for bead block mb: x^T = x_0 + sum_mode y~^T M
         d4 ax[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) ax[d] = d4{0.0, 0.0, 0.0, 0.0};
@@ -240,21 +297,25 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             const int ra = 4 * r + lq;
             const int ia = a0 + ra;
             if (ia >= N) continue;
+            const double *ar = sA + ra * AW;
             const size_t xb = (size_t)ia * 3 * P + bead;
             double e2 = 0.0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const double xj = sX[ra * XS + d * P] + ax[d][r];
+                const double xj = ar[TA_X0 + d] + ax[d][r];
                 a.x[xb + d * P] = xj;
                 const double dd = xj - sC[ra * 4 + d];
                 e2 += dd * dd;
                 if (!isfinite(xj)) acc_bad = 1.0;
             }
-            if (a.atoms[ia * 4 + AT_ACTIVE] != 0.0) acc_emax = fmax(acc_emax, e2);
+            if (ar[TA_ACT] != 0.0) acc_emax = fmax(acc_emax, e2);
         }
     }
 
-    // per-block partials (plain stores; k_finalize runs next)
+    // per-block partials (plain stores; k_finalize runs next); the reduction
+    // scratch reuses the tiles' LDS once every wave is done with it
+    __syncthreads();
+    double *red = smem;
     double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
     block_sum<4>(s4, red);
     const double emax = block_max(acc_emax, red);
@@ -276,23 +337,20 @@ template <int P>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma(FusedArgs a)
 {
     extern __shared__ double smem[];
-    __shared__ double red[kBlock * 4];
-    mfma_tiles<P>(a, blockIdx.x, gridDim.x, smem, red, a.partials + (size_t)blockIdx.x * PF_COUNT);
+    mfma_tiles<P>(a, blockIdx.x, gridDim.x, smem, a.partials + (size_t)blockIdx.x * PF_COUNT);
 }
 
-// Batched: item (system, block tile of T x 16 atoms) for systems with this P.
+// Batched: one block per item (system, block tile of T x 16 atoms), for the
+// systems with this P; the grid is the item count.
 template <int P>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma_batch(const FusedArgs *table,
-                                                             const int2 *items, int n_items)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma_batch(
+    const FusedArgs *table, const int2 *items, int n_items)
 {
     extern __shared__ double smem[];
-    __shared__ double red[kBlock * 4];
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 item = items[it];
-        FusedArgs a = table[item.x];
-        a.mode = FUSED_STEP;
-        mfma_tiles<P>(a, item.y, 1 << 30, smem, red, a.partials + (size_t)item.y * PF_COUNT);
-    }
+    if ((int)blockIdx.x >= n_items) return;
+    const int2 item = items[blockIdx.x];
+    const FusedArgs &a = table[item.x];
+    mfma_tiles<P>(a, item.y, 1 << 30, smem, a.partials + (size_t)item.y * PF_COUNT);
 }
 
 namespace {
