@@ -24,9 +24,10 @@ constexpr int kGraphChunk = 32;   // steps per captured graph
 
 struct Layout {
     size_t x, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
-        partials, fpartials, ctl, total;
+        partials, fpartials, ctl, cell_atoms, cell_sorted, cell_scnt, cinfo, total;
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
     int valu_tiles, mfma_tiles;
+    int ncell, cell_cap, nc[3];   // centroid cells (ncell = 0: none)
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -151,26 +152,63 @@ std::vector<int> internal_order(const pimd_params *p, const pimd_topology *topo,
     return orig;
 }
 
+// Generous bound on the bead-centroid excursion of the lightest active atom:
+// three thermal wavelengths hbar / sqrt(m kB T mvv2e).  Zero when the caller
+// fixes the list capacity (the masses are then optional for sizing).
+double excursion_guess(const pimd_params *p, const double *mass, const std::vector<int> &orig,
+                       int n_active)
+{
+    if (p->nbr_capacity > 0 || n_active == 0 || p->n_beads < 2 || !mass) return 0.0;
+    double mmin = 1e300;
+    for (int q = 0; q < n_active; ++q) mmin = std::min(mmin, mass[orig[q]]);
+    const double lam = p->hbar / std::sqrt(mmin * p->kB * p->temp * p->mvv2e);
+    return 3.0 * lam;
+}
+
 int neighbor_capacity(const pimd_params *p, const double *mass, const std::vector<int> &orig,
                       int n_active)
 {
     if (p->nbr_capacity > 0) return p->nbr_capacity;
     if (n_active == 0) return 1;
-    // generous bound on the bead-centroid excursion of the lightest active
-    // atom: three thermal wavelengths hbar / sqrt(m kB T mvv2e)
-    double mmin = 1e300;
-    for (int q = 0; q < n_active; ++q) mmin = std::min(mmin, mass[orig[q]]);
-    const double lam = p->hbar / std::sqrt(mmin * p->kB * p->temp * p->mvv2e);
-    const double e_guess = (p->n_beads > 1) ? 3.0 * lam : 0.0;
+    const double e_guess = excursion_guess(p, mass, orig, n_active);
     const double r = p->lj_rc + p->skin + 2.0 * e_guess;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     const double nb = (double)n_active / vol * (4.0 / 3.0) * M_PI * r * r * r;
     return (int)std::ceil(1.4 * nb) + 32;
 }
 
-Layout make_layout(const pimd_params *p, int n_active, int cap)
+// Centroid cells of width >= the expected list cutoff rc + skin + 2 E, so that
+// a rebuild normally scans 3 x 3 x 3 cells; none when a dim holds fewer than
+// three cells (small boxes use the all-pairs scan with periodic images) or
+// when the grid would be much sparser than the atoms.
+void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
+{
+    L.ncell = 0;
+    L.cell_cap = 0;
+    L.nc[0] = L.nc[1] = L.nc[2] = 0;
+    if (!is_pair(p->potential) || n_active == 0) return;
+    const double w = p->lj_rc + p->skin + 2.0 * e_guess;
+    long long ncell = 1;
+    int nc[3];
+    for (int d = 0; d < 3; ++d) {
+        const double q = std::floor(p->box[d] / w);
+        if (!(q >= 3.0)) return;
+        nc[d] = (int)std::min(q, 1024.0);
+        ncell *= nc[d];
+    }
+    if (ncell > 8LL * n_active + 64) return;
+    const double mean = (double)n_active / (double)ncell;
+    const int cap = (int)std::ceil(2.0 * mean) + 16;
+    if (cap > kSortBuf || ncell > kMaxCells) return;
+    L.ncell = (int)ncell;
+    L.cell_cap = cap;
+    for (int d = 0; d < 3; ++d) L.nc[d] = nc[d];
+}
+
+Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
 {
     Layout L{};
+    cell_grid(p, n_active, e_guess, L);
     const size_t N = (size_t)p->n_atoms, P = (size_t)p->n_beads;
     const size_t arr = N * 3 * P * sizeof(double);
     const bool pair = is_pair(p->potential);
@@ -207,6 +245,10 @@ Layout make_layout(const pimd_params *p, int n_active, int cap)
     L.partials = take((size_t)nparts * PF_COUNT * sizeof(double));
     L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
     L.ctl = take(sizeof(Ctl));
+    L.cell_atoms = take((size_t)L.ncell * L.cell_cap * sizeof(int));
+    L.cell_sorted = take((size_t)L.ncell * L.cell_cap * sizeof(int));
+    L.cell_scnt = take((size_t)L.ncell * sizeof(int));
+    L.cinfo = take(L.ncell ? N * sizeof(int4) : 0);
     L.total = o;
     return L;
 }
@@ -343,7 +385,7 @@ int pimd_workspace_bytes(const pimd_params *p, const double *mass, const pimd_to
     int n_active = 0;
     std::vector<int> orig = internal_order(p, topo, &n_active);
     const int cap = is_pair(p->potential) ? neighbor_capacity(p, mass, orig, n_active) : 0;
-    *bytes = make_layout(p, n_active, cap).total;
+    *bytes = make_layout(p, n_active, cap, excursion_guess(p, mass, orig, n_active)).total;
     return PIMD_OK;
 }
 
@@ -366,7 +408,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     const int N = p->n_atoms, P = p->n_beads;
     const bool pair = is_pair(p->potential);
     const int cap = pair ? neighbor_capacity(p, mass, c->orig, n_active) : 0;
-    c->lay = make_layout(p, n_active, cap);
+    c->lay = make_layout(p, n_active, cap, excursion_guess(p, mass, c->orig, n_active));
     const Layout &L = c->lay;
 
     auto cleanup = [&](int code, const std::string &msg) {
@@ -460,6 +502,8 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     if (e == hipSuccess) e = hipMemset(c->d_cent, 0, (size_t)N * 3 * sizeof(double));
     if (e == hipSuccess && pair) e = hipMemset(c->d_nbr_count, 0, (size_t)N * sizeof(int));
     if (e == hipSuccess) e = hipMemset(c->d_ctl, 0, sizeof(Ctl));
+    if (e == hipSuccess && L.ncell)
+        e = hipMemset(w + L.cell_scnt, 0, (size_t)L.ncell * sizeof(int));
     if (e != hipSuccess) return cleanup(PIMD_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
 
     FusedArgs &a = c->fa;
@@ -482,6 +526,17 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.fpartials = c->d_fpartials;
     a.n_fpartials = L.pair_grid;
     a.ctl = c->d_ctl;
+    a.ncell = L.ncell;
+    a.cell_cap = L.cell_cap;
+    for (int d = 0; d < 3; ++d) {
+        a.nc[d] = L.nc[d];
+        a.box[d] = p->box[d];
+        a.icw[d] = L.ncell ? (double)L.nc[d] / p->box[d] : 0.0;
+    }
+    a.cell_atoms = L.ncell ? (int *)(w + L.cell_atoms) : nullptr;
+    a.cell_sorted = L.ncell ? (int *)(w + L.cell_sorted) : nullptr;
+    a.cell_scnt = L.ncell ? (int *)(w + L.cell_scnt) : nullptr;
+    a.cinfo = L.ncell ? (int4 *)(w + L.cinfo) : nullptr;
 
     PairArgs &q = c->pa;
     q.N = N; q.P = P; q.n_active = n_active; q.cap = L.cap;
@@ -501,6 +556,11 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     q.nbr_count = c->d_nbr_count; q.nbr = c->d_nbr; q.bond_j = c->d_bond_j;
     q.fpartials = c->d_fpartials;
     q.ctl = c->d_ctl;
+    for (int d = 0; d < 3; ++d) q.nc[d] = L.nc[d];
+    q.cell_cap = L.cell_cap;
+    q.cell_sorted = a.cell_sorted;
+    q.cell_scnt = a.cell_scnt;
+    q.cinfo = a.cinfo;
 
     *out = c;
     return PIMD_OK;

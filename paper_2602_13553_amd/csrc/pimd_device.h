@@ -10,6 +10,22 @@ namespace pimd {
 // --------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
 // --------------------------------------------------------------------------
+// 64 x 64 -> 128-bit product from four 32 x 32 + 64 multiply-adds
+// (v_mad_u64_u32), the carries folded into the addends:
+//   a*b = t + (u_lo + ah*bl) 2^32 + (u_hi + ah*bh) 2^64,  t = al*bl,
+//   u = al*bh + t_hi,  v = ah*bl + u_lo,  lo = v_lo:t_lo,  hi = ah*bh + u_hi + v_hi.
+__device__ __forceinline__ void mulhilo64(unsigned long long a, unsigned long long b,
+                                          unsigned long long &lo, unsigned long long &hi)
+{
+    const unsigned al = (unsigned)a, ah = (unsigned)(a >> 32);
+    const unsigned bl = (unsigned)b, bh = (unsigned)(b >> 32);
+    const unsigned long long t = (unsigned long long)al * bl;
+    const unsigned long long u = (unsigned long long)al * bh + (t >> 32);
+    const unsigned long long v = (unsigned long long)ah * bl + (unsigned)u;
+    lo = (v << 32) | (unsigned)t;
+    hi = (unsigned long long)ah * bh + ((u >> 32) + (v >> 32));
+}
+
 __device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0,
                                               unsigned long long k1)
 {
@@ -17,8 +33,9 @@ __device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned 
     const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const unsigned long long lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const unsigned long long lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        unsigned long long lo0, hi0, lo1, hi1;
+        mulhilo64(M0, c[0], lo0, hi0);
+        mulhilo64(M1, c[2], lo1, hi1);
         const unsigned long long n0 = hi1 ^ c[1] ^ k0;
         const unsigned long long n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
@@ -26,60 +43,196 @@ __device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned 
     }
 }
 
-__device__ __forceinline__ double u01(unsigned long long w)
+// The uniform of a word: n = (top 53 bits) + 1 in [1, 2^53], u = n 2^-53 on (0, 1].
+
+// -2 ln u for u = n 2^-53.  With n = 2^e m, m in [sqrt(1/2), sqrt(2)):
+// ln u = (e - 53) ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, and
+// atanh(s) = s (1 + s^2/3 + s^4/5 + ...) summed to s^22 (next term < 2^-60).
+__device__ __forceinline__ double neg2log_u(unsigned long long w)
 {
-    // top 53 bits + 1, times 2^-53: uniform on (0, 1], exact in FP64
-    return ((double)(w >> 11) + 1.0) * 1.1102230246251565404e-16;
+    const double n = (double)(w >> 11) + 1.0;                 // exact
+    int e = __builtin_amdgcn_frexp_exp(n);                     // n = 2^e * m0, m0 in [0.5, 1)
+    double m = __builtin_amdgcn_frexp_mant(n);
+    if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }      // m in [sqrt(1/2), sqrt(2))
+    const double num = m - 1.0, den = m + 1.0;
+    double r = __builtin_amdgcn_rcp(den);                      // two Newton steps
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    double s = num * r;
+    s = fma(fma(-den, s, num), r, s);                          // residual correction
+    const double s2 = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, s2, 1.0 / 21.0);
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double lnm = 2.0 * fma(s * s2, p, s);
+    // ln 2 = LN2_HI + LN2_LO, LN2_HI = ln 2 truncated to 40 fraction bits (so
+    // that k LN2_HI is exact for |k| < 2^12)
+    const double LN2_HI = 0x1.62e42fefa2p-1, LN2_LO = 0x1.9ef35793c7673p-41;
+    const double k = (double)(e - 53);
+    const double lnu = fma(k, LN2_HI, fma(k, LN2_LO, lnm));
+    return -2.0 * lnu;
+}
+
+// sin and cos of 2 pi u for u = n 2^-53.  The octant q = floor(8u) and the
+// offset inside it come exactly from the integer n; the angle t in [0, pi/4]
+// (measured from the nearer octant edge) goes through Taylor series to t^19
+// and t^20 (truncation < 2^-64), then q maps (sin t, cos t) back.
+__device__ __forceinline__ void sincos_2pi_u(unsigned long long w, double &sn, double &cs)
+{
+    const unsigned long long n = (w >> 11) + 1ULL;              // [1, 2^53]
+    const unsigned q = (unsigned)(n >> 50);                     // 0..8
+    const unsigned long long rem = n & ((1ULL << 50) - 1ULL);
+    const bool odd = (q & 1u) != 0u;
+    const unsigned long long tq = odd ? (1ULL << 50) - rem : rem;
+    const double t = (double)tq * (0.78539816339744830962 * 8.8817841970012523234e-16);
+    const double t2 = t * t;
+    double ps = -1.0 / 121645100408832000.0;                   // -1/19!
+    ps = fma(ps, t2, 1.0 / 355687428096000.0);
+    ps = fma(ps, t2, -1.0 / 1307674368000.0);
+    ps = fma(ps, t2, 1.0 / 6227020800.0);
+    ps = fma(ps, t2, -1.0 / 39916800.0);
+    ps = fma(ps, t2, 1.0 / 362880.0);
+    ps = fma(ps, t2, -1.0 / 5040.0);
+    ps = fma(ps, t2, 1.0 / 120.0);
+    ps = fma(ps, t2, -1.0 / 6.0);
+    const double S = fma(t * t2, ps, t);
+    double pc = 1.0 / 2432902008176640000.0;                    // 1/20!
+    pc = fma(pc, t2, -1.0 / 6402373705728000.0);
+    pc = fma(pc, t2, 1.0 / 20922789888000.0);
+    pc = fma(pc, t2, -1.0 / 87178291200.0);
+    pc = fma(pc, t2, 1.0 / 479001600.0);
+    pc = fma(pc, t2, -1.0 / 3628800.0);
+    pc = fma(pc, t2, 1.0 / 40320.0);
+    pc = fma(pc, t2, -1.0 / 720.0);
+    pc = fma(pc, t2, 1.0 / 24.0);
+    pc = fma(pc, t2, -0.5);
+    const double C = fma(t2, pc, 1.0);
+    // angle = p pi/2 + (odd ? pi/2 - t : t), p = (q >> 1) & 3
+    const double bs = odd ? C : S, bc = odd ? S : C;
+    const unsigned p = (q >> 1) & 3u;
+    sn = (p == 0u) ? bs : (p == 1u) ? bc : (p == 2u) ? -bs : -bc;
+    cs = (p == 0u) ? bc : (p == 1u) ? -bs : (p == 2u) ? -bc : bs;
 }
 
 // Three N(0,1) deviates for atom i, mode k, step s: counter (i, k, s, 0),
-// key (seed, 0); (z0, z1) from (u0, u1), z2 from (u2, u3).
+// key (seed, 0); Box-Muller (z0, z1) from (u0, u1), z2 from (u2, u3).
 __device__ __forceinline__ void gauss3(unsigned long long seed, unsigned long long i,
                                        unsigned long long k, unsigned long long s, double z[3])
 {
     unsigned long long c[4] = {i, k, s, 0ULL};
     philox4x64_10(c, seed, 0ULL);
-    const double r0 = sqrt(-2.0 * log(u01(c[0])));
-    const double r2 = sqrt(-2.0 * log(u01(c[2])));
-    double s1, c1;
-    sincospi(2.0 * u01(c[1]), &s1, &c1);
+    const double r0 = sqrt(neg2log_u(c[0]));
+    const double r2 = sqrt(neg2log_u(c[2]));
+    double s1, c1, s3, c3;
+    sincos_2pi_u(c[1], s1, c1);
+    sincos_2pi_u(c[3], s3, c3);
     z[0] = r0 * c1;
     z[1] = r0 * s1;
-    z[2] = r2 * cospi(2.0 * u01(c[3]));
+    z[2] = r2 * c3;
 }
 
 // --------------------------------------------------------------------------
 // Block reductions (fixed order).
 // --------------------------------------------------------------------------
+// Wave butterflies, then the kBlock/64 wave results in index order: the
+// same order on every call, two barriers per reduction.
 template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double *red /* [kBlock*NV] */)
+__device__ inline void block_sum(double (&v)[NV], double *red /* >= NV * kBlock/64 */)
 {
-    const int t = threadIdx.x;
+    constexpr int NW = kBlock / 64;
+    const int t = threadIdx.x, w = t >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) red[q * kBlock + t] = v[q];
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (t < w) {
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) red[q * kBlock + t] += red[q * kBlock + t + w];
-        }
-        __syncthreads();
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        v[q] = x;
     }
+    if ((t & 63) == 0) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = red[q * kBlock];
+        for (int q = 0; q < NV; ++q) red[q * NW + w] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = red[q * NW];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) x += red[q * NW + u];
+        v[q] = x;
+    }
+    __syncthreads();
+}
+
+// Cell of an active atom's centroid c in the periodic cell grid, stored in
+// cinfo with the integer box index of the unwrapped centroid (the list build
+// forms image shifts from integers alone).  A plain store per atom: the cell
+// lists themselves are built by k_finalize, and only at a rebuild.
+// Non-finite centroids land in a clamped (valid) cell; the non-finite flag of
+// the step catches them.
+__device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
+{
+    int cc[3], nb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double L = a.box[d];
+        const double fl = floor(c[d] / L);
+        const double w = c[d] - L * fl;
+        int q = (w >= 0.0 && w < L) ? (int)(w * a.icw[d]) : 0;
+        q = q < 0 ? 0 : (q >= a.nc[d] ? a.nc[d] - 1 : q);
+        cc[d] = q;
+        nb[d] = (fl > -1e6 && fl < 1e6) ? (int)fl : 0;
+    }
+    const int cell = (cc[2] * a.nc[1] + cc[1]) * a.nc[0] + cc[0];
+    a.cinfo[ia] = make_int4(cell, nb[0], nb[1], nb[2]);
+    return cell;
+}
+
+template <int NV>
+__device__ inline void block_maxv(double (&v)[NV], double *red /* >= NV * kBlock/64 */)
+{
+    constexpr int NW = kBlock / 64;
+    const int t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+        v[q] = x;
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q * NW + w] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = red[q * NW];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) x = fmax(x, red[q * NW + u]);
+        v[q] = x;
+    }
     __syncthreads();
 }
 
 __device__ inline double block_max(double v, double *red)
 {
-    const int t = threadIdx.x;
-    red[t] = v;
+    constexpr int NW = kBlock / 64;
+    const int t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((t & 63) == 0) red[w] = v;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] = fmax(red[t], red[t + w]);
-        __syncthreads();
-    }
     v = red[0];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v = fmax(v, red[u]);
     __syncthreads();
     return v;
 }

@@ -266,16 +266,17 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 sY[(d * 16 + ra) * PS + m] = xt[d];
             }
             if (m == 0) {
-                double d2 = 0.0;
+                double d2 = 0.0, c[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double c = x0[d] + xt[d] / sqrtP;
-                    sC[ra * 4 + d] = c;
-                    a.cent[ia * 3 + d] = c;
-                    const double dd = c - ar[TA_CREF + d];
+                    c[d] = x0[d] + xt[d] / sqrtP;
+                    sC[ra * 4 + d] = c[d];
+                    a.cent[ia * 3 + d] = c[d];
+                    const double dd = c[d] - ar[TA_CREF + d];
                     d2 += dd * dd;
                 }
                 if (ar[TA_ACT] != 0.0) acc_dmax = fmax(acc_dmax, d2);
+                if (a.ncell > 0 && ia < a.n_active) (void)cell_of(a, ia, c);
             }
         }
         __syncthreads();   // the tile's y~ (all modes) and centroids are in LDS

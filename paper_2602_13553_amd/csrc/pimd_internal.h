@@ -19,6 +19,8 @@ constexpr int kBlock = 256;      // threads per block for the step kernels
 constexpr int kMaxBeads = 128;   // P limit of this build (LDS-resident M)
 constexpr int kMaxBonds = 4;     // bonds per atom
 constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
+constexpr int kSortBuf = 4096;   // ints of LDS for sorting the centroid cells
+constexpr int kMaxCells = 4096;  // centroid cells per system, at most (LDS histogram)
 
 // Per-block partial slots written by the fused kernel.
 enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_PAD, PF_COUNT };
@@ -50,6 +52,8 @@ struct Ctl {
     unsigned long long count;
     double sum[kNumEst];
     double sumsq[kNumEst];
+    int cell_ok;               // 1: the coming rebuild may use the sorted cells
+    int cell_R[3];             // stencil half-width in cells per dim for that rebuild
 };
 
 struct FusedArgs {
@@ -80,6 +84,15 @@ struct FusedArgs {
     const double *fpartials;  // [n_fpartials] force-kernel energy partials
     int n_fpartials;
     Ctl *ctl;
+    // centroid cells (ncell = 0: no cell list, lists come from the all-pairs scan)
+    int ncell, cell_cap;
+    int nc[3];                // cells per dim, each >= 3
+    double box[3];
+    double icw[3];            // cells per unit length
+    int *cell_atoms;          // [ncell][cell_cap] a rebuild's cell lists, placement order
+    int *cell_sorted;         // [ncell][cell_cap] the same, increasing index
+    int *cell_scnt;           // [ncell] atoms per cell
+    int4 *cinfo;              // [N] (cell, image index per dim) of each active atom's centroid
 };
 
 // modes[k*8 + ...]
@@ -104,6 +117,10 @@ struct PairArgs {
     const int *bond_j;        // [N][kMaxBonds] partner or -1
     double *fpartials;        // [gridDim]
     Ctl *ctl;
+    int nc[3], cell_cap;      // centroid cells (see FusedArgs)
+    const int *cell_sorted;
+    const int *cell_scnt;
+    const int4 *cinfo;
 };
 
 // Launchers (pimd_kernels.hip).

@@ -254,15 +254,16 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 }
                 if (active != 0.0) acc_emax = fmax(acc_emax, e2);
                 if (j == 0) {
-                    double d2 = 0.0;
+                    double d2 = 0.0, c[3];
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        const double c = sC[la * 3 + d];
-                        a.cent[i * 3 + d] = c;
-                        const double dd = c - a.cref[i * 3 + d];
+                        c[d] = sC[la * 3 + d];
+                        a.cent[i * 3 + d] = c[d];
+                        const double dd = c[d] - a.cref[i * 3 + d];
                         d2 += dd * dd;
                     }
                     if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
+                    if (a.ncell > 0 && i < a.n_active) (void)cell_of(a, i, c);
                 }
             }
         }
@@ -292,7 +293,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
 __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
 {
     extern __shared__ double smem[];
-    __shared__ double red[kBlock * 4];
+    __shared__ double red[64];
     fused_tiles(a, blockIdx.x, gridDim.x, smem, red, a.partials + (size_t)blockIdx.x * PF_COUNT,
                 true);
 }
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *table, 
                                                         int n_items, int mode)
 {
     extern __shared__ double smem[];
-    __shared__ double red[kBlock * 4];
+    __shared__ double red[64];
     int prev = -1;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
@@ -322,7 +323,112 @@ __global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *table, 
 // running sums, advances the step counter and decides the neighbor-list
 // rebuild for the coming force pass.
 // --------------------------------------------------------------------------
-__device__ void finalize_system(const FusedArgs &a, int nblocks, double *red)
+// At a rebuild, builds the centroid cell lists from the cells recorded by
+// the step pass: an LDS histogram, placement through LDS cursors, then a rank
+// sort of each cell (staged in LDS) so that its atoms are in increasing index
+// order, whatever the order of the placement; the list build then sees its
+// candidates in a fixed order.  Decides whether the cells can serve this
+// rebuild: no cell over capacity, and a stencil of 2R+1 cells per dim that
+// does not wrap onto itself.  One block; no global atomics.
+__device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int *shist, int *sflag)
+{
+    const int t = threadIdx.x;
+    const int ncell = a.ncell, cap = a.cell_cap, na = a.n_active;
+    Ctl *c = a.ctl;
+    for (int q = t; q < ncell; q += kBlock) shist[q] = 0;
+    if (t == 0) sflag[0] = 0;
+    __syncthreads();
+    // eight cell reads in flight per thread, then their LDS increments
+    constexpr int U = 8;
+    for (int i0 = t; i0 < na; i0 += U * kBlock) {
+        int cl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kBlock;
+            cl[u] = i < na ? a.cinfo[i].x : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (cl[u] >= 0) atomicAdd(&shist[cl[u]], 1);
+    }
+    __syncthreads();
+    for (int q = t; q < ncell; q += kBlock)
+        if (shist[q] > cap) sflag[0] = 1;
+    __syncthreads();
+    bool ok = sflag[0] == 0 && cap <= kSortBuf;
+    int R[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double rr = rlist * a.icw[d];
+        if (rr > 0.0 && rr <= 0.5 * (double)(a.nc[d] - 1))
+            R[d] = (int)ceil(rr);
+        else
+            ok = false;
+        if (2 * R[d] + 1 > a.nc[d]) ok = false;
+    }
+    if (ok) {
+        // placement in arrival order (the cursors end equal to the counts)
+        for (int q = t; q < ncell; q += kBlock) {
+            a.cell_scnt[q] = shist[q];
+            shist[q] = 0;
+        }
+        __syncthreads();
+        for (int i0 = t; i0 < na; i0 += U * kBlock) {
+            int cl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kBlock;
+                cl[u] = i < na ? a.cinfo[i].x : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (cl[u] >= 0) {
+                    const int slot = atomicAdd(&shist[cl[u]], 1);
+                    a.cell_atoms[(size_t)cl[u] * cap + slot] = i0 + u * kBlock;
+                }
+        }
+        __threadfence_block();
+        __syncthreads();
+        // index order inside each cell
+        const int cb = kSortBuf / cap;            // cells per LDS batch
+        for (int c0 = 0; c0 < ncell; c0 += cb) {
+            const int nb = min(cb, ncell - c0);
+            const int ne = nb * cap;
+            for (int e0 = t; e0 < ne; e0 += U * kBlock) {
+                int v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * kBlock;
+                    v[u] = e < ne ? a.cell_atoms[(size_t)c0 * cap + e] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (e0 + u * kBlock < ne) sbuf[e0 + u * kBlock] = v[u];
+            }
+            __syncthreads();
+            for (int e = t; e < nb * cap; e += kBlock) {
+                const int cl = e / cap, sl = e - cl * cap;
+                const int n = shist[c0 + cl];
+                if (sl < n) {
+                    const int v = sbuf[e];
+                    const int *row = sbuf + cl * cap;
+                    int rank = 0;
+                    for (int q = 0; q < n; ++q) rank += row[q] < v ? 1 : 0;
+                    a.cell_sorted[(size_t)(c0 + cl) * cap + rank] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        c->cell_ok = ok ? 1 : 0;
+        c->cell_R[0] = R[0];
+        c->cell_R[1] = R[1];
+        c->cell_R[2] = R[2];
+    }
+}
+
+__device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, int *sbuf, int *sflag)
 {
     const int t = threadIdx.x;
     const int P = a.P;
@@ -340,30 +446,42 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red)
     const bool est_now = closing || mode == FUSED_EST;
     const bool est_after = (mode == FUSED_STEP) && ext;
 
-    double tot[4] = {0.0, 0.0, 0.0, 0.0};
-    double emax = 0.0, dmax = 0.0, bad = 0.0, upair = 0.0;
+    // thread 0's read-modify-write state, fetched now so that its latency
+    // overlaps the partial reductions
+    double run_sum[kNumEst], run_sq[kNumEst];
+    unsigned long long run_count = 0;
+    double ebuild = 0.0;
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < kNumEst; ++q) {
+            run_sum[q] = c->sum[q];
+            run_sq[q] = c->sumsq[q];
+        }
+        run_count = c->count;
+        ebuild = c->ebuild;
+    }
+
+    double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double mx[3] = {0.0, 0.0, 0.0};   // emax^2, dmax^2, non-finite flag
+#pragma unroll 2
     for (int b = t; b < nblocks; b += kBlock) {
         const double *pp = a.partials + (size_t)b * PF_COUNT;
         tot[0] += pp[PF_EKIN];
         tot[1] += pp[PF_ESPRING];
         tot[2] += pp[PF_VIR];
         tot[3] += pp[PF_UEXT];
-        emax = fmax(emax, pp[PF_EMAX]);
-        dmax = fmax(dmax, pp[PF_DMAX]);
-        bad = fmax(bad, pp[PF_NONFINITE]);
+        mx[0] = fmax(mx[0], pp[PF_EMAX]);
+        mx[1] = fmax(mx[1], pp[PF_DMAX]);
+        mx[2] = fmax(mx[2], pp[PF_NONFINITE]);
     }
     if (a.pair && est_now) {
-        for (int b = t; b < a.n_fpartials; b += kBlock) upair += a.fpartials[b];
+#pragma unroll 4
+        for (int b = t; b < a.n_fpartials; b += kBlock) tot[4] += a.fpartials[b];
     }
-    block_sum<4>(tot, red);
-    {
-        double u1[1] = {upair};
-        block_sum<1>(u1, red);
-        upair = u1[0];
-    }
-    emax = sqrt(block_max(emax, red));
-    dmax = sqrt(block_max(dmax, red));
-    bad = block_max(bad, red);
+    block_sum<5>(tot, red);
+    block_maxv<3>(mx, red);
+    const double upair = tot[4];
+    const double emax = sqrt(mx[0]), dmax = sqrt(mx[1]), bad = mx[2];
 
     if (t == 0) {
         if (est_now || est_after) {
@@ -380,10 +498,10 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red)
             for (int q = 0; q < kNumEst; ++q) c->value[q] = v[q];
             c->est_step = est_after ? step + 1 : step;
             if (mode != FUSED_EST) {
-                c->count += 1;
+                c->count = run_count + 1;
                 for (int q = 0; q < kNumEst; ++q) {
-                    c->sum[q] += v[q];
-                    c->sumsq[q] += v[q] * v[q];
+                    c->sum[q] = run_sum[q] + v[q];
+                    c->sumsq[q] = run_sq[q] + v[q] * v[q];
                 }
             }
         }
@@ -401,7 +519,7 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red)
             c->rlist = a.rc + a.skin + 2.0 * emax;
             c->n_rebuilds += 1;
         } else if (a.pair && mode == FUSED_STEP) {
-            if (dmax + emax > 0.5 * a.skin + c->ebuild) {
+            if (dmax + emax > 0.5 * a.skin + ebuild) {
                 c->rebuild = 1;
                 c->ebuild = emax;
                 c->rlist = a.rc + a.skin + 2.0 * emax;
@@ -412,23 +530,39 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red)
         }
         if (bad != 0.0) c->nonfinite = 1;
     }
+    // the centroid cell lists of a rebuild (cells recorded by this pass)
+    if (a.pair && a.ncell > 0 && (mode == FUSED_STEP || mode == FUSED_PREP)) {
+        if (t == 0) {
+            red[0] = c->rebuild ? 1.0 : 0.0;
+            red[1] = c->rlist;
+        }
+        __syncthreads();
+        const bool rb = red[0] != 0.0;
+        const double rl = red[1];
+        __syncthreads();
+        if (rb) cells_finalize(a, rl, sbuf, sbuf + kSortBuf, sflag);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
 {
-    __shared__ double red[kBlock * 4];
-    finalize_system(a, nblocks, red);
+    __shared__ double red[64];
+    __shared__ int sbuf[kSortBuf + kMaxCells];
+    __shared__ int sflag[1];
+    finalize_system(a, nblocks, red, sbuf, sflag);
 }
 
 // Batched: block s finalizes system s from its per-tile partials.
 __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FusedArgs *table,
                                                            const int *nparts, int n_sys, int mode)
 {
-    __shared__ double red[kBlock * 4];
+    __shared__ double red[64];
+    __shared__ int sbuf[kSortBuf + kMaxCells];
+    __shared__ int sflag[1];
     for (int sidx = blockIdx.x; sidx < n_sys; sidx += gridDim.x) {
         FusedArgs a = table[sidx];
         a.mode = mode;
-        if (nparts[sidx] > 0) finalize_system(a, nparts[sidx], red);
+        if (nparts[sidx] > 0) finalize_system(a, nparts[sidx], red, sbuf, sflag);
         __syncthreads();
     }
 }
@@ -535,7 +669,85 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     if (a.ctl->rebuild && !rl_ok) {
         if (tile == 0 && t == 0) a.ctl->nonfinite = 1;
     }
-    if (a.ctl->rebuild && rl_ok) {
+    // Lists from the sorted centroid cells: the first min(G, 64) lanes of each
+    // atom's group (they lie in one wave) scan the 2R+1 cells per dim around
+    // the atom's cell, cells and their atoms in a fixed order; wave ballots
+    // place the hits.  Image shifts come from the integer box indices kept at
+    // binning and the wrap of the stencil cell.
+    const bool wave_aligned = (G % 64 == 0) || (64 % G == 0);
+    const bool use_cells = a.ctl->rebuild && rl_ok && a.ctl->cell_ok && wave_aligned;
+    if (use_cells) {
+        const double rl2 = rl_in * rl_in;
+        const int Gb = G < 64 ? G : 64;
+        const int lane = t & 63;
+        const int gbase = lane - g;
+        const unsigned long long gmask = (Gb == 64) ? ~0ull : (((1ull << Gb) - 1ull) << gbase);
+        const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        int total = 0;
+        const bool builder = act && i < a.n_active && g < Gb;
+        if (builder) {
+            const int4 ii = a.cinfo[i];
+            const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+            const int cx = ii.x % nx, cy = (ii.x / nx) % ny, cz = ii.x / (nx * ny);
+            const int R0 = a.ctl->cell_R[0], R1 = a.ctl->cell_R[1], R2 = a.ctl->cell_R[2];
+            const double ci0 = a.cent[i * 3], ci1 = a.cent[i * 3 + 1], ci2 = a.cent[i * 3 + 2];
+            int2 *mylist = a.nbr + (size_t)i * a.cap;
+            for (int oz = -R2; oz <= R2; ++oz) {
+                int qz = cz + oz, kz = 0;
+                if (qz < 0) { qz += nz; kz = -1; } else if (qz >= nz) { qz -= nz; kz = 1; }
+                for (int oy = -R1; oy <= R1; ++oy) {
+                    int qy = cy + oy, ky = 0;
+                    if (qy < 0) { qy += ny; ky = -1; } else if (qy >= ny) { qy -= ny; ky = 1; }
+                    for (int ox = -R0; ox <= R0; ++ox) {
+                        int qx = cx + ox, kx = 0;
+                        if (qx < 0) { qx += nx; kx = -1; } else if (qx >= nx) { qx -= nx; kx = 1; }
+                        const int cell = (qz * ny + qy) * nx + qx;
+                        const int n = a.cell_scnt[cell];
+                        const int *cl = a.cell_sorted + (size_t)cell * a.cell_cap;
+                        for (int q0 = 0; q0 < n; q0 += Gb) {
+                            const int q = q0 + g;
+                            bool pass = false;
+                            int j = 0, sx = 0, sy = 0, sz = 0;
+                            if (q < n) {
+                                j = cl[q];
+                                const int4 jj = a.cinfo[j];
+                                sx = jj.y - ii.y - kx;
+                                sy = jj.z - ii.z - ky;
+                                sz = jj.w - ii.w - kz;
+                                const double ex = ci0 - a.cent[j * 3] + sx * L0;
+                                const double ey = ci1 - a.cent[j * 3 + 1] + sy * L1;
+                                const double ez = ci2 - a.cent[j * 3 + 2] + sz * L2;
+                                pass = (j != i) && (ex * ex + ey * ey + ez * ez < rl2);
+                            }
+                            const unsigned long long hit = __ballot(pass) & gmask;
+                            if (pass) {
+                                const int w = total + __popcll(hit & below);
+                                if (w < a.cap) mylist[w] = make_int2(j, pack_shift(sx, sy, sz));
+                            }
+                            total += __popcll(hit);
+                        }
+                    }
+                }
+            }
+        }
+        if (act && g == 0) {
+            if (i < a.n_active) {
+                if (total > a.cap) {
+                    a.ctl->overflow = 1;
+                    total = a.cap;
+                }
+                a.nbr_count[i] = total;
+            } else {
+                a.nbr_count[i] = 0;
+            }
+            a.cref[i * 3] = a.cent[i * 3];
+            a.cref[i * 3 + 1] = a.cent[i * 3 + 1];
+            a.cref[i * 3 + 2] = a.cent[i * 3 + 2];
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    if (a.ctl->rebuild && rl_ok && !use_cells) {
         const double rl = rl_in;
         const double rl2 = rl * rl;
         const bool big = (L0 >= 2.0 * rl) && (L1 >= 2.0 * rl) && (L2 >= 2.0 * rl);
@@ -686,20 +898,15 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
     }
     // block sum (fixed order)
-    red[t] = e;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    if (t == 0) a.fpartials[tile] = red[0];
-    __syncthreads();
+    double e1[1] = {e};
+    block_sum<1>(e1, red);
+    if (t == 0) a.fpartials[tile] = e1[0];
 }
 
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
 {
     __shared__ int s_cnt[kBlock];
-    __shared__ double red[kBlock];
+    __shared__ double red[64];
     __shared__ double s_f[kBlock * 3];
     // Tiles holding LJ-active atoms come first.  Each of the two tile ranges
     // is laid out contiguously per XCD, so both are spread over all XCDs.
@@ -713,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *table, co
                                                        int n_items)
 {
     __shared__ int s_cnt[kBlock];
-    __shared__ double red[kBlock];
+    __shared__ double red[64];
     __shared__ double s_f[kBlock * 3];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
@@ -858,6 +1065,7 @@ __global__ void k_ctl_init(Ctl *c, unsigned long long step)
         c->n_rebuilds = 0;
         c->budget = -1;
         c->ran = 1;
+        c->cell_ok = 0;
         c->est_step = step;
         c->count = 0;
         for (int q = 0; q < kNumEst; ++q) {

@@ -92,8 +92,17 @@ def workspace_bytes(spec) -> int:
 
 
 def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32,
-          keep_states: bool = False, realtime: bool = True) -> ServeReport:
-    """Replay ``trace`` (jobs with arrival times in seconds) through one batch."""
+          keep_states: bool = False, realtime: bool = True,
+          max_active_bead_atoms: float = 4e6) -> ServeReport:
+    """Replay ``trace`` (jobs with arrival times in seconds) through one batch.
+
+    Admission is first-come first-served under three limits: the slot count,
+    the HBM budget (``pimd_workspace_bytes`` of the running jobs) and the
+    bead*atoms stepped together.  The last one stops admitting once the GPU
+    is saturated: beyond it, another job only slows every running job down
+    (shared throughput) instead of raising the aggregate rate, so waiting
+    jobs start later but every job finishes sooner.  A job is always admitted
+    when nothing runs."""
     batch = pimd.Batch()
     pre = _Prefetch(sorted(trace, key=lambda j: j.arrival))
     report = ServeReport()
@@ -102,6 +111,7 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
     exhausted = False
     running = {}                           # sid -> (job, bytes, admitted time)
     used = 0.0
+    active_ba = 0
     t0 = time.perf_counter()
 
     def now():
@@ -124,7 +134,8 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
         while waiting and len(running) < max_active:
             job, spec = waiting[0]
             nbytes = workspace_bytes(spec)
-            if used + nbytes > hbm_budget and running:
+            ba = job.n_atoms * job.n_beads
+            if running and (used + nbytes > hbm_budget or active_ba + ba > max_active_bead_atoms):
                 break
             waiting.popleft()
             sid = batch.add(spec)
@@ -132,6 +143,7 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
             batch.set_budget(sid, job.nsteps)
             running[sid] = (job, nbytes, now())
             used += nbytes
+            active_ba += ba
         report.max_active = max(report.max_active, len(running))
         if not running:
             if exhausted and not waiting:
@@ -156,6 +168,7 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
                 r.x, r.p, r.step = batch.get_state(sid)
             batch.remove(sid)
             used -= nbytes
+            active_ba -= job.n_atoms * job.n_beads
             report.results.append(r)
     report.wall = now()
     batch.close()
