@@ -82,9 +82,29 @@ typedef struct pimd_params {
     int32_t flags;        /* PIMD_FLAG_* (0 = defaults) */
 } pimd_params;
 
-/* flags: force the FP64 vector-ALU transforms instead of the FP64 matrix-core
- * (MFMA) ones that the step pass uses for P = 16, 32 and 64 */
+/* flags.  By default the launch shapes come from the library's tuning table
+ * (measured on MI355X by paper_2602_13553_amd/autotune.py): the step pass
+ * runs its normal-mode transforms on the FP64 matrix cores (MFMA) for
+ * P = 16, 32, 64 once N*P reaches the tuned size for that P, and on the FP64
+ * vector ALUs otherwise; the force pass shares each atom's list among the
+ * tuned number of lane sub-groups.  The flags override the table:
+ *   PIMD_FLAG_VALU_TRANSFORMS   vector-ALU transforms at every size
+ *   PIMD_FLAG_MFMA_TRANSFORMS   matrix-core transforms wherever P allows
+ *                               (with both set, VALU wins)
+ *   PIMD_PAIR_SUBGROUPS(S)      S = 1, 2, 4, 8 or 16 sub-groups of P lanes
+ *                               per atom in the force pass (S*P <= 256)
+ * Results do not depend on the launch shape beyond the rounding of the
+ * transforms (MFMA and VALU sum in different orders). */
 #define PIMD_FLAG_VALU_TRANSFORMS 1
+#define PIMD_FLAG_MFMA_TRANSFORMS 2
+#define PIMD_PAIR_SUBGROUPS_SHIFT 8
+#define PIMD_PAIR_SUBGROUPS_MASK (0xF << PIMD_PAIR_SUBGROUPS_SHIFT)
+#define PIMD_PAIR_SUBGROUPS(S)                                                   \
+    ((S) == 1 ? 1 << PIMD_PAIR_SUBGROUPS_SHIFT                                   \
+     : (S) == 2 ? 2 << PIMD_PAIR_SUBGROUPS_SHIFT                                 \
+     : (S) == 4 ? 3 << PIMD_PAIR_SUBGROUPS_SHIFT                                 \
+     : (S) == 8 ? 4 << PIMD_PAIR_SUBGROUPS_SHIFT                                 \
+     : (S) == 16 ? 5 << PIMD_PAIR_SUBGROUPS_SHIFT : 0)
 
 typedef struct pimd_topology {
     const int32_t *lj_active; /* [N] 1 = takes part in LJ; NULL = every atom */

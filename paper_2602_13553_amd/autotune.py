@@ -1,0 +1,170 @@
+"""Autotuner for libpimd.so's launch shapes, run on the GPU the library targets.
+
+It sweeps LJ quantum liquids with the batched workload's physics: reduced
+density 0.8, kT 0.7, hbar 0.1, rc 2.5, dt 0.002, tau 0.5. The grid is
+P in {8, 16, 32, 64} and N = 64, 128, ..., 32768. For each system it times
+the following, with HIP events on the library's stream over the same steps:
+
+* the step pass with matrix-core (MFMA) and with vector-ALU transforms
+  (P = 16, 32, 64 only);
+* the force pass with S = 1, 2, 4, 8, 16 lane sub-groups per atom (S*P <= 256).
+
+From the timings it picks two things:
+
+* per P, the smallest N*P from which the matrix cores are at least as fast
+  at every larger size of the sweep;
+* per (P, N), the fastest S.
+
+With --write it rewrites csrc/pimd_tuning.h. The library compiles that table
+in, so a given system always gets the same launch shapes. Runs are then
+reproducible, and a system in a batch matches its solo run bit for bit.
+Rebuild the library (``__graft_entry__.build()``) after writing.
+
+    python -m paper_2602_13553_amd.autotune [--write] [--steps 40] [--json out.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import inputs, pimd
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HEADER = os.path.join(HERE, "csrc", "pimd_tuning.h")
+
+BEADS = (8, 16, 32, 64)
+ATOMS = tuple(2 ** k for k in range(6, 16))          # 64 ... 32768
+SUBGROUPS = (1, 2, 4, 8, 16)
+MFMA_BEADS = (16, 32, 64)
+
+
+def time_kernels(spec, flags: int, steps: int, warmup: int) -> dict:
+    """Average per-launch time (ms) of each kernel kind over `steps` steps."""
+    ctx = pimd.Context.from_spec(spec, flags=flags)
+    try:
+        ctx.set_state(spec.x0, spec.v0, 0)
+        ctx.step(warmup)
+        ctx.profile_begin()
+        ctx.step(steps)
+        prof = ctx.profile_end()
+    finally:
+        ctx.close()
+    return {k: (ms / n if n else 0.0) for k, (n, ms) in prof.items()}
+
+
+def sweep(steps: int = 40, warmup: int = 10, log=print) -> dict:
+    rows = []
+    for P in BEADS:
+        for N in ATOMS:
+            spec = inputs.lj_liquid(n_atoms=N, n_beads=P)
+            rec = {"P": P, "N": N}
+            if P in MFMA_BEADS:
+                for tag, fl in (("mfma", pimd.PIMD_FLAG_MFMA_TRANSFORMS),
+                                ("valu", pimd.PIMD_FLAG_VALU_TRANSFORMS)):
+                    rec["fused_" + tag] = time_kernels(spec, fl, steps, warmup)["fused"]
+            for S in SUBGROUPS:
+                if S * P > 256:
+                    continue
+                rec["pair_S%d" % S] = time_kernels(spec, pimd.PIMD_PAIR_SUBGROUPS(S),
+                                                   steps, warmup)["pair"]
+            rows.append(rec)
+            log(json.dumps(rec))
+    return {"device": _device_name(), "steps": steps, "warmup": warmup, "rows": rows}
+
+
+def _device_name() -> str:
+    try:
+        import torch
+        pr = torch.cuda.get_device_properties(0)
+        return "%s (%s)" % (pr.name, getattr(pr, "gcnArchName", "?"))
+    except Exception:       # the table still records where it came from
+        return "unknown"
+
+
+def choose(result: dict) -> tuple[list, list]:
+    rows = result["rows"]
+    mfma_min = []
+    for P in MFMA_BEADS:
+        r = sorted((x for x in rows if x["P"] == P), key=lambda x: x["N"])
+        thr = None
+        # the smallest size from which MFMA is never slower (2% grace)
+        for i in range(len(r)):
+            if all(x["fused_mfma"] <= 1.02 * x["fused_valu"] for x in r[i:]):
+                thr = r[i]["N"] * P
+                break
+        mfma_min.append(thr if thr is not None else 1 << 62)
+    table = []
+    for P in BEADS:
+        line = []
+        for N in ATOMS:
+            x = next(x for x in rows if x["P"] == P and x["N"] == N)
+            cand = {S: x["pair_S%d" % S] for S in SUBGROUPS if "pair_S%d" % S in x}
+            line.append(min(cand, key=cand.get))
+        table.append(line)
+    return mfma_min, table
+
+
+def header_text(result: dict, mfma_min: list, table: list) -> str:
+    stamp = time.strftime("%Y-%m-%d")
+    rows = ",\n".join("    {" + ", ".join(str(v) for v in line) + "}" for line in table)
+    return (
+        "// Launch-shape table of libpimd.so.  Written by paper_2602_13553_amd/autotune.py\n"
+        "// from kernel timings on the GPU; regenerate with\n"
+        "//   python -m paper_2602_13553_amd.autotune --write\n"
+        "// (the sweep, its workloads and the raw timings are described there).\n"
+        "// Measured on %s, %s, %d timed steps per point.\n"
+        "#pragma once\n\n"
+        "namespace pimd {\n"
+        "namespace tuning {\n\n"
+        "// Smallest N*P from which the matrix-core step pass is faster than the\n"
+        "// vector-ALU one, for P = 16, 32, 64.\n"
+        "constexpr long long kMfmaMinBeadAtoms[3] = {%s};\n\n"
+        "// Force-pass lane sub-groups per atom for P = 8, 16, 32, 64 (rows) and N in\n"
+        "// [2^6, 2^7), [2^7, 2^8), ..., [2^15, 2^16) (columns; clamped at both ends).\n"
+        "// 0: the occupancy heuristic decides.\n"
+        "constexpr int kPairSubgroups[4][10] = {\n%s,\n};\n\n"
+        "}  // namespace tuning\n"
+        "}  // namespace pimd\n"
+        % (result["device"], stamp, result["steps"],
+           ", ".join("%dLL" % v for v in mfma_min), rows))
+
+
+def summary_text(result: dict, mfma_min: list, table: list) -> str:
+    out = ["# fused pass (us): matrix cores vs vector ALUs; force pass (us) per S",
+           "%4s %6s %10s %10s  %s" % ("P", "N", "mfma", "valu", "pair S=1,2,4,8,16")]
+    for x in result["rows"]:
+        pr = " ".join("%8.2f" % (1e3 * x["pair_S%d" % S]) if "pair_S%d" % S in x else "%8s" % "-"
+                      for S in SUBGROUPS)
+        out.append("%4d %6d %10s %10s  %s" % (
+            x["P"], x["N"],
+            "%.2f" % (1e3 * x["fused_mfma"]) if "fused_mfma" in x else "-",
+            "%.2f" % (1e3 * x["fused_valu"]) if "fused_valu" in x else "-", pr))
+    out.append("kMfmaMinBeadAtoms (P=16,32,64): %s" % mfma_min)
+    out.append("kPairSubgroups (rows P=8,16,32,64; cols N=2^6..2^15): %s" % table)
+    return "\n".join(out)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--write", action="store_true", help="rewrite csrc/pimd_tuning.h")
+    ap.add_argument("--json", help="also save the raw timings here")
+    args = ap.parse_args(argv)
+    res = sweep(args.steps, args.warmup, log=lambda m: print(m, file=sys.stderr, flush=True))
+    mfma_min, table = choose(res)
+    print(summary_text(res, mfma_min, table), flush=True)
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(res, f, indent=1)
+    if args.write:
+        with open(HEADER, "w") as f:
+            f.write(header_text(res, mfma_min, table))
+        print("wrote %s" % HEADER, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -13,6 +13,7 @@
 
 #include "../../include/pimd.h"
 #include "pimd_internal.h"
+#include "pimd_tuning.h"
 
 using namespace pimd;
 
@@ -92,6 +93,15 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
     if (p->n_atoms < 1) { why = "n_atoms must be >= 1"; return PIMD_ERR_ARG; }
     if (p->n_beads < 1) { why = "n_beads must be >= 1"; return PIMD_ERR_ARG; }
     if (p->n_beads > kMaxBeads) { why = "n_beads > 128 is not supported"; return PIMD_ERR_UNSUPPORTED; }
+    {
+        const int known = PIMD_FLAG_VALU_TRANSFORMS | PIMD_FLAG_MFMA_TRANSFORMS | PIMD_PAIR_SUBGROUPS_MASK;
+        const int code = (p->flags & PIMD_PAIR_SUBGROUPS_MASK) >> PIMD_PAIR_SUBGROUPS_SHIFT;
+        if (p->flags & ~known) { why = "unknown bits in flags"; return PIMD_ERR_ARG; }
+        if (code > 5 || (code > 0 && (1 << (code - 1)) * p->n_beads > kBlock)) {
+            why = "PIMD_PAIR_SUBGROUPS(S) needs S in {1, 2, 4, 8, 16} and S * n_beads <= 256";
+            return PIMD_ERR_ARG;
+        }
+    }
     if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) { why = "bad ensemble"; return PIMD_ERR_ARG; }
     if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_WATER) { why = "bad potential"; return PIMD_ERR_ARG; }
     if (!finite_pos(p->temp) || !finite_pos(p->kB) || !finite_pos(p->hbar) || !finite_pos(p->mvv2e) ||
@@ -205,6 +215,35 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
     for (int d = 0; d < 3; ++d) L.nc[d] = nc[d];
 }
 
+// Transform variant of the step pass: the flags, else the tuned size at which
+// the matrix cores overtake the vector ALUs for this P.
+bool use_mfma(const pimd_params *p)
+{
+    const int P = p->n_beads;
+    if (!fused_mfma_supported(P) || (p->flags & PIMD_FLAG_VALU_TRANSFORMS)) return false;
+    if (p->flags & PIMD_FLAG_MFMA_TRANSFORMS) return true;
+    const int row = P == 16 ? 0 : (P == 32 ? 1 : 2);
+    return (long long)p->n_atoms * P >= tuning::kMfmaMinBeadAtoms[row];
+}
+
+// Lane sub-groups per atom in the force pass: the flags, else the tuning
+// table, else the occupancy heuristic.
+int choose_pair_subgroups(const pimd_params *p)
+{
+    const int P = p->n_beads, N = p->n_atoms;
+    const int code = (p->flags & PIMD_PAIR_SUBGROUPS_MASK) >> PIMD_PAIR_SUBGROUPS_SHIFT;
+    if (code > 0) return 1 << (code - 1);
+    const int row = P == 8 ? 0 : P == 16 ? 1 : P == 32 ? 2 : P == 64 ? 3 : -1;
+    if (row >= 0) {
+        int lg = 0;
+        while ((2 << lg) <= N) ++lg;            // floor(log2 N)
+        const int col = std::min(std::max(lg - 6, 0), 9);
+        const int S = tuning::kPairSubgroups[row][col];
+        if (S > 0 && S * P <= kBlock) return S;
+    }
+    return pair_subgroups(N, P);
+}
+
 Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
 {
     Layout L{};
@@ -215,10 +254,8 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.cap = cap;
     L.n_active = n_active;
     L.fused_grid = fused_grid(p->n_atoms, p->n_beads);
-    L.mfma_grid = (!(p->flags & PIMD_FLAG_VALU_TRANSFORMS) && fused_mfma_supported(p->n_beads))
-                      ? fused_mfma_grid(p->n_atoms, p->n_beads)
-                      : 0;
-    L.pair_S = pair ? pair_subgroups(p->n_atoms, p->n_beads) : 1;
+    L.mfma_grid = use_mfma(p) ? fused_mfma_grid(p->n_atoms, p->n_beads) : 0;
+    L.pair_S = pair ? choose_pair_subgroups(p) : 1;
     L.pair_grid = pair ? pair_grid(p->n_atoms, p->n_beads, L.pair_S) : 0;
     L.pair_active_tiles = pair ? pair_active_tiles(n_active, p->n_beads, L.pair_S) : 0;
     size_t o = 0;

@@ -21,6 +21,14 @@ ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PI
 PIMD_NVT, PIMD_NVE = 0, 1
 PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER = 0, 1, 2, 3
 PIMD_FLAG_VALU_TRANSFORMS = 1
+PIMD_FLAG_MFMA_TRANSFORMS = 2
+PIMD_PAIR_SUBGROUPS_SHIFT = 8
+
+
+def PIMD_PAIR_SUBGROUPS(S: int) -> int:
+    """Flag bits that fix the force pass's lane sub-groups per atom (S in 1..16)."""
+    code = {1: 1, 2: 2, 4: 3, 8: 4, 16: 5}[S]
+    return code << PIMD_PAIR_SUBGROUPS_SHIFT
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_destroy",

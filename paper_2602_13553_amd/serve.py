@@ -93,7 +93,7 @@ def workspace_bytes(spec) -> int:
 
 def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32,
           keep_states: bool = False, realtime: bool = True,
-          max_active_bead_atoms: float = 4e6) -> ServeReport:
+          max_active_bead_atoms: float = 2e6) -> ServeReport:
     """Replay ``trace`` (jobs with arrival times in seconds) through one batch.
 
     Admission is first-come first-served under three limits: the slot count,
