@@ -12,6 +12,7 @@ events on the library's stream, and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -43,6 +44,53 @@ WORKLOADS = {
     "harmonic": ("harmonic oscillators, N=64, P=4", inputs.harmonic_tiny,
                  "synthetic (seeded Gaussian positions, Maxwell-Boltzmann bead velocities at P*T)"),
 }
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+# the kernel sources a profile's counters belong to (host-side code excluded)
+KERNEL_SOURCES = ("pimd_device.h", "pimd_fused_mfma.hip", "pimd_internal.h", "pimd_kernels.hip",
+                  "pimd_tuning.h")
+
+
+# committed rocprofv3 summaries by (workload, kernel)
+PROFILE_FILES = {
+    ("lj", "k_pair"): "k_pair_lj_n4000_p32.txt",
+    ("lj", "k_fused"): "k_fused_lj_n4000_p32.txt",
+    ("water64", "k_fused_mfma<64>"): "k_fused_mfma_water_n32766_p64.txt",
+    ("water64", "k_pair"): "k_pair_water_n32766_p64.txt",
+}
+
+
+def _counter_name(kname: str) -> str:
+    """The kernel's name as rocprofv3 prints it."""
+    return "void pimd::%s" % kname if "<" in kname else "pimd::%s(" % kname
+
+
+def kernel_source_sha256() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_13553_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(fname: str, kernel: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the counter
+    reads for a plain copy of known size), or None when there is none or the
+    kernel sources have changed since the counters were taken."""
+    try:
+        with open(os.path.join(PROFILES, fname)) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if ln.startswith("traffic " + kernel):
+            kv = dict(t.split("=", 1) for t in ln.split() if "=" in t)
+            if kv.get("source_sha256") != kernel_source_sha256():
+                return None
+            return int(kv["total_bytes"])
+    return None
 
 
 def log(msg):
@@ -86,8 +134,9 @@ def run_gpu(spec, steps, warmup, profile_steps, flags=0):
     prof = ctx.profile_end()
     t3 = time.perf_counter()
     x, p, s = ctx.get_state()
+    info = ctx.launch_info()
     ctx.close()
-    return ms_step, est, prof, (t3 - t2) * 1e3 / profile_steps, x
+    return ms_step, est, prof, (t3 - t2) * 1e3 / profile_steps, x, info
 
 
 def kernel_avgs(prof):
@@ -202,28 +251,34 @@ def main():
         from paper_2602_13553_amd import pimd as _p
         flags = _p.PIMD_FLAG_VALU_TRANSFORMS
     log("workload %s: %d warmup + %d timed steps" % (spec.name, args.warmup, args.steps))
-    ms_step, est, prof, ms_prof, x = run_gpu(spec, args.steps, args.warmup, args.profile_steps,
-                                             flags)
+    ms_step, est, prof, ms_prof, x, info = run_gpu(spec, args.steps, args.warmup,
+                                                   args.profile_steps, flags)
     ba = spec.bead_atoms
     value = ba * 1e3 / ms_step
     avgs = kernel_avgs(prof)
     log("ms/step %.4f (profiled %.4f); kernels %s" % (ms_step, ms_prof, avgs))
 
     # dominant kernel of the workload and its roofline
+    fused_name = ("k_fused_mfma<%d>" % spec.n_beads) if info["transforms"] else "k_fused"
     dom = max(("fused", "pair"), key=lambda k: avgs[k][0] * avgs[k][1])
     if dom == "pair":
         npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc, spec.lj_active)
         flops = LJ_FLOPS_PER_PAIR * npairs
         ach = flops / (avgs["pair"][0] * 1e-3) / 1e12
         roof = {"kernel": "k_pair", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "traffic": profiled_traffic(PROFILE_FILES.get((args.workload, "k_pair"), ""),
+                                            "pimd::k_pair("),
                 "work_per_launch": "%d ordered bead pairs inside rc x %d flops"
                                    % (npairs, LJ_FLOPS_PER_PAIR)}
     else:
         byts = (FUSED_BYTES_PAIR if spec.potential != inputs.POT_HARMONIC else FUSED_BYTES_EXT) * ba
         ach = byts / (avgs["fused"][0] * 1e-3) / 1e9
-        roof = {"kernel": "k_fused", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+        roof = {"kernel": fused_name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": profiled_traffic(PROFILE_FILES.get((args.workload, fused_name), ""),
+                                            _counter_name(fused_name)),
+                "bytes_per_launch": byts}
     fused_gbs = FUSED_BYTES_PAIR * ba / (avgs["fused"][0] * 1e-3) / 1e9
 
     out = {
@@ -246,6 +301,7 @@ def main():
                    "transforms": args.transforms},
         "roofline": roof,
         "kernels_ms": {k: v[0] for k, v in avgs.items()},
+        "launch": info,
         "fused_in_cache_gbs": fused_gbs,
         "estimators": {"kcv_per_atom": est["kcv"] / spec.n_atoms,
                        "kprim_per_atom": est["kprim"] / spec.n_atoms, "temp": est["temp"]},
@@ -258,18 +314,21 @@ def main():
         # the water-shaped workload at P=64 (N=32766, 2.1e6 bead*atoms, 252 MB/step)
         w = inputs.water(n_beads=64)
         log("hbm probe %s" % w.name)
-        ms_w, _, prof_w, _, _ = run_gpu(w, 50, 10, 50)
+        ms_w, _, prof_w, _, _, info_w = run_gpu(w, 50, 10, 50)
         aw = kernel_avgs(prof_w)
         gbs = FUSED_BYTES_PAIR * w.bead_atoms / (aw["fused"][0] * 1e-3) / 1e9
-        out["fused_roofline"] = {"kernel": "k_fused", "workload": w.name, "bound": "hbm",
+        kname = ("k_fused_mfma<64>" if info_w["transforms"] else "k_fused")
+        out["fused_roofline"] = {"kernel": kname, "workload": w.name, "bound": "hbm",
                                  "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                                 "frac": gbs / HBM_PEAK_GBS,
+                                 "traffic": profiled_traffic(
+                                     PROFILE_FILES.get(("water64", kname), ""), _counter_name(kname)),
                                  "bytes_per_launch": FUSED_BYTES_PAIR * w.bead_atoms}
         out["water_p64"] = {"bead_atom_steps_per_s": w.bead_atoms * 1e3 / ms_w,
                             "ms_per_step": ms_w, "kernels_ms": {k: v[0] for k, v in aw.items()}}
         # the same pass with the transforms on the FP64 vector ALUs instead of MFMA
         from paper_2602_13553_amd import pimd as _p
-        ms_v, _, prof_v, _, _ = run_gpu(w, 50, 10, 50, flags=_p.PIMD_FLAG_VALU_TRANSFORMS)
+        ms_v, _, prof_v, _, _, _ = run_gpu(w, 50, 10, 50, flags=_p.PIMD_FLAG_VALU_TRANSFORMS)
         av = kernel_avgs(prof_v)
         out["transform_variants_water_p64_fused_ms"] = {"mfma": aw["fused"][0],
                                                          "valu": av["fused"][0]}

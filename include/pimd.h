@@ -209,6 +209,21 @@ typedef struct pimd_profile {
 int pimd_profile_begin(pimd_ctx *ctx);
 int pimd_profile_end(pimd_ctx *ctx, pimd_profile *out);
 
+/* Launch shapes the context uses (chosen at pimd_create from the tuning
+ * table and the flags; fixed for the context's life).  transforms: 1 = FP64
+ * matrix cores, 0 = FP64 vector ALUs in the step pass; fused_blocks: blocks
+ * of the step pass; pair_subgroups, pair_blocks: lane sub-groups per atom and
+ * blocks of the force pass (0 without pair forces); cells: centroid cells of
+ * the list build (0 = all-pairs scan).  Errors: ARG. */
+typedef struct pimd_launch_info {
+    int32_t transforms;
+    int32_t fused_blocks;
+    int32_t pair_subgroups;
+    int32_t pair_blocks;
+    int32_t cells;
+} pimd_launch_info;
+int pimd_get_launch_info(const pimd_ctx *ctx, pimd_launch_info *out);
+
 /* ---- Batched execution ------------------------------------------------
  * Many independent systems (each with its own N, P, T, potential, seed, ...)
  * advanced together: one step of the whole batch is a fixed handful of

@@ -25,7 +25,7 @@ constexpr int kGraphChunk = 32;   // steps per captured graph
 
 struct Layout {
     size_t x, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
-        partials, fpartials, ctl, cell_atoms, cell_sorted, cell_scnt, cinfo, total;
+        partials, fpartials, ctl, cell_atoms, cell_ent, cell_scnt, cinfo, total;
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
     int valu_tiles, mfma_tiles;
     int ncell, cell_cap, nc[3];   // centroid cells (ncell = 0: none)
@@ -208,7 +208,7 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
     }
     if (ncell > 8LL * n_active + 64) return;
     const double mean = (double)n_active / (double)ncell;
-    const int cap = (int)std::ceil(2.0 * mean) + 16;
+    const int cap = ((int)std::ceil(2.0 * mean) + 16 + 3) & ~3;   // rows of whole int4
     if (cap > kSortBuf || ncell > kMaxCells) return;
     L.ncell = (int)ncell;
     L.cell_cap = cap;
@@ -283,7 +283,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
     L.ctl = take(sizeof(Ctl));
     L.cell_atoms = take((size_t)L.ncell * L.cell_cap * sizeof(int));
-    L.cell_sorted = take((size_t)L.ncell * L.cell_cap * sizeof(int));
+    L.cell_ent = take((size_t)L.ncell * L.cell_cap * sizeof(CellEntry));
     L.cell_scnt = take((size_t)L.ncell * sizeof(int));
     L.cinfo = take(L.ncell ? N * sizeof(int4) : 0);
     L.total = o;
@@ -571,7 +571,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         a.icw[d] = L.ncell ? (double)L.nc[d] / p->box[d] : 0.0;
     }
     a.cell_atoms = L.ncell ? (int *)(w + L.cell_atoms) : nullptr;
-    a.cell_sorted = L.ncell ? (int *)(w + L.cell_sorted) : nullptr;
+    a.cell_ent = L.ncell ? (CellEntry *)(w + L.cell_ent) : nullptr;
     a.cell_scnt = L.ncell ? (int *)(w + L.cell_scnt) : nullptr;
     a.cinfo = L.ncell ? (int4 *)(w + L.cinfo) : nullptr;
 
@@ -595,7 +595,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     q.ctl = c->d_ctl;
     for (int d = 0; d < 3; ++d) q.nc[d] = L.nc[d];
     q.cell_cap = L.cell_cap;
-    q.cell_sorted = a.cell_sorted;
+    q.cell_ent = a.cell_ent;
     q.cell_scnt = a.cell_scnt;
     q.cinfo = a.cinfo;
 
@@ -669,6 +669,18 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
     for (; left > 0; --left) enqueue_step(c);
     if (c->fa.pair) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
     return launch_error(c, "step launch");
+}
+
+int pimd_get_launch_info(const pimd_ctx *c, pimd_launch_info *out)
+{
+    if (!c || !out) return fail(nullptr, PIMD_ERR_ARG, "ctx or out is NULL");
+    const Layout &L = c->lay;
+    out->transforms = L.mfma_grid > 0 ? 1 : 0;
+    out->fused_blocks = L.mfma_grid > 0 ? L.mfma_grid : L.fused_grid;
+    out->pair_subgroups = c->fa.pair ? L.pair_S : 0;
+    out->pair_blocks = c->fa.pair ? L.pair_grid : 0;
+    out->cells = L.ncell;
+    return PIMD_OK;
 }
 
 int pimd_profile_begin(pimd_ctx *c)

@@ -56,6 +56,15 @@ struct Ctl {
     int cell_R[3];             // stencil half-width in cells per dim for that rebuild
 };
 
+// One atom of a centroid cell as the list build reads it: its centroid, its
+// index and the integer box index of the unwrapped centroid per dim.
+struct __attribute__((aligned(16))) CellEntry {
+    double c[3];
+    int j;
+    int nb[3];
+    int pad;
+};
+
 struct FusedArgs {
     int N, P, n_active;
     int mode;                 // FusedMode
@@ -90,7 +99,7 @@ struct FusedArgs {
     double box[3];
     double icw[3];            // cells per unit length
     int *cell_atoms;          // [ncell][cell_cap] a rebuild's cell lists, placement order
-    int *cell_sorted;         // [ncell][cell_cap] the same, increasing index
+    CellEntry *cell_ent;      // [ncell][cell_cap] the same, increasing index, with centroids
     int *cell_scnt;           // [ncell] atoms per cell
     int4 *cinfo;              // [N] (cell, image index per dim) of each active atom's centroid
 };
@@ -118,7 +127,7 @@ struct PairArgs {
     double *fpartials;        // [gridDim]
     Ctl *ctl;
     int nc[3], cell_cap;      // centroid cells (see FusedArgs)
-    const int *cell_sorted;
+    const CellEntry *cell_ent;
     const int *cell_scnt;
     const int4 *cinfo;
 };

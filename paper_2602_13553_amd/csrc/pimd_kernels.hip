@@ -330,7 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *table, 
 // candidates in a fixed order.  Decides whether the cells can serve this
 // rebuild: no cell over capacity, and a stencil of 2R+1 cells per dim that
 // does not wrap onto itself.  One block; no global atomics.
-__device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int *shist, int *sflag)
+__device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int *sord, int *shist,
+                               int *sflag)
 {
     const int t = threadIdx.x;
     const int ncell = a.ncell, cap = a.cell_cap, na = a.n_active;
@@ -406,15 +407,49 @@ __device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int 
                     if (e0 + u * kBlock < ne) sbuf[e0 + u * kBlock] = v[u];
             }
             __syncthreads();
-            for (int e = t; e < nb * cap; e += kBlock) {
+            // ranks from LDS only: each atom's place among its cell's atoms
+            for (int e = t; e < ne; e += kBlock) {
                 const int cl = e / cap, sl = e - cl * cap;
                 const int n = shist[c0 + cl];
                 if (sl < n) {
                     const int v = sbuf[e];
-                    const int *row = sbuf + cl * cap;
+                    const int4 *row4 = reinterpret_cast<const int4 *>(sbuf + cl * cap);
                     int rank = 0;
-                    for (int q = 0; q < n; ++q) rank += row[q] < v ? 1 : 0;
-                    a.cell_sorted[(size_t)(c0 + cl) * cap + rank] = v;
+#pragma unroll 4
+                    for (int q4 = 0; q4 < (n + 3) >> 2; ++q4) {
+                        const int4 r = row4[q4];
+                        const int b = 4 * q4;
+                        rank += (b < n && r.x < v) + (b + 1 < n && r.y < v) +
+                                (b + 2 < n && r.z < v) + (b + 3 < n && r.w < v);
+                    }
+                    sord[cl * cap + rank] = v;
+                }
+            }
+            __syncthreads();
+            // the entries in index order, with each atom's centroid and box
+            // indices (eight gathers in flight per thread)
+            for (int e0 = t; e0 < ne; e0 += U * kBlock) {
+                int v[U];
+                double cx[U], cy[U], cz[U];
+                int4 ci[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * kBlock;
+                    const int cl = e / cap, sl = e - cl * cap;
+                    v[u] = (e < ne && sl < shist[c0 + min(cl, nb - 1)]) ? sord[e] : -1;
+                    const int vv = v[u] < 0 ? 0 : v[u];
+                    cx[u] = a.cent[vv * 3]; cy[u] = a.cent[vv * 3 + 1]; cz[u] = a.cent[vv * 3 + 2];
+                    ci[u] = a.cinfo[vv];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (v[u] < 0) continue;
+                    CellEntry ce;
+                    ce.c[0] = cx[u]; ce.c[1] = cy[u]; ce.c[2] = cz[u];
+                    ce.j = v[u];
+                    ce.nb[0] = ci[u].y; ce.nb[1] = ci[u].z; ce.nb[2] = ci[u].w;
+                    ce.pad = 0;
+                    a.cell_ent[(size_t)c0 * cap + e0 + u * kBlock] = ce;
                 }
             }
             __syncthreads();
@@ -540,14 +575,14 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         const bool rb = red[0] != 0.0;
         const double rl = red[1];
         __syncthreads();
-        if (rb) cells_finalize(a, rl, sbuf, sbuf + kSortBuf, sflag);
+        if (rb) cells_finalize(a, rl, sbuf, sbuf + kSortBuf, sbuf + 2 * kSortBuf, sflag);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
 {
     __shared__ double red[64];
-    __shared__ int sbuf[kSortBuf + kMaxCells];
+    __shared__ __align__(16) int sbuf[2 * kSortBuf + kMaxCells];
     __shared__ int sflag[1];
     finalize_system(a, nblocks, red, sbuf, sflag);
 }
@@ -557,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FusedArgs *tabl
                                                            const int *nparts, int n_sys, int mode)
 {
     __shared__ double red[64];
-    __shared__ int sbuf[kSortBuf + kMaxCells];
+    __shared__ __align__(16) int sbuf[2 * kSortBuf + kMaxCells];
     __shared__ int sflag[1];
     for (int sidx = blockIdx.x; sidx < n_sys; sidx += gridDim.x) {
         FusedArgs a = table[sidx];
@@ -687,47 +722,59 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         const bool builder = act && i < a.n_active && g < Gb;
         if (builder) {
             const int4 ii = a.cinfo[i];
-            const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+            const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2], ccap = a.cell_cap;
             const int cx = ii.x % nx, cy = (ii.x / nx) % ny, cz = ii.x / (nx * ny);
             const int R0 = a.ctl->cell_R[0], R1 = a.ctl->cell_R[1], R2 = a.ctl->cell_R[2];
+            const int sx_n = 2 * R0 + 1, sy_n = 2 * R1 + 1;
+            const int NS = sx_n * sy_n * (2 * R2 + 1);
             const double ci0 = a.cent[i * 3], ci1 = a.cent[i * 3 + 1], ci2 = a.cent[i * 3 + 2];
             int2 *mylist = a.nbr + (size_t)i * a.cap;
-            for (int oz = -R2; oz <= R2; ++oz) {
-                int qz = cz + oz, kz = 0;
-                if (qz < 0) { qz += nz; kz = -1; } else if (qz >= nz) { qz -= nz; kz = 1; }
-                for (int oy = -R1; oy <= R1; ++oy) {
-                    int qy = cy + oy, ky = 0;
-                    if (qy < 0) { qy += ny; ky = -1; } else if (qy >= ny) { qy -= ny; ky = 1; }
-                    for (int ox = -R0; ox <= R0; ++ox) {
-                        int qx = cx + ox, kx = 0;
-                        if (qx < 0) { qx += nx; kx = -1; } else if (qx >= nx) { qx -= nx; kx = 1; }
-                        const int cell = (qz * ny + qy) * nx + qx;
-                        const int n = a.cell_scnt[cell];
-                        const int *cl = a.cell_sorted + (size_t)cell * a.cell_cap;
-                        for (int q0 = 0; q0 < n; q0 += Gb) {
-                            const int q = q0 + g;
-                            bool pass = false;
-                            int j = 0, sx = 0, sy = 0, sz = 0;
-                            if (q < n) {
-                                j = cl[q];
-                                const int4 jj = a.cinfo[j];
-                                sx = jj.y - ii.y - kx;
-                                sy = jj.z - ii.z - ky;
-                                sz = jj.w - ii.w - kz;
-                                const double ex = ci0 - a.cent[j * 3] + sx * L0;
-                                const double ey = ci1 - a.cent[j * 3 + 1] + sy * L1;
-                                const double ez = ci2 - a.cent[j * 3 + 2] + sz * L2;
-                                pass = (j != i) && (ex * ex + ey * ey + ez * ez < rl2);
-                            }
-                            const unsigned long long hit = __ballot(pass) & gmask;
-                            if (pass) {
-                                const int w = total + __popcll(hit & below);
-                                if (w < a.cap) mylist[w] = make_int2(j, pack_shift(sx, sy, sz));
-                            }
-                            total += __popcll(hit);
-                        }
-                    }
+            // stencil cell s (fixed order, x fastest) and the image it wraps to
+            auto stencil = [&](int s, int &kx, int &ky, int &kz) {
+                const int ox = s % sx_n - R0, oy = (s / sx_n) % sy_n - R1, oz = s / (sx_n * sy_n) - R2;
+                int qx = cx + ox, qy = cy + oy, qz = cz + oz;
+                kx = qx < 0 ? -1 : (qx >= nx ? 1 : 0);
+                ky = qy < 0 ? -1 : (qy >= ny ? 1 : 0);
+                kz = qz < 0 ? -1 : (qz >= nz ? 1 : 0);
+                qx -= kx * nx; qy -= ky * ny; qz -= kz * nz;
+                return (qz * ny + qy) * nx + qx;
+            };
+            auto entry = [&](int cell, int q) {
+                CellEntry e = {{0.0, 0.0, 0.0}, -1, {0, 0, 0}, 0};
+                if (q < ccap) e = a.cell_ent[(size_t)cell * ccap + q];
+                return e;
+            };
+            auto test = [&](const CellEntry &e, bool in, int kx, int ky, int kz) {
+                const int j = e.j;
+                const int sx = e.nb[0] - ii.y - kx, sy = e.nb[1] - ii.z - ky, sz = e.nb[2] - ii.w - kz;
+                const double ex = ci0 - e.c[0] + sx * L0;
+                const double ey = ci1 - e.c[1] + sy * L1;
+                const double ez = ci2 - e.c[2] + sz * L2;
+                const bool pass = in && (j != i) && (ex * ex + ey * ey + ez * ez < rl2);
+                const unsigned long long hit = __ballot(pass) & gmask;
+                if (pass) {
+                    const int w = total + __popcll(hit & below);
+                    if (w < a.cap) mylist[w] = make_int2(j, pack_shift(sx, sy, sz));
                 }
+                total += __popcll(hit);
+            };
+            // one cell ahead: the next cell's count and first entries are in
+            // flight while the current one is tested
+            int kx, ky, kz;
+            int cell = stencil(0, kx, ky, kz);
+            int n = a.cell_scnt[cell];
+            CellEntry e = entry(cell, g);
+            for (int s = 0; s < NS; ++s) {
+                const int ccell = cell, cn = n, ckx = kx, cky = ky, ckz = kz;
+                const CellEntry ce = e;
+                if (s + 1 < NS) {
+                    cell = stencil(s + 1, kx, ky, kz);
+                    n = a.cell_scnt[cell];
+                    e = entry(cell, g);
+                }
+                test(ce, g < cn, ckx, cky, ckz);
+                for (int q0 = Gb; q0 < cn; q0 += Gb)
+                    test(entry(ccell, q0 + g), q0 + g < cn, ckx, cky, ckz);
             }
         }
         if (act && g == 0) {

@@ -32,7 +32,7 @@ def PIMD_PAIR_SUBGROUPS(S: int) -> int:
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_destroy",
-            "pimd_last_error", "pimd_profile_begin", "pimd_profile_end",
+            "pimd_last_error", "pimd_profile_begin", "pimd_profile_end", "pimd_get_launch_info",
             "pimd_batch_create", "pimd_batch_add", "pimd_batch_remove", "pimd_batch_set_state",
             "pimd_batch_set_budget", "pimd_batch_step", "pimd_batch_get_estimators",
             "pimd_batch_get_state", "pimd_batch_destroy", "pimd_batch_last_error")
@@ -72,6 +72,11 @@ class pimd_profile(C.Structure):
     _fields_ = [("launches", C.c_uint64 * 4), ("ms", C.c_double * 4)]
 
 
+class pimd_launch_info(C.Structure):
+    _fields_ = [("transforms", C.c_int32), ("fused_blocks", C.c_int32),
+                ("pair_subgroups", C.c_int32), ("pair_blocks", C.c_int32), ("cells", C.c_int32)]
+
+
 _lib = None
 
 
@@ -100,6 +105,7 @@ def load() -> C.CDLL:
         lib.pimd_destroy.restype = None
         lib.pimd_profile_begin.argtypes = [C.c_void_p]
         lib.pimd_profile_end.argtypes = [C.c_void_p, P(pimd_profile)]
+        lib.pimd_get_launch_info.argtypes = [C.c_void_p, P(pimd_launch_info)]
         lib.pimd_last_error.argtypes = [C.c_void_p]
         lib.pimd_last_error.restype = C.c_char_p
         lib.pimd_batch_create.argtypes = [C.c_void_p, P(C.c_void_p)]
@@ -255,6 +261,12 @@ class Context:
         r = pimd_profile()
         self._check(self._lib.pimd_profile_end(self._h, C.byref(r)), self._h)
         return {n: (int(r.launches[q]), float(r.ms[q])) for q, n in enumerate(KERNEL_NAMES)}
+
+    def launch_info(self) -> dict:
+        """Launch shapes of this context (transform variant, grids, sub-groups, cells)."""
+        r = pimd_launch_info()
+        self._check(self._lib.pimd_get_launch_info(self._h, C.byref(r)), self._h)
+        return {f: int(getattr(r, f)) for f, _ in pimd_launch_info._fields_}
 
     def reset_averages(self) -> None:
         self._check(self._lib.pimd_reset_averages(self._h), self._h)

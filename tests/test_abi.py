@@ -48,6 +48,7 @@ def test_binding_structs_follow_header():
     assert fields("pimd_topology") == [f[0] for f in pimd.pimd_topology._fields_]
     assert fields("pimd_estimators") == [f[0] for f in pimd.pimd_estimators._fields_]
     assert fields("pimd_profile") == [f[0] for f in pimd.pimd_profile._fields_]
+    assert fields("pimd_launch_info") == [f[0] for f in pimd.pimd_launch_info._fields_]
 
 
 def test_create_rejects_bad_parameters_without_gpu():
@@ -71,6 +72,23 @@ def test_create_rejects_bad_parameters_without_gpu():
     assert lib.pimd_workspace_bytes(C.byref(lj), pimd._dp(np.ones(32)), None, C.byref(n)) == -6
     h = C.c_void_p()
     assert lib.pimd_create(C.byref(bad), pimd._dp(mass), None, None, 0, None, C.byref(h)) == -1
+
+
+def test_flags_are_validated_without_gpu():
+    """Launch-shape flags: unknown bits and sub-group counts beyond one block fail."""
+    lib = pimd.load()
+    spec = inputs.lj_liquid(n_atoms=256, n_beads=32)
+    mass = np.ascontiguousarray(spec.mass)
+    n = C.c_size_t()
+    for flags, rc in ((pimd.PIMD_FLAG_VALU_TRANSFORMS, 0), (pimd.PIMD_FLAG_MFMA_TRANSFORMS, 0),
+                      (pimd.PIMD_PAIR_SUBGROUPS(8), 0), (pimd.PIMD_PAIR_SUBGROUPS(16), -1),
+                      (1 << 20, -1), (6 << pimd.PIMD_PAIR_SUBGROUPS_SHIFT, -1)):
+        p = pimd.params_from_spec(spec, flags)
+        assert lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n)) == rc, flags
+    # the header's macro and the binding agree on the encoding
+    src = open(HEADER).read()
+    assert "#define PIMD_PAIR_SUBGROUPS_SHIFT %d" % pimd.PIMD_PAIR_SUBGROUPS_SHIFT in src
+    assert "#define PIMD_FLAG_MFMA_TRANSFORMS %d" % pimd.PIMD_FLAG_MFMA_TRANSFORMS in src
 
 
 def test_workload_generators():
