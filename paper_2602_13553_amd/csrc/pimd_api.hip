@@ -93,6 +93,10 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
     if (p->n_atoms < 1) { why = "n_atoms must be >= 1"; return PIMD_ERR_ARG; }
     if (p->n_beads < 1) { why = "n_beads must be >= 1"; return PIMD_ERR_ARG; }
     if (p->n_beads > kMaxBeads) { why = "n_beads > 128 is not supported"; return PIMD_ERR_UNSUPPORTED; }
+    if ((long long)p->n_atoms * 3 * p->n_beads >= (1LL << 31)) {
+        why = "n_atoms * 3 * n_beads must stay below 2^31";
+        return PIMD_ERR_UNSUPPORTED;
+    }
     {
         const int known = PIMD_FLAG_VALU_TRANSFORMS | PIMD_FLAG_MFMA_TRANSFORMS | PIMD_PAIR_SUBGROUPS_MASK;
         const int code = (p->flags & PIMD_PAIR_SUBGROUPS_MASK) >> PIMD_PAIR_SUBGROUPS_SHIFT;

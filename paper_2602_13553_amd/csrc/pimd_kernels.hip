@@ -668,7 +668,12 @@ __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, d
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
-        const double ir2 = 1.0 / r2;
+        // 1/r2: hardware reciprocal refined by two Newton steps (a few ulp at
+        // most, far inside the FP64 parity bar) instead of the IEEE division
+        // sequence
+        double ir2 = __builtin_amdgcn_rcp(r2);
+        ir2 = fma(fma(-r2, ir2, 1.0), ir2, ir2);
+        ir2 = fma(fma(-r2, ir2, 1.0), ir2, ir2);
         const double sr2 = sig2 * ir2;
         const double sr6 = sr2 * sr2 * sr2;
         const double fr = eps24 * (2.0 * sr6 * sr6 - sr6) * ir2;
@@ -754,7 +759,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                 const unsigned long long hit = __ballot(pass) & gmask;
                 if (pass) {
                     const int w = total + __popcll(hit & below);
-                    if (w < a.cap) mylist[w] = make_int2(j, pack_shift(sx, sy, sz));
+                    if (w < a.cap) mylist[w] = make_int2(j * 3 * P, pack_shift(sx, sy, sz));
                 }
                 total += __popcll(hit);
             };
@@ -849,7 +854,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                             if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
                             const double ex = dx + sx * L0, ey = dy + sy * L1, ez = dz + sz * L2;
                             if (ex * ex + ey * ey + ez * ez < rl2) {
-                                if (w < a.cap) mylist[w] = make_int2(j, pack_shift(sx, sy, sz));
+                                if (w < a.cap) mylist[w] = make_int2(j * 3 * P, pack_shift(sx, sy, sz));
                                 ++w;
                             }
                         }
@@ -895,7 +900,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
             double xj[4], yj[4], zj[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const size_t jb = (size_t)en[u].x * P3 + k;
+                const int jb = en[u].x + k;
                 xj[u] = X[jb]; yj[u] = X[jb + P]; zj[u] = X[jb + 2 * P];
             }
 #pragma unroll
@@ -910,7 +915,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
             const int2 en = lst[q];
             double sx, sy, sz;
             unpack_shift(en.y, sx, sy, sz);
-            const size_t jb = (size_t)en.x * P3 + k;
+            const int jb = en.x + k;
             lj_accumulate(xi - X[jb] + sx * L0, yi - X[jb + P] + sy * L1, zi - X[jb + 2 * P] + sz * L2,
                           rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
         }
