@@ -79,30 +79,51 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         const int a0 = tile * A;
         const int na = min(A, N - a0);
         const int nel = na * 3 * P;
-        __syncthreads();
-        {
-            const double *xg = a.x + (size_t)a0 * 3 * P;
-            for (int e = t; e < nel; e += kBlock) sX[e] = xg[e];
-            if (need_f) {
-                const double *fg = a.f + (size_t)a0 * 3 * P;
-                for (int e = t; e < nel; e += kBlock) sF[e] = fg[e];
-            } else if (mode == FUSED_PREP) {
-                const double *vg = a.vin + (size_t)a0 * 3 * P;
-                for (int e = t; e < nel; e += kBlock) sF[e] = vg[e];
-            }
-        }
-        __syncthreads();
-
         const bool act = lane_ok && la < na;
         const int i = a0 + la;
-        double xt[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0}, vt[3] = {0.0, 0.0, 0.0};
-        double ref[3] = {0.0, 0.0, 0.0};
+        // Every global read of the tile in flight at once, before the barrier
+        // that frees the previous tile's LDS: the x tile and the f (or PREP's
+        // v) tile, 3 doubles each per thread (A*3P <= 3*256), this lane's v~
+        // and per-atom constants.
+        constexpr int NL = 3;
+        const double *xg = a.x + (size_t)a0 * 3 * P;
+        const double *fg = need_f ? a.f + (size_t)a0 * 3 * P
+                                  : (mode == FUSED_PREP ? a.vin + (size_t)a0 * 3 * P : nullptr);
+        double rx[NL], rf[NL];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = t + q * kBlock;
+            rx[q] = e < nel ? xg[e] : 0.0;
+            rf[q] = (fg && e < nel) ? fg[e] : 0.0;
+        }
         double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0;
+        double vpre[3] = {0.0, 0.0, 0.0};
+        unsigned long long oi = 0;
         if (act) {
             hm = a.atoms[i * 4 + AT_HALF_M];
             im = a.atoms[i * 4 + AT_INV_M];
             sg = a.atoms[i * 4 + AT_SIGMA];
             active = a.atoms[i * 4 + AT_ACTIVE];
+            oi = (unsigned long long)a.orig[i];
+            if (mode != FUSED_PREP) {
+                const size_t vb = (size_t)i * 3 * P + k;
+                vpre[0] = a.v[vb]; vpre[1] = a.v[vb + P]; vpre[2] = a.v[vb + 2 * P];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = t + q * kBlock;
+            if (e < nel) {
+                sX[e] = rx[q];
+                if (fg) sF[e] = rf[q];
+            }
+        }
+        __syncthreads();
+
+        double xt[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0}, vt[3] = {0.0, 0.0, 0.0};
+        double ref[3] = {0.0, 0.0, 0.0};
+        if (act) {
             // Forward transforms of this mode.  Positions are carried relative
             // to the atom's bead 0 for the whole step: y_j = x_j - x_0 (exact),
             // y~ = M y.  Since the non-centroid rows of M sum to zero,
@@ -130,7 +151,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 vt[0] = ft[0]; vt[1] = ft[1]; vt[2] = ft[2];
                 ft[0] = ft[1] = ft[2] = 0.0;
             } else {
-                vt[0] = a.v[vb]; vt[1] = a.v[vb + P]; vt[2] = a.v[vb + 2 * P];
+                vt[0] = vpre[0]; vt[1] = vpre[1]; vt[2] = vpre[2];
             }
             // absolute mode coordinate x~_k (differs from y~_k only for k = 0)
             const double off = (k == 0) ? sqrtP : 0.0;
@@ -167,7 +188,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 // O(dt): PILE-L at P*T
                 if (a.nvt) {
                     double z[3];
-                    gauss3(a.seed, (unsigned long long)a.orig[i], (unsigned long long)k, step, z);
+                    gauss3(a.seed, oi, (unsigned long long)k, step, z);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
                 }
