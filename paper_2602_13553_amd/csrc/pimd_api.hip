@@ -24,7 +24,7 @@ thread_local std::string g_create_error = "no error";
 constexpr int kGraphChunk = 32;   // steps per captured graph
 
 struct Layout {
-    size_t x, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
+    size_t x, yt, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
         partials, fpartials, ctl, cell_atoms, cell_ent, cell_scnt, cinfo, total;
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
     int valu_tiles, mfma_tiles;
@@ -265,6 +265,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
     L.x = take(arr);
+    L.yt = take(arr);
     L.v = take(arr);
     L.f = take(pair ? arr : 0);
     L.stage = take(arr);
@@ -560,7 +561,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.kT15PN = 1.5 * (double)P * (double)N * kT;
     a.temp_norm = 2.0 / (3.0 * (double)N * (double)P * (double)P * p->kB);
     a.seed = p->seed;
-    a.x = c->d_x; a.v = c->d_v; a.f = c->d_f; a.vin = c->d_f;
+    a.x = c->d_x; a.yt = (double *)(w + L.yt); a.v = c->d_v; a.f = c->d_f; a.vin = c->d_f;
     a.cent = c->d_cent; a.cref = c->d_cref;
     a.M = c->d_M; a.MT = c->d_MT; a.modes = c->d_modes; a.atoms = c->d_atoms; a.orig = c->d_orig;
     a.partials = c->d_partials;

@@ -1,25 +1,30 @@
 // Fused BAOAB step pass with the normal-mode transforms on the FP64 matrix
 // cores (v_mfma_f64_16x16x4f64), for P in {16, 32, 64}.
 //
-// A block works on T = 64/P tiles of 16 atoms at once.  The x and f values of
-// those atoms are loaded into LDS with coalesced reads (atom rows padded to
-// 3P+1 doubles, which makes the operand reads conflict-free); each tile is
-// shared by P/16 waves, wave w taking mode block (and, in the inverse, bead
-// block) w % (P/16).  Per dim d the wave forms
-//   y~^T[atom][mode] = sum_bead (x - x_0)^T[atom][bead] M^T[bead][mode]
+// The positions' normal modes are carried from step to step relative to each
+// atom's bead 0: y~ = M (x - x_0 1) (App. B, Eq. B1; exact because the
+// non-centroid rows of M sum to zero), so a step needs two of the three
+// transforms of Sec. IV.A, f~ = M f and the inverse x = x_0 + M^T y~.  At the
+// end of the step the reference moves to the new bead 0, which changes only
+// the centroid mode, by -sqrt(P) times that bead's offset.
+//
+// A block works on T = 64/P tiles of 16 atoms at once.  The f and y~ values of
+// those atoms are loaded into LDS with coalesced reads (f in atom rows padded
+// to 3P+1 doubles, y~ in [dim][atom][mode] rows padded to P+1, which makes the
+// operand reads conflict-free); each tile is shared by P/16 waves, wave w
+// taking mode block (and, in the inverse, bead block) w % (P/16).  Per dim d
+// the wave forms
 //   f~^T[atom][mode] = sum_bead f^T[atom][bead] M^T[bead][mode]
 //   x^T[atom][bead]  = x_0 + sum_mode y~^T[atom][mode] M[mode][bead]
-// (App. B, Eqs. B1, B3; positions relative to bead 0, exact because the
-// non-centroid rows of M sum to zero).  The wave's slices of M live in
-// registers; the new y~ goes to LDS (over the f values, no longer needed) for
-// the inverse.
+// with the B operands (4 rows x 16 columns of M^T or M) read from global
+// memory, where they stay cache resident.
 //
 // Operand layout of the instruction (checked on the device): A[i][k] in lane
 // i + 16k, B[k][j] in lane j + 16k, and accumulator register r of lane l
 // holds D[4r + l/16][l%16].  With atoms as rows, lane l holds, for one mode
 // (column l%16 of the wave's mode block), the four atoms 4r + l/16: the
 // per-(atom, mode) work (B, A, O with one Philox call for the three dims, A)
-// runs in registers, and v~ is read and written as 128-byte segments.
+// runs in registers, and v~ and y~ are read and written as 128-byte segments.
 #include "pimd_device.h"
 #include "pimd_internal.h"
 
@@ -42,7 +47,7 @@ struct Lds {
     static constexpr int T = kWaves / NMB;        // atom tiles per block
     static constexpr int XS = 3 * P + 1;          // padded atom row of a tile
     static constexpr int PS = P + 1;              // padded row of the y~ staging
-    static constexpr int XY_ELEMS = 3 * 16 * PS;  // x [16][XS], later y~ [3][16][PS]
+    static constexpr int XY_ELEMS = 3 * 16 * PS;  // y~ [3][16][PS]
     static constexpr int F_ELEMS = 16 * XS;       // f [16][XS]
     static constexpr int AT_W = 12;               // per-atom row of the atom table
     static constexpr int AT_ELEMS = 16 * AT_W;
@@ -51,7 +56,6 @@ struct Lds {
     static constexpr int MK_ELEMS = 8 * P;        // the per-mode table, shared by the block
     static constexpr int bytes = 8 * (T * TILE + MK_ELEMS);
     static constexpr int NLD = 16 * T * 3 * P / kBlock;   // tile elements per thread
-    static_assert(16 * XS <= XY_ELEMS, "x tile must fit the y~ region");
     static_assert(16 * T * 3 * P == NLD * kBlock, "tile elements split evenly");
     static_assert(16 * T <= kBlock, "one thread per atom of the block tile");
 };
@@ -82,9 +86,8 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const int lr = l & 15, lq = l >> 4;
     const int tt = w / NMB;           // this wave's atom tile within the block
     const int mb = w - tt * NMB;      // this wave's mode block (and bead block)
-    double *sX = smem + tt * L::TILE;             // [16][XS] x, then y~ [3][16][PS]
-    double *sY = sX;
-    double *sF = sX + L::XY_ELEMS;                // [16][XS]: f
+    double *sY = smem + tt * L::TILE;             // y~ [3][16][PS]: carried, then new
+    double *sF = sY + L::XY_ELEMS;                // [16][XS]: f
     double *sA = sF + L::F_ELEMS;                 // [16][AW]: atom table
     double *sC = sA + L::AT_ELEMS;                // [16][4]: centroids
     // B operands: forward M^T[4kb + lq][mb*16 + lr], inverse M[4kb + lq][mb*16 + lr];
@@ -115,15 +118,17 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         const int nel = nat * 3 * P;
         const int a0 = b0 + tt * 16;                   // first atom of this wave's tile
 
-        // ---- all global reads of the tile, in flight together
-        double rx[NLD], rf[NLD];
+        // ---- all global reads of the tile, in flight together: the carried
+        // normal-mode positions y~ and the forces (coalesced tile copies),
+        // this lane's v~, the per-atom table and each atom's bead-0 position
+        double ry[NLD], rf[NLD];
         {
-            const double *xg = a.x + (size_t)b0 * 3 * P;
+            const double *yg = a.yt + (size_t)b0 * 3 * P;
             const double *fg = a.f + (size_t)b0 * 3 * P;
 #pragma unroll
             for (int q = 0; q < NLD; ++q) {
                 const int e = t + q * kBlock;
-                rx[q] = e < nel ? xg[e] : 0.0;
+                ry[q] = e < nel ? yg[e] : 0.0;
                 rf[q] = (need_f && e < nel) ? fg[e] : 0.0;
             }
         }
@@ -135,14 +140,17 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 #pragma unroll
             for (int d = 0; d < 3; ++d) rv[r][d] = ia < N ? a.v[vb + d * P] : 0.0;
         }
-        double ratom[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double ratom[11] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (t < nat) {
             const int ia = b0 + t;
 #pragma unroll
             for (int q = 0; q < 4; ++q) ratom[q] = a.atoms[ia * 4 + q];
             ratom[4] = (double)a.orig[ia];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ratom[5 + d] = a.cref[ia * 3 + d];
+            for (int d = 0; d < 3; ++d) {
+                ratom[5 + d] = a.cref[ia * 3 + d];
+                ratom[8 + d] = a.x[(size_t)ia * 3 * P + d * P];
+            }
         }
 
         __syncthreads();                               // previous tile's LDS use is done
@@ -150,11 +158,10 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         for (int q = 0; q < NLD; ++q) {
             const int e = t + q * kBlock;
             const int at = e / (3 * P), rr = e - at * (3 * P);
-            double *dst = smem + (at >> 4) * L::TILE + (at & 15) * XS + rr;
-            dst[0] = rx[q];
-            dst[L::XY_ELEMS] = rf[q];
-            if (rr % P == 0) smem[(at >> 4) * L::TILE + L::XY_ELEMS + L::F_ELEMS +
-                                 (at & 15) * AW + TA_X0 + rr / P] = rx[q];
+            const int d = rr / P, mm = rr - d * P;
+            double *tile = smem + (at >> 4) * L::TILE;
+            tile[(d * 16 + (at & 15)) * PS + mm] = ry[q];              // y~ [d][atom][mode]
+            tile[L::XY_ELEMS + (at & 15) * XS + rr] = rf[q];           // f [atom][d*P + bead]
         }
         if (t < 16 * T) {
             double *ar = smem + (t >> 4) * L::TILE + L::XY_ELEMS + L::F_ELEMS + (t & 15) * AW;
@@ -164,35 +171,32 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             ar[TA_ACT] = ratom[AT_ACTIVE];
             ar[TA_ORIG] = ratom[4];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ar[TA_CREF + d] = ratom[5 + d];
+            for (int d = 0; d < 3; ++d) {
+                ar[TA_CREF + d] = ratom[5 + d];
+                ar[TA_X0 + d] = ratom[8 + d];
+            }
         }
         __syncthreads();
 
-        // ---- forward products: y~ and f~ of mode block mb for the tile's 16 atoms
+        // ---- forward products: f~ of mode block mb for the tile's 16 atoms
+        // (the positions' modes are carried from the previous step)
         const bool ok_op = (a0 + lr) < N;
-        d4 ay[3], af[3];
+        d4 af[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            ay[d] = d4{0.0, 0.0, 0.0, 0.0};
-            af[d] = d4{0.0, 0.0, 0.0, 0.0};
-        }
-        const double *xr = sX + lr * XS;
-        const double *fr = sF + lr * XS;
+        for (int d = 0; d < 3; ++d) af[d] = d4{0.0, 0.0, 0.0, 0.0};
+        if (need_f) {
+            const double *fr = sF + lr * XS;
 #pragma unroll 4
-        for (int kb = 0; kb < NK4; ++kb) {
-            const int bead = 4 * kb + lq;
-            const double bm = bmT[4 * kb * P];
+            for (int kb = 0; kb < NK4; ++kb) {
+                const int bead = 4 * kb + lq;
+                const double bm = bmT[4 * kb * P];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double xv = ok_op ? xr[d * P + bead] - xr[d * P] : 0.0;
-                ay[d] = mfma4(xv, bm, ay[d]);
-                if (need_f) {
+                for (int d = 0; d < 3; ++d) {
                     const double fv = ok_op ? fr[d * P + bead] : 0.0;
                     af[d] = mfma4(fv, bm, af[d]);
                 }
             }
         }
-        __syncthreads();   // every wave is done with the x tile before y~ replaces it
 
         // ---- per (atom, mode) update: lane l, register r: atom a0 + 4r + lq, mode m
 #pragma unroll
@@ -205,7 +209,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             double xt[3], ft[3], vt[3], x0[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                xt[d] = ay[d][r];
+                xt[d] = sY[(d * 16 + ra) * PS + m];
                 ft[d] = af[d][r];
                 x0[d] = ar[TA_X0 + d];
                 vt[d] = rv[r][d];
@@ -264,6 +268,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             for (int d = 0; d < 3; ++d) {
                 if (!isfinite(vt[d])) acc_bad = 1.0;
                 sY[(d * 16 + ra) * PS + m] = xt[d];
+                // carried to the next step; the centroid mode is re-referenced
+                // to the new bead 0 after the inverse
+                if (m != 0) a.yt[vb + d * P] = xt[d];
             }
             if (m == 0) {
                 double d2 = 0.0, c[3];
@@ -310,6 +317,13 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 if (!isfinite(xj)) acc_bad = 1.0;
             }
             if (ar[TA_ACT] != 0.0) acc_emax = fmax(acc_emax, e2);
+            if (bead == 0) {
+                // the next step's reference is this step's new bead 0: only the
+                // centroid mode changes, by -sqrt(P) times the bead's offset
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    a.yt[xb + d * P] = sY[(d * 16 + ra) * PS] - sqrtP * ax[d][r];
+            }
         }
     }
 

@@ -79,6 +79,7 @@ struct FusedArgs {
     double temp_norm;         // 2 / (3 N P^2 kB)
     unsigned long long seed;
     double *x;                // [N][3][P] Cartesian, unwrapped
+    double *yt;               // [N][3][P] y~ = M (x - x_bead0): the positions' modes, carried
     double *v;                // [N][3][P] normal-mode velocities
     const double *f;          // [N][3][P] Cartesian forces (pair) or nullptr
     const double *vin;        // PREP: [N][3][P] Cartesian velocities

@@ -62,6 +62,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     const bool est_now = closing || mode == FUSED_EST;          // estimators of this state
     const bool need_f = a.pair && (mode == FUSED_STEP || est_now);
     const bool inverse = (mode == FUSED_STEP);
+    const bool carry = (mode == FUSED_STEP);     // positions' modes carried in yt
     const double sqrtP = sqrt((double)P);
 
     const int la = t / P, k = t - (t / P) * P;
@@ -85,6 +86,9 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         // that frees the previous tile's LDS: the x tile and the f (or PREP's
         // v) tile, 3 doubles each per thread (A*3P <= 3*256), this lane's v~
         // and per-atom constants.
+        // The step pass reads the positions' modes carried from the previous
+        // step (y~ relative to bead 0) and each atom's bead-0 position instead
+        // of the x tile.
         constexpr int NL = 3;
         const double *xg = a.x + (size_t)a0 * 3 * P;
         const double *fg = need_f ? a.f + (size_t)a0 * 3 * P
@@ -93,11 +97,11 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int e = t + q * kBlock;
-            rx[q] = e < nel ? xg[e] : 0.0;
+            rx[q] = (!carry && e < nel) ? xg[e] : 0.0;
             rf[q] = (fg && e < nel) ? fg[e] : 0.0;
         }
         double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0;
-        double vpre[3] = {0.0, 0.0, 0.0};
+        double vpre[3] = {0.0, 0.0, 0.0}, ypre[3] = {0.0, 0.0, 0.0}, xref[3] = {0.0, 0.0, 0.0};
         unsigned long long oi = 0;
         if (act) {
             hm = a.atoms[i * 4 + AT_HALF_M];
@@ -105,9 +109,14 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             sg = a.atoms[i * 4 + AT_SIGMA];
             active = a.atoms[i * 4 + AT_ACTIVE];
             oi = (unsigned long long)a.orig[i];
+            const size_t vb = (size_t)i * 3 * P + k;
             if (mode != FUSED_PREP) {
-                const size_t vb = (size_t)i * 3 * P + k;
                 vpre[0] = a.v[vb]; vpre[1] = a.v[vb + P]; vpre[2] = a.v[vb + 2 * P];
+            }
+            if (carry) {
+                ypre[0] = a.yt[vb]; ypre[1] = a.yt[vb + P]; ypre[2] = a.yt[vb + 2 * P];
+                const size_t xb0 = (size_t)i * 3 * P;
+                xref[0] = a.x[xb0]; xref[1] = a.x[xb0 + P]; xref[2] = a.x[xb0 + 2 * P];
             }
         }
         __syncthreads();
@@ -115,7 +124,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         for (int q = 0; q < NL; ++q) {
             const int e = t + q * kBlock;
             if (e < nel) {
-                sX[e] = rx[q];
+                if (!carry) sX[e] = rx[q];
                 if (fg) sF[e] = rf[q];
             }
         }
@@ -133,20 +142,40 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             const double *xr = sX + la * 3 * P;
             const double *fr = sF + la * 3 * P;
             const bool tf = need_f || mode == FUSED_PREP;
-            const double r0 = xr[0], r1 = xr[P], r2 = xr[2 * P];
-            for (int j = 0; j < P; ++j) {
-                const double m = sMT[j * PS + k];
-                xt[0] += m * (xr[j] - r0);
-                xt[1] += m * (xr[P + j] - r1);
-                xt[2] += m * (xr[2 * P + j] - r2);
-                if (tf) {
-                    ft[0] += m * fr[j];
-                    ft[1] += m * fr[P + j];
-                    ft[2] += m * fr[2 * P + j];
+            if (carry) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    xt[d] = ypre[d];
+                    ref[d] = xref[d];
                 }
+                if (tf) {
+                    for (int j = 0; j < P; ++j) {
+                        const double m = sMT[j * PS + k];
+                        ft[0] += m * fr[j];
+                        ft[1] += m * fr[P + j];
+                        ft[2] += m * fr[2 * P + j];
+                    }
+                }
+            } else {
+                const double r0 = xr[0], r1 = xr[P], r2 = xr[2 * P];
+                for (int j = 0; j < P; ++j) {
+                    const double m = sMT[j * PS + k];
+                    xt[0] += m * (xr[j] - r0);
+                    xt[1] += m * (xr[P + j] - r1);
+                    xt[2] += m * (xr[2 * P + j] - r2);
+                    if (tf) {
+                        ft[0] += m * fr[j];
+                        ft[1] += m * fr[P + j];
+                        ft[2] += m * fr[2 * P + j];
+                    }
+                }
+                ref[0] = r0; ref[1] = r1; ref[2] = r2;
             }
-            ref[0] = r0; ref[1] = r1; ref[2] = r2;
             const size_t vb = (size_t)i * 3 * P + k;
+            if (mode == FUSED_PREP) {
+                // the carried modes of the positions, relative to bead 0
+                a.yt[vb] = xt[0]; a.yt[vb + P] = xt[1]; a.yt[vb + 2 * P] = xt[2];
+            }
             if (mode == FUSED_PREP) {
                 vt[0] = ft[0]; vt[1] = ft[1]; vt[2] = ft[2];
                 ft[0] = ft[1] = ft[2] = 0.0;
@@ -231,8 +260,14 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         if (mode == FUSED_STEP) {
             __syncthreads();   // all reads of sX done
             if (act) {
+                const size_t yb = (size_t)i * 3 * P + k;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) sX[(la * 3 + d) * P + k] = xt[d];
+                for (int d = 0; d < 3; ++d) {
+                    sX[(la * 3 + d) * P + k] = xt[d];
+                    // carried to the next step; the centroid mode is
+                    // re-referenced to the new bead 0 after the inverse
+                    if (k != 0) a.yt[yb + d * P] = xt[d];
+                }
                 if (k == 0) {
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
@@ -258,9 +293,16 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                         xj[1] += w * xr[P + m];
                         xj[2] += w * xr[2 * P + m];
                     }
+                    const size_t xb = (size_t)i * 3 * P + j;
+                    if (j == 0) {
+                        // the next step's reference is the new bead 0: only the
+                        // centroid mode changes, by -sqrt(P) times its offset
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            a.yt[xb + d * P] = sX[(la * 3 + d) * P] - sqrtP * xj[d];
+                    }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) xj[d] += sR[la * 3 + d];
-                    const size_t xb = (size_t)i * 3 * P + j;
                     a.x[xb] = xj[0]; a.x[xb + P] = xj[1]; a.x[xb + 2 * P] = xj[2];
                 } else {
 #pragma unroll
