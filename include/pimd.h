@@ -93,10 +93,18 @@ typedef struct pimd_params {
  *                               (with both set, VALU wins)
  *   PIMD_PAIR_SUBGROUPS(S)      S = 1, 2, 4, 8 or 16 sub-groups of P lanes
  *                               per atom in the force pass (S*P <= 256)
+ *   PIMD_FLAG_CLUSTER_PAIRS     force pass on cluster lists: the 256/P
+ *                               consecutive atoms of a block share one list,
+ *                               and each neighbor's bead rows are staged once
+ *                               per block (P >= 8; blocks whose cluster is too
+ *                               wide for the box fall back to per-atom lists)
+ *   PIMD_FLAG_ATOM_PAIRS        force pass on per-atom lists only
  * Results do not depend on the launch shape beyond the rounding of the
  * transforms (MFMA and VALU sum in different orders). */
 #define PIMD_FLAG_VALU_TRANSFORMS 1
 #define PIMD_FLAG_MFMA_TRANSFORMS 2
+#define PIMD_FLAG_CLUSTER_PAIRS 4
+#define PIMD_FLAG_ATOM_PAIRS 8
 #define PIMD_PAIR_SUBGROUPS_SHIFT 8
 #define PIMD_PAIR_SUBGROUPS_MASK (0xF << PIMD_PAIR_SUBGROUPS_SHIFT)
 #define PIMD_PAIR_SUBGROUPS(S)                                                   \
@@ -214,13 +222,15 @@ int pimd_profile_end(pimd_ctx *ctx, pimd_profile *out);
  * matrix cores, 0 = FP64 vector ALUs in the step pass; fused_blocks: blocks
  * of the step pass; pair_subgroups, pair_blocks: lane sub-groups per atom and
  * blocks of the force pass (0 without pair forces); cells: centroid cells of
- * the list build (0 = all-pairs scan).  Errors: ARG. */
+ * the list build (0 = all-pairs scan); cluster_pairs: 1 when the force pass
+ * runs on cluster lists.  Errors: ARG. */
 typedef struct pimd_launch_info {
     int32_t transforms;
     int32_t fused_blocks;
     int32_t pair_subgroups;
     int32_t pair_blocks;
     int32_t cells;
+    int32_t cluster_pairs;
 } pimd_launch_info;
 int pimd_get_launch_info(const pimd_ctx *ctx, pimd_launch_info *out);
 

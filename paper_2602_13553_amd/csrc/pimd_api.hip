@@ -29,6 +29,9 @@ struct Layout {
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
     int valu_tiles, mfma_tiles;
     int ncell, cell_cap, nc[3];   // centroid cells (ncell = 0: none)
+    bool clusters;                // force pass on cluster lists
+    int n_clusters;
+    size_t clist, ccount, cframe, cmode;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -98,7 +101,8 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
         return PIMD_ERR_UNSUPPORTED;
     }
     {
-        const int known = PIMD_FLAG_VALU_TRANSFORMS | PIMD_FLAG_MFMA_TRANSFORMS | PIMD_PAIR_SUBGROUPS_MASK;
+        const int known = PIMD_FLAG_VALU_TRANSFORMS | PIMD_FLAG_MFMA_TRANSFORMS | PIMD_PAIR_SUBGROUPS_MASK |
+                          PIMD_FLAG_CLUSTER_PAIRS | PIMD_FLAG_ATOM_PAIRS;
         const int code = (p->flags & PIMD_PAIR_SUBGROUPS_MASK) >> PIMD_PAIR_SUBGROUPS_SHIFT;
         if (p->flags & ~known) { why = "unknown bits in flags"; return PIMD_ERR_ARG; }
         if (code > 5 || (code > 0 && (1 << (code - 1)) * p->n_beads > kBlock)) {
@@ -230,6 +234,22 @@ bool use_mfma(const pimd_params *p)
     return (long long)p->n_atoms * P >= tuning::kMfmaMinBeadAtoms[row];
 }
 
+// Cluster lists in the force pass: the flags, else the tuning table.  They
+// need a cluster of at most 32 atoms (P >= 8) and LJ-active atoms.
+bool use_clusters(const pimd_params *p, int n_active)
+{
+    const int P = p->n_beads, N = p->n_atoms;
+    if (!is_pair(p->potential) || n_active == 0 || P < 8 || kBlock / P > 32) return false;
+    if (p->flags & PIMD_FLAG_ATOM_PAIRS) return false;
+    if (p->flags & PIMD_FLAG_CLUSTER_PAIRS) return true;
+    const int row = P == 8 ? 0 : P == 16 ? 1 : P == 32 ? 2 : P == 64 ? 3 : -1;
+    if (row < 0) return false;
+    int lg = 0;
+    while ((2 << lg) <= N) ++lg;
+    const int col = std::min(std::max(lg - 6, 0), 9);
+    return tuning::kClusterPairs[row][col] != 0;
+}
+
 // Lane sub-groups per atom in the force pass: the flags, else the tuning
 // table, else the occupancy heuristic.
 int choose_pair_subgroups(const pimd_params *p)
@@ -259,7 +279,8 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.n_active = n_active;
     L.fused_grid = fused_grid(p->n_atoms, p->n_beads);
     L.mfma_grid = use_mfma(p) ? fused_mfma_grid(p->n_atoms, p->n_beads) : 0;
-    L.pair_S = pair ? choose_pair_subgroups(p) : 1;
+    L.clusters = pair && use_clusters(p, n_active);
+    L.pair_S = pair ? (L.clusters ? 1 : choose_pair_subgroups(p)) : 1;
     L.pair_grid = pair ? pair_grid(p->n_atoms, p->n_beads, L.pair_S) : 0;
     L.pair_active_tiles = pair ? pair_active_tiles(n_active, p->n_beads, L.pair_S) : 0;
     size_t o = 0;
@@ -291,6 +312,11 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.cell_ent = take((size_t)L.ncell * L.cell_cap * sizeof(CellEntry));
     L.cell_scnt = take((size_t)L.ncell * sizeof(int));
     L.cinfo = take(L.ncell ? N * sizeof(int4) : 0);
+    L.n_clusters = L.clusters ? (n_active + (kBlock / p->n_beads) - 1) / (kBlock / p->n_beads) : 0;
+    L.clist = take((size_t)L.n_clusters * kClusterMax * sizeof(int4));
+    L.ccount = take((size_t)L.n_clusters * sizeof(int));
+    L.cframe = take(L.clusters ? (size_t)n_active * sizeof(int) : 0);
+    L.cmode = take((size_t)L.n_clusters * sizeof(int));
     L.total = o;
     return L;
 }
@@ -548,6 +574,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         e = hipMemset(w + L.cell_scnt, 0, (size_t)L.ncell * sizeof(int));
     if (e != hipSuccess) return cleanup(PIMD_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
 
+    if (L.n_clusters) set_pair_smem();
     FusedArgs &a = c->fa;
     a.N = N; a.P = P; a.n_active = n_active;
     a.mode = FUSED_STEP;
@@ -601,6 +628,12 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     for (int d = 0; d < 3; ++d) q.nc[d] = L.nc[d];
     q.cell_cap = L.cell_cap;
     q.cell_ent = a.cell_ent;
+    q.n_clusters = L.n_clusters;
+    q.ccap = kClusterMax;
+    q.clist = L.n_clusters ? (int4 *)(w + L.clist) : nullptr;
+    q.ccount = L.n_clusters ? (int *)(w + L.ccount) : nullptr;
+    q.cframe = L.n_clusters ? (int *)(w + L.cframe) : nullptr;
+    q.cmode = L.n_clusters ? (int *)(w + L.cmode) : nullptr;
     q.cell_scnt = a.cell_scnt;
     q.cinfo = a.cinfo;
 
@@ -685,6 +718,7 @@ int pimd_get_launch_info(const pimd_ctx *c, pimd_launch_info *out)
     out->pair_subgroups = c->fa.pair ? L.pair_S : 0;
     out->pair_blocks = c->fa.pair ? L.pair_grid : 0;
     out->cells = L.ncell;
+    out->cluster_pairs = L.n_clusters > 0 ? 1 : 0;
     return PIMD_OK;
 }
 
@@ -816,6 +850,7 @@ struct pimd_batch {
     std::vector<Group> step_groups;
     int pair_off = 0, pair_n = 0, close_off = 0, close_n = 0, n_sys_plan = 0;
     int smem_valu = 0;   // dynamic LDS of the batched vector-ALU pass: max over its systems
+    bool pair_clusters = false;   // some system's force pass uses cluster lists
     int ncu = 256;
     bool dirty = true;
     hipGraph_t graph = nullptr;
@@ -920,10 +955,12 @@ int rebuild_plan(pimd_batch *b)
         if (g.n) b->step_groups.push_back(g);
     }
     b->pair_off = (int)items.size();
+    b->pair_clusters = false;
     for (int s = 0; s < n; ++s) {
         pimd_ctx *c = b->sys[s];
         if (!c || !b->active[s] || !c->fa.pair) continue;
         for (int t = 0; t < c->lay.pair_grid; ++t) items.push_back(make_int2(s, t));
+        if (c->lay.n_clusters) b->pair_clusters = true;
     }
     b->pair_n = (int)items.size() - b->pair_off;
     b->close_off = (int)items.size();
@@ -976,7 +1013,7 @@ void enqueue_batch_step(pimd_batch *b)
     launch_finalize_batch(b->d_fa, b->d_nparts, b->n_sys_plan, FUSED_STEP, b->stream);
     if (b->pair_n)
         launch_pair_batch(b->d_pa, b->d_items + b->pair_off, b->pair_n, std::min(b->pair_n, 8 * ncu),
-                          b->stream);
+                          b->pair_clusters, b->stream);
 }
 
 }  // namespace

@@ -21,6 +21,9 @@ constexpr int kMaxBonds = 4;     // bonds per atom
 constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
 constexpr int kSortBuf = 4096;   // ints of LDS for sorting the centroid cells
 constexpr int kMaxCells = 4096;  // centroid cells per system, at most (LDS histogram)
+constexpr int kClusterMax = 512;         // union-list entries per force-pass cluster (LDS)
+constexpr int kClusterRows = 1536;       // doubles per staged chunk of neighbor bead rows
+constexpr int kClusterSmem = 8 * 2 * kClusterRows + 16 * kClusterMax;   // dynamic LDS bytes
 
 // Per-block partial slots written by the fused kernel.
 enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_PAD, PF_COUNT };
@@ -131,6 +134,14 @@ struct PairArgs {
     const CellEntry *cell_ent;
     const int *cell_scnt;
     const int4 *cinfo;
+    // cluster lists (n_clusters = 0: per-atom lists only).  Block b of the
+    // force pass takes the kBlock/P consecutive atoms b*A ...; its active atoms
+    // share one list of neighbors j with a mask of the atoms that use each.
+    int n_clusters, ccap;
+    int4 *clist;              // [n_clusters][ccap] (3P j, packed shift, atom mask, 0)
+    int *ccount;              // [n_clusters]
+    int *cframe;              // [n_active] packed box offset of each atom in its cluster's frame
+    int *cmode;               // [n_clusters] 0: cluster list, 1: per-atom lists (fallback)
 };
 
 // Launchers (pimd_kernels.hip).
@@ -151,8 +162,9 @@ void launch_fused_batch(const FusedArgs *table, const int2 *items, int n_items, 
 void set_batch_smem(int smem_bytes);
 void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys, int mode,
                            hipStream_t s);
+void set_pair_smem();
 void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
-                       hipStream_t s);
+                       bool clusters, hipStream_t s);
 int pair_subgroups(int N, int P);
 int pair_grid(int N, int P, int S);
 int pair_active_tiles(int n_active, int P, int S);

@@ -1018,16 +1018,232 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     if (t == 0) a.fpartials[tile] = e1[0];
 }
 
+// --------------------------------------------------------------------------
+// Cluster-pair force pass (a6).  Block b takes the A = kBlock/P consecutive
+// atoms b*A ... (thread = atom, bead); its LJ-active atoms share one neighbor
+// list (the union of their lists) with, per entry, a mask of the atoms that
+// use it, built at list rebuilds in index order.  Each neighbor's P bead rows
+// are staged in LDS once per block (double-buffered chunks) and read by every
+// atom of the block that has it as a neighbor, instead of one gather per atom.
+// Every pair of the block is taken in one frame: atom q's centroid is moved by
+// whole boxes u_q next to atom 0's, and each entry carries the image of j
+// nearest to atom 0.  That image is the pair's minimum image whenever
+// r_list + (cluster radius) < L/2, which the build checks; a block where it
+// fails (or whose list would overflow its LDS) uses the per-atom lists.
+// --------------------------------------------------------------------------
+
+__device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt, double *red,
+                             double *s_f)
+{
+    const int P = a.P, A = kBlock / P, P3 = 3 * P;
+    const int t = threadIdx.x;
+    const int la = t / P, k = t - la * P;
+    const int i0 = b * A;
+    const int i = i0 + la;
+    const bool act = (la < A) && (i < a.N);
+    const int na = min(A, a.n_active - i0);             // LJ-active atoms of the block (> 0)
+    const bool lj = act && la < na;
+    const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
+    if (!a.ctl->ran) return;
+
+    // per-atom fallback, decided at the last rebuild (uniform per block)
+    PairArgs a1 = a;
+    a1.S = 1;
+    const bool rebuild = a.ctl->rebuild != 0;
+    double *sCp = smem;                                   // [A][3] frame centroids
+    int4 *sEnt = reinterpret_cast<int4 *>(smem + 2 * kClusterRows);
+    if (rebuild) {
+        const double rl = a.ctl->rlist;
+        const double rl2 = rl * rl;
+        // frame: centroids of the block's active atoms moved next to atom 0's
+        if (t < na) {
+            const double c0x = a.cent[i0 * 3], c0y = a.cent[i0 * 3 + 1], c0z = a.cent[i0 * 3 + 2];
+            const double cx = a.cent[(i0 + t) * 3], cy = a.cent[(i0 + t) * 3 + 1],
+                         cz = a.cent[(i0 + t) * 3 + 2];
+            const double ux = -rint((cx - c0x) / L0), uy = -rint((cy - c0y) / L1),
+                         uz = -rint((cz - c0z) / L2);
+            sCp[t * 3] = cx + ux * L0;
+            sCp[t * 3 + 1] = cy + uy * L1;
+            sCp[t * 3 + 2] = cz + uz * L2;
+            const bool uok = fabs(ux) < 500.0 && fabs(uy) < 500.0 && fabs(uz) < 500.0;
+            a.cframe[i0 + t] = uok ? pack_shift((int)ux, (int)uy, (int)uz) : pack_shift(0, 0, 0);
+            s_cnt[t] = uok ? 0 : 1;
+        }
+        __syncthreads();
+        int ok = 1;
+        {
+            double r2max = 0.0;
+            for (int q = 0; q < na; ++q) {
+                const double dx = sCp[q * 3] - sCp[0], dy = sCp[q * 3 + 1] - sCp[1],
+                             dz = sCp[q * 3 + 2] - sCp[2];
+                r2max = fmax(r2max, dx * dx + dy * dy + dz * dz);
+                if (s_cnt[q]) ok = 0;
+            }
+            const double lmin = fmin(L0, fmin(L1, L2));
+            if (!(isfinite(rl) && rl > 0.0 && rl + sqrt(r2max) < 0.5 * lmin)) ok = 0;
+        }
+        __syncthreads();
+        int total = 0;
+        if (ok) {
+            int4 *cl = a.clist + (size_t)b * a.ccap;
+            const double c0x = sCp[0], c0y = sCp[1], c0z = sCp[2];
+            const int w = t >> 6, lane = t & 63;
+            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            for (int j0 = 0; j0 < a.n_active; j0 += kBlock) {
+                const int j = j0 + t;
+                int mask = 0, sx = 0, sy = 0, sz = 0;
+                if (j < a.n_active) {
+                    const double cx = a.cent[j * 3], cy = a.cent[j * 3 + 1], cz = a.cent[j * 3 + 2];
+                    const double fx = -rint((c0x - cx) / L0), fy = -rint((c0y - cy) / L1),
+                                 fz = -rint((c0z - cz) / L2);
+                    if (fabs(fx) < 500.0 && fabs(fy) < 500.0 && fabs(fz) < 500.0) {
+                        sx = (int)fx; sy = (int)fy; sz = (int)fz;
+                        const double jx = cx - sx * L0, jy = cy - sy * L1, jz = cz - sz * L2;
+                        for (int q = 0; q < na; ++q) {
+                            if (j == i0 + q) continue;
+                            const double ex = sCp[q * 3] - jx, ey = sCp[q * 3 + 1] - jy,
+                                         ez = sCp[q * 3 + 2] - jz;
+                            if (ex * ex + ey * ey + ez * ez < rl2) mask |= 1 << q;
+                        }
+                    }
+                }
+                // place the hits in index order: wave ballots, then wave offsets
+                const unsigned long long hit = __ballot(mask != 0);
+                if (lane == 0) s_cnt[w] = __popcll(hit);
+                __syncthreads();
+                int off = total;
+                for (int u = 0; u < w; ++u) off += s_cnt[u];
+                int chunk = 0;
+                for (int u = 0; u < kBlock / 64; ++u) chunk += s_cnt[u];
+                if (mask != 0) {
+                    const int wpos = off + __popcll(hit & below);
+                    if (wpos < a.ccap) cl[wpos] = make_int4(j * P3, pack_shift(sx, sy, sz), mask, 0);
+                }
+                total += chunk;
+                __syncthreads();
+            }
+            if (total > a.ccap || total > kClusterMax) ok = 0;
+        }
+        if (t == 0) {
+            a.cmode[b] = ok ? 0 : 1;
+            a.ccount[b] = ok ? total : 0;
+        }
+        if (ok && act) {
+            a.cref[i * 3] = a.cent[i * 3];
+            a.cref[i * 3 + 1] = a.cent[i * 3 + 1];
+            a.cref[i * 3 + 2] = a.cent[i * 3 + 2];
+        }
+        if (!ok) {
+            // the per-atom path of this block rebuilds its own lists
+            __syncthreads();
+            pair_tile(a1, b, s_cnt, red, s_f);
+            return;
+        }
+        __threadfence_block();
+        __syncthreads();
+    } else if (a.cmode[b] != 0) {
+        pair_tile(a1, b, s_cnt, red, s_f);
+        return;
+    }
+
+    // ---- forces
+    const double *__restrict__ X = a.x;
+    const int n = a.ccount[b];
+    for (int q = t; q < n; q += kBlock) sEnt[q] = a.clist[(size_t)b * a.ccap + q];
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    const size_t ib = (size_t)i * P3 + k;
+    if (act) {
+        xi = X[ib]; yi = X[ib + P]; zi = X[ib + 2 * P];
+    }
+    double xf = xi, yf = yi, zf = zi;                    // in the cluster's frame
+    if (lj) {
+        double ux, uy, uz;
+        unpack_shift(a.cframe[i], ux, uy, uz);
+        xf += ux * L0; yf += uy * L1; zf += uz * L2;
+    }
+    const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
+    const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
+    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    const int CH = kClusterRows / P3;                    // rows per chunk
+    const int nch = (n + CH - 1) / CH;
+    constexpr int NR = kClusterRows / kBlock;             // staged doubles per thread
+    double rr[NR];
+    __syncthreads();                                      // the entries are in LDS
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            const int q = t + v * kBlock;
+            const int u = q / P3, r = q - u * P3;
+            const int e_ = c * CH + u;
+            rr[v] = (u < CH && e_ < n) ? X[sEnt[e_].x + r] : 0.0;
+        }
+    };
+    auto stage = [&](int c) {
+        double *buf = smem + (c & 1) * kClusterRows;
+#pragma unroll
+        for (int v = 0; v < NR; ++v) buf[t + v * kBlock] = rr[v];
+    };
+    if (nch > 0) {
+        fetch(0);
+        stage(0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        if (c + 1 < nch) fetch(c + 1);
+        const double *buf = smem + (c & 1) * kClusterRows;
+        const int nu = min(CH, n - c * CH);
+        if (lj) {
+            for (int u = 0; u < nu; ++u) {
+                const int4 en = sEnt[c * CH + u];
+                if ((en.z >> la) & 1) {
+                    const double *row = buf + u * P3;
+                    double sx, sy, sz;
+                    unpack_shift(en.y, sx, sy, sz);
+                    lj_accumulate(xf - row[k] + sx * L0, yf - row[P + k] + sy * L1,
+                                  zf - row[2 * P + k] + sz * L2, rc2, sig2, eps4, eps24, ush,
+                                  fx, fy, fz, e);
+                }
+            }
+        }
+        if (c + 1 < nch) stage(c + 1);
+        __syncthreads();
+    }
+    if (act) {
+        for (int bb = 0; bb < kMaxBonds; ++bb) {
+            const int j = a.bond_j[i * kMaxBonds + bb];
+            if (j < 0) break;
+            const size_t jb = (size_t)j * P3 + k;
+            double dx = xi - X[jb], dy = yi - X[jb + P], dz = zi - X[jb + 2 * P];
+            dx -= L0 * rint(dx / L0);
+            dy -= L1 * rint(dy / L1);
+            dz -= L2 * rint(dz / L2);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double dr = r - a.bond_r0;
+            const double fr = -2.0 * a.bond_k * dr / r;
+            e += 0.5 * a.bond_k * dr * dr;
+            fx += fr * dx; fy += fr * dy; fz += fr * dz;
+        }
+        a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
+    }
+    double e1[1] = {e};
+    block_sum<1>(e1, red);
+    if (t == 0) a.fpartials[b] = e1[0];
+}
+
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
 {
     __shared__ int s_cnt[kBlock];
     __shared__ double red[64];
     __shared__ double s_f[kBlock * 3];
+    extern __shared__ double s_dyn[];
     // Tiles holding LJ-active atoms come first.  Each of the two tile ranges
     // is laid out contiguously per XCD, so both are spread over all XCDs.
     const int b = blockIdx.x, nA = a.n_active_tiles;
     const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
-    pair_tile(a, tile, s_cnt, red, s_f);
+    if (tile < a.n_clusters)
+        cluster_tile(a, tile, s_dyn, s_cnt, red, s_f);
+    else
+        pair_tile(a, tile, s_cnt, red, s_f);
 }
 
 // Batched: one (system, tile) item per block iteration.
@@ -1037,10 +1253,15 @@ __global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *table, co
     __shared__ int s_cnt[kBlock];
     __shared__ double red[64];
     __shared__ double s_f[kBlock * 3];
+    extern __shared__ double s_dyn[];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
         const PairArgs a = table[item.x];
-        pair_tile(a, item.y, s_cnt, red, s_f);
+        if (item.y < a.n_clusters)
+            cluster_tile(a, item.y, s_dyn, s_cnt, red, s_f);
+        else
+            pair_tile(a, item.y, s_cnt, red, s_f);
+        __syncthreads();
     }
 }
 
@@ -1085,9 +1306,10 @@ void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys,
 }
 
 void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
-                       hipStream_t s)
+                       bool clusters, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pair_batch, dim3(grid), dim3(kBlock), 0, s, table, items, n_items);
+    hipLaunchKernelGGL(k_pair_batch, dim3(grid), dim3(kBlock), clusters ? kClusterSmem : 0, s, table,
+                       items, n_items);
 }
 
 void set_batch_smem(int smem_bytes)
@@ -1096,9 +1318,18 @@ void set_batch_smem(int smem_bytes)
                               smem_bytes);
 }
 
+// The force pass's cluster path uses kClusterSmem bytes of dynamic LDS.
+void set_pair_smem()
+{
+    (void)hipFuncSetAttribute((const void *)k_pair, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kClusterSmem);
+    (void)hipFuncSetAttribute((const void *)k_pair_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kClusterSmem);
+}
+
 void launch_pair(const PairArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kBlock), a.n_clusters ? kClusterSmem : 0, s, a);
 }
 
 // --------------------------------------------------------------------------

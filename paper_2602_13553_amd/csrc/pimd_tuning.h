@@ -22,5 +22,14 @@ constexpr int kPairSubgroups[4][10] = {
     {4, 4, 4, 4, 4, 2, 4, 2, 1, 1},
 };
 
+// Force pass on cluster lists (1) or per-atom lists (0), same rows and
+// columns as kPairSubgroups.
+constexpr int kClusterPairs[4][10] = {
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+};
+
 }  // namespace tuning
 }  // namespace pimd

@@ -22,6 +22,8 @@ PIMD_NVT, PIMD_NVE = 0, 1
 PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER = 0, 1, 2, 3
 PIMD_FLAG_VALU_TRANSFORMS = 1
 PIMD_FLAG_MFMA_TRANSFORMS = 2
+PIMD_FLAG_CLUSTER_PAIRS = 4
+PIMD_FLAG_ATOM_PAIRS = 8
 PIMD_PAIR_SUBGROUPS_SHIFT = 8
 
 
@@ -74,7 +76,8 @@ class pimd_profile(C.Structure):
 
 class pimd_launch_info(C.Structure):
     _fields_ = [("transforms", C.c_int32), ("fused_blocks", C.c_int32),
-                ("pair_subgroups", C.c_int32), ("pair_blocks", C.c_int32), ("cells", C.c_int32)]
+                ("pair_subgroups", C.c_int32), ("pair_blocks", C.c_int32), ("cells", C.c_int32),
+                ("cluster_pairs", C.c_int32)]
 
 
 _lib = None

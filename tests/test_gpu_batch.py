@@ -59,6 +59,34 @@ def test_batch_equals_solo():
     b.close()
 
 
+def test_batch_equals_solo_cluster_pairs():
+    """Systems whose force pass runs on cluster lists (one falling back to
+    per-atom lists in its small box) next to systems on per-atom lists."""
+    pimd = _pimd()
+    specs = [inputs.lj_liquid(n_atoms=2048, n_beads=32, seed=41),
+             inputs.lj_liquid(n_atoms=256, n_beads=8, seed=42),
+             inputs.water(n_atoms=1536, n_beads=16, seed=43),
+             inputs.lj_liquid(n_atoms=500, n_beads=16, seed=44)]
+    flags = [pimd.PIMD_FLAG_CLUSTER_PAIRS] * 3 + [pimd.PIMD_FLAG_ATOM_PAIRS]
+    b = pimd.Batch()
+    ids = [b.add(s, flags=f) for s, f in zip(specs, flags)]
+    for i, s in zip(ids, specs):
+        b.set_state(i, s.x0, s.v0, 0)
+    b.step(25)
+    for i, s, f in zip(ids, specs, flags):
+        print("batch vs solo", s.name, f, flush=True)
+        c = pimd.Context.from_spec(s, flags=f)
+        c.set_state(s.x0, s.v0, 0)
+        c.step(25)
+        xs, ps, ss = c.get_state()
+        c.close()
+        xb, pb, sb = b.get_state(i)
+        assert sb == ss == 25
+        assert np.array_equal(xb, xs), s.name
+        assert np.array_equal(pb, ps), s.name
+    b.close()
+
+
 def test_batch_budgets_and_membership():
     pimd = _pimd()
     specs = mixed_specs()[:4]

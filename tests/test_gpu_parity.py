@@ -34,11 +34,11 @@ def rel_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def run_pair(spec, nsteps, chunks=None):
+def run_pair(spec, nsteps, chunks=None, flags=0):
     """Run the GPU and the oracle from the spec's state; return both states."""
     pimd = _pimd()
-    _say("case %s nsteps=%d" % (spec.name, nsteps))
-    ctx = pimd.Context.from_spec(spec)
+    _say("case %s nsteps=%d flags=%d" % (spec.name, nsteps, flags))
+    ctx = pimd.Context.from_spec(spec, flags=flags)
     ctx.set_state(spec.x0, spec.v0, 0)
     for c in (chunks or [nsteps]):
         ctx.step(c)
@@ -139,6 +139,45 @@ def test_water_full_size_p64_short():
     spec = inputs.water(n_beads=64)
     g, o = run_pair(spec, 3)
     check_states(g, o)
+
+
+# ------------------------------------------------------------ cluster lists
+@pytest.mark.parametrize("case", ["lj_full", "lj_p16", "lj_small_box", "water_p32", "water_small"])
+def test_cluster_pairs(case):
+    """The force pass on cluster lists (shared neighbor rows staged in LDS),
+    forced by flag, against the oracle.  The small boxes exercise the
+    per-block fallback to per-atom lists (cluster wider than the box allows);
+    the LJ runs span list rebuilds."""
+    pimd = _pimd()
+    spec, n = {
+        "lj_full": (inputs.lj_liquid(), 30),
+        "lj_p16": (inputs.lj_liquid(n_atoms=1372, n_beads=16, seed=21), 40),
+        "lj_small_box": (inputs.lj_liquid(n_atoms=256, n_beads=8, seed=11), 10),
+        "water_p32": (inputs.water(n_beads=32), 10),
+        "water_small": (inputs.water(n_atoms=384, n_beads=8, seed=3), 10),
+    }[case]
+    ctx = pimd.Context.from_spec(spec, flags=pimd.PIMD_FLAG_CLUSTER_PAIRS)
+    assert ctx.launch_info()["cluster_pairs"] == 1
+    ctx.close()
+    g, o = run_pair(spec, n, flags=pimd.PIMD_FLAG_CLUSTER_PAIRS)
+    check_states(g, o)
+    _say("  rebuilds %d" % g[3]["n_rebuilds"])
+
+
+def test_cluster_pairs_match_atom_pairs():
+    """The same LJ state through both force paths: same trajectory to
+    rounding (pair sums in a different order)."""
+    pimd = _pimd()
+    spec = inputs.lj_liquid(n_atoms=2048, n_beads=32, seed=31)
+    out = []
+    for fl in (pimd.PIMD_FLAG_CLUSTER_PAIRS, pimd.PIMD_FLAG_ATOM_PAIRS):
+        ctx = pimd.Context.from_spec(spec, flags=fl)
+        ctx.set_state(spec.x0, spec.v0, 0)
+        ctx.step(20)
+        out.append(ctx.get_state())
+        ctx.close()
+    assert rel_err(out[0][0], out[1][0]) <= TOL
+    assert rel_err(out[0][1], out[1][1]) <= TOL
 
 
 # ------------------------------------------------------------ running sums
