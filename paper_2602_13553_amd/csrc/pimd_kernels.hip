@@ -1235,9 +1235,20 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
     __shared__ int s_cnt[kBlock];
     __shared__ double red[64];
     __shared__ double s_f[kBlock * 3];
-    extern __shared__ double s_dyn[];
     // Tiles holding LJ-active atoms come first.  Each of the two tile ranges
     // is laid out contiguously per XCD, so both are spread over all XCDs.
+    const int b = blockIdx.x, nA = a.n_active_tiles;
+    const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
+    pair_tile(a, tile, s_cnt, red, s_f);
+}
+// The same pass with the active tiles on cluster lists (a kernel of its own,
+// so that the per-atom kernel keeps its register budget).
+__global__ __launch_bounds__(kBlock) void k_pair_clusters(PairArgs a)
+{
+    __shared__ int s_cnt[kBlock];
+    __shared__ double red[64];
+    __shared__ double s_f[kBlock * 3];
+    extern __shared__ double s_dyn[];
     const int b = blockIdx.x, nA = a.n_active_tiles;
     const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
     if (tile < a.n_clusters)
@@ -1321,7 +1332,7 @@ void set_batch_smem(int smem_bytes)
 // The force pass's cluster path uses kClusterSmem bytes of dynamic LDS.
 void set_pair_smem()
 {
-    (void)hipFuncSetAttribute((const void *)k_pair, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_pair_clusters, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kClusterSmem);
     (void)hipFuncSetAttribute((const void *)k_pair_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kClusterSmem);
@@ -1329,7 +1340,10 @@ void set_pair_smem()
 
 void launch_pair(const PairArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kBlock), a.n_clusters ? kClusterSmem : 0, s, a);
+    if (a.n_clusters)
+        hipLaunchKernelGGL(k_pair_clusters, dim3(grid), dim3(kBlock), kClusterSmem, s, a);
+    else
+        hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 // --------------------------------------------------------------------------
