@@ -176,7 +176,8 @@ __device__ inline void block_sum(double (&v)[NV], double *red /* >= NV * kBlock/
 // forms image shifts from integers alone).  A plain store per atom: the cell
 // lists themselves are built by k_finalize, and only at a rebuild.
 // Non-finite centroids land in a clamped (valid) cell; the non-finite flag of
-// the step catches them.
+// the step catches them.  Every atom's (cell, box index) pair places it within
+// rounding of its centroid, which the list build's stencil margin absorbs.
 __device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
 {
     int cc[3], nb[3];
@@ -185,7 +186,8 @@ __device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
         const double L = a.box[d];
         const double fl = floor(c[d] / L);
         const double w = c[d] - L * fl;
-        int q = (w >= 0.0 && w < L) ? (int)(w * a.icw[d]) : 0;
+        // w may round to L itself: the centroid then lies at the top of box fl
+        int q = (w < L) ? (w >= 0.0 ? (int)(w * a.icw[d]) : 0) : a.nc[d] - 1;
         q = q < 0 ? 0 : (q >= a.nc[d] ? a.nc[d] - 1 : q);
         cc[d] = q;
         nb[d] = (fl > -1e6 && fl < 1e6) ? (int)fl : 0;

@@ -9,9 +9,8 @@
 // the centroid mode, by -sqrt(P) times that bead's offset.
 //
 // A block works on T = 64/P tiles of 16 atoms at once.  The f and y~ values of
-// those atoms are loaded into LDS with coalesced reads (f in atom rows padded
-// to 3P+1 doubles, y~ in [dim][atom][mode] rows padded to P+1, which makes the
-// operand reads conflict-free); each tile is shared by P/16 waves, wave w
+// those atoms are loaded into LDS with coalesced reads (f in [atom][3P] rows,
+// y~ in [dim][atom][mode] rows); each tile is shared by P/16 waves, wave w
 // taking mode block (and, in the inverse, bead block) w % (P/16).  Per dim d
 // the wave forms
 //   f~^T[atom][mode] = sum_bead f^T[atom][bead] M^T[bead][mode]
@@ -25,6 +24,15 @@
 // (column l%16 of the wave's mode block), the four atoms 4r + l/16: the
 // per-(atom, mode) work (B, A, O with one Philox call for the three dims, A)
 // runs in registers, and v~ and y~ are read and written as 128-byte segments.
+//
+// LDS bank swizzle.  A 64-bit LDS access of a wave is served in groups of 16
+// or 32 lanes; the banks hold 8-byte words at the word index modulo 16 or 32.
+// The operand reads take lane (i, k) -> row i, column c + k (i < 16, k < 4),
+// the update takes lane (i, k) -> row 4r + k, column c + i.  Column j of row a
+// is stored at j ^ sw(a), sw(a) = (a mod 16) + 16 (a mod 2) when rows are a
+// multiple of 32 words long and sw(a) = a mod 16 when they are 16 modulo 32
+// (the row stride supplies the 16 (a mod 2) then).  Both patterns then hit
+// distinct banks within every group of 16 and of 32 lanes.
 #include "pimd_device.h"
 #include "pimd_internal.h"
 
@@ -45,8 +53,8 @@ template <int P>
 struct Lds {
     static constexpr int NMB = P / 16;            // mode blocks = waves per atom tile
     static constexpr int T = kWaves / NMB;        // atom tiles per block
-    static constexpr int XS = 3 * P + 1;          // padded atom row of a tile
-    static constexpr int PS = P + 1;              // padded row of the y~ staging
+    static constexpr int XS = 3 * P;              // atom row of the f tile
+    static constexpr int PS = P;                  // row of the y~ tile
     static constexpr int XY_ELEMS = 3 * 16 * PS;  // y~ [3][16][PS]
     static constexpr int F_ELEMS = 16 * XS;       // f [16][XS]
     static constexpr int AT_W = 12;               // per-atom row of the atom table
@@ -59,6 +67,14 @@ struct Lds {
     static_assert(16 * T * 3 * P == NLD * kBlock, "tile elements split evenly");
     static_assert(16 * T <= kBlock, "one thread per atom of the block tile");
 };
+
+// column swizzle of row a (a < 16) in a tile whose rows are `row` words long
+template <int row>
+__device__ __forceinline__ int sw(int a)
+{
+    static_assert(row % 32 == 0 || row % 32 == 16, "row length 0 or 16 modulo 32");
+    return (row % 32 == 0) ? ((a & 15) | ((a & 1) << 4)) : (a & 15);
+}
 
 // atom-table columns (per atom of a tile)
 enum { TA_X0 = 0, TA_HM = 3, TA_IM = 4, TA_SG = 5, TA_ACT = 6, TA_ORIG = 7, TA_CREF = 8 };
@@ -103,9 +119,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const bool need_f = a.pair != 0;
     const double sqrtP = sqrt((double)P);
     const int m = mb * 16 + lr;       // this lane's mode
-    double *sMk = smem + T * L::TILE;             // [P][8]: per-mode coefficients
-    for (int e = t; e < 8 * P; e += kBlock) sMk[e] = a.modes[e];
-    const double *mk = sMk + m * 8;
+    double *sMk = smem + T * L::TILE;             // [8][P]: per-mode coefficients
+    for (int e = t; e < 8 * P; e += kBlock) sMk[(e & 7) * P + (e >> 3)] = a.modes[e];
+    const double *mk = sMk + m;                   // coefficient q at mk[q * P]
     const double off = (m == 0) ? sqrtP : 0.0;
 
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
@@ -160,8 +176,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             const int at = e / (3 * P), rr = e - at * (3 * P);
             const int d = rr / P, mm = rr - d * P;
             double *tile = smem + (at >> 4) * L::TILE;
-            tile[(d * 16 + (at & 15)) * PS + mm] = ry[q];              // y~ [d][atom][mode]
-            tile[L::XY_ELEMS + (at & 15) * XS + rr] = rf[q];           // f [atom][d*P + bead]
+            const int a16 = at & 15;
+            tile[(d * 16 + a16) * PS + (mm ^ sw<PS>(a16))] = ry[q];      // y~ [d][atom][mode]
+            tile[L::XY_ELEMS + a16 * XS + (rr ^ sw<XS>(a16))] = rf[q];   // f [atom][d*P + bead]
         }
         if (t < 16 * T) {
             double *ar = smem + (t >> 4) * L::TILE + L::XY_ELEMS + L::F_ELEMS + (t & 15) * AW;
@@ -186,13 +203,14 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         for (int d = 0; d < 3; ++d) af[d] = d4{0.0, 0.0, 0.0, 0.0};
         if (need_f) {
             const double *fr = sF + lr * XS;
+            const int swf = sw<XS>(lr);
 #pragma unroll 4
             for (int kb = 0; kb < NK4; ++kb) {
                 const int bead = 4 * kb + lq;
                 const double bm = bmT[4 * kb * P];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double fv = ok_op ? fr[d * P + bead] : 0.0;
+                    const double fv = ok_op ? fr[(d * P + bead) ^ swf] : 0.0;
                     af[d] = mfma4(fv, bm, af[d]);
                 }
             }
@@ -206,10 +224,11 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             if (ia >= N) continue;
             const double *ar = sA + ra * AW;
             const double hm = ar[TA_HM], im = ar[TA_IM], sg = ar[TA_SG];
+            const int cy = m ^ sw<PS>(ra);
             double xt[3], ft[3], vt[3], x0[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                xt[d] = sY[(d * 16 + ra) * PS + m];
+                xt[d] = sY[(d * 16 + ra) * PS + cy];
                 ft[d] = af[d][r];
                 x0[d] = ar[TA_X0 + d];
                 vt[d] = rv[r][d];
@@ -223,8 +242,8 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 for (int d = 0; d < 3; ++d) {
                     vt[d] += a.hdt * im * ft[d];
                     acc_ekin += hm * vt[d] * vt[d];
-                    acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
-                    acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
+                    acc_esp += hm * mk[MD_SPRING * P] * xt[d] * xt[d];
+                    acc_vir += mk[MD_NONCENTROID * P] * xt[d] * ft[d];
                 }
             }
             // opening B, A(dt/2), O(dt), A(dt/2)
@@ -233,20 +252,20 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double q = xt[d], p = vt[d];
-                xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                xt[d] = mk[MD_A00 * P] * q + mk[MD_A01 * P] * p;
+                vt[d] = mk[MD_A10 * P] * q + mk[MD_A11 * P] * p;
             }
             if (a.nvt) {
                 double z[3];
                 gauss3(a.seed, (unsigned long long)ar[TA_ORIG], (unsigned long long)m, step, z);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
+                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1 * P] * vt[d] + mk[MD_C2 * P] * sg * z[d];
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double q = xt[d], p = vt[d];
-                xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                xt[d] = mk[MD_A00 * P] * q + mk[MD_A01 * P] * p;
+                vt[d] = mk[MD_A10 * P] * q + mk[MD_A11 * P] * p;
             }
             if (ext) {
                 // closing B with the trap force of the new positions, and
@@ -257,9 +276,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                     ft[d] = -2.0 * hm * a.omega2 * xa;
                     vt[d] += a.hdt * im * ft[d];
                     acc_ekin += hm * vt[d] * vt[d];
-                    acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
+                    acc_esp += hm * mk[MD_SPRING * P] * xt[d] * xt[d];
                     acc_uext += hm * a.omega2 * xa * xa;
-                    acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
+                    acc_vir += mk[MD_NONCENTROID * P] * xt[d] * ft[d];
                 }
             }
             const size_t vb = (size_t)ia * 3 * P + m;
@@ -267,7 +286,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 if (!isfinite(vt[d])) acc_bad = 1.0;
-                sY[(d * 16 + ra) * PS + m] = xt[d];
+                sY[(d * 16 + ra) * PS + cy] = xt[d];
                 // carried to the next step; the centroid mode is re-referenced
                 // to the new bead 0 after the inverse
                 if (m != 0) a.yt[vb + d * P] = xt[d];
@@ -292,9 +311,10 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         d4 ax[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) ax[d] = d4{0.0, 0.0, 0.0, 0.0};
+        const int swy = sw<PS>(lr);
 #pragma unroll 4
         for (int kb = 0; kb < NK4; ++kb) {
-            const int mm = 4 * kb + lq;
+            const int mm = (4 * kb + lq) ^ swy;
             const double bm = bmM[4 * kb * P];
 #pragma unroll
             for (int d = 0; d < 3; ++d) ax[d] = mfma4(sY[(d * 16 + lr) * PS + mm], bm, ax[d]);
@@ -322,7 +342,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 // centroid mode changes, by -sqrt(P) times the bead's offset
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    a.yt[xb + d * P] = sY[(d * 16 + ra) * PS] - sqrtP * ax[d][r];
+                    a.yt[xb + d * P] = sY[(d * 16 + ra) * PS + sw<PS>(ra)] - sqrtP * ax[d][r];
             }
         }
     }

@@ -21,6 +21,7 @@ constexpr int kMaxBonds = 4;     // bonds per atom
 constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
 constexpr int kSortBuf = 4096;   // ints of LDS for sorting the centroid cells
 constexpr int kMaxCells = 4096;  // centroid cells per system, at most (LDS histogram)
+constexpr int kPairStage = 2048;        // neighbor-list entries staged in LDS per force-pass block
 constexpr int kClusterMax = 512;         // union-list entries per force-pass cluster (LDS)
 constexpr int kClusterRows = 1536;       // doubles per staged chunk of neighbor bead rows
 constexpr int kClusterSmem = 8 * 2 * kClusterRows + 16 * kClusterMax;   // dynamic LDS bytes

@@ -423,7 +423,8 @@ __device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int 
     int R[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double rr = rlist * a.icw[d];
+        // a relative margin covers centroids placed within rounding of a cell face
+        const double rr = rlist * a.icw[d] * (1.0 + 1e-12);
         if (rr > 0.0 && rr <= 0.5 * (double)(a.nc[d] - 1))
             R[d] = (int)ceil(rr);
         else
@@ -947,19 +948,38 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int P3 = 3 * P;
     const size_t ib = (size_t)i * P3 + k;
+    const double *__restrict__ X = a.x;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    const int cnt = (act && i < a.n_active) ? a.nbr_count[i] : 0;
     if (act) {
-        const double *__restrict__ X = a.x;
-        const double xi = X[ib], yi = X[ib + P], zi = X[ib + 2 * P];
-        const int cnt = (i < a.n_active) ? a.nbr_count[i] : 0;
-        const int2 *__restrict__ lst = a.nbr + (size_t)i * a.cap;
-        const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
-        const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
-        int q = sg;
+        xi = X[ib]; yi = X[ib + P]; zi = X[ib + 2 * P];
+    }
+    // The block's list entries pass through LDS, up to C = kPairStage/A per
+    // atom at a time, in one coalesced copy: the loop then waits only on the
+    // bead-row gathers.  Entry q still goes to sub-group q mod S, in order.
+    __shared__ int2 s_lst[kPairStage];
+    if (g == 0) s_cnt[la] = cnt;
+    __syncthreads();
+    int nmax = 0;
+    for (int u = 0; u < A; ++u) nmax = max(nmax, s_cnt[u]);
+    const int C = kPairStage / A;
+    const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
+    const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
+    for (int c0 = 0; c0 < nmax; c0 += C) {
+        const int span = min(C, nmax - c0);
+        for (int e2 = t; e2 < A * span; e2 += kBlock) {
+            const int aa = e2 / span, qq = c0 + (e2 - aa * span);
+            if (qq < s_cnt[aa]) s_lst[e2] = a.nbr[(size_t)(tile * A + aa) * a.cap + qq];
+        }
+        __syncthreads();
+        const int2 *ls = s_lst + la * span;                 // entry q at ls[q - c0]
+        const int qend = min(cnt, c0 + span);
+        int q = c0 + sg;
         // four entries per iteration: all gathers issued before any use
-        for (; q + 3 * S < cnt; q += 4 * S) {
+        for (; q + 3 * S < qend; q += 4 * S) {
             int2 en[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) en[u] = lst[q + u * S];
+            for (int u = 0; u < 4; ++u) en[u] = ls[q - c0 + u * S];
             double xj[4], yj[4], zj[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -974,14 +994,17 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                               rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
             }
         }
-        for (; q < cnt; q += S) {
-            const int2 en = lst[q];
+        for (; q < qend; q += S) {
+            const int2 en = ls[q - c0];
             double sx, sy, sz;
             unpack_shift(en.y, sx, sy, sz);
             const int jb = en.x + k;
             lj_accumulate(xi - X[jb] + sx * L0, yi - X[jb + P] + sy * L1, zi - X[jb + 2 * P] + sz * L2,
                           rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
         }
+        __syncthreads();
+    }
+    if (act) {
         if (sg == 0) {
             for (int bb = 0; bb < kMaxBonds; ++bb) {
                 const int j = a.bond_j[i * kMaxBonds + bb];

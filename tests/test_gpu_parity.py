@@ -141,6 +141,37 @@ def test_water_full_size_p64_short():
     check_states(g, o)
 
 
+# ------------------------------------------------------------ transform variants
+@pytest.mark.parametrize("kind,N,P", [
+    ("harmonic", 37, 16), ("harmonic", 50, 32), ("harmonic", 5, 64), ("harmonic", 333, 64),
+    ("lj", 250, 16), ("lj", 500, 32), ("lj", 130, 64), ("water", 387, 32), ("water", 99, 64)])
+def test_mfma_transforms(kind, N, P):
+    """The matrix-core step pass forced on small systems: ragged last tiles
+    (N not a multiple of the 16-atom tile or of the block tile), the trap path
+    and the pair path, for each bead count it supports."""
+    pimd = _pimd()
+    fl = pimd.PIMD_FLAG_MFMA_TRANSFORMS
+    if kind == "harmonic":
+        spec = inputs.harmonic_tiny(n_atoms=N, n_beads=P, seed=7 * N + P)
+        g, o = run_pair(spec, 40, chunks=[1, 7, 32], flags=fl)
+    elif kind == "lj":
+        spec = inputs.lj_liquid(n_atoms=N, n_beads=P, seed=N + P)
+        g, o = run_pair(spec, 10, chunks=[4, 6], flags=fl)
+    else:
+        spec = inputs.water(n_atoms=N, n_beads=P, seed=N)
+        g, o = run_pair(spec, 10, flags=fl)
+    check_states(g, o)
+
+
+def test_valu_transforms_water_full_size():
+    """The vector-ALU step pass at the water-shaped workload's size (the size
+    picks the matrix cores by default)."""
+    pimd = _pimd()
+    spec = inputs.water(n_beads=32)
+    g, o = run_pair(spec, 5, flags=pimd.PIMD_FLAG_VALU_TRANSFORMS)
+    check_states(g, o)
+
+
 # ------------------------------------------------------------ cluster lists
 @pytest.mark.parametrize("case", ["lj_full", "lj_p16", "lj_small_box", "water_p32", "water_small"])
 def test_cluster_pairs(case):
