@@ -197,6 +197,51 @@ __device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
     return cell;
 }
 
+// Sums of NS values and maxima of NM values in one exchange (one barrier).
+// The caller passes a barrier before red is written again.
+template <int NS, int NM>
+__device__ inline void block_sum_max(double (&sv)[NS], double (&mv)[NM],
+                                     double *red /* >= (NS + NM) * kBlock/64 */)
+{
+    constexpr int NW = kBlock / 64;
+    const int t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double x = sv[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        sv[q] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+        double x = mv[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+        mv[q] = x;
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) red[q * NW + w] = sv[q];
+#pragma unroll
+        for (int q = 0; q < NM; ++q) red[(NS + q) * NW + w] = mv[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double x = red[q * NW];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) x += red[q * NW + u];
+        sv[q] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+        double x = red[(NS + q) * NW];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) x = fmax(x, red[(NS + q) * NW + u]);
+        mv[q] = x;
+    }
+}
+
 template <int NV>
 __device__ inline void block_maxv(double (&v)[NV], double *red /* >= NV * kBlock/64 */)
 {

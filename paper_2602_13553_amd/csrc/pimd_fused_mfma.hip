@@ -93,8 +93,6 @@ template <int P>
 __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *smem,
                            double *partial_out)
 {
-    // a system whose step budget is spent takes no step (uniform per block)
-    if (a.ctl->budget == 0) return;
     using L = Lds<P>;
     constexpr int NMB = L::NMB, T = L::T, XS = L::XS, PS = L::PS, NLD = L::NLD, AW = L::AT_W;
     constexpr int NK4 = P / 4;        // k-steps of 4
@@ -112,15 +110,26 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const double *bmM = a.M + lq * P + mb * 16 + lr;
 
     const int N = a.N;
+    // The control block, the per-mode table and the first tile are read
+    // together; a spent budget is acted on once the tile's reads are issued.
+    const long long budget = a.ctl->budget;
     const unsigned long long step = a.ctl->step;
     const int synced = a.ctl->synced;
+    // a system whose step budget is spent takes no step (uniform per block)
+    const bool spent = budget == 0;
     const bool ext = !a.pair;
     const bool closing = a.pair && !synced;
     const bool need_f = a.pair != 0;
     const double sqrtP = sqrt((double)P);
     const int m = mb * 16 + lr;       // this lane's mode
     double *sMk = smem + T * L::TILE;             // [8][P]: per-mode coefficients
-    for (int e = t; e < 8 * P; e += kBlock) sMk[(e & 7) * P + (e >> 3)] = a.modes[e];
+    constexpr int NMK = (8 * P + kBlock - 1) / kBlock;
+    double rmk[NMK];
+#pragma unroll
+    for (int q = 0; q < NMK; ++q) {
+        const int e = t + q * kBlock;
+        rmk[q] = e < 8 * P ? a.modes[e] : 0.0;
+    }
     const double *mk = sMk + m;                   // coefficient q at mk[q * P]
     const double off = (m == 0) ? sqrtP : 0.0;
 
@@ -169,7 +178,15 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
             }
         }
 
+        if (spent) return;
         __syncthreads();                               // previous tile's LDS use is done
+        if (bt == first) {
+#pragma unroll
+            for (int q = 0; q < NMK; ++q) {
+                const int e = t + q * kBlock;
+                if (e < 8 * P) sMk[(e & 7) * P + (e >> 3)] = rmk[q];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = t + q * kBlock;
@@ -349,13 +366,13 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 
     // per-block partials (plain stores; k_finalize runs next); the reduction
     // scratch reuses the tiles' LDS once every wave is done with it
+    if (spent) return;
     __syncthreads();
     double *red = smem;
     double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
-    block_sum<4>(s4, red);
-    const double emax = block_max(acc_emax, red);
-    const double dmax = block_max(acc_dmax, red);
-    const double bad = block_max(acc_bad, red);
+    double m3[3] = {acc_emax, acc_dmax, acc_bad};
+    block_sum_max<4, 3>(s4, m3, red);
+    const double emax = m3[0], dmax = m3[1], bad = m3[2];
     if (t == 0) {
         double *pp = partial_out;
         pp[PF_EKIN] = s4[0];

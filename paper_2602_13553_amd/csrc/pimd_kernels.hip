@@ -34,8 +34,6 @@ int fused_smem_bytes(int P)
 __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *smem, double *red,
                            double *partial_out, bool stage_m)
 {
-    // a system whose step budget is spent takes no step (uniform per block)
-    if (a.mode == FUSED_STEP && a.ctl->budget == 0) return;
     const int P = a.P, N = a.N;
     const int A = kBlock / P;
     const int PS = P + 1;
@@ -44,23 +42,32 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     double *sF = sX + 3 * A * P;        // [A][3][P]
     double *sC = sF + 3 * A * P;        // [A][3] centroids
     double *sR = sC + 3 * A;            // [A][3] bead-0 reference positions
-
     const int t = threadIdx.x;
-    __syncthreads();   // the previous call's shared-memory reads are done
-    if (stage_m) {
-        for (int e = t; e < P * P; e += kBlock) {
-            const int k = e / P, j = e - k * P;
-            sMT[j * PS + k] = a.M[e];
-        }
-    }
 
-    const int mode = a.mode;
+    // The control block, the matrix (for P <= 32) and the first tile are read
+    // together: nothing waits for the control block before the tile's reads
+    // are issued, and a spent budget is acted on once they are in flight.
+    constexpr int NM = 4;               // matrix elements held per thread (P*P <= NM*kBlock)
+    const bool m_regs = P * P <= NM * kBlock;
+    double mreg[NM];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) {
+        const int e = t + q * kBlock;
+        mreg[q] = (stage_m && m_regs && e < P * P) ? a.M[e] : 0.0;
+    }
+    const long long budget = a.ctl->budget;
     const unsigned long long step = a.ctl->step;
     const int synced = a.ctl->synced;
+    // a system whose step budget is spent takes no step (uniform per block)
+    const bool spent = (a.mode == FUSED_STEP && budget == 0);
+
+    const int mode = a.mode;
     const int ext = !a.pair;                                    // forces in-kernel
     const bool closing = (mode == FUSED_STEP || mode == FUSED_CLOSE) && !synced && a.pair;
     const bool est_now = closing || mode == FUSED_EST;          // estimators of this state
-    const bool need_f = a.pair && (mode == FUSED_STEP || est_now);
+    // f is read whenever a pass may need it (a closing pass finds out from
+    // the control block), so that its reads need not wait for that block
+    const bool need_f = a.pair && mode != FUSED_PREP;
     const bool inverse = (mode == FUSED_STEP);
     const bool carry = (mode == FUSED_STEP);     // positions' modes carried in yt
     const double sqrtP = sqrt((double)P);
@@ -102,6 +109,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         }
         double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0;
         double vpre[3] = {0.0, 0.0, 0.0}, ypre[3] = {0.0, 0.0, 0.0}, xref[3] = {0.0, 0.0, 0.0};
+        double cref[3] = {0.0, 0.0, 0.0};
         unsigned long long oi = 0;
         if (act) {
             hm = a.atoms[i * 4 + AT_HALF_M];
@@ -118,8 +126,29 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 const size_t xb0 = (size_t)i * 3 * P;
                 xref[0] = a.x[xb0]; xref[1] = a.x[xb0 + P]; xref[2] = a.x[xb0 + 2 * P];
             }
+            if (k == 0 && (mode == FUSED_STEP || mode == FUSED_PREP)) {
+                cref[0] = a.cref[i * 3]; cref[1] = a.cref[i * 3 + 1]; cref[2] = a.cref[i * 3 + 2];
+            }
         }
-        __syncthreads();
+        if (spent) return;
+        __syncthreads();   // the previous tile's (or call's) shared-memory reads are done
+        if (stage_m && tile == t0) {
+            if (m_regs) {
+#pragma unroll
+                for (int q = 0; q < NM; ++q) {
+                    const int e = t + q * kBlock;
+                    if (e < P * P) {
+                        const int kk = e / P, j = e - kk * P;
+                        sMT[j * PS + kk] = mreg[q];
+                    }
+                }
+            } else {
+                for (int e = t; e < P * P; e += kBlock) {
+                    const int kk = e / P, j = e - kk * P;
+                    sMT[j * PS + kk] = a.M[e];
+                }
+            }
+        }
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int e = t + q * kBlock;
@@ -322,7 +351,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                     for (int d = 0; d < 3; ++d) {
                         c[d] = sC[la * 3 + d];
                         a.cent[i * 3 + d] = c[d];
-                        const double dd = c[d] - a.cref[i * 3 + d];
+                        const double dd = c[d] - cref[d];
                         d2 += dd * dd;
                     }
                     if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
@@ -332,14 +361,14 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         }
     }
 
+    if (spent) return;
     // ---- per-block partials (plain stores; k_finalize runs after this
     // kernel, so the kernel boundary makes them visible)
     {
         double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
-        block_sum<4>(s4, red);
-        const double emax = block_max(acc_emax, red);
-        const double dmax = block_max(acc_dmax, red);
-        const double bad = block_max(acc_bad, red);
+        double m3[3] = {acc_emax, acc_dmax, acc_bad};
+        block_sum_max<4, 3>(s4, m3, red);
+        const double emax = m3[0], dmax = m3[1], bad = m3[2];
         if (t == 0) {
             double *pp = partial_out;
             pp[PF_EKIN] = s4[0];
@@ -533,11 +562,9 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
     const int P = a.P;
     const int mode = a.mode;
     Ctl *c = a.ctl;
-    if (mode == FUSED_STEP && c->budget == 0) {
-        // no step was taken: nothing to combine, and no force pass follows
-        if (t == 0) c->ran = 0;
-        return;
-    }
+    // the control block, thread 0's read-modify-write state and the partials
+    // are read together; a spent budget is acted on once they are in
+    const long long budget = c->budget;
     const unsigned long long step = c->step;
     const int synced = c->synced;
     const int ext = !a.pair;
@@ -573,12 +600,19 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         mx[1] = fmax(mx[1], pp[PF_DMAX]);
         mx[2] = fmax(mx[2], pp[PF_NONFINITE]);
     }
-    if (a.pair && est_now) {
+    // (summed whether or not this pass needs them, so the loads do not wait
+    // for the control block)
+    if (a.pair) {
 #pragma unroll 4
         for (int b = t; b < a.n_fpartials; b += kBlock) tot[4] += a.fpartials[b];
     }
     block_sum<5>(tot, red);
     block_maxv<3>(mx, red);
+    if (mode == FUSED_STEP && budget == 0) {
+        // no step was taken: nothing to combine, and no force pass follows
+        if (t == 0) c->ran = 0;
+        return;
+    }
     const double upair = tot[4];
     const double emax = sqrt(mx[0]), dmax = sqrt(mx[1]), bad = mx[2];
 
