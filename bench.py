@@ -296,7 +296,7 @@ def main():
         "data": data,
         "config": {"workload": title, "n_atoms": spec.n_atoms,
                    "n_beads": spec.n_beads, "bead_atoms": ba, "kT": spec.temp,
-                   "hbar": spec.hbar, "rc": spec.lj_rc, "dt": spec.dt, "tau": spec.tau,
+                   "hbar": spec.hbar, "rc": spec.lj_rc, "skin": spec.skin, "dt": spec.dt, "tau": spec.tau,
                    "ensemble": "NVT PILE-L", "integrator": "BAOAB",
                    "transforms": args.transforms},
         "roofline": roof,

@@ -25,7 +25,7 @@ constexpr int kGraphChunk = 32;   // steps per captured graph
 
 struct Layout {
     size_t x, yt, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
-        partials, fpartials, ctl, cell_atoms, cell_ent, cell_scnt, cinfo, total;
+        partials, fpartials, ctl, cell_ent, cell_scnt, cinfo, total;
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
     int valu_tiles, mfma_tiles;
     int ncell, cell_cap, nc[3];   // centroid cells (ncell = 0: none)
@@ -217,7 +217,7 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
     if (ncell > 8LL * n_active + 64) return;
     const double mean = (double)n_active / (double)ncell;
     const int cap = ((int)std::ceil(2.0 * mean) + 16 + 3) & ~3;   // rows of whole int4
-    if (cap > kSortBuf || ncell > kMaxCells) return;
+    if (cap > kCellCapMax || ncell > kMaxCells) return;
     L.ncell = (int)ncell;
     L.cell_cap = cap;
     for (int d = 0; d < 3; ++d) L.nc[d] = nc[d];
@@ -308,7 +308,6 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.partials = take((size_t)nparts * PF_COUNT * sizeof(double));
     L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
     L.ctl = take(sizeof(Ctl));
-    L.cell_atoms = take((size_t)L.ncell * L.cell_cap * sizeof(int));
     L.cell_ent = take((size_t)L.ncell * L.cell_cap * sizeof(CellEntry));
     L.cell_scnt = take((size_t)L.ncell * sizeof(int));
     L.cinfo = take(L.ncell ? N * sizeof(int4) : 0);
@@ -602,7 +601,6 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         a.box[d] = p->box[d];
         a.icw[d] = L.ncell ? (double)L.nc[d] / p->box[d] : 0.0;
     }
-    a.cell_atoms = L.ncell ? (int *)(w + L.cell_atoms) : nullptr;
     a.cell_ent = L.ncell ? (CellEntry *)(w + L.cell_ent) : nullptr;
     a.cell_scnt = L.ncell ? (int *)(w + L.cell_scnt) : nullptr;
     a.cinfo = L.ncell ? (int4 *)(w + L.cinfo) : nullptr;

@@ -19,8 +19,8 @@ constexpr int kBlock = 256;      // threads per block for the step kernels
 constexpr int kMaxBeads = 128;   // P limit of this build (LDS-resident M)
 constexpr int kMaxBonds = 4;     // bonds per atom
 constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
-constexpr int kSortBuf = 4096;   // ints of LDS for sorting the centroid cells
-constexpr int kMaxCells = 4096;  // centroid cells per system, at most (LDS histogram)
+constexpr int kCellCapMax = 4096;  // atoms per centroid cell, at most
+constexpr int kMaxCells = 3072;    // centroid cells per system, at most (LDS counts, 4 per cell)
 constexpr int kPairStage = 2048;        // neighbor-list entries staged in LDS per force-pass block
 constexpr int kClusterMax = 512;         // union-list entries per force-pass cluster (LDS)
 constexpr int kClusterRows = 1536;       // doubles per staged chunk of neighbor bead rows
@@ -103,7 +103,6 @@ struct FusedArgs {
     int nc[3];                // cells per dim, each >= 3
     double box[3];
     double icw[3];            // cells per unit length
-    int *cell_atoms;          // [ncell][cell_cap] a rebuild's cell lists, placement order
     CellEntry *cell_ent;      // [ncell][cell_cap] the same, increasing index, with centroids
     int *cell_scnt;           // [ncell] atoms per cell
     int4 *cinfo;              // [N] (cell, image index per dim) of each active atom's centroid

@@ -416,39 +416,81 @@ __global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *table, 
 // rebuild for the coming force pass.
 // --------------------------------------------------------------------------
 // At a rebuild, builds the centroid cell lists from the cells recorded by
-// the step pass: an LDS histogram, placement through LDS cursors, then a rank
-// sort of each cell (staged in LDS) so that its atoms are in increasing index
-// order, whatever the order of the placement; the list build then sees its
-// candidates in a fixed order.  Decides whether the cells can serve this
+// the step pass, each cell's atoms in increasing index order, without a sort:
+// wave w takes the contiguous atom range [w*na/4, (w+1)*na/4) in chunks of 64
+// in index order.  A first pass counts, per wave, the atoms of each cell; the
+// place of wave w's atoms in cell q starts after the atoms of waves < w.  The
+// second pass places each atom at its wave's running offset in its cell plus
+// its rank among the lower lanes of its chunk that share the cell (groups of
+// equal cells from one ballot per cell-index bit), and writes its entry with
+// its centroid and box indices.  Decides whether the cells can serve this
 // rebuild: no cell over capacity, and a stencil of 2R+1 cells per dim that
-// does not wrap onto itself.  One block; no global atomics.
-__device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int *sord, int *shist,
+// does not wrap onto itself.  One block; no atomics.
+namespace {
+
+// lanes of the wave whose value of q equals this lane's (ok lanes only)
+__device__ __forceinline__ unsigned long long same_cell_lanes(bool ok, int q, int nbits)
+{
+    unsigned long long same = __ballot(ok);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = ((q >> b) & 1) != 0;
+        const unsigned long long m = __ballot(ok && bit);
+        same &= bit ? m : ~m;
+    }
+    return same;
+}
+
+}  // namespace
+
+__device__ void cells_finalize(const FusedArgs &a, double rlist, int *scnt /* [4][ncell] */,
                                int *sflag)
 {
-    const int t = threadIdx.x;
+    static_assert(kBlock == 256, "four waves split the atoms");
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int ncell = a.ncell, cap = a.cell_cap, na = a.n_active;
     Ctl *c = a.ctl;
-    for (int q = t; q < ncell; q += kBlock) shist[q] = 0;
+    for (int q = t; q < 4 * ncell; q += kBlock) scnt[q] = 0;
     if (t == 0) sflag[0] = 0;
+    int nbits = 0;
+    while ((1 << nbits) < ncell) ++nbits;
+    const int per = (na + 3) / 4;
+    const int lo = min(na, w * per), hi = min(na, lo + per);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int *mine = scnt + w * ncell;
     __syncthreads();
-    // eight cell reads in flight per thread, then their LDS increments
-    constexpr int U = 8;
-    for (int i0 = t; i0 < na; i0 += U * kBlock) {
-        int cl[U];
+    // pass 1: per-wave counts (the lowest lane of each equal-cell group adds
+    // the group's size; the groups of one chunk have distinct cells)
+    constexpr int U = 16;
+    for (int i0 = lo; i0 < hi; i0 += 64 * U) {
+        int qv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * kBlock;
-            cl[u] = i < na ? a.cinfo[i].x : -1;
+            const int i = i0 + u * 64 + lane;
+            qv[u] = i < hi ? a.cinfo[i].x : -1;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (cl[u] >= 0) atomicAdd(&shist[cl[u]], 1);
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * 64 >= hi) break;                    // uniform over the wave
+            const bool ok = qv[u] >= 0;
+            const unsigned long long same = same_cell_lanes(ok, qv[u], nbits);
+            if (ok && (same & below) == 0) mine[qv[u]] += __popcll(same);
+        }
     }
     __syncthreads();
-    for (int q = t; q < ncell; q += kBlock)
-        if (shist[q] > cap) sflag[0] = 1;
+    // offsets of each wave in each cell, totals, capacity
+    for (int q = t; q < ncell; q += kBlock) {
+        int o = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = scnt[u * ncell + q];
+            scnt[u * ncell + q] = o;
+            o += v;
+        }
+        a.cell_scnt[q] = o;
+        if (o > cap) sflag[0] = 1;
+    }
     __syncthreads();
-    bool ok = sflag[0] == 0 && cap <= kSortBuf;
+    bool ok_all = sflag[0] == 0;
     int R[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -457,99 +499,44 @@ __device__ void cells_finalize(const FusedArgs &a, double rlist, int *sbuf, int 
         if (rr > 0.0 && rr <= 0.5 * (double)(a.nc[d] - 1))
             R[d] = (int)ceil(rr);
         else
-            ok = false;
-        if (2 * R[d] + 1 > a.nc[d]) ok = false;
+            ok_all = false;
+        if (2 * R[d] + 1 > a.nc[d]) ok_all = false;
     }
-    if (ok) {
-        // placement in arrival order (the cursors end equal to the counts)
-        for (int q = t; q < ncell; q += kBlock) {
-            a.cell_scnt[q] = shist[q];
-            shist[q] = 0;
-        }
-        __syncthreads();
-        for (int i0 = t; i0 < na; i0 += U * kBlock) {
-            int cl[U];
+    if (ok_all) {
+        // pass 2: placement in index order, entries written directly
+        constexpr int V = 8;
+        for (int i0 = lo; i0 < hi; i0 += 64 * V) {
+            int4 ci[V];
+            double cx[V], cy[V], cz[V];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * kBlock;
-                cl[u] = i < na ? a.cinfo[i].x : -1;
+            for (int u = 0; u < V; ++u) {
+                const int i = i0 + u * 64 + lane;
+                const int ii = i < hi ? i : lo;
+                ci[u] = i < hi ? a.cinfo[ii] : make_int4(-1, 0, 0, 0);
+                cx[u] = a.cent[ii * 3]; cy[u] = a.cent[ii * 3 + 1]; cz[u] = a.cent[ii * 3 + 2];
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (cl[u] >= 0) {
-                    const int slot = atomicAdd(&shist[cl[u]], 1);
-                    a.cell_atoms[(size_t)cl[u] * cap + slot] = i0 + u * kBlock;
-                }
-        }
-        __threadfence_block();
-        __syncthreads();
-        // index order inside each cell
-        const int cb = kSortBuf / cap;            // cells per LDS batch
-        for (int c0 = 0; c0 < ncell; c0 += cb) {
-            const int nb = min(cb, ncell - c0);
-            const int ne = nb * cap;
-            for (int e0 = t; e0 < ne; e0 += U * kBlock) {
-                int v[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int e = e0 + u * kBlock;
-                    v[u] = e < ne ? a.cell_atoms[(size_t)c0 * cap + e] : 0;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (e0 + u * kBlock < ne) sbuf[e0 + u * kBlock] = v[u];
-            }
-            __syncthreads();
-            // ranks from LDS only: each atom's place among its cell's atoms
-            for (int e = t; e < ne; e += kBlock) {
-                const int cl = e / cap, sl = e - cl * cap;
-                const int n = shist[c0 + cl];
-                if (sl < n) {
-                    const int v = sbuf[e];
-                    const int4 *row4 = reinterpret_cast<const int4 *>(sbuf + cl * cap);
-                    int rank = 0;
-#pragma unroll 4
-                    for (int q4 = 0; q4 < (n + 3) >> 2; ++q4) {
-                        const int4 r = row4[q4];
-                        const int b = 4 * q4;
-                        rank += (b < n && r.x < v) + (b + 1 < n && r.y < v) +
-                                (b + 2 < n && r.z < v) + (b + 3 < n && r.w < v);
-                    }
-                    sord[cl * cap + rank] = v;
-                }
-            }
-            __syncthreads();
-            // the entries in index order, with each atom's centroid and box
-            // indices (eight gathers in flight per thread)
-            for (int e0 = t; e0 < ne; e0 += U * kBlock) {
-                int v[U];
-                double cx[U], cy[U], cz[U];
-                int4 ci[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int e = e0 + u * kBlock;
-                    const int cl = e / cap, sl = e - cl * cap;
-                    v[u] = (e < ne && sl < shist[c0 + min(cl, nb - 1)]) ? sord[e] : -1;
-                    const int vv = v[u] < 0 ? 0 : v[u];
-                    cx[u] = a.cent[vv * 3]; cy[u] = a.cent[vv * 3 + 1]; cz[u] = a.cent[vv * 3 + 2];
-                    ci[u] = a.cinfo[vv];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (v[u] < 0) continue;
+            for (int u = 0; u < V; ++u) {
+                if (i0 + u * 64 >= hi) break;                // uniform over the wave
+                const int q = ci[u].x;
+                const bool ok = q >= 0;
+                const unsigned long long same = same_cell_lanes(ok, q, nbits);
+                if (ok) {
+                    const int slot = mine[q] + __popcll(same & below);
                     CellEntry ce;
                     ce.c[0] = cx[u]; ce.c[1] = cy[u]; ce.c[2] = cz[u];
-                    ce.j = v[u];
+                    ce.j = i0 + u * 64 + lane;
                     ce.nb[0] = ci[u].y; ce.nb[1] = ci[u].z; ce.nb[2] = ci[u].w;
                     ce.pad = 0;
-                    a.cell_ent[(size_t)c0 * cap + e0 + u * kBlock] = ce;
+                    a.cell_ent[(size_t)q * cap + slot] = ce;
                 }
+                // every lane has read its offset before the group's leader moves it
+                if (ok && (same & below) == 0) mine[q] += __popcll(same);
             }
-            __syncthreads();
         }
     }
     if (t == 0) {
-        c->cell_ok = ok ? 1 : 0;
+        c->cell_ok = ok_all ? 1 : 0;
         c->cell_R[0] = R[0];
         c->cell_R[1] = R[1];
         c->cell_R[2] = R[2];
@@ -575,7 +562,7 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
     // thread 0's read-modify-write state, fetched now so that its latency
     // overlaps the partial reductions
     double run_sum[kNumEst], run_sq[kNumEst];
-    unsigned long long run_count = 0;
+    unsigned long long run_count = 0, n_rebuilds = 0;
     double ebuild = 0.0;
     if (t == 0) {
 #pragma unroll
@@ -585,29 +572,50 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         }
         run_count = c->count;
         ebuild = c->ebuild;
+        n_rebuilds = c->n_rebuilds;
     }
 
     double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double mx[3] = {0.0, 0.0, 0.0};   // emax^2, dmax^2, non-finite flag
-#pragma unroll 2
-    for (int b = t; b < nblocks; b += kBlock) {
-        const double *pp = a.partials + (size_t)b * PF_COUNT;
-        tot[0] += pp[PF_EKIN];
-        tot[1] += pp[PF_ESPRING];
-        tot[2] += pp[PF_VIR];
-        tot[3] += pp[PF_UEXT];
-        mx[0] = fmax(mx[0], pp[PF_EMAX]);
-        mx[1] = fmax(mx[1], pp[PF_DMAX]);
-        mx[2] = fmax(mx[2], pp[PF_NONFINITE]);
+    // Loads in fixed batches held in registers, so that a batch's reads are in
+    // flight together; out-of-range slots add +0, and each thread's sums run
+    // in loop order, so the result is that of the plain loop.
+    constexpr int NB = 4, NF = 16;
+    for (int b0 = t; b0 < nblocks; b0 += NB * kBlock) {
+        double pv[NB][7];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int b = b0 + u * kBlock;
+            const double *pp = a.partials + (size_t)(b < nblocks ? b : 0) * PF_COUNT;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) pv[u][q] = b < nblocks ? pp[q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            tot[0] += pv[u][PF_EKIN];
+            tot[1] += pv[u][PF_ESPRING];
+            tot[2] += pv[u][PF_VIR];
+            tot[3] += pv[u][PF_UEXT];
+            mx[0] = fmax(mx[0], pv[u][PF_EMAX]);
+            mx[1] = fmax(mx[1], pv[u][PF_DMAX]);
+            mx[2] = fmax(mx[2], pv[u][PF_NONFINITE]);
+        }
     }
     // (summed whether or not this pass needs them, so the loads do not wait
     // for the control block)
     if (a.pair) {
-#pragma unroll 4
-        for (int b = t; b < a.n_fpartials; b += kBlock) tot[4] += a.fpartials[b];
+        for (int b0 = t; b0 < a.n_fpartials; b0 += NF * kBlock) {
+            double fv[NF];
+#pragma unroll
+            for (int u = 0; u < NF; ++u) {
+                const int b = b0 + u * kBlock;
+                fv[u] = b < a.n_fpartials ? a.fpartials[b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NF; ++u) tot[4] += fv[u];
+        }
     }
-    block_sum<5>(tot, red);
-    block_maxv<3>(mx, red);
+    block_sum_max<5, 3>(tot, mx, red);
     if (mode == FUSED_STEP && budget == 0) {
         // no step was taken: nothing to combine, and no force pass follows
         if (t == 0) c->ran = 0;
@@ -641,46 +649,42 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         if (mode == FUSED_STEP) {
             c->step = step + 1;
             c->synced = ext ? 1 : 0;
-            if (c->budget > 0) c->budget -= 1;
+            if (budget > 0) c->budget = budget - 1;
         } else if (mode == FUSED_CLOSE) {
             c->synced = 1;
         }
         c->ran = 1;
-        if (a.pair && mode == FUSED_PREP) {
+        const bool rebuild = a.pair && (mode == FUSED_PREP ||
+                                        (mode == FUSED_STEP && dmax + emax > 0.5 * a.skin + ebuild));
+        const double rlist = a.rc + a.skin + 2.0 * emax;
+        if (rebuild) {
             c->rebuild = 1;
             c->ebuild = emax;
-            c->rlist = a.rc + a.skin + 2.0 * emax;
-            c->n_rebuilds += 1;
+            c->rlist = rlist;
+            c->n_rebuilds = n_rebuilds + 1;
         } else if (a.pair && mode == FUSED_STEP) {
-            if (dmax + emax > 0.5 * a.skin + ebuild) {
-                c->rebuild = 1;
-                c->ebuild = emax;
-                c->rlist = a.rc + a.skin + 2.0 * emax;
-                c->n_rebuilds += 1;
-            } else {
-                c->rebuild = 0;
-            }
+            c->rebuild = 0;
         }
         if (bad != 0.0) c->nonfinite = 1;
+        // this pass's decision, for the cell build below (slots past the
+        // reduction's, which other threads may still be reading)
+        red[32] = rebuild ? 1.0 : 0.0;
+        red[33] = rlist;
     }
     // the centroid cell lists of a rebuild (cells recorded by this pass)
     if (a.pair && a.ncell > 0 && (mode == FUSED_STEP || mode == FUSED_PREP)) {
-        if (t == 0) {
-            red[0] = c->rebuild ? 1.0 : 0.0;
-            red[1] = c->rlist;
-        }
         __syncthreads();
-        const bool rb = red[0] != 0.0;
-        const double rl = red[1];
+        const bool rb = red[32] != 0.0;
+        const double rl = red[33];
         __syncthreads();
-        if (rb) cells_finalize(a, rl, sbuf, sbuf + kSortBuf, sbuf + 2 * kSortBuf, sflag);
+        if (rb) cells_finalize(a, rl, sbuf, sflag);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
 {
     __shared__ double red[64];
-    __shared__ __align__(16) int sbuf[2 * kSortBuf + kMaxCells];
+    __shared__ __align__(16) int sbuf[4 * kMaxCells];
     __shared__ int sflag[1];
     finalize_system(a, nblocks, red, sbuf, sflag);
 }
@@ -690,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FusedArgs *tabl
                                                            const int *nparts, int n_sys, int mode)
 {
     __shared__ double red[64];
-    __shared__ __align__(16) int sbuf[2 * kSortBuf + kMaxCells];
+    __shared__ __align__(16) int sbuf[4 * kMaxCells];
     __shared__ int sflag[1];
     for (int sidx = blockIdx.x; sidx < n_sys; sidx += gridDim.x) {
         FusedArgs a = table[sidx];

@@ -134,7 +134,7 @@ def free_ring_polymer(seed: int = 7, n_atoms: int = 16, n_beads: int = 8, kT: fl
 def lj_liquid(n_atoms: int = 4000, n_beads: int = 32, rho: float = 0.8, kT: float = 0.7,
               hbar: float = 0.1, dt: float = 0.002, tau: float = 0.5, rc: float = 2.5,
               seed: int = 20260213, jitter: float = 0.01, nsteps: int = 1000,
-              ensemble: int = NVT, skin: float = 0.3) -> SystemSpec:
+              ensemble: int = NVT, skin: float = 0.2) -> SystemSpec:
     """FCC start (first n_atoms sites of the smallest cubic FCC block that holds
     them), cubic box L = (N/rho)^(1/3), independent N(0, jitter^2) offsets per
     (bead, atom, dim)."""
@@ -156,7 +156,7 @@ def lj_liquid(n_atoms: int = 4000, n_beads: int = 32, rho: float = 0.8, kT: floa
 # --- water-shaped system ----------------------------------------------------------
 def water(n_atoms: int = 32768, n_beads: int = 32, seed: int = 20260213, temp: float = 300.0,
           dt: float = 0.25, tau: float = 100.0, density: float = 1.0, nsteps: int = 500,
-          ensemble: int = NVT, skin: float = 0.4, jitter: float = 0.01) -> SystemSpec:
+          ensemble: int = NVT, skin: float = 0.3, jitter: float = 0.01) -> SystemSpec:
     """Water-shaped system in real units.  n_atoms is rounded down to whole
     molecules (32768 -> 10922 molecules, 32766 atoms).  O atoms sit on the first
     n_mol sites of the smallest cubic grid that holds them; each molecule gets
