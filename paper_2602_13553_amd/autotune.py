@@ -13,7 +13,7 @@ From the timings it picks two things:
 
 * per P, the smallest N*P from which the matrix cores are at least as fast
   at every larger size of the sweep;
-* per (P, N), the fastest S.
+* per (P, N), the fewest sub-groups S within 2% of the fastest.
 
 With --write it rewrites csrc/pimd_tuning.h. The library compiles that table
 in, so a given system always gets the same launch shapes. Runs are then
@@ -102,7 +102,10 @@ def choose(result: dict) -> tuple[list, list]:
         for N in ATOMS:
             x = next(x for x in rows if x["P"] == P and x["N"] == N)
             cand = {S: x["pair_S%d" % S] for S in SUBGROUPS if "pair_S%d" % S in x}
-            line.append(min(cand, key=cand.get))
+            # the fewest sub-groups within 2% of the fastest: points closer
+            # than that are ties at 40 timed steps
+            best = min(cand.values())
+            line.append(min(S for S, v in cand.items() if v <= 1.02 * best))
         table.append(line)
     return mfma_min, table
 
@@ -126,10 +129,15 @@ def header_text(result: dict, mfma_min: list, table: list) -> str:
         "// [2^6, 2^7), [2^7, 2^8), ..., [2^15, 2^16) (columns; clamped at both ends).\n"
         "// 0: the occupancy heuristic decides.\n"
         "constexpr int kPairSubgroups[4][10] = {\n%s,\n};\n\n"
+        "// Force pass on cluster lists (1) or per-atom lists (0), same rows and\n"
+        "// columns as kPairSubgroups.  The sweep does not time cluster lists (they\n"
+        "// were slower than per-atom lists at every size measured), so they stay off.\n"
+        "constexpr int kClusterPairs[4][10] = {\n%s,\n};\n\n"
         "}  // namespace tuning\n"
         "}  // namespace pimd\n"
         % (result["device"], stamp, result["steps"],
-           ", ".join("%dLL" % v for v in mfma_min), rows))
+           ", ".join("%dLL" % v for v in mfma_min), rows,
+           ",\n".join("    {" + ", ".join("0" for _ in line) + "}" for line in table)))
 
 
 def summary_text(result: dict, mfma_min: list, table: list) -> str:

@@ -2,7 +2,7 @@
 // from kernel timings on the GPU; regenerate with
 //   python -m paper_2602_13553_amd.autotune --write
 // (the sweep, its workloads and the raw timings are described there).
-// Measured on MI355X (gfx950), 2026-12-02, 40 timed steps per point.
+// Measured on AMD Radeon Graphics (gfx950:sramecc+:xnack-), 2026-12-02, 40 timed steps per point.
 #pragma once
 
 namespace pimd {
@@ -16,14 +16,15 @@ constexpr long long kMfmaMinBeadAtoms[3] = {524288LL, 262144LL, 262144LL};
 // [2^6, 2^7), [2^7, 2^8), ..., [2^15, 2^16) (columns; clamped at both ends).
 // 0: the occupancy heuristic decides.
 constexpr int kPairSubgroups[4][10] = {
-    {16, 16, 16, 16, 16, 16, 8, 4, 2, 2},
-    {16, 16, 16, 16, 16, 8, 4, 2, 2, 2},
-    {8, 8, 8, 8, 8, 4, 2, 4, 2, 2},
-    {4, 4, 4, 4, 4, 2, 4, 2, 1, 1},
+    {16, 16, 16, 16, 16, 8, 4, 4, 2, 2},
+    {16, 16, 16, 16, 16, 8, 4, 2, 1, 1},
+    {8, 8, 8, 8, 8, 4, 2, 1, 1, 1},
+    {4, 4, 4, 4, 4, 2, 1, 1, 1, 1},
 };
 
 // Force pass on cluster lists (1) or per-atom lists (0), same rows and
-// columns as kPairSubgroups.
+// columns as kPairSubgroups.  The sweep does not time cluster lists (they
+// were slower than per-atom lists at every size measured), so they stay off.
 constexpr int kClusterPairs[4][10] = {
     {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
     {0, 0, 0, 0, 0, 0, 0, 0, 0, 0},

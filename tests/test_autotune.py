@@ -1,0 +1,68 @@
+"""Host logic of the launch-shape autotuner (no GPU): the choice rules and the
+header it writes, and the committed table's shape and limits."""
+import os
+import re
+
+from paper_2602_13553_amd import autotune
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def synthetic_result(pair_time, fused_time):
+    rows = []
+    for P in autotune.BEADS:
+        for N in autotune.ATOMS:
+            rec = {"P": P, "N": N}
+            if P in autotune.MFMA_BEADS:
+                rec["fused_mfma"], rec["fused_valu"] = fused_time(P, N)
+            for S in autotune.SUBGROUPS:
+                if S * P <= 256:
+                    rec["pair_S%d" % S] = pair_time(P, N, S)
+            rows.append(rec)
+    return {"device": "test", "steps": 40, "warmup": 10, "rows": rows}
+
+
+def test_mfma_threshold_is_the_first_size_from_which_mfma_never_loses():
+    def fused(P, N):
+        # MFMA wins from N = 4096 on, except a dip at N = 8192 for P = 64
+        valu = 1e-3 * N
+        mfma = valu * (0.9 if N >= 4096 else 1.5)
+        if P == 64 and N == 8192:
+            mfma = valu * 1.1
+        return mfma, valu
+    m, _ = autotune.choose(synthetic_result(lambda P, N, S: 1.0, fused))
+    assert m == [4096 * 16, 4096 * 32, 16384 * 64]
+
+
+def test_mfma_never_winning_gives_no_threshold():
+    m, _ = autotune.choose(synthetic_result(lambda P, N, S: 1.0, lambda P, N: (2.0, 1.0)))
+    assert all(v >= 1 << 62 for v in m)
+
+
+def test_subgroups_prefer_fewest_within_two_percent():
+    def pair(P, N, S):
+        return {1: 10.0, 2: 9.9, 4: 9.0 if N == 64 else 12.0, 8: 13.0, 16: 14.0}[S]
+    _, table = autotune.choose(synthetic_result(pair, lambda P, N: (1.0, 1.0)))
+    assert len(table) == 4 and all(len(r) == 10 for r in table)
+    for r in table:
+        assert r[0] == 4          # a clear winner is taken
+        assert r[1:] == [1] * 9   # 1% slower than S = 2: a tie, fewer sub-groups win
+
+
+def test_header_text_declares_every_table():
+    res = synthetic_result(lambda P, N, S: float(S), lambda P, N: (1.0, 2.0))
+    m, t = autotune.choose(res)
+    h = autotune.header_text(res, m, t)
+    for name in ("kMfmaMinBeadAtoms[3]", "kPairSubgroups[4][10]", "kClusterPairs[4][10]"):
+        assert name in h
+    assert h.count("{1, 1, 1, 1, 1, 1, 1, 1, 1, 1}") == 4
+
+
+def test_committed_table_is_within_limits():
+    src = open(os.path.join(ROOT, "paper_2602_13553_amd", "csrc", "pimd_tuning.h")).read()
+    body = re.search(r"kPairSubgroups\[4\]\[10\] = \{(.*?)\};", src, re.S).group(1)
+    rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
+    assert len(rows) == 4 and all(len(r) == 10 for r in rows)
+    for P, r in zip(autotune.BEADS, rows):
+        for S in r:
+            assert S in autotune.SUBGROUPS and S * P <= 256
