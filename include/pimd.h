@@ -56,6 +56,10 @@ extern "C" {
 #define PIMD_POT_HARMONIC 1  /* U = sum_i 1/2 m_i omega^2 |r_i|^2 (trap at the origin) */
 #define PIMD_POT_LJ 2        /* 12-6 Lennard-Jones among all atoms, periodic box */
 #define PIMD_POT_WATER 3     /* LJ among topology-active atoms + harmonic bonds */
+#define PIMD_POT_EXTERNAL 4  /* forces from the caller (pimd_set_forces), e.g. a machine-learned
+                                potential evaluated on each bead (Sec. II: the force on bead k is
+                                minus the gradient of U at replica k; Sec. IV.A: one force call
+                                per replica per step) */
 
 typedef struct pimd_params {
     int32_t n_atoms;    /* N >= 1 */
@@ -196,6 +200,36 @@ int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
 
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);
+
+/* External forces (PIMD_POT_EXTERNAL).  The library computes no forces; the
+ * caller evaluates its potential on the P replicas of the current positions
+ * and hands back the forces, once per step (Sec. IV.A: the force call of the
+ * step, made by the caller instead of the library):
+ *
+ *   pimd_set_state(ctx, x, v, s0);
+ *   loop: pimd_get_positions(ctx, xd);  f = -dU/dx at xd (caller);
+ *         pimd_set_forces(ctx, fd, U);  pimd_step(ctx, 1);
+ *
+ * pimd_set_forces completes the pending closing half-kick of the last step
+ * (or, right after pimd_set_state, nothing) and records the estimators of the
+ * state with these forces, as pimd_step does for the library's potentials.
+ * pimd_step then takes exactly one step; pimd_get_estimators and the momenta
+ * of pimd_get_state need the forces of the current positions (STATE
+ * otherwise).  Not available in a batch. */
+
+/* Enqueue a copy of the Cartesian positions (unwrapped) into x, a [P][N][3]
+ * DEVICE array on the context's device (caller's atom order), on the
+ * context's stream; order the caller's reads after it on that stream.  Any
+ * potential.  Errors: ARG (NULL), STATE (no set_state yet), DEVICE. */
+int pimd_get_positions(pimd_ctx *ctx, double *x);
+
+/* Forces on the current positions, f [P][N][3] DEVICE array (caller's atom
+ * order; read on the context's stream, so the caller may reuse it once that
+ * stream has passed this call), and their total potential energy
+ * epot = sum_k U^(k) (App. A, item 3).  Enqueued; returns without waiting.
+ * Errors: STATE (potential not PIMD_POT_EXTERNAL, or no set_state yet),
+ * ARG (NULL f or non-finite epot), DEVICE. */
+int pimd_set_forces(pimd_ctx *ctx, const double *f, double epot);
 
 /* Per-kernel timing.  Between pimd_profile_begin and pimd_profile_end,
  * pimd_step launches its kernels directly (no graph) and brackets each one

@@ -77,6 +77,8 @@ def lib():
             "orc_forces_bead": (C.c_double, [S, d, d]),
             "orc_forces": (None, [S, d, d, d]),
             "orc_step": (None, [S, d, d, d, d, u64, C.c_int32]),
+            "orc_step_positions": (None, [S, d, d, d, u64]),
+            "orc_step_kick": (None, [S, d, d]),
             "orc_estimators": (None, [S, d, d, d, d, C.POINTER(_Est)]),
             "orc_spring_energy_nm": (C.c_double, [S, d]),
             "orc_kcv_nm": (C.c_double, [S, d, d]),
@@ -188,7 +190,8 @@ class System:
     def from_spec(cls, spec) -> "System":
         """Build from any object with the workload-spec attributes (duck-typed,
         so this package imports nothing from the product package)."""
-        pot = {0: POT_NONE, 1: POT_HARMONIC, 2: POT_PAIR, 3: POT_PAIR}[int(spec.potential)]
+        # 4: forces supplied by the caller (State.external); no built-in potential
+        pot = {0: POT_NONE, 1: POT_HARMONIC, 2: POT_PAIR, 3: POT_PAIR, 4: POT_NONE}[int(spec.potential)]
         return cls(n_atoms=spec.n_atoms, n_beads=spec.n_beads, mass=np.asarray(spec.mass),
                    temp=spec.temp, kB=spec.kB, hbar=spec.hbar, mvv2e=spec.mvv2e, dt=spec.dt,
                    tau=spec.tau, tau_scale=spec.tau_scale, nve=bool(spec.ensemble == 1),
@@ -255,6 +258,31 @@ class State:
         s = self.sys.cstruct()
         lib().orc_step(C.byref(s), _dp(self.x), _dp(self.vt), _dp(self.f), _dp(self.U),
                        self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)), int(n))
+
+    # --- forces supplied by the caller (an external potential) -----------
+    @classmethod
+    def external(cls, system: System, x: np.ndarray, v: np.ndarray, force_fn, step: int = 0) -> "State":
+        """A state whose forces come from ``force_fn(x) -> (f [P][N][3], U [P])``
+        (per-bead forces and energies) instead of the built-in potential."""
+        st = cls(system, x, v, step)
+        st._set_forces(force_fn)
+        return st
+
+    def _set_forces(self, force_fn) -> None:
+        f, U = force_fn(self.x.copy())
+        self.f = np.ascontiguousarray(f, dtype=np.float64).copy()
+        self.U = np.ascontiguousarray(U, dtype=np.float64).reshape(self.sys.n_beads).copy()
+
+    def step_external(self, force_fn, n: int = 1) -> None:
+        """n steps, each B A O A (orc_step_positions), the caller's forces at
+        the new positions, then the closing B (orc_step_kick): the step of
+        ``step`` with the force call made by ``force_fn``."""
+        s = self.sys.cstruct()
+        for _ in range(int(n)):
+            lib().orc_step_positions(C.byref(s), _dp(self.x), _dp(self.vt), _dp(self.f),
+                                     self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)))
+            self._set_forces(force_fn)
+            lib().orc_step_kick(C.byref(s), _dp(self.vt), _dp(self.f))
 
     def estimators(self) -> dict:
         e = _Est()

@@ -361,8 +361,27 @@ void orc_forces(const orc_system *sys, const double *x, double *f, double *U)
  * The noise eta for mode k, atom i, dim a at step s is orc_gaussians(seed, 0,
  * i, k, s)[a].
  * --------------------------------------------------------------------- */
-void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U,
-              uint64_t *step, int32_t nsteps)
+/* Half-kick B(h): v~ += h (M f) / m, f in energy/length, v~ in length/time. */
+static void orc_kick(const orc_system *sys, double *vt, const double *f, double *ft)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const double h = 0.5 * sys->dt;
+    const double ftm2v = 1.0 / sys->mvv2e;
+    orc_to_normal(P, N, f, ft);
+    for (int32_t k = 0; k < P; ++k)
+        for (int32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                size_t e = ((size_t)k * N + i) * 3 + d;
+                vt[e] += h * ft[e] * ftm2v / sys->mass[i];
+            }
+}
+
+/* The first part of step s: B(dt/2) with the forces f of the current
+ * positions, then A(dt/2), O(dt) with the noise of step s, A(dt/2), and the
+ * new Cartesian positions.  The step counter advances to s + 1; the closing
+ * B(dt/2) waits for the forces of the new positions (orc_step_kick). */
+void orc_step_positions(const orc_system *sys, double *x, double *vt, const double *f,
+                        uint64_t *step)
 {
     const int32_t P = sys->n_beads, N = sys->n_atoms;
     const size_t n = (size_t)P * N * 3;
@@ -370,56 +389,54 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
     const double ftm2v = 1.0 / sys->mvv2e;
     double *xt = (double *)malloc(sizeof(double) * n);
     double *ft = (double *)malloc(sizeof(double) * n);
-    double *Ah = (double *)malloc(sizeof(double) * 4 * (size_t)P);
-    double *c1 = (double *)malloc(sizeof(double) * (size_t)P);
-    double *c2 = (double *)malloc(sizeof(double) * (size_t)P);
+    double Ah[4], c1, c2;
+    const uint64_t s = *step;
+    /* B */
+    orc_kick(sys, vt, f, ft);
+    /* A, O, A */
+    orc_to_normal(P, N, x, xt);
     for (int32_t k = 0; k < P; ++k) {
-        orc_free_rp_matrix(sys, k, h, Ah + 4 * k);
-        orc_pile_coeffs(sys, k, c1 + k, c2 + k);
-    }
-
-    for (int32_t it = 0; it < nsteps; ++it) {
-        const uint64_t s = *step;
-        /* B */
-        orc_to_normal(P, N, f, ft);
-        for (int32_t k = 0; k < P; ++k)
-            for (int32_t i = 0; i < N; ++i)
-                for (int d = 0; d < 3; ++d) {
-                    size_t e = ((size_t)k * N + i) * 3 + d;
-                    vt[e] += h * ft[e] * ftm2v / sys->mass[i];
-                }
-        /* A, O, A */
-        orc_to_normal(P, N, x, xt);
-        for (int32_t k = 0; k < P; ++k) {
-            const double *A = Ah + 4 * k;
-            for (int32_t i = 0; i < N; ++i) {
-                double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
-                double z[3] = {0.0, 0.0, 0.0};
-                if (!sys->nve) orc_gaussians(sys->seed, 0, (uint64_t)i, (uint64_t)k, s, z);
-                for (int d = 0; d < 3; ++d) {
-                    size_t e = ((size_t)k * N + i) * 3 + d;
-                    double q = xt[e], p = vt[e];
-                    double q1 = A[0] * q + A[1] * p;
-                    double p1 = A[2] * q + A[3] * p;
-                    if (!sys->nve) p1 = c1[k] * p1 + c2[k] * sigma * z[d];
-                    xt[e] = A[0] * q1 + A[1] * p1;
-                    vt[e] = A[2] * q1 + A[3] * p1;
-                }
+        orc_free_rp_matrix(sys, k, h, Ah);
+        orc_pile_coeffs(sys, k, &c1, &c2);
+        for (int32_t i = 0; i < N; ++i) {
+            double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
+            double z[3] = {0.0, 0.0, 0.0};
+            if (!sys->nve) orc_gaussians(sys->seed, 0, (uint64_t)i, (uint64_t)k, s, z);
+            for (int d = 0; d < 3; ++d) {
+                size_t e = ((size_t)k * N + i) * 3 + d;
+                double q = xt[e], p = vt[e];
+                double q1 = Ah[0] * q + Ah[1] * p;
+                double p1 = Ah[2] * q + Ah[3] * p;
+                if (!sys->nve) p1 = c1 * p1 + c2 * sigma * z[d];
+                xt[e] = Ah[0] * q1 + Ah[1] * p1;
+                vt[e] = Ah[2] * q1 + Ah[3] * p1;
             }
         }
-        orc_from_normal(P, N, xt, x);
+    }
+    orc_from_normal(P, N, xt, x);
+    *step = s + 1;
+    free(xt);
+    free(ft);
+}
+
+/* The closing B(dt/2) of a step, with the forces f of the new positions. */
+void orc_step_kick(const orc_system *sys, double *vt, const double *f)
+{
+    const size_t n = (size_t)sys->n_beads * sys->n_atoms * 3;
+    double *ft = (double *)malloc(sizeof(double) * n);
+    orc_kick(sys, vt, f, ft);
+    free(ft);
+}
+
+void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U,
+              uint64_t *step, int32_t nsteps)
+{
+    for (int32_t it = 0; it < nsteps; ++it) {
+        orc_step_positions(sys, x, vt, f, step);
         /* forces at the new positions, then B */
         orc_forces(sys, x, f, U);
-        orc_to_normal(P, N, f, ft);
-        for (int32_t k = 0; k < P; ++k)
-            for (int32_t i = 0; i < N; ++i)
-                for (int d = 0; d < 3; ++d) {
-                    size_t e = ((size_t)k * N + i) * 3 + d;
-                    vt[e] += h * ft[e] * ftm2v / sys->mass[i];
-                }
-        *step = s + 1;
+        orc_step_kick(sys, vt, f);
     }
-    free(xt); free(ft); free(Ah); free(c1); free(c2);
 }
 
 /* ------------------------------------------------------------------------

@@ -99,6 +99,12 @@ void orc_forces(const orc_system *sys, const double *x, double *f, double *U);
  * counter s used in the noise counter; it is incremented once per step. */
 void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U,
               uint64_t *step, int32_t nsteps);
+/* The two parts of orc_step around the force call, for forces supplied by
+ * the caller: B A O A to the new positions (advancing the step counter),
+ * then the closing B with the new positions' forces. */
+void orc_step_positions(const orc_system *sys, double *x, double *vt, const double *f,
+                        uint64_t *step);
+void orc_step_kick(const orc_system *sys, double *vt, const double *f);
 
 /* --- estimators (App. A) ----------------------------------------------- */
 /* At a synchronized state.  U is [P] from orc_forces. */

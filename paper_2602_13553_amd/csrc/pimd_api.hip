@@ -37,6 +37,8 @@ struct Layout {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool is_pair(int pot) { return pot == PIMD_POT_LJ || pot == PIMD_POT_WATER; }
+// forces from an array (the force pass or the caller) rather than in the step pass
+bool forces_in_array(int pot) { return is_pair(pot) || pot == PIMD_POT_EXTERNAL; }
 
 }  // namespace
 
@@ -48,6 +50,10 @@ struct pimd_ctx {
     char *ws = nullptr;
     bool own_ws = false;
     bool have_state = false;
+    // external forces: the forces in d_f belong to the current positions, and
+    // the velocities are at the full step (no closing kick pending)
+    bool forces_current = true;
+    bool synced = true;
     double *d_x, *d_v, *d_f, *d_stage, *d_cent, *d_cref, *d_M, *d_MT, *d_modes, *d_atoms, *d_mass;
     double *d_partials, *d_fpartials;
     int *d_orig, *d_bond_j, *d_nbr_count;
@@ -111,7 +117,7 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
         }
     }
     if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) { why = "bad ensemble"; return PIMD_ERR_ARG; }
-    if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_WATER) { why = "bad potential"; return PIMD_ERR_ARG; }
+    if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_EXTERNAL) { why = "bad potential"; return PIMD_ERR_ARG; }
     if (!finite_pos(p->temp) || !finite_pos(p->kB) || !finite_pos(p->hbar) || !finite_pos(p->mvv2e) ||
         !finite_pos(p->dt)) {
         why = "temp, kB, hbar, mvv2e and dt must be finite and > 0";
@@ -288,7 +294,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.x = take(arr);
     L.yt = take(arr);
     L.v = take(arr);
-    L.f = take(pair ? arr : 0);
+    L.f = take(forces_in_array(p->potential) ? arr : 0);
     L.stage = take(arr);
     L.cent = take(N * 3 * sizeof(double));
     L.cref = take(N * 3 * sizeof(double));
@@ -429,7 +435,7 @@ void enqueue_fused(pimd_ctx *c, int mode, int kind)
 void enqueue_step(pimd_ctx *c)
 {
     enqueue_fused(c, FUSED_STEP, PIMD_KERNEL_FUSED);
-    if (c->fa.pair) {
+    if (c->lay.pair_grid > 0) {
         size_t e = prof_begin(c, PIMD_KERNEL_PAIR);
         launch_pair(c->pa, c->lay.pair_grid, c->stream);
         prof_end(c, e);
@@ -509,7 +515,8 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     char *w = c->ws;
     c->d_x = (double *)(w + L.x);
     c->d_v = (double *)(w + L.v);
-    c->d_f = pair ? (double *)(w + L.f) : nullptr;
+    // forces live in d_f for the pair potentials and for the caller's forces
+    c->d_f = forces_in_array(p->potential) ? (double *)(w + L.f) : nullptr;
     c->d_stage = (double *)(w + L.stage);
     c->d_cent = (double *)(w + L.cent);
     c->d_cref = (double *)(w + L.cref);
@@ -573,11 +580,14 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         e = hipMemset(w + L.cell_scnt, 0, (size_t)L.ncell * sizeof(int));
     if (e != hipSuccess) return cleanup(PIMD_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
 
+    if (forces_in_array(p->potential) && !c->d_f)
+        return cleanup(PIMD_ERR_DEVICE, "internal: no force array for a potential that needs one");
     if (L.n_clusters) set_pair_smem();
     FusedArgs &a = c->fa;
     a.N = N; a.P = P; a.n_active = n_active;
     a.mode = FUSED_STEP;
-    a.pair = pair ? 1 : 0;
+    a.pair = forces_in_array(p->potential) ? 1 : 0;
+    a.lists = pair ? 1 : 0;
     a.nvt = p->ensemble == PIMD_NVT ? 1 : 0;
     a.hdt = 0.5 * p->dt;
     a.omega2 = p->potential == PIMD_POT_HARMONIC ? p->omega * p->omega : 0.0;
@@ -592,7 +602,8 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.M = c->d_M; a.MT = c->d_MT; a.modes = c->d_modes; a.atoms = c->d_atoms; a.orig = c->d_orig;
     a.partials = c->d_partials;
     a.fpartials = c->d_fpartials;
-    a.n_fpartials = L.pair_grid;
+    // the force pass's energy partials; external forces bring one total
+    a.n_fpartials = p->potential == PIMD_POT_EXTERNAL ? 1 : L.pair_grid;
     a.ctl = c->d_ctl;
     a.ncell = L.ncell;
     a.cell_cap = L.cell_cap;
@@ -660,14 +671,20 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     a.mode = FUSED_PREP;
     launch_fused(a, c->lay.fused_grid, c->stream);
     launch_finalize(a, c->lay.fused_grid, c->stream);
-    if (a.pair) launch_pair(c->pa, c->lay.pair_grid, c->stream);
-    a.mode = FUSED_EST;
-    launch_fused(a, c->lay.fused_grid, c->stream);
-    launch_finalize(a, c->lay.fused_grid, c->stream);
+    const bool external = c->p.potential == PIMD_POT_EXTERNAL;
+    if (c->lay.pair_grid > 0) launch_pair(c->pa, c->lay.pair_grid, c->stream);
+    if (!external) {
+        // external forces: the estimators wait for the caller's forces
+        a.mode = FUSED_EST;
+        launch_fused(a, c->lay.fused_grid, c->stream);
+        launch_finalize(a, c->lay.fused_grid, c->stream);
+    }
     int rc = launch_error(c, "set_state launch");
     if (rc != PIMD_OK) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->have_state = true;
+    c->forces_current = !external;
+    c->synced = true;
     return PIMD_OK;
 }
 
@@ -677,6 +694,15 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
     if (!c->have_state) return fail(c, PIMD_ERR_STATE, "pimd_step before pimd_set_state");
     if (nsteps < 0) return fail(c, PIMD_ERR_ARG, "nsteps < 0");
     if (nsteps == 0) return PIMD_OK;
+    if (c->p.potential == PIMD_POT_EXTERNAL) {
+        if (nsteps != 1) return fail(c, PIMD_ERR_ARG, "external forces: one step per call");
+        if (!c->forces_current)
+            return fail(c, PIMD_ERR_STATE, "external forces: pimd_set_forces for the current positions first");
+        enqueue_step(c);
+        c->forces_current = false;
+        c->synced = false;
+        return launch_error(c, "step launch");
+    }
     int64_t left = nsteps;
     if (left >= kGraphChunk && !c->graph_failed && !c->profiling) {
         if (!c->graph_exec) {
@@ -703,7 +729,7 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
         }
     }
     for (; left > 0; --left) enqueue_step(c);
-    if (c->fa.pair) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
+    if (c->lay.pair_grid > 0) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
     return launch_error(c, "step launch");
 }
 
@@ -713,8 +739,8 @@ int pimd_get_launch_info(const pimd_ctx *c, pimd_launch_info *out)
     const Layout &L = c->lay;
     out->transforms = L.mfma_grid > 0 ? 1 : 0;
     out->fused_blocks = L.mfma_grid > 0 ? L.mfma_grid : L.fused_grid;
-    out->pair_subgroups = c->fa.pair ? L.pair_S : 0;
-    out->pair_blocks = c->fa.pair ? L.pair_grid : 0;
+    out->pair_subgroups = L.pair_grid > 0 ? L.pair_S : 0;
+    out->pair_blocks = L.pair_grid;
     out->cells = L.ncell;
     out->cluster_pairs = L.n_clusters > 0 ? 1 : 0;
     return PIMD_OK;
@@ -752,6 +778,8 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
     if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
     if (!out) return fail(c, PIMD_ERR_ARG, "out is NULL");
     if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    if (!c->forces_current)
+        return fail(c, PIMD_ERR_STATE, "external forces: pimd_set_forces for the current positions first");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     Ctl h;
     HIP_TRY(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
@@ -775,6 +803,8 @@ int pimd_get_state(pimd_ctx *c, double *x, double *p, uint64_t *step)
 {
     if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
     if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    if (p && !c->synced)
+        return fail(c, PIMD_ERR_STATE, "external forces: momenta need pimd_set_forces for the current positions");
     const int N = c->p.n_atoms, P = c->p.n_beads;
     const size_t n = (size_t)N * 3 * P;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -798,6 +828,35 @@ int pimd_get_state(pimd_ctx *c, double *x, double *p, uint64_t *step)
         *step = h.step;
     }
     return PIMD_OK;
+}
+
+int pimd_get_positions(pimd_ctx *c, double *x)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!x) return fail(c, PIMD_ERR_ARG, "x is NULL");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    launch_export(c->d_x, c->d_v, c->d_mass, c->d_M, c->d_orig, x, nullptr, c->p.n_atoms, c->p.n_beads,
+                  c->stream);
+    return launch_error(c, "get_positions");
+}
+
+int pimd_set_forces(pimd_ctx *c, const double *f, double epot)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (c->p.potential != PIMD_POT_EXTERNAL)
+        return fail(c, PIMD_ERR_STATE, "pimd_set_forces needs the external potential");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    if (!f) return fail(c, PIMD_ERR_ARG, "f is NULL");
+    if (!std::isfinite(epot)) return fail(c, PIMD_ERR_ARG, "epot is not finite");
+    if (!c->d_f || !c->d_fpartials) return fail(c, PIMD_ERR_STATE, "internal: no force array");
+    launch_import(f, c->d_f, c->d_orig, c->p.n_atoms, c->p.n_beads, c->stream);
+    launch_store_scalar(c->d_fpartials, epot, c->stream);
+    // a pending closing kick and the estimators of this state (or, right after
+    // set_state, the estimators alone)
+    enqueue_fused(c, c->synced ? FUSED_EST : FUSED_CLOSE, PIMD_KERNEL_CLOSE);
+    c->forces_current = true;
+    c->synced = true;
+    return launch_error(c, "set_forces launch");
 }
 
 int pimd_reset_averages(pimd_ctx *c)
@@ -1040,7 +1099,9 @@ int pimd_batch_create(void *stream, pimd_batch **out)
 int pimd_batch_add(pimd_batch *b, const pimd_params *p, const double *mass, const pimd_topology *topo,
                    int32_t *sys)
 {
-    if (!b || !sys) return bfail(b, PIMD_ERR_ARG, "NULL argument");
+    if (!b || !sys || !p) return bfail(b, PIMD_ERR_ARG, "NULL argument");
+    if (p->potential == PIMD_POT_EXTERNAL)
+        return bfail(b, PIMD_ERR_UNSUPPORTED, "external forces are not batched (the caller steps each system)");
     pimd_ctx *c = nullptr;
     int rc = pimd_create(p, mass, topo, nullptr, 0, (void *)b->stream, &c);
     if (rc != PIMD_OK) return bfail(b, rc, pimd_last_error(nullptr));

@@ -72,7 +72,8 @@ struct __attribute__((aligned(16))) CellEntry {
 struct FusedArgs {
     int N, P, n_active;
     int mode;                 // FusedMode
-    int pair;                 // 1: forces come from the pair kernel (array f)
+    int pair;                 // 1: forces come from array f (the pair kernel or the caller)
+    int lists;                // 1: neighbor lists (rebuild decisions) exist
     int nvt;                  // 1: PILE-L O step
     double hdt;               // dt / 2
     double omega2;            // external trap omega^2 (0 for none / pair)
@@ -173,6 +174,7 @@ void launch_import(const double *src, double *dst, const int *orig, int N, int P
 void launch_export(const double *x, const double *v, const double *atoms_mass, const double *M,
                    const int *orig, double *xdst, double *pdst, int N, int P, hipStream_t s);
 void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s);
+void launch_store_scalar(double *dst, double v, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, unsigned long long step, hipStream_t s);
 void launch_ctl_set_budget(Ctl *ctl, long long budget, hipStream_t s);
 

@@ -654,7 +654,7 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             c->synced = 1;
         }
         c->ran = 1;
-        const bool rebuild = a.pair && (mode == FUSED_PREP ||
+        const bool rebuild = a.lists && (mode == FUSED_PREP ||
                                         (mode == FUSED_STEP && dmax + emax > 0.5 * a.skin + ebuild));
         const double rlist = a.rc + a.skin + 2.0 * emax;
         if (rebuild) {
@@ -662,7 +662,7 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             c->ebuild = emax;
             c->rlist = rlist;
             c->n_rebuilds = n_rebuilds + 1;
-        } else if (a.pair && mode == FUSED_STEP) {
+        } else if (a.lists && mode == FUSED_STEP) {
             c->rebuild = 0;
         }
         if (bad != 0.0) c->nonfinite = 1;
@@ -672,7 +672,7 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         red[33] = rlist;
     }
     // the centroid cell lists of a rebuild (cells recorded by this pass)
-    if (a.pair && a.ncell > 0 && (mode == FUSED_STEP || mode == FUSED_PREP)) {
+    if (a.lists && a.ncell > 0 && (mode == FUSED_STEP || mode == FUSED_PREP)) {
         __syncthreads();
         const bool rb = red[32] != 0.0;
         const double rl = red[33];
@@ -1471,6 +1471,16 @@ __global__ void k_ctl_reset_sums(Ctl *c)
             c->sumsq[q] = 0.0;
         }
     }
+}
+
+__global__ void k_store_scalar(double *dst, double v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
+}
+
+void launch_store_scalar(double *dst, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_store_scalar, dim3(1), dim3(64), 0, s, dst, v);
 }
 
 __global__ void k_ctl_init(Ctl *c, unsigned long long step)

@@ -19,7 +19,7 @@ PIMD_OK = 0
 ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PIMD_ERR_STATE",
           -5: "PIMD_ERR_NONFINITE", -6: "PIMD_ERR_UNSUPPORTED", -7: "PIMD_ERR_OVERFLOW"}
 PIMD_NVT, PIMD_NVE = 0, 1
-PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER = 0, 1, 2, 3
+PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER, PIMD_POT_EXTERNAL = 0, 1, 2, 3, 4
 PIMD_FLAG_VALU_TRANSFORMS = 1
 PIMD_FLAG_MFMA_TRANSFORMS = 2
 PIMD_FLAG_CLUSTER_PAIRS = 4
@@ -33,7 +33,8 @@ def PIMD_PAIR_SUBGROUPS(S: int) -> int:
     return code << PIMD_PAIR_SUBGROUPS_SHIFT
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
-            "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_destroy",
+            "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_get_positions",
+            "pimd_set_forces", "pimd_destroy",
             "pimd_last_error", "pimd_profile_begin", "pimd_profile_end", "pimd_get_launch_info",
             "pimd_batch_create", "pimd_batch_add", "pimd_batch_remove", "pimd_batch_set_state",
             "pimd_batch_set_budget", "pimd_batch_step", "pimd_batch_get_estimators",
@@ -104,6 +105,8 @@ def load() -> C.CDLL:
         lib.pimd_get_estimators.argtypes = [C.c_void_p, P(pimd_estimators)]
         lib.pimd_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_uint64)]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
+        lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
+        lib.pimd_set_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         lib.pimd_destroy.argtypes = [C.c_void_p]
         lib.pimd_destroy.restype = None
         lib.pimd_profile_begin.argtypes = [C.c_void_p]
@@ -273,6 +276,23 @@ class Context:
 
     def reset_averages(self) -> None:
         self._check(self._lib.pimd_reset_averages(self._h), self._h)
+
+    def _device_array(self, t) -> C.c_void_p:
+        import torch
+        assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+        assert t.is_contiguous() and tuple(t.shape) == (self.P, self.N, 3)
+        return C.c_void_p(t.data_ptr())
+
+    def get_positions(self, out) -> None:
+        """Enqueue a copy of the positions into ``out`` (float64 CUDA tensor
+        [P][N][3]); synchronize (e.g. ``torch.cuda.synchronize()``) before
+        reading it."""
+        self._check(self._lib.pimd_get_positions(self._h, self._device_array(out)), self._h)
+
+    def set_forces(self, f, epot: float) -> None:
+        """External potential: forces (float64 CUDA tensor [P][N][3]) on the
+        current positions and their total energy sum_k U^(k)."""
+        self._check(self._lib.pimd_set_forces(self._h, self._device_array(f), float(epot)), self._h)
 
     def close(self) -> None:
         if getattr(self, "_h", None):

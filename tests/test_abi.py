@@ -74,6 +74,25 @@ def test_create_rejects_bad_parameters_without_gpu():
     assert lib.pimd_create(C.byref(bad), pimd._dp(mass), None, None, 0, None, C.byref(h)) == -1
 
 
+def test_external_potential_is_accepted_without_gpu():
+    """PIMD_POT_EXTERNAL (forces from the caller) needs no box or pair
+    parameters; the next code is rejected."""
+    lib = pimd.load()
+    spec = inputs.harmonic_tiny()
+    mass = np.ascontiguousarray(spec.mass)
+    n = C.c_size_t()
+    p = pimd.params_from_spec(spec)
+    p.potential = pimd.PIMD_POT_EXTERNAL
+    assert lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n)) == 0
+    n_ext = n.value
+    p.potential = pimd.PIMD_POT_HARMONIC
+    assert lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n)) == 0
+    assert n_ext > n.value            # room for the caller's forces
+    p.potential = pimd.PIMD_POT_EXTERNAL + 1
+    assert lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n)) == -1
+    assert "#define PIMD_POT_EXTERNAL %d" % pimd.PIMD_POT_EXTERNAL in open(HEADER).read()
+
+
 def test_flags_are_validated_without_gpu():
     """Launch-shape flags: unknown bits and sub-group counts beyond one block fail."""
     lib = pimd.load()

@@ -1,0 +1,135 @@
+"""External forces (an MLIP-style caller potential) through the C ABI: the
+library's step with the caller's forces against the oracle's step with the
+same force field, element by element; and the call-order errors.
+
+The force field is a per-bead anharmonic trap evaluated in numpy on each
+side's own positions (the GPU side reads its positions back with
+pimd_get_positions), so no expected value comes from the GPU path."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_13553_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _pimd():
+    from paper_2602_13553_amd import pimd
+    return pimd
+
+
+def quartic_trap(x, a=0.7, b=0.05):
+    r2 = (x * x).sum(axis=2)
+    U = (a * r2 + b * r2 * r2).sum(axis=1)
+    f = -(2.0 * a + 4.0 * b * r2)[..., None] * x
+    return f, U
+
+
+def external_spec(N, P, seed, ensemble=inputs.NVT):
+    spec = inputs.harmonic_tiny(n_atoms=N, n_beads=P, seed=seed, ensemble=ensemble)
+    return dataclasses.replace(spec, potential=_pimd().PIMD_POT_EXTERNAL, omega=0.0,
+                               name="external N=%d P=%d" % (N, P))
+
+
+def gpu_forces(ctx, xd, torch):
+    ctx.get_positions(xd)
+    torch.cuda.synchronize()
+    f, U = quartic_trap(xd.cpu().numpy())
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    torch.cuda.synchronize()
+    ctx.set_forces(fd, float(U.sum()))
+    return fd
+
+
+def run_external(spec, nsteps, flags=0):
+    import torch
+    pimd = _pimd()
+    print("case %s nsteps=%d flags=%d" % (spec.name, nsteps, flags), flush=True)
+    sys.stdout.flush()
+    ctx = pimd.Context.from_spec(spec, flags=flags)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    xd = torch.empty((spec.n_beads, spec.n_atoms, 3), dtype=torch.float64, device="cuda")
+    fd = gpu_forces(ctx, xd, torch)
+    for _ in range(nsteps):
+        ctx.step(1)
+        fd = gpu_forces(ctx, xd, torch)
+    est = ctx.estimators()
+    gx, gp, gs = ctx.get_state()
+    del fd
+    ctx.close()
+    st = oracle.State.external(oracle.System.from_spec(spec), spec.x0, spec.v0, quartic_trap)
+    st.step_external(quartic_trap, nsteps)
+    return (gx, gp, gs, est), (st.x, st.p, int(st.step_count[0]), st.estimators())
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("N,P,mfma", [(37, 8, False), (33, 7, False), (70, 32, True), (20, 64, True)])
+def test_external_forces_match_oracle(N, P, mfma):
+    pimd = _pimd()
+    spec = external_spec(N, P, seed=11 * N + P)
+    g, o = run_external(spec, 10, pimd.PIMD_FLAG_MFMA_TRANSFORMS if mfma else 0)
+    gx, gp, gs, gest = g
+    ox, op, os_, oest = o
+    assert gs == os_ == 10
+    print("  x rel %.3e  p rel %.3e" % (rel(gx, ox), rel(gp, op)), flush=True)
+    assert rel(gx, ox) <= TOL and rel(gp, op) <= TOL
+    scale = max(abs(oest["ekin"]), abs(oest["espring"]), abs(oest["epot"]))
+    for name in ("ekin", "espring", "epot", "etot", "kprim", "kcv"):
+        assert abs(gest[name] - oest[name]) <= 1e-10 * scale, name
+    # one accumulation per step (the set_state estimators are not summed)
+    assert gest["count"] == 10
+
+
+def test_external_forces_call_order():
+    import torch
+    pimd = _pimd()
+    spec = external_spec(12, 4, seed=3)
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    with pytest.raises(pimd.PimdError) as e:
+        ctx.step(1)                      # no forces for the current positions
+    assert e.value.code == -4
+    with pytest.raises(pimd.PimdError) as e:
+        ctx.estimators()
+    assert e.value.code == -4
+    xd = torch.empty((4, 12, 3), dtype=torch.float64, device="cuda")
+    fd = gpu_forces(ctx, xd, torch)
+    with pytest.raises(pimd.PimdError) as e:
+        ctx.step(2)                      # one step per call
+    assert e.value.code == -1
+    ctx.step(1)
+    with pytest.raises(pimd.PimdError) as e:
+        ctx.get_state()                  # momenta need the new forces
+    assert e.value.code == -4
+    fd = gpu_forces(ctx, xd, torch)
+    x, p, s = ctx.get_state()
+    assert s == 1 and np.isfinite(x).all() and np.isfinite(p).all()
+    with pytest.raises(pimd.PimdError) as e:
+        ctx.set_forces(fd, float("nan"))
+    assert e.value.code == -1
+    torch.cuda.synchronize()
+    del fd
+    ctx.close()
+    # forces cannot be set on a built-in potential, and external systems are not batched
+    lj = inputs.lj_liquid(n_atoms=64, n_beads=4, seed=1)
+    c2 = pimd.Context.from_spec(lj)
+    c2.set_state(lj.x0, lj.v0, 0)
+    f0 = torch.zeros((4, 64, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(pimd.PimdError) as e:
+        c2.set_forces(f0, 0.0)
+    assert e.value.code == -4
+    c2.close()
+    b = pimd.Batch()
+    with pytest.raises(pimd.PimdError) as e:
+        b.add(spec)
+    assert e.value.code == -6
+    b.close()

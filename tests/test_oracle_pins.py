@@ -248,6 +248,55 @@ def test_p1_is_velocity_verlet():
     assert np.abs(st.v[0] - vv).max() < 1e-11
 
 
+def _quartic_trap(x, a=0.7, b=0.05):
+    """Per-bead anharmonic trap U = sum_i a r^2 + b r^4: a caller-side force
+    field for the external-force mode (forces and per-bead energies)."""
+    r2 = (x * x).sum(axis=2)
+    U = (a * r2 + b * r2 * r2).sum(axis=1)
+    f = -(2.0 * a + 4.0 * b * r2)[..., None] * x
+    return f, U
+
+
+def test_external_forces_p1_is_velocity_verlet():
+    """Forces from a caller-side function (P = 1, NVE): textbook velocity
+    Verlet on that force field, written out here."""
+    rng = np.random.default_rng(4)
+    N, dt = 9, 0.01
+    s = oracle.System(n_atoms=N, n_beads=1, mass=np.full(N, 1.3), temp=1.0, pot=oracle.POT_NONE,
+                      nve=True, dt=dt)
+    x = rng.standard_normal((1, N, 3))
+    v = rng.standard_normal((1, N, 3))
+    st = oracle.State.external(s, x, v, _quartic_trap)
+    st.step_external(_quartic_trap, 40)
+    xv, vv = x[0].copy(), v[0].copy()
+    a = _quartic_trap(xv[None])[0][0] / 1.3
+    for _ in range(40):
+        xv = xv + dt * vv + 0.5 * dt * dt * a
+        a2 = _quartic_trap(xv[None])[0][0] / 1.3
+        vv = vv + 0.5 * dt * (a + a2)
+        a = a2
+    assert np.abs(st.x[0] - xv).max() < 1e-12
+    assert np.abs(st.v[0] - vv).max() < 1e-12
+    assert int(st.step_count[0]) == 40
+
+
+def test_external_forces_equal_builtin_step():
+    """The built-in potential supplied as an external force field gives the
+    built-in step bit for bit (the split step is the step)."""
+    s, x = _lj_box(N=20, L=5.8, seed=5, P=4)
+    s.temp, s.hbar, s.dt, s.seed = 0.8, 0.2, 0.002, 77
+    rng = np.random.default_rng(2)
+    x4 = x[None] + 0.02 * rng.standard_normal((4, 20, 3))
+    v4 = rng.standard_normal((4, 20, 3))
+    a = oracle.State(s, x4, v4, 3)
+    a.step(6)
+    b = oracle.State.external(s, x4, v4, s.forces, 3)
+    b.step_external(s.forces, 6)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.vt, b.vt)
+    assert int(a.step_count[0]) == int(b.step_count[0]) == 9
+    assert a.estimators() == b.estimators()
+
+
 def test_free_ring_polymer_nve_conserves_h():
     spec = inputs.free_ring_polymer(n_atoms=6, n_beads=8, dt=0.05)
     st = oracle.State.from_spec(spec)
