@@ -206,6 +206,43 @@ def bench_batched(n_systems, steps, seed=20260213):
             "speedup": ts / tb}
 
 
+def bench_external(steps=500, warmup=50):
+    """External-force mode on the LJ liquid's shape (N=4000, P=32): the
+    library's share of a step (positions out, forces in, one step), with the
+    caller's force evaluation replaced by a fixed device array."""
+    import dataclasses
+    import torch
+    from paper_2602_13553_amd import pimd
+    lj = inputs.lj_liquid()
+    spec = dataclasses.replace(lj, potential=pimd.PIMD_POT_EXTERNAL, box=(0.0, 0.0, 0.0))
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    xd = torch.empty((spec.n_beads, spec.n_atoms, 3), dtype=torch.float64, device="cuda")
+    fd = torch.zeros_like(xd)
+    torch.cuda.synchronize()
+
+    def one():
+        ctx.get_positions(xd)
+        ctx.set_forces(fd, 0.0)
+        ctx.step(1)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    ctx.get_positions(xd)
+    ctx.set_forces(fd, 0.0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.close()
+    return {"workload": "external forces, N=4000, P=32 (library share: positions out, forces in, "
+                        "one step; the caller's force evaluation excluded)",
+            "ms_per_step": ms, "bead_atom_steps_per_s": spec.bead_atoms * 1e3 / ms,
+            "steps": steps}
+
+
 def bench_serving(n_jobs, seed=20260213):
     """Poisson arrivals at 20 jobs/s (harmonic, LJ or water-shaped; N
     log-uniform in [256, 32768]; P from {8..64}; 200-5000 steps), admitted under
@@ -334,6 +371,8 @@ def main():
                                                          "valu": av["fused"][0]}
 
     if not args.no_batch:
+        log("external forces")
+        out["external_forces"] = bench_external()
         log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))
         out["batched"] = bench_batched(args.batch_systems, args.batch_steps)
     if not args.no_serve:

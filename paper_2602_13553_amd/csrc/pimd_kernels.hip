@@ -393,19 +393,21 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
 // Batched: item (system, tile); the system's arguments come from the table and
 // its partials are per tile.  Items are grouped by system, so the matrix is
 // restaged only when the system changes.
-__global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *table, const int2 *items,
-                                                        int n_items, int mode)
+__global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *__restrict__ table,
+                                                        const int2 *__restrict__ items, int n_items,
+                                                        int mode)
 {
     extern __shared__ double smem[];
     __shared__ double red[64];
     int prev = -1;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 item = items[it];
-        FusedArgs a = table[item.x];
+        // the item is the same for the whole block: scalar loads of its arguments
+        const int sys = __builtin_amdgcn_readfirstlane(items[it].x);
+        const int tile = __builtin_amdgcn_readfirstlane(items[it].y);
+        FusedArgs a = table[sys];
         a.mode = mode;
-        fused_tiles(a, item.y, 1 << 30, smem, red, a.partials + (size_t)item.y * PF_COUNT,
-                    item.x != prev);
-        prev = item.x;
+        fused_tiles(a, tile, 1 << 30, smem, red, a.partials + (size_t)tile * PF_COUNT, sys != prev);
+        prev = sys;
     }
 }
 
@@ -1318,9 +1320,25 @@ __global__ __launch_bounds__(kBlock) void k_pair_clusters(PairArgs a)
         pair_tile(a, tile, s_cnt, red, s_f);
 }
 
-// Batched: one (system, tile) item per block iteration.
-__global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *table, const int2 *items,
-                                                       int n_items)
+// Batched: one (system, tile) item per block (grid = item count).  Per-atom
+// lists only, so that the kernel keeps the per-atom kernel's register budget.
+__global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *__restrict__ table,
+                                                       const int2 *__restrict__ items, int n_items)
+{
+    __shared__ int s_cnt[kBlock];
+    __shared__ double red[64];
+    __shared__ double s_f[kBlock * 3];
+    if ((int)blockIdx.x >= n_items) return;
+    // the item is the same for the whole block: scalar loads of its arguments
+    const int sys = __builtin_amdgcn_readfirstlane(items[blockIdx.x].x);
+    const int tile = __builtin_amdgcn_readfirstlane(items[blockIdx.x].y);
+    const PairArgs a = table[sys];
+    pair_tile(a, tile, s_cnt, red, s_f);
+}
+
+// The same with cluster lists for the systems that use them.
+__global__ __launch_bounds__(kBlock) void k_pair_batch_clusters(const PairArgs *table,
+                                                                const int2 *items, int n_items)
 {
     __shared__ int s_cnt[kBlock];
     __shared__ double red[64];
@@ -1380,8 +1398,11 @@ void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys,
 void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
                        bool clusters, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pair_batch, dim3(grid), dim3(kBlock), clusters ? kClusterSmem : 0, s, table,
-                       items, n_items);
+    if (clusters)
+        hipLaunchKernelGGL(k_pair_batch_clusters, dim3(grid), dim3(kBlock), kClusterSmem, s, table,
+                           items, n_items);
+    else
+        hipLaunchKernelGGL(k_pair_batch, dim3(n_items), dim3(kBlock), 0, s, table, items, n_items);
 }
 
 void set_batch_smem(int smem_bytes)
@@ -1395,8 +1416,8 @@ void set_pair_smem()
 {
     (void)hipFuncSetAttribute((const void *)k_pair_clusters, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kClusterSmem);
-    (void)hipFuncSetAttribute((const void *)k_pair_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kClusterSmem);
+    (void)hipFuncSetAttribute((const void *)k_pair_batch_clusters,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kClusterSmem);
 }
 
 void launch_pair(const PairArgs &a, int grid, hipStream_t s)
