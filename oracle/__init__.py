@@ -48,6 +48,7 @@ class _System(C.Structure):
         ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("mass", C.POINTER(C.c_double)), ("lj_active", C.POINTER(C.c_int32)),
         ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32)),
+        ("atom_id", C.POINTER(C.c_int64)),
     ]
 
 
@@ -162,6 +163,7 @@ class System:
     bond_r0: float = 0.0
     lj_active: np.ndarray | None = None
     bonds: np.ndarray | None = None
+    atom_id: np.ndarray | None = None   # noise-counter index per atom (None: 0..N-1)
     _c: _System = field(default=None, init=False, repr=False)
 
     def cstruct(self) -> _System:
@@ -183,6 +185,10 @@ class System:
             self._bonds = np.ascontiguousarray(self.bonds, dtype=np.int32).reshape(-1, 2)
             s.n_bonds = self._bonds.shape[0]
             s.bonds = self._bonds.ctypes.data_as(C.POINTER(C.c_int32))
+        if self.atom_id is not None:
+            self._aid = np.ascontiguousarray(self.atom_id, dtype=np.int64)
+            assert self._aid.shape == (self.n_atoms,)
+            s.atom_id = self._aid.ctypes.data_as(C.POINTER(C.c_int64))
         self._c = s
         return s
 

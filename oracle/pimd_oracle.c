@@ -401,7 +401,8 @@ void orc_step_positions(const orc_system *sys, double *x, double *vt, const doub
         for (int32_t i = 0; i < N; ++i) {
             double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
             double z[3] = {0.0, 0.0, 0.0};
-            if (!sys->nve) orc_gaussians(sys->seed, 0, (uint64_t)i, (uint64_t)k, s, z);
+            const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
+            if (!sys->nve) orc_gaussians(sys->seed, 0, id, (uint64_t)k, s, z);
             for (int d = 0; d < 3; ++d) {
                 size_t e = ((size_t)k * N + i) * 3 + d;
                 double q = xt[e], p = vt[e];

@@ -56,6 +56,9 @@ typedef struct orc_system {
     const int32_t *lj_active; /* [N] 0/1, or NULL = every atom */
     int32_t n_bonds;
     const int32_t *bonds;   /* [n_bonds][2] atom pairs */
+    const int64_t *atom_id; /* [N] each atom's index in the noise counter, or NULL = its
+                               position; lets a sample of a system of independent atoms
+                               (trap, free) be stepped alone with its original noise */
 } orc_system;
 
 typedef struct orc_est {

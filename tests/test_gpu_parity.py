@@ -80,6 +80,34 @@ def test_harmonic_ragged_and_odd(N, P):
     check_states(g, o)
 
 
+def test_max_beads_large_system_sampled():
+    """P = 128 (the largest this build takes) on 2^19 trapped atoms: 2^26
+    bead*atoms, 1.6 GB per state array, grids far past one wave of blocks.
+    The atoms of a trap do not interact, so the oracle steps a sample of them
+    alone, with their own indices in the noise counter, and the GPU's
+    positions and momenta of those atoms must match element by element."""
+    pimd = _pimd()
+    N, P, nsteps = 1 << 19, 128, 2
+    spec = inputs.harmonic_tiny(n_atoms=N, n_beads=P, seed=5)
+    _say("case harmonic N=%d P=%d nsteps=%d" % (N, P, nsteps))
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    ctx.step(nsteps)
+    est = ctx.estimators()
+    gx, gp, gs = ctx.get_state()
+    ctx.close()
+    assert gs == nsteps and est["nonfinite"] == 0
+    idx = np.sort(np.random.default_rng(1).choice(N, 48, replace=False))
+    idx = np.concatenate([[0, 1], idx, [N - 2, N - 1]])
+    sub = oracle.System.from_spec(spec)
+    sub.n_atoms, sub.mass, sub.atom_id = len(idx), np.asarray(spec.mass)[idx], idx
+    st = oracle.State(sub, spec.x0[:, idx], spec.v0[:, idx])
+    st.step(nsteps)
+    ex, ep = rel_err(gx[:, idx], st.x), rel_err(gp[:, idx], st.p)
+    _say("  sampled x rel %.3e  p rel %.3e" % (ex, ep))
+    assert ex <= TOL and ep <= TOL
+
+
 def test_free_ring_polymer_nve():
     spec = inputs.free_ring_polymer(n_atoms=29, n_beads=8, dt=0.05)
     g, o = run_pair(spec, 200)

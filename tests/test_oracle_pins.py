@@ -410,3 +410,24 @@ def test_free_rp_nvt_mode_variances_exact():
     for k in range(P):
         m, se = _block_mean((vs[:, k] ** 2).mean(axis=(1, 2)))
         assert abs(m - P * kT) < 4 * se, (k, m, se)
+
+
+def test_atom_ids_step_a_sample_of_independent_atoms():
+    """In a harmonic trap the atoms do not interact, so a sample of them stepped
+    alone with their own indices in the noise counter gives exactly their part
+    of the whole system's step."""
+    spec = inputs.harmonic_tiny(n_atoms=40, n_beads=8, seed=21)
+    full = oracle.State.from_spec(spec)
+    full.step(7)
+    idx = np.array([3, 17, 18, 39])
+    sub = oracle.System.from_spec(spec)
+    sub.n_atoms, sub.mass, sub.atom_id = len(idx), np.asarray(spec.mass)[idx], idx
+    part = oracle.State(sub, spec.x0[:, idx], spec.v0[:, idx])
+    part.step(7)
+    assert np.array_equal(part.x, full.x[:, idx])
+    assert np.array_equal(part.vt, full.vt[:, idx])
+    # without the ids the sample draws other noise
+    sub.atom_id = None
+    other = oracle.State(sub, spec.x0[:, idx], spec.v0[:, idx])
+    other.step(7)
+    assert not np.array_equal(other.x, full.x[:, idx])
