@@ -84,7 +84,19 @@ typedef struct pimd_params {
     double bond_r0;
     int32_t nbr_capacity; /* neighbors per atom; 0 = sized from the density */
     int32_t flags;        /* PIMD_FLAG_* (0 = defaults) */
+    int32_t integrator;   /* PIMD_BAOAB (0) or PIMD_OBABO (1) */
 } pimd_params;
+
+/* integrator: the Trotter splitting of one step (Sec. III.C; the paper's
+ * example input uses OBABO).
+ *   PIMD_BAOAB  B(dt/2) A(dt/2) O(dt) A(dt/2) B(dt/2); one noise draw per step,
+ *               counter (atom, mode, step, 0)
+ *   PIMD_OBABO  O(dt/2) B(dt/2) A(dt) B(dt/2) O(dt/2); A(dt) is A(dt/2) twice;
+ *               the two half-step O use counters (atom, mode, step, 0) and
+ *               (atom, mode, step, 1), with c1 = exp(-dt/(2 tau_k))
+ * In both the estimators are taken at the end of the step. */
+#define PIMD_BAOAB 0
+#define PIMD_OBABO 1
 
 /* flags.  By default the launch shapes come from the library's tuning table
  * (measured on MI355X by paper_2602_13553_amd/autotune.py): the step pass

@@ -48,7 +48,7 @@ class _System(C.Structure):
         ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("mass", C.POINTER(C.c_double)), ("lj_active", C.POINTER(C.c_int32)),
         ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32)),
-        ("atom_id", C.POINTER(C.c_int64)),
+        ("atom_id", C.POINTER(C.c_int64)), ("integrator", C.c_int32),
     ]
 
 
@@ -73,13 +73,14 @@ def lib():
             "orc_from_normal": (None, [C.c_int32, C.c_int32, d, d]),
             "orc_philox4x64_10": (None, [u64, u64, u64]),
             "orc_gaussians": (None, [C.c_uint64] * 5 + [d]),
+            "orc_gaussians_q": (None, [C.c_uint64] * 6 + [d]),
             "orc_free_rp_matrix": (None, [S, C.c_int32, C.c_double, d]),
             "orc_pile_coeffs": (None, [S, C.c_int32, d, d]),
             "orc_forces_bead": (C.c_double, [S, d, d]),
             "orc_forces": (None, [S, d, d, d]),
             "orc_step": (None, [S, d, d, d, d, u64, C.c_int32]),
             "orc_step_positions": (None, [S, d, d, d, u64]),
-            "orc_step_kick": (None, [S, d, d]),
+            "orc_step_kick": (None, [S, d, d, C.c_uint64]),
             "orc_estimators": (None, [S, d, d, d, d, C.POINTER(_Est)]),
             "orc_spring_energy_nm": (C.c_double, [S, d]),
             "orc_kcv_nm": (C.c_double, [S, d, d]),
@@ -132,9 +133,9 @@ def philox4x64_10(ctr, key) -> list[int]:
     return [int(v) for v in o]
 
 
-def gaussians(seed: int, tag: int, i: int, k: int, s: int) -> np.ndarray:
+def gaussians(seed: int, tag: int, i: int, k: int, s: int, q: int = 0) -> np.ndarray:
     z = np.zeros(3)
-    lib().orc_gaussians(seed, tag, i, k, s, _dp(z))
+    lib().orc_gaussians_q(seed, tag, i, k, s, q, _dp(z))
     return z
 
 
@@ -164,6 +165,7 @@ class System:
     lj_active: np.ndarray | None = None
     bonds: np.ndarray | None = None
     atom_id: np.ndarray | None = None   # noise-counter index per atom (None: 0..N-1)
+    integrator: int = 0                 # 0: BAOAB, 1: OBABO
     _c: _System = field(default=None, init=False, repr=False)
 
     def cstruct(self) -> _System:
@@ -177,6 +179,7 @@ class System:
         s.omega = self.omega
         s.lj_eps, s.lj_sigma, s.lj_rc = self.lj_eps, self.lj_sigma, self.lj_rc
         s.bond_k, s.bond_r0 = self.bond_k, self.bond_r0
+        s.integrator = int(self.integrator)
         s.mass = _dp(self._mass)
         if self.lj_active is not None:
             self._act = np.ascontiguousarray(self.lj_active, dtype=np.int32)
@@ -204,7 +207,7 @@ class System:
                    pot=pot, box=tuple(spec.box), seed=spec.seed, omega=spec.omega,
                    lj_eps=spec.lj_eps, lj_sigma=spec.lj_sigma, lj_rc=spec.lj_rc,
                    bond_k=spec.bond_k, bond_r0=spec.bond_r0, lj_active=spec.lj_active,
-                   bonds=spec.bonds)
+                   bonds=spec.bonds, integrator=int(getattr(spec, "integrator", 0)))
 
     # --- per-function wrappers -------------------------------------------
     def free_rp_matrix(self, k: int, h: float) -> np.ndarray:
@@ -288,7 +291,7 @@ class State:
             lib().orc_step_positions(C.byref(s), _dp(self.x), _dp(self.vt), _dp(self.f),
                                      self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)))
             self._set_forces(force_fn)
-            lib().orc_step_kick(C.byref(s), _dp(self.vt), _dp(self.f))
+            lib().orc_step_kick(C.byref(s), _dp(self.vt), _dp(self.f), int(self.step_count[0]) - 1)
 
     def estimators(self) -> dict:
         e = _Est()

@@ -173,7 +173,13 @@ static double u01_open0(uint64_t w)
 void orc_gaussians(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s,
                    double z[3])
 {
-    uint64_t ctr[4] = {i, k, s, 0};
+    orc_gaussians_q(seed, tag, i, k, s, 0, z);
+}
+
+void orc_gaussians_q(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s, uint64_t q,
+                     double z[3])
+{
+    uint64_t ctr[4] = {i, k, s, q};
     uint64_t key[2] = {seed, tag};
     uint64_t w[4];
     orc_philox4x64_10(ctr, key, w);
@@ -223,7 +229,9 @@ void orc_pile_coeffs(const orc_system *sys, int32_t k, double *c1, double *c2)
 {
     if (sys->nve) { *c1 = 1.0; *c2 = 0.0; return; }
     double tau_k = (k == 0) ? sys->tau : sys->tau_scale / (2.0 * omega_k(sys, k));
-    double a = exp(-sys->dt / tau_k);
+    /* the O step lasts dt in BAOAB and dt/2 for each of OBABO's two */
+    double t_o = (sys->integrator == 1) ? 0.5 * sys->dt : sys->dt;
+    double a = exp(-t_o / tau_k);
     *c1 = a;
     *c2 = sqrt(1.0 - a * a);
 }
@@ -376,6 +384,61 @@ static void orc_kick(const orc_system *sys, double *vt, const double *f, double 
             }
 }
 
+/* O step q of step s alone (OBABO): v~ <- c1 v~ + c2 sigma z, mode by mode. */
+static void orc_o_step(const orc_system *sys, double *vt, uint64_t s, uint64_t q)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const double ftm2v = 1.0 / sys->mvv2e;
+    if (sys->nve) return;
+    for (int32_t k = 0; k < P; ++k) {
+        double c1, c2;
+        orc_pile_coeffs(sys, k, &c1, &c2);
+        for (int32_t i = 0; i < N; ++i) {
+            double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
+            const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
+            double z[3];
+            orc_gaussians_q(sys->seed, 0, id, (uint64_t)k, s, q, z);
+            for (int d = 0; d < 3; ++d) {
+                size_t e = ((size_t)k * N + i) * 3 + d;
+                vt[e] = c1 * vt[e] + c2 * sigma * z[d];
+            }
+        }
+    }
+}
+
+/* OBABO's first part of step s: O(dt/2) (q = 0), B(dt/2) with the current
+ * positions' forces, A(dt) as A(dt/2) twice, and the new positions. */
+static void orc_step_positions_obabo(const orc_system *sys, double *x, double *vt,
+                                     const double *f, uint64_t *step)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double h = 0.5 * sys->dt;
+    double *xt = (double *)malloc(sizeof(double) * n);
+    double *ft = (double *)malloc(sizeof(double) * n);
+    double Ah[4];
+    const uint64_t s = *step;
+    orc_o_step(sys, vt, s, 0);
+    orc_kick(sys, vt, f, ft);
+    orc_to_normal(P, N, x, xt);
+    for (int32_t k = 0; k < P; ++k) {
+        orc_free_rp_matrix(sys, k, h, Ah);
+        for (int32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                size_t e = ((size_t)k * N + i) * 3 + d;
+                for (int rep = 0; rep < 2; ++rep) {
+                    double q = xt[e], p = vt[e];
+                    xt[e] = Ah[0] * q + Ah[1] * p;
+                    vt[e] = Ah[2] * q + Ah[3] * p;
+                }
+            }
+    }
+    orc_from_normal(P, N, xt, x);
+    *step = s + 1;
+    free(xt);
+    free(ft);
+}
+
 /* The first part of step s: B(dt/2) with the forces f of the current
  * positions, then A(dt/2), O(dt) with the noise of step s, A(dt/2), and the
  * new Cartesian positions.  The step counter advances to s + 1; the closing
@@ -383,6 +446,10 @@ static void orc_kick(const orc_system *sys, double *vt, const double *f, double 
 void orc_step_positions(const orc_system *sys, double *x, double *vt, const double *f,
                         uint64_t *step)
 {
+    if (sys->integrator == 1) {
+        orc_step_positions_obabo(sys, x, vt, f, step);
+        return;
+    }
     const int32_t P = sys->n_beads, N = sys->n_atoms;
     const size_t n = (size_t)P * N * 3;
     const double h = 0.5 * sys->dt;
@@ -420,12 +487,14 @@ void orc_step_positions(const orc_system *sys, double *x, double *vt, const doub
     free(ft);
 }
 
-/* The closing B(dt/2) of a step, with the forces f of the new positions. */
-void orc_step_kick(const orc_system *sys, double *vt, const double *f)
+/* The closing B(dt/2) of step s, with the forces f of the new positions, and
+ * for OBABO the step's second O(dt/2) (q = 1). */
+void orc_step_kick(const orc_system *sys, double *vt, const double *f, uint64_t s)
 {
     const size_t n = (size_t)sys->n_beads * sys->n_atoms * 3;
     double *ft = (double *)malloc(sizeof(double) * n);
     orc_kick(sys, vt, f, ft);
+    if (sys->integrator == 1) orc_o_step(sys, vt, s, 1);
     free(ft);
 }
 
@@ -434,9 +503,9 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
 {
     for (int32_t it = 0; it < nsteps; ++it) {
         orc_step_positions(sys, x, vt, f, step);
-        /* forces at the new positions, then B */
+        /* forces at the new positions, then B (and OBABO's last O) */
         orc_forces(sys, x, f, U);
-        orc_step_kick(sys, vt, f);
+        orc_step_kick(sys, vt, f, *step - 1);
     }
 }
 

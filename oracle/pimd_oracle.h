@@ -59,6 +59,7 @@ typedef struct orc_system {
     const int64_t *atom_id; /* [N] each atom's index in the noise counter, or NULL = its
                                position; lets a sample of a system of independent atoms
                                (trap, free) be stepped alone with its original noise */
+    int32_t integrator;     /* 0: BAOAB; 1: OBABO (O(dt/2) B(dt/2) A(dt) B(dt/2) O(dt/2)) */
 } orc_system;
 
 typedef struct orc_est {
@@ -85,6 +86,10 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 /* three standard normal deviates for (seed, tag) and counter (i, k, s, 0) */
 void orc_gaussians(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s,
                    double z[3]);
+/* The same for O step q of step s (0, or 1 for OBABO's second O): counter
+ * (i, k, s, q). */
+void orc_gaussians_q(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s, uint64_t q,
+                     double z[3]);
 
 /* --- free ring-polymer propagator and thermostat coefficients ---------- */
 /* A(h) for mode k: [[a00, a01], [a10, a11]] acting on (x~, v~) */
@@ -107,7 +112,7 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
  * then the closing B with the new positions' forces. */
 void orc_step_positions(const orc_system *sys, double *x, double *vt, const double *f,
                         uint64_t *step);
-void orc_step_kick(const orc_system *sys, double *vt, const double *f);
+void orc_step_kick(const orc_system *sys, double *vt, const double *f, uint64_t s);
 
 /* --- estimators (App. A) ----------------------------------------------- */
 /* At a synchronized state.  U is [P] from orc_forces. */

@@ -117,6 +117,7 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
         }
     }
     if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) { why = "bad ensemble"; return PIMD_ERR_ARG; }
+    if (p->integrator != PIMD_BAOAB && p->integrator != PIMD_OBABO) { why = "bad integrator"; return PIMD_ERR_ARG; }
     if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_EXTERNAL) { why = "bad potential"; return PIMD_ERR_ARG; }
     if (!finite_pos(p->temp) || !finite_pos(p->kB) || !finite_pos(p->hbar) || !finite_pos(p->mvv2e) ||
         !finite_pos(p->dt)) {
@@ -356,8 +357,9 @@ std::vector<double> nm_matrix(int P)
 
 // Per-mode constants: exact free-ring-polymer flow over h = dt/2 for the
 // spring frequency omega_k = 2 omega_n |sin(pi k / P)|, omega_n = P kB T / hbar
-// (Eqs. 2, B2); PILE-L c1 = exp(-dt/tau_k), c2 = sqrt(1 - c1^2) with tau_0 = tau
-// and tau_k = tau_scale / (2 omega_k) (Eqs. D1, D2); omega_k^2 for the spring
+// (Eqs. 2, B2); PILE-L c1 = exp(-t/tau_k), c2 = sqrt(1 - c1^2) with tau_0 = tau
+// and tau_k = tau_scale / (2 omega_k) (Eqs. D1, D2) for the O step's length t
+// (dt in BAOAB, dt/2 for each of OBABO's two O steps); omega_k^2 for the spring
 // energy.
 std::vector<double> mode_table(const pimd_params *p)
 {
@@ -376,8 +378,9 @@ std::vector<double> mode_table(const pimd_params *p)
         }
         if (p->ensemble == PIMD_NVT) {
             const double tau_k = (k == 0) ? p->tau : p->tau_scale / (2.0 * wk);
-            r[MD_C1] = std::exp(-p->dt / tau_k);
-            r[MD_C2] = std::sqrt(-std::expm1(-2.0 * p->dt / tau_k));
+            const double to = (p->integrator == PIMD_OBABO) ? 0.5 * p->dt : p->dt;
+            r[MD_C1] = std::exp(-to / tau_k);
+            r[MD_C2] = std::sqrt(-std::expm1(-2.0 * to / tau_k));
         } else {
             r[MD_C1] = 1.0; r[MD_C2] = 0.0;
         }
@@ -589,6 +592,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.pair = forces_in_array(p->potential) ? 1 : 0;
     a.lists = pair ? 1 : 0;
     a.nvt = p->ensemble == PIMD_NVT ? 1 : 0;
+    a.obabo = p->integrator == PIMD_OBABO ? 1 : 0;
     a.hdt = 0.5 * p->dt;
     a.omega2 = p->potential == PIMD_POT_HARMONIC ? p->omega * p->omega : 0.0;
     a.skin = p->skin;
@@ -902,6 +906,7 @@ struct pimd_batch {
     size_t cap_sys = 0, cap_items = 0;
     struct Group {
         int P;        // bead count (MFMA groups) or 0 (vector-ALU group)
+        int obabo;    // MFMA groups: the systems' splitting (1: OBABO)
         int off, n;   // items [off, off + n)
     };
     std::vector<Group> step_groups;
@@ -987,20 +992,23 @@ int rebuild_plan(pimd_batch *b)
             pa[s] = b->sys[s]->pa;
         }
     }
-    // MFMA groups by bead count, then the vector-ALU group
-    for (int P : {16, 32, 64}) {
-        pimd_batch::Group g{P, (int)items.size(), 0};
-        for (int s = 0; s < n; ++s) {
-            pimd_ctx *c = b->sys[s];
-            if (!c || !b->active[s] || c->p.n_beads != P || c->lay.mfma_grid == 0) continue;
-            for (int t = 0; t < c->lay.mfma_tiles; ++t) items.push_back(make_int2(s, t));
-            nparts[s] = c->lay.mfma_tiles;
+    // MFMA groups by bead count and splitting, then the vector-ALU group
+    for (int P : {16, 32, 64})
+        for (int ob = 0; ob < 2; ++ob) {
+            pimd_batch::Group g{P, ob, (int)items.size(), 0};
+            for (int s = 0; s < n; ++s) {
+                pimd_ctx *c = b->sys[s];
+                if (!c || !b->active[s] || c->p.n_beads != P || c->lay.mfma_grid == 0 ||
+                    c->fa.obabo != ob)
+                    continue;
+                for (int t = 0; t < c->lay.mfma_tiles; ++t) items.push_back(make_int2(s, t));
+                nparts[s] = c->lay.mfma_tiles;
+            }
+            g.n = (int)items.size() - g.off;
+            if (g.n) b->step_groups.push_back(g);
         }
-        g.n = (int)items.size() - g.off;
-        if (g.n) b->step_groups.push_back(g);
-    }
     {
-        pimd_batch::Group g{0, (int)items.size(), 0};
+        pimd_batch::Group g{0, 0, (int)items.size(), 0};
         for (int s = 0; s < n; ++s) {
             pimd_ctx *c = b->sys[s];
             if (!c || !b->active[s] || c->lay.mfma_grid != 0) continue;
@@ -1062,7 +1070,7 @@ void enqueue_batch_step(pimd_batch *b)
     const int ncu = b->ncu;
     for (const auto &g : b->step_groups) {
         if (g.P)
-            launch_fused_mfma_batch(g.P, b->d_fa, b->d_items + g.off, g.n, g.n, b->stream);
+            launch_fused_mfma_batch(g.P, g.obabo != 0, b->d_fa, b->d_items + g.off, g.n, g.n, b->stream);
         else
             launch_fused_batch(b->d_fa, b->d_items + g.off, g.n, FUSED_STEP, b->smem_valu,
                                std::min(g.n, 2 * ncu), b->stream);

@@ -122,12 +122,14 @@ __device__ __forceinline__ void sincos_2pi_u(unsigned long long w, double &sn, d
     cs = (p == 0u) ? bc : (p == 1u) ? -bs : (p == 2u) ? -bc : bs;
 }
 
-// Three N(0,1) deviates for atom i, mode k, step s: counter (i, k, s, 0),
-// key (seed, 0); Box-Muller (z0, z1) from (u0, u1), z2 from (u2, u3).
+// Three N(0,1) deviates for atom i, mode k, step s and O step q of the step
+// (0, or 1 for OBABO's second): counter (i, k, s, q), key (seed, 0);
+// Box-Muller (z0, z1) from (u0, u1), z2 from (u2, u3).
 __device__ __forceinline__ void gauss3(unsigned long long seed, unsigned long long i,
-                                       unsigned long long k, unsigned long long s, double z[3])
+                                       unsigned long long k, unsigned long long s, double z[3],
+                                       unsigned long long q = 0ULL)
 {
-    unsigned long long c[4] = {i, k, s, 0ULL};
+    unsigned long long c[4] = {i, k, s, q};
     philox4x64_10(c, seed, 0ULL);
     const double r0 = sqrt(neg2log_u(c[0]));
     const double r2 = sqrt(neg2log_u(c[2]));

@@ -89,7 +89,7 @@ enum { TA_X0 = 0, TA_HM = 3, TA_IM = 4, TA_SG = 5, TA_ACT = 6, TA_ORIG = 7, TA_C
 // releases the previous tile's LDS; the forward products read x and f from
 // LDS; after a barrier the y~ of the update overwrite the x region; a last
 // barrier precedes the inverse products.
-template <int P>
+template <int P, bool OB>
 __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *smem,
                            double *partial_out)
 {
@@ -254,44 +254,62 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * x0[d]);
             }
-            if (closing) {
+            // PILE-L at P*T over one O step (dt in BAOAB, dt/2 in OBABO), noise
+            // of step s_ and O step q_ of that step
+            auto o_step = [&](unsigned long long s_, unsigned long long q_) {
+                double z[3];
+                gauss3(a.seed, (unsigned long long)ar[TA_ORIG], (unsigned long long)m, s_, z, q_);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1 * P] * vt[d] + mk[MD_C2 * P] * sg * z[d];
+            };
+            // A(dt/2): exact free-ring-polymer flow of this mode
+            auto a_step = [&]() {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    vt[d] += a.hdt * im * ft[d];
+                    const double q = xt[d], p = vt[d];
+                    xt[d] = mk[MD_A00 * P] * q + mk[MD_A01 * P] * p;
+                    vt[d] = mk[MD_A10 * P] * q + mk[MD_A11 * P] * p;
+                }
+            };
+            if (closing) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                // OBABO: the last O of the step being closed
+                if (OB && a.nvt) o_step(step - 1, 1);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
                     acc_ekin += hm * vt[d] * vt[d];
                     acc_esp += hm * mk[MD_SPRING * P] * xt[d] * xt[d];
                     acc_vir += mk[MD_NONCENTROID * P] * xt[d] * ft[d];
                 }
             }
-            // opening B, A(dt/2), O(dt), A(dt/2)
+            if constexpr (OB) {
+                // O(dt/2), B(dt/2), A(dt) = A(dt/2) A(dt/2)
+                if (a.nvt) o_step(step, 0);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                a_step();
+                a_step();
+            } else {
+                // B(dt/2), A(dt/2), O(dt), A(dt/2)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double q = xt[d], p = vt[d];
-                xt[d] = mk[MD_A00 * P] * q + mk[MD_A01 * P] * p;
-                vt[d] = mk[MD_A10 * P] * q + mk[MD_A11 * P] * p;
-            }
-            if (a.nvt) {
-                double z[3];
-                gauss3(a.seed, (unsigned long long)ar[TA_ORIG], (unsigned long long)m, step, z);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1 * P] * vt[d] + mk[MD_C2 * P] * sg * z[d];
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double q = xt[d], p = vt[d];
-                xt[d] = mk[MD_A00 * P] * q + mk[MD_A01 * P] * p;
-                vt[d] = mk[MD_A10 * P] * q + mk[MD_A11 * P] * p;
+                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                a_step();
+                if (a.nvt) o_step(step, 0);
+                a_step();
             }
             if (ext) {
-                // closing B with the trap force of the new positions, and
-                // the estimators of the new state
+                // closing B with the trap force of the new positions (and
+                // OBABO's last O), then the estimators of the new state
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * x0[d]);
+                    vt[d] += a.hdt * im * ft[d];
+                }
+                if (OB && a.nvt) o_step(step, 1);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const double xa = xt[d] + off * x0[d];
-                    ft[d] = -2.0 * hm * a.omega2 * xa;
-                    vt[d] += a.hdt * im * ft[d];
                     acc_ekin += hm * vt[d] * vt[d];
                     acc_esp += hm * mk[MD_SPRING * P] * xt[d] * xt[d];
                     acc_uext += hm * a.omega2 * xa * xa;
@@ -385,16 +403,18 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     }
 }
 
-template <int P>
+// OB: the OBABO splitting (a kernel of its own, so that BAOAB keeps its
+// register budget).
+template <int P, bool OB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma(FusedArgs a)
 {
     extern __shared__ double smem[];
-    mfma_tiles<P>(a, blockIdx.x, gridDim.x, smem, a.partials + (size_t)blockIdx.x * PF_COUNT);
+    mfma_tiles<P, OB>(a, blockIdx.x, gridDim.x, smem, a.partials + (size_t)blockIdx.x * PF_COUNT);
 }
 
 // Batched: one block per item (system, block tile of T x 16 atoms), for the
 // systems with this P; the grid is the item count.
-template <int P>
+template <int P, bool OB>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma_batch(
     const FusedArgs *table, const int2 *items, int n_items)
 {
@@ -402,7 +422,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if ((int)blockIdx.x >= n_items) return;
     const int2 item = items[blockIdx.x];
     const FusedArgs &a = table[item.x];
-    mfma_tiles<P>(a, item.y, 1 << 30, smem, a.partials + (size_t)item.y * PF_COUNT);
+    mfma_tiles<P, OB>(a, item.y, 1 << 30, smem, a.partials + (size_t)item.y * PF_COUNT);
 }
 
 namespace {
@@ -410,7 +430,9 @@ namespace {
 template <int P>
 int grid_for(int N)
 {
-    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P>,
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -418,13 +440,43 @@ int grid_for(int N)
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
     int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_mfma<P>, kBlock,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_mfma<P, false>, kBlock,
                                                      Lds<P>::bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     const int want = (N + 16 * Lds<P>::T - 1) / (16 * Lds<P>::T);
     const int cap = ncu * per_cu;
     return want < cap ? want : cap;
+}
+
+template <int P>
+void launch_one(const FusedArgs &a, int grid, hipStream_t s)
+{
+    if (a.obabo)
+        hipLaunchKernelGGL((k_fused_mfma<P, true>), dim3(grid), dim3(kBlock), Lds<P>::bytes, s, a);
+    else
+        hipLaunchKernelGGL((k_fused_mfma<P, false>), dim3(grid), dim3(kBlock), Lds<P>::bytes, s, a);
+}
+
+template <int P>
+void launch_batch(bool ob, const FusedArgs *table, const int2 *items, int n_items, int grid,
+                  hipStream_t s)
+{
+    if (ob)
+        hipLaunchKernelGGL((k_fused_mfma_batch<P, true>), dim3(grid), dim3(kBlock), Lds<P>::bytes, s,
+                           table, items, n_items);
+    else
+        hipLaunchKernelGGL((k_fused_mfma_batch<P, false>), dim3(grid), dim3(kBlock), Lds<P>::bytes, s,
+                           table, items, n_items);
+}
+
+template <int P>
+void set_batch_attr()
+{
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma_batch<P, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma_batch<P, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
 }
 
 }  // namespace
@@ -444,17 +496,10 @@ int fused_mfma_grid(int N, int P)
 void launch_fused_mfma(const FusedArgs &a, int grid, hipStream_t s)
 {
     switch (a.P) {
-    case 16:
-        hipLaunchKernelGGL(k_fused_mfma<16>, dim3(grid), dim3(kBlock), Lds<16>::bytes, s, a);
-        break;
-    case 32:
-        hipLaunchKernelGGL(k_fused_mfma<32>, dim3(grid), dim3(kBlock), Lds<32>::bytes, s, a);
-        break;
-    case 64:
-        hipLaunchKernelGGL(k_fused_mfma<64>, dim3(grid), dim3(kBlock), Lds<64>::bytes, s, a);
-        break;
-    default:
-        break;
+    case 16: launch_one<16>(a, grid, s); break;
+    case 32: launch_one<32>(a, grid, s); break;
+    case 64: launch_one<64>(a, grid, s); break;
+    default: break;
     }
 }
 
@@ -466,32 +511,19 @@ int mfma_block_tiles(int N, int P)
 
 void set_mfma_batch_smem()
 {
-    (void)hipFuncSetAttribute((const void *)k_fused_mfma_batch<16>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<16>::bytes);
-    (void)hipFuncSetAttribute((const void *)k_fused_mfma_batch<32>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<32>::bytes);
-    (void)hipFuncSetAttribute((const void *)k_fused_mfma_batch<64>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<64>::bytes);
+    set_batch_attr<16>();
+    set_batch_attr<32>();
+    set_batch_attr<64>();
 }
 
-void launch_fused_mfma_batch(int P, const FusedArgs *table, const int2 *items, int n_items,
+void launch_fused_mfma_batch(int P, bool obabo, const FusedArgs *table, const int2 *items, int n_items,
                              int grid, hipStream_t s)
 {
     switch (P) {
-    case 16:
-        hipLaunchKernelGGL(k_fused_mfma_batch<16>, dim3(grid), dim3(kBlock), Lds<16>::bytes, s,
-                           table, items, n_items);
-        break;
-    case 32:
-        hipLaunchKernelGGL(k_fused_mfma_batch<32>, dim3(grid), dim3(kBlock), Lds<32>::bytes, s,
-                           table, items, n_items);
-        break;
-    case 64:
-        hipLaunchKernelGGL(k_fused_mfma_batch<64>, dim3(grid), dim3(kBlock), Lds<64>::bytes, s,
-                           table, items, n_items);
-        break;
-    default:
-        break;
+    case 16: launch_batch<16>(obabo, table, items, n_items, grid, s); break;
+    case 32: launch_batch<32>(obabo, table, items, n_items, grid, s); break;
+    case 64: launch_batch<64>(obabo, table, items, n_items, grid, s); break;
+    default: break;
     }
 }
 

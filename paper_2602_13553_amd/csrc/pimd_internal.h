@@ -75,6 +75,7 @@ struct FusedArgs {
     int pair;                 // 1: forces come from array f (the pair kernel or the caller)
     int lists;                // 1: neighbor lists (rebuild decisions) exist
     int nvt;                  // 1: PILE-L O step
+    int obabo;                // 1: OBABO splitting (O half steps around B A A B), 0: BAOAB
     double hdt;               // dt / 2
     double omega2;            // external trap omega^2 (0 for none / pair)
     double skin;
@@ -156,8 +157,8 @@ void launch_fused_mfma(const FusedArgs &a, int grid, hipStream_t s);
 // batched launches: items are (system index, tile) pairs grouped by system
 int mfma_block_tiles(int N, int P);
 void set_mfma_batch_smem();
-void launch_fused_mfma_batch(int P, const FusedArgs *table, const int2 *items, int n_items,
-                             int grid, hipStream_t s);
+void launch_fused_mfma_batch(int P, bool obabo, const FusedArgs *table, const int2 *items,
+                             int n_items, int grid, hipStream_t s);
 void launch_fused_batch(const FusedArgs *table, const int2 *items, int n_items, int mode,
                         int smem_bytes, int grid, hipStream_t s);
 void set_batch_smem(int smem_bytes);

@@ -218,9 +218,28 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * ref[d]);
             }
+            // PILE-L at P*T over one O step (dt in BAOAB, dt/2 in OBABO), noise
+            // of step s_ and O step q_ of that step
+            auto o_step = [&](unsigned long long s_, unsigned long long q_) {
+                double z[3];
+                gauss3(a.seed, oi, (unsigned long long)k, s_, z, q_);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
+            };
+            // A(dt/2): exact free-ring-polymer flow of this mode
+            auto a_step = [&]() {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double q = xt[d], p = vt[d];
+                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
+                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                }
+            };
             if (closing) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                // OBABO: the last O of the step being closed
+                if (a.obabo && a.nvt) o_step(step - 1, 1);
             }
             if (est_now) {
 #pragma unroll
@@ -233,38 +252,30 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 }
             }
             if (mode == FUSED_STEP) {
-                // opening B
+                if (a.obabo) {
+                    // O(dt/2), B(dt/2), A(dt) = A(dt/2) A(dt/2)
+                    if (a.nvt) o_step(step, 0);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
-                // A(dt/2)
+                    for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                    a_step();
+                    a_step();
+                } else {
+                    // B(dt/2), A(dt/2), O(dt), A(dt/2)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double q = xt[d], p = vt[d];
-                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
-                }
-                // O(dt): PILE-L at P*T
-                if (a.nvt) {
-                    double z[3];
-                    gauss3(a.seed, oi, (unsigned long long)k, step, z);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
-                }
-                // A(dt/2)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double q = xt[d], p = vt[d];
-                    xt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                    for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
+                    a_step();
+                    if (a.nvt) o_step(step, 0);
+                    a_step();
                 }
                 if (ext) {
-                    // closing B with the trap force of the new positions, then
-                    // the estimators of the new state
+                    // closing B with the trap force of the new positions (and
+                    // OBABO's last O), then the estimators of the new state
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * ref[d]);
                         vt[d] += a.hdt * im * ft[d];
                     }
+                    if (a.obabo && a.nvt) o_step(step, 1);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         const double xa = xt[d] + off * ref[d];

@@ -72,6 +72,7 @@ class SystemSpec:
     bond_k: float = 0.0
     bond_r0: float = 0.0
     skin: float = 0.3               # neighbor-list skin (GPU library only)
+    integrator: int = 0             # 0: BAOAB, 1: OBABO
     lj_active: np.ndarray | None = None   # [N] 0/1
     bonds: np.ndarray | None = None       # [n_bonds][2]
     nsteps: int = 0                 # length of the workload's run

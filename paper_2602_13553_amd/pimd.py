@@ -19,6 +19,7 @@ PIMD_OK = 0
 ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PIMD_ERR_STATE",
           -5: "PIMD_ERR_NONFINITE", -6: "PIMD_ERR_UNSUPPORTED", -7: "PIMD_ERR_OVERFLOW"}
 PIMD_NVT, PIMD_NVE = 0, 1
+PIMD_BAOAB, PIMD_OBABO = 0, 1
 PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER, PIMD_POT_EXTERNAL = 0, 1, 2, 3, 4
 PIMD_FLAG_VALU_TRANSFORMS = 1
 PIMD_FLAG_MFMA_TRANSFORMS = 2
@@ -56,7 +57,7 @@ class pimd_params(C.Structure):
         ("box", C.c_double * 3), ("seed", C.c_uint64), ("omega", C.c_double),
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double), ("lj_rc", C.c_double),
         ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
-        ("nbr_capacity", C.c_int32), ("flags", C.c_int32),
+        ("nbr_capacity", C.c_int32), ("flags", C.c_int32), ("integrator", C.c_int32),
     ]
 
 
@@ -182,6 +183,7 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     p.omega = spec.omega
     p.lj_eps, p.lj_sigma, p.lj_rc = spec.lj_eps, spec.lj_sigma, spec.lj_rc
     p.skin, p.bond_k, p.bond_r0 = spec.skin, spec.bond_k, spec.bond_r0
+    p.integrator = int(getattr(spec, "integrator", PIMD_BAOAB))
     return p
 
 

@@ -59,6 +59,41 @@ def test_batch_equals_solo():
     b.close()
 
 
+def test_batch_mixed_splittings_equal_solo():
+    """BAOAB and OBABO systems in one batch, on both transform variants (the
+    matrix-core groups split by splitting): each equals its solo run."""
+    pimd = _pimd()
+    M = pimd.PIMD_FLAG_MFMA_TRANSFORMS
+    cases = []
+    for k, (spec, fl) in enumerate([
+            (inputs.harmonic_tiny(n_atoms=40, n_beads=4, seed=11), 0),
+            (inputs.lj_liquid(n_atoms=108, n_beads=8, seed=12), 0),
+            (inputs.lj_liquid(n_atoms=64, n_beads=32, seed=13), M),
+            (inputs.lj_liquid(n_atoms=64, n_beads=32, seed=14), M),
+            (inputs.harmonic_tiny(n_atoms=20, n_beads=64, seed=15), M),
+            (inputs.water(n_atoms=192, n_beads=16, seed=16), M)]):
+        if k % 2 == 1 or k == 4:
+            spec.integrator = pimd.PIMD_OBABO
+        cases.append((spec, fl))
+    b = pimd.Batch()
+    ids = [b.add(s, fl) for s, fl in cases]
+    for i, (s, fl) in zip(ids, cases):
+        b.set_state(i, s.x0, s.v0, 0)
+    b.step(12)
+    for i, (s, fl) in zip(ids, cases):
+        print("batch vs solo", s.name, "obabo" if s.integrator else "baoab", fl, flush=True)
+        c = pimd.Context.from_spec(s, flags=fl)
+        c.set_state(s.x0, s.v0, 0)
+        c.step(12)
+        xs, ps, ss = c.get_state()
+        c.close()
+        xb, pb, sb = b.get_state(i)
+        assert sb == ss == 12
+        assert np.array_equal(xb, xs), s.name
+        assert np.array_equal(pb, ps), s.name
+    b.close()
+
+
 def test_batch_equals_solo_cluster_pairs():
     """Systems whose force pass runs on cluster lists (one falling back to
     per-atom lists in its small box) next to systems on per-atom lists."""

@@ -200,6 +200,27 @@ def test_valu_transforms_water_full_size():
     check_states(g, o)
 
 
+# ------------------------------------------------------------ OBABO splitting
+@pytest.mark.parametrize("kind,N,P,mfma", [
+    ("harmonic", 37, 8, False), ("harmonic", 50, 32, True), ("lj", 256, 8, False),
+    ("lj", 130, 64, True), ("water", 387, 32, False), ("water", 99, 16, True)])
+def test_obabo_matches_oracle(kind, N, P, mfma):
+    """O(dt/2) B A(dt) B O(dt/2), the two O steps with their own draws, on the
+    trap (in-kernel forces) and the pair potentials (the closing pass carries
+    the second O), on both transform variants."""
+    pimd = _pimd()
+    if kind == "harmonic":
+        spec = inputs.harmonic_tiny(n_atoms=N, n_beads=P, seed=3 * N + P)
+    elif kind == "lj":
+        spec = inputs.lj_liquid(n_atoms=N, n_beads=P, seed=N + 2 * P)
+    else:
+        spec = inputs.water(n_atoms=N, n_beads=P, seed=N + 1)
+    spec.integrator = pimd.PIMD_OBABO
+    g, o = run_pair(spec, 10, chunks=[1, 7, 2],
+                    flags=pimd.PIMD_FLAG_MFMA_TRANSFORMS if mfma else 0)
+    check_states(g, o)
+
+
 # ------------------------------------------------------------ cluster lists
 @pytest.mark.parametrize("case", ["lj_full", "lj_p16", "lj_small_box", "water_p32", "water_small"])
 def test_cluster_pairs(case):

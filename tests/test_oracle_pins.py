@@ -431,3 +431,75 @@ def test_atom_ids_step_a_sample_of_independent_atoms():
     other = oracle.State(sub, spec.x0[:, idx], spec.v0[:, idx])
     other.step(7)
     assert not np.array_equal(other.x, full.x[:, idx])
+
+
+# ---------------------------------------------------------------- OBABO
+def test_obabo_nve_equals_baoab_nve():
+    """Without the thermostat both splittings are B A(dt/2) A(dt/2) B: the
+    same trajectory bit for bit."""
+    s, x = _lj_box(N=18, L=5.6, seed=8, P=4)
+    s.temp, s.hbar, s.dt, s.nve = 0.8, 0.2, 0.002, True
+    rng = np.random.default_rng(5)
+    x4 = x[None] + 0.02 * rng.standard_normal((4, 18, 3))
+    v4 = rng.standard_normal((4, 18, 3))
+    a = oracle.State(s, x4, v4)
+    a.step(8)
+    s2 = oracle.System(**{f: getattr(s, f) for f in ("n_atoms", "n_beads", "mass", "temp", "kB",
+                                                      "hbar", "mvv2e", "dt", "tau", "tau_scale",
+                                                      "nve", "pot", "box", "seed", "lj_eps",
+                                                      "lj_sigma", "lj_rc")}, integrator=1)
+    b = oracle.State(s2, x4, v4)
+    b.step(8)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.vt, b.vt)
+
+
+def test_obabo_one_step_by_hand():
+    """One OBABO step of free particles (P = 1, U = 0), written out: O(dt/2)
+    with the draw (s, q=0), free flight over dt, O(dt/2) with (s, q=1)."""
+    N, dt, tau, kT, m, seed, s0 = 5, 0.1, 0.7, 1.3, 2.0, 99, 12
+    s = oracle.System(n_atoms=N, n_beads=1, mass=np.full(N, m), temp=kT, pot=oracle.POT_NONE,
+                      dt=dt, tau=tau, seed=seed, integrator=1)
+    rng = np.random.default_rng(0)
+    x, v = rng.standard_normal((1, N, 3)), rng.standard_normal((1, N, 3))
+    st = oracle.State(s, x, v, s0)
+    st.step(1)
+    c1 = math.exp(-0.5 * dt / tau)
+    c2 = math.sqrt(1 - c1 * c1)
+    sig = math.sqrt(kT / m)
+    for i in range(N):
+        z0 = oracle.gaussians(seed, 0, i, 0, s0, 0)
+        z1 = oracle.gaussians(seed, 0, i, 0, s0, 1)
+        vh = c1 * v[0, i] + c2 * sig * z0
+        x1 = x[0, i] + 0.5 * dt * vh + 0.5 * dt * vh
+        v1 = c1 * vh + c2 * sig * z1
+        assert np.allclose(st.x[0, i], x1, rtol=0, atol=1e-15)
+        assert np.allclose(st.v[0, i], v1, rtol=0, atol=1e-15)
+    assert int(st.step_count[0]) == s0 + 1
+
+
+def test_obabo_free_rp_mode_variances_exact():
+    """OBABO with U = 0: O(dt/2), exact A(dt), O(dt/2) all keep the Boltzmann
+    distribution of each mode, so <v~_k^2> = P kT/m and <x~_k^2> =
+    P kT / (m w_k^2) (k >= 1) hold for any dt."""
+    P, kT = 8, 1.0
+    spec = inputs.free_ring_polymer(n_atoms=64, n_beads=P, dt=0.05, ensemble=inputs.NVT, kT=kT)
+    spec.mass = np.ones(64)
+    spec.integrator = 1
+    spec.v0 = spec.v0 * 0 + np.random.default_rng(3).standard_normal(spec.v0.shape) * math.sqrt(P)
+    st = oracle.State.from_spec(spec)
+    assert st.sys.integrator == 1
+    wn = P * kT / spec.hbar
+    st.step(300)
+    xs, vs = [], []
+    for _ in range(1500):
+        st.step(1)
+        xs.append(oracle.to_normal(st.x))
+        vs.append(st.vt.copy())
+    xs, vs = np.array(xs), np.array(vs)
+    for k in range(1, P):
+        wk = 2 * wn * math.sin(math.pi * k / P)
+        mm, se = _block_mean((xs[:, k] ** 2).mean(axis=(1, 2)))
+        assert abs(mm - P * kT / wk ** 2) < 4 * se, (k, mm, P * kT / wk ** 2, se)
+    for k in range(P):
+        mm, se = _block_mean((vs[:, k] ** 2).mean(axis=(1, 2)))
+        assert abs(mm - P * kT) < 4 * se, (k, mm, se)
