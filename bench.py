@@ -371,6 +371,13 @@ def main():
                                                          "valu": av["fused"][0]}
 
     if not args.no_batch:
+        log("OBABO splitting")
+        ob = make()
+        ob.integrator = 1
+        ms_ob, _, prof_ob, _, _, _ = run_gpu(ob, 500, 50, 100, flags)
+        out["obabo"] = {"workload": title + ", OBABO splitting (two O half steps per step)",
+                        "ms_per_step": ms_ob, "bead_atom_steps_per_s": ob.bead_atoms * 1e3 / ms_ob,
+                        "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_ob).items()}}
         log("external forces")
         out["external_forces"] = bench_external()
         log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))
