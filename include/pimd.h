@@ -1,13 +1,14 @@
 /*
- * pimd.h -- C ABI of libpimd.so: the ring-polymer BAOAB step with the PILE-L
- * Langevin thermostat on one MI355X (gfx950), all P beads of all N atoms
- * resident in HBM.
+ * pimd.h -- C ABI of libpimd.so: the ring-polymer BAOAB (or OBABO) step with
+ * the PILE-L Langevin thermostat on one MI355X (gfx950), all P beads of all N
+ * atoms resident in HBM.
  *
  * Method: Li et al., "fix pimd/langevin: An Efficient Implementation of Path
  * Integral Molecular Dynamics in LAMMPS", arXiv:2602.13553.
  *   - ring-polymer Hamiltonian and spring frequency: Sec. II, Eqs. 1-2
  *   - normal-mode transform and its inverse: App. B, Eqs. B1-B3
  *   - BAOAB splitting in normal modes, thermostat at P*T: Sec. III.C, IV.A
+ *     (OBABO, the splitting of the paper's example input: Sec. III.C)
  *   - PILE-L O step and damping times: App. D, Eqs. D1-D2
  *   - unwrapped coordinates for transforms and estimators: Sec. IV.B
  *   - estimators K, S, U, H, K_PR, K_CV: App. A, Eqs. A4, A5, A7
@@ -17,7 +18,8 @@
  *     parameters are left untouched and pimd_last_error() describes it.  No
  *     C++ exception crosses this boundary.
  *   - Host pointers are borrowed for the duration of the call only
- *     (copy-in / copy-out).  Device state is owned by the context, or lives
+ *     (copy-in / copy-out).  Only pimd_get_positions and pimd_set_forces
+ *     take device pointers.  Device state is owned by the context, or lives
  *     in a caller-provided device workspace (see pimd_create).
  *   - A context is used by one host thread at a time.
  *   - Host-side bead arrays use the layout [P][N][3] (bead k, atom i,
@@ -43,7 +45,7 @@ extern "C" {
 #define PIMD_ERR_DEVICE (-3)      /* HIP runtime error */
 #define PIMD_ERR_STATE (-4)       /* call out of order (e.g. step before set_state) */
 #define PIMD_ERR_NONFINITE (-5)   /* a position or velocity became NaN/Inf */
-#define PIMD_ERR_UNSUPPORTED (-6) /* valid but not supported by this build */
+#define PIMD_ERR_UNSUPPORTED (-6) /* valid but not supported by the library */
 #define PIMD_ERR_OVERFLOW (-7)    /* neighbor-list capacity exceeded */
 
 /* ensemble (Sec. III.C): NVT = PILE-L thermostat at P*T, NVE = no thermostat */
@@ -63,7 +65,7 @@ extern "C" {
 
 typedef struct pimd_params {
     int32_t n_atoms;    /* N >= 1 */
-    int32_t n_beads;    /* P >= 1 (the paper's n); this build supports P <= 128 */
+    int32_t n_beads;    /* P >= 1 (the paper's n); the library supports P <= 128 */
     int32_t ensemble;   /* PIMD_NVT or PIMD_NVE */
     int32_t potential;  /* PIMD_POT_* */
     double temp;        /* T > 0; the thermostat acts at P*T (Sec. IV.A) */
@@ -186,18 +188,22 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
 /* Load a state (Sec. IV.A: Cartesian positions, velocities turned into normal
  * modes v~ = M v).  x and v are [P][N][3] host arrays; x is taken as
  * unwrapped (all beads of an atom in the same periodic image, Sec. IV.B).
- * Computes f(x), the neighbor lists and the estimators of this state, and
- * sets the thermostat step counter to `step`.  Synchronizes.
+ * Computes f(x), the neighbor lists and the estimators of this state (with
+ * external forces: neither; they follow pimd_set_forces), and sets the
+ * thermostat step counter to `step`.  Synchronizes.
  * Errors: ARG (NULL or non-finite input), DEVICE. */
 int pimd_set_state(pimd_ctx *ctx, const double *x, const double *v, uint64_t step);
 
-/* Enqueue nsteps >= 0 BAOAB steps on the context's stream and return without
- * waiting.  Each step: B(dt/2), A(dt/2), O(dt), A(dt/2), forces, B(dt/2), in
- * normal modes; the noise for mode k, atom i, dim a at step s is the
- * Philox4x64-10 stream keyed by (seed, 0) at counter (i, k, s, 0).  After the
- * call's work completes the state is synchronized (full-step velocities) and
- * the estimators of every step are in the running sums.
- * Errors: STATE (no set_state yet), ARG (nsteps < 0), DEVICE. */
+/* Enqueue nsteps >= 0 steps on the context's stream and return without
+ * waiting.  Each BAOAB step: B(dt/2), A(dt/2), O(dt), A(dt/2), forces,
+ * B(dt/2), in normal modes (OBABO: see the integrator field); the noise for
+ * mode k, atom i, dim a at step s is the Philox4x64-10 stream keyed by
+ * (seed, 0) at counter (i, k, s, 0) (and (i, k, s, 1) for OBABO's second O).
+ * After the call's work completes the state is synchronized (full-step
+ * velocities) and the estimators of every step are in the running sums.
+ * External forces take one step per call (see pimd_set_forces).
+ * Errors: STATE (no set_state yet; external forces not set), ARG (nsteps < 0;
+ * external forces and nsteps > 1), DEVICE. */
 int pimd_step(pimd_ctx *ctx, int64_t nsteps);
 
 /* Wait for the stream, then copy out the estimators.  Returns

@@ -16,7 +16,7 @@
 namespace pimd {
 
 constexpr int kBlock = 256;      // threads per block for the step kernels
-constexpr int kMaxBeads = 128;   // P limit of this build (LDS-resident M)
+constexpr int kMaxBeads = 128;   // P limit of the library (LDS-resident M)
 constexpr int kMaxBonds = 4;     // bonds per atom
 constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
 constexpr int kCellCapMax = 4096;  // atoms per centroid cell, at most

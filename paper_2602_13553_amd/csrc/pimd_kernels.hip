@@ -1,26 +1,30 @@
 // HIP kernels of libpimd.so for gfx950 (CDNA4, wave64).
 //
-// k_fused  : one pass over (x, v~, f) per step: normal-mode transforms
-//            (App. B), pending closing B + estimators (App. A), opening B,
-//            A(dt/2), PILE-L O(dt) (App. D), A(dt/2), inverse transform.
+// k_fused  : one pass over (y~, v~, f) per step on the FP64 vector ALUs:
+//            f~ = M f (App. B; the positions' modes y~ are carried between
+//            steps), the pending closing half-kick and the estimators
+//            (App. A), then the step's B, A, O, A (BAOAB) or O, B, A, A
+//            (OBABO) per mode (Eqs. 1-2, App. D), and the inverse transform.
 //            With an external trap the forces are evaluated in normal modes
 //            inside the same pass and the whole step is this one kernel.
+//            (The matrix-core variant is k_fused_mfma, pimd_fused_mfma.hip.)
 // k_pair   : bead-batched short-range forces for all P replicas in one
 //            launch (LJ among active atoms + harmonic bonds), each atom's
-//            neighbor list rebuilt in place from centroids when requested.
-//
-// k_finalize: one block after k_fused; combines the per-block partials in
-//            block order (deterministic), records estimators and running
-//            sums, advances the step counter, decides list rebuilds.
+//            neighbor list rebuilt from the centroid cells when requested.
+// k_finalize: one block after the step pass; combines the per-block partials
+//            in block order (deterministic), records estimators and running
+//            sums, advances the step counter, decides list rebuilds and, at
+//            a rebuild, builds the centroid cell lists.
 #include "pimd_device.h"
 #include "pimd_internal.h"
 
 namespace pimd {
 
 // --------------------------------------------------------------------------
-// Fused step kernel.
-// Shared memory: M^T padded [P][P+1], tile X [A][3][P], tile F [A][3][P],
-// centroids [A][3], reduction scratch.
+// Fused step kernel (vector ALUs).
+// Shared memory: M^T padded [P][P+1], tile X [A][3][P] (the modes y~, then
+// the new ones for the inverse), tile F [A][3][P] (f, or v in PREP),
+// centroids [A][3], bead-0 references [A][3].
 // --------------------------------------------------------------------------
 int fused_smem_bytes(int P)
 {
@@ -748,11 +752,12 @@ void launch_finalize(const FusedArgs &a, int fused_blocks, hipStream_t s)
 }
 
 // --------------------------------------------------------------------------
-// Pair forces.  Block = A = kBlock/P atoms, thread (atom, bead).  When the
-// control block requests it, each atom's group of P lanes first rebuilds that
-// atom's list: it scans every active atom's centroid (and, in boxes smaller
-// than twice the list cutoff, every periodic image within reach) and keeps
-// entries with |c_i - c_j + s L| < rlist, in (j, image) order.
+// Pair forces.  Block = A = kBlock/(S P) atoms, thread (atom, sub-group, bead).
+// When the control block requests it, each atom's lanes first rebuild that
+// atom's list with entries |c_i - c_j + s L| < rlist: from the centroid cells
+// (the 2R+1 cells per dim around the atom's cell, in a fixed order) or, when
+// the box has too few cells, by scanning every active atom's centroid and
+// every periodic image within reach, in (j, image) order.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int pack_shift(int sx, int sy, int sz)
 {
@@ -1093,7 +1098,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
 }
 
 // --------------------------------------------------------------------------
-// Cluster-pair force pass (a6).  Block b takes the A = kBlock/P consecutive
+// Cluster-pair force pass.  Block b takes the A = kBlock/P consecutive
 // atoms b*A ... (thread = atom, bead); its LJ-active atoms share one neighbor
 // list (the union of their lists) with, per entry, a mask of the atoms that
 // use it, built at list rebuilds in index order.  Each neighbor's P bead rows

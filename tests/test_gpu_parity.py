@@ -81,7 +81,7 @@ def test_harmonic_ragged_and_odd(N, P):
 
 
 def test_max_beads_large_system_sampled():
-    """P = 128 (the largest this build takes) on 2^19 trapped atoms: 2^26
+    """P = 128 (the largest the library takes) on 2^19 trapped atoms: 2^26
     bead*atoms, 1.6 GB per state array, grids far past one wave of blocks.
     The atoms of a trap do not interact, so the oracle steps a sample of them
     alone, with their own indices in the noise counter, and the GPU's
