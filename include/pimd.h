@@ -87,7 +87,17 @@ typedef struct pimd_params {
     int32_t nbr_capacity; /* neighbors per atom; 0 = sized from the density */
     int32_t flags;        /* PIMD_FLAG_* (0 = defaults) */
     int32_t integrator;   /* PIMD_BAOAB (0) or PIMD_OBABO (1) */
+    int32_t fixcom;       /* 1: remove the centroids' center-of-mass velocity at the end
+                             of every step (Sec. III.C's fixcom keyword); not in a batch */
 } pimd_params;
+
+/* fixcom = 1: at the end of every step (after the closing B, and OBABO's
+ * second O) the mass-weighted mean u = sum_i m_i v~0_i / sum_i m_i of the
+ * centroid-mode velocities is subtracted from every atom's centroid mode, i.e.
+ * the centroids' center-of-mass velocity u / sqrt(P) is removed from every
+ * bead; the estimators are those of the state after the removal.  With the
+ * pair potentials the closing half-kick then runs in a pass of its own
+ * before each step. */
 
 /* integrator: the Trotter splitting of one step (Sec. III.C; the paper's
  * example input uses OBABO).

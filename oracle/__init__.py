@@ -48,7 +48,7 @@ class _System(C.Structure):
         ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("mass", C.POINTER(C.c_double)), ("lj_active", C.POINTER(C.c_int32)),
         ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32)),
-        ("atom_id", C.POINTER(C.c_int64)), ("integrator", C.c_int32),
+        ("atom_id", C.POINTER(C.c_int64)), ("integrator", C.c_int32), ("fixcom", C.c_int32),
     ]
 
 
@@ -166,6 +166,7 @@ class System:
     bonds: np.ndarray | None = None
     atom_id: np.ndarray | None = None   # noise-counter index per atom (None: 0..N-1)
     integrator: int = 0                 # 0: BAOAB, 1: OBABO
+    fixcom: int = 0                     # 1: centroid COM velocity removed every step
     _c: _System = field(default=None, init=False, repr=False)
 
     def cstruct(self) -> _System:
@@ -180,6 +181,7 @@ class System:
         s.lj_eps, s.lj_sigma, s.lj_rc = self.lj_eps, self.lj_sigma, self.lj_rc
         s.bond_k, s.bond_r0 = self.bond_k, self.bond_r0
         s.integrator = int(self.integrator)
+        s.fixcom = int(self.fixcom)
         s.mass = _dp(self._mass)
         if self.lj_active is not None:
             self._act = np.ascontiguousarray(self.lj_active, dtype=np.int32)
@@ -207,7 +209,8 @@ class System:
                    pot=pot, box=tuple(spec.box), seed=spec.seed, omega=spec.omega,
                    lj_eps=spec.lj_eps, lj_sigma=spec.lj_sigma, lj_rc=spec.lj_rc,
                    bond_k=spec.bond_k, bond_r0=spec.bond_r0, lj_active=spec.lj_active,
-                   bonds=spec.bonds, integrator=int(getattr(spec, "integrator", 0)))
+                   bonds=spec.bonds, integrator=int(getattr(spec, "integrator", 0)),
+                   fixcom=int(getattr(spec, "fixcom", 0)))
 
     # --- per-function wrappers -------------------------------------------
     def free_rp_matrix(self, k: int, h: float) -> np.ndarray:

@@ -487,14 +487,31 @@ void orc_step_positions(const orc_system *sys, double *x, double *vt, const doub
     free(ft);
 }
 
-/* The closing B(dt/2) of step s, with the forces f of the new positions, and
- * for OBABO the step's second O(dt/2) (q = 1). */
+/* fixcom: the centroid of atom i moves with v~0_i / sqrt(P) (row 0 of M is
+ * 1/sqrt(P)), so removing the centroids' center-of-mass velocity V from every
+ * bead subtracts sqrt(P) V = sum_j m_j v~0_j / sum_j m_j from every atom's
+ * centroid mode and leaves the other modes alone. */
+static void orc_remove_com(const orc_system *sys, double *vt)
+{
+    const int32_t N = sys->n_atoms;
+    double msum = 0.0, p[3] = {0.0, 0.0, 0.0};
+    for (int32_t i = 0; i < N; ++i) {
+        msum += sys->mass[i];
+        for (int d = 0; d < 3; ++d) p[d] += sys->mass[i] * vt[(size_t)i * 3 + d];
+    }
+    for (int32_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) vt[(size_t)i * 3 + d] -= p[d] / msum;
+}
+
+/* The closing B(dt/2) of step s, with the forces f of the new positions, for
+ * OBABO the step's second O(dt/2) (q = 1), and the fixcom removal. */
 void orc_step_kick(const orc_system *sys, double *vt, const double *f, uint64_t s)
 {
     const size_t n = (size_t)sys->n_beads * sys->n_atoms * 3;
     double *ft = (double *)malloc(sizeof(double) * n);
     orc_kick(sys, vt, f, ft);
     if (sys->integrator == 1) orc_o_step(sys, vt, s, 1);
+    if (sys->fixcom) orc_remove_com(sys, vt);
     free(ft);
 }
 

@@ -60,6 +60,8 @@ typedef struct orc_system {
                                position; lets a sample of a system of independent atoms
                                (trap, free) be stepped alone with its original noise */
     int32_t integrator;     /* 0: BAOAB; 1: OBABO (O(dt/2) B(dt/2) A(dt) B(dt/2) O(dt/2)) */
+    int32_t fixcom;         /* 1: remove the centroids' center-of-mass velocity at the end
+                               of every step */
 } orc_system;
 
 typedef struct orc_est {

@@ -118,6 +118,7 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
     }
     if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) { why = "bad ensemble"; return PIMD_ERR_ARG; }
     if (p->integrator != PIMD_BAOAB && p->integrator != PIMD_OBABO) { why = "bad integrator"; return PIMD_ERR_ARG; }
+    if (p->fixcom != 0 && p->fixcom != 1) { why = "fixcom must be 0 or 1"; return PIMD_ERR_ARG; }
     if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_EXTERNAL) { why = "bad potential"; return PIMD_ERR_ARG; }
     if (!finite_pos(p->temp) || !finite_pos(p->kB) || !finite_pos(p->hbar) || !finite_pos(p->mvv2e) ||
         !finite_pos(p->dt)) {
@@ -437,6 +438,10 @@ void enqueue_fused(pimd_ctx *c, int mode, int kind)
 
 void enqueue_step(pimd_ctx *c)
 {
+    // fixcom with a force pass: the last step's closing half-kick runs in a
+    // pass of its own, so that its centroid momentum is known (and removed at
+    // the start of the step pass) before the step's opening half-kick
+    if (c->fa.fixcom && c->lay.pair_grid > 0) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
     enqueue_fused(c, FUSED_STEP, PIMD_KERNEL_FUSED);
     if (c->lay.pair_grid > 0) {
         size_t e = prof_begin(c, PIMD_KERNEL_PAIR);
@@ -593,6 +598,12 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.lists = pair ? 1 : 0;
     a.nvt = p->ensemble == PIMD_NVT ? 1 : 0;
     a.obabo = p->integrator == PIMD_OBABO ? 1 : 0;
+    a.fixcom = p->fixcom ? 1 : 0;
+    {
+        double hsum = 0.0;
+        for (int i = 0; i < N; ++i) hsum += atoms[(size_t)i * 4 + AT_HALF_M];
+        a.inv_hsum = hsum > 0.0 ? 1.0 / hsum : 0.0;
+    }
     a.hdt = 0.5 * p->dt;
     a.omega2 = p->potential == PIMD_POT_HARMONIC ? p->omega * p->omega : 0.0;
     a.skin = p->skin;
@@ -705,7 +716,7 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
         enqueue_step(c);
         c->forces_current = false;
         c->synced = false;
-        return launch_error(c, "step launch");
+        return launch_error(c, "step launch");   // the closing (and fixcom) follow the forces
     }
     int64_t left = nsteps;
     if (left >= kGraphChunk && !c->graph_failed && !c->profiling) {
@@ -734,6 +745,8 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
     }
     for (; left > 0; --left) enqueue_step(c);
     if (c->lay.pair_grid > 0) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
+    // fixcom: the last step's centroid velocity is removed before the call ends
+    if (c->fa.fixcom) launch_apply_ucom(c->fa, c->stream);
     return launch_error(c, "step launch");
 }
 
@@ -858,6 +871,7 @@ int pimd_set_forces(pimd_ctx *c, const double *f, double epot)
     // a pending closing kick and the estimators of this state (or, right after
     // set_state, the estimators alone)
     enqueue_fused(c, c->synced ? FUSED_EST : FUSED_CLOSE, PIMD_KERNEL_CLOSE);
+    if (c->fa.fixcom) launch_apply_ucom(c->fa, c->stream);
     c->forces_current = true;
     c->synced = true;
     return launch_error(c, "set_forces launch");
@@ -1110,6 +1124,7 @@ int pimd_batch_add(pimd_batch *b, const pimd_params *p, const double *mass, cons
     if (!b || !sys || !p) return bfail(b, PIMD_ERR_ARG, "NULL argument");
     if (p->potential == PIMD_POT_EXTERNAL)
         return bfail(b, PIMD_ERR_UNSUPPORTED, "external forces are not batched (the caller steps each system)");
+    if (p->fixcom) return bfail(b, PIMD_ERR_UNSUPPORTED, "fixcom is not batched");
     pimd_ctx *c = nullptr;
     int rc = pimd_create(p, mass, topo, nullptr, 0, (void *)b->stream, &c);
     if (rc != PIMD_OK) return bfail(b, rc, pimd_last_error(nullptr));

@@ -115,6 +115,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const long long budget = a.ctl->budget;
     const unsigned long long step = a.ctl->step;
     const int synced = a.ctl->synced;
+    // fixcom: the last step's centroid-mode velocity still to be removed
+    const bool ucom_now = a.fixcom && a.ctl->ucom_pending;
+    const double ucom[3] = {a.ctl->ucom[0], a.ctl->ucom[1], a.ctl->ucom[2]};
     // a system whose step budget is spent takes no step (uniform per block)
     const bool spent = budget == 0;
     const bool ext = !a.pair;
@@ -135,6 +138,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
 
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
     double acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
+    double acc_p[3] = {0.0, 0.0, 0.0};   // fixcom: sum of hm v~0 after a step's end
 
     const int nbt = (N + 16 * T - 1) / (16 * T);
     for (int bt = first; bt < nbt; bt += stride) {
@@ -250,6 +254,10 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 x0[d] = ar[TA_X0 + d];
                 vt[d] = rv[r][d];
             }
+            if (ucom_now && m == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] -= ucom[d];
+            }
             if (ext) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ft[d] = -2.0 * hm * a.omega2 * (xt[d] + off * x0[d]);
@@ -276,6 +284,10 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
                 // OBABO: the last O of the step being closed
                 if (OB && a.nvt) o_step(step - 1, 1);
+                if (a.fixcom && m == 0) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
+                }
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     acc_ekin += hm * vt[d] * vt[d];
@@ -307,6 +319,10 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                     vt[d] += a.hdt * im * ft[d];
                 }
                 if (OB && a.nvt) o_step(step, 1);
+                if (a.fixcom && m == 0) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
+                }
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const double xa = xt[d] + off * x0[d];
@@ -387,9 +403,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     if (spent) return;
     __syncthreads();
     double *red = smem;
-    double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
+    double s4[7] = {acc_ekin, acc_esp, acc_vir, acc_uext, acc_p[0], acc_p[1], acc_p[2]};
     double m3[3] = {acc_emax, acc_dmax, acc_bad};
-    block_sum_max<4, 3>(s4, m3, red);
+    block_sum_max<7, 3>(s4, m3, red);
     const double emax = m3[0], dmax = m3[1], bad = m3[2];
     if (t == 0) {
         double *pp = partial_out;
@@ -400,6 +416,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         pp[PF_EMAX] = emax;
         pp[PF_DMAX] = dmax;
         pp[PF_NONFINITE] = bad;
+        pp[PF_PX] = s4[4];
+        pp[PF_PY] = s4[5];
+        pp[PF_PZ] = s4[6];
     }
 }
 

@@ -27,7 +27,9 @@ constexpr int kClusterRows = 1536;       // doubles per staged chunk of neighbor
 constexpr int kClusterSmem = 8 * 2 * kClusterRows + 16 * kClusterMax;   // dynamic LDS bytes
 
 // Per-block partial slots written by the fused kernel.
-enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_PAD, PF_COUNT };
+// PF_PX..PF_PZ: sum of hm * v~0 over the block's atoms (fixcom momentum)
+enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_PX, PF_PY, PF_PZ,
+       PF_PAD, PF_COUNT };
 
 // Fused-kernel modes.
 enum FusedMode : int {
@@ -58,6 +60,9 @@ struct Ctl {
     double sumsq[kNumEst];
     int cell_ok;               // 1: the coming rebuild may use the sorted cells
     int cell_R[3];             // stencil half-width in cells per dim for that rebuild
+    double ucom[3];            // fixcom: centroid-mode velocity to subtract from every atom
+    int ucom_pending;          // 1: ucom is still to be subtracted
+    int pad2;
 };
 
 // One atom of a centroid cell as the list build reads it: its centroid, its
@@ -76,6 +81,8 @@ struct FusedArgs {
     int lists;                // 1: neighbor lists (rebuild decisions) exist
     int nvt;                  // 1: PILE-L O step
     int obabo;                // 1: OBABO splitting (O half steps around B A A B), 0: BAOAB
+    int fixcom;               // 1: centroid COM velocity removed at the end of every step
+    double inv_hsum;          // 1 / sum_i hm_i (fixcom)
     double hdt;               // dt / 2
     double omega2;            // external trap omega^2 (0 for none / pair)
     double skin;
@@ -176,6 +183,7 @@ void launch_export(const double *x, const double *v, const double *atoms_mass, c
                    const int *orig, double *xdst, double *pdst, int N, int P, hipStream_t s);
 void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s);
 void launch_store_scalar(double *dst, double v, hipStream_t s);
+void launch_apply_ucom(const FusedArgs &a, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, unsigned long long step, hipStream_t s);
 void launch_ctl_set_budget(Ctl *ctl, long long budget, hipStream_t s);
 

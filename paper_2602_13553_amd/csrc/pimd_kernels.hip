@@ -62,6 +62,9 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     const long long budget = a.ctl->budget;
     const unsigned long long step = a.ctl->step;
     const int synced = a.ctl->synced;
+    // fixcom: the last step's centroid-mode velocity still to be removed
+    const bool ucom_now = a.fixcom && a.mode == FUSED_STEP && a.ctl->ucom_pending;
+    const double ucom[3] = {a.ctl->ucom[0], a.ctl->ucom[1], a.ctl->ucom[2]};
     // a system whose step budget is spent takes no step (uniform per block)
     const bool spent = (a.mode == FUSED_STEP && budget == 0);
 
@@ -81,6 +84,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
 
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
     double acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
+    double acc_p[3] = {0.0, 0.0, 0.0};   // fixcom: sum of hm v~0 after a step's end
 
     double mk[8];
 #pragma unroll
@@ -215,6 +219,10 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             } else {
                 vt[0] = vpre[0]; vt[1] = vpre[1]; vt[2] = vpre[2];
             }
+            if (ucom_now && k == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] -= ucom[d];
+            }
             // absolute mode coordinate x~_k (differs from y~_k only for k = 0)
             const double off = (k == 0) ? sqrtP : 0.0;
             if (ext) {
@@ -244,6 +252,10 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
                 // OBABO: the last O of the step being closed
                 if (a.obabo && a.nvt) o_step(step - 1, 1);
+                if (a.fixcom && k == 0) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
+                }
             }
             if (est_now) {
 #pragma unroll
@@ -280,6 +292,10 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                         vt[d] += a.hdt * im * ft[d];
                     }
                     if (a.obabo && a.nvt) o_step(step, 1);
+                    if (a.fixcom && k == 0) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
+                    }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         const double xa = xt[d] + off * ref[d];
@@ -380,9 +396,9 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     // ---- per-block partials (plain stores; k_finalize runs after this
     // kernel, so the kernel boundary makes them visible)
     {
-        double s4[4] = {acc_ekin, acc_esp, acc_vir, acc_uext};
+        double s4[7] = {acc_ekin, acc_esp, acc_vir, acc_uext, acc_p[0], acc_p[1], acc_p[2]};
         double m3[3] = {acc_emax, acc_dmax, acc_bad};
-        block_sum_max<4, 3>(s4, m3, red);
+        block_sum_max<7, 3>(s4, m3, red);
         const double emax = m3[0], dmax = m3[1], bad = m3[2];
         if (t == 0) {
             double *pp = partial_out;
@@ -393,6 +409,9 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             pp[PF_EMAX] = emax;
             pp[PF_DMAX] = dmax;
             pp[PF_NONFINITE] = bad;
+            pp[PF_PX] = s4[4];
+            pp[PF_PY] = s4[5];
+            pp[PF_PZ] = s4[6];
         }
     }
 }
@@ -592,20 +611,21 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         n_rebuilds = c->n_rebuilds;
     }
 
-    double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // ekin, espring, vir, uext, pair energy, fixcom momentum (3)
+    double tot[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double mx[3] = {0.0, 0.0, 0.0};   // emax^2, dmax^2, non-finite flag
     // Loads in fixed batches held in registers, so that a batch's reads are in
     // flight together; out-of-range slots add +0, and each thread's sums run
     // in loop order, so the result is that of the plain loop.
     constexpr int NB = 4, NF = 16;
     for (int b0 = t; b0 < nblocks; b0 += NB * kBlock) {
-        double pv[NB][7];
+        double pv[NB][PF_PAD];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int b = b0 + u * kBlock;
             const double *pp = a.partials + (size_t)(b < nblocks ? b : 0) * PF_COUNT;
 #pragma unroll
-            for (int q = 0; q < 7; ++q) pv[u][q] = b < nblocks ? pp[q] : 0.0;
+            for (int q = 0; q < PF_PAD; ++q) pv[u][q] = b < nblocks ? pp[q] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -616,6 +636,9 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             mx[0] = fmax(mx[0], pv[u][PF_EMAX]);
             mx[1] = fmax(mx[1], pv[u][PF_DMAX]);
             mx[2] = fmax(mx[2], pv[u][PF_NONFINITE]);
+            tot[5] += pv[u][PF_PX];
+            tot[6] += pv[u][PF_PY];
+            tot[7] += pv[u][PF_PZ];
         }
     }
     // (summed whether or not this pass needs them, so the loads do not wait
@@ -632,7 +655,7 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             for (int u = 0; u < NF; ++u) tot[4] += fv[u];
         }
     }
-    block_sum_max<5, 3>(tot, mx, red);
+    block_sum_max<8, 3>(tot, mx, red);
     if (mode == FUSED_STEP && budget == 0) {
         // no step was taken: nothing to combine, and no force pass follows
         if (t == 0) c->ran = 0;
@@ -642,8 +665,23 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
     const double emax = sqrt(mx[0]), dmax = sqrt(mx[1]), bad = mx[2];
 
     if (t == 0) {
+        // fixcom: a step ended in this pass (closing half-kick, or the whole
+        // step with the trap): its centroid momentum Pi = sum hm v~0 fixes the
+        // velocity u = Pi / sum hm to remove from every atom's centroid mode,
+        // which lowers the kinetic energy by |Pi|^2 / sum hm
+        double dekin = 0.0;
+        if (a.fixcom && (closing || est_after)) {
+            const double px = tot[5], py = tot[6], pz = tot[7];
+            c->ucom[0] = px * a.inv_hsum;
+            c->ucom[1] = py * a.inv_hsum;
+            c->ucom[2] = pz * a.inv_hsum;
+            c->ucom_pending = 1;
+            dekin = (px * px + py * py + pz * pz) * a.inv_hsum;
+        } else if (a.fixcom && mode == FUSED_STEP) {
+            c->ucom_pending = 0;        // the step pass removed it
+        }
         if (est_now || est_after) {
-            const double ekin = tot[0], esp = tot[1], vir = tot[2];
+            const double ekin = tot[0] - dekin, esp = tot[1], vir = tot[2];
             const double epot = a.pair ? upair : tot[3];
             double v[kNumEst];
             v[0] = ekin;
@@ -1510,6 +1548,32 @@ __global__ void k_ctl_reset_sums(Ctl *c)
     }
 }
 
+// fixcom: remove a pending centroid-mode velocity from every atom (mode 0 of
+// v~ for each dim), then clear the flag in a launch of its own.
+__global__ void k_apply_ucom(FusedArgs a)
+{
+    if (!a.ctl->ucom_pending) return;
+    const double u0 = a.ctl->ucom[0], u1 = a.ctl->ucom[1], u2 = a.ctl->ucom[2];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += gridDim.x * blockDim.x) {
+        const size_t b = (size_t)i * 3 * a.P;
+        a.v[b] -= u0;
+        a.v[b + a.P] -= u1;
+        a.v[b + 2 * (size_t)a.P] -= u2;
+    }
+}
+
+__global__ void k_clear_ucom(Ctl *c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->ucom_pending = 0;
+}
+
+void launch_apply_ucom(const FusedArgs &a, hipStream_t s)
+{
+    const int grid = (a.N + 255) / 256 < 1024 ? (a.N + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_apply_ucom, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_clear_ucom, dim3(1), dim3(64), 0, s, a.ctl);
+}
+
 __global__ void k_store_scalar(double *dst, double v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
@@ -1534,6 +1598,8 @@ __global__ void k_ctl_init(Ctl *c, unsigned long long step)
         c->budget = -1;
         c->ran = 1;
         c->cell_ok = 0;
+        c->ucom[0] = c->ucom[1] = c->ucom[2] = 0.0;
+        c->ucom_pending = 0;
         c->est_step = step;
         c->count = 0;
         for (int q = 0; q < kNumEst; ++q) {

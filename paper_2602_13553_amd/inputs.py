@@ -73,6 +73,7 @@ class SystemSpec:
     bond_r0: float = 0.0
     skin: float = 0.3               # neighbor-list skin (GPU library only)
     integrator: int = 0             # 0: BAOAB, 1: OBABO
+    fixcom: int = 0                 # 1: remove the centroids' COM velocity every step
     lj_active: np.ndarray | None = None   # [N] 0/1
     bonds: np.ndarray | None = None       # [n_bonds][2]
     nsteps: int = 0                 # length of the workload's run

@@ -58,6 +58,7 @@ class pimd_params(C.Structure):
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double), ("lj_rc", C.c_double),
         ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("nbr_capacity", C.c_int32), ("flags", C.c_int32), ("integrator", C.c_int32),
+        ("fixcom", C.c_int32),
     ]
 
 
@@ -184,6 +185,7 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     p.lj_eps, p.lj_sigma, p.lj_rc = spec.lj_eps, spec.lj_sigma, spec.lj_rc
     p.skin, p.bond_k, p.bond_r0 = spec.skin, spec.bond_k, spec.bond_r0
     p.integrator = int(getattr(spec, "integrator", PIMD_BAOAB))
+    p.fixcom = int(getattr(spec, "fixcom", 0))
     return p
 
 

@@ -89,6 +89,21 @@ def test_external_forces_match_oracle(N, P, mfma):
     assert gest["count"] == 10
 
 
+def test_external_forces_with_fixcom_and_obabo():
+    pimd = _pimd()
+    spec = external_spec(37, 8, seed=41)
+    spec.fixcom = 1
+    spec.integrator = pimd.PIMD_OBABO
+    g, o = run_external(spec, 10)
+    gx, gp, gs, gest = g
+    ox, op, os_, oest = o
+    assert gs == os_ == 10
+    assert rel(gx, ox) <= TOL and rel(gp, op) <= TOL
+    scale = max(abs(oest["ekin"]), abs(oest["espring"]), abs(oest["epot"]))
+    for name in ("ekin", "espring", "epot", "etot", "kprim", "kcv"):
+        assert abs(gest[name] - oest[name]) <= 1e-10 * scale, name
+
+
 def test_external_forces_call_order():
     import torch
     pimd = _pimd()
@@ -131,5 +146,10 @@ def test_external_forces_call_order():
     b = pimd.Batch()
     with pytest.raises(pimd.PimdError) as e:
         b.add(spec)
+    assert e.value.code == -6
+    fx = inputs.harmonic_tiny(n_atoms=12, n_beads=4, seed=3)
+    fx.fixcom = 1
+    with pytest.raises(pimd.PimdError) as e:
+        b.add(fx)                        # fixcom is not batched either
     assert e.value.code == -6
     b.close()

@@ -221,6 +221,34 @@ def test_obabo_matches_oracle(kind, N, P, mfma):
     check_states(g, o)
 
 
+# ------------------------------------------------------------ fixcom
+@pytest.mark.parametrize("kind,N,P,mfma,obabo", [
+    ("harmonic", 37, 8, False, False), ("harmonic", 50, 32, True, False),
+    ("lj", 256, 8, False, False), ("lj", 130, 64, True, False), ("water", 387, 32, False, False),
+    ("lj", 108, 8, False, True), ("harmonic", 20, 16, True, True)])
+def test_fixcom_matches_oracle(kind, N, P, mfma, obabo):
+    """The centroids' center-of-mass velocity removed at the end of every step:
+    in-kernel for the trap, through a closing pass of its own before each step
+    with the pair potentials; estimators of the state after the removal."""
+    pimd = _pimd()
+    if kind == "harmonic":
+        spec = inputs.harmonic_tiny(n_atoms=N, n_beads=P, seed=5 * N + P)
+    elif kind == "lj":
+        spec = inputs.lj_liquid(n_atoms=N, n_beads=P, seed=N + 3 * P)
+    else:
+        spec = inputs.water(n_atoms=N, n_beads=P, seed=N + 2)
+    spec.fixcom = 1
+    spec.integrator = pimd.PIMD_OBABO if obabo else pimd.PIMD_BAOAB
+    g, o = run_pair(spec, 10, chunks=[1, 7, 2],
+                    flags=pimd.PIMD_FLAG_MFMA_TRANSFORMS if mfma else 0)
+    check_states(g, o)
+    gx, gp, gs, gest = g
+    mass = np.asarray(spec.mass)
+    com = (gp.mean(axis=0)).sum(axis=0) / mass.sum()   # centroid COM velocity
+    assert np.abs(com).max() <= 1e-12 * np.abs(gp / mass[None, :, None]).max()
+    assert gest["count"] == 10
+
+
 # ------------------------------------------------------------ cluster lists
 @pytest.mark.parametrize("case", ["lj_full", "lj_p16", "lj_small_box", "water_p32", "water_small"])
 def test_cluster_pairs(case):

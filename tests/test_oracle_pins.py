@@ -503,3 +503,38 @@ def test_obabo_free_rp_mode_variances_exact():
     for k in range(P):
         mm, se = _block_mean((vs[:, k] ** 2).mean(axis=(1, 2)))
         assert abs(mm - P * kT) < 4 * se, (k, mm, se)
+
+
+# ---------------------------------------------------------------- fixcom
+def test_fixcom_removes_the_centroid_com_velocity_by_hand():
+    """One NVT step with fixcom equals the same step without it followed by
+    subtracting, from every bead's Cartesian velocity, the mass-weighted mean
+    of the centroid velocities (bead averages), written out here; the other
+    parts of the bead velocities are untouched."""
+    spec = inputs.harmonic_tiny(n_atoms=7, n_beads=4, seed=31)
+    spec.mass = np.array([1.0, 2.0, 0.5, 3.0, 1.5, 1.0, 2.5])
+    a = oracle.State.from_spec(spec, step=5)
+    a.step(1)
+    spec.fixcom = 1
+    b = oracle.State.from_spec(spec, step=5)
+    assert b.sys.fixcom == 1
+    b.step(1)
+    va = a.v                                    # [P][N][3] Cartesian
+    vc = va.mean(axis=0)                        # centroid velocities [N][3]
+    V = (spec.mass[:, None] * vc).sum(axis=0) / spec.mass.sum()
+    assert np.abs(b.v - (va - V[None, None, :])).max() < 1e-14
+    assert np.array_equal(a.x, b.x)             # positions are those of the step
+    vcb = b.v.mean(axis=0)
+    assert np.abs((spec.mass[:, None] * vcb).sum(axis=0)).max() < 1e-13
+
+
+def test_fixcom_keeps_zero_com_with_thermostat_and_pair_forces():
+    s, x = _lj_box(N=20, L=5.8, seed=4, P=4)
+    s.temp, s.hbar, s.dt, s.seed, s.fixcom = 0.8, 0.2, 0.002, 5, 1
+    rng = np.random.default_rng(6)
+    st = oracle.State(s, x[None] + 0.02 * rng.standard_normal((4, 20, 3)),
+                      rng.standard_normal((4, 20, 3)))
+    for _ in range(5):
+        st.step(1)
+        com = (s.mass[:, None] * st.v.mean(axis=0)).sum(axis=0)
+        assert np.abs(com).max() < 1e-12, com
