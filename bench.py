@@ -381,6 +381,14 @@ def main():
         out["obabo"] = {"workload": title + ", OBABO splitting (two O half steps per step)",
                         "ms_per_step": ms_ob, "bead_atom_steps_per_s": ob.bead_atoms * 1e3 / ms_ob,
                         "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_ob).items()}}
+        log("fixcom")
+        fc = make()
+        fc.fixcom = 1
+        ms_fc, _, prof_fc, _, _, _ = run_gpu(fc, 500, 50, 100, flags)
+        out["fixcom"] = {"workload": title + ", fixcom (centroid COM velocity removed every step; "
+                                             "the closing half-kick in a pass of its own)",
+                         "ms_per_step": ms_fc, "bead_atom_steps_per_s": fc.bead_atoms * 1e3 / ms_fc,
+                         "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_fc).items()}}
         log("external forces")
         out["external_forces"] = bench_external()
         log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))
