@@ -55,8 +55,8 @@ KERNEL_SOURCES = ("pimd_device.h", "pimd_fused_mfma.hip", "pimd_internal.h", "pi
 # committed rocprofv3 summaries by (workload, kernel)
 PROFILE_FILES = {
     ("lj", "k_pair"): "k_pair_lj_n4000_p32.txt",
-    ("lj", "k_fused"): "k_fused_lj_n4000_p32.txt",
-    ("water64", "k_fused_mfma<64, false>"): "k_fused_mfma_water_n32766_p64.txt",
+    ("lj", "k_fused<false>"): "k_fused_lj_n4000_p32.txt",
+    ("water64", "k_fused_mfma<64, false, false>"): "k_fused_mfma_water_n32766_p64.txt",
     ("water64", "k_pair"): "k_pair_water_n32766_p64.txt",
 }
 
@@ -296,9 +296,10 @@ def main():
     log("ms/step %.4f (profiled %.4f); kernels %s" % (ms_step, ms_prof, avgs))
 
     # dominant kernel of the workload and its roofline
-    # the matrix-core pass is instantiated per splitting (false: BAOAB)
-    fused_name = (("k_fused_mfma<%d, %s>" % (spec.n_beads, "true" if spec.integrator else "false"))
-                  if info["transforms"] else "k_fused")
+    # the step passes are instantiated per splitting and fixcom (false: BAOAB, none)
+    tf = lambda v: "true" if v else "false"
+    fused_name = (("k_fused_mfma<%d, %s, %s>" % (spec.n_beads, tf(spec.integrator), tf(spec.fixcom)))
+                  if info["transforms"] else "k_fused<%s>" % tf(spec.fixcom))
     dom = max(("fused", "pair"), key=lambda k: avgs[k][0] * avgs[k][1])
     if dom == "pair":
         npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc, spec.lj_active)
@@ -356,8 +357,8 @@ def main():
         ms_w, _, prof_w, _, _, info_w = run_gpu(w, 50, 10, 50)
         aw = kernel_avgs(prof_w)
         gbs = FUSED_BYTES_PAIR * w.bead_atoms / (aw["fused"][0] * 1e-3) / 1e9
-        # the matrix-core pass is instantiated per splitting (false: BAOAB)
-        kname = ("k_fused_mfma<64, false>" if info_w["transforms"] else "k_fused")
+        # the step passes are instantiated per splitting and fixcom (false: BAOAB, none)
+        kname = ("k_fused_mfma<64, false, false>" if info_w["transforms"] else "k_fused<false>")
         out["fused_roofline"] = {"kernel": kname, "workload": w.name, "bound": "hbm",
                                  "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": gbs / HBM_PEAK_GBS,

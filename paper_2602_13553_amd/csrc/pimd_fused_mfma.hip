@@ -89,7 +89,7 @@ enum { TA_X0 = 0, TA_HM = 3, TA_IM = 4, TA_SG = 5, TA_ACT = 6, TA_ORIG = 7, TA_C
 // releases the previous tile's LDS; the forward products read x and f from
 // LDS; after a barrier the y~ of the update overwrite the x region; a last
 // barrier precedes the inverse products.
-template <int P, bool OB>
+template <int P, bool OB, bool FC>
 __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *smem,
                            double *partial_out)
 {
@@ -116,7 +116,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     const unsigned long long step = a.ctl->step;
     const int synced = a.ctl->synced;
     // fixcom: the last step's centroid-mode velocity still to be removed
-    const bool ucom_now = a.fixcom && a.ctl->ucom_pending;
+    const bool ucom_now = FC && a.ctl->ucom_pending;
     const double ucom[3] = {a.ctl->ucom[0], a.ctl->ucom[1], a.ctl->ucom[2]};
     // a system whose step budget is spent takes no step (uniform per block)
     const bool spent = budget == 0;
@@ -284,7 +284,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
                 // OBABO: the last O of the step being closed
                 if (OB && a.nvt) o_step(step - 1, 1);
-                if (a.fixcom && m == 0) {
+                if (FC && m == 0) {
 #pragma unroll
                     for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
                 }
@@ -319,7 +319,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                     vt[d] += a.hdt * im * ft[d];
                 }
                 if (OB && a.nvt) o_step(step, 1);
-                if (a.fixcom && m == 0) {
+                if (FC && m == 0) {
 #pragma unroll
                     for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
                 }
@@ -403,9 +403,14 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     if (spent) return;
     __syncthreads();
     double *red = smem;
-    double s4[7] = {acc_ekin, acc_esp, acc_vir, acc_uext, acc_p[0], acc_p[1], acc_p[2]};
+    constexpr int NS = FC ? 7 : 4;   // the fixcom momentum only where it is used
+    double s4[NS];
+    s4[0] = acc_ekin; s4[1] = acc_esp; s4[2] = acc_vir; s4[3] = acc_uext;
+    if constexpr (FC) {
+        s4[4] = acc_p[0]; s4[5] = acc_p[1]; s4[6] = acc_p[2];
+    }
     double m3[3] = {acc_emax, acc_dmax, acc_bad};
-    block_sum_max<7, 3>(s4, m3, red);
+    block_sum_max<NS, 3>(s4, m3, red);
     const double emax = m3[0], dmax = m3[1], bad = m3[2];
     if (t == 0) {
         double *pp = partial_out;
@@ -416,19 +421,19 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         pp[PF_EMAX] = emax;
         pp[PF_DMAX] = dmax;
         pp[PF_NONFINITE] = bad;
-        pp[PF_PX] = s4[4];
-        pp[PF_PY] = s4[5];
-        pp[PF_PZ] = s4[6];
+        pp[PF_PX] = FC ? s4[NS > 4 ? 4 : 0] : 0.0;
+        pp[PF_PY] = FC ? s4[NS > 5 ? 5 : 0] : 0.0;
+        pp[PF_PZ] = FC ? s4[NS > 6 ? 6 : 0] : 0.0;
     }
 }
 
 // OB: the OBABO splitting (a kernel of its own, so that BAOAB keeps its
 // register budget).
-template <int P, bool OB>
+template <int P, bool OB, bool FC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mfma(FusedArgs a)
 {
     extern __shared__ double smem[];
-    mfma_tiles<P, OB>(a, blockIdx.x, gridDim.x, smem, a.partials + (size_t)blockIdx.x * PF_COUNT);
+    mfma_tiles<P, OB, FC>(a, blockIdx.x, gridDim.x, smem, a.partials + (size_t)blockIdx.x * PF_COUNT);
 }
 
 // Batched: one block per item (system, block tile of T x 16 atoms), for the
@@ -441,7 +446,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if ((int)blockIdx.x >= n_items) return;
     const int2 item = items[blockIdx.x];
     const FusedArgs &a = table[item.x];
-    mfma_tiles<P, OB>(a, item.y, 1 << 30, smem, a.partials + (size_t)item.y * PF_COUNT);
+    // (batches hold no fixcom systems)
+    mfma_tiles<P, OB, false>(a, item.y, 1 << 30, smem, a.partials + (size_t)item.y * PF_COUNT);
 }
 
 namespace {
@@ -449,9 +455,13 @@ namespace {
 template <int P>
 int grid_for(int N)
 {
-    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, false>,
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, false, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
-    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, true>,
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, true, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
+    (void)hipFuncSetAttribute((const void *)k_fused_mfma<P, true, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, Lds<P>::bytes);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
@@ -459,7 +469,7 @@ int grid_for(int N)
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
     int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_mfma<P, false>, kBlock,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused_mfma<P, false, false>, kBlock,
                                                      Lds<P>::bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -471,10 +481,15 @@ int grid_for(int N)
 template <int P>
 void launch_one(const FusedArgs &a, int grid, hipStream_t s)
 {
-    if (a.obabo)
-        hipLaunchKernelGGL((k_fused_mfma<P, true>), dim3(grid), dim3(kBlock), Lds<P>::bytes, s, a);
+    const size_t sm = Lds<P>::bytes;
+    if (a.obabo && a.fixcom)
+        hipLaunchKernelGGL((k_fused_mfma<P, true, true>), dim3(grid), dim3(kBlock), sm, s, a);
+    else if (a.obabo)
+        hipLaunchKernelGGL((k_fused_mfma<P, true, false>), dim3(grid), dim3(kBlock), sm, s, a);
+    else if (a.fixcom)
+        hipLaunchKernelGGL((k_fused_mfma<P, false, true>), dim3(grid), dim3(kBlock), sm, s, a);
     else
-        hipLaunchKernelGGL((k_fused_mfma<P, false>), dim3(grid), dim3(kBlock), Lds<P>::bytes, s, a);
+        hipLaunchKernelGGL((k_fused_mfma<P, false, false>), dim3(grid), dim3(kBlock), sm, s, a);
 }
 
 template <int P>

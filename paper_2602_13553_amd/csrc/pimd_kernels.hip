@@ -35,6 +35,9 @@ int fused_smem_bytes(int P)
 // Processes tiles t0, t0 + tstride, ... of one system and writes one set of
 // partials.  stage_m = false keeps the matrix already staged in shared
 // memory (same system or same P as the previous call of this block).
+// FC: the system removes its centroids' center-of-mass velocity (fixcom); a
+// separate instantiation, so that the others carry none of its code.
+template <bool FC>
 __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *smem, double *red,
                            double *partial_out, bool stage_m)
 {
@@ -63,7 +66,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     const unsigned long long step = a.ctl->step;
     const int synced = a.ctl->synced;
     // fixcom: the last step's centroid-mode velocity still to be removed
-    const bool ucom_now = a.fixcom && a.mode == FUSED_STEP && a.ctl->ucom_pending;
+    const bool ucom_now = FC && a.mode == FUSED_STEP && a.ctl->ucom_pending;
     const double ucom[3] = {a.ctl->ucom[0], a.ctl->ucom[1], a.ctl->ucom[2]};
     // a system whose step budget is spent takes no step (uniform per block)
     const bool spent = (a.mode == FUSED_STEP && budget == 0);
@@ -252,7 +255,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                 for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
                 // OBABO: the last O of the step being closed
                 if (a.obabo && a.nvt) o_step(step - 1, 1);
-                if (a.fixcom && k == 0) {
+                if (FC && k == 0) {
 #pragma unroll
                     for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
                 }
@@ -292,7 +295,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
                         vt[d] += a.hdt * im * ft[d];
                     }
                     if (a.obabo && a.nvt) o_step(step, 1);
-                    if (a.fixcom && k == 0) {
+                    if (FC && k == 0) {
 #pragma unroll
                         for (int d = 0; d < 3; ++d) acc_p[d] += hm * vt[d];
                     }
@@ -396,9 +399,14 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     // ---- per-block partials (plain stores; k_finalize runs after this
     // kernel, so the kernel boundary makes them visible)
     {
-        double s4[7] = {acc_ekin, acc_esp, acc_vir, acc_uext, acc_p[0], acc_p[1], acc_p[2]};
+        constexpr int NS = FC ? 7 : 4;   // the fixcom momentum only where it is used
+        double s4[NS];
+        s4[0] = acc_ekin; s4[1] = acc_esp; s4[2] = acc_vir; s4[3] = acc_uext;
+        if constexpr (FC) {
+            s4[4] = acc_p[0]; s4[5] = acc_p[1]; s4[6] = acc_p[2];
+        }
         double m3[3] = {acc_emax, acc_dmax, acc_bad};
-        block_sum_max<7, 3>(s4, m3, red);
+        block_sum_max<NS, 3>(s4, m3, red);
         const double emax = m3[0], dmax = m3[1], bad = m3[2];
         if (t == 0) {
             double *pp = partial_out;
@@ -409,19 +417,20 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             pp[PF_EMAX] = emax;
             pp[PF_DMAX] = dmax;
             pp[PF_NONFINITE] = bad;
-            pp[PF_PX] = s4[4];
-            pp[PF_PY] = s4[5];
-            pp[PF_PZ] = s4[6];
+            pp[PF_PX] = FC ? s4[NS > 4 ? 4 : 0] : 0.0;
+            pp[PF_PY] = FC ? s4[NS > 5 ? 5 : 0] : 0.0;
+            pp[PF_PZ] = FC ? s4[NS > 6 ? 6 : 0] : 0.0;
         }
     }
 }
 
+template <bool FC>
 __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
 {
     extern __shared__ double smem[];
     __shared__ double red[64];
-    fused_tiles(a, blockIdx.x, gridDim.x, smem, red, a.partials + (size_t)blockIdx.x * PF_COUNT,
-                true);
+    fused_tiles<FC>(a, blockIdx.x, gridDim.x, smem, red, a.partials + (size_t)blockIdx.x * PF_COUNT,
+                    true);
 }
 
 // Batched: item (system, tile); the system's arguments come from the table and
@@ -440,7 +449,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_batch(const FusedArgs *__restr
         const int tile = __builtin_amdgcn_readfirstlane(items[it].y);
         FusedArgs a = table[sys];
         a.mode = mode;
-        fused_tiles(a, tile, 1 << 30, smem, red, a.partials + (size_t)tile * PF_COUNT, sys != prev);
+        // (batches hold no fixcom systems)
+        fused_tiles<false>(a, tile, 1 << 30, smem, red, a.partials + (size_t)tile * PF_COUNT,
+                           sys != prev);
         prev = sys;
     }
 }
@@ -579,6 +590,8 @@ __device__ void cells_finalize(const FusedArgs &a, double rlist, int *scnt /* [4
     }
 }
 
+// FC: the system uses fixcom (its partials carry the centroid momentum)
+template <bool FC>
 __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, int *sbuf, int *sflag)
 {
     const int t = threadIdx.x;
@@ -619,13 +632,14 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
     // in loop order, so the result is that of the plain loop.
     constexpr int NB = 4, NF = 16;
     for (int b0 = t; b0 < nblocks; b0 += NB * kBlock) {
+        constexpr int NQ = FC ? PF_PAD : PF_NONFINITE + 1;
         double pv[NB][PF_PAD];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int b = b0 + u * kBlock;
             const double *pp = a.partials + (size_t)(b < nblocks ? b : 0) * PF_COUNT;
 #pragma unroll
-            for (int q = 0; q < PF_PAD; ++q) pv[u][q] = b < nblocks ? pp[q] : 0.0;
+            for (int q = 0; q < PF_PAD; ++q) pv[u][q] = (q < NQ && b < nblocks) ? pp[q] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -670,14 +684,14 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         // velocity u = Pi / sum hm to remove from every atom's centroid mode,
         // which lowers the kinetic energy by |Pi|^2 / sum hm
         double dekin = 0.0;
-        if (a.fixcom && (closing || est_after)) {
+        if (FC && (closing || est_after)) {
             const double px = tot[5], py = tot[6], pz = tot[7];
             c->ucom[0] = px * a.inv_hsum;
             c->ucom[1] = py * a.inv_hsum;
             c->ucom[2] = pz * a.inv_hsum;
             c->ucom_pending = 1;
             dekin = (px * px + py * py + pz * pz) * a.inv_hsum;
-        } else if (a.fixcom && mode == FUSED_STEP) {
+        } else if (FC && mode == FUSED_STEP) {
             c->ucom_pending = 0;        // the step pass removed it
         }
         if (est_now || est_after) {
@@ -736,12 +750,13 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
     }
 }
 
+template <bool FC>
 __global__ __launch_bounds__(kBlock) void k_finalize(FusedArgs a, int nblocks)
 {
     __shared__ double red[64];
     __shared__ __align__(16) int sbuf[4 * kMaxCells];
     __shared__ int sflag[1];
-    finalize_system(a, nblocks, red, sbuf, sflag);
+    finalize_system<FC>(a, nblocks, red, sbuf, sflag);
 }
 
 // Batched: block s finalizes system s from its per-tile partials.
@@ -754,7 +769,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(const FusedArgs *tabl
     for (int sidx = blockIdx.x; sidx < n_sys; sidx += gridDim.x) {
         FusedArgs a = table[sidx];
         a.mode = mode;
-        if (nparts[sidx] > 0) finalize_system(a, nparts[sidx], red, sbuf, sflag);
+        // (batches hold no fixcom systems)
+        if (nparts[sidx] > 0) finalize_system<false>(a, nparts[sidx], red, sbuf, sflag);
         __syncthreads();
     }
 }
@@ -769,10 +785,12 @@ int fused_grid(int N, int P)
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
     }
     // large P needs more than the default 64 KB of dynamic LDS per block
-    (void)hipFuncSetAttribute((const void *)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_fused<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              fused_smem_bytes(P));
+    (void)hipFuncSetAttribute((const void *)k_fused<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               fused_smem_bytes(P));
     int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, kBlock, fused_smem_bytes(P)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<false>, kBlock, fused_smem_bytes(P)) !=
             hipSuccess || per_cu < 1)
         per_cu = 1;
     const int cap = ncu * per_cu;
@@ -781,12 +799,18 @@ int fused_grid(int N, int P)
 
 void launch_fused(const FusedArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kBlock), fused_smem_bytes(a.P), s, a);
+    if (a.fixcom)
+        hipLaunchKernelGGL(k_fused<true>, dim3(grid), dim3(kBlock), fused_smem_bytes(a.P), s, a);
+    else
+        hipLaunchKernelGGL(k_fused<false>, dim3(grid), dim3(kBlock), fused_smem_bytes(a.P), s, a);
 }
 
 void launch_finalize(const FusedArgs &a, int fused_blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, a, fused_blocks);
+    if (a.fixcom)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(1), dim3(kBlock), 0, s, a, fused_blocks);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(kBlock), 0, s, a, fused_blocks);
 }
 
 // --------------------------------------------------------------------------
