@@ -150,10 +150,10 @@ typedef struct pimd_topology {
 
 /* Instantaneous estimators at the state's step, and running sums over every
  * step completed by pimd_step since the last pimd_reset_averages. */
-#define PIMD_NEST 7
+#define PIMD_NEST 8
 typedef struct pimd_estimators {
     uint64_t step;     /* thermostat step counter of the state */
-    /* order of the arrays below: ekin, espring, epot, etot, kprim, kcv, temp */
+    /* order of the arrays below: ekin, espring, epot, etot, kprim, kcv, temp, pcv */
     double value[PIMD_NEST];
     uint64_t count;    /* number of steps in the running sums */
     double sum[PIMD_NEST];
@@ -170,7 +170,16 @@ typedef struct pimd_estimators {
  * etot    = H = ekin + espring + epot (Eq. A4)
  * kprim   = K_PR = 3 P N kB T / 2 - espring / P (Eq. A5, read with the 1/P)
  * kcv     = K_CV = 3 N kB T / 2 - (1/2P) sum_k sum_i (r_i^k - r_i^c).F_i^k (Eq. A7)
- * temp    = 2 ekin / (3 N P^2 kB): the ring-polymer temperature over P (Sec. III.A) */
+ * temp    = 2 ekin / (3 N P^2 kB): the ring-polymer temperature over P (Sec. III.A)
+ * pcv     = P_CV, the centroid-virial pressure (App. A):
+ *           [sum_i m_i |v~_i^(0)|^2 - sum_k sum_i (r_i^k - r_i^c).F_i^k
+ *            + sum_k Tr Xi^k] / (3 P V), with V the box volume and Tr Xi^k the
+ *           cell virial of bead k (the sum of r_ij.F_ij over interacting pairs,
+ *           every periodic image, and bonds; equal to minus the derivative of
+ *           U^(k) under a uniform scaling of positions and box).  Computed for
+ *           PIMD_POT_LJ and PIMD_POT_WATER; 0 for every other potential, whose
+ *           forces carry no cell virial here.  With fixcom the centroid term is
+ *           taken after the center-of-mass velocity is removed. */
 
 typedef struct pimd_ctx pimd_ctx;
 

@@ -53,7 +53,8 @@ class _System(C.Structure):
 
 
 class _Est(C.Structure):
-    _fields_ = [(n, C.c_double) for n in ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")]
+    _fields_ = [(n, C.c_double) for n in ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp",
+                                          "pcv")]
 
 
 _lib = None
@@ -78,6 +79,7 @@ def lib():
             "orc_pile_coeffs": (None, [S, C.c_int32, d, d]),
             "orc_forces_bead": (C.c_double, [S, d, d]),
             "orc_forces": (None, [S, d, d, d]),
+            "orc_virial_bead": (C.c_double, [S, d]),
             "orc_step": (None, [S, d, d, d, d, u64, C.c_int32]),
             "orc_step_positions": (None, [S, d, d, d, u64]),
             "orc_step_kick": (None, [S, d, d, C.c_uint64]),
@@ -230,6 +232,11 @@ class System:
         lib().orc_forces(C.byref(self.cstruct()), _dp(x), _dp(f), _dp(U))
         return f, U
 
+    def virial(self, xk: np.ndarray) -> float:
+        """Cell virial Tr Xi of one bead configuration xk [N][3]."""
+        xk = np.ascontiguousarray(xk, dtype=np.float64)
+        return lib().orc_virial_bead(C.byref(self.cstruct()), _dp(xk))
+
     def spring_energy_nm(self, x: np.ndarray) -> float:
         x = np.ascontiguousarray(x, dtype=np.float64)
         return lib().orc_spring_energy_nm(C.byref(self.cstruct()), _dp(x))
@@ -240,7 +247,7 @@ class System:
         return lib().orc_kcv_nm(C.byref(self.cstruct()), _dp(x), _dp(f))
 
 
-ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
+ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv")
 
 
 class State:

@@ -351,6 +351,77 @@ double orc_forces_bead(const orc_system *sys, const double *xk, double *fk)
     return U;
 }
 
+double orc_virial_bead(const orc_system *sys, const double *xk)
+{
+    const int32_t N = sys->n_atoms;
+    if (sys->pot != ORC_POT_PAIR || !(sys->box[0] > 0.0)) return 0.0;
+    const double L0 = sys->box[0], L1 = sys->box[1], L2 = sys->box[2];
+    const double rc = sys->lj_rc, rc2 = rc * rc;
+    const double eps = sys->lj_eps, sig = sys->lj_sigma;
+    double src2 = sig * sig / rc2, src6 = src2 * src2 * src2;
+    const double ushift = 4.0 * eps * (src6 * src6 - src6);
+    const int minimg = (L0 >= 2.0 * rc) && (L1 >= 2.0 * rc) && (L2 >= 2.0 * rc);
+    const int n0 = (int)ceil(rc / L0) + 1, n1 = (int)ceil(rc / L1) + 1, n2 = (int)ceil(rc / L2) + 1;
+    /* every ordered pair (i, j, image) once, half each: r . F = fr r^2; per
+     * atom, then summed in atom order */
+    double *wat = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+    if (eps != 0.0) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int32_t i = 0; i < N; ++i) {
+            if (sys->lj_active && !sys->lj_active[i]) continue;
+            double wi = 0.0;
+            for (int32_t j = 0; j < N; ++j) {
+                if (sys->lj_active && !sys->lj_active[j]) continue;
+                double dx = xk[3 * i] - xk[3 * j];
+                double dy = xk[3 * i + 1] - xk[3 * j + 1];
+                double dz = xk[3 * i + 2] - xk[3 * j + 2];
+                if (minimg) {
+                    /* at most one image of j within rc: the nearest */
+                    if (j == i) continue;
+                    dx -= L0 * nearbyint(dx / L0);
+                    dy -= L1 * nearbyint(dy / L1);
+                    dz -= L2 * nearbyint(dz / L2);
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < rc2) {
+                        double u, fr;
+                        lj_pair(eps, sig, rc2, ushift, r2, &u, &fr);
+                        wi += 0.5 * fr * r2;
+                    }
+                    continue;
+                }
+                for (int a = -n0; a <= n0; ++a)
+                    for (int b = -n1; b <= n1; ++b)
+                        for (int c = -n2; c <= n2; ++c) {
+                            if (j == i && a == 0 && b == 0 && c == 0) continue;
+                            double ex = dx + a * L0, ey = dy + b * L1, ez = dz + c * L2;
+                            double r2 = ex * ex + ey * ey + ez * ez;
+                            if (r2 < rc2) {
+                                double u, fr;
+                                lj_pair(eps, sig, rc2, ushift, r2, &u, &fr);
+                                wi += 0.5 * fr * r2;
+                            }
+                        }
+            }
+            wat[i] = wi;
+        }
+    }
+    double w = 0.0;
+    for (int32_t i = 0; i < N; ++i) w += wat[i];
+    free(wat);
+    for (int32_t b = 0; b < sys->n_bonds; ++b) {
+        int32_t i = sys->bonds[2 * b], j = sys->bonds[2 * b + 1];
+        double d[3];
+        for (int a = 0; a < 3; ++a) {
+            d[a] = xk[3 * i + a] - xk[3 * j + a];
+            d[a] -= sys->box[a] * nearbyint(d[a] / sys->box[a]);
+        }
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double fr = -2.0 * sys->bond_k * (r - sys->bond_r0) / r;
+        w += fr * r * r;
+    }
+    return w;
+}
+
 void orc_forces(const orc_system *sys, const double *x, double *f, double *U)
 {
     const size_t stride = 3 * (size_t)sys->n_atoms;
@@ -573,6 +644,20 @@ void orc_estimators(const orc_system *sys, const double *x, const double *vt,
     out->kprim = 1.5 * (double)P * (double)N * kT - espring / (double)P;
     out->kcv = 1.5 * (double)N * kT - vir / (2.0 * (double)P);
     out->temp = 2.0 * ekin / (3.0 * (double)N * (double)P * (double)P * sys->kB);
+    /* P_CV = (sum_i m v~0_i^2 - sum_k sum_i (r_i^k - r_i^c) . F_i^k + sum_k Tr Xi^k) / (3 P V)
+     * (App. A); the first term with mvv2e, as every kinetic term here */
+    out->pcv = 0.0;
+    if (sys->pot == ORC_POT_PAIR && sys->box[0] > 0.0) {
+        double k0 = 0.0, w = 0.0;
+        for (int32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double v = vt[(size_t)i * 3 + d];   /* mode 0 */
+                k0 += sys->mass[i] * sys->mvv2e * v * v;
+            }
+        for (int32_t k = 0; k < P; ++k) w += orc_virial_bead(sys, x + (size_t)k * N * 3);
+        const double V = sys->box[0] * sys->box[1] * sys->box[2];
+        out->pcv = (k0 - vir + w) / (3.0 * (double)P * V);
+    }
 }
 
 double orc_spring_energy_nm(const orc_system *sys, const double *x)

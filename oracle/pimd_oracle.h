@@ -72,6 +72,7 @@ typedef struct orc_est {
     double kprim;   /* K_PR, Eq. A5 (read with 1/n and omega_n^2) */
     double kcv;     /* K_CV, Eq. A7 */
     double temp;    /* ring-polymer temperature divided by P (Sec. III.A) */
+    double pcv;     /* P_CV, App. A (centroid-virial pressure); 0 without a periodic box */
 } orc_est;
 
 /* --- normal modes (App. B) --------------------------------------------- */
@@ -101,6 +102,11 @@ void orc_pile_coeffs(const orc_system *sys, int32_t k, double *c1, double *c2);
 /* --- forces, per bead independently ----------------------------------- */
 /* x, f: [N][3] of one bead; returns U^(k) */
 double orc_forces_bead(const orc_system *sys, const double *xk, double *fk);
+/* The cell virial Tr Xi of one bead (App. A, under the primitive pressure
+ * estimator): minus the derivative of U under a uniform scaling of the
+ * positions and the box, i.e. the sum of r_ij . F_ij over interacting pairs
+ * (every image) and bonds.  0 without a periodic box. */
+double orc_virial_bead(const orc_system *sys, const double *xk);
 /* x, f: [P][N][3]; U: [P] */
 void orc_forces(const orc_system *sys, const double *x, double *f, double *U);
 

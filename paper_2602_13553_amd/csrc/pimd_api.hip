@@ -314,7 +314,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.mfma_tiles = fused_mfma_supported(p->n_beads) ? mfma_block_tiles(p->n_atoms, p->n_beads) : 0;
     const int nparts = std::max(std::max(L.fused_grid, L.mfma_grid), std::max(L.valu_tiles, L.mfma_tiles));
     L.partials = take((size_t)nparts * PF_COUNT * sizeof(double));
-    L.fpartials = take((size_t)std::max(L.pair_grid, 1) * sizeof(double));
+    L.fpartials = take((size_t)2 * std::max(L.pair_grid, 1) * sizeof(double));
     L.ctl = take(sizeof(Ctl));
     L.cell_ent = take((size_t)L.ncell * L.cell_cap * sizeof(CellEntry));
     L.cell_scnt = take((size_t)L.ncell * sizeof(int));
@@ -611,6 +611,10 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.kT15N = 1.5 * (double)N * kT;
     a.kT15PN = 1.5 * (double)P * (double)N * kT;
     a.temp_norm = 2.0 / (3.0 * (double)N * (double)P * (double)P * p->kB);
+    {
+        const double V = p->box[0] * p->box[1] * p->box[2];
+        a.inv_3pv = (pair && V > 0.0) ? 1.0 / (3.0 * (double)P * V) : 0.0;
+    }
     a.seed = p->seed;
     a.x = c->d_x; a.yt = (double *)(w + L.yt); a.v = c->d_v; a.f = c->d_f; a.vin = c->d_f;
     a.cent = c->d_cent; a.cref = c->d_cref;
@@ -867,7 +871,7 @@ int pimd_set_forces(pimd_ctx *c, const double *f, double epot)
     if (!std::isfinite(epot)) return fail(c, PIMD_ERR_ARG, "epot is not finite");
     if (!c->d_f || !c->d_fpartials) return fail(c, PIMD_ERR_STATE, "internal: no force array");
     launch_import(f, c->d_f, c->d_orig, c->p.n_atoms, c->p.n_beads, c->stream);
-    launch_store_scalar(c->d_fpartials, epot, c->stream);
+    launch_store_energy(c->d_fpartials, epot, c->stream);
     // a pending closing kick and the estimators of this state (or, right after
     // set_state, the estimators alone)
     enqueue_fused(c, c->synced ? FUSED_EST : FUSED_CLOSE, PIMD_KERNEL_CLOSE);

@@ -139,6 +139,7 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
     double acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
     double acc_p[3] = {0.0, 0.0, 0.0};   // fixcom: sum of hm v~0 after a step's end
+    double acc_k0 = 0.0;                 // sum of hm |v~0|^2 at the estimator point
 
     const int nbt = (N + 16 * T - 1) / (16 * T);
     for (int bt = first; bt < nbt; bt += stride) {
@@ -290,7 +291,9 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
                 }
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    acc_ekin += hm * vt[d] * vt[d];
+                    const double kd = hm * vt[d] * vt[d];
+                    acc_ekin += kd;
+                    if (m == 0) acc_k0 += kd;
                     acc_esp += hm * mk[MD_SPRING * P] * xt[d] * xt[d];
                     acc_vir += mk[MD_NONCENTROID * P] * xt[d] * ft[d];
                 }
@@ -403,11 +406,11 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
     if (spent) return;
     __syncthreads();
     double *red = smem;
-    constexpr int NS = FC ? 7 : 4;   // the fixcom momentum only where it is used
+    constexpr int NS = FC ? 8 : 5;   // the fixcom momentum only where it is used
     double s4[NS];
-    s4[0] = acc_ekin; s4[1] = acc_esp; s4[2] = acc_vir; s4[3] = acc_uext;
+    s4[0] = acc_ekin; s4[1] = acc_esp; s4[2] = acc_vir; s4[3] = acc_uext; s4[4] = acc_k0;
     if constexpr (FC) {
-        s4[4] = acc_p[0]; s4[5] = acc_p[1]; s4[6] = acc_p[2];
+        s4[5] = acc_p[0]; s4[6] = acc_p[1]; s4[7] = acc_p[2];
     }
     double m3[3] = {acc_emax, acc_dmax, acc_bad};
     block_sum_max<NS, 3>(s4, m3, red);
@@ -421,9 +424,10 @@ __device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *sm
         pp[PF_EMAX] = emax;
         pp[PF_DMAX] = dmax;
         pp[PF_NONFINITE] = bad;
-        pp[PF_PX] = FC ? s4[NS > 4 ? 4 : 0] : 0.0;
-        pp[PF_PY] = FC ? s4[NS > 5 ? 5 : 0] : 0.0;
-        pp[PF_PZ] = FC ? s4[NS > 6 ? 6 : 0] : 0.0;
+        pp[PF_K0] = s4[4];
+        pp[PF_PX] = FC ? s4[NS > 5 ? 5 : 0] : 0.0;
+        pp[PF_PY] = FC ? s4[NS > 6 ? 6 : 0] : 0.0;
+        pp[PF_PZ] = FC ? s4[NS > 7 ? 7 : 0] : 0.0;
     }
 }
 

@@ -18,7 +18,7 @@ namespace pimd {
 constexpr int kBlock = 256;      // threads per block for the step kernels
 constexpr int kMaxBeads = 128;   // P limit of the library (LDS-resident M)
 constexpr int kMaxBonds = 4;     // bonds per atom
-constexpr int kNumEst = 7;       // ekin, espring, epot, etot, kprim, kcv, temp
+constexpr int kNumEst = 8;       // ekin, espring, epot, etot, kprim, kcv, temp, pcv
 constexpr int kCellCapMax = 4096;  // atoms per centroid cell, at most
 constexpr int kMaxCells = 3072;    // centroid cells per system, at most (LDS counts, 4 per cell)
 constexpr int kPairStage = 2048;        // neighbor-list entries staged in LDS per force-pass block
@@ -28,8 +28,9 @@ constexpr int kClusterSmem = 8 * 2 * kClusterRows + 16 * kClusterMax;   // dynam
 
 // Per-block partial slots written by the fused kernel.
 // PF_PX..PF_PZ: sum of hm * v~0 over the block's atoms (fixcom momentum)
-enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_PX, PF_PY, PF_PZ,
-       PF_PAD, PF_COUNT };
+// PF_K0: sum of hm |v~0|^2 over the block's atoms (centroid-virial pressure)
+enum { PF_EKIN = 0, PF_ESPRING, PF_VIR, PF_UEXT, PF_EMAX, PF_DMAX, PF_NONFINITE, PF_K0, PF_PX, PF_PY,
+       PF_PZ, PF_COUNT };
 
 // Fused-kernel modes.
 enum FusedMode : int {
@@ -83,6 +84,7 @@ struct FusedArgs {
     int obabo;                // 1: OBABO splitting (O half steps around B A A B), 0: BAOAB
     int fixcom;               // 1: centroid COM velocity removed at the end of every step
     double inv_hsum;          // 1 / sum_i hm_i (fixcom)
+    double inv_3pv;           // 1 / (3 P V) for periodic pair systems, else 0 (P_CV)
     double hdt;               // dt / 2
     double omega2;            // external trap omega^2 (0 for none / pair)
     double skin;
@@ -104,7 +106,7 @@ struct FusedArgs {
     const double *atoms;      // [N][4] per-atom constants
     const int *orig;          // [N] caller's atom index (noise counter)
     double *partials;         // [gridDim][PF_COUNT]
-    const double *fpartials;  // [n_fpartials] force-kernel energy partials
+    const double *fpartials;  // [n_fpartials][2] force-pass (energy, cell virial) per block
     int n_fpartials;
     Ctl *ctl;
     // centroid cells (ncell = 0: no cell list, lists come from the all-pairs scan)
@@ -137,7 +139,7 @@ struct PairArgs {
     int *nbr_count;           // [N]
     int2 *nbr;                // [N][cap] (j, packed image shift)
     const int *bond_j;        // [N][kMaxBonds] partner or -1
-    double *fpartials;        // [gridDim]
+    double *fpartials;        // [gridDim][2]: (energy, cell virial) per block
     Ctl *ctl;
     int nc[3], cell_cap;      // centroid cells (see FusedArgs)
     const CellEntry *cell_ent;
@@ -182,7 +184,7 @@ void launch_import(const double *src, double *dst, const int *orig, int N, int P
 void launch_export(const double *x, const double *v, const double *atoms_mass, const double *M,
                    const int *orig, double *xdst, double *pdst, int N, int P, hipStream_t s);
 void launch_ctl_reset_sums(Ctl *ctl, hipStream_t s);
-void launch_store_scalar(double *dst, double v, hipStream_t s);
+void launch_store_energy(double *dst, double v, hipStream_t s);
 void launch_apply_ucom(const FusedArgs &a, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, unsigned long long step, hipStream_t s);
 void launch_ctl_set_budget(Ctl *ctl, long long budget, hipStream_t s);

@@ -88,6 +88,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     double acc_ekin = 0.0, acc_esp = 0.0, acc_vir = 0.0, acc_uext = 0.0;
     double acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
     double acc_p[3] = {0.0, 0.0, 0.0};   // fixcom: sum of hm v~0 after a step's end
+    double acc_k0 = 0.0;                 // sum of hm |v~0|^2 at the estimator point
 
     double mk[8];
 #pragma unroll
@@ -263,7 +264,9 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             if (est_now) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    acc_ekin += hm * vt[d] * vt[d];
+                    const double kd = hm * vt[d] * vt[d];
+                    acc_ekin += kd;
+                    if (k == 0) acc_k0 += kd;
                     acc_esp += hm * mk[MD_SPRING] * xt[d] * xt[d];
                     acc_vir += mk[MD_NONCENTROID] * xt[d] * ft[d];
                     const double xa = xt[d] + off * ref[d];
@@ -399,11 +402,11 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
     // ---- per-block partials (plain stores; k_finalize runs after this
     // kernel, so the kernel boundary makes them visible)
     {
-        constexpr int NS = FC ? 7 : 4;   // the fixcom momentum only where it is used
+        constexpr int NS = FC ? 8 : 5;   // the fixcom momentum only where it is used
         double s4[NS];
-        s4[0] = acc_ekin; s4[1] = acc_esp; s4[2] = acc_vir; s4[3] = acc_uext;
+        s4[0] = acc_ekin; s4[1] = acc_esp; s4[2] = acc_vir; s4[3] = acc_uext; s4[4] = acc_k0;
         if constexpr (FC) {
-            s4[4] = acc_p[0]; s4[5] = acc_p[1]; s4[6] = acc_p[2];
+            s4[5] = acc_p[0]; s4[6] = acc_p[1]; s4[7] = acc_p[2];
         }
         double m3[3] = {acc_emax, acc_dmax, acc_bad};
         block_sum_max<NS, 3>(s4, m3, red);
@@ -417,9 +420,10 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             pp[PF_EMAX] = emax;
             pp[PF_DMAX] = dmax;
             pp[PF_NONFINITE] = bad;
-            pp[PF_PX] = FC ? s4[NS > 4 ? 4 : 0] : 0.0;
-            pp[PF_PY] = FC ? s4[NS > 5 ? 5 : 0] : 0.0;
-            pp[PF_PZ] = FC ? s4[NS > 6 ? 6 : 0] : 0.0;
+            pp[PF_K0] = s4[4];
+            pp[PF_PX] = FC ? s4[NS > 5 ? 5 : 0] : 0.0;
+            pp[PF_PY] = FC ? s4[NS > 6 ? 6 : 0] : 0.0;
+            pp[PF_PZ] = FC ? s4[NS > 7 ? 7 : 0] : 0.0;
         }
     }
 }
@@ -624,22 +628,23 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         n_rebuilds = c->n_rebuilds;
     }
 
-    // ekin, espring, vir, uext, pair energy, fixcom momentum (3)
-    double tot[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // ekin, espring, vir, uext, pair energy, fixcom momentum (3), centroid
+    // kinetic sum, cell virial
+    double tot[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double mx[3] = {0.0, 0.0, 0.0};   // emax^2, dmax^2, non-finite flag
     // Loads in fixed batches held in registers, so that a batch's reads are in
     // flight together; out-of-range slots add +0, and each thread's sums run
     // in loop order, so the result is that of the plain loop.
     constexpr int NB = 4, NF = 16;
     for (int b0 = t; b0 < nblocks; b0 += NB * kBlock) {
-        constexpr int NQ = FC ? PF_PAD : PF_NONFINITE + 1;
-        double pv[NB][PF_PAD];
+        constexpr int NQ = FC ? PF_COUNT : PF_K0 + 1;
+        double pv[NB][PF_COUNT];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int b = b0 + u * kBlock;
             const double *pp = a.partials + (size_t)(b < nblocks ? b : 0) * PF_COUNT;
 #pragma unroll
-            for (int q = 0; q < PF_PAD; ++q) pv[u][q] = (q < NQ && b < nblocks) ? pp[q] : 0.0;
+            for (int q = 0; q < PF_COUNT; ++q) pv[u][q] = (q < NQ && b < nblocks) ? pp[q] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -653,23 +658,30 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             tot[5] += pv[u][PF_PX];
             tot[6] += pv[u][PF_PY];
             tot[7] += pv[u][PF_PZ];
+            tot[8] += pv[u][PF_K0];
         }
     }
     // (summed whether or not this pass needs them, so the loads do not wait
     // for the control block)
     if (a.pair) {
+        const double2 *fp = reinterpret_cast<const double2 *>(a.fpartials);
         for (int b0 = t; b0 < a.n_fpartials; b0 += NF * kBlock) {
-            double fv[NF];
+            double2 fv[NF];
 #pragma unroll
             for (int u = 0; u < NF; ++u) {
                 const int b = b0 + u * kBlock;
-                fv[u] = b < a.n_fpartials ? a.fpartials[b] : 0.0;
+                fv[u] = b < a.n_fpartials ? fp[b] : make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int u = 0; u < NF; ++u) tot[4] += fv[u];
+            for (int u = 0; u < NF; ++u) {
+                tot[4] += fv[u].x;
+                tot[9] += fv[u].y;
+            }
         }
     }
-    block_sum_max<8, 3>(tot, mx, red);
+    block_sum_max<10, 3>(tot, mx, red);
+    constexpr int kRedFlag = (10 + 3) * (kBlock / 64);   // first slot past the reduction's
+    static_assert(kRedFlag + 2 <= 64, "reduction scratch");
     if (mode == FUSED_STEP && budget == 0) {
         // no step was taken: nothing to combine, and no force pass follows
         if (t == 0) c->ran = 0;
@@ -705,6 +717,9 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             v[4] = a.kT15PN - esp / (double)P;
             v[5] = a.kT15N - vir / (2.0 * (double)P);
             v[6] = ekin * a.temp_norm;
+            // P_CV: the centroids' kinetic term (2 sum hm |v~0|^2, after the
+            // fixcom removal), minus the centroid virial, plus the cell virial
+            v[7] = a.lists ? (2.0 * (tot[8] - dekin) - vir + tot[9]) * a.inv_3pv : 0.0;
             for (int q = 0; q < kNumEst; ++q) c->value[q] = v[q];
             c->est_step = est_after ? step + 1 : step;
             if (mode != FUSED_EST) {
@@ -737,14 +752,14 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
         if (bad != 0.0) c->nonfinite = 1;
         // this pass's decision, for the cell build below (slots past the
         // reduction's, which other threads may still be reading)
-        red[32] = rebuild ? 1.0 : 0.0;
-        red[33] = rlist;
+        red[kRedFlag] = rebuild ? 1.0 : 0.0;
+        red[kRedFlag + 1] = rlist;
     }
     // the centroid cell lists of a rebuild (cells recorded by this pass)
     if (a.lists && a.ncell > 0 && (mode == FUSED_STEP || mode == FUSED_PREP)) {
         __syncthreads();
-        const bool rb = red[32] != 0.0;
-        const double rl = red[33];
+        const bool rb = red[kRedFlag] != 0.0;
+        const double rl = red[kRedFlag + 1];
         __syncthreads();
         if (rb) cells_finalize(a, rl, sbuf, sflag);
     }
@@ -843,10 +858,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Half of each ordered pair's energy 4 eps (sr12 - sr6) - ushift and of its
+// cell virial r . F = 24 eps (2 sr12 - sr6), from the thread's sums.
+__device__ __forceinline__ void lj_energy_virial(double s12, double s6, int np, double eps4,
+                                                 double eps24, double ushift, double &e, double &w)
+{
+    e += 0.5 * (eps4 * (s12 - s6) - ushift * (double)np);
+    w += 0.5 * eps24 * (2.0 * s12 - s6);
+}
+
 __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, double rc2,
-                                              double sig2, double eps4, double eps24,
-                                              double ushift, double &fx, double &fy,
-                                              double &fz, double &e)
+                                              double sig2, double eps24,
+                                              double &fx, double &fy, double &fz,
+                                              double &s12, double &s6, int &np)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
@@ -857,9 +881,11 @@ __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, d
         ir2 = fma(fma(-r2, ir2, 1.0), ir2, ir2);
         ir2 = fma(fma(-r2, ir2, 1.0), ir2, ir2);
         const double sr2 = sig2 * ir2;
-        const double sr6 = sr2 * sr2 * sr2;
-        const double fr = eps24 * (2.0 * sr6 * sr6 - sr6) * ir2;
-        e += 0.5 * (eps4 * (sr6 * sr6 - sr6) - ushift);
+        const double sr6 = sr2 * sr2 * sr2, sr12 = sr6 * sr6;
+        const double fr = eps24 * (2.0 * sr12 - sr6) * ir2;
+        // the pair energy and virial are linear in (sr12, sr6, 1): their sums
+        // are formed once per thread (lj_energy_virial)
+        s12 += sr12; s6 += sr6; ++np;
         fx += fr * dx; fy += fr * dy; fz += fr * dz;
     }
 }
@@ -1062,7 +1088,8 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         __syncthreads();
     }
 
-    double e = 0.0;
+    double e = 0.0, wv = 0.0, s12 = 0.0, s6 = 0.0;
+    int np = 0;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int P3 = 3 * P;
     const size_t ib = (size_t)i * P3 + k;
@@ -1109,7 +1136,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                 double sx, sy, sz;
                 unpack_shift(en[u].y, sx, sy, sz);
                 lj_accumulate(xi - xj[u] + sx * L0, yi - yj[u] + sy * L1, zi - zj[u] + sz * L2,
-                              rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
+                              rc2, sig2, eps24, fx, fy, fz, s12, s6, np);
             }
         }
         for (; q < qend; q += S) {
@@ -1118,10 +1145,11 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
             unpack_shift(en.y, sx, sy, sz);
             const int jb = en.x + k;
             lj_accumulate(xi - X[jb] + sx * L0, yi - X[jb + P] + sy * L1, zi - X[jb + 2 * P] + sz * L2,
-                          rc2, sig2, eps4, eps24, ush, fx, fy, fz, e);
+                          rc2, sig2, eps24, fx, fy, fz, s12, s6, np);
         }
         __syncthreads();
     }
+    lj_energy_virial(s12, s6, np, eps4, eps24, ush, e, wv);
     if (act) {
         if (sg == 0) {
             for (int bb = 0; bb < kMaxBonds; ++bb) {
@@ -1136,6 +1164,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                 const double dr = r - a.bond_r0;
                 const double fr = -2.0 * a.bond_k * dr / r;
                 e += 0.5 * a.bond_k * dr * dr;
+                wv += 0.5 * fr * r * r;  // each bond is seen from both atoms
                 fx += fr * dx; fy += fr * dy; fz += fr * dz;
             }
         }
@@ -1153,10 +1182,10 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     if (act && sg == 0) {
         a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
     }
-    // block sum (fixed order)
-    double e1[1] = {e};
-    block_sum<1>(e1, red);
-    if (t == 0) a.fpartials[tile] = e1[0];
+    // block sums (fixed order): energy, then the cell virial after all partials
+    double e1[2] = {e, wv};
+    block_sum<2>(e1, red);
+    if (t == 0) reinterpret_cast<double2 *>(a.fpartials)[tile] = make_double2(e1[0], e1[1]);
 }
 
 // --------------------------------------------------------------------------
@@ -1304,7 +1333,8 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
     }
     const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
     const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
-    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    double e = 0.0, wv = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, s12 = 0.0, s6 = 0.0;
+    int np = 0;
     const int CH = kClusterRows / P3;                    // rows per chunk
     const int nch = (n + CH - 1) / CH;
     constexpr int NR = kClusterRows / kBlock;             // staged doubles per thread
@@ -1341,14 +1371,15 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
                     double sx, sy, sz;
                     unpack_shift(en.y, sx, sy, sz);
                     lj_accumulate(xf - row[k] + sx * L0, yf - row[P + k] + sy * L1,
-                                  zf - row[2 * P + k] + sz * L2, rc2, sig2, eps4, eps24, ush,
-                                  fx, fy, fz, e);
+                                  zf - row[2 * P + k] + sz * L2, rc2, sig2, eps24,
+                                  fx, fy, fz, s12, s6, np);
                 }
             }
         }
         if (c + 1 < nch) stage(c + 1);
         __syncthreads();
     }
+    lj_energy_virial(s12, s6, np, eps4, eps24, ush, e, wv);
     if (act) {
         for (int bb = 0; bb < kMaxBonds; ++bb) {
             const int j = a.bond_j[i * kMaxBonds + bb];
@@ -1362,13 +1393,14 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
             const double dr = r - a.bond_r0;
             const double fr = -2.0 * a.bond_k * dr / r;
             e += 0.5 * a.bond_k * dr * dr;
+            wv += 0.5 * fr * r * r;  // each bond is seen from both atoms
             fx += fr * dx; fy += fr * dy; fz += fr * dz;
         }
         a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
     }
-    double e1[1] = {e};
-    block_sum<1>(e1, red);
-    if (t == 0) a.fpartials[b] = e1[0];
+    double e1[2] = {e, wv};
+    block_sum<2>(e1, red);
+    if (t == 0) reinterpret_cast<double2 *>(a.fpartials)[b] = make_double2(e1[0], e1[1]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
@@ -1598,14 +1630,17 @@ void launch_apply_ucom(const FusedArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_clear_ucom, dim3(1), dim3(64), 0, s, a.ctl);
 }
 
-__global__ void k_store_scalar(double *dst, double v)
+__global__ void k_store_energy(double *dst, double v)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        dst[0] = v;     // the caller's potential energy
+        dst[1] = 0.0;   // no cell virial for forces from outside
+    }
 }
 
-void launch_store_scalar(double *dst, double v, hipStream_t s)
+void launch_store_energy(double *dst, double v, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_store_scalar, dim3(1), dim3(64), 0, s, dst, v);
+    hipLaunchKernelGGL(k_store_energy, dim3(1), dim3(64), 0, s, dst, v);
 }
 
 __global__ void k_ctl_init(Ctl *c, unsigned long long step)

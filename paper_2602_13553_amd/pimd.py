@@ -32,7 +32,8 @@ def PIMD_PAIR_SUBGROUPS(S: int) -> int:
     """Flag bits that fix the force pass's lane sub-groups per atom (S in 1..16)."""
     code = {1: 1, 2: 2, 4: 3, 8: 4, 16: 5}[S]
     return code << PIMD_PAIR_SUBGROUPS_SHIFT
-ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
+ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv")
+NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
@@ -68,8 +69,8 @@ class pimd_topology(C.Structure):
 
 
 class pimd_estimators(C.Structure):
-    _fields_ = [("step", C.c_uint64), ("value", C.c_double * 7), ("count", C.c_uint64),
-                ("sum", C.c_double * 7), ("sumsq", C.c_double * 7), ("nonfinite", C.c_int32),
+    _fields_ = [("step", C.c_uint64), ("value", C.c_double * NEST), ("count", C.c_uint64),
+                ("sum", C.c_double * NEST), ("sumsq", C.c_double * NEST), ("nonfinite", C.c_int32),
                 ("overflow", C.c_int32), ("n_rebuilds", C.c_uint64), ("rlist", C.c_double)]
 
 

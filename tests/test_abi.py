@@ -48,6 +48,8 @@ def test_binding_structs_follow_header():
     assert fields("pimd_topology") == [f[0] for f in pimd.pimd_topology._fields_]
     assert fields("pimd_estimators") == [f[0] for f in pimd.pimd_estimators._fields_]
     assert fields("pimd_profile") == [f[0] for f in pimd.pimd_profile._fields_]
+    nest = int(re.search(r"#define PIMD_NEST (\d+)", src).group(1))
+    assert pimd.NEST == nest == len(pimd.ESTIMATOR_NAMES)
     assert fields("pimd_launch_info") == [f[0] for f in pimd.pimd_launch_info._fields_]
 
 

@@ -47,12 +47,24 @@ def run_pair(spec, nsteps, chunks=None, flags=0):
     ctx.close()
     st = oracle.State.from_spec(spec)
     st.step(nsteps)
-    return (gx, gp, gs, est), (st.x, st.p, int(st.step_count[0]), st.estimators())
+    return (gx, gp, gs, est), (st.x, st.p, int(st.step_count[0]), st.estimators(), st.sys)
+
+
+def pcv_scale(s, x, ekin):
+    """Size of P_CV's three terms for system s at positions x [P][N][3]: the
+    bar for P_CV is relative to it, since the terms largely cancel."""
+    if s.pot != oracle.POT_PAIR or not s.box[0] > 0:
+        return 0.0
+    P = x.shape[0]
+    f, _ = s.forces(x)
+    vir = np.abs((x - x.mean(axis=0)) * f).sum()
+    w = sum(abs(s.virial(x[k])) for k in range(P))
+    return (2 * abs(ekin) + vir + w) / (3 * P * float(np.prod(s.box)))
 
 
 def check_states(g, o, tol=TOL, est_tol=1e-10):
     gx, gp, gs, gest = g
-    ox, op, os_, oest = o
+    ox, op, os_, oest, osys = o
     assert gs == os_
     ex, ep = rel_err(gx, ox), rel_err(gp, op)
     _say("  x rel %.3e  p rel %.3e" % (ex, ep))
@@ -62,6 +74,9 @@ def check_states(g, o, tol=TOL, est_tol=1e-10):
     for name in ("ekin", "espring", "epot", "etot", "kprim", "kcv"):
         assert abs(gest[name] - oest[name]) <= est_tol * scale, (name, gest[name], oest[name])
     assert abs(gest["temp"] - oest["temp"]) <= est_tol * abs(oest["temp"])
+    psc = pcv_scale(osys, ox, oest["ekin"])
+    _say("  pcv %.10e (oracle %.10e, scale %.3e)" % (gest["pcv"], oest["pcv"], psc))
+    assert abs(gest["pcv"] - oest["pcv"]) <= est_tol * psc, (gest["pcv"], oest["pcv"])
 
 
 # ------------------------------------------------------------ harmonic trap
@@ -304,9 +319,10 @@ def test_running_sums_match_oracle_per_step():
         for n, v in st.estimators().items():
             acc[n].append(v)
     assert e["count"] == 6
+    psc = pcv_scale(st.sys, st.x, acc["ekin"][-1])
     for n in oracle.ESTIMATOR_NAMES:
         s = sum(acc[n])
-        sc = max(abs(x) for x in acc[n]) * 6
+        sc = max(abs(x) for x in acc[n] + ([psc] if n == "pcv" else [])) * 6
         assert abs(e["sum"][n] - s) <= 1e-10 * sc, n
         assert abs(e["sumsq"][n] - sum(x * x for x in acc[n])) <= 1e-10 * sc * sc / 6, n
 

@@ -538,3 +538,72 @@ def test_fixcom_keeps_zero_com_with_thermostat_and_pair_forces():
         st.step(1)
         com = (s.mass[:, None] * st.v.mean(axis=0)).sum(axis=0)
         assert np.abs(com).max() < 1e-12, com
+
+
+# ---------------------------------------------------------------- pressure
+def _scaled_energy(s, xk, lam):
+    box = tuple(lam * b for b in s.box)
+    s2 = oracle.System(**{f: getattr(s, f) for f in ("n_atoms", "n_beads", "mass", "temp", "kB",
+                                                      "hbar", "mvv2e", "dt", "tau", "tau_scale",
+                                                      "nve", "pot", "seed", "lj_eps", "lj_sigma",
+                                                      "lj_rc", "bond_k", "bond_r0", "lj_active",
+                                                      "bonds")}, box=box)
+    f, U = s2.forces((lam * xk)[None])
+    return U[0]
+
+
+@pytest.mark.parametrize("case", ["lj_images", "water", "water_wrapped"])
+def test_virial_is_minus_the_scaling_derivative_of_u(case):
+    """Tr Xi = -dU/d(lambda) at lambda = 1 when positions and box scale by
+    lambda (App. A's cell virial), by central differences.  The wrapped case
+    folds every atom into the box, so that bonds cross its faces."""
+    if case == "lj_images":
+        s, xk = _lj_box(N=12, L=4.2, seed=7)          # L < 2 rc: image sums
+    else:
+        spec = inputs.water(n_atoms=96, n_beads=1, seed=4)
+        s = oracle.System.from_spec(spec)
+        xk = spec.x0[0]
+        if case == "water_wrapped":
+            xk = np.mod(xk + 0.45 * np.asarray(s.box), np.asarray(s.box))
+    w = s.virial(xk)
+    h = 1e-6
+    dudl = (_scaled_energy(s, xk, 1 + h) - _scaled_energy(s, xk, 1 - h)) / (2 * h)
+    assert abs(w + dudl) <= 1e-6 * max(1.0, abs(w)), (w, -dudl)
+
+
+def test_pcv_kinetic_term_is_the_centroid_pressure():
+    """With no interactions P_CV is the ideal-gas pressure of the centroids,
+    sum_i m_i |v_c,i|^2 / (3V), v_c the bead average of the Cartesian
+    velocities (this fixes the normal-mode factor of the printed formula)."""
+    s, x = _lj_box(N=10, L=5.0, seed=2, P=4)
+    s.lj_eps = 0.0
+    s.mass = np.linspace(1.0, 2.0, 10)
+    rng = np.random.default_rng(8)
+    st = oracle.State(s, x[None] + 0.01 * rng.standard_normal((4, 10, 3)),
+                      rng.standard_normal((4, 10, 3)))
+    e = st.estimators()
+    vc = st.v.mean(axis=0)
+    want = (s.mass[:, None] * vc * vc).sum() / (3 * 5.0 ** 3)
+    assert abs(e["pcv"] - want) <= 1e-13 * abs(want)
+
+
+def test_pcv_is_the_centroid_virial_of_an_isolated_cluster():
+    """For a cluster far from the box faces (no pair reaches across a face),
+    each bead's cell virial is sum_i r_i . F_i, and P_CV reduces to the
+    textbook centroid-virial form
+    [sum_i m_i |v_c,i|^2 + (1/P) sum_k sum_i r_c,i . F_i^k] / (3V),
+    which has no (r - r_c) term: this fixes the signs of the three terms."""
+    N, P, L = 12, 3, 40.0
+    s, xc = _lj_box(N=N, L=3.6, seed=11, P=P)
+    s.box = (L, L, L)
+    s.mass = np.linspace(1.0, 3.0, N)
+    rng = np.random.default_rng(12)
+    x = (xc + 17.0)[None] + 0.05 * rng.standard_normal((P, N, 3))
+    st = oracle.State(s, x, rng.standard_normal((P, N, 3)))
+    e = st.estimators()
+    f, _ = s.forces(x)
+    rc = x.mean(axis=0)
+    vc = st.v.mean(axis=0)
+    want = ((s.mass[:, None] * vc * vc).sum() + (rc[None] * f).sum() / P) / (3 * L ** 3)
+    assert np.abs(x).max() < L and np.abs(f).max() > 1.0
+    assert abs(e["pcv"] - want) <= 1e-12 * max(abs(want), np.abs(rc[None] * f).sum() / (3 * P * L ** 3))
