@@ -345,7 +345,7 @@ def main():
         "fused_in_cache_gbs": fused_gbs,
         "estimators": {"kcv_per_atom": est["kcv"] / spec.n_atoms,
                        "kprim_per_atom": est["kprim"] / spec.n_atoms, "temp": est["temp"],
-                       "pcv": est["pcv"]},
+                       "pcv": est["pcv"], "ppr": est["ppr"], "pmd": est["pmd"]},
         "neighbor_lists": {"rlist": est["rlist"], "builds": est["n_rebuilds"],
                            "steps": args.warmup + args.steps},
     }

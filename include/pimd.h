@@ -150,10 +150,10 @@ typedef struct pimd_topology {
 
 /* Instantaneous estimators at the state's step, and running sums over every
  * step completed by pimd_step since the last pimd_reset_averages. */
-#define PIMD_NEST 8
+#define PIMD_NEST 10
 typedef struct pimd_estimators {
     uint64_t step;     /* thermostat step counter of the state */
-    /* order of the arrays below: ekin, espring, epot, etot, kprim, kcv, temp, pcv */
+    /* order of the arrays below: ekin, espring, epot, etot, kprim, kcv, temp, pcv, ppr, pmd */
     double value[PIMD_NEST];
     uint64_t count;    /* number of steps in the running sums */
     double sum[PIMD_NEST];
@@ -179,7 +179,13 @@ typedef struct pimd_estimators {
  *           U^(k) under a uniform scaling of positions and box).  Computed for
  *           PIMD_POT_LJ and PIMD_POT_WATER; 0 for every other potential, whose
  *           forces carry no cell virial here.  With fixcom the centroid term is
- *           taken after the center-of-mass velocity is removed. */
+ *           taken after the center-of-mass velocity is removed.
+ * ppr     = P_PR, the primitive pressure (App. A), read with the virial and the
+ *           1/P that the printed formula lacks (kB T times the volume derivative
+ *           of the log of the ring polymer's Boltzmann weight):
+ *           [3 P N kB T - (2 espring - sum_k Tr Xi^k) / P] / (3V); 0 likewise
+ * pmd     = P_MD, the pressure of the extended classical system (App. A):
+ *           [2 ekin + sum_k Tr Xi^k] / (3V); 0 likewise */
 
 typedef struct pimd_ctx pimd_ctx;
 

@@ -54,7 +54,7 @@ class _System(C.Structure):
 
 class _Est(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp",
-                                          "pcv")]
+                                          "pcv", "ppr", "pmd")]
 
 
 _lib = None
@@ -227,6 +227,8 @@ class System:
 
     def forces(self, x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
         x = np.ascontiguousarray(x, dtype=np.float64)
+        if x.shape != (self.n_beads, self.n_atoms, 3):
+            raise ValueError("x must be [n_beads][n_atoms][3], got %s" % (x.shape,))
         f = np.zeros_like(x)
         U = np.zeros(self.n_beads)
         lib().orc_forces(C.byref(self.cstruct()), _dp(x), _dp(f), _dp(U))
@@ -235,6 +237,8 @@ class System:
     def virial(self, xk: np.ndarray) -> float:
         """Cell virial Tr Xi of one bead configuration xk [N][3]."""
         xk = np.ascontiguousarray(xk, dtype=np.float64)
+        if xk.shape != (self.n_atoms, 3):
+            raise ValueError("xk must be [n_atoms][3], got %s" % (xk.shape,))
         return lib().orc_virial_bead(C.byref(self.cstruct()), _dp(xk))
 
     def spring_energy_nm(self, x: np.ndarray) -> float:
@@ -247,7 +251,7 @@ class System:
         return lib().orc_kcv_nm(C.byref(self.cstruct()), _dp(x), _dp(f))
 
 
-ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv")
+ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv", "ppr", "pmd")
 
 
 class State:

@@ -606,6 +606,14 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
  *   K_PR = 3 P N kB T / 2 - S / P
  *   K_CV = 3 N kB T / 2 - (1/2P) sum_k sum_i (r_i^k - r_i^c) . F_i^k
  *   temp = 2 K / (3 N P^2 kB)
+ * and, with a periodic box of volume V and W = sum_k Tr Xi^k (orc_virial_bead),
+ *   P_CV = (sum_i m |v~_i^0|^2 - sum_k sum_i (r_i^k - r_i^c) . F_i^k + W) / (3 P V)
+ *   P_PR = (3 P N kB T - (2 S - W) / P) / (3 V)
+ *   P_MD = (2 K + W) / (3 V)
+ * P_PR as printed lacks the virial and the 1/P; it is read as kB T times the
+ * volume derivative of the log of the ring polymer's Boltzmann weight, the
+ * beads' potentials carrying 1/P (the weight of K_PR's 1/P). P_MD is the
+ * pressure of the extended classical system of P beads per atom.
  * --------------------------------------------------------------------- */
 void orc_estimators(const orc_system *sys, const double *x, const double *vt,
                     const double *f, const double *U, orc_est *out)
@@ -646,7 +654,7 @@ void orc_estimators(const orc_system *sys, const double *x, const double *vt,
     out->temp = 2.0 * ekin / (3.0 * (double)N * (double)P * (double)P * sys->kB);
     /* P_CV = (sum_i m v~0_i^2 - sum_k sum_i (r_i^k - r_i^c) . F_i^k + sum_k Tr Xi^k) / (3 P V)
      * (App. A); the first term with mvv2e, as every kinetic term here */
-    out->pcv = 0.0;
+    out->pcv = out->ppr = out->pmd = 0.0;
     if (sys->pot == ORC_POT_PAIR && sys->box[0] > 0.0) {
         double k0 = 0.0, w = 0.0;
         for (int32_t i = 0; i < N; ++i)
@@ -657,6 +665,8 @@ void orc_estimators(const orc_system *sys, const double *x, const double *vt,
         for (int32_t k = 0; k < P; ++k) w += orc_virial_bead(sys, x + (size_t)k * N * 3);
         const double V = sys->box[0] * sys->box[1] * sys->box[2];
         out->pcv = (k0 - vir + w) / (3.0 * (double)P * V);
+        out->ppr = (3.0 * (double)P * (double)N * kT - (2.0 * espring - w) / (double)P) / (3.0 * V);
+        out->pmd = (2.0 * ekin + w) / (3.0 * V);
     }
 }
 

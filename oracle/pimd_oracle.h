@@ -73,6 +73,8 @@ typedef struct orc_est {
     double kcv;     /* K_CV, Eq. A7 */
     double temp;    /* ring-polymer temperature divided by P (Sec. III.A) */
     double pcv;     /* P_CV, App. A (centroid-virial pressure); 0 without a periodic box */
+    double ppr;     /* P_PR, App. A (primitive pressure, read with the virial and 1/P); 0 likewise */
+    double pmd;     /* P_MD, App. A (pressure of the extended classical system); 0 likewise */
 } orc_est;
 
 /* --- normal modes (App. B) --------------------------------------------- */

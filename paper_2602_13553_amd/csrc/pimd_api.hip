@@ -613,7 +613,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.temp_norm = 2.0 / (3.0 * (double)N * (double)P * (double)P * p->kB);
     {
         const double V = p->box[0] * p->box[1] * p->box[2];
-        a.inv_3pv = (pair && V > 0.0) ? 1.0 / (3.0 * (double)P * V) : 0.0;
+        a.inv_3v = (pair && V > 0.0) ? 1.0 / (3.0 * V) : 0.0;
     }
     a.seed = p->seed;
     a.x = c->d_x; a.yt = (double *)(w + L.yt); a.v = c->d_v; a.f = c->d_f; a.vin = c->d_f;

@@ -18,7 +18,7 @@ namespace pimd {
 constexpr int kBlock = 256;      // threads per block for the step kernels
 constexpr int kMaxBeads = 128;   // P limit of the library (LDS-resident M)
 constexpr int kMaxBonds = 4;     // bonds per atom
-constexpr int kNumEst = 8;       // ekin, espring, epot, etot, kprim, kcv, temp, pcv
+constexpr int kNumEst = 10;      // ekin, espring, epot, etot, kprim, kcv, temp, pcv, ppr, pmd
 constexpr int kCellCapMax = 4096;  // atoms per centroid cell, at most
 constexpr int kMaxCells = 3072;    // centroid cells per system, at most (LDS counts, 4 per cell)
 constexpr int kPairStage = 2048;        // neighbor-list entries staged in LDS per force-pass block
@@ -84,7 +84,7 @@ struct FusedArgs {
     int obabo;                // 1: OBABO splitting (O half steps around B A A B), 0: BAOAB
     int fixcom;               // 1: centroid COM velocity removed at the end of every step
     double inv_hsum;          // 1 / sum_i hm_i (fixcom)
-    double inv_3pv;           // 1 / (3 P V) for periodic pair systems, else 0 (P_CV)
+    double inv_3v;            // 1 / (3 V) for periodic pair systems, else 0 (pressures)
     double hdt;               // dt / 2
     double omega2;            // external trap omega^2 (0 for none / pair)
     double skin;

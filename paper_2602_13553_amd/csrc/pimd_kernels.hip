@@ -717,9 +717,14 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             v[4] = a.kT15PN - esp / (double)P;
             v[5] = a.kT15N - vir / (2.0 * (double)P);
             v[6] = ekin * a.temp_norm;
+            // pressures, with W = sum_k Tr Xi^k, the force pass's cell virial.
             // P_CV: the centroids' kinetic term (2 sum hm |v~0|^2, after the
-            // fixcom removal), minus the centroid virial, plus the cell virial
-            v[7] = a.lists ? (2.0 * (tot[8] - dekin) - vir + tot[9]) * a.inv_3pv : 0.0;
+            // fixcom removal), minus the centroid virial, plus W, over 3PV.
+            // P_PR: 3PNkT - (2S - W)/P over 3V.  P_MD: 2K + W over 3V.
+            const double W = tot[9], iP = 1.0 / (double)P;
+            v[7] = a.lists ? (2.0 * (tot[8] - dekin) - vir + W) * iP * a.inv_3v : 0.0;
+            v[8] = a.lists ? (2.0 * a.kT15PN - (2.0 * esp - W) * iP) * a.inv_3v : 0.0;
+            v[9] = a.lists ? (2.0 * ekin + W) * a.inv_3v : 0.0;
             for (int q = 0; q < kNumEst; ++q) c->value[q] = v[q];
             c->est_step = est_after ? step + 1 : step;
             if (mode != FUSED_EST) {

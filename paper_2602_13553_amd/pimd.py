@@ -32,7 +32,7 @@ def PIMD_PAIR_SUBGROUPS(S: int) -> int:
     """Flag bits that fix the force pass's lane sub-groups per atom (S in 1..16)."""
     code = {1: 1, 2: 2, 4: 3, 8: 4, 16: 5}[S]
     return code << PIMD_PAIR_SUBGROUPS_SHIFT
-ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv")
+ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv", "ppr", "pmd")
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_get_positions",

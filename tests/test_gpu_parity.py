@@ -50,16 +50,21 @@ def run_pair(spec, nsteps, chunks=None, flags=0):
     return (gx, gp, gs, est), (st.x, st.p, int(st.step_count[0]), st.estimators(), st.sys)
 
 
-def pcv_scale(s, x, ekin):
-    """Size of P_CV's three terms for system s at positions x [P][N][3]: the
-    bar for P_CV is relative to it, since the terms largely cancel."""
+def pressure_scales(s, x, est):
+    """Sizes of the terms of P_CV, P_PR and P_MD for system s at positions x
+    [P][N][3]: the bar for each pressure is relative to it, since the terms
+    largely cancel.  Zero where the pressures are not defined (no box)."""
     if s.pot != oracle.POT_PAIR or not s.box[0] > 0:
-        return 0.0
-    P = x.shape[0]
+        return {"pcv": 0.0, "ppr": 0.0, "pmd": 0.0}
+    P, N = x.shape[0], x.shape[1]
     f, _ = s.forces(x)
     vir = np.abs((x - x.mean(axis=0)) * f).sum()
     w = sum(abs(s.virial(x[k])) for k in range(P))
-    return (2 * abs(ekin) + vir + w) / (3 * P * float(np.prod(s.box)))
+    v3 = 3 * float(np.prod(s.box))
+    ek, es = abs(est["ekin"]), abs(est["espring"])
+    return {"pcv": (2 * ek + vir + w) / (P * v3),
+            "ppr": (3 * P * N * s.kB * s.temp + (2 * es + w) / P) / v3,
+            "pmd": (2 * ek + w) / v3}
 
 
 def check_states(g, o, tol=TOL, est_tol=1e-10):
@@ -74,9 +79,9 @@ def check_states(g, o, tol=TOL, est_tol=1e-10):
     for name in ("ekin", "espring", "epot", "etot", "kprim", "kcv"):
         assert abs(gest[name] - oest[name]) <= est_tol * scale, (name, gest[name], oest[name])
     assert abs(gest["temp"] - oest["temp"]) <= est_tol * abs(oest["temp"])
-    psc = pcv_scale(osys, ox, oest["ekin"])
-    _say("  pcv %.10e (oracle %.10e, scale %.3e)" % (gest["pcv"], oest["pcv"], psc))
-    assert abs(gest["pcv"] - oest["pcv"]) <= est_tol * psc, (gest["pcv"], oest["pcv"])
+    for name, psc in pressure_scales(osys, ox, oest).items():
+        _say("  %s %.10e (oracle %.10e, scale %.3e)" % (name, gest[name], oest[name], psc))
+        assert abs(gest[name] - oest[name]) <= est_tol * psc, (name, gest[name], oest[name])
 
 
 # ------------------------------------------------------------ harmonic trap
@@ -319,10 +324,10 @@ def test_running_sums_match_oracle_per_step():
         for n, v in st.estimators().items():
             acc[n].append(v)
     assert e["count"] == 6
-    psc = pcv_scale(st.sys, st.x, acc["ekin"][-1])
+    psc = pressure_scales(st.sys, st.x, {q: acc[q][-1] for q in acc})
     for n in oracle.ESTIMATOR_NAMES:
         s = sum(acc[n])
-        sc = max(abs(x) for x in acc[n] + ([psc] if n == "pcv" else [])) * 6
+        sc = max(abs(x) for x in acc[n] + [psc.get(n, 0.0)]) * 6
         assert abs(e["sum"][n] - s) <= 1e-10 * sc, n
         assert abs(e["sumsq"][n] - sum(x * x for x in acc[n])) <= 1e-10 * sc * sc / 6, n
 

@@ -542,8 +542,9 @@ def test_fixcom_keeps_zero_com_with_thermostat_and_pair_forces():
 
 # ---------------------------------------------------------------- pressure
 def _scaled_energy(s, xk, lam):
+    """U of one bead configuration xk [N][3] with positions and box scaled by lam."""
     box = tuple(lam * b for b in s.box)
-    s2 = oracle.System(**{f: getattr(s, f) for f in ("n_atoms", "n_beads", "mass", "temp", "kB",
+    s2 = oracle.System(n_beads=1, **{f: getattr(s, f) for f in ("n_atoms", "mass", "temp", "kB",
                                                       "hbar", "mvv2e", "dt", "tau", "tau_scale",
                                                       "nve", "pot", "seed", "lj_eps", "lj_sigma",
                                                       "lj_rc", "bond_k", "bond_r0", "lj_active",
@@ -607,3 +608,44 @@ def test_pcv_is_the_centroid_virial_of_an_isolated_cluster():
     want = ((s.mass[:, None] * vc * vc).sum() + (rc[None] * f).sum() / P) / (3 * L ** 3)
     assert np.abs(x).max() < L and np.abs(f).max() > 1.0
     assert abs(e["pcv"] - want) <= 1e-12 * max(abs(want), np.abs(rc[None] * f).sum() / (3 * P * L ** 3))
+
+
+def test_ppr_is_the_volume_derivative_of_the_ring_polymer_weight():
+    """P_PR = kT d ln(weight)/dV: the measure gives 3PN kT/(3V), and the
+    exponent -beta/P sum_k [U^k + P S_k] under r -> lambda r, L -> lambda L
+    gives -(1/P)(dU/dlambda + 2S)/(3V), dU/dlambda by central differences of
+    the oracle's energies (not its virial)."""
+    N, P, L = 16, 4, 4.6
+    s, xc = _lj_box(N=N, L=L, seed=13, P=P)
+    s.hbar = 0.3
+    s.mass = np.linspace(1.0, 2.0, N)
+    rng = np.random.default_rng(14)
+    x = xc[None] + 0.05 * rng.standard_normal((P, N, 3))
+    st = oracle.State(s, x, rng.standard_normal((P, N, 3)))
+    e = st.estimators()
+    h = 1e-6
+    dudl = sum((_scaled_energy(s, x[k], 1 + h) - _scaled_energy(s, x[k], 1 - h)) / (2 * h)
+               for k in range(P))
+    kT = s.kB * s.temp
+    want = (3 * P * N * kT - (dudl + 2 * e["espring"]) / P) / (3 * L ** 3)
+    assert abs(e["ppr"] - want) <= 1e-7 * (3 * P * N * kT + abs(dudl) + 2 * e["espring"]) / (3 * L ** 3)
+    # the springs enter: a wrong sign or weight on S moves P_PR by more than the bar
+    assert 2 * e["espring"] / P / (3 * L ** 3) > 1e-3 * abs(want)
+
+
+def test_pmd_is_the_classical_pressure_of_the_beads():
+    """P_MD = (sum_k sum_i m |v~|^2 + W)/(3V); at P = 1 it equals P_CV (the
+    centroid is the particle), and with no interactions it is the ideal-gas
+    pressure of the P N beads' velocities."""
+    s, x = _lj_box(N=14, L=4.4, seed=15)
+    rng = np.random.default_rng(16)
+    st = oracle.State(s, x[None], rng.standard_normal((1, 14, 3)))
+    e = st.estimators()
+    assert abs(e["pmd"] - e["pcv"]) <= 1e-13 * max(abs(e["pmd"]), 1.0)
+    s2, x2 = _lj_box(N=10, L=5.0, seed=2, P=3)
+    s2.lj_eps = 0.0
+    v = rng.standard_normal((3, 10, 3))
+    st2 = oracle.State(s2, x2[None] + 0.01 * rng.standard_normal((3, 10, 3)), v)
+    e2 = st2.estimators()
+    want = (s2.mass[None, :, None] * v * v).sum() / (3 * 5.0 ** 3)
+    assert abs(e2["pmd"] - want) <= 1e-13 * want
