@@ -49,7 +49,12 @@ class _System(C.Structure):
         ("mass", C.POINTER(C.c_double)), ("lj_active", C.POINTER(C.c_int32)),
         ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32)),
         ("atom_id", C.POINTER(C.c_int64)), ("integrator", C.c_int32), ("fixcom", C.c_int32),
+        ("npt", C.c_int32), ("p_ext", C.c_double), ("tau_p", C.c_double),
     ]
+
+
+class _Baro(C.Structure):
+    _fields_ = [("vw", C.c_double), ("box", C.c_double * 3)]
 
 
 class _Est(C.Structure):
@@ -86,6 +91,12 @@ def lib():
             "orc_estimators": (None, [S, d, d, d, d, C.POINTER(_Est)]),
             "orc_spring_energy_nm": (C.c_double, [S, d]),
             "orc_kcv_nm": (C.c_double, [S, d, d]),
+            "orc_baro_mass": (C.c_double, [S]),
+            "orc_sinhc": (C.c_double, [C.c_double]),
+            "orc_baro_kick": (None, [S, C.POINTER(_Baro), d, d, d, C.c_double]),
+            "orc_baro_centroid_flow": (None, [C.c_double, C.c_double, d, d]),
+            "orc_npt_step": (None, [S, C.POINTER(_Baro), d, d, d, d, u64, C.c_int32]),
+            "orc_baro_energies": (None, [S, C.POINTER(_Baro), C.c_double, d]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -169,6 +180,9 @@ class System:
     atom_id: np.ndarray | None = None   # noise-counter index per atom (None: 0..N-1)
     integrator: int = 0                 # 0: BAOAB, 1: OBABO
     fixcom: int = 0                     # 1: centroid COM velocity removed every step
+    npt: int = 0                        # 1: isotropic BZP barostat (OBABO only); nve -> NpH
+    p_ext: float = 0.0                  # target pressure
+    tau_p: float = 1.0                  # barostat time, W = 3 P N kB T tau_p^2
     _c: _System = field(default=None, init=False, repr=False)
 
     def cstruct(self) -> _System:
@@ -184,6 +198,7 @@ class System:
         s.bond_k, s.bond_r0 = self.bond_k, self.bond_r0
         s.integrator = int(self.integrator)
         s.fixcom = int(self.fixcom)
+        s.npt, s.p_ext, s.tau_p = int(self.npt), float(self.p_ext), float(self.tau_p)
         s.mass = _dp(self._mass)
         if self.lj_active is not None:
             self._act = np.ascontiguousarray(self.lj_active, dtype=np.int32)
@@ -267,6 +282,23 @@ class State:
         self.vt = to_normal(np.ascontiguousarray(v, dtype=np.float64))
         self.f, self.U = system.forces(self.x)
         self.step_count = np.array([step], dtype=np.uint64)
+        if system.npt:
+            if system.integrator != 1:
+                raise ValueError("the BZP barostat runs with the OBABO splitting")
+            self.baro = _Baro()
+            self.baro.vw = 0.0
+            self.baro.box = (C.c_double * 3)(*system.box)
+
+    @property
+    def box(self) -> tuple:
+        return tuple(self.baro.box) if self.sys.npt else tuple(self.sys.box)
+
+    def _cs(self) -> _System:
+        """The system's struct with the current box."""
+        s = self.sys.cstruct()
+        if self.sys.npt:
+            s.box = (C.c_double * 3)(*self.baro.box)
+        return s
 
     @property
     def v(self) -> np.ndarray:
@@ -279,8 +311,20 @@ class State:
 
     def step(self, n: int = 1) -> None:
         s = self.sys.cstruct()
+        if self.sys.npt:
+            lib().orc_npt_step(C.byref(s), C.byref(self.baro), _dp(self.x), _dp(self.vt),
+                               _dp(self.f), _dp(self.U),
+                               self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)), int(n))
+            return
         lib().orc_step(C.byref(s), _dp(self.x), _dp(self.vt), _dp(self.f), _dp(self.U),
                        self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)), int(n))
+
+    def baro_energies(self) -> dict:
+        """NpT: volume, K_W, U_W, J_W and the enthalpy of App. A, and v_W."""
+        out = np.zeros(5)
+        lib().orc_baro_energies(C.byref(self._cs()), C.byref(self.baro),
+                                self.estimators()["etot"], _dp(out))
+        return dict(zip(("volume", "kw", "uw", "jw", "enthalpy"), out.tolist()), vw=self.baro.vw)
 
     # --- forces supplied by the caller (an external potential) -----------
     @classmethod
@@ -309,6 +353,6 @@ class State:
 
     def estimators(self) -> dict:
         e = _Est()
-        lib().orc_estimators(C.byref(self.sys.cstruct()), _dp(self.x), _dp(self.vt), _dp(self.f),
+        lib().orc_estimators(C.byref(self._cs()), _dp(self.x), _dp(self.vt), _dp(self.f),
                              _dp(self.U), C.byref(e))
         return {n: getattr(e, n) for n in ESTIMATOR_NAMES}

@@ -704,3 +704,170 @@ double orc_kcv_nm(const orc_system *sys, const double *x, const double *f)
     free(xt); free(ft);
     return 1.5 * (double)N * sys->kB * sys->temp - vir / (2.0 * (double)P);
 }
+
+/* ------------------------------------------------------------------------
+ * BZP barostat, App. E, isotropic, with the OBABO splitting of the paper's
+ * example input.  A step at a synchronized state (forces f of x in box L):
+ *   O(dt/2) on the beads (q = 0) and on v_W;
+ *   B(dt/2): v_W and v~ kicked together;
+ *   A(dt): the centroid mode under the barostat, the other modes by the free
+ *          ring-polymer flow (A(dt/2) twice), L <- exp(dt v_W) L;
+ *   forces of the new positions in the new box;
+ *   B(dt/2); O(dt/2) on v_W and on the beads (q = 1).
+ * Readings of App. E:
+ *  - the barostat's force is (3/W)[P V (P_CV - P_ext) + P kB T]: the printed
+ *    1/(n kB T) is read as n kB T, the value for which App. A's enthalpy
+ *    H + K_W + U_W + J_W (J_W = -P kB T ln V) is a constant of the NpH motion;
+ *  - B is the exact flow of the kick: v~0 moves linearly over the kick, so the
+ *    centroid kinetic term integrates to h K + h^2 F~0.v~0 + h^3 |F~0|^2/(3m)
+ *    from the momenta at the kick's start, which is what the printed h^2 and
+ *    h^3 terms are;
+ *  - the scaling acts on the centroid mode only (the one mode that P_CV's
+ *    kinetic term and F~0.v~0 see);
+ *  - the barostat's thermostat is an O step over dt/2 with c1 = exp(-dt/(2 tau_0))
+ *    (tau_0 as printed) and noise sqrt(P kB T / W) z (W for the printed m_i);
+ *    z is the first Gaussian of counter (2^64 - 1, 0, s, q).
+ * --------------------------------------------------------------------- */
+double orc_baro_mass(const orc_system *sys)
+{
+    return 3.0 * (double)sys->n_beads * (double)sys->n_atoms * sys->kB * sys->temp * sys->tau_p *
+           sys->tau_p;
+}
+
+double orc_sinhc(double u)
+{
+    if (fabs(u) < 1e-3) {
+        const double u2 = u * u;
+        return 1.0 + u2 / 6.0 * (1.0 + u2 / 20.0 * (1.0 + u2 / 42.0));
+    }
+    return sinh(u) / u;
+}
+
+static orc_system orc_in_box(const orc_system *sys, const orc_baro *b)
+{
+    orc_system s = *sys;
+    for (int d = 0; d < 3; ++d) s.box[d] = b->box[d];
+    return s;
+}
+
+void orc_baro_kick(const orc_system *sys0, orc_baro *b, const double *x, const double *vt,
+                   const double *f, double h)
+{
+    const orc_system sb = orc_in_box(sys0, b);
+    const orc_system *sys = &sb;
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double kT = sys->kB * sys->temp, W = orc_baro_mass(sys);
+    const double V = sys->box[0] * sys->box[1] * sys->box[2];
+    double *ft = (double *)malloc(sizeof(double) * n);
+    orc_to_normal(P, N, f, ft);
+    /* centroid sums (mode 0 rows of v~ and f~) */
+    double k0 = 0.0, fv = 0.0, f2 = 0.0;
+    for (int32_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double v = vt[(size_t)i * 3 + d], F = ft[(size_t)i * 3 + d];
+            k0 += sys->mass[i] * sys->mvv2e * v * v;
+            fv += F * v;
+            f2 += F * F / (sys->mass[i] * sys->mvv2e);
+        }
+    /* sum_k sum_i (r - r_c) . F and the cell virial */
+    double vir = 0.0, w = 0.0;
+    for (int32_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double c = 0.0;
+            for (int32_t k = 0; k < P; ++k) c += x[((size_t)k * N + i) * 3 + d];
+            c /= (double)P;
+            for (int32_t k = 0; k < P; ++k) {
+                const size_t e = ((size_t)k * N + i) * 3 + d;
+                vir += (x[e] - c) * f[e];
+            }
+        }
+    for (int32_t k = 0; k < P; ++k) w += orc_virial_bead(sys, x + (size_t)k * N * 3);
+    /* 3 P V P_CV = k0 - vir + w */
+    b->vw += h / W * (k0 - vir + w - 3.0 * (double)P * V * sys->p_ext + 3.0 * (double)P * kT) +
+             h * h / W * fv + h * h * h / (3.0 * W) * f2;
+    free(ft);
+}
+
+void orc_baro_centroid_flow(double vw, double t, double *xt0, double *vt0)
+{
+    const double u = t * vw;
+    const double e = exp(u), ei = exp(-u), s = t * orc_sinhc(u);
+    *xt0 = e * *xt0 + s * *vt0;
+    *vt0 = ei * *vt0;
+}
+
+static void orc_baro_o(const orc_system *sys, orc_baro *b, uint64_t s, uint64_t q)
+{
+    if (sys->nve) return;
+    const double h = 0.5 * sys->dt;
+    const double c1 = exp(-h / sys->tau), c2 = sqrt(1.0 - c1 * c1);
+    const double sigma = sqrt((double)sys->n_beads * sys->kB * sys->temp / orc_baro_mass(sys));
+    double z[3];
+    orc_gaussians_q(sys->seed, 0, ~(uint64_t)0, 0, s, q, z);
+    b->vw = c1 * b->vw + c2 * sigma * z[0];
+}
+
+void orc_npt_step(const orc_system *sys0, orc_baro *b, double *x, double *vt, double *f,
+                  double *U, uint64_t *step, int32_t nsteps)
+{
+    const int32_t P = sys0->n_beads, N = sys0->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double h = 0.5 * sys0->dt;
+    double *xt = (double *)malloc(sizeof(double) * n);
+    double *ft = (double *)malloc(sizeof(double) * n);
+    for (int32_t it = 0; it < nsteps; ++it) {
+        orc_system sys = orc_in_box(sys0, b);
+        const uint64_t s = *step;
+        /* O */
+        orc_o_step(&sys, vt, s, 0);
+        orc_baro_o(&sys, b, s, 0);
+        /* B */
+        orc_baro_kick(&sys, b, x, vt, f, h);
+        orc_kick(&sys, vt, f, ft);
+        /* A */
+        orc_to_normal(P, N, x, xt);
+        double Ah[4];
+        for (int32_t k = 1; k < P; ++k) {
+            orc_free_rp_matrix(&sys, k, h, Ah);
+            for (int32_t i = 0; i < N; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    const size_t e = ((size_t)k * N + i) * 3 + d;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        const double q = xt[e], p = vt[e];
+                        xt[e] = Ah[0] * q + Ah[1] * p;
+                        vt[e] = Ah[2] * q + Ah[3] * p;
+                    }
+                }
+        }
+        for (size_t e = 0; e < (size_t)N * 3; ++e) orc_baro_centroid_flow(b->vw, sys.dt, &xt[e], &vt[e]);
+        orc_from_normal(P, N, xt, x);
+        const double scale = exp(sys.dt * b->vw);
+        for (int d = 0; d < 3; ++d) b->box[d] *= scale;
+        *step = s + 1;
+        /* forces in the new box */
+        sys = orc_in_box(sys0, b);
+        orc_forces(&sys, x, f, U);
+        /* B, O */
+        orc_baro_kick(&sys, b, x, vt, f, h);
+        orc_kick(&sys, vt, f, ft);
+        orc_baro_o(&sys, b, s, 1);
+        orc_o_step(&sys, vt, s, 1);
+    }
+    free(xt);
+    free(ft);
+}
+
+void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, double out[5])
+{
+    const double P = (double)sys->n_beads, kT = sys->kB * sys->temp;
+    const double V = b->box[0] * b->box[1] * b->box[2];
+    const double kw = 0.5 * orc_baro_mass(sys) * b->vw * b->vw;
+    const double uw = P * sys->p_ext * V;
+    const double jw = -P * kT * log(V);
+    out[0] = V;
+    out[1] = kw;
+    out[2] = uw;
+    out[3] = jw;
+    out[4] = etot + kw + uw + jw;
+}

@@ -62,6 +62,10 @@ typedef struct orc_system {
     int32_t integrator;     /* 0: BAOAB; 1: OBABO (O(dt/2) B(dt/2) A(dt) B(dt/2) O(dt/2)) */
     int32_t fixcom;         /* 1: remove the centroids' center-of-mass velocity at the end
                                of every step */
+    int32_t npt;            /* 1: isotropic BZP barostat (App. E), OBABO only; with nve = 1
+                               the barostat's thermostat is off too (NpH) */
+    double p_ext;           /* target pressure (energy per volume) */
+    double tau_p;           /* barostat time: W = 3 P N kB T tau_p^2 */
 } orc_system;
 
 typedef struct orc_est {
@@ -123,6 +127,31 @@ void orc_step(const orc_system *sys, double *x, double *vt, double *f, double *U
 void orc_step_positions(const orc_system *sys, double *x, double *vt, const double *f,
                         uint64_t *step);
 void orc_step_kick(const orc_system *sys, double *vt, const double *f, uint64_t s);
+
+/* --- BZP barostat (App. E, isotropic) ---------------------------------- */
+typedef struct orc_baro {
+    double vw;              /* barostat velocity v_W */
+    double box[3];          /* current box lengths */
+} orc_baro;
+/* W = 3 P N kB T tau_p^2 (App. A) */
+double orc_baro_mass(const orc_system *sys);
+/* sinh(u)/u, by its Taylor series for |u| < 1e-3 */
+double orc_sinhc(double u);
+/* The barostat's share of a kick of length h: v_W advances along the exact
+ * flow of the kick (forces, positions and box fixed, v~ += h f~/m), from the
+ * momenta at the start of the kick.  vt and f as for orc_step. */
+void orc_baro_kick(const orc_system *sys, orc_baro *b, const double *x, const double *vt,
+                   const double *f, double h);
+/* The centroid mode's flow under the barostat over a time t (App. E):
+ * (x~0, v~0) -> (e x~0 + t sinhc(t v_W) v~0, v~0 / e), e = exp(t v_W). */
+void orc_baro_centroid_flow(double vw, double t, double *xt0, double *vt0);
+/* nsteps NpT (or NpH) steps: O, B, A, forces, B, O with the barostat; the box
+ * in b moves with the centroids, and f, U are those of the new box. */
+void orc_npt_step(const orc_system *sys, orc_baro *b, double *x, double *vt, double *f,
+                  double *U, uint64_t *step, int32_t nsteps);
+/* Barostat terms of App. A at box b: out = {V, K_W, U_W, J_W, enthalpy}, the
+ * enthalpy H + K_W + U_W + J_W with H = etot. */
+void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, double out[5]);
 
 /* --- estimators (App. A) ----------------------------------------------- */
 /* At a synchronized state.  U is [P] from orc_forces. */

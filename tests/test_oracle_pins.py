@@ -649,3 +649,156 @@ def test_pmd_is_the_classical_pressure_of_the_beads():
     e2 = st2.estimators()
     want = (s2.mass[None, :, None] * v * v).sum() / (3 * 5.0 ** 3)
     assert abs(e2["pmd"] - want) <= 1e-13 * want
+
+
+# ---------------------------------------------------------------- BZP barostat
+def _nph(dt, t_total=1.0, npt=1):
+    """LJ (rc = 3, small force jump at the cutoff) at P = 4 in NpH (both
+    thermostats off), started far from mechanical equilibrium so that the
+    volume moves by ~40%; returns App. A's enthalpy (or H without the
+    barostat) every fifth step and the volumes."""
+    g, L, P, T = 5, 6.3, 4, 2.0
+    N = g ** 3
+    pts = np.stack(np.meshgrid(*[np.arange(g)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.1, dt=dt,
+                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=1.0, lj_sigma=1.0, lj_rc=3.0,
+                      integrator=1, npt=npt, nve=True, p_ext=1.0, tau_p=0.5, seed=3)
+    rng = np.random.default_rng(1)
+    x = (pts + 0.5) * (L / g)
+    st = oracle.State(s, x[None] + 0.02 * rng.standard_normal((P, N, 3)),
+                      rng.standard_normal((P, N, 3)) * math.sqrt(P * T))
+    H, V = [], []
+    for _ in range(int(round(t_total / dt)) // 5):
+        st.step(5)
+        if npt:
+            b = st.baro_energies()
+            H.append(b["enthalpy"])
+            V.append(b["volume"])
+        else:
+            H.append(st.estimators()["etot"])
+    return np.array(H), np.array(V)
+
+
+def test_bzp_nph_conserves_the_enthalpy_to_second_order():
+    """App. A's enthalpy H + K_W + U_W + J_W is a constant of the NpH motion:
+    its spread falls as dt^2 (a wrong term in the barostat's force, in the
+    centroid's flow or in the box update leaves an O(1) or O(dt) error),
+    while U_W and J_W themselves change by hundreds and by ~1.5."""
+    H1, V1 = _nph(0.002)
+    H2, V2 = _nph(0.001)
+    assert V1.max() / V1.min() > 1.3          # the barostat does move the box
+    r = np.ptp(H1) / np.ptp(H2)
+    assert 3.0 < r < 5.0, (np.ptp(H1), np.ptp(H2))
+    assert np.ptp(H2) < 0.3
+    # no worse than the same system's NVE energy at the same dt (the cutoff's
+    # force jump dominates both)
+    E2, _ = _nph(0.001, npt=0)
+    assert np.ptp(H2) < 2.5 * np.ptp(E2)
+
+
+def test_bzp_barostat_kick_is_the_exact_flow_of_the_kick():
+    """v_W after a kick of length h equals the integral of
+    (3/W)[P V (P_CV(v~(t)) - P_ext) + P kT] along v~(t) = v~ + t f~/m, done by
+    RK4 on the oracle's own P_CV estimator (not the closed form)."""
+    s, x = _lj_box(N=20, L=5.2, seed=21, P=3)
+    s.integrator, s.npt, s.p_ext, s.tau_p, s.hbar = 1, 1, 0.7, 0.3, 0.3
+    rng = np.random.default_rng(22)
+    st = oracle.State(s, x[None] + 0.03 * rng.standard_normal((3, 20, 3)),
+                      rng.standard_normal((3, 20, 3)) * 1.5)
+    h = 0.01
+    W = oracle.lib().orc_baro_mass(oracle.C.byref(s.cstruct()))
+    V = 5.2 ** 3
+    ft = oracle.to_normal(st.f)
+    vt0 = st.vt.copy()
+
+    def rate(t):
+        st.vt = vt0 + t * ft / s.mass[None, :, None]
+        return 3 / W * (3 * V * (st.estimators()["pcv"] - s.p_ext) + 3 * s.kB * s.temp)
+
+    n, acc = 40, 0.0
+    dt = h / n
+    for j in range(n):
+        t = j * dt
+        acc += dt / 6 * (rate(t) + 2 * rate(t + dt / 2) + 2 * rate(t + dt / 2) + rate(t + dt))
+    st.vt = vt0
+    st.baro.vw = 0.25
+    oracle.lib().orc_baro_kick(oracle.C.byref(s.cstruct()), oracle.C.byref(st.baro),
+                               oracle._dp(st.x), oracle._dp(st.vt), oracle._dp(st.f), h)
+    assert abs(st.baro.vw - 0.25 - acc) <= 1e-12 * abs(acc) + 1e-15, (st.baro.vw - 0.25, acc)
+    assert abs(acc) > 1e-6
+
+
+@pytest.mark.parametrize("vw", [0.0, 1e-9, 3e-4, -0.7, 2.5])
+def test_bzp_centroid_flow_is_the_exact_linear_flow(vw):
+    """App. E's centroid update against scipy's expm of d/dt (x~0, v~0) =
+    [[v_W, 1], [0, -v_W]] (x~0, v~0), including v_W = 0 and the small-v_W
+    series of sinh(u)/u."""
+    t = 0.37
+    x0, v0 = 1.3, -0.45
+    xa = np.array([x0]); va = np.array([v0])
+    oracle.lib().orc_baro_centroid_flow(vw, t, oracle._dp(xa), oracle._dp(va))
+    E = scipy.linalg.expm(np.array([[vw, 1.0], [0.0, -vw]]) * t)
+    want = E @ np.array([x0, v0])
+    assert abs(xa[0] - want[0]) <= 2e-15 * max(1.0, abs(want[0]))
+    assert abs(va[0] - want[1]) <= 2e-15 * max(1.0, abs(want[1]))
+
+
+def test_bzp_with_a_heavy_barostat_is_obabo():
+    """With W -> infinity the box stays put and the NpT step is the NVT OBABO
+    step on the same noise (the barostat draws from its own counter)."""
+    spec = inputs.lj_liquid(n_atoms=108, n_beads=4, seed=23)
+    s = oracle.System.from_spec(spec)
+    s.integrator = 1
+    a = oracle.State(s, spec.x0, spec.v0)
+    sn = oracle.System.from_spec(spec)
+    sn.integrator, sn.npt, sn.p_ext, sn.tau_p = 1, 1, 1.0, 1e9
+    b = oracle.State(sn, spec.x0, spec.v0)
+    a.step(20)
+    b.step(20)
+    assert abs(b.box[0] / spec.box[0] - 1) < 1e-12
+    assert np.abs(b.x - a.x).max() <= 1e-9 * np.abs(a.x).max()
+    assert np.abs(b.vt - a.vt).max() <= 1e-9 * np.abs(a.vt).max()
+
+
+def test_bzp_barostat_equipartition():
+    """NpT: v_W's marginal is Gaussian with variance P kT / W (the enthalpy
+    is separable in v_W and sampled at P T), so <K_W> = P kT / 2; a dilute
+    ring-polymer gas, 6e4 steps, block-averaged error bar."""
+    N, P, L = 8, 4, 4.0
+    rng = np.random.default_rng(5)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.2, dt=0.01,
+                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=0.0, lj_rc=1.0, integrator=1,
+                      npt=1, p_ext=0.5, tau_p=0.2, tau=0.05, seed=9)
+    st = oracle.State(s, rng.uniform(0, L, (1, N, 3)) + 0.01 * rng.standard_normal((P, N, 3)),
+                      rng.standard_normal((P, N, 3)) * 2)
+    W = oracle.lib().orc_baro_mass(oracle.C.byref(s.cstruct()))
+    st.step(1000)
+    kw = []
+    for _ in range(60000):
+        st.step(1)
+        kw.append(0.5 * W * st.baro.vw ** 2)
+    blocks = np.array(kw).reshape(40, -1).mean(axis=1)
+    se = blocks.std() / math.sqrt(40)
+    assert abs(blocks.mean() - 0.5 * P * s.kB * s.temp) < 5 * se, (blocks.mean(), se)
+    assert se < 0.1
+
+
+def test_bzp_barostat_thermostat_rate():
+    """With a very heavy barostat the kicks vanish and v_W is the
+    Ornstein-Uhlenbeck chain of its two O(dt/2) steps per step: lag-one
+    autocorrelation exp(-dt/tau_0) per step (tau_0, as printed)."""
+    N, P, L = 8, 4, 4.0
+    rng = np.random.default_rng(6)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.2, dt=0.01,
+                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=0.0, lj_rc=1.0, integrator=1,
+                      npt=1, p_ext=0.5, tau_p=1e6, tau=0.05, seed=10)
+    st = oracle.State(s, rng.uniform(0, L, (1, N, 3)) + 0.01 * rng.standard_normal((P, N, 3)),
+                      rng.standard_normal((P, N, 3)) * 2)
+    vw = []
+    for _ in range(20000):
+        st.step(1)
+        vw.append(st.baro.vw)
+    vw = np.array(vw)
+    rho = np.dot(vw[1:], vw[:-1]) / np.dot(vw[:-1], vw[:-1])
+    want = math.exp(-s.dt / s.tau)
+    assert abs(rho - want) < 5 * math.sqrt((1 - want ** 2) / len(vw)), (rho, want)
