@@ -116,6 +116,31 @@ def sync(ctx):
     return ctx.estimators()
 
 
+def bench_npt(make):
+    """The barostat's step (two passes with their finalizes, then the forces
+    in the new box) on the LJ liquid, and on the shape of the paper's NpT
+    example: 128 water molecules, P = 32, 300 K, dt 0.5 fs, PILE-L tau 0.1 ps,
+    BZP tau_p 0.5 ps at 1 bar (water-shaped potential in place of its DP
+    model)."""
+    out = {}
+    lj = make()
+    lj.integrator, lj.ensemble, lj.p_ext, lj.tau_p = 1, inputs.NPT, 0.5, 0.5
+    ms, _, prof, _, _, _ = run_gpu(lj, 500, 50, 100)
+    out["lj"] = {"workload": "LJ quantum liquid, N=%d, P=%d, NpT (OBABO + BZP, p_ext=0.5, tau_p=0.5)"
+                             % (lj.n_atoms, lj.n_beads),
+                 "ms_per_step": ms, "bead_atom_steps_per_s": lj.bead_atoms * 1e3 / ms,
+                 "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof).items()}}
+    w = inputs.water(n_atoms=384, n_beads=32, dt=0.5, tau=100.0)
+    bar = 1.0 / 69476.95                   # kcal/mol/A^3
+    w.integrator, w.ensemble, w.p_ext, w.tau_p = 1, inputs.NPT, bar, 500.0
+    ms, _, prof, _, _, _ = run_gpu(w, 1000, 100, 100)
+    out["water_128"] = {"workload": "128 water molecules (N=384), P=32, NpT at 300 K and 1 bar, "
+                                    "dt 0.5 fs (the paper's NpT example's shape)",
+                        "ms_per_step": ms, "ns_per_day": 0.5e-6 * 86400.0 * 1e3 / ms,
+                        "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof).items()}}
+    return out
+
+
 def run_gpu(spec, steps, warmup, profile_steps, flags=0):
     from paper_2602_13553_amd import pimd
     ctx = pimd.Context.from_spec(spec, flags=flags)
@@ -391,6 +416,8 @@ def main():
                                              "the closing half-kick in a pass of its own)",
                          "ms_per_step": ms_fc, "bead_atom_steps_per_s": fc.bead_atoms * 1e3 / ms_fc,
                          "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_fc).items()}}
+        log("NpT (BZP barostat)")
+        out["npt"] = bench_npt(make)
         log("external forces")
         out["external_forces"] = bench_external()
         log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))

@@ -48,9 +48,15 @@ extern "C" {
 #define PIMD_ERR_UNSUPPORTED (-6) /* valid but not supported by the library */
 #define PIMD_ERR_OVERFLOW (-7)    /* neighbor-list capacity exceeded */
 
-/* ensemble (Sec. III.C): NVT = PILE-L thermostat at P*T, NVE = no thermostat */
+/* ensemble (Sec. III.C): NVT = PILE-L thermostat at P*T, NVE = no thermostat;
+ * NPT = PILE-L and the isotropic BZP barostat (Sec. IV.A, App. E) with a
+ * thermostat on its velocity, NPH = the barostat with neither thermostat.
+ * NPT and NPH need PIMD_OBABO, PIMD_POT_LJ or PIMD_POT_WATER, fixcom = 0; they
+ * are not batched. */
 #define PIMD_NVT 0
 #define PIMD_NVE 1
+#define PIMD_NPT 2
+#define PIMD_NPH 3
 
 /* potential U of one bead (the U(r^(k)) term of Eq. 1); every bead is an
  * independent copy of the physical system */
@@ -66,7 +72,7 @@ extern "C" {
 typedef struct pimd_params {
     int32_t n_atoms;    /* N >= 1 */
     int32_t n_beads;    /* P >= 1 (the paper's n); the library supports P <= 128 */
-    int32_t ensemble;   /* PIMD_NVT or PIMD_NVE */
+    int32_t ensemble;   /* PIMD_NVT, PIMD_NVE, PIMD_NPT or PIMD_NPH */
     int32_t potential;  /* PIMD_POT_* */
     double temp;        /* T > 0; the thermostat acts at P*T (Sec. IV.A) */
     double kB;          /* Boltzmann constant (energy per temperature) > 0 */
@@ -89,7 +95,22 @@ typedef struct pimd_params {
     int32_t integrator;   /* PIMD_BAOAB (0) or PIMD_OBABO (1) */
     int32_t fixcom;       /* 1: remove the centroids' center-of-mass velocity at the end
                              of every step (Sec. III.C's fixcom keyword); not in a batch */
+    double p_ext;         /* NPT, NPH: target pressure, energy per volume (finite) */
+    double tau_p;         /* NPT, NPH: barostat time > 0; mass W = 3 P N kB T tau_p^2 */
 } pimd_params;
+
+/* The barostat (NPT, NPH; App. E, isotropic).  A step: O(dt/2) on the beads
+ * and on v_W; B(dt/2) on v_W and the beads together; A(dt) with the centroid
+ * modes under the barostat, x~0 <- e x~0 + dt sinh(u)/u v~0, v~0 <- v~0 / e
+ * (u = dt v_W, e = exp(u)), the other modes by the free flow, and the box
+ * L <- e L; the forces in the new box; B(dt/2); O(dt/2) on v_W and the beads.
+ * v_W's force is (3/W)[P V (P_CV - p_ext) + P kB T] (the value for which the
+ * enthalpy H + K_W + U_W + J_W of App. A is conserved in NPH; J_W =
+ * -P kB T ln V); its kick integrates the centroid kinetic term along the
+ * beads' kick (App. E's h^2 and h^3 terms, from the momenta at the kick's
+ * start).  Its O step: v_W <- c1 v_W + c2 sqrt(P kB T / W) z, c1 =
+ * exp(-dt/(2 tau)), z the first Gaussian of counter (2^64 - 1, 0, step, q).
+ * The box starts at params.box with v_W = 0 at every pimd_set_state. */
 
 /* fixcom = 1: at the end of every step (after the closing B, and OBABO's
  * second O) the mass-weighted mean u = sum_i m_i v~0_i / sum_i m_i of the
@@ -162,6 +183,11 @@ typedef struct pimd_estimators {
     int32_t overflow;  /* 1 if a neighbor list ran out of capacity */
     uint64_t n_rebuilds; /* neighbor-list builds since set_state (LJ, WATER) */
     double rlist;        /* centroid cutoff of the current neighbor lists */
+    /* NPT, NPH (0 otherwise), at the state's step: */
+    double volume;       /* V of the current box */
+    double vw;           /* barostat velocity v_W */
+    double enthalpy;     /* H + K_W + U_W + J_W (App. A): K_W = W v_W^2 / 2, U_W = P p_ext V,
+                            J_W = -P kB T ln V */
 } pimd_estimators;
 /* ekin    = sum_k sum_i 1/2 m_i |v~_i^(k)|^2 (App. A item 1)
  * espring = sum_k sum_i 1/2 m_i omega_n^2 lambda_k |x~_i^(k)|^2 (App. A item 2,
@@ -240,6 +266,11 @@ int pimd_get_estimators(pimd_ctx *ctx, pimd_estimators *out);
  * momenta p = m M^T v~, both [P][N][3] host arrays (either may be NULL), and
  * the step counter (may be NULL).  Errors: STATE, DEVICE. */
 int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
+
+/* NPT, NPH: wait for the stream, then copy out the current box lengths
+ * (box[3], may be NULL) and the barostat velocity (vw, may be NULL).
+ * Errors: STATE, UNSUPPORTED (no barostat), DEVICE. */
+int pimd_get_barostat(pimd_ctx *ctx, double *box, double *vw);
 
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);

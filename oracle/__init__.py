@@ -222,12 +222,14 @@ class System:
         pot = {0: POT_NONE, 1: POT_HARMONIC, 2: POT_PAIR, 3: POT_PAIR, 4: POT_NONE}[int(spec.potential)]
         return cls(n_atoms=spec.n_atoms, n_beads=spec.n_beads, mass=np.asarray(spec.mass),
                    temp=spec.temp, kB=spec.kB, hbar=spec.hbar, mvv2e=spec.mvv2e, dt=spec.dt,
-                   tau=spec.tau, tau_scale=spec.tau_scale, nve=bool(spec.ensemble == 1),
+                   tau=spec.tau, tau_scale=spec.tau_scale, nve=bool(spec.ensemble in (1, 3)),
                    pot=pot, box=tuple(spec.box), seed=spec.seed, omega=spec.omega,
                    lj_eps=spec.lj_eps, lj_sigma=spec.lj_sigma, lj_rc=spec.lj_rc,
                    bond_k=spec.bond_k, bond_r0=spec.bond_r0, lj_active=spec.lj_active,
                    bonds=spec.bonds, integrator=int(getattr(spec, "integrator", 0)),
-                   fixcom=int(getattr(spec, "fixcom", 0)))
+                   fixcom=int(getattr(spec, "fixcom", 0)),
+                   npt=int(spec.ensemble in (2, 3)), p_ext=float(getattr(spec, "p_ext", 0.0)),
+                   tau_p=float(getattr(spec, "tau_p", 1.0)))
 
     # --- per-function wrappers -------------------------------------------
     def free_rp_matrix(self, k: int, h: float) -> np.ndarray:

@@ -32,11 +32,17 @@ struct Layout {
     bool clusters;                // force pass on cluster lists
     int n_clusters;
     size_t clist, ccount, cframe, cmode;
+    int npt_grid;                 // barostat passes' blocks (0: no barostat)
+    size_t nft, npart;            // barostat: f~ and pass partials
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool is_pair(int pot) { return pot == PIMD_POT_LJ || pot == PIMD_POT_WATER; }
+// the BZP barostat moves the box
+bool is_npt(const pimd_params *p) { return p->ensemble == PIMD_NPT || p->ensemble == PIMD_NPH; }
+// a PILE-L thermostat on the beads
+bool thermostatted(const pimd_params *p) { return p->ensemble == PIMD_NVT || p->ensemble == PIMD_NPT; }
 // forces from an array (the force pass or the caller) rather than in the step pass
 bool forces_in_array(int pot) { return is_pair(pot) || pot == PIMD_POT_EXTERNAL; }
 
@@ -62,6 +68,7 @@ struct pimd_ctx {
     std::vector<int> orig;          // internal -> caller index
     FusedArgs fa;
     PairArgs pa;
+    NptArgs na;                     // the barostat's passes (NPT, NPH)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_failed = false;
@@ -116,7 +123,7 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
             return PIMD_ERR_ARG;
         }
     }
-    if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) { why = "bad ensemble"; return PIMD_ERR_ARG; }
+    if (p->ensemble < PIMD_NVT || p->ensemble > PIMD_NPH) { why = "bad ensemble"; return PIMD_ERR_ARG; }
     if (p->integrator != PIMD_BAOAB && p->integrator != PIMD_OBABO) { why = "bad integrator"; return PIMD_ERR_ARG; }
     if (p->fixcom != 0 && p->fixcom != 1) { why = "fixcom must be 0 or 1"; return PIMD_ERR_ARG; }
     if (p->potential < PIMD_POT_NONE || p->potential > PIMD_POT_EXTERNAL) { why = "bad potential"; return PIMD_ERR_ARG; }
@@ -125,9 +132,23 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
         why = "temp, kB, hbar, mvv2e and dt must be finite and > 0";
         return PIMD_ERR_ARG;
     }
-    if (p->ensemble == PIMD_NVT && (!finite_pos(p->tau) || !finite_pos(p->tau_scale))) {
-        why = "tau and tau_scale must be finite and > 0 for NVT";
+    if (thermostatted(p) && (!finite_pos(p->tau) || !finite_pos(p->tau_scale))) {
+        why = "tau and tau_scale must be finite and > 0 for NVT and NPT";
         return PIMD_ERR_ARG;
+    }
+    if (is_npt(p)) {
+        if (!finite_pos(p->tau_p) || !std::isfinite(p->p_ext)) {
+            why = "the barostat needs tau_p > 0 and a finite p_ext";
+            return PIMD_ERR_ARG;
+        }
+        if (p->integrator != PIMD_OBABO || !is_pair(p->potential) || p->fixcom) {
+            why = "the barostat runs with PIMD_OBABO, PIMD_POT_LJ or PIMD_POT_WATER, and fixcom = 0";
+            return PIMD_ERR_UNSUPPORTED;
+        }
+        if (p->flags & (PIMD_FLAG_MFMA_TRANSFORMS | PIMD_FLAG_CLUSTER_PAIRS)) {
+            why = "the barostat's passes use the vector-ALU transforms and per-atom lists";
+            return PIMD_ERR_UNSUPPORTED;
+        }
     }
     if (p->potential == PIMD_POT_HARMONIC && !std::isfinite(p->omega)) { why = "bad omega"; return PIMD_ERR_ARG; }
     if (is_pair(p->potential)) {
@@ -212,7 +233,8 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
     L.ncell = 0;
     L.cell_cap = 0;
     L.nc[0] = L.nc[1] = L.nc[2] = 0;
-    if (!is_pair(p->potential) || n_active == 0) return;
+    // the barostat moves the box, and with it the cell grid: all-pairs scans
+    if (!is_pair(p->potential) || n_active == 0 || is_npt(p)) return;
     const double w = p->lj_rc + p->skin + 2.0 * e_guess;
     long long ncell = 1;
     int nc[3];
@@ -236,7 +258,7 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
 bool use_mfma(const pimd_params *p)
 {
     const int P = p->n_beads;
-    if (!fused_mfma_supported(P) || (p->flags & PIMD_FLAG_VALU_TRANSFORMS)) return false;
+    if (!fused_mfma_supported(P) || (p->flags & PIMD_FLAG_VALU_TRANSFORMS) || is_npt(p)) return false;
     if (p->flags & PIMD_FLAG_MFMA_TRANSFORMS) return true;
     const int row = P == 16 ? 0 : (P == 32 ? 1 : 2);
     return (long long)p->n_atoms * P >= tuning::kMfmaMinBeadAtoms[row];
@@ -247,7 +269,7 @@ bool use_mfma(const pimd_params *p)
 bool use_clusters(const pimd_params *p, int n_active)
 {
     const int P = p->n_beads, N = p->n_atoms;
-    if (!is_pair(p->potential) || n_active == 0 || P < 8 || kBlock / P > 32) return false;
+    if (!is_pair(p->potential) || n_active == 0 || P < 8 || kBlock / P > 32 || is_npt(p)) return false;
     if (p->flags & PIMD_FLAG_ATOM_PAIRS) return false;
     if (p->flags & PIMD_FLAG_CLUSTER_PAIRS) return true;
     const int row = P == 8 ? 0 : P == 16 ? 1 : P == 32 ? 2 : P == 64 ? 3 : -1;
@@ -324,6 +346,9 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.ccount = take((size_t)L.n_clusters * sizeof(int));
     L.cframe = take(L.clusters ? (size_t)n_active * sizeof(int) : 0);
     L.cmode = take((size_t)L.n_clusters * sizeof(int));
+    L.npt_grid = is_npt(p) ? npt_grid(p->n_atoms, p->n_beads) : 0;
+    L.nft = take(L.npt_grid ? arr : 0);
+    L.npart = take((size_t)L.npt_grid * NP_COUNT * sizeof(double));
     L.total = o;
     return L;
 }
@@ -377,7 +402,7 @@ std::vector<double> mode_table(const pimd_params *p)
             const double c = std::cos(wk * h), s = std::sin(wk * h);
             r[MD_A00] = c; r[MD_A01] = s / wk; r[MD_A10] = -wk * s; r[MD_A11] = c;
         }
-        if (p->ensemble == PIMD_NVT) {
+        if (thermostatted(p)) {
             const double tau_k = (k == 0) ? p->tau : p->tau_scale / (2.0 * wk);
             const double to = (p->integrator == PIMD_OBABO) ? 0.5 * p->dt : p->dt;
             r[MD_C1] = std::exp(-to / tau_k);
@@ -436,8 +461,26 @@ void enqueue_fused(pimd_ctx *c, int mode, int kind)
     prof_end(c, e);
 }
 
+// One barostat step: pass A (pending closing, estimators, opening O) and
+// pass B (kick, A, inverse transform), each with its finalize, then the
+// forces in the new box.
+void enqueue_step_npt(pimd_ctx *c)
+{
+    size_t e = prof_begin(c, PIMD_KERNEL_FUSED);
+    launch_npt_a(c->na, NPT_STEP, c->stream);
+    launch_npt_b(c->na, c->stream);
+    prof_end(c, e);
+    e = prof_begin(c, PIMD_KERNEL_PAIR);
+    launch_pair_npt(c->pa, c->lay.pair_grid, c->stream);
+    prof_end(c, e);
+}
+
 void enqueue_step(pimd_ctx *c)
 {
+    if (c->lay.npt_grid) {
+        enqueue_step_npt(c);
+        return;
+    }
     // fixcom with a force pass: the last step's closing half-kick runs in a
     // pass of its own, so that its centroid momentum is known (and removed at
     // the start of the step pass) before the step's opening half-kick
@@ -596,7 +639,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.mode = FUSED_STEP;
     a.pair = forces_in_array(p->potential) ? 1 : 0;
     a.lists = pair ? 1 : 0;
-    a.nvt = p->ensemble == PIMD_NVT ? 1 : 0;
+    a.nvt = thermostatted(p) ? 1 : 0;
     a.obabo = p->integrator == PIMD_OBABO ? 1 : 0;
     a.fixcom = p->fixcom ? 1 : 0;
     {
@@ -665,6 +708,21 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     q.cell_scnt = a.cell_scnt;
     q.cinfo = a.cinfo;
 
+    if (L.npt_grid) {
+        NptArgs &b = c->na;
+        b.f = c->fa;
+        b.ft = (double *)(w + L.nft);
+        b.part = (double *)(w + L.npart);
+        b.dt = p->dt;
+        b.p_ext = p->p_ext;
+        const double kT = p->kB * p->temp;
+        b.kTP = (double)P * kT;
+        b.wmass = 3.0 * (double)P * (double)N * kT * p->tau_p * p->tau_p;
+        b.bc1 = p->ensemble == PIMD_NPT ? std::exp(-0.5 * p->dt / p->tau) : 1.0;
+        b.bc2 = std::sqrt(1.0 - b.bc1 * b.bc1);
+        b.bsig = std::sqrt(b.kTP / b.wmass);
+    }
+
     *out = c;
     return PIMD_OK;
 }
@@ -681,6 +739,7 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     // the device layout; PREP then turns v into v~ = M v in place (each tile
     // is staged in shared memory before it is overwritten).
     launch_ctl_init(c->d_ctl, (unsigned long long)step, c->stream);
+    if (c->lay.npt_grid) launch_npt_init(c->d_ctl, c->p.box, c->stream);
     HIP_TRY(c, hipMemcpyAsync(c->d_stage, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     launch_import(c->d_stage, c->d_x, c->d_orig, N, P, c->stream);
     HIP_TRY(c, hipMemcpyAsync(c->d_stage, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -691,8 +750,13 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     launch_fused(a, c->lay.fused_grid, c->stream);
     launch_finalize(a, c->lay.fused_grid, c->stream);
     const bool external = c->p.potential == PIMD_POT_EXTERNAL;
-    if (c->lay.pair_grid > 0) launch_pair(c->pa, c->lay.pair_grid, c->stream);
-    if (!external) {
+    if (c->lay.npt_grid) {
+        launch_pair_npt(c->pa, c->lay.pair_grid, c->stream);
+        launch_npt_a(c->na, NPT_EST, c->stream);
+    } else if (c->lay.pair_grid > 0) {
+        launch_pair(c->pa, c->lay.pair_grid, c->stream);
+    }
+    if (!external && !c->lay.npt_grid) {
         // external forces: the estimators wait for the caller's forces
         a.mode = FUSED_EST;
         launch_fused(a, c->lay.fused_grid, c->stream);
@@ -748,7 +812,13 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
         }
     }
     for (; left > 0; --left) enqueue_step(c);
-    if (c->lay.pair_grid > 0) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
+    if (c->lay.npt_grid) {
+        size_t e = prof_begin(c, PIMD_KERNEL_CLOSE);
+        launch_npt_a(c->na, NPT_CLOSE, c->stream);
+        prof_end(c, e);
+    } else if (c->lay.pair_grid > 0) {
+        enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
+    }
     // fixcom: the last step's centroid velocity is removed before the call ends
     if (c->fa.fixcom) launch_apply_ucom(c->fa, c->stream);
     return launch_error(c, "step launch");
@@ -815,8 +885,26 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
     out->overflow = h.overflow;
     out->n_rebuilds = h.n_rebuilds;
     out->rlist = h.rlist;
+    const bool baro = c->lay.npt_grid > 0;
+    out->volume = baro ? h.volume : 0.0;
+    out->vw = baro ? h.vw : 0.0;
+    out->enthalpy = baro ? h.enthalpy : 0.0;
     if (h.nonfinite) return fail(c, PIMD_ERR_NONFINITE, "non-finite position or velocity");
     if (h.overflow) return fail(c, PIMD_ERR_OVERFLOW, "neighbor list capacity exceeded");
+    return PIMD_OK;
+}
+
+int pimd_get_barostat(pimd_ctx *c, double *box, double *vw)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!c->lay.npt_grid) return fail(c, PIMD_ERR_UNSUPPORTED, "no barostat (ensemble is not NPT or NPH)");
+    if (!c->have_state) return fail(c, PIMD_ERR_STATE, "no state");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Ctl h;
+    HIP_TRY(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (box)
+        for (int d = 0; d < 3; ++d) box[d] = h.box[d];
+    if (vw) *vw = h.vw;
     return PIMD_OK;
 }
 
@@ -1129,6 +1217,7 @@ int pimd_batch_add(pimd_batch *b, const pimd_params *p, const double *mass, cons
     if (p->potential == PIMD_POT_EXTERNAL)
         return bfail(b, PIMD_ERR_UNSUPPORTED, "external forces are not batched (the caller steps each system)");
     if (p->fixcom) return bfail(b, PIMD_ERR_UNSUPPORTED, "fixcom is not batched");
+    if (is_npt(p)) return bfail(b, PIMD_ERR_UNSUPPORTED, "the barostat is not batched");
     pimd_ctx *c = nullptr;
     int rc = pimd_create(p, mass, topo, nullptr, 0, (void *)b->stream, &c);
     if (rc != PIMD_OK) return bfail(b, rc, pimd_last_error(nullptr));

@@ -64,6 +64,13 @@ struct Ctl {
     double ucom[3];            // fixcom: centroid-mode velocity to subtract from every atom
     int ucom_pending;          // 1: ucom is still to be subtracted
     int pad2;
+    // barostat (NpT, NpH): the box moves with v_W, so the passes read it here
+    double box[3];             // current box lengths
+    double box_build[3];       // box lengths at the last neighbor-list build
+    double vw;                 // barostat velocity v_W
+    double volume;             // V, K_W + U_W + J_W and the enthalpy at the estimator point
+    double ebaro;
+    double enthalpy;
 };
 
 // One atom of a centroid cell as the list build reads it: its centroid, its
@@ -154,6 +161,31 @@ struct PairArgs {
     int *cframe;              // [n_active] packed box offset of each atom in its cluster's frame
     int *cmode;               // [n_clusters] 0: cluster list, 1: per-atom lists (fallback)
 };
+
+// Barostat passes (pimd_npt.hip).  A step is: NPT_STEP pass A (pending
+// closing kick and O, estimators, opening O, the barostat's sums) -> its
+// finalize (the barostat's kicks and O steps) -> pass B (kick, A with the
+// centroid scaling, inverse transform) -> its finalize (box, rebuild) ->
+// forces in the new box.
+enum NptMode : int { NPT_STEP = 0, NPT_CLOSE = 1, NPT_EST = 2 };
+// per-block partials of pass A
+enum { NP_EKIN = 0, NP_ESPRING, NP_VIR, NP_K0, NP_K0A, NP_FVA, NP_F2, NP_K0B, NP_FVB, NP_BAD,
+       NP_COUNT };
+struct NptArgs {
+    FusedArgs f;              // the system (x, v, f, tables, control block, partials)
+    double *ft;               // [N][3][P] f~ of the current forces (pass A -> pass B)
+    double *part;             // [gridDim][NP_COUNT] pass A partials; pass B: [gridDim][3]
+    double dt;
+    double p_ext;
+    double wmass;             // W = 3 P N kB T tau_p^2
+    double bc1, bc2, bsig;    // v_W's O step over dt/2: c1, c2, sqrt(P kB T / W)
+    double kTP;               // P kB T
+};
+int npt_grid(int N, int P);
+void launch_npt_init(Ctl *ctl, const double box[3], hipStream_t s);
+void launch_npt_a(const NptArgs &a, int mode, hipStream_t s);
+void launch_npt_b(const NptArgs &a, hipStream_t s);
+void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s);
 
 // Launchers (pimd_kernels.hip).
 int fused_smem_bytes(int P);

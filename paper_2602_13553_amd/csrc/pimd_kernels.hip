@@ -899,6 +899,8 @@ __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, d
 // its neighbor list (entry q goes to sub-group q mod S) and their partial
 // forces are combined in sub-group order through shared memory; S > 1 only
 // when the system alone would leave the GPU with few waves to hide latency.
+// BOXDEV: the box lengths come from the control block (a barostat moves them)
+template <bool BOXDEV = false>
 __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, double *s_f)
 {
     const int P = a.P, S = a.S;
@@ -909,7 +911,9 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     const int sg = g / P, k = g - sg * P;   // sub-group, bead
     const int i = tile * A + la;
     const bool act = (la < A) && (i < a.N);
-    const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
+    const double L0 = BOXDEV ? a.ctl->box[0] : a.box[0];
+    const double L1 = BOXDEV ? a.ctl->box[1] : a.box[1];
+    const double L2 = BOXDEV ? a.ctl->box[2] : a.box[2];
     if (!a.ctl->ran) return;   // the system took no step (uniform per block)
 
     // A list cutoff that is not finite (non-finite positions) or that would
@@ -1533,6 +1537,22 @@ void set_pair_smem()
                               kClusterSmem);
     (void)hipFuncSetAttribute((const void *)k_pair_batch_clusters,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kClusterSmem);
+}
+
+// The force pass of a system under a barostat (per-atom lists, no cells).
+__global__ __launch_bounds__(kBlock) void k_pair_npt(PairArgs a)
+{
+    __shared__ int s_cnt[kBlock];
+    __shared__ double red[64];
+    __shared__ double s_f[kBlock * 3];
+    const int b = blockIdx.x, nA = a.n_active_tiles;
+    const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
+    pair_tile<true>(a, tile, s_cnt, red, s_f);
+}
+
+void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pair_npt, dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 void launch_pair(const PairArgs &a, int grid, hipStream_t s)

@@ -42,7 +42,7 @@ REAL_HBAR = _HBAR_SI * _NA / _KCAL * 1e15         # kcal/mol * fs
 REAL_MVV2E = _AMU * 1e10 * _NA / _KCAL            # kcal/mol per amu (A/fs)^2
 
 POT_NONE, POT_HARMONIC, POT_LJ, POT_WATER = 0, 1, 2, 3
-NVT, NVE = 0, 1
+NVT, NVE, NPT, NPH = 0, 1, 2, 3
 
 
 @dataclass
@@ -74,6 +74,8 @@ class SystemSpec:
     skin: float = 0.3               # neighbor-list skin (GPU library only)
     integrator: int = 0             # 0: BAOAB, 1: OBABO
     fixcom: int = 0                 # 1: remove the centroids' COM velocity every step
+    p_ext: float = 0.0              # NPT, NPH: target pressure
+    tau_p: float = 1.0              # NPT, NPH: barostat time
     lj_active: np.ndarray | None = None   # [N] 0/1
     bonds: np.ndarray | None = None       # [n_bonds][2]
     nsteps: int = 0                 # length of the workload's run

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpimd.so")
 PIMD_OK = 0
 ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PIMD_ERR_STATE",
           -5: "PIMD_ERR_NONFINITE", -6: "PIMD_ERR_UNSUPPORTED", -7: "PIMD_ERR_OVERFLOW"}
-PIMD_NVT, PIMD_NVE = 0, 1
+PIMD_NVT, PIMD_NVE, PIMD_NPT, PIMD_NPH = 0, 1, 2, 3
 PIMD_BAOAB, PIMD_OBABO = 0, 1
 PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER, PIMD_POT_EXTERNAL = 0, 1, 2, 3, 4
 PIMD_FLAG_VALU_TRANSFORMS = 1
@@ -35,7 +35,8 @@ def PIMD_PAIR_SUBGROUPS(S: int) -> int:
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv", "ppr", "pmd")
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
-            "pimd_get_estimators", "pimd_get_state", "pimd_reset_averages", "pimd_get_positions",
+            "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_reset_averages",
+            "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
             "pimd_last_error", "pimd_profile_begin", "pimd_profile_end", "pimd_get_launch_info",
             "pimd_batch_create", "pimd_batch_add", "pimd_batch_remove", "pimd_batch_set_state",
@@ -59,7 +60,7 @@ class pimd_params(C.Structure):
         ("lj_eps", C.c_double), ("lj_sigma", C.c_double), ("lj_rc", C.c_double),
         ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("nbr_capacity", C.c_int32), ("flags", C.c_int32), ("integrator", C.c_int32),
-        ("fixcom", C.c_int32),
+        ("fixcom", C.c_int32), ("p_ext", C.c_double), ("tau_p", C.c_double),
     ]
 
 
@@ -71,7 +72,8 @@ class pimd_topology(C.Structure):
 class pimd_estimators(C.Structure):
     _fields_ = [("step", C.c_uint64), ("value", C.c_double * NEST), ("count", C.c_uint64),
                 ("sum", C.c_double * NEST), ("sumsq", C.c_double * NEST), ("nonfinite", C.c_int32),
-                ("overflow", C.c_int32), ("n_rebuilds", C.c_uint64), ("rlist", C.c_double)]
+                ("overflow", C.c_int32), ("n_rebuilds", C.c_uint64), ("rlist", C.c_double),
+                ("volume", C.c_double), ("vw", C.c_double), ("enthalpy", C.c_double)]
 
 
 class pimd_profile(C.Structure):
@@ -107,6 +109,7 @@ def load() -> C.CDLL:
         lib.pimd_step.argtypes = [C.c_void_p, C.c_int64]
         lib.pimd_get_estimators.argtypes = [C.c_void_p, P(pimd_estimators)]
         lib.pimd_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_uint64)]
+        lib.pimd_get_barostat.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
         lib.pimd_set_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
@@ -152,6 +155,7 @@ def _estimators_dict(e) -> dict:
     out["sumsq"] = {n: e.sumsq[q] for q, n in enumerate(ESTIMATOR_NAMES)}
     out["nonfinite"], out["overflow"] = e.nonfinite, e.overflow
     out["n_rebuilds"], out["rlist"] = int(e.n_rebuilds), float(e.rlist)
+    out["volume"], out["vw"], out["enthalpy"] = float(e.volume), float(e.vw), float(e.enthalpy)
     return out
 
 
@@ -187,6 +191,8 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     p.skin, p.bond_k, p.bond_r0 = spec.skin, spec.bond_k, spec.bond_r0
     p.integrator = int(getattr(spec, "integrator", PIMD_BAOAB))
     p.fixcom = int(getattr(spec, "fixcom", 0))
+    p.p_ext = float(getattr(spec, "p_ext", 0.0))
+    p.tau_p = float(getattr(spec, "tau_p", 1.0))
     return p
 
 
@@ -263,6 +269,13 @@ class Context:
         s = C.c_uint64()
         self._check(self._lib.pimd_get_state(self._h, _dp(x), _dp(p), C.byref(s)), self._h)
         return x, p, int(s.value)
+
+    def barostat(self):
+        """NPT, NPH: the current box lengths and barostat velocity v_W."""
+        box = np.empty(3)
+        vw = C.c_double()
+        self._check(self._lib.pimd_get_barostat(self._h, _dp(box), C.byref(vw)), self._h)
+        return tuple(box.tolist()), float(vw.value)
 
     def profile_begin(self) -> None:
         self._check(self._lib.pimd_profile_begin(self._h), self._h)

@@ -136,3 +136,32 @@ def test_workload_generators():
     gaps = np.diff([j.arrival for j in tr])
     assert abs(gaps.mean() - 1 / 20) < 0.3 / 20
     assert all(j.n_atoms % 3 == 0 for j in tr if j.kind == "water")
+
+
+def test_barostat_validation_without_gpu():
+    """The barostat needs OBABO, a pair potential, no fixcom, tau_p > 0 and a
+    finite p_ext, and takes neither the matrix-core nor the cluster flags."""
+    lib = pimd.load()
+    spec = inputs.lj_liquid(n_atoms=32, n_beads=4)
+    mass = np.ascontiguousarray(spec.mass)
+    n = C.c_size_t()
+
+    def rc(**kw):
+        p = pimd.params_from_spec(spec)
+        p.ensemble, p.integrator, p.p_ext, p.tau_p = pimd.PIMD_NPT, pimd.PIMD_OBABO, 1.0, 0.5
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n))
+
+    assert rc() == 0
+    assert rc(ensemble=pimd.PIMD_NPH) == 0
+    assert rc(integrator=pimd.PIMD_BAOAB) == -6
+    assert rc(fixcom=1) == -6
+    assert rc(tau_p=0.0) == -1
+    assert rc(p_ext=float("nan")) == -1
+    assert rc(flags=pimd.PIMD_FLAG_MFMA_TRANSFORMS) == -6
+    assert rc(ensemble=4) == -1
+    h = pimd.params_from_spec(inputs.harmonic_tiny())
+    h.ensemble, h.integrator, h.tau_p = pimd.PIMD_NPT, pimd.PIMD_OBABO, 0.5
+    hm = np.ascontiguousarray(inputs.harmonic_tiny().mass)
+    assert lib.pimd_workspace_bytes(C.byref(h), pimd._dp(hm), None, C.byref(n)) == -6

@@ -1,0 +1,122 @@
+"""GPU parity of the BZP barostat (NPT, NPH) against the oracle's NpT step:
+positions, momenta, box, barostat velocity, the estimators and the enthalpy,
+on identical seeded inputs and noise streams, through the C ABI."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_13553_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _barostat(spec, ensemble, p_ext, tau_p):
+    spec.ensemble, spec.integrator, spec.p_ext, spec.tau_p = ensemble, 1, p_ext, tau_p
+    return spec
+
+
+def run_both(spec, chunks):
+    from paper_2602_13553_amd import pimd
+    n = sum(chunks)
+    _say("case %s ensemble=%d N=%d P=%d steps=%d" % (spec.name, spec.ensemble, spec.n_atoms,
+                                                      spec.n_beads, n))
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    for c in chunks:
+        ctx.step(c)
+    est = ctx.estimators()
+    gx, gp, gs = ctx.get_state()
+    box, vw = ctx.barostat()
+    ctx.close()
+    st = oracle.State.from_spec(spec)
+    st.step(n)
+    return (gx, gp, gs, est, box, vw), st
+
+
+def check(g, st, tol=TOL, est_tol=1e-10):
+    gx, gp, gs, gest, gbox, gvw = g
+    oest = st.estimators()
+    ob = st.baro_energies()
+    assert gs == int(st.step_count[0])
+    ex, ep = rel_err(gx, st.x), rel_err(gp, st.p)
+    W = oracle.lib().orc_baro_mass(oracle.C.byref(st.sys.cstruct()))
+    vscale = math.sqrt(st.sys.n_beads * st.sys.kB * st.sys.temp / W)
+    _say("  x rel %.3e  p rel %.3e  box %.12f / %.12f  vw %.6e / %.6e" %
+         (ex, ep, gbox[0], st.box[0], gvw, st.baro.vw))
+    assert ex <= tol and ep <= tol, (ex, ep)
+    assert abs(gbox[0] / st.box[0] - 1) <= tol
+    assert gbox[0] == gbox[1] == gbox[2]
+    assert abs(gvw - st.baro.vw) <= est_tol * max(abs(st.baro.vw), vscale)
+    scale = max(abs(oest["ekin"]), abs(oest["espring"]), abs(oest["epot"]))
+    for name in ("ekin", "espring", "epot", "etot", "kprim", "kcv"):
+        assert abs(gest[name] - oest[name]) <= est_tol * scale, (name, gest[name], oest[name])
+    for name in ("pcv", "ppr", "pmd"):
+        # the terms of each pressure are of the order of the energies over 3V
+        assert abs(gest[name] - oest[name]) <= est_tol * 10 * scale / ob["volume"], name
+    assert abs(gest["volume"] - ob["volume"]) <= tol * ob["volume"]
+    hscale = scale + abs(ob["uw"]) + abs(ob["jw"]) + abs(ob["kw"])
+    assert abs(gest["enthalpy"] - ob["enthalpy"]) <= est_tol * hscale
+    assert abs(gest["vw"] - st.baro.vw) <= est_tol * max(abs(st.baro.vw), vscale)
+
+
+@pytest.mark.parametrize("ensemble", [2, 3])
+def test_barostat_lj_matches_oracle(ensemble):
+    spec = _barostat(inputs.lj_liquid(n_atoms=256, n_beads=8, seed=41), ensemble, 2.0, 0.2)
+    g, st = run_both(spec, [1, 6, 3])
+    check(g, st)
+
+
+def test_barostat_water_matches_oracle():
+    w = inputs.water(n_atoms=384, n_beads=8, seed=42)
+    # pressure in kcal/mol/A^3 (about 3.5e4 bar, near the start's P_CV), 200 fs
+    spec = _barostat(w, 2, 0.5, 200.0)
+    g, st = run_both(spec, [2, 8])
+    check(g, st)
+
+
+def test_barostat_long_run_with_rebuilds():
+    """200 steps under a fast barostat: the box shrinks by ~9% and the lists
+    are rebuilt on the way; every bead pair inside rc must still be found
+    (the oracle sums all pairs)."""
+    spec = _barostat(inputs.lj_liquid(n_atoms=256, n_beads=4, seed=43), 2, 1.0, 0.1)
+    g, st = run_both(spec, [64, 64, 72])
+    _say("  rebuilds %d" % g[3]["n_rebuilds"])
+    assert g[3]["n_rebuilds"] >= 2
+    assert st.box[0] < 0.95 * spec.box[0]
+    check(g, st, tol=1e-9, est_tol=1e-8)
+
+
+def test_barostat_running_sums_and_get_barostat_errors():
+    from paper_2602_13553_amd import pimd
+    spec = _barostat(inputs.lj_liquid(n_atoms=108, n_beads=4, seed=44), 2, 1.0, 0.3)
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    ctx.step(5)
+    e = ctx.estimators()
+    ctx.close()
+    st = oracle.State.from_spec(spec)
+    acc = []
+    for _ in range(5):
+        st.step(1)
+        acc.append(st.estimators()["etot"])
+    assert e["count"] == 5
+    assert abs(e["sum"]["etot"] - sum(acc)) <= 1e-10 * max(abs(a) for a in acc) * 5
+    nvt = pimd.Context.from_spec(inputs.lj_liquid(n_atoms=108, n_beads=4, seed=44))
+    nvt.set_state(spec.x0, spec.v0, 0)
+    with pytest.raises(pimd.PimdError):
+        nvt.barostat()
+    nvt.close()
