@@ -110,7 +110,8 @@ typedef struct pimd_params {
  * beads' kick (App. E's h^2 and h^3 terms, from the momenta at the kick's
  * start).  Its O step: v_W <- c1 v_W + c2 sqrt(P kB T / W) z, c1 =
  * exp(-dt/(2 tau)), z the first Gaussian of counter (2^64 - 1, 0, step, q).
- * The box starts at params.box with v_W = 0 at every pimd_set_state. */
+ * pimd_set_state starts the box at params.box with v_W = 0, or at the values
+ * given to pimd_set_barostat before it (a restart). */
 
 /* fixcom = 1: at the end of every step (after the closing B, and OBABO's
  * second O) the mass-weighted mean u = sum_i m_i v~0_i / sum_i m_i of the
@@ -271,6 +272,14 @@ int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
  * (box[3], may be NULL) and the barostat velocity (vw, may be NULL).
  * Errors: STATE, UNSUPPORTED (no barostat), DEVICE. */
 int pimd_get_barostat(pimd_ctx *ctx, double *box, double *vw);
+
+/* NPT, NPH: the box lengths (box[3], all equal and > 0: the barostat is
+ * isotropic) and barostat velocity that the next pimd_set_state starts from,
+ * e.g. those pimd_get_barostat returned with the state being restored; the
+ * state's forces and estimators are then those of this box.  Host-side only
+ * (no device work).  Errors: ARG (bad box or non-finite vw), UNSUPPORTED (no
+ * barostat). */
+int pimd_set_barostat(pimd_ctx *ctx, const double *box, double vw);
 
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);

@@ -69,6 +69,8 @@ struct pimd_ctx {
     FusedArgs fa;
     PairArgs pa;
     NptArgs na;                     // the barostat's passes (NPT, NPH)
+    double start_box[3] = {0.0, 0.0, 0.0};   // the box and v_W the next set_state starts from
+    double start_vw = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_failed = false;
@@ -709,6 +711,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     q.cinfo = a.cinfo;
 
     if (L.npt_grid) {
+        for (int d = 0; d < 3; ++d) c->start_box[d] = p->box[d];
         NptArgs &b = c->na;
         b.f = c->fa;
         b.ft = (double *)(w + L.nft);
@@ -739,7 +742,7 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     // the device layout; PREP then turns v into v~ = M v in place (each tile
     // is staged in shared memory before it is overwritten).
     launch_ctl_init(c->d_ctl, (unsigned long long)step, c->stream);
-    if (c->lay.npt_grid) launch_npt_init(c->d_ctl, c->p.box, c->stream);
+    if (c->lay.npt_grid) launch_npt_init(c->d_ctl, c->start_box, c->start_vw, c->stream);
     HIP_TRY(c, hipMemcpyAsync(c->d_stage, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     launch_import(c->d_stage, c->d_x, c->d_orig, N, P, c->stream);
     HIP_TRY(c, hipMemcpyAsync(c->d_stage, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -905,6 +908,18 @@ int pimd_get_barostat(pimd_ctx *c, double *box, double *vw)
     if (box)
         for (int d = 0; d < 3; ++d) box[d] = h.box[d];
     if (vw) *vw = h.vw;
+    return PIMD_OK;
+}
+
+int pimd_set_barostat(pimd_ctx *c, const double *box, double vw)
+{
+    if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
+    if (!c->lay.npt_grid) return fail(c, PIMD_ERR_UNSUPPORTED, "no barostat (ensemble is not NPT or NPH)");
+    if (!box || !finite_pos(box[0]) || box[1] != box[0] || box[2] != box[0])
+        return fail(c, PIMD_ERR_ARG, "box must hold three equal lengths > 0");
+    if (!std::isfinite(vw)) return fail(c, PIMD_ERR_ARG, "vw must be finite");
+    for (int d = 0; d < 3; ++d) c->start_box[d] = box[d];
+    c->start_vw = vw;
     return PIMD_OK;
 }
 

@@ -182,7 +182,7 @@ struct NptArgs {
     double kTP;               // P kB T
 };
 int npt_grid(int N, int P);
-void launch_npt_init(Ctl *ctl, const double box[3], hipStream_t s);
+void launch_npt_init(Ctl *ctl, const double box[3], double vw, hipStream_t s);
 void launch_npt_a(const NptArgs &a, int mode, hipStream_t s);
 void launch_npt_b(const NptArgs &a, hipStream_t s);
 void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s);

@@ -383,22 +383,22 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
     c->ran = 1;
 }
 
-__global__ void k_npt_init(Ctl *c, double b0, double b1, double b2)
+__global__ void k_npt_init(Ctl *c, double b0, double b1, double b2, double vw)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->box[0] = c->box_build[0] = b0;
         c->box[1] = c->box_build[1] = b1;
         c->box[2] = c->box_build[2] = b2;
-        c->vw = 0.0;
+        c->vw = vw;
         c->volume = b0 * b1 * b2;
         c->ebaro = 0.0;
         c->enthalpy = 0.0;
     }
 }
 
-void launch_npt_init(Ctl *ctl, const double box[3], hipStream_t s)
+void launch_npt_init(Ctl *ctl, const double box[3], double vw, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_npt_init, dim3(1), dim3(64), 0, s, ctl, box[0], box[1], box[2]);
+    hipLaunchKernelGGL(k_npt_init, dim3(1), dim3(64), 0, s, ctl, box[0], box[1], box[2], vw);
 }
 
 void launch_npt_a(const NptArgs &a, int mode, hipStream_t s)

@@ -35,7 +35,8 @@ def PIMD_PAIR_SUBGROUPS(S: int) -> int:
 ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "pcv", "ppr", "pmd")
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
-            "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_reset_averages",
+            "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_set_barostat",
+            "pimd_reset_averages",
             "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
             "pimd_last_error", "pimd_profile_begin", "pimd_profile_end", "pimd_get_launch_info",
@@ -110,6 +111,7 @@ def load() -> C.CDLL:
         lib.pimd_get_estimators.argtypes = [C.c_void_p, P(pimd_estimators)]
         lib.pimd_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_uint64)]
         lib.pimd_get_barostat.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+        lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), C.c_double]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
         lib.pimd_set_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
@@ -276,6 +278,11 @@ class Context:
         vw = C.c_double()
         self._check(self._lib.pimd_get_barostat(self._h, _dp(box), C.byref(vw)), self._h)
         return tuple(box.tolist()), float(vw.value)
+
+    def set_barostat(self, box, vw: float) -> None:
+        """NPT, NPH: the box and v_W that the next set_state starts from."""
+        b = np.ascontiguousarray(box, dtype=np.float64)
+        self._check(self._lib.pimd_set_barostat(self._h, _dp(b), float(vw)), self._h)
 
     def profile_begin(self) -> None:
         self._check(self._lib.pimd_profile_begin(self._h), self._h)

@@ -120,3 +120,37 @@ def test_barostat_running_sums_and_get_barostat_errors():
     with pytest.raises(pimd.PimdError):
         nvt.barostat()
     nvt.close()
+
+
+def test_barostat_checkpoint_restart():
+    """20 steps in one go equal 10 steps, a checkpoint (state, box, v_W) and
+    10 more steps in a new context."""
+    from paper_2602_13553_amd import pimd
+    spec = _barostat(inputs.lj_liquid(n_atoms=256, n_beads=8, seed=45), 2, 1.0, 0.2)
+    a = pimd.Context.from_spec(spec)
+    a.set_state(spec.x0, spec.v0, 0)
+    a.step(20)
+    xa, pa, sa = a.get_state()
+    boxa, vwa = a.barostat()
+    a.close()
+    b = pimd.Context.from_spec(spec)
+    b.set_state(spec.x0, spec.v0, 0)
+    b.step(10)
+    x, p, s = b.get_state()
+    box, vw = b.barostat()
+    b.close()
+    c = pimd.Context.from_spec(spec)
+    c.set_barostat(box, vw)
+    c.set_state(x, p / spec.mass[None, :, None], s)
+    c.step(10)
+    xc, pc, sc = c.get_state()
+    boxc, vwc = c.barostat()
+    with pytest.raises(pimd.PimdError):
+        c.set_barostat((1.0, 2.0, 1.0), 0.0)
+    c.close()
+    _say("  restart x rel %.3e p rel %.3e box %.3e vw %.3e" % (
+        rel_err(xc, xa), rel_err(pc, pa), abs(boxc[0] / boxa[0] - 1), abs(vwc - vwa)))
+    assert sc == sa == 20
+    assert rel_err(xc, xa) <= TOL and rel_err(pc, pa) <= 1e-11
+    assert abs(boxc[0] / boxa[0] - 1) <= TOL
+    assert abs(vwc - vwa) <= 1e-10 * max(abs(vwa), 1e-3)
