@@ -11,7 +11,9 @@
  *     (OBABO, the splitting of the paper's example input: Sec. III.C)
  *   - PILE-L O step and damping times: App. D, Eqs. D1-D2
  *   - unwrapped coordinates for transforms and estimators: Sec. IV.B
- *   - estimators K, S, U, H, K_PR, K_CV: App. A, Eqs. A4, A5, A7
+ *   - estimators K, S, U, H, K_PR, K_CV: App. A, Eqs. A4, A5, A7; the
+ *     pressures P_CV, P_PR, P_MD and the barostat's enthalpy: App. A
+ *   - isotropic BZP barostat (NpT, NpH): Sec. IV.A, App. E
  *
  * Conventions for every entry point:
  *   - Return 0 (PIMD_OK) or a negative PIMD_ERR_* code.  On error, out

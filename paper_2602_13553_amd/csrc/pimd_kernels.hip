@@ -10,7 +10,10 @@
 //            (The matrix-core variant is k_fused_mfma, pimd_fused_mfma.hip.)
 // k_pair   : bead-batched short-range forces for all P replicas in one
 //            launch (LJ among active atoms + harmonic bonds), each atom's
-//            neighbor list rebuilt from the centroid cells when requested.
+//            neighbor list rebuilt from the centroid cells when requested;
+//            per block, the energy and the cell virial (the pressures of
+//            App. A).  k_pair_npt: the same with the box from the control
+//            block (the barostat's passes are in pimd_npt.hip).
 // k_finalize: one block after the step pass; combines the per-block partials
 //            in block order (deterministic), records estimators and running
 //            sums, advances the step counter, decides list rebuilds and, at

@@ -80,10 +80,17 @@ def test_barostat_lj_matches_oracle(ensemble):
     check(g, st)
 
 
-def test_barostat_water_matches_oracle():
-    w = inputs.water(n_atoms=384, n_beads=8, seed=42)
-    # pressure in kcal/mol/A^3 (about 3.5e4 bar, near the start's P_CV), 200 fs
-    spec = _barostat(w, 2, 0.5, 200.0)
+@pytest.mark.parametrize("case", ["p8_high_pressure", "paper_example"])
+def test_barostat_water_matches_oracle(case):
+    """Water-shaped N = 384: at P = 8 under 0.5 kcal/mol/A^3 (about 3.5e4 bar,
+    near the start's P_CV) with tau_p = 200 fs; and in the shape of the
+    paper's NpT example: 128 molecules, P = 32, 300 K, 1 bar, dt 0.5 fs,
+    PILE-L tau 100 fs, tau_p 500 fs."""
+    if case == "p8_high_pressure":
+        spec = _barostat(inputs.water(n_atoms=384, n_beads=8, seed=42), 2, 0.5, 200.0)
+    else:
+        spec = _barostat(inputs.water(n_atoms=384, n_beads=32, seed=46, dt=0.5, tau=100.0), 2,
+                         1.0 / 69476.95, 500.0)
     g, st = run_both(spec, [2, 8])
     check(g, st)
 
