@@ -161,3 +161,42 @@ def test_barostat_checkpoint_restart():
     assert rel_err(xc, xa) <= TOL and rel_err(pc, pa) <= 1e-11
     assert abs(boxc[0] / boxa[0] - 1) <= TOL
     assert abs(vwc - vwa) <= 1e-10 * max(abs(vwa), 1e-3)
+
+
+def test_barostat_full_size_nph_conserves_the_enthalpy():
+    """The LJ liquid at full size (N = 4000, P = 32), where the oracle cannot
+    follow: in NpH the enthalpy H + K_W + U_W + J_W is a constant of the
+    motion, so its spread must fall about fourfold when dt halves (measured:
+    3.0 from dt = 0.002 to 0.001, 4.0 from 0.001 to 0.0005, over one time
+    unit), and stay within a few times the NVE energy's spread at the same
+    dt (measured: 3.0 times), while the volume moves by ~40%.  rc = 3 keeps
+    the force's jump at the cutoff small."""
+    from paper_2602_13553_amd import pimd
+
+    def run(dt, ensemble, t_total=1.0):
+        spec = inputs.lj_liquid(seed=47)
+        spec.lj_rc, spec.dt = 3.0, dt
+        if ensemble == 3:
+            spec = _barostat(spec, 3, 1.0, 0.5)
+        else:
+            spec.ensemble, spec.integrator = 1, 1
+        ctx = pimd.Context.from_spec(spec)
+        ctx.set_state(spec.x0, spec.v0, 0)
+        h, v = [], []
+        n = int(round(t_total / dt))
+        for _ in range(n // 20):
+            ctx.step(20)
+            e = ctx.estimators()
+            h.append(e["enthalpy"] if ensemble == 3 else e["etot"])
+            v.append(e["volume"])
+        ctx.close()
+        return np.ptp(h), (max(v) / min(v) if ensemble == 3 else 1.0)
+
+    h1, vr = run(0.001, 3)
+    h2, _ = run(0.0005, 3)
+    e2, _ = run(0.0005, 1)
+    _say("  enthalpy spread dt=0.001: %.4e  dt=0.0005: %.4e  NVE: %.4e  V ratio %.3f" %
+         (h1, h2, e2, vr))
+    assert vr > 1.2
+    assert 3.0 < h1 / h2 < 5.0
+    assert h2 < 5.0 * e2
