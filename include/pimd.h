@@ -97,7 +97,9 @@ typedef struct pimd_params {
     int32_t integrator;   /* PIMD_BAOAB (0) or PIMD_OBABO (1) */
     int32_t fixcom;       /* 1: remove the centroids' center-of-mass velocity at the end
                              of every step (Sec. III.C's fixcom keyword); not in a batch */
-    double p_ext;         /* NPT, NPH: target pressure, energy per volume (finite) */
+    double p_ext;         /* NPT, NPH: target pressure, energy per volume (finite); the
+                             default neighbor capacity allows twice the starting density
+                             (set nbr_capacity for more) */
     double tau_p;         /* NPT, NPH: barostat time > 0; mass W = 3 P N kB T tau_p^2 */
 } pimd_params;
 

@@ -223,7 +223,8 @@ int neighbor_capacity(const pimd_params *p, const double *mass, const std::vecto
     const double r = p->lj_rc + p->skin + 2.0 * e_guess;
     const double vol = p->box[0] * p->box[1] * p->box[2];
     const double nb = (double)n_active / vol * (4.0 / 3.0) * M_PI * r * r * r;
-    return (int)std::ceil(1.4 * nb) + 32;
+    // a barostat may compress the box: room for twice the starting density
+    return (int)std::ceil((is_npt(p) ? 2.8 : 1.4) * nb) + 32;
 }
 
 // Centroid cells of width >= the expected list cutoff rc + skin + 2 E, so that
