@@ -80,6 +80,15 @@ def test_barostat_lj_matches_oracle(ensemble):
     check(g, st)
 
 
+@pytest.mark.parametrize("N,P", [(97, 3), (130, 6), (64, 1)])
+def test_barostat_ragged_and_odd(N, P):
+    """Bead counts that do not divide the block (ragged last tiles), and
+    P = 1 (the classical NpT of the centroids alone)."""
+    spec = _barostat(inputs.lj_liquid(n_atoms=N, n_beads=P, seed=48 + P), 2, 1.0, 0.3)
+    g, st = run_both(spec, [3, 7])
+    check(g, st)
+
+
 @pytest.mark.parametrize("case", ["p8_high_pressure", "paper_example"])
 def test_barostat_water_matches_oracle(case):
     """Water-shaped N = 384: at P = 8 under 0.5 kcal/mol/A^3 (about 3.5e4 bar,
