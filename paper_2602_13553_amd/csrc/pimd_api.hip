@@ -236,9 +236,13 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
     L.ncell = 0;
     L.cell_cap = 0;
     L.nc[0] = L.nc[1] = L.nc[2] = 0;
-    // the barostat moves the box, and with it the cell grid: all-pairs scans
-    if (!is_pair(p->potential) || n_active == 0 || is_npt(p)) return;
-    const double w = p->lj_rc + p->skin + 2.0 * e_guess;
+    if (!is_pair(p->potential) || n_active == 0) return;
+    // Under a barostat the grid keeps its cell count while the box moves:
+    // cells 25% wider than the cutoff leave room for the box to shrink (a
+    // rebuild whose stencil no longer fits falls back to the all-pairs scan),
+    // and the cell capacity allows twice the starting density.
+    const bool npt = is_npt(p);
+    const double w = (p->lj_rc + p->skin + 2.0 * e_guess) * (npt ? 1.25 : 1.0);
     long long ncell = 1;
     int nc[3];
     for (int d = 0; d < 3; ++d) {
@@ -249,7 +253,7 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
     }
     if (ncell > 8LL * n_active + 64) return;
     const double mean = (double)n_active / (double)ncell;
-    const int cap = ((int)std::ceil(2.0 * mean) + 16 + 3) & ~3;   // rows of whole int4
+    const int cap = ((int)std::ceil((npt ? 4.0 : 2.0) * mean) + 16 + 3) & ~3;   // rows of whole int4
     if (cap > kCellCapMax || ncell > kMaxCells) return;
     L.ncell = (int)ncell;
     L.cell_cap = cap;
@@ -751,6 +755,9 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     FusedArgs a = c->fa;
     a.vin = c->d_v;
     a.mode = FUSED_PREP;
+    // a barostat's box may differ from params.box (pimd_set_barostat): its
+    // first lists come from the all-pairs scan, its cells from later rebuilds
+    if (c->lay.npt_grid) a.ncell = 0;
     launch_fused(a, c->lay.fused_grid, c->stream);
     launch_finalize(a, c->lay.fused_grid, c->stream);
     const bool external = c->p.potential == PIMD_POT_EXTERNAL;

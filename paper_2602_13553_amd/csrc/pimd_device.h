@@ -180,16 +180,18 @@ __device__ inline void block_sum(double (&v)[NV], double *red /* >= NV * kBlock/
 // Non-finite centroids land in a clamped (valid) cell; the non-finite flag of
 // the step catches them.  Every atom's (cell, box index) pair places it within
 // rounding of its centroid, which the list build's stencil margin absorbs.
-__device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
+// box, icw: the box lengths and cells per unit length to bin in.
+__device__ inline int cell_of_in(const FusedArgs &a, int ia, const double c[3], const double *box,
+                                 const double *icw)
 {
     int cc[3], nb[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double L = a.box[d];
+        const double L = box[d];
         const double fl = floor(c[d] / L);
         const double w = c[d] - L * fl;
         // w may round to L itself: the centroid then lies at the top of box fl
-        int q = (w < L) ? (w >= 0.0 ? (int)(w * a.icw[d]) : 0) : a.nc[d] - 1;
+        int q = (w < L) ? (w >= 0.0 ? (int)(w * icw[d]) : 0) : a.nc[d] - 1;
         q = q < 0 ? 0 : (q >= a.nc[d] ? a.nc[d] - 1 : q);
         cc[d] = q;
         nb[d] = (fl > -1e6 && fl < 1e6) ? (int)fl : 0;
@@ -198,6 +200,136 @@ __device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
     a.cinfo[ia] = make_int4(cell, nb[0], nb[1], nb[2]);
     return cell;
 }
+
+__device__ inline int cell_of(const FusedArgs &a, int ia, const double c[3])
+{
+    return cell_of_in(a, ia, c, a.box, a.icw);
+}
+// At a rebuild, builds the centroid cell lists from the cells recorded by
+// the step pass, each cell's atoms in increasing index order, without a sort:
+// wave w takes the contiguous atom range [w*na/4, (w+1)*na/4) in chunks of 64
+// in index order.  A first pass counts, per wave, the atoms of each cell; the
+// place of wave w's atoms in cell q starts after the atoms of waves < w.  The
+// second pass places each atom at its wave's running offset in its cell plus
+// its rank among the lower lanes of its chunk that share the cell (groups of
+// equal cells from one ballot per cell-index bit), and writes its entry with
+// its centroid and box indices.  Decides whether the cells can serve this
+// rebuild: no cell over capacity, and a stencil of 2R+1 cells per dim that
+// does not wrap onto itself.  One block; no atomics.
+// lanes of the wave whose value of q equals this lane's (ok lanes only)
+__device__ __forceinline__ unsigned long long same_cell_lanes(bool ok, int q, int nbits)
+{
+    unsigned long long same = __ballot(ok);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = ((q >> b) & 1) != 0;
+        const unsigned long long m = __ballot(ok && bit);
+        same &= bit ? m : ~m;
+    }
+    return same;
+}
+
+// icw: cells per unit length of the box the centroids were binned in.
+__device__ inline void cells_finalize(const FusedArgs &a, const double *icw, double rlist,
+                                      int *scnt /* [4][ncell] */, int *sflag)
+{
+    static_assert(kBlock == 256, "four waves split the atoms");
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int ncell = a.ncell, cap = a.cell_cap, na = a.n_active;
+    Ctl *c = a.ctl;
+    for (int q = t; q < 4 * ncell; q += kBlock) scnt[q] = 0;
+    if (t == 0) sflag[0] = 0;
+    int nbits = 0;
+    while ((1 << nbits) < ncell) ++nbits;
+    const int per = (na + 3) / 4;
+    const int lo = min(na, w * per), hi = min(na, lo + per);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int *mine = scnt + w * ncell;
+    __syncthreads();
+    // pass 1: per-wave counts (the lowest lane of each equal-cell group adds
+    // the group's size; the groups of one chunk have distinct cells)
+    constexpr int U = 16;
+    for (int i0 = lo; i0 < hi; i0 += 64 * U) {
+        int qv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * 64 + lane;
+            qv[u] = i < hi ? a.cinfo[i].x : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * 64 >= hi) break;                    // uniform over the wave
+            const bool ok = qv[u] >= 0;
+            const unsigned long long same = same_cell_lanes(ok, qv[u], nbits);
+            if (ok && (same & below) == 0) mine[qv[u]] += __popcll(same);
+        }
+    }
+    __syncthreads();
+    // offsets of each wave in each cell, totals, capacity
+    for (int q = t; q < ncell; q += kBlock) {
+        int o = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int v = scnt[u * ncell + q];
+            scnt[u * ncell + q] = o;
+            o += v;
+        }
+        a.cell_scnt[q] = o;
+        if (o > cap) sflag[0] = 1;
+    }
+    __syncthreads();
+    bool ok_all = sflag[0] == 0;
+    int R[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // a relative margin covers centroids placed within rounding of a cell face
+        const double rr = rlist * icw[d] * (1.0 + 1e-12);
+        if (rr > 0.0 && rr <= 0.5 * (double)(a.nc[d] - 1))
+            R[d] = (int)ceil(rr);
+        else
+            ok_all = false;
+        if (2 * R[d] + 1 > a.nc[d]) ok_all = false;
+    }
+    if (ok_all) {
+        // pass 2: placement in index order, entries written directly
+        constexpr int V = 8;
+        for (int i0 = lo; i0 < hi; i0 += 64 * V) {
+            int4 ci[V];
+            double cx[V], cy[V], cz[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const int i = i0 + u * 64 + lane;
+                const int ii = i < hi ? i : lo;
+                ci[u] = i < hi ? a.cinfo[ii] : make_int4(-1, 0, 0, 0);
+                cx[u] = a.cent[ii * 3]; cy[u] = a.cent[ii * 3 + 1]; cz[u] = a.cent[ii * 3 + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                if (i0 + u * 64 >= hi) break;                // uniform over the wave
+                const int q = ci[u].x;
+                const bool ok = q >= 0;
+                const unsigned long long same = same_cell_lanes(ok, q, nbits);
+                if (ok) {
+                    const int slot = mine[q] + __popcll(same & below);
+                    CellEntry ce;
+                    ce.c[0] = cx[u]; ce.c[1] = cy[u]; ce.c[2] = cz[u];
+                    ce.j = i0 + u * 64 + lane;
+                    ce.nb[0] = ci[u].y; ce.nb[1] = ci[u].z; ce.nb[2] = ci[u].w;
+                    ce.pad = 0;
+                    a.cell_ent[(size_t)q * cap + slot] = ce;
+                }
+                // every lane has read its offset before the group's leader moves it
+                if (ok && (same & below) == 0) mine[q] += __popcll(same);
+            }
+        }
+    }
+    if (t == 0) {
+        c->cell_ok = ok_all ? 1 : 0;
+        c->cell_R[0] = R[0];
+        c->cell_R[1] = R[1];
+        c->cell_R[2] = R[2];
+    }
+}
+
 
 // Sums of NS values and maxima of NM values in one exchange (one barrier).
 // The caller passes a barrier before red is written again.

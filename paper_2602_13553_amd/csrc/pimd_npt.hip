@@ -322,7 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
         if (k == 0) {
             // displacement from the last build's centroid carried along by the
             // box scaling since that build
-            const double g = a.ctl->box[0] * exp(na.dt * vw) / a.ctl->box_build[0];
+            const double s = exp(na.dt * vw);
+            const double g = a.ctl->box[0] * s / a.ctl->box_build[0];
             double d2 = 0.0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -331,6 +332,16 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
                 d2 += dd * dd;
             }
             if (active != 0.0) m3[0] = d2;
+            if (a.ncell > 0 && i < a.n_active) {
+                // the centroid's cell in the box after this step's scaling
+                double bn[3], icw[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    bn[d] = a.ctl->box[d] * s;
+                    icw[d] = (double)a.nc[d] / bn[d];
+                }
+                (void)cell_of_in(a, i, c, bn, icw);
+            }
         }
     }
     block_maxv<3>(m3, red);
@@ -352,6 +363,9 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
     const FusedArgs &a = na.f;
     Ctl *c = a.ctl;
     __shared__ double red[64];
+    __shared__ __align__(16) int sbuf[4 * kMaxCells];
+    __shared__ int sflag[1];
+    __shared__ double s_dec[5];   // rebuild flag, r_list, new box
     const int t = threadIdx.x;
     double m3[3] = {0.0, 0.0, 0.0};
     for (int b = t; b < nblocks; b += kBlock) {
@@ -359,28 +373,44 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
         for (int q = 0; q < 3; ++q) m3[q] = fmax(m3[q], na.part[(size_t)b * 3 + q]);
     }
     block_maxv<3>(m3, red);
-    if (t != 0) return;
-    const double s = exp(na.dt * c->vw);
+    if (t == 0) {
+        const double s = exp(na.dt * c->vw);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) c->box[d] *= s;
-    c->step = c->step + 1;
-    c->synced = 0;
-    if (c->budget > 0) c->budget = c->budget - 1;
-    const double dmax = sqrt(m3[0]), emax = sqrt(m3[1]);
-    const double g = c->box[0] / c->box_build[0];
-    const bool rebuild = a.rc + 2.0 * (emax + dmax) > g * c->rlist;
-    if (rebuild) {
-        c->rebuild = 1;
-        c->ebuild = emax;
-        c->rlist = a.rc + a.skin + 2.0 * emax;
-        c->n_rebuilds = c->n_rebuilds + 1;
+        for (int d = 0; d < 3; ++d) c->box[d] *= s;
+        c->step = c->step + 1;
+        c->synced = 0;
+        if (c->budget > 0) c->budget = c->budget - 1;
+        const double dmax = sqrt(m3[0]), emax = sqrt(m3[1]);
+        const double g = c->box[0] / c->box_build[0];
+        const bool rebuild = a.rc + 2.0 * (emax + dmax) > g * c->rlist;
+        const double rl = a.rc + a.skin + 2.0 * emax;
+        if (rebuild) {
+            c->rebuild = 1;
+            c->ebuild = emax;
+            c->rlist = rl;
+            c->n_rebuilds = c->n_rebuilds + 1;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) c->box_build[d] = c->box[d];
-    } else {
-        c->rebuild = 0;
+            for (int d = 0; d < 3; ++d) c->box_build[d] = c->box[d];
+        } else {
+            c->rebuild = 0;
+        }
+        if (m3[2] != 0.0) c->nonfinite = 1;
+        c->ran = 1;
+        s_dec[0] = rebuild ? 1.0 : 0.0;
+        s_dec[1] = rl;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s_dec[2 + d] = c->box[d];
     }
-    if (m3[2] != 0.0) c->nonfinite = 1;
-    c->ran = 1;
+    // the centroid cell lists of a rebuild, binned in the new box by pass B
+    if (a.ncell > 0) {
+        __syncthreads();
+        if (s_dec[0] != 0.0) {
+            double icw[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) icw[d] = (double)a.nc[d] / s_dec[2 + d];
+            cells_finalize(a, icw, s_dec[1], sbuf, sflag);
+        }
+    }
 }
 
 __global__ void k_npt_init(Ctl *c, double b0, double b1, double b2, double vw)
