@@ -1417,7 +1417,8 @@ void set_pair_smem()
                               hipFuncAttributeMaxDynamicSharedMemorySize, kClusterSmem);
 }
 
-// The force pass of a system under a barostat (per-atom lists, no cells).
+// The force pass of a system under a barostat (per-atom lists; cells binned
+// in the moving box).
 __global__ __launch_bounds__(kBlock) void k_pair_npt(PairArgs a)
 {
     __shared__ int s_cnt[kBlock];
