@@ -97,6 +97,8 @@ def lib():
             "orc_baro_centroid_flow": (None, [C.c_double, C.c_double, d, d]),
             "orc_npt_step": (None, [S, C.POINTER(_Baro), d, d, d, d, u64, C.c_int32]),
             "orc_baro_energies": (None, [S, C.POINTER(_Baro), C.c_double, d]),
+            "orc_boson_spring": (C.c_double, [C.c_int32, C.c_int32, C.c_double, C.c_double, d, d,
+                                              d]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -144,6 +146,18 @@ def philox4x64_10(ctr, key) -> list[int]:
     o = (C.c_uint64 * 4)()
     lib().orc_philox4x64_10(c, k, o)
     return [int(v) for v in o]
+
+
+def boson_spring(x: np.ndarray, kspring: float, beta_n: float):
+    """Bosonic exchange spring energy V_B of bead positions x [P][N][3], its
+    forces -dV_B/dx and the link probabilities [N][N] (l's last bead to l''s
+    first)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    P, N, _ = x.shape
+    f = np.zeros_like(x)
+    prob = np.zeros((N, N))
+    v = lib().orc_boson_spring(N, P, kspring, beta_n, _dp(x), _dp(f), _dp(prob))
+    return v, f, prob
 
 
 def gaussians(seed: int, tag: int, i: int, k: int, s: int, q: int = 0) -> np.ndarray:

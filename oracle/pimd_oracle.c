@@ -871,3 +871,99 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
     out[3] = jw;
     out[4] = etot + kw + uw + jw;
 }
+
+/* ------------------------------------------------------------------------
+ * Bosonic exchange: the recursion over the cycle containing the last
+ * particle, and its gradient by reverse accumulation through the same
+ * recursion (each V[n] is a soft minimum of E[n,k] + V[n-k] with weights
+ * w[n,k] = exp(-beta_n (E[n,k] + V[n-k] - V[n])) / n summing to one).
+ * Plain O(N^3 P): every E[n,k] is summed out, no prefix sums.
+ * --------------------------------------------------------------------- */
+static double orc_sq3(const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) s += (a[d] - b[d]) * (a[d] - b[d]);
+    return s;
+}
+
+double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
+                        double *f, double *prob)
+{
+    /* bead j of particle l (0-based) at x + (j*N + l)*3 */
+#define XB(j, l) (x + ((size_t)(j) * N + (l)) * 3)
+    double *eint = (double *)calloc((size_t)N, sizeof(double));
+    double *link = (double *)calloc((size_t)N * N, sizeof(double));   /* [l][l'] */
+    double *E = (double *)calloc((size_t)(N + 1) * (N + 1), sizeof(double));   /* E[n][k] */
+    double *V = (double *)calloc((size_t)(N + 1), sizeof(double));
+    double *w = (double *)calloc((size_t)(N + 1) * (N + 1), sizeof(double));
+    double *adj = (double *)calloc((size_t)(N + 1), sizeof(double));
+    double *pl = (double *)calloc((size_t)N * N, sizeof(double));
+    for (int32_t l = 0; l < N; ++l)
+        for (int32_t j = 0; j + 1 < P; ++j) eint[l] += kspring * orc_sq3(XB(j + 1, l), XB(j, l));
+    for (int32_t l = 0; l < N; ++l)
+        for (int32_t l2 = 0; l2 < N; ++l2) link[(size_t)l * N + l2] = kspring * orc_sq3(XB(0, l2), XB(P - 1, l));
+    /* E[n][k]: ring through particles n-k .. n-1 (0-based), in order, closed
+     * from n-1 back to n-k */
+    for (int32_t n = 1; n <= N; ++n)
+        for (int32_t k = 1; k <= n; ++k) {
+            double e = 0.0;
+            for (int32_t l = n - k; l < n; ++l) e += eint[l];
+            for (int32_t l = n - k; l + 1 < n; ++l) e += link[(size_t)l * N + l + 1];
+            e += link[(size_t)(n - 1) * N + (n - k)];
+            E[(size_t)n * (N + 1) + k] = e;
+        }
+    V[0] = 0.0;
+    for (int32_t n = 1; n <= N; ++n) {
+        double lo = INFINITY;
+        for (int32_t k = 1; k <= n; ++k) {
+            const double a = E[(size_t)n * (N + 1) + k] + V[n - k];
+            if (a < lo) lo = a;
+        }
+        double s = 0.0;
+        for (int32_t k = 1; k <= n; ++k)
+            s += exp(-beta_n * (E[(size_t)n * (N + 1) + k] + V[n - k] - lo));
+        V[n] = lo - log(s / (double)n) / beta_n;
+        for (int32_t k = 1; k <= n; ++k)
+            w[(size_t)n * (N + 1) + k] =
+                exp(-beta_n * (E[(size_t)n * (N + 1) + k] + V[n - k] - V[n])) / (double)n;
+    }
+    /* adjoints: adj[n] = dV[N]/dV[n]; dV[N]/dE[n][k] = adj[n] w[n][k] */
+    adj[N] = 1.0;
+    for (int32_t n = N; n >= 1; --n)
+        for (int32_t k = 1; k <= n; ++k) adj[n - k] += adj[n] * w[(size_t)n * (N + 1) + k];
+    /* link probabilities: the weight every E[n][k] gives each of its links */
+    for (int32_t n = 1; n <= N; ++n)
+        for (int32_t k = 1; k <= n; ++k) {
+            const double q = adj[n] * w[(size_t)n * (N + 1) + k];
+            for (int32_t l = n - k; l + 1 < n; ++l) pl[(size_t)l * N + l + 1] += q;
+            pl[(size_t)(n - 1) * N + (n - k)] += q;
+        }
+    if (prob)
+        for (size_t e = 0; e < (size_t)N * N; ++e) prob[e] = pl[e];
+    if (f) {
+        for (size_t e = 0; e < (size_t)P * N * 3; ++e) f[e] = 0.0;
+        /* springs inside every ring: weight one (each particle lies on one cycle) */
+        for (int32_t l = 0; l < N; ++l)
+            for (int32_t j = 0; j + 1 < P; ++j)
+                for (int d = 0; d < 3; ++d) {
+                    const double g = 2.0 * kspring * (XB(j + 1, l)[d] - XB(j, l)[d]);
+                    f[((size_t)(j + 1) * N + l) * 3 + d] -= g;
+                    f[((size_t)j * N + l) * 3 + d] += g;
+                }
+        /* links, weighted by their probabilities */
+        for (int32_t l = 0; l < N; ++l)
+            for (int32_t l2 = 0; l2 < N; ++l2) {
+                const double q = pl[(size_t)l * N + l2];
+                if (q == 0.0) continue;
+                for (int d = 0; d < 3; ++d) {
+                    const double g = 2.0 * kspring * q * (XB(0, l2)[d] - XB(P - 1, l)[d]);
+                    f[((size_t)0 * N + l2) * 3 + d] -= g;
+                    f[((size_t)(P - 1) * N + l) * 3 + d] += g;
+                }
+            }
+    }
+    const double vb = V[N];
+    free(eint); free(link); free(E); free(V); free(w); free(adj); free(pl);
+#undef XB
+    return vb;
+}

@@ -153,6 +153,25 @@ void orc_npt_step(const orc_system *sys, orc_baro *b, double *x, double *vt, dou
  * enthalpy H + K_W + U_W + J_W with H = etot. */
 void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, double out[5]);
 
+/* --- bosonic exchange (Sec. III.C's fix pimd/langevin/bosonic; the
+ * exchange potential of Hirshberg et al. 2019 as evaluated in quadratic time by
+ * Feldman and Hirshberg 2023, both cited by the paper) ----------------------
+ * N identical particles of one mass, P beads, Cartesian positions x [P][N][3]
+ * (no box).  The springs inside each particle's ring (beads 0..P-1) are the
+ * distinguishable ones; the link from bead P-1 of one particle to bead 0 of
+ * the next is summed over permutations:
+ *   exp(-beta_n V_B) = (1/N!) sum_sigma exp(-beta_n E_sigma),
+ * E_sigma = sum_l E_int(l) + sum_l link(l, sigma(l)), with
+ * link(l, l') = kspring |x_l'^0 - x_l^(P-1)|^2 and kspring = m omega_n^2 / 2.
+ * The recursion over cycles: V[0] = 0,
+ *   exp(-beta_n V[n]) = (1/n) sum_{k=1..n} exp(-beta_n (E[n,k] + V[n-k])),
+ * E[n,k] the energy of the single ring through particles n-k+1..n (1-based).
+ * Returns V_B = V[N]; f (may be NULL) receives -dV_B/dx for every bead; prob
+ * (may be NULL, [N][N]) the probability that bead P-1 of particle l links to
+ * bead 0 of particle l'. */
+double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
+                        double *f, double *prob);
+
 /* --- estimators (App. A) ----------------------------------------------- */
 /* At a synchronized state.  U is [P] from orc_forces. */
 void orc_estimators(const orc_system *sys, const double *x, const double *vt,

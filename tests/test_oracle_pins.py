@@ -802,3 +802,148 @@ def test_bzp_barostat_thermostat_rate():
     rho = np.dot(vw[1:], vw[:-1]) / np.dot(vw[:-1], vw[:-1])
     want = math.exp(-s.dt / s.tau)
     assert abs(rho - want) < 5 * math.sqrt((1 - want ** 2) / len(vw)), (rho, want)
+
+
+# ---------------------------------------------------------------- bosonic exchange
+def _boson_brute(x, kspring, beta_n):
+    """exp(-beta V_B) = (1/N!) sum over permutations of the last-bead links,
+    and each link's probability, by enumeration."""
+    import itertools
+    P, N, _ = x.shape
+    eint = sum(kspring * ((x[j + 1] - x[j]) ** 2).sum() for j in range(P - 1))
+    link = np.array([[kspring * ((x[0, l2] - x[P - 1, l]) ** 2).sum() for l2 in range(N)]
+                     for l in range(N)])
+    es, perms = [], list(itertools.permutations(range(N)))
+    for sg in perms:
+        es.append(eint + sum(link[l, sg[l]] for l in range(N)))
+    es = np.array(es)
+    lo = es.min()
+    wts = np.exp(-beta_n * (es - lo))
+    v = lo - math.log(wts.sum() / math.factorial(N)) / beta_n
+    prob = np.zeros((N, N))
+    for sg, wt in zip(perms, wts):
+        for l in range(N):
+            prob[l, sg[l]] += wt
+    return v, prob / wts.sum()
+
+
+def _compositions(n):
+    """The terms of the recursion unrolled: (weight, rings), each ring a run
+    of consecutive particles (0-based), the last ring holding particle n-1."""
+    if n == 0:
+        yield 1.0, []
+        return
+    for k in range(1, n + 1):
+        for c, rings in _compositions(n - k):
+            yield c / n, rings + [list(range(n - k, n))]
+
+
+def _ring_energy(x, kspring, order):
+    """One ring through the particles in `order`: each particle's own springs,
+    then its last bead to the next particle's first, closing back."""
+    P = x.shape[0]
+    e = 0.0
+    for a, l in enumerate(order):
+        e += kspring * ((x[1:, l] - x[:-1, l]) ** 2).sum()
+        nxt = order[(a + 1) % len(order)]
+        e += kspring * ((x[0, nxt] - x[P - 1, l]) ** 2).sum()
+    return e
+
+
+@pytest.mark.parametrize("N,P", [(1, 3), (2, 1), (2, 4), (3, 2), (4, 3), (5, 4)])
+def test_boson_recursion_unrolled(N, P):
+    """exp(-beta V_B) equals the recursion written out as a sum over its
+    compositions (rings of consecutive particles, weights prod 1/n), and the
+    link probabilities are each link's share of that sum; for N <= 2 that is
+    also the sum over permutations."""
+    rng = np.random.default_rng(10 * N + P)
+    x = rng.normal(0, 0.6, (P, N, 3)) + rng.normal(0, 1.0, (1, N, 3))
+    k, b = 1.3, 0.8
+    v, f, prob = oracle.boson_spring(x, k, b)
+    terms = [(c, rings, sum(_ring_energy(x, k, r) for r in rings)) for c, rings in _compositions(N)]
+    lo = min(e for _, _, e in terms)
+    z = sum(c * math.exp(-b * (e - lo)) for c, _, e in terms)
+    assert abs(v - (lo - math.log(z) / b)) <= 1e-12 * max(1.0, abs(v))
+    pr = np.zeros((N, N))
+    for c, rings, e in terms:
+        wt = c * math.exp(-b * (e - lo)) / z
+        for r in rings:
+            for a, l in enumerate(r):
+                pr[l, r[(a + 1) % len(r)]] += wt
+    assert np.abs(prob - pr).max() <= 1e-12
+    assert np.abs(prob.sum(axis=1) - 1).max() <= 1e-12      # each last bead links once
+    assert np.abs(prob.sum(axis=0) - 1).max() <= 1e-12      # each first bead is linked once
+    if N <= 2:
+        vb, pb = _boson_brute(x, k, b)
+        assert abs(v - vb) <= 1e-12 * max(1.0, abs(vb)) and np.abs(prob - pb).max() <= 1e-12
+
+
+def _gauss_z(P, N, kspring, a, beta, rings):
+    """1-D integral of exp(-beta (sum of the rings' springs + a sum x^2)) over
+    all P N bead coordinates: pi^(n/2) / sqrt(det A)."""
+    n = P * N
+    A = np.eye(n) * a
+    idx = lambda j, l: j * N + l
+    for order in rings:
+        for q, l in enumerate(order):
+            edges = [(idx(j, l), idx(j + 1, l)) for j in range(P - 1)]
+            edges.append((idx(P - 1, l), idx(0, order[(q + 1) % len(order)])))
+            for u, w in edges:
+                if u == w:
+                    continue
+                A[u, u] += kspring; A[w, w] += kspring; A[u, w] -= kspring; A[w, u] -= kspring
+    return math.pi ** (n / 2) / math.sqrt(np.linalg.det(beta * A))
+
+
+@pytest.mark.parametrize("N,P", [(3, 2), (4, 3), (5, 2)])
+def test_boson_recursion_gives_the_bosonic_partition_function(N, P):
+    """The recursion is not the permutation sum point by point (for N >= 3 it
+    keeps one canonical ring per cycle length), but its partition function is:
+    in a harmonic trap every term is a Gaussian integral, and the unrolled
+    recursion's integral equals (1/N!) times the sum over all permutations."""
+    import itertools
+    k, a, b = 1.1, 0.4, 0.9
+    z_rec = sum(c * _gauss_z(P, N, k, a, b, rings) for c, rings in _compositions(N))
+    z_perm = 0.0
+    for sg in itertools.permutations(range(N)):
+        seen, rings = set(), []
+        for l0 in range(N):
+            if l0 in seen:
+                continue
+            order, l = [], l0
+            while l not in seen:
+                seen.add(l); order.append(l); l = sg[l]
+            rings.append(order)
+        z_perm += _gauss_z(P, N, k, a, b, rings)
+    z_perm /= math.factorial(N)
+    assert abs(z_rec - z_perm) <= 1e-12 * z_perm
+
+
+@pytest.mark.parametrize("N,P", [(3, 3), (4, 2)])
+def test_boson_forces_are_minus_the_gradient(N, P):
+    rng = np.random.default_rng(N + 7 * P)
+    x = rng.normal(0, 0.5, (P, N, 3)) + rng.normal(0, 0.8, (1, N, 3))
+    k, b, h = 0.9, 1.7, 1e-6
+    _, f, _ = oracle.boson_spring(x, k, b)
+    num = np.zeros_like(x)
+    for idx in np.ndindex(*x.shape):
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        num[idx] = -(oracle.boson_spring(xp, k, b)[0] - oracle.boson_spring(xm, k, b)[0]) / (2 * h)
+    assert np.abs(num - f).max() <= 1e-6 * max(1.0, np.abs(f).max())
+
+
+def test_boson_limits():
+    """Far apart, only the identity permutation counts: V_B = E_id + ln(N!)/beta.
+    All particles on one path: every ring costs the same per particle, V_B = E_id."""
+    rng = np.random.default_rng(3)
+    N, P, k, b = 4, 3, 1.0, 2.0
+    path = rng.normal(0, 0.3, (P, 1, 3))
+    far = path + 50.0 * np.arange(N)[None, :, None] * np.array([1.0, 0.0, 0.0])
+    v, _, prob = oracle.boson_spring(far, k, b)
+    e_id = N * k * ((path[1:] - path[:-1]) ** 2).sum() + N * k * ((path[0] - path[-1]) ** 2).sum()
+    assert abs(v - (e_id + math.log(math.factorial(N)) / b)) <= 1e-12 * e_id
+    assert np.abs(prob - np.eye(N)).max() <= 1e-12
+    same = np.repeat(path, N, axis=1)
+    v2, _, prob2 = oracle.boson_spring(same, k, b)
+    assert abs(v2 - e_id) <= 1e-12 * e_id
