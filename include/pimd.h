@@ -277,8 +277,9 @@ int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
  * Errors: STATE, UNSUPPORTED (no barostat), DEVICE. */
 int pimd_get_barostat(pimd_ctx *ctx, double *box, double *vw);
 
-/* NPT, NPH: the box lengths (box[3], all equal and > 0: the barostat is
- * isotropic) and barostat velocity that the next pimd_set_state starts from,
+/* NPT, NPH: the box lengths (box[3], > 0, in the aspect ratio of params.box:
+ * the barostat is isotropic) and barostat velocity that the next
+ * pimd_set_state starts from,
  * e.g. those pimd_get_barostat returned with the state being restored; the
  * state's forces and estimators are then those of this box.  Host-side only
  * (no device work).  Errors: ARG (bad box or non-finite vw), UNSUPPORTED (no

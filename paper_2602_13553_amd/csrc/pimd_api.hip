@@ -923,8 +923,13 @@ int pimd_set_barostat(pimd_ctx *c, const double *box, double vw)
 {
     if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
     if (!c->lay.npt_grid) return fail(c, PIMD_ERR_UNSUPPORTED, "no barostat (ensemble is not NPT or NPH)");
-    if (!box || !finite_pos(box[0]) || box[1] != box[0] || box[2] != box[0])
-        return fail(c, PIMD_ERR_ARG, "box must hold three equal lengths > 0");
+    // the barostat scales all three lengths together: the aspect ratio stays
+    // that of params.box
+    bool ok = box != nullptr;
+    for (int d = 0; ok && d < 3; ++d) ok = finite_pos(box[d]);
+    const double g = ok ? box[0] / c->p.box[0] : 0.0;
+    for (int d = 1; ok && d < 3; ++d) ok = std::fabs(box[d] / c->p.box[d] - g) <= 1e-9 * g;
+    if (!ok) return fail(c, PIMD_ERR_ARG, "box must hold lengths > 0 in the aspect ratio of params.box");
     if (!std::isfinite(vw)) return fail(c, PIMD_ERR_ARG, "vw must be finite");
     for (int d = 0; d < 3; ++d) c->start_box[d] = box[d];
     c->start_vw = vw;
