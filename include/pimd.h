@@ -53,8 +53,8 @@ extern "C" {
 /* ensemble (Sec. III.C): NVT = PILE-L thermostat at P*T, NVE = no thermostat;
  * NPT = PILE-L and the isotropic BZP barostat (Sec. IV.A, App. E) with a
  * thermostat on its velocity, NPH = the barostat with neither thermostat.
- * NPT and NPH need PIMD_OBABO, PIMD_POT_LJ or PIMD_POT_WATER, fixcom = 0; they
- * are not batched. */
+ * NPT and NPH need PIMD_POT_LJ or PIMD_POT_WATER and fixcom = 0; they are not
+ * batched. */
 #define PIMD_NVT 0
 #define PIMD_NVE 1
 #define PIMD_NPT 2
@@ -103,17 +103,20 @@ typedef struct pimd_params {
     double tau_p;         /* NPT, NPH: barostat time > 0; mass W = 3 P N kB T tau_p^2 */
 } pimd_params;
 
-/* The barostat (NPT, NPH; App. E, isotropic).  A step: O(dt/2) on the beads
- * and on v_W; B(dt/2) on v_W and the beads together; A(dt) with the centroid
- * modes under the barostat, x~0 <- e x~0 + dt sinh(u)/u v~0, v~0 <- v~0 / e
- * (u = dt v_W, e = exp(u)), the other modes by the free flow, and the box
- * L <- e L; the forces in the new box; B(dt/2); O(dt/2) on v_W and the beads.
+/* The barostat (NPT, NPH; App. E, isotropic).  An OBABO step: O(dt/2) on the
+ * beads and on v_W; B(dt/2) on v_W and the beads together; A(dt) with the
+ * centroid modes under the barostat, x~0 <- e x~0 + t sinh(u)/u v~0,
+ * v~0 <- v~0 / e (t = dt, u = t v_W, e = exp(u)), the other modes by the free
+ * flow, and the box L <- e L; the forces in the new box; B(dt/2); O(dt/2) on
+ * v_W and the beads.  A BAOAB step: B(dt/2); A(dt/2) as above with t = dt/2;
+ * O(dt) on the beads and on v_W; A(dt/2) with the new v_W; forces; B(dt/2).
  * v_W's force is (3/W)[P V (P_CV - p_ext) + P kB T] (the value for which the
  * enthalpy H + K_W + U_W + J_W of App. A is conserved in NPH; J_W =
  * -P kB T ln V); its kick integrates the centroid kinetic term along the
  * beads' kick (App. E's h^2 and h^3 terms, from the momenta at the kick's
  * start).  Its O step: v_W <- c1 v_W + c2 sqrt(P kB T / W) z, c1 =
- * exp(-dt/(2 tau)), z the first Gaussian of counter (2^64 - 1, 0, step, q).
+ * exp(-t/tau) over the O step's length t, z the first Gaussian of counter
+ * (2^64 - 1, 0, step, q) (q as for the beads' O steps).
  * pimd_set_state starts the box at params.box with v_W = 0, or at the values
  * given to pimd_set_barostat before it (a restart). */
 

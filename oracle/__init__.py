@@ -299,8 +299,6 @@ class State:
         self.f, self.U = system.forces(self.x)
         self.step_count = np.array([step], dtype=np.uint64)
         if system.npt:
-            if system.integrator != 1:
-                raise ValueError("the BZP barostat runs with the OBABO splitting")
             self.baro = _Baro()
             self.baro.vw = 0.0
             self.baro.box = (C.c_double * 3)(*system.box)

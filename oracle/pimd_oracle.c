@@ -706,14 +706,17 @@ double orc_kcv_nm(const orc_system *sys, const double *x, const double *f)
 }
 
 /* ------------------------------------------------------------------------
- * BZP barostat, App. E, isotropic, with the OBABO splitting of the paper's
- * example input.  A step at a synchronized state (forces f of x in box L):
+ * BZP barostat, App. E, isotropic.  An OBABO step (the splitting of the
+ * paper's example input) at a synchronized state (forces f of x in box L):
  *   O(dt/2) on the beads (q = 0) and on v_W;
  *   B(dt/2): v_W and v~ kicked together;
  *   A(dt): the centroid mode under the barostat, the other modes by the free
  *          ring-polymer flow (A(dt/2) twice), L <- exp(dt v_W) L;
  *   forces of the new positions in the new box;
  *   B(dt/2); O(dt/2) on v_W and on the beads (q = 1).
+ * A BAOAB step: B(dt/2); A(dt/2) with the centroid under the barostat;
+ * O(dt) on the beads and on v_W (q = 0); A(dt/2) with the new v_W; forces;
+ * B(dt/2).
  * Readings of App. E:
  *  - the barostat's force is (3/W)[P V (P_CV - P_ext) + P kB T]: the printed
  *    1/(n kB T) is read as n kB T, the value for which App. A's enthalpy
@@ -797,10 +800,11 @@ void orc_baro_centroid_flow(double vw, double t, double *xt0, double *vt0)
     *vt0 = ei * *vt0;
 }
 
+/* v_W's O step over t: dt/2 in OBABO (q = 0, 1), dt in BAOAB (q = 0) */
 static void orc_baro_o(const orc_system *sys, orc_baro *b, uint64_t s, uint64_t q)
 {
     if (sys->nve) return;
-    const double h = 0.5 * sys->dt;
+    const double h = sys->integrator == 1 ? 0.5 * sys->dt : sys->dt;
     const double c1 = exp(-h / sys->tau), c2 = sqrt(1.0 - c1 * c1);
     const double sigma = sqrt((double)sys->n_beads * sys->kB * sys->temp / orc_baro_mass(sys));
     double z[3];
@@ -819,6 +823,56 @@ void orc_npt_step(const orc_system *sys0, orc_baro *b, double *x, double *vt, do
     for (int32_t it = 0; it < nsteps; ++it) {
         orc_system sys = orc_in_box(sys0, b);
         const uint64_t s = *step;
+        if (sys0->integrator != 1) {
+            /* BAOAB: B(dt/2) on v_W and the beads; A(dt/2) with the centroid
+             * under the barostat; O(dt) on the beads and on v_W; A(dt/2);
+             * forces in the new box; B(dt/2) */
+            orc_baro_kick(&sys, b, x, vt, f, h);
+            orc_kick(&sys, vt, f, ft);
+            orc_to_normal(P, N, x, xt);
+            double Ah[4], c1, c2;
+            for (int half = 0; half < 2; ++half) {
+                for (int32_t k = 1; k < P; ++k) {
+                    orc_free_rp_matrix(&sys, k, h, Ah);
+                    for (int32_t i = 0; i < N; ++i)
+                        for (int d = 0; d < 3; ++d) {
+                            const size_t e = ((size_t)k * N + i) * 3 + d;
+                            const double q = xt[e], p = vt[e];
+                            xt[e] = Ah[0] * q + Ah[1] * p;
+                            vt[e] = Ah[2] * q + Ah[3] * p;
+                        }
+                }
+                for (size_t e = 0; e < (size_t)N * 3; ++e)
+                    orc_baro_centroid_flow(b->vw, h, &xt[e], &vt[e]);
+                const double sc = exp(h * b->vw);
+                for (int d = 0; d < 3; ++d) b->box[d] *= sc;
+                if (half == 0 && !sys.nve) {
+                    /* O(dt) on the beads' modes, then on v_W */
+                    for (int32_t k = 0; k < P; ++k) {
+                        orc_pile_coeffs(&sys, k, &c1, &c2);
+                        for (int32_t i = 0; i < N; ++i) {
+                            const double sigma = sqrt((double)P * sys.kB * sys.temp *
+                                                      (1.0 / sys.mvv2e) / sys.mass[i]);
+                            const uint64_t id = sys.atom_id ? (uint64_t)sys.atom_id[i] : (uint64_t)i;
+                            double z[3];
+                            orc_gaussians(sys.seed, 0, id, (uint64_t)k, s, z);
+                            for (int d = 0; d < 3; ++d) {
+                                const size_t e = ((size_t)k * N + i) * 3 + d;
+                                vt[e] = c1 * vt[e] + c2 * sigma * z[d];
+                            }
+                        }
+                    }
+                    orc_baro_o(&sys, b, s, 0);
+                }
+            }
+            orc_from_normal(P, N, xt, x);
+            *step = s + 1;
+            sys = orc_in_box(sys0, b);
+            orc_forces(&sys, x, f, U);
+            orc_baro_kick(&sys, b, x, vt, f, h);
+            orc_kick(&sys, vt, f, ft);
+            continue;
+        }
         /* O */
         orc_o_step(&sys, vt, s, 0);
         orc_baro_o(&sys, b, s, 0);

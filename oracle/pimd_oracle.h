@@ -62,8 +62,8 @@ typedef struct orc_system {
     int32_t integrator;     /* 0: BAOAB; 1: OBABO (O(dt/2) B(dt/2) A(dt) B(dt/2) O(dt/2)) */
     int32_t fixcom;         /* 1: remove the centroids' center-of-mass velocity at the end
                                of every step */
-    int32_t npt;            /* 1: isotropic BZP barostat (App. E), OBABO only; with nve = 1
-                               the barostat's thermostat is off too (NpH) */
+    int32_t npt;            /* 1: isotropic BZP barostat (App. E) with either splitting; with
+                               nve = 1 the barostat's thermostat is off too (NpH) */
     double p_ext;           /* target pressure (energy per volume) */
     double tau_p;           /* barostat time: W = 3 P N kB T tau_p^2 */
 } orc_system;

@@ -143,8 +143,8 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
             why = "the barostat needs tau_p > 0 and a finite p_ext";
             return PIMD_ERR_ARG;
         }
-        if (p->integrator != PIMD_OBABO || !is_pair(p->potential) || p->fixcom) {
-            why = "the barostat runs with PIMD_OBABO, PIMD_POT_LJ or PIMD_POT_WATER, and fixcom = 0";
+        if (!is_pair(p->potential) || p->fixcom) {
+            why = "the barostat runs with PIMD_POT_LJ or PIMD_POT_WATER, and fixcom = 0";
             return PIMD_ERR_UNSUPPORTED;
         }
         if (p->flags & (PIMD_FLAG_MFMA_TRANSFORMS | PIMD_FLAG_CLUSTER_PAIRS)) {
@@ -726,7 +726,9 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         const double kT = p->kB * p->temp;
         b.kTP = (double)P * kT;
         b.wmass = 3.0 * (double)P * (double)N * kT * p->tau_p * p->tau_p;
-        b.bc1 = p->ensemble == PIMD_NPT ? std::exp(-0.5 * p->dt / p->tau) : 1.0;
+        // v_W's O step: over dt/2 (twice per step) in OBABO, over dt in BAOAB
+        const double to = p->integrator == PIMD_OBABO ? 0.5 * p->dt : p->dt;
+        b.bc1 = p->ensemble == PIMD_NPT ? std::exp(-to / p->tau) : 1.0;
         b.bc2 = std::sqrt(1.0 - b.bc1 * b.bc1);
         b.bsig = std::sqrt(b.kTP / b.wmass);
     }

@@ -1,16 +1,18 @@
-// The isotropic BZP barostat (App. E) with the OBABO splitting: NpT, or NpH
-// with both thermostats off.  A step at a synchronized state is
+// The isotropic BZP barostat (App. E): NpT, or NpH with both thermostats off.
+// An OBABO step at a synchronized state is
 //   O(dt/2) on the beads and on v_W; B(dt/2) on v_W and the beads together;
 //   A(dt): the centroid mode under the barostat, the other modes by the free
 //   ring-polymer flow, L <- exp(dt v_W) L; forces in the new box;
 //   B(dt/2); O(dt/2) on v_W and on the beads.
+// A BAOAB step is B(dt/2); A(dt/2); O(dt) on the beads and on v_W; A(dt/2)
+// with the new v_W; forces; B(dt/2).
 // The barostat's force is (3/W)[P V (P_CV - P_ext) + P kB T], the value for
 // which the enthalpy H + K_W + U_W + J_W (App. A) is conserved in NpH.  Its
 // kick is the exact flow of the kick: the centroid kinetic term, linear in
 // time along the kick, integrates to h sum m|v~0|^2 + h^2 sum f~0.v~0 +
 // (h^3/3) sum |f~0|^2/m from the momenta at the kick's start.  Its O step
-// uses c1 = exp(-dt/(2 tau_0)) and noise sqrt(P kB T / W) z, z the first
-// Gaussian of counter (2^64 - 1, 0, s, q).
+// over a time t uses c1 = exp(-t/tau_0) and noise sqrt(P kB T / W) z, z the
+// first Gaussian of counter (2^64 - 1, 0, s, q).
 //
 // The kicks need sums over all atoms taken between per-element updates, so a
 // step is two passes, each followed by a one-block finalize (scalar barostat
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) vt[d] += a.hdt * im * ft[d];
-            if (a.nvt) o_step(step - 1, 1);
+            if (a.obabo && a.nvt) o_step(step - 1, 1);
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
             }
         }
         if (opening) {
-            if (a.nvt) o_step(step, 0);
+            if (a.obabo && a.nvt) o_step(step, 0);
             if (k == 0) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_a(NptArgs na, int mode, int 
     double vw = c->vw;
     if (closing) {
         vw = baro_kick(na, vw, h, 2.0 * tot[NP_K0A], vir, w, V, tot[NP_FVA], f2);
-        if (a.nvt) vw = baro_o(na, vw, step - 1, 1);
+        if (a.obabo && a.nvt) vw = baro_o(na, vw, step - 1, 1);
     }
     if (est_now) {
         const double ekin = tot[NP_EKIN], esp = tot[NP_ESPRING], epot = tot[NP_COUNT];
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_a(NptArgs na, int mode, int 
     }
     if (closing) c->synced = 1;
     if (mode == NPT_STEP) {
-        if (a.nvt) vw = baro_o(na, vw, step, 0);
+        if (a.obabo && a.nvt) vw = baro_o(na, vw, step, 0);
         vw = baro_kick(na, vw, h, 2.0 * tot[NP_K0B], vir, w, V, tot[NP_FVB], f2);
     }
     c->vw = vw;
@@ -242,6 +244,10 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
     const int i = blockIdx.x * A + la;
     const bool act = la < A && i < N;
     const double vw = a.ctl->vw;
+    const unsigned long long step = a.ctl->step;
+    // BAOAB: v_W for the second A(dt/2), after its O(dt) (noise alone, so
+    // every thread forms it; the finalize forms the same value)
+    const double vw2 = (!a.obabo && a.nvt) ? baro_o(na, vw, step, 0) : vw;
     const size_t vb = (size_t)i * 3 * P + k;
     const double sqrtP = sqrt((double)P);
     if (act) {
@@ -262,32 +268,48 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
             for (int d = 0; d < 3; ++d) yt[d] += m * (xr[d * P + j] - x0[d]);
         }
         const double im = a.atoms[i * 4 + AT_INV_M];
+        const double sg = a.atoms[i * 4 + AT_SIGMA];
         active = a.atoms[i * 4 + AT_ACTIVE];
         const double *mk = a.modes + k * 8;
         double vt[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) vt[d] = a.v[vb + d * P] + a.hdt * im * na.ft[vb + d * P];
-        if (k == 0) {
-            // the centroid under the barostat over dt, in absolute coordinates
-            // x~0 = y~0 + sqrt(P) x_0
-            const double u = na.dt * vw;
-            const double e = exp(u), ei = exp(-u), s = na.dt * sinhc(u);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double X = e * (yt[d] + sqrtP * x0[d]) + s * vt[d];
-                vt[d] *= ei;
-                yt[d] = X - sqrtP * x0[d];
-            }
-        } else {
-            // free ring-polymer flow over dt as A(dt/2) twice
-            for (int rep = 0; rep < 2; ++rep) {
+        // A over a time t_: the centroid under the barostat (velocity vw_),
+        // in absolute coordinates x~0 = y~0 + sqrt(P) x_0; the other modes by
+        // the free ring-polymer flow, A(dt/2) n_ times
+        auto a_flow = [&](double t_, double vw_, int n_) {
+            if (k == 0) {
+                const double u = t_ * vw_;
+                const double e = exp(u), ei = exp(-u), s = t_ * sinhc(u);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double q = yt[d], p = vt[d];
-                    yt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
-                    vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                    const double X = e * (yt[d] + sqrtP * x0[d]) + s * vt[d];
+                    vt[d] *= ei;
+                    yt[d] = X - sqrtP * x0[d];
+                }
+            } else {
+                for (int rep = 0; rep < n_; ++rep) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double q = yt[d], p = vt[d];
+                        yt[d] = mk[MD_A00] * q + mk[MD_A01] * p;
+                        vt[d] = mk[MD_A10] * q + mk[MD_A11] * p;
+                    }
                 }
             }
+        };
+        if (a.obabo) {
+            a_flow(na.dt, vw, 2);
+        } else {
+            // A(dt/2), O(dt) on the beads (the step's one draw), A(dt/2)
+            a_flow(a.hdt, vw, 1);
+            if (a.nvt) {
+                double z[3];
+                gauss3(a.seed, (unsigned long long)a.orig[i], (unsigned long long)k, step, z, 0ULL);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
+            }
+            a_flow(a.hdt, vw2, 1);
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) a.v[vb + d * P] = vt[d];
@@ -322,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
         if (k == 0) {
             // displacement from the last build's centroid carried along by the
             // box scaling since that build
-            const double s = exp(na.dt * vw);
+            const double s = a.obabo ? exp(na.dt * vw) : exp(a.hdt * vw) * exp(a.hdt * vw2);
             const double g = a.ctl->box[0] * s / a.ctl->box_build[0];
             double d2 = 0.0;
 #pragma unroll
@@ -374,9 +396,19 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
     }
     block_maxv<3>(m3, red);
     if (t == 0) {
-        const double s = exp(na.dt * c->vw);
+        if (a.obabo) {
+            const double s = exp(na.dt * c->vw);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) c->box[d] *= s;
+            for (int d = 0; d < 3; ++d) c->box[d] *= s;
+        } else {
+            // the two A(dt/2), around v_W's O(dt)
+            const double vw1 = c->vw;
+            const double vw2 = a.nvt ? baro_o(na, vw1, c->step, 0) : vw1;
+            const double s1 = exp(a.hdt * vw1), s2 = exp(a.hdt * vw2);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c->box[d] = c->box[d] * s1 * s2;
+            c->vw = vw2;
+        }
         c->step = c->step + 1;
         c->synced = 0;
         if (c->budget > 0) c->budget = c->budget - 1;

@@ -24,8 +24,8 @@ def rel_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def _barostat(spec, ensemble, p_ext, tau_p):
-    spec.ensemble, spec.integrator, spec.p_ext, spec.tau_p = ensemble, 1, p_ext, tau_p
+def _barostat(spec, ensemble, p_ext, tau_p, integrator=1):
+    spec.ensemble, spec.integrator, spec.p_ext, spec.tau_p = ensemble, integrator, p_ext, tau_p
     return spec
 
 
@@ -77,6 +77,20 @@ def check(g, st, tol=TOL, est_tol=1e-10):
 def test_barostat_lj_matches_oracle(ensemble):
     spec = _barostat(inputs.lj_liquid(n_atoms=256, n_beads=8, seed=41), ensemble, 2.0, 0.2)
     g, st = run_both(spec, [1, 6, 3])
+    check(g, st)
+
+
+@pytest.mark.parametrize("ensemble", [2, 3])
+def test_barostat_baoab_matches_oracle(ensemble):
+    """The BAOAB splitting: A(dt/2), O(dt) on the beads and on v_W, A(dt/2)
+    with the new v_W."""
+    spec = _barostat(inputs.lj_liquid(n_atoms=256, n_beads=8, seed=50), ensemble, 2.0, 0.2,
+                     integrator=0)
+    g, st = run_both(spec, [1, 6, 3])
+    check(g, st)
+    spec = _barostat(inputs.water(n_atoms=384, n_beads=8, seed=51), ensemble, 0.5, 200.0,
+                     integrator=0)
+    g, st = run_both(spec, [4, 6])
     check(g, st)
 
 

@@ -652,7 +652,7 @@ def test_pmd_is_the_classical_pressure_of_the_beads():
 
 
 # ---------------------------------------------------------------- BZP barostat
-def _nph(dt, t_total=1.0, npt=1):
+def _nph(dt, t_total=1.0, npt=1, integrator=1):
     """LJ (rc = 3, small force jump at the cutoff) at P = 4 in NpH (both
     thermostats off), started far from mechanical equilibrium so that the
     volume moves by ~40%; returns App. A's enthalpy (or H without the
@@ -662,7 +662,7 @@ def _nph(dt, t_total=1.0, npt=1):
     pts = np.stack(np.meshgrid(*[np.arange(g)] * 3, indexing="ij"), -1).reshape(-1, 3)
     s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.1, dt=dt,
                       pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=1.0, lj_sigma=1.0, lj_rc=3.0,
-                      integrator=1, npt=npt, nve=True, p_ext=1.0, tau_p=0.5, seed=3)
+                      integrator=integrator, npt=npt, nve=True, p_ext=1.0, tau_p=0.5, seed=3)
     rng = np.random.default_rng(1)
     x = (pts + 0.5) * (L / g)
     st = oracle.State(s, x[None] + 0.02 * rng.standard_normal((P, N, 3)),
@@ -679,20 +679,22 @@ def _nph(dt, t_total=1.0, npt=1):
     return np.array(H), np.array(V)
 
 
-def test_bzp_nph_conserves_the_enthalpy_to_second_order():
+@pytest.mark.parametrize("integrator", [1, 0])
+def test_bzp_nph_conserves_the_enthalpy_to_second_order(integrator):
     """App. A's enthalpy H + K_W + U_W + J_W is a constant of the NpH motion:
     its spread falls as dt^2 (a wrong term in the barostat's force, in the
     centroid's flow or in the box update leaves an O(1) or O(dt) error),
-    while U_W and J_W themselves change by hundreds and by ~1.5."""
-    H1, V1 = _nph(0.002)
-    H2, V2 = _nph(0.001)
+    while U_W and J_W themselves change by hundreds and by ~1.5; with the
+    OBABO and with the BAOAB splitting."""
+    H1, V1 = _nph(0.002, integrator=integrator)
+    H2, V2 = _nph(0.001, integrator=integrator)
     assert V1.max() / V1.min() > 1.3          # the barostat does move the box
     r = np.ptp(H1) / np.ptp(H2)
     assert 3.0 < r < 5.0, (np.ptp(H1), np.ptp(H2))
     assert np.ptp(H2) < 0.3
     # no worse than the same system's NVE energy at the same dt (the cutoff's
     # force jump dominates both)
-    E2, _ = _nph(0.001, npt=0)
+    E2, _ = _nph(0.001, npt=0, integrator=integrator)
     assert np.ptp(H2) < 2.5 * np.ptp(E2)
 
 
@@ -743,15 +745,17 @@ def test_bzp_centroid_flow_is_the_exact_linear_flow(vw):
     assert abs(va[0] - want[1]) <= 2e-15 * max(1.0, abs(want[1]))
 
 
-def test_bzp_with_a_heavy_barostat_is_obabo():
-    """With W -> infinity the box stays put and the NpT step is the NVT OBABO
-    step on the same noise (the barostat draws from its own counter)."""
+@pytest.mark.parametrize("integrator", [1, 0])
+def test_bzp_with_a_heavy_barostat_is_the_nvt_step(integrator):
+    """With W -> infinity the box stays put and the NpT step is the NVT step
+    of the same splitting on the same noise (the barostat draws from its own
+    counter)."""
     spec = inputs.lj_liquid(n_atoms=108, n_beads=4, seed=23)
     s = oracle.System.from_spec(spec)
-    s.integrator = 1
+    s.integrator = integrator
     a = oracle.State(s, spec.x0, spec.v0)
     sn = oracle.System.from_spec(spec)
-    sn.integrator, sn.npt, sn.p_ext, sn.tau_p = 1, 1, 1.0, 1e9
+    sn.integrator, sn.npt, sn.p_ext, sn.tau_p = integrator, 1, 1.0, 1e9
     b = oracle.State(sn, spec.x0, spec.v0)
     a.step(20)
     b.step(20)
@@ -760,15 +764,16 @@ def test_bzp_with_a_heavy_barostat_is_obabo():
     assert np.abs(b.vt - a.vt).max() <= 1e-9 * np.abs(a.vt).max()
 
 
-def test_bzp_barostat_equipartition():
+@pytest.mark.parametrize("integrator", [1, 0])
+def test_bzp_barostat_equipartition(integrator):
     """NpT: v_W's marginal is Gaussian with variance P kT / W (the enthalpy
     is separable in v_W and sampled at P T), so <K_W> = P kT / 2; a dilute
     ring-polymer gas, 6e4 steps, block-averaged error bar."""
     N, P, L = 8, 4, 4.0
     rng = np.random.default_rng(5)
     s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.2, dt=0.01,
-                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=0.0, lj_rc=1.0, integrator=1,
-                      npt=1, p_ext=0.5, tau_p=0.2, tau=0.05, seed=9)
+                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=0.0, lj_rc=1.0,
+                      integrator=integrator, npt=1, p_ext=0.5, tau_p=0.2, tau=0.05, seed=9)
     st = oracle.State(s, rng.uniform(0, L, (1, N, 3)) + 0.01 * rng.standard_normal((P, N, 3)),
                       rng.standard_normal((P, N, 3)) * 2)
     W = oracle.lib().orc_baro_mass(oracle.C.byref(s.cstruct()))
@@ -783,15 +788,17 @@ def test_bzp_barostat_equipartition():
     assert se < 0.1
 
 
-def test_bzp_barostat_thermostat_rate():
+@pytest.mark.parametrize("integrator", [1, 0])
+def test_bzp_barostat_thermostat_rate(integrator):
     """With a very heavy barostat the kicks vanish and v_W is the
-    Ornstein-Uhlenbeck chain of its two O(dt/2) steps per step: lag-one
-    autocorrelation exp(-dt/tau_0) per step (tau_0, as printed)."""
+    Ornstein-Uhlenbeck chain of its O steps (two of dt/2 in OBABO, one of dt in
+    BAOAB): lag-one autocorrelation exp(-dt/tau_0) per step (tau_0, as
+    printed)."""
     N, P, L = 8, 4, 4.0
     rng = np.random.default_rng(6)
     s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.2, dt=0.01,
-                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=0.0, lj_rc=1.0, integrator=1,
-                      npt=1, p_ext=0.5, tau_p=1e6, tau=0.05, seed=10)
+                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=0.0, lj_rc=1.0,
+                      integrator=integrator, npt=1, p_ext=0.5, tau_p=1e6, tau=0.05, seed=10)
     st = oracle.State(s, rng.uniform(0, L, (1, N, 3)) + 0.01 * rng.standard_normal((P, N, 3)),
                       rng.standard_normal((P, N, 3)) * 2)
     vw = []
