@@ -289,6 +289,24 @@ int pimd_get_barostat(pimd_ctx *ctx, double *box, double *vw);
  * barostat). */
 int pimd_set_barostat(pimd_ctx *ctx, const double *box, double vw);
 
+/* Bosonic exchange (the bosonic fix of Sec. III.C; the exchange potential of
+ * Hirshberg et al. 2019, cited by the paper).  For N identical particles of
+ * P beads, x [P][N][3] (bead, particle, dim; device memory, no box), with
+ * springs kspring |r - r'|^2 (kspring = m omega_n^2 / 2) inside each
+ * particle's ring and, summed over exchange cycles, from bead P-1 of a
+ * particle to bead 0 of the next:
+ *   exp(-beta_n V[n]) = (1/n) sum_{k=1..n} exp(-beta_n (E[n,k] + V[n-k])),
+ * V[0] = 0, E[n,k] the single ring through particles n-k..n-1 (0-based).
+ * Writes V_B = V[N] to v (device, one double), the spring forces -dV_B/dx to
+ * f ([P][N][3], device, overwritten) and to prob ([N][N], device) the
+ * probability that bead P-1 of particle l links to bead 0 of particle l'.
+ * Runs on the null stream and waits for it.  A building block of bosonic
+ * PIMD (its Cartesian integrator is not in this library).
+ * Errors: ARG (NULL pointer, N < 1, P < 1, kspring < 0 or not finite,
+ * beta_n <= 0), UNSUPPORTED (N > 512, P > 128), DEVICE. */
+int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
+                      double *f, double *prob, double *v);
+
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpimd.so")
-SOURCES = ["pimd_kernels.hip", "pimd_fused_mfma.hip", "pimd_npt.hip", "pimd_api.hip"]
+SOURCES = ["pimd_kernels.hip", "pimd_fused_mfma.hip", "pimd_npt.hip", "pimd_boson.hip",
+           "pimd_api.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -907,6 +907,22 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
     return PIMD_OK;
 }
 
+int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
+                      double *f, double *prob, double *v)
+{
+    if (!x || !f || !prob || !v) return fail(nullptr, PIMD_ERR_ARG, "x, f, prob and v must be non-NULL");
+    if (N < 1 || P < 1) return fail(nullptr, PIMD_ERR_ARG, "N and P must be >= 1");
+    if (!(kspring >= 0.0) || !std::isfinite(kspring) || !finite_pos(beta_n))
+        return fail(nullptr, PIMD_ERR_ARG, "kspring >= 0 and beta_n > 0 must be finite");
+    if (N > boson_max() || P > kMaxBeads)
+        return fail(nullptr, PIMD_ERR_UNSUPPORTED, "N > 512 or P > 128");
+    launch_boson_spring(x, N, P, kspring, beta_n, f, prob, v, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return fail(nullptr, PIMD_ERR_DEVICE, hipGetErrorString(e));
+    return PIMD_OK;
+}
+
 int pimd_get_barostat(pimd_ctx *c, double *box, double *vw)
 {
     if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");

@@ -187,6 +187,12 @@ void launch_npt_a(const NptArgs &a, int mode, hipStream_t s);
 void launch_npt_b(const NptArgs &a, hipStream_t s);
 void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s);
 
+// Bosonic exchange spring energy, forces and link probabilities
+// (pimd_boson.hip); x, f: [P][N][3]; prob: [N][N]; out: one double.
+int boson_max();
+void launch_boson_spring(const double *x, int N, int P, double kspring, double beta_n, double *f,
+                         double *prob, double *out, hipStream_t st);
+
 // Launchers (pimd_kernels.hip).
 int fused_smem_bytes(int P);
 int fused_grid(int N, int P);

@@ -36,6 +36,7 @@ ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "p
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_set_barostat",
+            "pimd_boson_spring",
             "pimd_reset_averages",
             "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
@@ -111,6 +112,8 @@ def load() -> C.CDLL:
         lib.pimd_get_estimators.argtypes = [C.c_void_p, P(pimd_estimators)]
         lib.pimd_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_uint64)]
         lib.pimd_get_barostat.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+        lib.pimd_boson_spring.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                          C.c_void_p, C.c_void_p, C.c_void_p]
         lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), C.c_double]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
@@ -196,6 +199,26 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     p.p_ext = float(getattr(spec, "p_ext", 0.0))
     p.tau_p = float(getattr(spec, "tau_p", 1.0))
     return p
+
+
+def boson_spring(x, kspring: float, beta_n: float):
+    """Bosonic exchange spring energy V_B, forces [P][N][3] and link
+    probabilities [N][N] of bead positions x ([P][N][3], float64; a torch
+    CUDA tensor, or host data copied to the device), computed on the GPU."""
+    import torch
+    lib = load()
+    xd = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    P, N, _ = xd.shape
+    f = torch.empty_like(xd)
+    prob = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    v = torch.empty(1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    rc = lib.pimd_boson_spring(xd.data_ptr(), int(N), int(P), float(kspring), float(beta_n),
+                               f.data_ptr(), prob.data_ptr(), v.data_ptr())
+    if rc != PIMD_OK:
+        msg = lib.pimd_last_error(None)
+        raise PimdError(rc, msg.decode() if msg else "")
+    return float(v.item()), f, prob
 
 
 class Context:

@@ -1,0 +1,42 @@
+"""GPU parity of the bosonic exchange spring kernel (pimd_boson_spring, through
+the C ABI) against the oracle's recursion: V_B, the forces and the link
+probabilities, element by element."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("N,P", [(1, 4), (2, 1), (3, 8), (17, 32), (64, 16), (300, 4)])
+def test_boson_spring_matches_oracle(N, P):
+    from paper_2602_13553_amd import pimd
+    rng = np.random.default_rng(N * 131 + P)
+    # particles spread over a few thermal lengths, so that exchange matters
+    x = rng.normal(0, 0.4, (P, N, 3)) + rng.normal(0, 1.2, (1, N, 3))
+    k, b = 1.1, 0.9
+    _say("case boson N=%d P=%d" % (N, P))
+    v, f, prob = pimd.boson_spring(x, k, b)
+    f, prob = f.cpu().numpy(), prob.cpu().numpy()
+    vo, fo, po = oracle.boson_spring(x, k, b)
+    ef = np.abs(f - fo).max() / max(np.abs(fo).max(), 1e-300)
+    _say("  V %.15e / %.15e  f rel %.3e  prob %.3e" % (v, vo, ef, np.abs(prob - po).max()))
+    assert abs(v - vo) <= 1e-12 * max(1.0, abs(vo))
+    assert ef <= 1e-12
+    assert np.abs(prob - po).max() <= 1e-12
+
+
+def test_boson_spring_errors():
+    from paper_2602_13553_amd import pimd
+    with pytest.raises(pimd.PimdError):
+        pimd.boson_spring(np.zeros((2, 513, 3)), 1.0, 1.0)
+    with pytest.raises(pimd.PimdError):
+        pimd.boson_spring(np.zeros((2, 3, 3)), 1.0, 0.0)
