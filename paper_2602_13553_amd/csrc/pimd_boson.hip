@@ -1,7 +1,6 @@
 // Bosonic exchange spring energy (the bosonic fix of Sec. III.C; the
-// recursion of Hirshberg et al. 2019, which the paper cites with Feldman and
-// Hirshberg's quadratic-time evaluation; here the energy and the adjoints
-// take O(N^2) and the chain links' probabilities O(N^3)).  N identical
+// recursion of Hirshberg et al. 2019, evaluated in O(N^2) like Feldman and
+// Hirshberg's algorithm, both cited by the paper).  N identical
 // particles, P beads; the springs inside each particle's ring are the
 // distinguishable ones, and the link from bead P-1 of a particle to bead 0 of
 // the next is summed over exchange cycles by
@@ -27,6 +26,8 @@ struct BosonLds {
     double schain[kBosonMax + 1];// prefix sums of the links l -> l+1
     double V[kBosonMax + 1];
     double adj[kBosonMax + 1];
+    double wsuf[kBosonMax + 1];  // one n's ring weights, then their suffix sums over k
+    double chain[kBosonMax];     // probability of the chain link l -> l+1
     double red[64];
 };
 
@@ -129,26 +130,44 @@ __global__ __launch_bounds__(kBlock) void k_boson_spring(const double *x, int N,
         }
         __syncthreads();
     }
-    // link probabilities: each closing link n-1 -> n-k takes its ring's
-    // weight; each chain link l -> l+1 the weights of every ring (n, k) that
-    // spans it (cubic in N, as in the oracle)
+    // link probabilities.  Ring (n, k) carries q[n,k] = adj[n] w[n,k]: its
+    // closing link n-1 -> n-k takes q[n,k], and each chain link l -> l+1 with
+    // n-k <= l <= n-2 takes it too, so the chain link l gets, from each n,
+    // the suffix sum over k >= n-l of q[n,k]: one block scan per n, O(N^2)
+    // in all.
     for (int e = t; e < N * N; e += kBlock) prob[e] = 0.0;
+    for (int l = t; l < N; l += kBlock) s.chain[l] = 0.0;
     __syncthreads();
+    constexpr int KT = (kBosonMax + kBlock - 1) / kBlock;   // k per thread
     for (int n = 1; n <= N; ++n) {
         for (int k = 1 + t; k <= n; k += kBlock) {
             const double q = s.adj[n] *
                              exp(-beta_n * (ring_e(s, kspring, n, k) + s.V[n - k] - s.V[n])) / (double)n;
-            prob[(size_t)(n - 1) * N + (n - k)] += q;   // one (n, k) per entry
+            prob[(size_t)(n - 1) * N + (n - k)] = q;    // one (n, k) per entry
+            s.wsuf[k] = q;
         }
+        __syncthreads();
+        // suffix sums over k = 1..n (Hillis-Steele, in place)
+        for (int off = 1; off < n; off <<= 1) {
+            double add[KT];
+#pragma unroll
+            for (int u = 0; u < KT; ++u) {
+                const int k = 1 + t + u * kBlock;
+                add[u] = (k <= n && k + off <= n) ? s.wsuf[k + off] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < KT; ++u) {
+                const int k = 1 + t + u * kBlock;
+                if (k <= n) s.wsuf[k] += add[u];
+            }
+            __syncthreads();
+        }
+        // chain link l (l <= n-2) collects the rings with k >= n-l
+        for (int l = t; l + 2 <= n; l += kBlock) s.chain[l] += s.wsuf[n - l];
+        __syncthreads();
     }
-    for (int l = t; l + 1 < N; l += kBlock) {
-        double q = 0.0;
-        for (int n = l + 2; n <= N; ++n)
-            for (int k = n - l; k <= n; ++k)
-                q += s.adj[n] * exp(-beta_n * (ring_e(s, kspring, n, k) + s.V[n - k] - s.V[n])) /
-                     (double)n;
-        prob[(size_t)l * N + l + 1] = q;                 // no closing link goes forward
-    }
+    for (int l = t; l + 1 < N; l += kBlock) prob[(size_t)l * N + l + 1] = s.chain[l];
     __threadfence_block();
     __syncthreads();
     // link forces, one thread per particle: its last bead pulled toward the
