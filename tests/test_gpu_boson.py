@@ -1,6 +1,13 @@
 """GPU parity of the bosonic exchange spring kernel (pimd_boson_spring, through
 the C ABI) against the oracle's recursion: V_B, the forces and the link
-probabilities, element by element."""
+probabilities, element by element.
+
+Bar: V_B to 1e-12 relative.  The kernel forms each ring energy as a
+difference of prefix sums, whose rounding is about eps * V_B in absolute
+terms, against the oracle's direct sums; every ring's weight
+exp(-beta_n (E + V - V)) then carries a relative error of about
+beta_n * eps * V_B.  The probabilities (absolute) and the forces (relative to
+their largest) are held to max(1e-12, 20 beta_n eps V_B)."""
 import sys
 
 import numpy as np
@@ -16,7 +23,7 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("N,P", [(1, 4), (2, 1), (3, 8), (17, 32), (64, 16), (300, 4)])
+@pytest.mark.parametrize("N,P", [(1, 4), (2, 1), (3, 8), (17, 32), (64, 16), (300, 4), (512, 2)])
 def test_boson_spring_matches_oracle(N, P):
     from paper_2602_13553_amd import pimd
     rng = np.random.default_rng(N * 131 + P)
@@ -29,9 +36,10 @@ def test_boson_spring_matches_oracle(N, P):
     vo, fo, po = oracle.boson_spring(x, k, b)
     ef = np.abs(f - fo).max() / max(np.abs(fo).max(), 1e-300)
     _say("  V %.15e / %.15e  f rel %.3e  prob %.3e" % (v, vo, ef, np.abs(prob - po).max()))
+    bar = max(1e-12, 20 * b * np.finfo(float).eps * abs(vo))
     assert abs(v - vo) <= 1e-12 * max(1.0, abs(vo))
-    assert ef <= 1e-12
-    assert np.abs(prob - po).max() <= 1e-12
+    assert ef <= bar, (ef, bar)
+    assert np.abs(prob - po).max() <= bar, (np.abs(prob - po).max(), bar)
 
 
 def test_boson_spring_errors():
