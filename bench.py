@@ -116,6 +116,27 @@ def sync(ctx):
     return ctx.estimators()
 
 
+def bench_boson():
+    """The bosonic exchange spring kernel (energy, forces, link
+    probabilities) per call, on N particles of P beads spread over a few
+    thermal lengths."""
+    import torch
+    from paper_2602_13553_amd import pimd
+    out = {}
+    for N, P in ((64, 32), (512, 8)):
+        rng = np.random.default_rng(N + P)
+        x = torch.tensor(rng.normal(0, 0.4, (P, N, 3)) + rng.normal(0, 1.2, (1, N, 3)),
+                         dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            pimd.boson_spring(x, 1.1, 0.9)
+        n = 50
+        t0 = time.perf_counter()
+        for _ in range(n):
+            pimd.boson_spring(x, 1.1, 0.9)
+        out["N%d_P%d_us_per_call" % (N, P)] = (time.perf_counter() - t0) / n * 1e6
+    return out
+
+
 def bench_npt(make):
     """The barostat's step (two passes with their finalizes, then the forces
     in the new box) on the LJ liquid, and on the shape of the paper's NpT
@@ -418,6 +439,8 @@ def main():
                          "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_fc).items()}}
         log("NpT (BZP barostat)")
         out["npt"] = bench_npt(make)
+        log("bosonic exchange kernel")
+        out["boson_spring"] = bench_boson()
         log("external forces")
         out["external_forces"] = bench_external()
         log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))
