@@ -99,6 +99,8 @@ def lib():
             "orc_baro_energies": (None, [S, C.POINTER(_Baro), C.c_double, d]),
             "orc_boson_spring": (C.c_double, [C.c_int32, C.c_int32, C.c_double, C.c_double, d, d,
                                               d]),
+            "orc_boson_forces": (C.c_double, [S, d, d, d]),
+            "orc_boson_step": (None, [S, d, d, d, d, d, u64, C.c_int32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -370,3 +372,33 @@ class State:
         lib().orc_estimators(C.byref(self._cs()), _dp(self.x), _dp(self.vt), _dp(self.f),
                              _dp(self.U), C.byref(e))
         return {n: getattr(e, n) for n in ESTIMATOR_NAMES}
+
+
+class BosonState:
+    """Bosonic ring polymers in Cartesian coordinates (the bosonic fix's
+    step): positions x and bead velocities v [P][N][3], total forces f."""
+
+    def __init__(self, system: System, x: np.ndarray, v: np.ndarray, step: int = 0):
+        if len(set(np.asarray(system.mass).tolist())) != 1:
+            raise ValueError("bosons of one species: all masses equal")
+        self.sys = system
+        self.x = np.ascontiguousarray(x, dtype=np.float64).copy()
+        self.v = np.ascontiguousarray(v, dtype=np.float64).copy()
+        self.f = np.zeros_like(self.x)
+        self.U = np.zeros(system.n_beads)
+        self.vb = np.zeros(1)
+        self.vb[0] = lib().orc_boson_forces(C.byref(system.cstruct()), _dp(self.x), _dp(self.f),
+                                            _dp(self.U))
+        self.step_count = np.array([step], dtype=np.uint64)
+
+    def step(self, n: int = 1) -> None:
+        lib().orc_boson_step(C.byref(self.sys.cstruct()), _dp(self.x), _dp(self.v), _dp(self.f),
+                             _dp(self.U), _dp(self.vb),
+                             self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)), int(n))
+
+    def energies(self) -> dict:
+        """K (Cartesian), the exchange spring energy V_B, U, H = K + V_B + U."""
+        m = np.asarray(self.sys.mass)[None, :, None]
+        k = float((0.5 * m * self.sys.mvv2e * self.v * self.v).sum())
+        u = float(self.U.sum())
+        return {"ekin": k, "vb": float(self.vb[0]), "epot": u, "etot": k + float(self.vb[0]) + u}

@@ -1021,3 +1021,58 @@ double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, con
 #undef XB
     return vb;
 }
+
+/* ------------------------------------------------------------------------
+ * The bosonic step in Cartesian coordinates (see the header).
+ * --------------------------------------------------------------------- */
+double orc_boson_forces(const orc_system *sys, const double *x, double *f, double *U)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double kT = sys->kB * sys->temp;
+    const double wn = omega_n(sys);
+    const double ks = 0.5 * sys->mass[0] * sys->mvv2e * wn * wn;
+    double *fs = (double *)malloc(sizeof(double) * n);
+    orc_forces(sys, x, f, U);
+    const double vb = orc_boson_spring(N, P, ks, 1.0 / ((double)P * kT), x, fs, NULL);
+    for (size_t e = 0; e < n; ++e) f[e] += fs[e];
+    free(fs);
+    return vb;
+}
+
+void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, double *U, double *vb,
+                    uint64_t *step, int32_t nsteps)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const double h = 0.5 * sys->dt;
+    const double kT = sys->kB * sys->temp;
+    const double c1 = sys->nve ? 1.0 : exp(-sys->dt / sys->tau), c2 = sqrt(1.0 - c1 * c1);
+    for (int32_t it = 0; it < nsteps; ++it) {
+        const uint64_t s = *step;
+        for (int32_t j = 0; j < P; ++j)
+            for (int32_t i = 0; i < N; ++i) {
+                const double im = 1.0 / (sys->mass[i] * sys->mvv2e);
+                const double sigma = sqrt((double)P * kT * im);
+                const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
+                double z[3] = {0.0, 0.0, 0.0};
+                if (!sys->nve) orc_gaussians(sys->seed, 0, id, (uint64_t)j, s, z);
+                for (int d = 0; d < 3; ++d) {
+                    const size_t e = ((size_t)j * N + i) * 3 + d;
+                    v[e] += h * f[e] * im;                 /* B */
+                    x[e] += h * v[e];                      /* A */
+                    v[e] = c1 * v[e] + c2 * sigma * z[d];  /* O */
+                    x[e] += h * v[e];                      /* A */
+                }
+            }
+        *vb = orc_boson_forces(sys, x, f, U);
+        for (int32_t j = 0; j < P; ++j)
+            for (int32_t i = 0; i < N; ++i) {
+                const double im = 1.0 / (sys->mass[i] * sys->mvv2e);
+                for (int d = 0; d < 3; ++d) {
+                    const size_t e = ((size_t)j * N + i) * 3 + d;
+                    v[e] += h * f[e] * im;                 /* B */
+                }
+            }
+        *step = s + 1;
+    }
+}

@@ -171,6 +171,19 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
  * bead 0 of particle l'. */
 double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
                         double *f, double *prob);
+/* The bosonic fix's step (Sec. III.C: Cartesian coordinates, since the normal
+ * modes change under exchange; the thermostat of Eq. D3), BAOAB in Cartesian
+ * bead velocities v [P][N][3]: B(dt/2) with the potential's forces plus the
+ * exchange springs' (orc_boson_spring, kspring = m mvv2e omega_n^2 / 2,
+ * beta_n = 1/(P kB T), masses all equal to mass[0]); A(dt/2) drift; O(dt)
+ * v <- c1 v + c2 sigma z with c1 = exp(-dt/tau) for every bead, sigma =
+ * sqrt(P kB T / (m mvv2e)), z from counter (atom, bead, step, 0); A(dt/2);
+ * forces; B(dt/2).  f holds the total forces of x, U the beads' potential
+ * energies, *vb the exchange spring energy; all are those of the new x. */
+void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, double *U, double *vb,
+                    uint64_t *step, int32_t nsteps);
+/* Total forces (potential + exchange springs), U per bead, returns V_B. */
+double orc_boson_forces(const orc_system *sys, const double *x, double *f, double *U);
 
 /* --- estimators (App. A) ----------------------------------------------- */
 /* At a synchronized state.  U is [P] from orc_forces. */

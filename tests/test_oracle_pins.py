@@ -954,3 +954,89 @@ def test_boson_limits():
     same = np.repeat(path, N, axis=1)
     v2, _, prob2 = oracle.boson_spring(same, k, b)
     assert abs(v2 - e_id) <= 1e-12 * e_id
+
+
+def _trapped_bosons(N, P, dt, nve, seed=3, spread=0.8):
+    rng = np.random.default_rng(seed)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.5, dt=dt,
+                      tau=0.1, nve=nve, pot=oracle.POT_HARMONIC, omega=1.0, seed=seed)
+    x = rng.normal(0, spread, (1, N, 3)) + rng.normal(0, 0.2, (P, N, 3))
+    v = rng.normal(0, math.sqrt(P * 1.0), (P, N, 3))
+    return s, x, v
+
+
+def test_boson_step_conserves_h_to_second_order():
+    """Without the thermostat the Cartesian step conserves H = K + V_B + U,
+    with a spread that falls fourfold when dt halves (three bosons that
+    exchange: particles within a thermal length of each other)."""
+    spreads = []
+    for dt in (0.004, 0.002):
+        s, x, v = _trapped_bosons(3, 8, dt, True)
+        st = oracle.BosonState(s, x, v)
+        h = []
+        for _ in range(int(round(2.0 / dt)) // 10):
+            st.step(10)
+            h.append(st.energies()["etot"])
+        spreads.append(np.ptp(h))
+    r = spreads[0] / spreads[1]
+    assert 3.3 < r < 4.7, spreads
+
+
+def test_boson_step_p1_is_velocity_verlet():
+    """One bead, one particle, no thermostat: the step is velocity Verlet in
+    the trap, written out by hand (the exchange term of one particle with one
+    bead is zero)."""
+    s, x, v = _trapped_bosons(1, 1, 0.01, True)
+    st = oracle.BosonState(s, x, v)
+    st.step(50)
+    xx, vv = x[0, 0].copy(), v[0, 0].copy()
+    w2 = s.omega ** 2
+    for _ in range(50):
+        vv = vv - 0.5 * s.dt * w2 * xx
+        xx = xx + s.dt * vv
+        vv = vv - 0.5 * s.dt * w2 * xx
+    assert np.abs(st.x[0, 0] - xx).max() <= 1e-13 and np.abs(st.v[0, 0] - vv).max() <= 1e-13
+
+
+def test_boson_far_apart_are_distinguishable_rings():
+    """Bosons far apart never exchange: two of them step exactly as two
+    separate one-particle systems with the same noise (atom ids)."""
+    s, x, v = _trapped_bosons(2, 6, 0.005, False, spread=0.0)
+    x = x.copy()
+    x[:, 1] += 40.0                                   # far apart (and in a weak trap)
+    s.omega = 1e-3
+    st = oracle.BosonState(s, x, v)
+    st.step(40)
+    for l in range(2):
+        s1 = oracle.System(n_atoms=1, n_beads=6, mass=np.ones(1), temp=1.0, hbar=0.5, dt=0.005,
+                           tau=0.1, pot=oracle.POT_HARMONIC, omega=1e-3, seed=3,
+                           atom_id=np.array([l]))
+        one = oracle.BosonState(s1, x[:, l:l + 1], v[:, l:l + 1])
+        one.step(40)
+        assert np.abs(one.x[:, 0] - st.x[:, l]).max() <= 1e-12 * np.abs(st.x).max()
+        assert np.abs(one.v[:, 0] - st.v[:, l]).max() <= 1e-11 * np.abs(st.v).max()
+
+
+def test_boson_thermostat_equipartition():
+    """With the Cartesian thermostat every bead velocity component has
+    <m v^2> = P kB T (Eq. D3 at the ring-polymer temperature P T)."""
+    s, x, v = _trapped_bosons(3, 4, 0.01, False, seed=8)
+    st = oracle.BosonState(s, x, v)
+    st.step(200)
+    acc = []
+    for _ in range(3000):
+        st.step(1)
+        acc.append((st.v * st.v).mean())
+    acc = np.array(acc)
+    blocks = acc.reshape(30, -1).mean(axis=1)
+    assert abs(blocks.mean() - 4.0) < 5 * blocks.std() / math.sqrt(30) + 0.02, blocks.mean()
+
+
+def test_boson_single_particle_spring_is_the_ring_polymer_spring():
+    """One particle has no partner: V_B is the distinguishable ring's spring
+    energy S of Eq. 1 (the oracle's estimator, pinned above), which fixes the
+    spring constant m omega_n^2 / 2 of the bosonic step."""
+    s, x, v = _trapped_bosons(1, 7, 0.01, True, seed=12)
+    b = oracle.BosonState(s, x, v)
+    e = oracle.State(s, x, v).estimators()
+    assert abs(b.energies()["vb"] - e["espring"]) <= 1e-12 * e["espring"]
