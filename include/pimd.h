@@ -307,6 +307,26 @@ int pimd_set_barostat(pimd_ctx *ctx, const double *box, double vw);
 int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
                       double *f, double *prob, double *v);
 
+/* The bosonic fix's step (Sec. III.C: Cartesian coordinates, since the normal
+ * modes change under exchange; the thermostat of Eq. D3) for N identical
+ * particles of one mass in a harmonic trap U = 1/2 m mvv2e omega^2 |r|^2 per
+ * bead (omega = 0: free): nsteps of BAOAB on Cartesian bead positions x and
+ * velocities v ([P][N][3], device, updated in place): B(dt/2) with the trap's
+ * and the exchange springs' forces (pimd_boson_spring with kspring =
+ * m mvv2e omega_n^2 / 2, omega_n = P kB T / hbar, beta_n = 1/(P kB T)),
+ * A(dt/2) drift, O(dt) v <- c1 v + c2 sqrt(P kB T/(m mvv2e)) z (c1 =
+ * exp(-dt/tau) on every bead when thermostat is 1, no O otherwise; z from
+ * counter (particle, bead, step, 0), step = step0, step0 + 1, ...), A(dt/2),
+ * forces, B(dt/2).  On return f ([P][N][3]) holds the forces of the final x,
+ * ubead ([P*N], bead-major) the trap energies, vb (one double) V_B; prob
+ * ([N][N]) is scratch (the final link probabilities).  All pointers are
+ * device memory; runs on the null stream and waits.
+ * Errors: ARG, UNSUPPORTED (N > 512, P > 128), DEVICE. */
+int pimd_boson_step(double *x, double *v, int32_t N, int32_t P, double mass, double temp, double kB,
+                    double hbar, double mvv2e, double dt, double tau, double omega, uint64_t seed,
+                    int32_t thermostat, uint64_t step0, int64_t nsteps, double *f, double *prob,
+                    double *ubead, double *vb);
+
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);
 

@@ -211,9 +211,72 @@ __global__ __launch_bounds__(kBlock) void k_boson_inner(const double *x, int N, 
     }
 }
 
+// The potential's forces added to the springs': a harmonic trap
+// U = 1/2 m mvv2e omega^2 |x|^2 per bead (kk = m mvv2e omega^2), and each
+// bead's U for the energies.
+__global__ __launch_bounds__(kBlock) void k_boson_trap(const double *x, int N, int P, double kk,
+                                                       double *f, double *ubead)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= N * P) return;
+    double r2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double xv = x[(size_t)e * 3 + d];
+        f[(size_t)e * 3 + d] -= kk * xv;
+        r2 += xv * xv;
+    }
+    ubead[e] = 0.5 * kk * r2;
+}
+
+// B(dt/2) A(dt/2) O(dt) A(dt/2) per bead velocity component (the opening of a
+// step), or B(dt/2) alone (the closing): Cartesian, every bead with the same
+// c1 (Eq. D3), noise of counter (particle, bead, step, 0).
+__global__ __launch_bounds__(kBlock) void k_boson_update(double *x, double *v, const double *f,
+                                                         int N, int P, double h, double im,
+                                                         double c1, double c2, double sigma,
+                                                         unsigned long long seed,
+                                                         unsigned long long step, int opening,
+                                                         int thermo)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= N * P) return;
+    const int j = e / N, l = e - j * N;
+    double z[3] = {0.0, 0.0, 0.0};
+    if (opening && thermo)
+        gauss3(seed, (unsigned long long)l, (unsigned long long)j, step, z, 0ULL);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const size_t q = (size_t)e * 3 + d;
+        double vv = v[q] + h * f[q] * im;
+        if (opening) {
+            double xx = x[q] + h * vv;
+            vv = c1 * vv + c2 * sigma * z[d];
+            x[q] = xx + h * vv;
+        }
+        v[q] = vv;
+    }
+}
+
 }  // namespace
 
 int boson_max() { return kBosonMax; }
+
+void launch_boson_forces(const double *x, int N, int P, double kspring, double beta_n, double kk,
+                         double *f, double *prob, double *ubead, double *vb, hipStream_t st)
+{
+    launch_boson_spring(x, N, P, kspring, beta_n, f, prob, vb, st);
+    hipLaunchKernelGGL(k_boson_trap, dim3((N * P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, x, N,
+                       P, kk, f, ubead);
+}
+
+void launch_boson_update(double *x, double *v, const double *f, int N, int P, double h, double im,
+                         double c1, double c2, double sigma, unsigned long long seed,
+                         unsigned long long step, int opening, int thermo, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_boson_update, dim3((N * P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, x,
+                       v, f, N, P, h, im, c1, c2, sigma, seed, step, opening, thermo);
+}
 
 void launch_boson_spring(const double *x, int N, int P, double kspring, double beta_n, double *f,
                          double *prob, double *out, hipStream_t st)

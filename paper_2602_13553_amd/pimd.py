@@ -36,7 +36,7 @@ ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "p
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_set_barostat",
-            "pimd_boson_spring",
+            "pimd_boson_spring", "pimd_boson_step",
             "pimd_reset_averages",
             "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
@@ -114,6 +114,8 @@ def load() -> C.CDLL:
         lib.pimd_get_barostat.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
         lib.pimd_boson_spring.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                           C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.pimd_boson_step.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32] + \
+            [C.c_double] * 8 + [C.c_uint64, C.c_int32, C.c_uint64, C.c_int64] + [C.c_void_p] * 4
         lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), C.c_double]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
@@ -219,6 +221,31 @@ def boson_spring(x, kspring: float, beta_n: float):
         msg = lib.pimd_last_error(None)
         raise PimdError(rc, msg.decode() if msg else "")
     return float(v.item()), f, prob
+
+
+def boson_step(x, v, mass: float, temp: float, kB: float, hbar: float, mvv2e: float, dt: float,
+               tau: float, omega: float, seed: int, thermostat: bool, step0: int, nsteps: int):
+    """The bosonic fix's Cartesian step on the GPU (pimd_boson_step): returns
+    the new x, v ([P][N][3] torch CUDA tensors), the forces, the beads' trap
+    energies [P][N] and V_B."""
+    import torch
+    lib = load()
+    xd = torch.as_tensor(x, dtype=torch.float64, device="cuda").clone().contiguous()
+    vd = torch.as_tensor(v, dtype=torch.float64, device="cuda").clone().contiguous()
+    P, N, _ = xd.shape
+    f = torch.empty_like(xd)
+    prob = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    ub = torch.empty((P, N), dtype=torch.float64, device="cuda")
+    vb = torch.empty(1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    rc = lib.pimd_boson_step(xd.data_ptr(), vd.data_ptr(), int(N), int(P), mass, temp, kB, hbar,
+                             mvv2e, dt, tau, omega, int(seed), 1 if thermostat else 0, int(step0),
+                             int(nsteps), f.data_ptr(), prob.data_ptr(), ub.data_ptr(),
+                             vb.data_ptr())
+    if rc != PIMD_OK:
+        msg = lib.pimd_last_error(None)
+        raise PimdError(rc, msg.decode() if msg else "")
+    return xd, vd, f, ub, float(vb.item())
 
 
 class Context:

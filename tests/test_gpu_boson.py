@@ -48,3 +48,29 @@ def test_boson_spring_errors():
         pimd.boson_spring(np.zeros((2, 513, 3)), 1.0, 1.0)
     with pytest.raises(pimd.PimdError):
         pimd.boson_spring(np.zeros((2, 3, 3)), 1.0, 0.0)
+
+
+@pytest.mark.parametrize("N,P,thermo", [(3, 8, True), (5, 4, False), (1, 1, True), (40, 16, True)])
+def test_boson_step_matches_oracle(N, P, thermo):
+    """The bosonic Cartesian step (pimd_boson_step) against the oracle's
+    orc_boson_step: 20 steps of trapped bosons, positions and velocities
+    element by element, V_B and the beads' trap energies."""
+    from paper_2602_13553_amd import pimd
+    rng = np.random.default_rng(7 * N + P)
+    dt, tau, hbar, omega, seed = 0.005, 0.1, 0.5, 1.0, 11
+    x = rng.normal(0, 0.8, (1, N, 3)) + rng.normal(0, 0.2, (P, N, 3))
+    v = rng.normal(0, np.sqrt(P), (P, N, 3))
+    _say("case boson step N=%d P=%d thermostat=%d" % (N, P, thermo))
+    gx, gv, gf, gu, gvb = pimd.boson_step(x, v, 1.0, 1.0, 1.0, hbar, 1.0, dt, tau, omega, seed,
+                                          thermo, 0, 20)
+    gx, gv, gu = gx.cpu().numpy(), gv.cpu().numpy(), gu.cpu().numpy()
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=hbar, dt=dt, tau=tau,
+                      nve=not thermo, pot=oracle.POT_HARMONIC, omega=omega, seed=seed)
+    st = oracle.BosonState(s, x, v)
+    st.step(20)
+    ex = np.abs(gx - st.x).max() / np.abs(st.x).max()
+    ev = np.abs(gv - st.v).max() / np.abs(st.v).max()
+    _say("  x rel %.3e  v rel %.3e  V_B %.12e / %.12e" % (ex, ev, gvb, st.vb[0]))
+    assert ex <= 1e-12 and ev <= 1e-12
+    assert abs(gvb - st.vb[0]) <= 1e-12 * max(1.0, abs(st.vb[0]))
+    assert np.abs(gu.sum(axis=1) - st.U).max() <= 1e-12 * max(1.0, np.abs(st.U).max())
