@@ -12,7 +12,11 @@ LIB = os.path.join(HERE, "libpimd.so")
 SOURCES = ["pimd_kernels.hip", "pimd_fused_mfma.hip", "pimd_npt.hip", "pimd_boson.hip",
            "pimd_api.hip"]
 
-# Packed FP32 instructions are disabled for every HIP translation unit.
+# Packed FP32 instructions (v_pk_*_f32) are disabled for every HIP translation
+# unit.  The host pass prints "'-packed-fp32-ops' is not a recognized feature
+# for this target": it has no such feature and ignores it.  The gfx950 device
+# pass honours it: a float2 multiply-add kernel compiles to v_pk_fma_f32
+# without the flag and to none with it (tests/test_build_flags.py).
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

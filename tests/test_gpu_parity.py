@@ -183,9 +183,10 @@ def test_water_full_size_p32():
     check_states(g, o)
 
 
-def test_water_full_size_p64_short():
+def test_water_full_size_p64():
+    """N=32766, P=64 (the largest water-shaped workload), 10 steps."""
     spec = inputs.water(n_beads=64)
-    g, o = run_pair(spec, 3)
+    g, o = run_pair(spec, 10)
     check_states(g, o)
 
 
