@@ -932,91 +932,115 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
  * recursion (each V[n] is a soft minimum of E[n,k] + V[n-k] with weights
  * w[n,k] = exp(-beta_n (E[n,k] + V[n-k] - V[n])) / n summing to one).
  * Plain O(N^3 P): every E[n,k] is summed out, no prefix sums.
+ *
+ * Extended precision: every energy, V[n], weight, adjoint and probability is
+ * held in x87 extended precision (64-bit significand) and rounded to FP64
+ * once, at the output.  The exponent of each weight is a difference of
+ * quantities of the size of V_B (every E[n,k] + V[n-k] carries all inner
+ * ring energies), so FP64 arithmetic would leave a relative error of about
+ * beta_n eps V_B in the weights, 1e-12 and more at a few hundred particles.
+ * The steps and their order are those of the FP64 recursion.
  * --------------------------------------------------------------------- */
-static double orc_sq3(const double *a, const double *b)
+static long double orc_sq3l(const double *a, const double *b)
 {
-    double s = 0.0;
-    for (int d = 0; d < 3; ++d) s += (a[d] - b[d]) * (a[d] - b[d]);
+    long double s = 0.0L;
+    for (int d = 0; d < 3; ++d) {
+        const long double u = (long double)a[d] - (long double)b[d];
+        s += u * u;
+    }
     return s;
 }
 
 double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
-                        double *f, double *prob)
+                        double *f, double *prob, double *ev)
 {
     /* bead j of particle l (0-based) at x + (j*N + l)*3 */
 #define XB(j, l) (x + ((size_t)(j) * N + (l)) * 3)
-    double *eint = (double *)calloc((size_t)N, sizeof(double));
-    double *link = (double *)calloc((size_t)N * N, sizeof(double));   /* [l][l'] */
-    double *E = (double *)calloc((size_t)(N + 1) * (N + 1), sizeof(double));   /* E[n][k] */
-    double *V = (double *)calloc((size_t)(N + 1), sizeof(double));
-    double *w = (double *)calloc((size_t)(N + 1) * (N + 1), sizeof(double));
-    double *adj = (double *)calloc((size_t)(N + 1), sizeof(double));
-    double *pl = (double *)calloc((size_t)N * N, sizeof(double));
+    typedef long double ld;
+    const ld ks = (ld)kspring, bn = (ld)beta_n;
+    ld *eint = (ld *)calloc((size_t)N, sizeof(ld));
+    ld *link = (ld *)calloc((size_t)N * N, sizeof(ld));   /* [l][l'] */
+    ld *E = (ld *)calloc((size_t)(N + 1) * (N + 1), sizeof(ld));   /* E[n][k] */
+    ld *V = (ld *)calloc((size_t)(N + 1), sizeof(ld));
+    ld *w = (ld *)calloc((size_t)(N + 1) * (N + 1), sizeof(ld));
+    ld *adj = (ld *)calloc((size_t)(N + 1), sizeof(ld));
+    ld *pl = (ld *)calloc((size_t)N * N, sizeof(ld));
     for (int32_t l = 0; l < N; ++l)
-        for (int32_t j = 0; j + 1 < P; ++j) eint[l] += kspring * orc_sq3(XB(j + 1, l), XB(j, l));
+        for (int32_t j = 0; j + 1 < P; ++j) eint[l] += ks * orc_sq3l(XB(j + 1, l), XB(j, l));
     for (int32_t l = 0; l < N; ++l)
-        for (int32_t l2 = 0; l2 < N; ++l2) link[(size_t)l * N + l2] = kspring * orc_sq3(XB(0, l2), XB(P - 1, l));
+        for (int32_t l2 = 0; l2 < N; ++l2) link[(size_t)l * N + l2] = ks * orc_sq3l(XB(0, l2), XB(P - 1, l));
     /* E[n][k]: ring through particles n-k .. n-1 (0-based), in order, closed
      * from n-1 back to n-k */
     for (int32_t n = 1; n <= N; ++n)
         for (int32_t k = 1; k <= n; ++k) {
-            double e = 0.0;
+            ld e = 0.0L;
             for (int32_t l = n - k; l < n; ++l) e += eint[l];
             for (int32_t l = n - k; l + 1 < n; ++l) e += link[(size_t)l * N + l + 1];
             e += link[(size_t)(n - 1) * N + (n - k)];
             E[(size_t)n * (N + 1) + k] = e;
         }
-    V[0] = 0.0;
+    V[0] = 0.0L;
     for (int32_t n = 1; n <= N; ++n) {
-        double lo = INFINITY;
+        ld lo = INFINITY;
         for (int32_t k = 1; k <= n; ++k) {
-            const double a = E[(size_t)n * (N + 1) + k] + V[n - k];
+            const ld a = E[(size_t)n * (N + 1) + k] + V[n - k];
             if (a < lo) lo = a;
         }
-        double s = 0.0;
+        ld s = 0.0L;
         for (int32_t k = 1; k <= n; ++k)
-            s += exp(-beta_n * (E[(size_t)n * (N + 1) + k] + V[n - k] - lo));
-        V[n] = lo - log(s / (double)n) / beta_n;
+            s += expl(-bn * (E[(size_t)n * (N + 1) + k] + V[n - k] - lo));
+        V[n] = lo - logl(s / (ld)n) / bn;
         for (int32_t k = 1; k <= n; ++k)
             w[(size_t)n * (N + 1) + k] =
-                exp(-beta_n * (E[(size_t)n * (N + 1) + k] + V[n - k] - V[n])) / (double)n;
+                expl(-bn * (E[(size_t)n * (N + 1) + k] + V[n - k] - V[n])) / (ld)n;
+    }
+    /* the weighted ring energy of the primitive estimator */
+    if (ev) {
+        ld *EV = (ld *)calloc((size_t)(N + 1), sizeof(ld));
+        for (int32_t n = 1; n <= N; ++n)
+            for (int32_t k = 1; k <= n; ++k)
+                EV[n] += w[(size_t)n * (N + 1) + k] * (E[(size_t)n * (N + 1) + k] + EV[n - k]);
+        *ev = (double)EV[N];
+        free(EV);
     }
     /* adjoints: adj[n] = dV[N]/dV[n]; dV[N]/dE[n][k] = adj[n] w[n][k] */
-    adj[N] = 1.0;
+    adj[N] = 1.0L;
     for (int32_t n = N; n >= 1; --n)
         for (int32_t k = 1; k <= n; ++k) adj[n - k] += adj[n] * w[(size_t)n * (N + 1) + k];
     /* link probabilities: the weight every E[n][k] gives each of its links */
     for (int32_t n = 1; n <= N; ++n)
         for (int32_t k = 1; k <= n; ++k) {
-            const double q = adj[n] * w[(size_t)n * (N + 1) + k];
+            const ld q = adj[n] * w[(size_t)n * (N + 1) + k];
             for (int32_t l = n - k; l + 1 < n; ++l) pl[(size_t)l * N + l + 1] += q;
             pl[(size_t)(n - 1) * N + (n - k)] += q;
         }
     if (prob)
-        for (size_t e = 0; e < (size_t)N * N; ++e) prob[e] = pl[e];
+        for (size_t e = 0; e < (size_t)N * N; ++e) prob[e] = (double)pl[e];
     if (f) {
-        for (size_t e = 0; e < (size_t)P * N * 3; ++e) f[e] = 0.0;
+        ld *fl = (ld *)calloc((size_t)P * N * 3, sizeof(ld));
         /* springs inside every ring: weight one (each particle lies on one cycle) */
         for (int32_t l = 0; l < N; ++l)
             for (int32_t j = 0; j + 1 < P; ++j)
                 for (int d = 0; d < 3; ++d) {
-                    const double g = 2.0 * kspring * (XB(j + 1, l)[d] - XB(j, l)[d]);
-                    f[((size_t)(j + 1) * N + l) * 3 + d] -= g;
-                    f[((size_t)j * N + l) * 3 + d] += g;
+                    const ld g = 2.0L * ks * ((ld)XB(j + 1, l)[d] - (ld)XB(j, l)[d]);
+                    fl[((size_t)(j + 1) * N + l) * 3 + d] -= g;
+                    fl[((size_t)j * N + l) * 3 + d] += g;
                 }
         /* links, weighted by their probabilities */
         for (int32_t l = 0; l < N; ++l)
             for (int32_t l2 = 0; l2 < N; ++l2) {
-                const double q = pl[(size_t)l * N + l2];
-                if (q == 0.0) continue;
+                const ld q = pl[(size_t)l * N + l2];
+                if (q == 0.0L) continue;
                 for (int d = 0; d < 3; ++d) {
-                    const double g = 2.0 * kspring * q * (XB(0, l2)[d] - XB(P - 1, l)[d]);
-                    f[((size_t)0 * N + l2) * 3 + d] -= g;
-                    f[((size_t)(P - 1) * N + l) * 3 + d] += g;
+                    const ld g = 2.0L * ks * q * ((ld)XB(0, l2)[d] - (ld)XB(P - 1, l)[d]);
+                    fl[((size_t)0 * N + l2) * 3 + d] -= g;
+                    fl[((size_t)(P - 1) * N + l) * 3 + d] += g;
                 }
             }
+        for (size_t e = 0; e < (size_t)P * N * 3; ++e) f[e] = (double)fl[e];
+        free(fl);
     }
-    const double vb = V[N];
+    const double vb = (double)V[N];
     free(eint); free(link); free(E); free(V); free(w); free(adj); free(pl);
 #undef XB
     return vb;
@@ -1034,7 +1058,7 @@ double orc_boson_forces(const orc_system *sys, const double *x, double *f, doubl
     const double ks = 0.5 * sys->mass[0] * sys->mvv2e * wn * wn;
     double *fs = (double *)malloc(sizeof(double) * n);
     orc_forces(sys, x, f, U);
-    const double vb = orc_boson_spring(N, P, ks, 1.0 / ((double)P * kT), x, fs, NULL);
+    const double vb = orc_boson_spring(N, P, ks, 1.0 / ((double)P * kT), x, fs, NULL, NULL);
     for (size_t e = 0; e < n; ++e) f[e] += fs[e];
     free(fs);
     return vb;

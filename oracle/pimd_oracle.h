@@ -168,9 +168,15 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
  * E[n,k] the energy of the single ring through particles n-k+1..n (1-based).
  * Returns V_B = V[N]; f (may be NULL) receives -dV_B/dx for every bead; prob
  * (may be NULL, [N][N]) the probability that bead P-1 of particle l links to
- * bead 0 of particle l'. */
+ * bead 0 of particle l'; ev (may be NULL) the ring energy averaged over the
+ * recursion's terms with their weights,
+ *   EV[0] = 0,  EV[n] = sum_{k=1..n} w[n,k] (E[n,k] + EV[n-k]),  *ev = EV[N],
+ * w[n,k] = exp(-beta_n (E[n,k] + V[n-k] - V[n])) / n: the spring energy that
+ * the bosonic primitive kinetic energy estimator (App. A's bosonic list, item
+ * 5) subtracts, K_PR = 3 P N kB T / 2 - EV[N] / P (with the 1/P of the
+ * distinguishable K_PR; EV[N] = d(beta_n V_B)/d(beta_n) at fixed positions). */
 double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
-                        double *f, double *prob);
+                        double *f, double *prob, double *ev);
 /* The bosonic fix's step (Sec. III.C: Cartesian coordinates, since the normal
  * modes change under exchange; the thermostat of Eq. D3), BAOAB in Cartesian
  * bead velocities v [P][N][3]: B(dt/2) with the potential's forces plus the

@@ -1040,3 +1040,35 @@ def test_boson_single_particle_spring_is_the_ring_polymer_spring():
     b = oracle.BosonState(s, x, v)
     e = oracle.State(s, x, v).estimators()
     assert abs(b.energies()["vb"] - e["espring"]) <= 1e-12 * e["espring"]
+
+
+@pytest.mark.parametrize("N,P", [(1, 5), (3, 4), (6, 2)])
+def test_boson_ev_is_the_beta_derivative(N, P):
+    """The primitive estimator's weighted ring energy EV[N] is the derivative
+    of beta_n V_B by beta_n at fixed positions (exp(-beta_n V_B) is a weighted
+    sum of exp(-beta_n E) over the recursion's terms), by central differences;
+    and it equals the inner ring energies plus every link's energy times its
+    probability, the same average taken link by link."""
+    rng = np.random.default_rng(5 * N + P)
+    x = rng.normal(0, 0.5, (P, N, 3)) + rng.normal(0, 0.9, (1, N, 3))
+    k, b, h = 1.2, 0.7, 1e-5
+    v, _, prob, ev = oracle.boson_spring(x, k, b, with_ev=True)
+    vp = oracle.boson_spring(x, k, b + h)[0]
+    vm = oracle.boson_spring(x, k, b - h)[0]
+    num = ((b + h) * vp - (b - h) * vm) / (2 * h)
+    assert abs(num - ev) <= 1e-7 * abs(ev), (num, ev)
+    eint = sum(k * ((x[j + 1] - x[j]) ** 2).sum() for j in range(P - 1))
+    link = np.array([[k * ((x[0, m] - x[P - 1, l]) ** 2).sum() for m in range(N)] for l in range(N)])
+    assert abs(eint + (prob * link).sum() - ev) <= 1e-12 * abs(ev)
+
+
+def test_boson_ev_far_apart_is_the_distinguishable_spring():
+    """Bosons far apart: only the identity term counts, so EV is the springs
+    of N separate rings and K_PR is the distinguishable one."""
+    rng = np.random.default_rng(9)
+    N, P, k, b = 4, 6, 1.0, 1.5
+    path = rng.normal(0, 0.3, (P, N, 3))
+    far = path + 60.0 * np.arange(N)[None, :, None] * np.array([0.0, 1.0, 0.0])
+    _, _, _, ev = oracle.boson_spring(far, k, b, with_ev=True)
+    e_id = sum(k * ((far[(j + 1) % P] - far[j]) ** 2).sum() for j in range(P))
+    assert abs(ev - e_id) <= 1e-12 * e_id
