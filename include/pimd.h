@@ -156,12 +156,18 @@ typedef struct pimd_params {
  *                               per block (P >= 8; blocks whose cluster is too
  *                               wide for the box fall back to per-atom lists)
  *   PIMD_FLAG_ATOM_PAIRS        force pass on per-atom lists only
+ *   PIMD_FLAG_NO_GRAPHS         pimd_step launches every step's kernels one
+ *                               by one instead of replaying a captured
+ *                               hipGraph (for callers that capture the stream
+ *                               themselves); this is also the path a context
+ *                               takes when the capture fails
  * Results do not depend on the launch shape beyond the rounding of the
  * transforms (MFMA and VALU sum in different orders). */
 #define PIMD_FLAG_VALU_TRANSFORMS 1
 #define PIMD_FLAG_MFMA_TRANSFORMS 2
 #define PIMD_FLAG_CLUSTER_PAIRS 4
 #define PIMD_FLAG_ATOM_PAIRS 8
+#define PIMD_FLAG_NO_GRAPHS 16
 #define PIMD_PAIR_SUBGROUPS_SHIFT 8
 #define PIMD_PAIR_SUBGROUPS_MASK (0xF << PIMD_PAIR_SUBGROUPS_SHIFT)
 #define PIMD_PAIR_SUBGROUPS(S)                                                   \

@@ -117,7 +117,7 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
     }
     {
         const int known = PIMD_FLAG_VALU_TRANSFORMS | PIMD_FLAG_MFMA_TRANSFORMS | PIMD_PAIR_SUBGROUPS_MASK |
-                          PIMD_FLAG_CLUSTER_PAIRS | PIMD_FLAG_ATOM_PAIRS;
+                          PIMD_FLAG_CLUSTER_PAIRS | PIMD_FLAG_ATOM_PAIRS | PIMD_FLAG_NO_GRAPHS;
         const int code = (p->flags & PIMD_PAIR_SUBGROUPS_MASK) >> PIMD_PAIR_SUBGROUPS_SHIFT;
         if (p->flags & ~known) { why = "unknown bits in flags"; return PIMD_ERR_ARG; }
         if (code > 5 || (code > 0 && (1 << (code - 1)) * p->n_beads > kBlock)) {
@@ -534,6 +534,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     pimd_ctx *c = new (std::nothrow) pimd_ctx();
     if (!c) return fail(nullptr, PIMD_ERR_OOM, "host allocation failed");
     c->p = *p;
+    c->graph_failed = (p->flags & PIMD_FLAG_NO_GRAPHS) != 0;
     int n_active = 0;
     c->orig = internal_order(p, topo, &n_active);
     const int N = p->n_atoms, P = p->n_beads;
@@ -811,7 +812,6 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 if (c->graph) (void)hipGraphDestroy(c->graph);
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
                 c->graph = nullptr;
                 c->graph_exec = nullptr;
                 c->graph_failed = true;

@@ -25,6 +25,7 @@ PIMD_FLAG_VALU_TRANSFORMS = 1
 PIMD_FLAG_MFMA_TRANSFORMS = 2
 PIMD_FLAG_CLUSTER_PAIRS = 4
 PIMD_FLAG_ATOM_PAIRS = 8
+PIMD_FLAG_NO_GRAPHS = 16
 PIMD_PAIR_SUBGROUPS_SHIFT = 8
 
 

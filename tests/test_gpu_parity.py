@@ -349,6 +349,30 @@ def test_bitwise_deterministic_and_graph_equivalent():
         assert np.array_equal(x, outs[0][0]) and np.array_equal(p, outs[0][1]) and s == 64
 
 
+def test_no_graph_path_with_profiling():
+    """PIMD_FLAG_NO_GRAPHS takes the path a context falls back to when graph
+    capture fails: every step launched one by one.  Profiling, stepping and
+    destroying the context then work, the profile counts every launch, and
+    the trajectory equals the graph-replayed one bit for bit."""
+    spec = inputs.lj_liquid(n_atoms=500, n_beads=16, seed=2)
+    pimd = _pimd()
+    outs = []
+    for flags in (0, pimd.PIMD_FLAG_NO_GRAPHS):
+        ctx = pimd.Context.from_spec(spec, flags=flags)
+        ctx.set_state(spec.x0, spec.v0, 0)
+        ctx.step(64)
+        ctx.profile_begin()
+        ctx.step(64)
+        prof = ctx.profile_end()
+        ctx.step(64)
+        outs.append(ctx.get_state())
+        ctx.close()
+        assert sum(n for n, _ in prof.values()) >= 2 * 64, prof
+        assert all(ms >= 0.0 for _, ms in prof.values()), prof
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2] == 192
+
+
 def test_checkpoint_restart():
     spec = inputs.lj_liquid(n_atoms=256, n_beads=8, seed=8)
     pimd = _pimd()
