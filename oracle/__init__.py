@@ -98,7 +98,7 @@ def lib():
             "orc_npt_step": (None, [S, C.POINTER(_Baro), d, d, d, d, u64, C.c_int32]),
             "orc_baro_energies": (None, [S, C.POINTER(_Baro), C.c_double, d]),
             "orc_boson_spring": (C.c_double, [C.c_int32, C.c_int32, C.c_double, C.c_double, d, d,
-                                              d, d]),
+                                              d, d, d]),
             "orc_boson_forces": (C.c_double, [S, d, d, d]),
             "orc_boson_step": (None, [S, d, d, d, d, d, u64, C.c_int32]),
         }
@@ -150,17 +150,19 @@ def philox4x64_10(ctr, key) -> list[int]:
     return [int(v) for v in o]
 
 
-def boson_spring(x: np.ndarray, kspring: float, beta_n: float, with_ev: bool = False):
+def boson_spring(x: np.ndarray, kspring: float, beta_n: float, with_ev: bool = False, box=None):
     """Bosonic exchange spring energy V_B of bead positions x [P][N][3], its
     forces -dV_B/dx and the link probabilities [N][N] (l's last bead to l''s
     first); with_ev: also the weighted ring energy EV of the primitive
-    estimator."""
+    estimator; box: periodic box lengths (links under the minimum image)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     P, N, _ = x.shape
     f = np.zeros_like(x)
     prob = np.zeros((N, N))
     ev = np.zeros(1)
-    v = lib().orc_boson_spring(N, P, kspring, beta_n, _dp(x), _dp(f), _dp(prob), _dp(ev))
+    bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    v = lib().orc_boson_spring(N, P, kspring, beta_n, _dp(x), None if bx is None else _dp(bx),
+                               _dp(f), _dp(prob), _dp(ev))
     return (v, f, prob, float(ev[0])) if with_ev else (v, f, prob)
 
 

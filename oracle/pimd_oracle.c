@@ -951,8 +951,21 @@ static long double orc_sq3l(const double *a, const double *b)
     return s;
 }
 
+/* a - b, under the minimum image in every dimension with box[d] > 0 (box may
+ * be NULL: no periodicity); the image is chosen in double precision, like
+ * the pair forces' minimum image. */
+static void orc_link_vec(const double *a, const double *b, const double *box, long double out[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        double u = a[d] - b[d];
+        long double ul = (long double)a[d] - (long double)b[d];
+        if (box && box[d] > 0.0) ul -= (long double)box[d] * (long double)nearbyint(u / box[d]);
+        out[d] = ul;
+    }
+}
+
 double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
-                        double *f, double *prob, double *ev)
+                        const double *box, double *f, double *prob, double *ev)
 {
     /* bead j of particle l (0-based) at x + (j*N + l)*3 */
 #define XB(j, l) (x + ((size_t)(j) * N + (l)) * 3)
@@ -968,7 +981,11 @@ double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, con
     for (int32_t l = 0; l < N; ++l)
         for (int32_t j = 0; j + 1 < P; ++j) eint[l] += ks * orc_sq3l(XB(j + 1, l), XB(j, l));
     for (int32_t l = 0; l < N; ++l)
-        for (int32_t l2 = 0; l2 < N; ++l2) link[(size_t)l * N + l2] = ks * orc_sq3l(XB(0, l2), XB(P - 1, l));
+        for (int32_t l2 = 0; l2 < N; ++l2) {
+            long double dv[3];
+            orc_link_vec(XB(0, l2), XB(P - 1, l), box, dv);
+            link[(size_t)l * N + l2] = ks * (dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        }
     /* E[n][k]: ring through particles n-k .. n-1 (0-based), in order, closed
      * from n-1 back to n-k */
     for (int32_t n = 1; n <= N; ++n)
@@ -1031,8 +1048,10 @@ double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, con
             for (int32_t l2 = 0; l2 < N; ++l2) {
                 const ld q = pl[(size_t)l * N + l2];
                 if (q == 0.0L) continue;
+                long double dv[3];
+                orc_link_vec(XB(0, l2), XB(P - 1, l), box, dv);
                 for (int d = 0; d < 3; ++d) {
-                    const ld g = 2.0L * ks * q * ((ld)XB(0, l2)[d] - (ld)XB(P - 1, l)[d]);
+                    const ld g = 2.0L * ks * q * dv[d];
                     fl[((size_t)0 * N + l2) * 3 + d] -= g;
                     fl[((size_t)(P - 1) * N + l) * 3 + d] += g;
                 }
@@ -1058,7 +1077,7 @@ double orc_boson_forces(const orc_system *sys, const double *x, double *f, doubl
     const double ks = 0.5 * sys->mass[0] * sys->mvv2e * wn * wn;
     double *fs = (double *)malloc(sizeof(double) * n);
     orc_forces(sys, x, f, U);
-    const double vb = orc_boson_spring(N, P, ks, 1.0 / ((double)P * kT), x, fs, NULL, NULL);
+    const double vb = orc_boson_spring(N, P, ks, 1.0 / ((double)P * kT), x, sys->box, fs, NULL, NULL);
     for (size_t e = 0; e < n; ++e) f[e] += fs[e];
     free(fs);
     return vb;

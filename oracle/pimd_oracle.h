@@ -163,6 +163,9 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
  *   exp(-beta_n V_B) = (1/N!) sum_sigma exp(-beta_n E_sigma),
  * E_sigma = sum_l E_int(l) + sum_l link(l, sigma(l)), with
  * link(l, l') = kspring |x_l'^0 - x_l^(P-1)|^2 and kspring = m omega_n^2 / 2.
+ * box (may be NULL; [3], 0 = not periodic in that dimension): each link's
+ * vector is taken under the minimum image (the springs inside a particle's
+ * ring use its unwrapped coordinates).
  * The recursion over cycles: V[0] = 0,
  *   exp(-beta_n V[n]) = (1/n) sum_{k=1..n} exp(-beta_n (E[n,k] + V[n-k])),
  * E[n,k] the energy of the single ring through particles n-k+1..n (1-based).
@@ -176,7 +179,7 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
  * 5) subtracts, K_PR = 3 P N kB T / 2 - EV[N] / P (with the 1/P of the
  * distinguishable K_PR; EV[N] = d(beta_n V_B)/d(beta_n) at fixed positions). */
 double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
-                        double *f, double *prob, double *ev);
+                        const double *box, double *f, double *prob, double *ev);
 /* The bosonic fix's step (Sec. III.C: Cartesian coordinates, since the normal
  * modes change under exchange; the thermostat of Eq. D3), BAOAB in Cartesian
  * bead velocities v [P][N][3]: B(dt/2) with the potential's forces plus the

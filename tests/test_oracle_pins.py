@@ -956,6 +956,90 @@ def test_boson_limits():
     assert abs(v2 - e_id) <= 1e-12 * e_id
 
 
+def _mic(d, box):
+    """Minimum image of the vectors d [..., 3] in the periodic box."""
+    L = np.asarray(box, dtype=np.float64)
+    return d - L * np.rint(d / L)
+
+
+def _ring_energy_box(x, kspring, order, box):
+    """_ring_energy with each link between particles (bead P-1 to the next
+    particle's bead 0) under the minimum image; a particle's own springs in
+    its unwrapped coordinates."""
+    P = x.shape[0]
+    e = 0.0
+    for a, l in enumerate(order):
+        e += kspring * ((x[1:, l] - x[:-1, l]) ** 2).sum()
+        nxt = order[(a + 1) % len(order)]
+        e += kspring * (_mic(x[0, nxt] - x[P - 1, l], box) ** 2).sum()
+    return e
+
+
+@pytest.mark.parametrize("N,P", [(2, 3), (4, 2), (5, 3)])
+def test_boson_periodic_links_unrolled(N, P):
+    """In a periodic box the recursion equals its compositions written out
+    with every link under the minimum image: particles spread over a small
+    box so that many links cross a face."""
+    rng = np.random.default_rng(5 * N + P)
+    box = np.array([2.1, 2.6, 3.0])
+    x = rng.normal(0, 0.3, (P, N, 3)) + rng.uniform(0, 1, (1, N, 3)) * box
+    # particles 0 and 1 on either side of the x face, so that their links
+    # cross it
+    x[:, 0, 0] += 0.15 - x[:, 0, 0].mean()
+    x[:, 1, 0] += box[0] - 0.15 - x[:, 1, 0].mean()
+    k, b = 1.2, 0.7
+    v, f, prob = oracle.boson_spring(x, k, b, box=box)
+    terms = [(c, rings, sum(_ring_energy_box(x, k, r, box) for r in rings))
+             for c, rings in _compositions(N)]
+    lo = min(e for _, _, e in terms)
+    z = sum(c * math.exp(-b * (e - lo)) for c, _, e in terms)
+    assert abs(v - (lo - math.log(z) / b)) <= 1e-12 * max(1.0, abs(v))
+    pr = np.zeros((N, N))
+    for c, rings, e in terms:
+        wt = c * math.exp(-b * (e - lo)) / z
+        for r in rings:
+            for a, l in enumerate(r):
+                pr[l, r[(a + 1) % len(r)]] += wt
+    assert np.abs(prob - pr).max() <= 1e-12
+    # without the box the same positions give another potential
+    assert abs(oracle.boson_spring(x, k, b)[0] - v) > 1e-3 * abs(v)
+
+
+def test_boson_periodic_translation_invariance():
+    """Moving one particle's whole ring by a box vector changes nothing; the
+    forces are minus the gradient in the box (central differences)."""
+    rng = np.random.default_rng(17)
+    N, P, k, b = 6, 4, 0.9, 1.1
+    box = np.array([3.0, 3.0, 3.0])
+    x = rng.normal(0, 0.25, (P, N, 3)) + rng.uniform(0, 1, (1, N, 3)) * box
+    v, f, prob = oracle.boson_spring(x, k, b, box=box)
+    y = x.copy()
+    y[:, 2] += box * np.array([1.0, -2.0, 1.0])
+    y[:, 4] -= box * np.array([0.0, 1.0, 0.0])
+    v2, f2, prob2 = oracle.boson_spring(y, k, b, box=box)
+    assert abs(v2 - v) <= 1e-12 * abs(v)
+    assert np.abs(f2 - f).max() <= 1e-11 * np.abs(f).max()
+    assert np.abs(prob2 - prob).max() <= 1e-12
+    h = 1e-6
+    num = np.zeros_like(x)
+    for idx in np.ndindex(*x.shape):
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        num[idx] = -(oracle.boson_spring(xp, k, b, box=box)[0] -
+                     oracle.boson_spring(xm, k, b, box=box)[0]) / (2 * h)
+    assert np.abs(num - f).max() <= 1e-6 * max(1.0, np.abs(f).max())
+
+
+def test_boson_large_box_is_no_box():
+    """A box much larger than the particles' spread leaves every link's
+    nearest image the direct one."""
+    rng = np.random.default_rng(4)
+    x = rng.normal(0, 0.4, (5, 7, 3)) + rng.normal(0, 1.0, (1, 7, 3))
+    a = oracle.boson_spring(x, 1.0, 0.8, with_ev=True)
+    c = oracle.boson_spring(x, 1.0, 0.8, with_ev=True, box=[1e3, 1e3, 1e3])
+    assert a[0] == c[0] and np.array_equal(a[1], c[1]) and np.array_equal(a[2], c[2]) and a[3] == c[3]
+
+
 def _trapped_bosons(N, P, dt, nve, seed=3, spread=0.8):
     rng = np.random.default_rng(seed)
     s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.5, dt=dt,
