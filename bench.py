@@ -2,8 +2,13 @@
 
 One step = the whole hot path over one batch of synthetic input: normal-mode
 transforms, B/A/O/A/B, PILE-L noise, bead-batched forces, estimators.  The
-headline workload is the LJ quantum liquid (N=4000 atoms, P=32 beads, reduced
-density 0.8, kT=0.7, hbar=0.1, rc=2.5, dt=0.002, tau=0.5, FCC start).
+headline workload is the water-shaped system (N=32766 atoms: O-H harmonic
+bonds plus O-O LJ at 9 A, 1 g/cm^3, 300 K, P=64 beads, dt=0.25 fs, PILE-L
+tau=100 fs), the shape of the paper's DP water runs.  Legs beside it: the
+same system at P=32, the LJ quantum liquid (N=4000, P=32), the step pass on a
+working set far beyond the 256 MB Infinity Cache (the water-shaped system
+four times larger, N=131070, P=64), a plain-copy HBM probe, and the CPU
+oracle on the host cores at one thread and at every core.
 
 Prints ONE JSON line: bead*atom*steps/s over exactly --steps timed steps
 (after --warmup untimed ones), the roofline of the dominant kernel from HIP
@@ -41,6 +46,9 @@ WORKLOADS = {
                 "synthetic (seeded water-shaped O/H lattice, Maxwell-Boltzmann bead velocities at P*T)"),
     "water64": ("water-shaped, N=32766, P=64", lambda: inputs.water(n_beads=64),
                 "synthetic (seeded water-shaped O/H lattice, Maxwell-Boltzmann bead velocities at P*T)"),
+    "water64x4": ("water-shaped, N=131070, P=64 (the N=32766 system four times larger at the "
+                  "same density)", lambda: inputs.water(n_atoms=131072, n_beads=64),
+                  "synthetic (seeded water-shaped O/H lattice, Maxwell-Boltzmann bead velocities at P*T)"),
     "harmonic": ("harmonic oscillators, N=64, P=4", inputs.harmonic_tiny,
                  "synthetic (seeded Gaussian positions, Maxwell-Boltzmann bead velocities at P*T)"),
 }
@@ -117,13 +125,14 @@ def sync(ctx):
 
 
 def bench_boson():
-    """The bosonic exchange spring kernel (energy, forces, link
+    """The bosonic exchange springs (energy, estimator energy, forces, link
     probabilities) per call, on N particles of P beads spread over a few
-    thermal lengths."""
+    thermal lengths; each call allocates and frees its scratch and waits for
+    its stream."""
     import torch
     from paper_2602_13553_amd import pimd
     out = {}
-    for N, P in ((64, 32), (512, 8)):
+    for N, P in ((64, 32), (512, 8), (1024, 8)):
         rng = np.random.default_rng(N + P)
         x = torch.tensor(rng.normal(0, 0.4, (P, N, 3)) + rng.normal(0, 1.2, (1, N, 3)),
                          dtype=torch.float64, device="cuda")
@@ -189,25 +198,93 @@ def kernel_avgs(prof):
     return {k: (ms / n if n else 0.0, n) for k, (n, ms) in prof.items()}
 
 
-def cpu_baseline(spec, max_seconds=25.0):
-    """The oracle as it stands on the host cores, on a bounded sample of the
-    same workload (a few steps from the same initial state)."""
+def _omp_threads(n: int) -> None:
+    """Thread count of the OpenMP runtime the oracle runs on (libgomp), for
+    the parallel regions that follow."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def host_cores() -> int:
+    """Host threads this process may use: OMP_NUM_THREADS when set (the box's
+    CPU share), else the CPU affinity mask."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_one(spec, threads: int, max_seconds: float, max_steps: int = 200):
+    """The oracle as it stands, at `threads` OpenMP threads, on a bounded
+    sample of the workload: steps from its initial state (the forces of the
+    initial state, computed when the state is set up, are outside the
+    timing) until max_seconds, at least one."""
     import oracle
+    _omp_threads(threads)
     st = oracle.State.from_spec(spec)
-    st.step(1)                      # first-touch / thread start-up outside the timing
     n, t = 0, 0.0
-    while t < max_seconds and n < 200:
+    while n < max_steps:
         t0 = time.perf_counter()
         st.step(1)
         t += time.perf_counter() - t0
         n += 1
-        if n >= 3 and t * (n + 1) / n > max_seconds:
+        if t * (n + 1) / n > max_seconds:
             break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": spec.bead_atoms * n / t, "unit": "bead*atom*steps/s", "cores": cores,
+    return {"value": spec.bead_atoms * n / t, "unit": "bead*atom*steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d steps of the same workload (N=%d, P=%d) from its initial state, %.1f s"
-                      % (n, spec.n_atoms, spec.n_beads, t)}
+            "sample": "%d step(s) of %s from its initial state, %.1f s" % (n, spec.name, t)}
+
+
+def cpu_baseline(spec, legs):
+    """The oracle on the host cores: the headline workload at every core and
+    at one thread, and the other workloads (`legs`: name -> spec) likewise on
+    smaller samples."""
+    cores = host_cores()
+    out = cpu_baseline_one(spec, cores, 20.0)
+    out["cpu_model"] = cpu_model()
+    out["single_thread"] = cpu_baseline_one(spec, 1, 60.0)
+    out["other_workloads"] = {}
+    for name, leg in legs.items():
+        out["other_workloads"][name] = {
+            "all_cores": cpu_baseline_one(leg, cores, 6.0),
+            "single_thread": cpu_baseline_one(leg, 1, 6.0)}
+    _omp_threads(cores)
+    return out
+
+
+def hbm_copy_probe(n_doubles: int = 2 ** 28, reps: int = 10):
+    """Plain device-to-device copy of 2 GiB (torch's copy kernel) timed with
+    HIP events: the HBM bandwidth a streaming kernel reaches on this GPU
+    (bytes read + bytes written per second)."""
+    import torch
+    a = torch.empty(n_doubles, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * 8 * n_doubles / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read": 8 * n_doubles, "bytes_written": 8 * n_doubles, "ms": ms, "GB/s": gbs,
+            "frac_of_8TB/s": gbs / HBM_PEAK_GBS}
 
 
 def bench_batched(n_systems, steps, seed=20260213):
@@ -304,21 +381,72 @@ def bench_serving(n_jobs, seed=20260213):
             "continuous_batching": rep, "one_at_a_time": seq}
 
 
+def pair_roofline(workload, spec, x, avgs):
+    """FP64 roofline of the force pass: 23 flops per ordered bead pair inside
+    rc (LJ among the active atoms, counted on the final state), over the
+    pass's average duration by HIP events.  The water-shaped system's bonds
+    (2 per molecule, about 2% of the pairs' work) are not counted."""
+    npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc, spec.lj_active)
+    flops = LJ_FLOPS_PER_PAIR * npairs
+    ach = flops / (avgs["pair"][0] * 1e-3) / 1e12
+    return {"kernel": "k_pair", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+            "traffic": profiled_traffic(PROFILE_FILES.get((workload, "k_pair"), ""),
+                                        "pimd::k_pair("),
+            "work_per_launch": "%d ordered bead pairs inside rc x %d flops" % (npairs, LJ_FLOPS_PER_PAIR),
+            "launch_us": avgs["pair"][0] * 1e3}
+
+
+def fused_kernel_name(spec, info):
+    # the step passes are instantiated per splitting and fixcom
+    tf = lambda v: "true" if v else "false"
+    return (("k_fused_mfma<%d, %s, %s>" % (spec.n_beads, tf(spec.integrator), tf(spec.fixcom)))
+            if info["transforms"] else "k_fused<%s>" % tf(spec.fixcom))
+
+
+def fused_roofline(workload, spec, info, avgs):
+    """HBM roofline of the step pass: the method's 120 B per bead*atom (read
+    x, v~, f; write x, v~; 96 B with the trap's in-pass forces) over the
+    pass's average duration by HIP events."""
+    name = fused_kernel_name(spec, info)
+    byts = (FUSED_BYTES_PAIR if spec.potential != inputs.POT_HARMONIC else FUSED_BYTES_EXT) * spec.bead_atoms
+    ach = byts / (avgs["fused"][0] * 1e-3) / 1e9
+    return {"kernel": name, "workload": spec.name, "bound": "hbm", "achieved": ach,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(PROFILE_FILES.get((workload, name), ""), _counter_name(name)),
+            "bytes_per_launch": byts, "launch_us": avgs["fused"][0] * 1e3}
+
+
+def leg(workload, steps, warmup, profile_steps, flags=0):
+    """ms/step, throughput and per-kernel averages of one more workload."""
+    title, make, _ = WORKLOADS[workload]
+    spec = make()
+    log("leg %s: %d warmup + %d timed steps" % (spec.name, warmup, steps))
+    ms, est, prof, _, x, info = run_gpu(spec, steps, warmup, profile_steps, flags)
+    avgs = kernel_avgs(prof)
+    return spec, x, info, avgs, {"workload": title, "ms_per_step": ms,
+                                 "bead_atom_steps_per_s": spec.bead_atoms * 1e3 / ms,
+                                 "kernels_ms": {k: v[0] for k, v in avgs.items()},
+                                 "launch": info}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-probe", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the P=32 and LJ legs")
     ap.add_argument("--batch-systems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="lj",
-                    help="workload of the timed steps (default: the LJ quantum liquid)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="water64",
+                    help="workload of the timed steps (default: water-shaped, N=32766, P=64)")
     ap.add_argument("--transforms", choices=("auto", "valu"), default="auto",
                     help="valu: normal-mode transforms on the FP64 vector ALUs only")
     args = ap.parse_args()
@@ -342,30 +470,11 @@ def main():
     log("ms/step %.4f (profiled %.4f); kernels %s" % (ms_step, ms_prof, avgs))
 
     # dominant kernel of the workload and its roofline
-    # the step passes are instantiated per splitting and fixcom (false: BAOAB, none)
-    tf = lambda v: "true" if v else "false"
-    fused_name = (("k_fused_mfma<%d, %s, %s>" % (spec.n_beads, tf(spec.integrator), tf(spec.fixcom)))
-                  if info["transforms"] else "k_fused<%s>" % tf(spec.fixcom))
     dom = max(("fused", "pair"), key=lambda k: avgs[k][0] * avgs[k][1])
     if dom == "pair":
-        npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc, spec.lj_active)
-        flops = LJ_FLOPS_PER_PAIR * npairs
-        ach = flops / (avgs["pair"][0] * 1e-3) / 1e12
-        roof = {"kernel": "k_pair", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                "traffic": profiled_traffic(PROFILE_FILES.get((args.workload, "k_pair"), ""),
-                                            "pimd::k_pair("),
-                "work_per_launch": "%d ordered bead pairs inside rc x %d flops"
-                                   % (npairs, LJ_FLOPS_PER_PAIR)}
+        roof = pair_roofline(args.workload, spec, x, avgs)
     else:
-        byts = (FUSED_BYTES_PAIR if spec.potential != inputs.POT_HARMONIC else FUSED_BYTES_EXT) * ba
-        ach = byts / (avgs["fused"][0] * 1e-3) / 1e9
-        roof = {"kernel": fused_name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": profiled_traffic(PROFILE_FILES.get((args.workload, fused_name), ""),
-                                            _counter_name(fused_name)),
-                "bytes_per_launch": byts}
-    fused_gbs = FUSED_BYTES_PAIR * ba / (avgs["fused"][0] * 1e-3) / 1e9
+        roof = fused_roofline(args.workload, spec, info, avgs)
 
     out = {
         "metric": "ring-polymer bead*atom*steps/s",
@@ -381,64 +490,65 @@ def main():
         "dtype": "f64",
         "data": data,
         "config": {"workload": title, "n_atoms": spec.n_atoms,
-                   "n_beads": spec.n_beads, "bead_atoms": ba, "kT": spec.temp,
+                   "n_beads": spec.n_beads, "bead_atoms": ba, "temp": spec.temp,
                    "hbar": spec.hbar, "rc": spec.lj_rc, "skin": spec.skin, "dt": spec.dt, "tau": spec.tau,
                    "ensemble": "NVT PILE-L", "integrator": "BAOAB",
                    "transforms": args.transforms},
         "roofline": roof,
+        "step_pass_roofline": fused_roofline(args.workload, spec, info, avgs),
         "kernels_ms": {k: v[0] for k, v in avgs.items()},
         "launch": info,
-        "fused_in_cache_gbs": fused_gbs,
         "estimators": {"kcv_per_atom": est["kcv"] / spec.n_atoms,
                        "kprim_per_atom": est["kprim"] / spec.n_atoms, "temp": est["temp"],
                        "pcv": est["pcv"], "ppr": est["ppr"], "pmd": est["pmd"]},
         "neighbor_lists": {"rlist": est["rlist"], "builds": est["n_rebuilds"],
-                           "steps": args.warmup + args.steps},
+                           "steps": args.warmup + args.profile_steps + args.steps},
     }
+    legs_for_cpu = {}
+    if not args.no_legs:
+        for wl in ("water32", "lj"):
+            if wl == args.workload:
+                continue
+            lspec, lx, linfo, lavgs, rec = leg(wl, 500, 50, 100)
+            rec["pair_roofline"] = pair_roofline(wl, lspec, lx, lavgs)
+            rec["step_pass_roofline"] = fused_roofline(wl, lspec, linfo, lavgs)
+            out[wl] = rec
+            legs_for_cpu[wl] = lspec
+        legs_for_cpu["harmonic"] = inputs.harmonic_tiny()
 
     if not args.no_hbm_probe:
-        # the fused pass on a working set larger than the 256 MB Infinity Cache:
-        # the water-shaped workload at P=64 (N=32766, 2.1e6 bead*atoms, 252 MB/step)
-        w = inputs.water(n_beads=64)
-        log("hbm probe %s" % w.name)
-        ms_w, _, prof_w, _, _, info_w = run_gpu(w, 50, 10, 50)
-        aw = kernel_avgs(prof_w)
-        gbs = FUSED_BYTES_PAIR * w.bead_atoms / (aw["fused"][0] * 1e-3) / 1e9
-        # the step passes are instantiated per splitting and fixcom (false: BAOAB, none)
-        kname = ("k_fused_mfma<64, false, false>" if info_w["transforms"] else "k_fused<false>")
-        out["fused_roofline"] = {"kernel": kname, "workload": w.name, "bound": "hbm",
-                                 "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": gbs / HBM_PEAK_GBS,
-                                 "traffic": profiled_traffic(
-                                     PROFILE_FILES.get(("water64", kname), ""), _counter_name(kname)),
-                                 "bytes_per_launch": FUSED_BYTES_PAIR * w.bead_atoms}
-        out["water_p64"] = {"bead_atom_steps_per_s": w.bead_atoms * 1e3 / ms_w,
-                            "ms_per_step": ms_w, "kernels_ms": {k: v[0] for k, v in aw.items()}}
-        # the same pass with the transforms on the FP64 vector ALUs instead of MFMA
+        # the step pass on a working set far beyond the 256 MB Infinity Cache:
+        # the water-shaped system four times larger (8.4e6 bead*atoms; the
+        # pass moves 120 B of algorithmic bytes per bead*atom, 1.0 GB)
+        wspec, _, winfo, wavgs, rec = leg("water64x4", 30, 5, 30)
+        rec["step_pass_roofline"] = fused_roofline("water64x4", wspec, winfo, wavgs)
+        out["fused_roofline"] = rec["step_pass_roofline"]
+        out["water64x4"] = rec
         from paper_2602_13553_amd import pimd as _p
-        ms_v, _, prof_v, _, _, _ = run_gpu(w, 50, 10, 50, flags=_p.PIMD_FLAG_VALU_TRANSFORMS)
-        av = kernel_avgs(prof_v)
-        out["transform_variants_water_p64_fused_ms"] = {"mfma": aw["fused"][0],
-                                                         "valu": av["fused"][0]}
+        _, _, vinfo, vavgs, _ = leg("water64x4", 10, 3, 10, flags=_p.PIMD_FLAG_VALU_TRANSFORMS)
+        out["water64x4"]["step_pass_valu_transforms"] = fused_roofline("water64x4", wspec, vinfo, vavgs)
+        log("hbm copy probe")
+        out["hbm_copy_probe"] = hbm_copy_probe()
 
     if not args.no_batch:
+        ljt, ljmake, _ = WORKLOADS["lj"]
         log("OBABO splitting")
-        ob = make()
+        ob = ljmake()
         ob.integrator = 1
         ms_ob, _, prof_ob, _, _, _ = run_gpu(ob, 500, 50, 100, flags)
-        out["obabo"] = {"workload": title + ", OBABO splitting (two O half steps per step)",
+        out["obabo"] = {"workload": ljt + ", OBABO splitting (two O half steps per step)",
                         "ms_per_step": ms_ob, "bead_atom_steps_per_s": ob.bead_atoms * 1e3 / ms_ob,
                         "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_ob).items()}}
         log("fixcom")
-        fc = make()
+        fc = ljmake()
         fc.fixcom = 1
         ms_fc, _, prof_fc, _, _, _ = run_gpu(fc, 500, 50, 100, flags)
-        out["fixcom"] = {"workload": title + ", fixcom (centroid COM velocity removed every step; "
-                                             "the closing half-kick in a pass of its own)",
+        out["fixcom"] = {"workload": ljt + ", fixcom (centroid COM velocity removed every step; "
+                                           "the closing half-kick in a pass of its own)",
                          "ms_per_step": ms_fc, "bead_atom_steps_per_s": fc.bead_atoms * 1e3 / ms_fc,
                          "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof_fc).items()}}
         log("NpT (BZP barostat)")
-        out["npt"] = bench_npt(make)
+        out["npt"] = bench_npt(ljmake)
         log("bosonic exchange kernel")
         out["boson_spring"] = bench_boson()
         log("external forces")
@@ -450,7 +560,7 @@ def main():
         out["serving"] = bench_serving(args.serve_jobs)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(spec)
+        out["cpu_baseline"] = cpu_baseline(spec, legs_for_cpu)
     print(json.dumps(out), flush=True)
 
 
