@@ -295,43 +295,33 @@ int pimd_get_barostat(pimd_ctx *ctx, double *box, double *vw);
  * barostat). */
 int pimd_set_barostat(pimd_ctx *ctx, const double *box, double vw);
 
-/* Bosonic exchange (the bosonic fix of Sec. III.C; the exchange potential of
- * Hirshberg et al. 2019, cited by the paper).  For N identical particles of
- * P beads, x [P][N][3] (bead, particle, dim; device memory, no box), with
- * springs kspring |r - r'|^2 (kspring = m omega_n^2 / 2) inside each
- * particle's ring and, summed over exchange cycles, from bead P-1 of a
- * particle to bead 0 of the next:
+/* Bosonic exchange springs (the bosonic fix of Sec. III.C; the exchange
+ * potential of Hirshberg et al. 2019, evaluated in quadratic time as in
+ * Feldman and Hirshberg 2023, both cited by the paper).  N identical
+ * particles of P beads, x [P][N][3] (bead, particle, dim; device memory).
+ * Springs kspring |r - r'|^2 (kspring = m omega_n^2 / 2) join bead j to j+1
+ * inside each particle's ring; the link from bead P-1 of a particle to bead 0
+ * of the next is summed over exchange cycles:
  *   exp(-beta_n V[n]) = (1/n) sum_{k=1..n} exp(-beta_n (E[n,k] + V[n-k])),
- * V[0] = 0, E[n,k] the single ring through particles n-k..n-1 (0-based).
- * Writes V_B = V[N] to v (device, one double), the spring forces -dV_B/dx to
- * f ([P][N][3], device, overwritten) and to prob ([N][N], device) the
+ * V[0] = 0, E[n,k] the single ring through particles n-k..n-1 (0-based),
+ * V_B = V[N].  box (host, [3]; NULL = no box): periodic lengths, 0 = not
+ * periodic in that dimension; each link's vector is then taken under the
+ * minimum image, while a particle's own springs use its unwrapped
+ * coordinates.
+ * Writes to out (device, two doubles) V_B and EV_B = sum_k w[n,k] (E[n,k] +
+ * EV[n-k]) at n = N (w the recursion's weights, EV[0] = 0), the ring energy
+ * that App. A's bosonic primitive kinetic energy estimator subtracts:
+ * K_PR = 3 P N kB T / 2 - EV_B / P.  f ([P][N][3], device, overwritten)
+ * receives the spring forces -dV_B/dx; prob ([N][N], device, or NULL) the
  * probability that bead P-1 of particle l links to bead 0 of particle l'.
- * Runs on the null stream and waits for it.  A building block of bosonic
- * PIMD (its Cartesian integrator is not in this library).
- * Errors: ARG (NULL pointer, N < 1, P < 1, kspring < 0 or not finite,
- * beta_n <= 0), UNSUPPORTED (N > 512, P > 128), DEVICE. */
+ * Work is enqueued on stream (a hipStream_t; NULL = the null stream); the
+ * call allocates its scratch (about 8 N^2 bytes), waits for the stream and
+ * frees it before it returns.
+ * Errors: ARG (NULL x, f or out, N < 1, P < 1, kspring < 0 or not finite,
+ * beta_n <= 0, a negative or non-finite box length), UNSUPPORTED (N > 1024,
+ * P > 128), OOM (scratch), DEVICE. */
 int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
-                      double *f, double *prob, double *v);
-
-/* The bosonic fix's step (Sec. III.C: Cartesian coordinates, since the normal
- * modes change under exchange; the thermostat of Eq. D3) for N identical
- * particles of one mass in a harmonic trap U = 1/2 m mvv2e omega^2 |r|^2 per
- * bead (omega = 0: free): nsteps of BAOAB on Cartesian bead positions x and
- * velocities v ([P][N][3], device, updated in place): B(dt/2) with the trap's
- * and the exchange springs' forces (pimd_boson_spring with kspring =
- * m mvv2e omega_n^2 / 2, omega_n = P kB T / hbar, beta_n = 1/(P kB T)),
- * A(dt/2) drift, O(dt) v <- c1 v + c2 sqrt(P kB T/(m mvv2e)) z (c1 =
- * exp(-dt/tau) on every bead when thermostat is 1, no O otherwise; z from
- * counter (particle, bead, step, 0), step = step0, step0 + 1, ...), A(dt/2),
- * forces, B(dt/2).  On return f ([P][N][3]) holds the forces of the final x,
- * ubead ([P*N], bead-major) the trap energies, vb (one double) V_B; prob
- * ([N][N]) is scratch (the final link probabilities).  All pointers are
- * device memory; runs on the null stream and waits.
- * Errors: ARG, UNSUPPORTED (N > 512, P > 128), DEVICE. */
-int pimd_boson_step(double *x, double *v, int32_t N, int32_t P, double mass, double temp, double kB,
-                    double hbar, double mvv2e, double dt, double tau, double omega, uint64_t seed,
-                    int32_t thermostat, uint64_t step0, int64_t nsteps, double *f, double *prob,
-                    double *ubead, double *vb);
+                      const double *box, double *f, double *prob, double *out, void *stream);
 
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);

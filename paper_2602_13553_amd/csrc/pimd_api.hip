@@ -909,62 +909,46 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
 
 }  // extern "C"
 
-namespace pimd {
-// the bosonic step's launchers (pimd_boson.hip)
-void launch_boson_forces(const double *x, int N, int P, double kspring, double beta_n, double kk,
-                         double *f, double *prob, double *ubead, double *vb, hipStream_t st);
-void launch_boson_update(double *x, double *v, const double *f, int N, int P, double h, double im,
-                         double c1, double c2, double sigma, unsigned long long seed,
-                         unsigned long long step, int opening, int thermo, hipStream_t st);
-}  // namespace pimd
-
 extern "C" {
 
-int pimd_boson_step(double *x, double *v, int32_t N, int32_t P, double mass, double temp, double kB,
-                    double hbar, double mvv2e, double dt, double tau, double omega, uint64_t seed,
-                    int32_t thermostat, uint64_t step0, int64_t nsteps, double *f, double *prob,
-                    double *ubead, double *vb)
-{
-    if (!x || !v || !f || !prob || !ubead || !vb)
-        return fail(nullptr, PIMD_ERR_ARG, "x, v, f, prob, ubead and vb must be non-NULL");
-    if (N < 1 || P < 1 || nsteps < 0) return fail(nullptr, PIMD_ERR_ARG, "N, P >= 1 and nsteps >= 0");
-    if (!finite_pos(mass) || !finite_pos(temp) || !finite_pos(kB) || !finite_pos(hbar) ||
-        !finite_pos(mvv2e) || !finite_pos(dt) || !std::isfinite(omega) ||
-        (thermostat && !finite_pos(tau)))
-        return fail(nullptr, PIMD_ERR_ARG, "mass, temp, kB, hbar, mvv2e, dt (and tau) must be > 0");
-    if (N > boson_max() || P > kMaxBeads)
-        return fail(nullptr, PIMD_ERR_UNSUPPORTED, "N > 512 or P > 128");
-    const double kT = kB * temp, wn = (double)P * kT / hbar;
-    const double ks = 0.5 * mass * mvv2e * wn * wn, beta_n = 1.0 / ((double)P * kT);
-    const double kk = mass * mvv2e * omega * omega, im = 1.0 / (mass * mvv2e);
-    const double c1 = thermostat ? std::exp(-dt / tau) : 1.0, c2 = std::sqrt(1.0 - c1 * c1);
-    const double sigma = std::sqrt((double)P * kT * im);
-    launch_boson_forces(x, N, P, ks, beta_n, kk, f, prob, ubead, vb, nullptr);
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const unsigned long long st = (unsigned long long)(step0 + (uint64_t)s);
-        launch_boson_update(x, v, f, N, P, 0.5 * dt, im, c1, c2, sigma, seed, st, 1, thermostat ? 1 : 0,
-                            nullptr);
-        launch_boson_forces(x, N, P, ks, beta_n, kk, f, prob, ubead, vb, nullptr);
-        launch_boson_update(x, v, f, N, P, 0.5 * dt, im, c1, c2, sigma, seed, st, 0, 0, nullptr);
-    }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) return fail(nullptr, PIMD_ERR_DEVICE, hipGetErrorString(e));
-    return PIMD_OK;
-}
-
 int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
-                      double *f, double *prob, double *v)
+                      const double *box, double *f, double *prob, double *out, void *stream)
 {
-    if (!x || !f || !prob || !v) return fail(nullptr, PIMD_ERR_ARG, "x, f, prob and v must be non-NULL");
+    if (!x || !f || !out) return fail(nullptr, PIMD_ERR_ARG, "x, f and out must be non-NULL");
     if (N < 1 || P < 1) return fail(nullptr, PIMD_ERR_ARG, "N and P must be >= 1");
     if (!(kspring >= 0.0) || !std::isfinite(kspring) || !finite_pos(beta_n))
         return fail(nullptr, PIMD_ERR_ARG, "kspring >= 0 and beta_n > 0 must be finite");
-    if (N > boson_max() || P > kMaxBeads)
-        return fail(nullptr, PIMD_ERR_UNSUPPORTED, "N > 512 or P > 128");
-    launch_boson_spring(x, N, P, kspring, beta_n, f, prob, v, nullptr);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (box)
+        for (int d = 0; d < 3; ++d)
+            if (!(box[d] >= 0.0) || !std::isfinite(box[d]))
+                return fail(nullptr, PIMD_ERR_ARG, "box lengths must be finite and >= 0");
+    if (N > kBosonMaxN || P > kMaxBeads)
+        return fail(nullptr, PIMD_ERR_UNSUPPORTED, "N > 1024 or P > 128");
+    hipStream_t st = (hipStream_t)stream;
+    double *scr = nullptr;
+    hipError_t e = hipMalloc((void **)&scr, boson_scr_doubles(N) * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, PIMD_ERR_OOM, "scratch allocation failed");
+    }
+    BosonArgs a{};
+    a.x = x;
+    a.N = N;
+    a.P = P;
+    a.layout = 0;
+    a.ks = kspring;
+    a.bn = beta_n;
+    for (int d = 0; d < 3; ++d) a.box[d] = box ? box[d] : 0.0;
+    a.f = f;
+    a.prob = prob;
+    a.scr = scr;
+    a.res = out;
+    launch_boson_springs(a, st);
+    e = hipGetLastError();
+    // the scratch is freed once the kernels that read it are done
+    const hipError_t es = hipStreamSynchronize(st);
+    (void)hipFree(scr);
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) return fail(nullptr, PIMD_ERR_DEVICE, hipGetErrorString(e));
     return PIMD_OK;
 }

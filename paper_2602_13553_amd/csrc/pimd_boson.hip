@@ -1,15 +1,34 @@
-// Bosonic exchange spring energy (the bosonic fix of Sec. III.C; the
-// recursion of Hirshberg et al. 2019, evaluated in O(N^2) like Feldman and
-// Hirshberg's algorithm, both cited by the paper).  N identical
-// particles, P beads; the springs inside each particle's ring are the
-// distinguishable ones, and the link from bead P-1 of a particle to bead 0 of
-// the next is summed over exchange cycles by
+// Bosonic exchange springs (the bosonic fix of Sec. III.C; the recursion of
+// Hirshberg et al. 2019, evaluated in O(N^2) like Feldman and Hirshberg's
+// algorithm, both cited by the paper).
+//
+// N identical particles of P beads.  The springs inside each particle's ring
+// (bead j to j+1, j < P-1) are those of distinguishable particles; the link
+// from bead P-1 of particle l to bead 0 of particle l' is summed over exchange
+// cycles by the recursion over the cycle that holds the last particle,
 //   exp(-beta_n V[n]) = (1/n) sum_{k=1..n} exp(-beta_n (E[n,k] + V[n-k])),
 // E[n,k] the single ring through particles n-k..n-1 (0-based), V[0] = 0.
-// One block: the recursion is sequential in n and parallel in k; its
-// gradient comes from the adjoints of the same recursion (each V[n] is a
-// soft minimum with weights w[n,k] that sum to one), recomputed rather than
-// stored, so the block holds O(N) values.
+//
+// Every term of V[n] holds the inner-ring energies of all of particles
+// 0..n-1 once, so V[n] = sum_{l<n} eint[l] + V'[n], with V' the same
+// recursion over the links alone (E'[n,k]: chain links n-k..n-2 plus the
+// closing link n-1 -> n-k).  The kernels run V' and add the inner energies
+// at the end, so no ring weight sees them.  The chain sums are differences of
+// double-double prefix sums and V' is carried in double-double, so each
+// weight's exponent E' + V'[n-k] - V'[n] is formed to the rounding of its
+// own size, not of V_B's.
+//
+//   k_boson_inner : inner-ring spring forces (sets f) and energies, one
+//                   thread per particle
+//   k_boson_seq   : one block: prefix sums, the forward recursion (V', the
+//                   ring weights w[n,k] into scratch, the weighted energy EV'
+//                   of the primitive estimator) and its adjoint (adj[n] =
+//                   dV'[N]/dV'[n]); sequential in n, parallel in k
+//   k_boson_rows  : one block per n: q[n,k] = adj[n] w[n,k] (the probability
+//                   of ring (n,k)'s closing link), and its suffix sums over k
+//   k_boson_links : one wave per particle: the chain links' probabilities
+//                   (sums of those suffix sums) and the link forces on the
+//                   particle's first and last beads
 #include "pimd_internal.h"
 #include "pimd_device.h"
 
@@ -17,274 +36,428 @@ namespace pimd {
 
 namespace {
 
-constexpr int kBosonMax = 512;   // particles per call (LDS-resident end beads)
+constexpr int kSeq = 256;   // threads of the sequential kernel
+constexpr int kSeqU = (kBosonMaxN + kSeq - 1) / kSeq;   // k per thread and stage
 
-struct BosonLds {
-    double e0[kBosonMax * 3];    // bead 0 of each particle
-    double el[kBosonMax * 3];    // bead P-1
-    double sint[kBosonMax + 1];  // prefix sums of the particles' inner ring energies
-    double schain[kBosonMax + 1];// prefix sums of the links l -> l+1
-    double V[kBosonMax + 1];
-    double adj[kBosonMax + 1];
-    double wsuf[kBosonMax + 1];  // one n's ring weights, then their suffix sums over k
-    double chain[kBosonMax];     // probability of the chain link l -> l+1
-    double red[64];
+__device__ __forceinline__ size_t tri_row(int n) { return (size_t)n * (size_t)(n - 1) / 2; }
+
+__device__ __forceinline__ size_t bidx(const BosonArgs &a, int j, int l, int d)
+{
+    return a.layout ? ((size_t)l * 3 + d) * a.P + j : ((size_t)j * a.N + l) * 3 + d;
+}
+
+// a - b under the minimum image in each periodic dimension
+__device__ __forceinline__ double mic(double a, double b, double L)
+{
+    const double u = a - b;
+    return L > 0.0 ? u - L * rint(u / L) : u;
+}
+
+// --- double-double arithmetic (error-free sums; no products involved) ---
+struct DD {
+    double hi, lo;
 };
 
-__device__ __forceinline__ double link_e(const BosonLds &s, double kspring, int l, int l2)
+__device__ __forceinline__ DD two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+    const DD s = two_sum(a.hi, b.hi);
+    const double lo = s.lo + (a.lo + b.lo);
+    const double hi = s.hi + lo;
+    return {hi, lo - (hi - s.hi)};
+}
+
+__device__ __forceinline__ DD dd_add1(DD a, double b)
+{
+    const DD s = two_sum(a.hi, b);
+    const double lo = s.lo + a.lo;
+    const double hi = s.hi + lo;
+    return {hi, lo - (hi - s.hi)};
+}
+
+// a - b, rounded once (to the rounding of the difference's own size)
+__device__ __forceinline__ double dd_diff(DD a, DD b)
+{
+    const DD s = two_sum(a.hi, -b.hi);
+    return s.hi + (s.lo + (a.lo - b.lo));
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Block reductions of the sequential kernel (kSeq threads); every thread gets
+// the result.  The waves' values are combined in wave order.
+__device__ __forceinline__ double seq_min(double v, double *red)
+{
+    constexpr int NW = kSeq / 64;
+    v = wave_min(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) r = fmin(r, red[u]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ void seq_sum2(double &a, double &b, double *red)
+{
+    constexpr int NW = kSeq / 64;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = a;
+        red[NW + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    double ra = red[0], rb = red[NW];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) {
+        ra += red[u];
+        rb += red[NW + u];
+    }
+    __syncthreads();
+    a = ra;
+    b = rb;
+}
+
+// Inner-ring springs: forces on every bead (overwrites f) and each particle's
+// inner spring energy eint[l] = kspring sum_j |x_{j+1} - x_j|^2.
+__global__ __launch_bounds__(kBlock) void k_boson_inner(BosonArgs a)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= a.N) return;
+    const int P = a.P;
+    const double k2 = 2.0 * a.ks;
+    double e = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double prev = 0.0, cur = a.x[bidx(a, 0, l, d)];
+        for (int j = 0; j < P; ++j) {
+            const double next = (j + 1 < P) ? a.x[bidx(a, j + 1, l, d)] : 0.0;
+            double g = 0.0;
+            if (j + 1 < P) {
+                const double u = next - cur;
+                g += k2 * u;
+                e += u * u;
+            }
+            if (j > 0) g -= k2 * (cur - prev);
+            a.f[bidx(a, j, l, d)] = g;
+            prev = cur;
+            cur = next;
+        }
+    }
+    a.scr[boson_scr_eint(a.N) + l] = a.ks * e;
+}
+
+struct SeqLds {
+    double e0[kBosonMaxN * 3];      // bead 0 of each particle
+    double el[kBosonMaxN * 3];      // bead P-1
+    double chi[kBosonMaxN + 1];     // prefix sums of the chain links l -> l+1 (double-double)
+    double clo[kBosonMaxN + 1];
+    double vhi[kBosonMaxN + 1];     // V' (double-double)
+    double vlo[kBosonMaxN + 1];
+    double ev[kBosonMaxN + 1];      // EV'
+    double adj[kBosonMaxN + 1];     // dV'[N]/dV'[n]; first the scan of chunk totals
+    double red[16];
+};
+
+__device__ __forceinline__ double link_e(const SeqLds &s, const BosonArgs &a, int l, int l2)
 {
     double e = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double dd = s.e0[l2 * 3 + d] - s.el[l * 3 + d];
-        e += dd * dd;
+        const double u = mic(s.e0[l2 * 3 + d], s.el[l * 3 + d], a.box[d]);
+        e += u * u;
     }
-    return kspring * e;
+    return a.ks * e;
 }
 
-// E[n,k]: inner rings of particles n-k..n-1, the chain links between them,
-// and the closing link from n-1 back to n-k
-__device__ __forceinline__ double ring_e(const BosonLds &s, double kspring, int n, int k)
+__global__ __launch_bounds__(kSeq) void k_boson_seq(BosonArgs a)
 {
-    return (s.sint[n] - s.sint[n - k]) + (s.schain[n - 1] - s.schain[n - k]) +
-           link_e(s, kspring, n - 1, n - k);
-}
-
-__device__ double block_min1(double v, double *red)
-{
-    constexpr int NW = kBlock / 64;
-    const int t = threadIdx.x, w = t >> 6;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    if ((t & 63) == 0) red[w] = v;
-    __syncthreads();
-    v = red[0];
-#pragma unroll
-    for (int u = 1; u < NW; ++u) v = fmin(v, red[u]);
-    __syncthreads();
-    return v;
-}
-
-__device__ double block_sum1(double v, double *red)
-{
-    double a[1] = {v};
-    block_sum<1>(a, red);
-    __syncthreads();
-    return a[0];
-}
-
-// x, f: [P][N][3] (bead, particle, dim); prob: [N][N]; out[0] = V_B
-__global__ __launch_bounds__(kBlock) void k_boson_spring(const double *x, int N, int P,
-                                                         double kspring, double beta_n,
-                                                         double *f, double *prob, double *out)
-{
-    __shared__ BosonLds s;
-    const int t = threadIdx.x;
-    auto X = [&](int j, int l, int d) { return x[((size_t)j * N + l) * 3 + d]; };
-    for (int e = t; e < N * 3; e += kBlock) {
+    __shared__ SeqLds s;
+    const int t = threadIdx.x, N = a.N;
+    double *w = a.scr;                               // ring weights w[n,k]
+    for (int e = t; e < N * 3; e += kSeq) {
         const int l = e / 3, d = e - l * 3;
-        s.e0[e] = X(0, l, d);
-        s.el[e] = X(P - 1, l, d);
+        s.e0[e] = a.x[bidx(a, 0, l, d)];
+        s.el[e] = a.x[bidx(a, a.P - 1, l, d)];
     }
-    // inner ring energies, then both prefix sums in index order (thread 0)
-    for (int l = t; l < N; l += kBlock) {
-        double e = 0.0;
-        for (int j = 0; j + 1 < P; ++j)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double dd = X(j + 1, l, d) - X(j, l, d);
-                e += dd * dd;
-            }
-        s.sint[l + 1] = kspring * e;
+    // the inner energies' sum, thread-strided, then in wave order
+    double esum = 0.0;
+    for (int l = t; l < N; l += kSeq) esum += a.scr[boson_scr_eint(N) + l];
+    {
+        double dummy = 0.0;
+        seq_sum2(esum, dummy, s.red);   // (its barrier also publishes e0, el)
     }
+    // Prefix sums ch[m] = sum_{l<m} link(l, l+1), m = 0..N-1, in
+    // double-double: each thread sums a contiguous chunk, the chunk totals
+    // are scanned (Hillis-Steele), then each chunk is written out.
+    const int nl = N - 1;                            // chain links
+    const int C = (nl + kSeq - 1) / kSeq;
+    const int l0 = t * C, l1 = min(l0 + C, nl);
+    DD tot = {0.0, 0.0};
+    for (int l = l0; l < l1; ++l) tot = dd_add1(tot, link_e(s, a, l, l + 1));
+    s.adj[t] = tot.hi;
+    s.ev[t] = tot.lo;
     __syncthreads();
+    for (int off = 1; off < kSeq; off <<= 1) {
+        DD add = {0.0, 0.0};
+        if (t >= off) add = {s.adj[t - off], s.ev[t - off]};
+        __syncthreads();
+        if (t >= off) {
+            const DD v = dd_add({s.adj[t], s.ev[t]}, add);
+            s.adj[t] = v.hi;
+            s.ev[t] = v.lo;
+        }
+        __syncthreads();
+    }
+    DD run = {0.0, 0.0};
+    if (t > 0) run = {s.adj[t - 1], s.ev[t - 1]};
+    __syncthreads();   // the scan's slots are read before s.ev is reused
     if (t == 0) {
-        s.sint[0] = 0.0;
-        for (int l = 1; l <= N; ++l) s.sint[l] += s.sint[l - 1];
-        s.schain[0] = 0.0;
-        for (int l = 1; l < N; ++l) s.schain[l] = s.schain[l - 1] + link_e(s, kspring, l - 1, l);
-        s.schain[N] = s.schain[N - 1];
-        s.V[0] = 0.0;
+        s.chi[0] = 0.0;
+        s.clo[0] = 0.0;
+    }
+    for (int l = l0; l < l1; ++l) {
+        run = dd_add1(run, link_e(s, a, l, l + 1));
+        s.chi[l + 1] = run.hi;
+        s.clo[l + 1] = run.lo;
+    }
+    if (t == 0) {
+        s.vhi[0] = 0.0;
+        s.vlo[0] = 0.0;
+        s.ev[0] = 0.0;
     }
     __syncthreads();
-    // forward: V[n] as a soft minimum over k, stabilized by the minimum
+
+    // Forward: V'[n] = V'[n-1] + delta_n, delta_n a soft minimum of
+    // b_k = E'[n,k] + V'[n-k] - V'[n-1] (all small), stabilized by the
+    // minimum; w[n,k] = exp(-beta_n (b_k - delta_n)) / n.  Thread t takes
+    // k = 1 + t + u kSeq.  V'[n-1] is in every thread's registers; V'[m] for
+    // m < n-1 was written by thread 0 before at least one barrier.
+    DD vprev = {0.0, 0.0};
+    const double bn = a.bn;
     for (int n = 1; n <= N; ++n) {
-        double lo = INFINITY;
-        for (int k = 1 + t; k <= n; k += kBlock) lo = fmin(lo, ring_e(s, kspring, n, k) + s.V[n - k]);
-        lo = block_min1(lo, s.red);
-        double sum = 0.0;
-        for (int k = 1 + t; k <= n; k += kBlock)
-            sum += exp(-beta_n * (ring_e(s, kspring, n, k) + s.V[n - k] - lo));
-        sum = block_sum1(sum, s.red);
-        if (t == 0) s.V[n] = lo - log(sum / (double)n) / beta_n;
-        __syncthreads();
+        const DD chn = {s.chi[n - 1], s.clo[n - 1]};
+        double b[kSeqU], E[kSeqU];
+        double mloc = INFINITY;
+#pragma unroll
+        for (int u = 0; u < kSeqU; ++u) {
+            const int k = 1 + t + u * kSeq;
+            b[u] = INFINITY;
+            E[u] = 0.0;
+            if (k <= n) {
+                const int j = n - k;
+                const double c = dd_diff(chn, {s.chi[j], s.clo[j]});
+                E[u] = c + link_e(s, a, n - 1, j);
+                const double dv = (k == 1) ? 0.0 : dd_diff({s.vhi[j], s.vlo[j]}, vprev);
+                b[u] = E[u] + dv;
+                mloc = fmin(mloc, b[u]);
+            }
+        }
+        const double m = seq_min(mloc, s.red);
+        double sw = 0.0, st = 0.0;
+        double ex[kSeqU];
+#pragma unroll
+        for (int u = 0; u < kSeqU; ++u) {
+            const int k = 1 + t + u * kSeq;
+            ex[u] = 0.0;
+            if (k <= n) {
+                ex[u] = exp(-bn * (b[u] - m));
+                sw += ex[u];
+                st += ex[u] * (E[u] + s.ev[n - k]);
+            }
+        }
+        seq_sum2(sw, st, s.red);
+        const double delta = m - log(sw / (double)n) / bn;
+        vprev = dd_add1(vprev, delta);
+        const double isw = 1.0 / sw;
+#pragma unroll
+        for (int u = 0; u < kSeqU; ++u) {
+            const int k = 1 + t + u * kSeq;
+            if (k <= n) w[tri_row(n) + (k - 1)] = ex[u] * isw;
+        }
+        if (t == 0) {
+            s.vhi[n] = vprev.hi;
+            s.vlo[n] = vprev.lo;
+            s.ev[n] = st * isw;
+        }
     }
-    // backward: adj[n] = dV[N]/dV[n]; weights recomputed from E and V
-    for (int e = t; e <= N; e += kBlock) s.adj[e] = (e == N) ? 1.0 : 0.0;
-    __syncthreads();
+    // Adjoints: adj[N] = 1, adj[n-k] += adj[n] w[n,k] for n = N..1 (the
+    // targets of one n are distinct); a barrier per n makes adj[n] final.
+    for (int e = t; e <= N; e += kSeq) s.adj[e] = (e == N) ? 1.0 : 0.0;
     for (int n = N; n >= 1; --n) {
+        double wr[kSeqU];
+#pragma unroll
+        for (int u = 0; u < kSeqU; ++u) {
+            const int k = 1 + t + u * kSeq;
+            wr[u] = (k <= n) ? w[tri_row(n) + (k - 1)] : 0.0;
+        }
+        __syncthreads();
         const double an = s.adj[n];
-        for (int k = 1 + t; k <= n; k += kBlock) {
-            const double w = exp(-beta_n * (ring_e(s, kspring, n, k) + s.V[n - k] - s.V[n])) / (double)n;
-            s.adj[n - k] += an * w;     // distinct k: distinct targets
+#pragma unroll
+        for (int u = 0; u < kSeqU; ++u) {
+            const int k = 1 + t + u * kSeq;
+            if (k <= n) s.adj[n - k] += an * wr[u];
         }
+    }
+    __syncthreads();
+    for (int e = t; e <= N; e += kSeq) a.scr[boson_scr_adj(N) + e] = s.adj[e];
+    if (t == 0) {
+        const DD vb = dd_add1({s.vhi[N], s.vlo[N]}, esum);
+        a.res[0] = vb.hi + vb.lo;
+        a.res[1] = esum + s.ev[N];
+    }
+}
+
+// Row n = blockIdx.x + 1: q[n,k] = adj[n] w[n,k], the probability of ring
+// (n,k)'s closing link n-1 -> n-k; T[n,k] = sum_{k' >= k} q[n,k'] (each
+// thread a contiguous chunk of k, then a scan of the chunk totals from the
+// right).  With prob, row n-1 of it gets the closing links and zeros (its
+// chain entry n is written by k_boson_links).
+__global__ __launch_bounds__(kBlock) void k_boson_rows(BosonArgs a)
+{
+    __shared__ double tot[kBlock];
+    const int n = blockIdx.x + 1, t = threadIdx.x, N = a.N;
+    const double an = a.scr[boson_scr_adj(N) + n];
+    const double *w = a.scr + tri_row(n);
+    double *T = a.scr + boson_scr_tri(N) + tri_row(n);
+    constexpr int CU = (kBosonMaxN + kBlock - 1) / kBlock;
+    const int C = (n + kBlock - 1) / kBlock;
+    const int k0 = 1 + t * C;
+    double q[CU];
+    double acc = 0.0;
+#pragma unroll
+    for (int u = CU - 1; u >= 0; --u) {
+        const int k = k0 + u;
+        q[u] = 0.0;
+        if (u < C && k <= n) {
+            q[u] = an * w[k - 1];
+            acc += q[u];
+        }
+    }
+    tot[t] = acc;
+    __syncthreads();
+    // suffix scan of the chunk totals: tot[t] = sum over threads >= t
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const double add = (t + off < kBlock) ? tot[t + off] : 0.0;
+        __syncthreads();
+        tot[t] += add;
         __syncthreads();
     }
-    // link probabilities.  Ring (n, k) carries q[n,k] = adj[n] w[n,k]: its
-    // closing link n-1 -> n-k takes q[n,k], and each chain link l -> l+1 with
-    // n-k <= l <= n-2 takes it too, so the chain link l gets, from each n,
-    // the suffix sum over k >= n-l of q[n,k]: one block scan per n, O(N^2)
-    // in all.
-    for (int e = t; e < N * N; e += kBlock) prob[e] = 0.0;
-    for (int l = t; l < N; l += kBlock) s.chain[l] = 0.0;
-    __syncthreads();
-    constexpr int KT = (kBosonMax + kBlock - 1) / kBlock;   // k per thread
-    for (int n = 1; n <= N; ++n) {
-        for (int k = 1 + t; k <= n; k += kBlock) {
-            const double q = s.adj[n] *
-                             exp(-beta_n * (ring_e(s, kspring, n, k) + s.V[n - k] - s.V[n])) / (double)n;
-            prob[(size_t)(n - 1) * N + (n - k)] = q;    // one (n, k) per entry
-            s.wsuf[k] = q;
-        }
-        __syncthreads();
-        // suffix sums over k = 1..n (Hillis-Steele, in place)
-        for (int off = 1; off < n; off <<= 1) {
-            double add[KT];
+    double run = (t + 1 < kBlock) ? tot[t + 1] : 0.0;
 #pragma unroll
-            for (int u = 0; u < KT; ++u) {
-                const int k = 1 + t + u * kBlock;
-                add[u] = (k <= n && k + off <= n) ? s.wsuf[k + off] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < KT; ++u) {
-                const int k = 1 + t + u * kBlock;
-                if (k <= n) s.wsuf[k] += add[u];
-            }
-            __syncthreads();
+    for (int u = CU - 1; u >= 0; --u) {
+        const int k = k0 + u;
+        if (u < C && k <= n) {
+            run += q[u];
+            T[k - 1] = run;
         }
-        // chain link l (l <= n-2) collects the rings with k >= n-l
-        for (int l = t; l + 2 <= n; l += kBlock) s.chain[l] += s.wsuf[n - l];
-        __syncthreads();
     }
-    for (int l = t; l + 1 < N; l += kBlock) prob[(size_t)l * N + l + 1] = s.chain[l];
-    __threadfence_block();
-    __syncthreads();
-    // link forces, one thread per particle: its last bead pulled toward the
-    // first beads it links to, its first bead toward the last beads linking
-    // to it
-    for (int l = t; l < N; l += kBlock) {
-        double gl[3] = {0.0, 0.0, 0.0}, g0[3] = {0.0, 0.0, 0.0};
-        for (int m = 0; m < N; ++m) {
-            const double qo = prob[(size_t)l * N + m], qi = prob[(size_t)m * N + l];
+    if (a.prob) {
+        double *row = a.prob + (size_t)(n - 1) * N;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                gl[d] += 2.0 * kspring * qo * (s.e0[m * 3 + d] - s.el[l * 3 + d]);
-                g0[d] -= 2.0 * kspring * qi * (s.e0[l * 3 + d] - s.el[m * 3 + d]);
-            }
+        for (int u = 0; u < CU; ++u) {
+            const int k = k0 + u;
+            if (u < C && k <= n) row[n - k] = q[u];
+        }
+        for (int j = n + t; j < N; j += kBlock) row[j] = 0.0;
+    }
+}
+
+// One wave per particle l: the chain links' probabilities
+//   chain[l] = sum_{n=l+2..N} T[n, n-l]   (the rings in which l -> l+1 is a link)
+// and the link forces on its last bead (links l -> l', l' <= l+1) and its
+// first bead (links l'' -> l, l'' >= l-1).
+__global__ __launch_bounds__(kBlock) void k_boson_links(BosonArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int N = a.N;
+    if (l >= N) return;
+    const double *w = a.scr;
+    const double *T = a.scr + boson_scr_tri(N);
+    const double *adj = a.scr + boson_scr_adj(N);
+    auto X = [&](int j, int p, int d) { return a.x[bidx(a, j, p, d)]; };
+    double cl = 0.0, cm = 0.0;
+    for (int n = l + 2 + lane; n <= N; n += 64) cl += T[tri_row(n) + (n - l) - 1];
+    if (l >= 1)
+        for (int n = l + 1 + lane; n <= N; n += 64) cm += T[tri_row(n) + (n - l + 1) - 1];
+    cl = wave_sum(cl);
+    cm = wave_sum(cm);
+    const double k2 = 2.0 * a.ks;
+    const int Pl = a.P - 1;
+    double el[3], e0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        el[d] = X(Pl, l, d);
+        e0[d] = X(0, l, d);
+    }
+    // last bead: closing links l -> l' (ring (l+1, l+1-l')), then the chain
+    double g[3] = {0.0, 0.0, 0.0};
+    const double an = adj[l + 1];
+    for (int lp = lane; lp <= l; lp += 64) {
+        const double q = an * w[tri_row(l + 1) + (l - lp)];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] += k2 * q * mic(X(0, lp, d), el[d], a.box[d]);
+    }
+    // first bead: closing links m -> l (ring (m+1, m+1-l)), m = l..N-1
+    double h[3] = {0.0, 0.0, 0.0};
+    for (int m = l + lane; m < N; m += 64) {
+        const double q = adj[m + 1] * w[tri_row(m + 1) + (m - l)];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) h[d] -= k2 * q * mic(e0[d], X(Pl, m, d), a.box[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        g[d] = wave_sum(g[d]);
+        h[d] = wave_sum(h[d]);
+    }
+    if (lane == 0) {
+        if (l + 1 < N) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[d] += k2 * cl * mic(X(0, l + 1, d), el[d], a.box[d]);
+            if (a.prob) a.prob[(size_t)l * N + l + 1] = cl;
+        }
+        if (l >= 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) h[d] -= k2 * cm * mic(e0[d], X(Pl, l - 1, d), a.box[d]);
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            f[((size_t)(P - 1) * N + l) * 3 + d] += gl[d];
-            f[((size_t)0 * N + l) * 3 + d] += g0[d];
+            a.f[bidx(a, Pl, l, d)] += g[d];
+            a.f[bidx(a, 0, l, d)] += h[d];
         }
-    }
-    if (t == 0) out[0] = s.V[N];
-}
-
-// The springs inside every particle's ring (weight one: each particle lies
-// on one cycle), one thread per bead; this sets f, and k_boson_spring then
-// adds the links.
-__global__ __launch_bounds__(kBlock) void k_boson_inner(const double *x, int N, int P,
-                                                        double kspring, double *f)
-{
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= N * P) return;
-    const int j = e / N, l = e - j * N;
-    auto X = [&](int jj, int d) { return x[((size_t)jj * N + l) * 3 + d]; };
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double g = 0.0;
-        if (j + 1 < P) g += 2.0 * kspring * (X(j + 1, d) - X(j, d));
-        if (j > 0) g -= 2.0 * kspring * (X(j, d) - X(j - 1, d));
-        f[((size_t)j * N + l) * 3 + d] = g;
-    }
-}
-
-// The potential's forces added to the springs': a harmonic trap
-// U = 1/2 m mvv2e omega^2 |x|^2 per bead (kk = m mvv2e omega^2), and each
-// bead's U for the energies.
-__global__ __launch_bounds__(kBlock) void k_boson_trap(const double *x, int N, int P, double kk,
-                                                       double *f, double *ubead)
-{
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= N * P) return;
-    double r2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double xv = x[(size_t)e * 3 + d];
-        f[(size_t)e * 3 + d] -= kk * xv;
-        r2 += xv * xv;
-    }
-    ubead[e] = 0.5 * kk * r2;
-}
-
-// B(dt/2) A(dt/2) O(dt) A(dt/2) per bead velocity component (the opening of a
-// step), or B(dt/2) alone (the closing): Cartesian, every bead with the same
-// c1 (Eq. D3), noise of counter (particle, bead, step, 0).
-__global__ __launch_bounds__(kBlock) void k_boson_update(double *x, double *v, const double *f,
-                                                         int N, int P, double h, double im,
-                                                         double c1, double c2, double sigma,
-                                                         unsigned long long seed,
-                                                         unsigned long long step, int opening,
-                                                         int thermo)
-{
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= N * P) return;
-    const int j = e / N, l = e - j * N;
-    double z[3] = {0.0, 0.0, 0.0};
-    if (opening && thermo)
-        gauss3(seed, (unsigned long long)l, (unsigned long long)j, step, z, 0ULL);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const size_t q = (size_t)e * 3 + d;
-        double vv = v[q] + h * f[q] * im;
-        if (opening) {
-            double xx = x[q] + h * vv;
-            vv = c1 * vv + c2 * sigma * z[d];
-            x[q] = xx + h * vv;
-        }
-        v[q] = vv;
     }
 }
 
 }  // namespace
 
-int boson_max() { return kBosonMax; }
-
-void launch_boson_forces(const double *x, int N, int P, double kspring, double beta_n, double kk,
-                         double *f, double *prob, double *ubead, double *vb, hipStream_t st)
+void launch_boson_springs(const BosonArgs &a, hipStream_t st)
 {
-    launch_boson_spring(x, N, P, kspring, beta_n, f, prob, vb, st);
-    hipLaunchKernelGGL(k_boson_trap, dim3((N * P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, x, N,
-                       P, kk, f, ubead);
-}
-
-void launch_boson_update(double *x, double *v, const double *f, int N, int P, double h, double im,
-                         double c1, double c2, double sigma, unsigned long long seed,
-                         unsigned long long step, int opening, int thermo, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_boson_update, dim3((N * P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, x,
-                       v, f, N, P, h, im, c1, c2, sigma, seed, step, opening, thermo);
-}
-
-void launch_boson_spring(const double *x, int N, int P, double kspring, double beta_n, double *f,
-                         double *prob, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_boson_inner, dim3((N * P + kBlock - 1) / kBlock), dim3(kBlock), 0, st, x,
-                       N, P, kspring, f);
-    hipLaunchKernelGGL(k_boson_spring, dim3(1), dim3(kBlock), 0, st, x, N, P, kspring, beta_n, f,
-                       prob, out);
+    hipLaunchKernelGGL(k_boson_inner, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_boson_seq, dim3(1), dim3(kSeq), 0, st, a);
+    hipLaunchKernelGGL(k_boson_rows, dim3(a.N), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_boson_links, dim3((a.N + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                       st, a);
 }
 
 }  // namespace pimd

@@ -187,11 +187,28 @@ void launch_npt_a(const NptArgs &a, int mode, hipStream_t s);
 void launch_npt_b(const NptArgs &a, hipStream_t s);
 void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s);
 
-// Bosonic exchange spring energy, forces and link probabilities
-// (pimd_boson.hip); x, f: [P][N][3]; prob: [N][N]; out: one double.
-int boson_max();
-void launch_boson_spring(const double *x, int N, int P, double kspring, double beta_n, double *f,
-                         double *prob, double *out, hipStream_t st);
+// Bosonic exchange springs (pimd_boson.hip).  Scratch (doubles): the ring
+// weights w[n,k] and their probabilities' suffix sums T[n,k] (rows n = 1..N
+// of n entries each, row n at n(n-1)/2), the adjoints adj[0..N] and the
+// particles' inner spring energies eint[N].
+constexpr int kBosonMaxN = 1024;   // particles (the sequential kernel's LDS)
+__host__ __device__ inline size_t boson_scr_tri(int N) { return (size_t)N * (size_t)(N + 1) / 2; }
+__host__ __device__ inline size_t boson_scr_adj(int N) { return 2 * boson_scr_tri(N); }
+__host__ __device__ inline size_t boson_scr_eint(int N) { return boson_scr_adj(N) + (size_t)N + 1; }
+__host__ __device__ inline size_t boson_scr_doubles(int N) { return boson_scr_eint(N) + (size_t)N; }
+struct BosonArgs {
+    const double *x;     // positions
+    int N, P;
+    int layout;          // 0: [P][N][3] (bead, particle, dim); 1: [N][3][P]
+    double ks;           // kspring: m omega_n^2 / 2 (in energy units)
+    double bn;           // beta_n = 1 / (P kB T)
+    double box[3];       // periodic lengths of the links' minimum image (0: none)
+    double *f;           // spring forces, same layout as x (overwritten)
+    double *prob;        // [N][N] link probabilities, or nullptr
+    double *scr;         // boson_scr_doubles(N)
+    double *res;         // [2]: V_B, EV_B (the primitive estimator's weighted ring energy)
+};
+void launch_boson_springs(const BosonArgs &a, hipStream_t st);
 
 // Launchers (pimd_kernels.hip).
 int fused_smem_bytes(int P);

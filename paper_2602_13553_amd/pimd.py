@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libpimd.so")
 PIMD_OK = 0
 ERRORS = {-1: "PIMD_ERR_ARG", -2: "PIMD_ERR_OOM", -3: "PIMD_ERR_DEVICE", -4: "PIMD_ERR_STATE",
           -5: "PIMD_ERR_NONFINITE", -6: "PIMD_ERR_UNSUPPORTED", -7: "PIMD_ERR_OVERFLOW"}
+PIMD_ERR_ARG, PIMD_ERR_OOM, PIMD_ERR_DEVICE, PIMD_ERR_STATE = -1, -2, -3, -4
+PIMD_ERR_NONFINITE, PIMD_ERR_UNSUPPORTED, PIMD_ERR_OVERFLOW = -5, -6, -7
 PIMD_NVT, PIMD_NVE, PIMD_NPT, PIMD_NPH = 0, 1, 2, 3
 PIMD_BAOAB, PIMD_OBABO = 0, 1
 PIMD_POT_NONE, PIMD_POT_HARMONIC, PIMD_POT_LJ, PIMD_POT_WATER, PIMD_POT_EXTERNAL = 0, 1, 2, 3, 4
@@ -37,7 +39,7 @@ ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "p
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_set_barostat",
-            "pimd_boson_spring", "pimd_boson_step",
+            "pimd_boson_spring",
             "pimd_reset_averages",
             "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
@@ -114,9 +116,8 @@ def load() -> C.CDLL:
         lib.pimd_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double), P(C.c_uint64)]
         lib.pimd_get_barostat.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
         lib.pimd_boson_spring.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                          C.c_void_p, C.c_void_p, C.c_void_p]
-        lib.pimd_boson_step.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32] + \
-            [C.c_double] * 8 + [C.c_uint64, C.c_int32, C.c_uint64, C.c_int64] + [C.c_void_p] * 4
+                                          P(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]
         lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), C.c_double]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
@@ -204,49 +205,30 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     return p
 
 
-def boson_spring(x, kspring: float, beta_n: float):
-    """Bosonic exchange spring energy V_B, forces [P][N][3] and link
-    probabilities [N][N] of bead positions x ([P][N][3], float64; a torch
-    CUDA tensor, or host data copied to the device), computed on the GPU."""
+def boson_spring(x, kspring: float, beta_n: float, box=None, with_prob: bool = True):
+    """Bosonic exchange springs on the GPU (pimd_boson_spring) for bead
+    positions x ([P][N][3], float64; a torch CUDA tensor, or host data copied
+    to the device): returns V_B, EV_B (the primitive estimator's weighted
+    ring energy), the spring forces [P][N][3] and the link probabilities
+    [N][N] (None without with_prob).  box: periodic box lengths of the
+    links' minimum image.  Runs on torch's current stream."""
     import torch
     lib = load()
     xd = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
     P, N, _ = xd.shape
     f = torch.empty_like(xd)
-    prob = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    v = torch.empty(1, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    rc = lib.pimd_boson_spring(xd.data_ptr(), int(N), int(P), float(kspring), float(beta_n),
-                               f.data_ptr(), prob.data_ptr(), v.data_ptr())
+    prob = torch.empty((N, N), dtype=torch.float64, device="cuda") if with_prob else None
+    out = torch.empty(2, dtype=torch.float64, device="cuda")
+    bx = None if box is None else (C.c_double * 3)(*[float(b) for b in box])
+    stream = torch.cuda.current_stream().cuda_stream
+    rc = lib.pimd_boson_spring(xd.data_ptr(), int(N), int(P), float(kspring), float(beta_n), bx,
+                               f.data_ptr(), prob.data_ptr() if prob is not None else None,
+                               out.data_ptr(), C.c_void_p(stream))
     if rc != PIMD_OK:
         msg = lib.pimd_last_error(None)
         raise PimdError(rc, msg.decode() if msg else "")
-    return float(v.item()), f, prob
-
-
-def boson_step(x, v, mass: float, temp: float, kB: float, hbar: float, mvv2e: float, dt: float,
-               tau: float, omega: float, seed: int, thermostat: bool, step0: int, nsteps: int):
-    """The bosonic fix's Cartesian step on the GPU (pimd_boson_step): returns
-    the new x, v ([P][N][3] torch CUDA tensors), the forces, the beads' trap
-    energies [P][N] and V_B."""
-    import torch
-    lib = load()
-    xd = torch.as_tensor(x, dtype=torch.float64, device="cuda").clone().contiguous()
-    vd = torch.as_tensor(v, dtype=torch.float64, device="cuda").clone().contiguous()
-    P, N, _ = xd.shape
-    f = torch.empty_like(xd)
-    prob = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    ub = torch.empty((P, N), dtype=torch.float64, device="cuda")
-    vb = torch.empty(1, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    rc = lib.pimd_boson_step(xd.data_ptr(), vd.data_ptr(), int(N), int(P), mass, temp, kB, hbar,
-                             mvv2e, dt, tau, omega, int(seed), 1 if thermostat else 0, int(step0),
-                             int(nsteps), f.data_ptr(), prob.data_ptr(), ub.data_ptr(),
-                             vb.data_ptr())
-    if rc != PIMD_OK:
-        msg = lib.pimd_last_error(None)
-        raise PimdError(rc, msg.decode() if msg else "")
-    return xd, vd, f, ub, float(vb.item())
+    o = out.cpu().numpy()
+    return float(o[0]), float(o[1]), f, prob
 
 
 class Context:
