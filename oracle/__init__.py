@@ -101,6 +101,7 @@ def lib():
                                               d, d, d]),
             "orc_boson_forces": (C.c_double, [S, d, d, d]),
             "orc_boson_step": (None, [S, d, d, d, d, d, u64, C.c_int32]),
+            "orc_boson_estimators": (None, [S, d, d, C.POINTER(_Est)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -399,6 +400,24 @@ class BosonState:
         lib().orc_boson_step(C.byref(self.sys.cstruct()), _dp(self.x), _dp(self.v), _dp(self.f),
                              _dp(self.U), _dp(self.vb),
                              self.step_count.ctypes.data_as(C.POINTER(C.c_uint64)), int(n))
+
+    @classmethod
+    def from_spec(cls, spec, step: int = 0) -> "BosonState":
+        return cls(System.from_spec(spec), spec.x0, spec.v0, step)
+
+    def estimators(self) -> dict:
+        """App. A's bosonic outputs at the current (synchronized) state:
+        ekin, espring (V_B), epot, etot, kprim (bosonic K_PR), kcv (holds
+        K_VR, the virial estimator), temp; pressures 0."""
+        e = _Est()
+        lib().orc_boson_estimators(C.byref(self.sys.cstruct()), _dp(self.x), _dp(self.v),
+                                   C.byref(e))
+        return {n: getattr(e, n) for n in ESTIMATOR_NAMES}
+
+    @property
+    def p(self) -> np.ndarray:
+        """Cartesian bead momenta m v."""
+        return np.asarray(self.sys.mass)[None, :, None] * self.v
 
     def energies(self) -> dict:
         """K (Cartesian), the exchange spring energy V_B, U, H = K + V_B + U."""

@@ -1089,7 +1089,11 @@ void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, doub
     const int32_t P = sys->n_beads, N = sys->n_atoms;
     const double h = 0.5 * sys->dt;
     const double kT = sys->kB * sys->temp;
-    const double c1 = sys->nve ? 1.0 : exp(-sys->dt / sys->tau), c2 = sqrt(1.0 - c1 * c1);
+    const int obabo = sys->integrator == 1;
+    /* each O step lasts dt (BAOAB) or dt/2 (OBABO) */
+    const double to = obabo ? 0.5 * sys->dt : sys->dt;
+    const double c1 = sys->nve ? 1.0 : exp(-to / sys->tau), c2 = sqrt(1.0 - c1 * c1);
+    /* O acts on every bead velocity with the noise of counter (atom, bead, s, q) */
     for (int32_t it = 0; it < nsteps; ++it) {
         const uint64_t s = *step;
         for (int32_t j = 0; j < P; ++j)
@@ -1098,24 +1102,69 @@ void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, doub
                 const double sigma = sqrt((double)P * kT * im);
                 const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
                 double z[3] = {0.0, 0.0, 0.0};
-                if (!sys->nve) orc_gaussians(sys->seed, 0, id, (uint64_t)j, s, z);
+                if (!sys->nve) orc_gaussians_q(sys->seed, 0, id, (uint64_t)j, s, 0, z);
                 for (int d = 0; d < 3; ++d) {
                     const size_t e = ((size_t)j * N + i) * 3 + d;
-                    v[e] += h * f[e] * im;                 /* B */
-                    x[e] += h * v[e];                      /* A */
-                    v[e] = c1 * v[e] + c2 * sigma * z[d];  /* O */
-                    x[e] += h * v[e];                      /* A */
+                    if (obabo) {
+                        v[e] = c1 * v[e] + c2 * sigma * z[d];  /* O(dt/2) */
+                        v[e] += h * f[e] * im;                 /* B */
+                        x[e] += h * v[e];                      /* A(dt) as A(dt/2) twice */
+                        x[e] += h * v[e];
+                    } else {
+                        v[e] += h * f[e] * im;                 /* B */
+                        x[e] += h * v[e];                      /* A */
+                        v[e] = c1 * v[e] + c2 * sigma * z[d];  /* O */
+                        x[e] += h * v[e];                      /* A */
+                    }
                 }
             }
         *vb = orc_boson_forces(sys, x, f, U);
         for (int32_t j = 0; j < P; ++j)
             for (int32_t i = 0; i < N; ++i) {
                 const double im = 1.0 / (sys->mass[i] * sys->mvv2e);
+                const double sigma = sqrt((double)P * kT * im);
+                const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
+                double z[3] = {0.0, 0.0, 0.0};
+                if (obabo && !sys->nve) orc_gaussians_q(sys->seed, 0, id, (uint64_t)j, s, 1, z);
                 for (int d = 0; d < 3; ++d) {
                     const size_t e = ((size_t)j * N + i) * 3 + d;
                     v[e] += h * f[e] * im;                 /* B */
+                    if (obabo) v[e] = c1 * v[e] + c2 * sigma * z[d];  /* O(dt/2) */
                 }
             }
         *step = s + 1;
     }
+}
+
+void orc_boson_estimators(const orc_system *sys, const double *x, const double *v, orc_est *out)
+{
+    const int32_t P = sys->n_beads, N = sys->n_atoms;
+    const size_t n = (size_t)P * N * 3;
+    const double kT = sys->kB * sys->temp;
+    const double wn = omega_n(sys);
+    const double ks = 0.5 * sys->mass[0] * sys->mvv2e * wn * wn;
+    double *fp = (double *)malloc(sizeof(double) * n);
+    double *U = (double *)malloc(sizeof(double) * (size_t)P);
+    orc_forces(sys, x, fp, U);
+    double ev = 0.0;
+    const double vb = orc_boson_spring(N, P, ks, 1.0 / ((double)P * kT), x, sys->box, NULL, NULL, &ev);
+    double ekin = 0.0, u = 0.0, rf = 0.0;
+    for (int32_t j = 0; j < P; ++j)
+        for (int32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                const size_t e = ((size_t)j * N + i) * 3 + d;
+                ekin += 0.5 * sys->mass[i] * sys->mvv2e * v[e] * v[e];
+                rf += x[e] * fp[e];
+            }
+    for (int32_t j = 0; j < P; ++j) u += U[j];
+    memset(out, 0, sizeof(*out));
+    out->ekin = ekin;
+    out->espring = vb;
+    out->epot = u;
+    out->etot = ekin + vb + u;
+    out->kprim = 1.5 * (double)P * (double)N * kT - ev / (double)P;
+    out->kcv = -rf / (2.0 * (double)P);
+    out->temp = 2.0 * ekin / (3.0 * (double)N * (double)P * (double)P * sys->kB);
+    free(fp);
+    free(U);
 }

@@ -181,18 +181,33 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
 double orc_boson_spring(int32_t N, int32_t P, double kspring, double beta_n, const double *x,
                         const double *box, double *f, double *prob, double *ev);
 /* The bosonic fix's step (Sec. III.C: Cartesian coordinates, since the normal
- * modes change under exchange; the thermostat of Eq. D3), BAOAB in Cartesian
- * bead velocities v [P][N][3]: B(dt/2) with the potential's forces plus the
- * exchange springs' (orc_boson_spring, kspring = m mvv2e omega_n^2 / 2,
- * beta_n = 1/(P kB T), masses all equal to mass[0]); A(dt/2) drift; O(dt)
+ * modes change under exchange; the thermostat of Eq. D3) in Cartesian bead
+ * velocities v [P][N][3], with the forces of the potential plus the exchange
+ * springs' (orc_boson_spring, kspring = m mvv2e omega_n^2 / 2, beta_n =
+ * 1/(P kB T), masses all equal to mass[0], links under the minimum image of
+ * sys->box).  BAOAB (integrator 0): B(dt/2); A(dt/2) drift; O(dt)
  * v <- c1 v + c2 sigma z with c1 = exp(-dt/tau) for every bead, sigma =
  * sqrt(P kB T / (m mvv2e)), z from counter (atom, bead, step, 0); A(dt/2);
- * forces; B(dt/2).  f holds the total forces of x, U the beads' potential
- * energies, *vb the exchange spring energy; all are those of the new x. */
+ * forces; B(dt/2).  OBABO (integrator 1): O(dt/2) (c1 = exp(-dt/(2 tau)),
+ * counter (atom, bead, step, 0)); B(dt/2); A(dt) as two drifts of dt/2;
+ * forces; B(dt/2); O(dt/2) (counter (atom, bead, step, 1)).  f holds the
+ * total forces of x, U the beads' potential energies, *vb the exchange spring
+ * energy; all are those of the new x. */
 void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, double *U, double *vb,
                     uint64_t *step, int32_t nsteps);
 /* Total forces (potential + exchange springs), U per bead, returns V_B. */
 double orc_boson_forces(const orc_system *sys, const double *x, double *f, double *U);
+/* The bosonic fix's outputs (App. A's bosonic list) at a synchronized state
+ * x, v (Cartesian bead velocities): ekin = sum_k K^(k) (item 1, Cartesian);
+ * espring = V_B, the exchange spring energy: bead 0 carries the links summed
+ * over exchange cycles and beads 1..P-1 their springs inside the rings
+ * (item 2), so sum_k S^(k) = V_B; epot = sum_k U^(k) (item 3); etot = H
+ * (item 4); kprim = 3 P N kB T / 2 - EV_B / P, the bosonic primitive
+ * estimator (item 5), EV_B from orc_boson_spring; kcv holds the virial
+ * estimator K_VR = -(1/2P) sum_k sum_i r_i^k . F_i^k (item 6) with the
+ * potential's forces alone; temp as for distinguishable particles; the
+ * pressures are 0. */
+void orc_boson_estimators(const orc_system *sys, const double *x, const double *v, orc_est *out);
 
 /* --- estimators (App. A) ----------------------------------------------- */
 /* At a synchronized state.  U is [P] from orc_forces. */

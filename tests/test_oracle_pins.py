@@ -2,6 +2,7 @@
 (closed forms, invariants, library routines, textbook special cases, brute
 force), chosen so that a dropped term, a wrong sign or index, or a transposed
 operand in the oracle fails at least one of them."""
+import dataclasses
 import math
 
 import numpy as np
@@ -1156,3 +1157,131 @@ def test_boson_ev_far_apart_is_the_distinguishable_spring():
     _, _, _, ev = oracle.boson_spring(far, k, b, with_ev=True)
     e_id = sum(k * ((far[(j + 1) % P] - far[j]) ** 2).sum() for j in range(P))
     assert abs(ev - e_id) <= 1e-12 * e_id
+
+
+# ------------------------------------------------ bosonic step (OBABO) and outputs
+def test_boson_obabo_nve_is_baoab_nve():
+    """Without the thermostat both splittings are velocity Verlet (OBABO's
+    A(dt) taken as two drifts of dt/2): the same trajectory bit for bit."""
+    s, x, v = _trapped_bosons(3, 5, 0.01, True, seed=21)
+    a = oracle.BosonState(s, x, v)
+    a.step(50)
+    s2 = dataclasses.replace(s, integrator=1)
+    b = oracle.BosonState(s2, x, v)
+    b.step(50)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v)
+
+
+def test_boson_obabo_one_step_by_hand():
+    """One OBABO step of one particle in a trap, written out: O(dt/2) with the
+    counter (atom, bead, 0, 0) draws, B, two drifts, forces of the new
+    positions (trap plus the ring's springs), B, O(dt/2) with (atom, bead, 0, 1)."""
+    s, x, v = _trapped_bosons(1, 3, 0.02, False, seed=5)
+    s = dataclasses.replace(s, integrator=1)
+    st = oracle.BosonState(s, x, v)
+    st.step(1)
+    P, N = 3, 1
+    kT, m = s.kB * s.temp, 1.0
+    c1 = math.exp(-0.5 * s.dt / s.tau)
+    c2 = math.sqrt(1 - c1 * c1)
+    sig = math.sqrt(P * kT / m)
+    wn = P * kT / s.hbar
+    ks = 0.5 * m * wn * wn
+
+    def force(y):
+        f = -m * s.omega ** 2 * y
+        for j in range(P):     # the ring: bead j linked to j+1 and j-1 (cyclic, one particle)
+            f[j] += -2 * ks * (y[j] - y[(j + 1) % P]) - 2 * ks * (y[j] - y[(j - 1) % P])
+        return f
+
+    h = 0.5 * s.dt
+    xx, vv = x[:, 0].copy(), v[:, 0].copy()
+    f0 = force(xx)
+    z0 = np.array([oracle.gaussians(s.seed, 0, 0, j, 0, 0) for j in range(P)])
+    z1 = np.array([oracle.gaussians(s.seed, 0, 0, j, 0, 1) for j in range(P)])
+    vv = c1 * vv + c2 * sig * z0
+    vv = vv + h * f0 / m
+    xx = xx + h * vv
+    xx = xx + h * vv
+    vv = vv + h * force(xx) / m
+    vv = c1 * vv + c2 * sig * z1
+    assert np.abs(st.x[:, 0] - xx).max() <= 1e-14 * np.abs(xx).max()
+    assert np.abs(st.v[:, 0] - vv).max() <= 1e-13 * np.abs(vv).max()
+
+
+def test_boson_outputs_reduce_to_distinguishable():
+    """Far apart (and for one particle) no exchange carries weight: the
+    bosonic primitive estimator equals the distinguishable one of the same
+    state, K_VR of the trap is sum_k U^(k) / P, H = K + V_B + U, and V_B
+    exceeds the distinguishable springs by ln(N!)/beta_n."""
+    rng = np.random.default_rng(9)
+    N, P = 4, 5
+    path = rng.normal(0, 0.3, (P, N, 3))
+    x = path + 40.0 * np.arange(N)[None, :, None] * np.array([1.0, 0.0, 0.0])
+    v = rng.normal(0, 1.0, (P, N, 3))
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=0.7, hbar=0.6, dt=0.01,
+                      tau=0.2, pot=oracle.POT_HARMONIC, omega=0.8, seed=2)
+    e = oracle.BosonState(s, x, v).estimators()
+    d = oracle.State(s, x, v).estimators()
+    bn = 1.0 / (P * s.kB * s.temp)
+    assert abs(e["kprim"] - d["kprim"]) <= 1e-11 * abs(d["kprim"])
+    assert abs(e["espring"] - d["espring"] - math.log(math.factorial(N)) / bn) <= 1e-11 * d["espring"]
+    assert abs(e["ekin"] - d["ekin"]) <= 1e-12 * d["ekin"]
+    assert abs(e["epot"] - d["epot"]) <= 1e-12 * d["epot"]
+    assert abs(e["kcv"] - e["epot"] / P) <= 1e-12 * e["epot"]
+    assert abs(e["etot"] - (e["ekin"] + e["espring"] + e["epot"])) <= 1e-12 * abs(e["etot"])
+    x1 = x[:, :1].copy()
+    s1 = dataclasses.replace(s, n_atoms=1, mass=np.ones(1))
+    e1 = oracle.BosonState(s1, x1, v[:, :1]).estimators()
+    d1 = oracle.State(s1, x1, v[:, :1]).estimators()
+    for n in ("kprim", "espring", "ekin", "epot", "etot"):
+        assert abs(e1[n] - d1[n]) <= 1e-12 * max(1.0, abs(d1[n])), n
+
+
+def _boson_trap_energy(N, P, beta, m=1.0, omega=1.0, hbar=1.0, h=1e-5):
+    """E = -d ln Z / d beta of N bosons in a 3-D harmonic trap at P beads:
+    Z = (m P / (2 pi beta hbar^2))^(3PN/2) sum over the recursion's
+    compositions of its weight times the cube of the 1-D Gaussian integral of
+    that composition's rings (springs m omega_n^2 / 2, omega_n = P/(beta hbar);
+    trap m omega^2 / 2 per bead; the Boltzmann factor at beta/P)."""
+    comps = list(_compositions(N))
+
+    def lnz(b):
+        wn = P / (b * hbar)
+        ks = 0.5 * m * wn * wn
+        z = sum(c * _gauss_z(P, N, ks, 0.5 * m * omega ** 2, b / P, rings) ** 3 for c, rings in comps)
+        return 1.5 * P * N * math.log(m * P / (2 * math.pi * b * hbar ** 2)) + math.log(z)
+
+    return -(lnz(beta * (1 + h)) - lnz(beta * (1 - h))) / (2 * beta * h)
+
+
+def test_boson_estimators_give_the_exact_trap_energy():
+    """Three bosons in a harmonic trap at kB T = 0.5 hbar omega, P = 4: the
+    averages of the primitive estimator K_PR and of the virial estimator K_VR
+    both equal half the exact finite-P energy, -(1/2) d ln Z / d beta, with Z
+    from the recursion's Gaussian integrals (for a harmonic trap the virial
+    theorem makes the kinetic energy equal to the potential energy).  Long
+    NVT run of the bosonic BAOAB step; the distinguishable particles' energy
+    is excluded."""
+    N, P, kT = 3, 4, 0.5
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=kT, hbar=1.0, dt=0.05,
+                      tau=1.0 / (2 * P * kT), pot=oracle.POT_HARMONIC, omega=1.0, seed=77)
+    rng = np.random.default_rng(1)
+    x = rng.normal(0, 0.5, (1, N, 3)) + rng.normal(0, 0.1, (P, N, 3))
+    v = rng.normal(0, math.sqrt(P * kT), (P, N, 3))
+    st = oracle.BosonState(s, x, v)
+    st.step(2000)
+    kp, kv = [], []
+    for _ in range(40000):
+        st.step(5)
+        e = st.estimators()
+        kp.append(e["kprim"])
+        kv.append(e["kcv"])
+    ex = 0.5 * _boson_trap_energy(N, P, 1.0 / kT)
+    kp, kv = np.array(kp).reshape(40, -1).mean(axis=1), np.array(kv).reshape(40, -1).mean(axis=1)
+    sp, sv = kp.std(ddof=1) / math.sqrt(40), kv.std(ddof=1) / math.sqrt(40)
+    assert abs(kp.mean() - ex) < 4 * sp + 2e-3 * ex, (kp.mean(), ex, sp)
+    assert abs(kv.mean() - ex) < 4 * sv + 2e-3 * ex, (kv.mean(), ex, sv)
+    # distinguishable particles in the same trap at the same P: a different energy
+    ed = 0.5 * N * _boson_trap_energy(1, P, 1.0 / kT)
+    assert abs(ed - ex) > 10 * max(sp, sv), (ed, ex)
