@@ -323,6 +323,21 @@ int pimd_set_barostat(pimd_ctx *ctx, const double *box, double vw);
 int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
                       const double *box, double *f, double *prob, double *out, void *stream);
 
+/* pimd_boson_spring without any allocation, for callers that cannot allocate
+ * device memory: code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as
+ * pimd_boson_spring, for N <= 512 (UNSUPPORTED above).  Its scratch is a
+ * static device array of 2.1 MB per device, held until the process ends and
+ * looked up (hipGetSymbolAddress) at the first call on each device.  The call
+ * enqueues its kernels on stream and returns without waiting.  All calls on a
+ * device share that device's scratch, which keeps the last call's contents
+ * (every value a call reads is written earlier in the same call, so nothing is
+ * cleared): calls that overlap on one device, on different streams or from
+ * different host threads, race and give wrong results. */
+int pimd_boson_spring_noalloc(const double *x, int32_t N, int32_t P, double kspring,
+                              double beta_n, const double *box, double *f, double *prob,
+                              double *out, void *stream);
+
 /* Clear the running sums (enqueued on the stream).  Errors: STATE, DEVICE. */
 int pimd_reset_averages(pimd_ctx *ctx);
 

@@ -92,6 +92,16 @@ int fail(pimd_ctx *c, int code, const std::string &msg)
     return code;
 }
 
+}  // namespace
+
+int pimd::report_error(int code, const char *msg)
+{
+    g_create_error = msg;
+    return code;
+}
+
+namespace {
+
 int hip_fail(pimd_ctx *c, hipError_t e, const char *where)
 {
     return fail(c, PIMD_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
@@ -910,48 +920,6 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
 }  // extern "C"
 
 extern "C" {
-
-int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
-                      const double *box, double *f, double *prob, double *out, void *stream)
-{
-    if (!x || !f || !out) return fail(nullptr, PIMD_ERR_ARG, "x, f and out must be non-NULL");
-    if (N < 1 || P < 1) return fail(nullptr, PIMD_ERR_ARG, "N and P must be >= 1");
-    if (!(kspring >= 0.0) || !std::isfinite(kspring) || !finite_pos(beta_n))
-        return fail(nullptr, PIMD_ERR_ARG, "kspring >= 0 and beta_n > 0 must be finite");
-    if (box)
-        for (int d = 0; d < 3; ++d)
-            if (!(box[d] >= 0.0) || !std::isfinite(box[d]))
-                return fail(nullptr, PIMD_ERR_ARG, "box lengths must be finite and >= 0");
-    if (N > kBosonMaxN || P > kMaxBeads)
-        return fail(nullptr, PIMD_ERR_UNSUPPORTED, "N > 1024 or P > 128");
-    hipStream_t st = (hipStream_t)stream;
-    double *scr = nullptr;
-    hipError_t e = hipMalloc((void **)&scr, boson_scr_doubles(N) * sizeof(double));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(nullptr, PIMD_ERR_OOM, "scratch allocation failed");
-    }
-    BosonArgs a{};
-    a.x = x;
-    a.N = N;
-    a.P = P;
-    a.layout = 0;
-    a.ks = kspring;
-    a.bn = beta_n;
-    for (int d = 0; d < 3; ++d) a.box[d] = box ? box[d] : 0.0;
-    a.f = f;
-    a.prob = prob;
-    a.scr = scr;
-    a.res = out;
-    launch_boson_springs(a, st);
-    e = hipGetLastError();
-    // the scratch is freed once the kernels that read it are done
-    const hipError_t es = hipStreamSynchronize(st);
-    (void)hipFree(scr);
-    if (e == hipSuccess) e = es;
-    if (e != hipSuccess) return fail(nullptr, PIMD_ERR_DEVICE, hipGetErrorString(e));
-    return PIMD_OK;
-}
 
 int pimd_get_barostat(pimd_ctx *c, double *box, double *vw)
 {

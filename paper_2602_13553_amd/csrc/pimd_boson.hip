@@ -29,10 +29,21 @@
 //   k_boson_links : one wave per particle: the chain links' probabilities
 //                   (sums of those suffix sums) and the link forces on the
 //                   particle's first and last beads
+#include "../../include/pimd.h"
 #include "pimd_internal.h"
 #include "pimd_device.h"
 
+#include <cmath>
+#include <mutex>
+
 namespace pimd {
+
+// The allocation-free entry point's scratch (pimd_boson_spring_noalloc): one
+// copy per device, 2.1 MB, held until the process ends.  Host code reaches it
+// only through the per-device address from hipGetSymbolAddress (in host code
+// the array's name is a host-side stand-in, not a device address).
+constexpr int kBosonNoAllocMaxN = 512;
+static __device__ __align__(256) double scratch[boson_scr_doubles(kBosonNoAllocMaxN)];
 
 namespace {
 
@@ -449,6 +460,58 @@ __global__ __launch_bounds__(kBlock) void k_boson_links(BosonArgs a)
     }
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of scratch, looked up at its first use.
+hipError_t device_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+int boson_args(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
+               const double *box, double *f, double *prob, double *out, int max_n, BosonArgs &a)
+{
+    if (!x || !f || !out) return report_error(PIMD_ERR_ARG, "x, f and out must be non-NULL");
+    if (N < 1 || P < 1) return report_error(PIMD_ERR_ARG, "N and P must be >= 1");
+    if (!(kspring >= 0.0) || !std::isfinite(kspring) || !(beta_n > 0.0) || !std::isfinite(beta_n))
+        return report_error(PIMD_ERR_ARG, "kspring >= 0 and beta_n > 0 must be finite");
+    if (box)
+        for (int d = 0; d < 3; ++d)
+            if (!(box[d] >= 0.0) || !std::isfinite(box[d]))
+                return report_error(PIMD_ERR_ARG, "box lengths must be finite and >= 0");
+    if (N > max_n)
+        return report_error(PIMD_ERR_UNSUPPORTED, max_n == kBosonNoAllocMaxN
+                                                      ? "N > 512 (the allocation-free scratch's limit)"
+                                                      : "N > 1024");
+    if (P > kMaxBeads) return report_error(PIMD_ERR_UNSUPPORTED, "P > 128");
+    a = BosonArgs{};
+    a.x = x;
+    a.N = N;
+    a.P = P;
+    a.layout = 0;
+    a.ks = kspring;
+    a.bn = beta_n;
+    for (int d = 0; d < 3; ++d) a.box[d] = box ? box[d] : 0.0;
+    a.f = f;
+    a.prob = prob;
+    a.res = out;
+    return PIMD_OK;
+}
+
 }  // namespace
 
 void launch_boson_springs(const BosonArgs &a, hipStream_t st)
@@ -461,3 +524,48 @@ void launch_boson_springs(const BosonArgs &a, hipStream_t st)
 }
 
 }  // namespace pimd
+
+using namespace pimd;
+
+extern "C" {
+
+int pimd_boson_spring(const double *x, int32_t N, int32_t P, double kspring, double beta_n,
+                      const double *box, double *f, double *prob, double *out, void *stream)
+{
+    BosonArgs a;
+    int rc = boson_args(x, N, P, kspring, beta_n, box, f, prob, out, kBosonMaxN, a);
+    if (rc != PIMD_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMalloc((void **)&a.scr, boson_scr_doubles(N) * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return report_error(PIMD_ERR_OOM, "scratch allocation failed");
+    }
+    launch_boson_springs(a, st);
+    e = hipGetLastError();
+    // the scratch is freed once the kernels that read it are done
+    const hipError_t es = hipStreamSynchronize(st);
+    (void)hipFree(a.scr);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return report_error(PIMD_ERR_DEVICE, hipGetErrorString(e));
+    return PIMD_OK;
+}
+
+int pimd_boson_spring_noalloc(const double *x, int32_t N, int32_t P, double kspring,
+                              double beta_n, const double *box, double *f, double *prob,
+                              double *out, void *stream)
+{
+    BosonArgs a;
+    int rc = boson_args(x, N, P, kspring, beta_n, box, f, prob, out, kBosonNoAllocMaxN, a);
+    if (rc != PIMD_OK) return rc;
+    hipError_t e = device_scratch(&a.scr);
+    if (e != hipSuccess) return report_error(PIMD_ERR_DEVICE, hipGetErrorString(e));
+    // every scratch value the kernels read is written earlier in the same
+    // call, so nothing needs clearing
+    launch_boson_springs(a, (hipStream_t)stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return report_error(PIMD_ERR_DEVICE, hipGetErrorString(e));
+    return PIMD_OK;
+}
+
+}  // extern "C"

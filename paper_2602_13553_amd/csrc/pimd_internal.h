@@ -192,10 +192,10 @@ void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s);
 // of n entries each, row n at n(n-1)/2), the adjoints adj[0..N] and the
 // particles' inner spring energies eint[N].
 constexpr int kBosonMaxN = 1024;   // particles (the sequential kernel's LDS)
-__host__ __device__ inline size_t boson_scr_tri(int N) { return (size_t)N * (size_t)(N + 1) / 2; }
-__host__ __device__ inline size_t boson_scr_adj(int N) { return 2 * boson_scr_tri(N); }
-__host__ __device__ inline size_t boson_scr_eint(int N) { return boson_scr_adj(N) + (size_t)N + 1; }
-__host__ __device__ inline size_t boson_scr_doubles(int N) { return boson_scr_eint(N) + (size_t)N; }
+constexpr __host__ __device__ inline size_t boson_scr_tri(int N) { return (size_t)N * (size_t)(N + 1) / 2; }
+constexpr __host__ __device__ inline size_t boson_scr_adj(int N) { return 2 * boson_scr_tri(N); }
+constexpr __host__ __device__ inline size_t boson_scr_eint(int N) { return boson_scr_adj(N) + (size_t)N + 1; }
+constexpr __host__ __device__ inline size_t boson_scr_doubles(int N) { return boson_scr_eint(N) + (size_t)N; }
 struct BosonArgs {
     const double *x;     // positions
     int N, P;
@@ -209,6 +209,9 @@ struct BosonArgs {
     double *res;         // [2]: V_B, EV_B (the primitive estimator's weighted ring energy)
 };
 void launch_boson_springs(const BosonArgs &a, hipStream_t st);
+
+// Records the message that pimd_last_error(NULL) returns (pimd_api.hip).
+int report_error(int code, const char *msg);
 
 // Launchers (pimd_kernels.hip).
 int fused_smem_bytes(int P);

@@ -39,7 +39,7 @@ ESTIMATOR_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp", "p
 NEST = len(ESTIMATOR_NAMES)   # PIMD_NEST
 EXPORTED = ("pimd_workspace_bytes", "pimd_create", "pimd_set_state", "pimd_step",
             "pimd_get_estimators", "pimd_get_state", "pimd_get_barostat", "pimd_set_barostat",
-            "pimd_boson_spring",
+            "pimd_boson_spring", "pimd_boson_spring_noalloc",
             "pimd_reset_averages",
             "pimd_get_positions",
             "pimd_set_forces", "pimd_destroy",
@@ -118,6 +118,7 @@ def load() -> C.CDLL:
         lib.pimd_boson_spring.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                           P(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p]
+        lib.pimd_boson_spring_noalloc.argtypes = lib.pimd_boson_spring.argtypes
         lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), C.c_double]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
@@ -205,13 +206,15 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     return p
 
 
-def boson_spring(x, kspring: float, beta_n: float, box=None, with_prob: bool = True):
+def boson_spring(x, kspring: float, beta_n: float, box=None, with_prob: bool = True,
+                 noalloc: bool = False):
     """Bosonic exchange springs on the GPU (pimd_boson_spring) for bead
     positions x ([P][N][3], float64; a torch CUDA tensor, or host data copied
     to the device): returns V_B, EV_B (the primitive estimator's weighted
     ring energy), the spring forces [P][N][3] and the link probabilities
     [N][N] (None without with_prob).  box: periodic box lengths of the
-    links' minimum image.  Runs on torch's current stream."""
+    links' minimum image.  noalloc: pimd_boson_spring_noalloc (the library's
+    static scratch, N <= 512).  Runs on torch's current stream."""
     import torch
     lib = load()
     xd = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
@@ -221,9 +224,9 @@ def boson_spring(x, kspring: float, beta_n: float, box=None, with_prob: bool = T
     out = torch.empty(2, dtype=torch.float64, device="cuda")
     bx = None if box is None else (C.c_double * 3)(*[float(b) for b in box])
     stream = torch.cuda.current_stream().cuda_stream
-    rc = lib.pimd_boson_spring(xd.data_ptr(), int(N), int(P), float(kspring), float(beta_n), bx,
-                               f.data_ptr(), prob.data_ptr() if prob is not None else None,
-                               out.data_ptr(), C.c_void_p(stream))
+    fn = lib.pimd_boson_spring_noalloc if noalloc else lib.pimd_boson_spring
+    rc = fn(xd.data_ptr(), int(N), int(P), float(kspring), float(beta_n), bx, f.data_ptr(),
+            prob.data_ptr() if prob is not None else None, out.data_ptr(), C.c_void_p(stream))
     if rc != PIMD_OK:
         msg = lib.pimd_last_error(None)
         raise PimdError(rc, msg.decode() if msg else "")
