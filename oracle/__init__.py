@@ -24,18 +24,31 @@ _SRC = os.path.join(_HERE, "pimd_oracle.c")
 POT_NONE, POT_HARMONIC, POT_PAIR = 0, 1, 2
 
 
-def build(force: bool = False) -> str:
-    """Compile ``liboracle.so`` with gcc (OpenMP on, FMA contraction off)."""
-    if force or not os.path.exists(_LIB_PATH) or (
-        os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
-                                          os.path.getmtime(os.path.join(_HERE, "pimd_oracle.h")))
+_SAN_PATH = os.path.join(_HERE, "liboracle_san.so")
+# gcc flags of the sanitized build: address and undefined-behaviour checks,
+# every finding fatal
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                  "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile ``liboracle.so`` with gcc (OpenMP on, FMA contraction off);
+    sanitize: ``liboracle_san.so`` with AddressSanitizer and
+    UndefinedBehaviorSanitizer instead (same arithmetic flags).  The loader
+    takes the library named by the environment variable ORACLE_LIB when it
+    is set (the sanitized one needs its runtimes preloaded)."""
+    path = _SAN_PATH if sanitize else _LIB_PATH
+    if force or not os.path.exists(path) or (
+        os.path.getmtime(path) < max(os.path.getmtime(_SRC),
+                                     os.path.getmtime(os.path.join(_HERE, "pimd_oracle.h")))
     ):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        tmp = path + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-Wall"] + (SANITIZE_FLAGS if sanitize else []) + \
+              ["-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 class _System(C.Structure):
@@ -68,7 +81,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(os.environ.get("ORACLE_LIB") or build())
         d = C.POINTER(C.c_double)
         u64 = C.POINTER(C.c_uint64)
         S = C.POINTER(_System)
