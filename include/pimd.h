@@ -101,7 +101,31 @@ typedef struct pimd_params {
                              default neighbor capacity allows twice the starting density
                              (set nbr_capacity for more) */
     double tau_p;         /* NPT, NPH: barostat time > 0; mass W = 3 P N kB T tau_p^2 */
+    int32_t bosonic;      /* 1: identical bosons with exchange (the bosonic fix; see below) */
+    int32_t pad0;
 } pimd_params;
+
+/* bosonic = 1: the bosonic fix of Sec. III.C.  The N atoms are identical
+ * bosons (all masses equal), integrated in Cartesian coordinates (the normal
+ * modes change under exchange): bead velocities v (Cartesian), forces of the
+ * potential plus the springs, the springs inside each particle's ring and
+ * the links from bead P-1 of one particle to bead 0 of another summed over
+ * exchange cycles (the potential of pimd_boson_spring; links under the
+ * minimum image of params.box where box > 0).  The step is BAOAB (B(dt/2)
+ * A(dt/2) O(dt) A(dt/2) B(dt/2)) or OBABO (O(dt/2) B(dt/2) A(dt) B(dt/2)
+ * O(dt/2), A(dt) as two drifts of dt/2), each O the Cartesian PILE of App. D
+ * on every bead velocity: v <- c1 v + c2 sqrt(P kB T / (m mvv2e)) z,
+ * c1 = exp(-t/tau) over the O step's length t, one damping time tau for all
+ * beads (App. D's default for Cartesian coordinates is tau = 1/(2 omega_n),
+ * omega_n = P kB T / hbar; tau_scale is unused), z of counter (atom, bead,
+ * step, q) with q as for distinguishable particles.  Ensembles NVT and NVE;
+ * potentials NONE, HARMONIC, LJ and EXTERNAL; N <= 1024; no fixcom, no
+ * barostat, not in a batch.  The estimators become App. A's bosonic outputs:
+ * espring = V_B (bead 0's exchange links plus the springs inside the rings),
+ * kprim the bosonic primitive estimator 3 P N kB T / 2 - EV_B / P (EV_B as in
+ * pimd_boson_spring), and the kcv slot holds the virial estimator K_VR =
+ * -(1/2P) sum_k sum_i r_i^k . F_i^k with the potential's forces; the
+ * pressures are 0.  pimd_get_state returns the Cartesian momenta m v. */
 
 /* The barostat (NPT, NPH; App. E, isotropic).  An OBABO step: O(dt/2) on the
  * beads and on v_W; B(dt/2) on v_W and the beads together; A(dt) with the

@@ -34,6 +34,8 @@ struct Layout {
     size_t clist, ccount, cframe, cmode;
     int npt_grid;                 // barostat passes' blocks (0: no barostat)
     size_t nft, npart;            // barostat: f~ and pass partials
+    size_t fs, bscr, bres;        // bosons: spring forces, exchange scratch, (V_B, EV_B)
+    int trap_grid;                // bosons in a trap: the trap kernel's blocks
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -45,6 +47,7 @@ bool is_npt(const pimd_params *p) { return p->ensemble == PIMD_NPT || p->ensembl
 bool thermostatted(const pimd_params *p) { return p->ensemble == PIMD_NVT || p->ensemble == PIMD_NPT; }
 // forces from an array (the force pass or the caller) rather than in the step pass
 bool forces_in_array(int pot) { return is_pair(pot) || pot == PIMD_POT_EXTERNAL; }
+bool forces_in_array(const pimd_params *p) { return p->bosonic || forces_in_array(p->potential); }
 
 }  // namespace
 
@@ -69,6 +72,7 @@ struct pimd_ctx {
     FusedArgs fa;
     PairArgs pa;
     NptArgs na;                     // the barostat's passes (NPT, NPH)
+    BosonArgs ba;                   // the exchange springs (bosonic)
     double start_box[3] = {0.0, 0.0, 0.0};   // the box and v_W the next set_state starts from
     double start_vw = 0.0;
     hipGraph_t graph = nullptr;
@@ -161,6 +165,27 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
             why = "the barostat's passes use the vector-ALU transforms and per-atom lists";
             return PIMD_ERR_UNSUPPORTED;
         }
+    }
+    if (p->bosonic != 0 && p->bosonic != 1) { why = "bosonic must be 0 or 1"; return PIMD_ERR_ARG; }
+    if (p->bosonic) {
+        if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) {
+            why = "bosons run in NVT or NVE";
+            return PIMD_ERR_UNSUPPORTED;
+        }
+        if (p->potential == PIMD_POT_WATER || p->fixcom) {
+            why = "bosons run with PIMD_POT_NONE, HARMONIC, LJ or EXTERNAL, and fixcom = 0";
+            return PIMD_ERR_UNSUPPORTED;
+        }
+        if (p->n_atoms > kBosonMaxN) { why = "more than 1024 bosons"; return PIMD_ERR_UNSUPPORTED; }
+        if (p->flags & PIMD_FLAG_CLUSTER_PAIRS) {
+            why = "bosons use per-atom neighbor lists";
+            return PIMD_ERR_UNSUPPORTED;
+        }
+        for (int d = 0; d < 3; ++d)
+            if (!(p->box[d] >= 0.0) || !std::isfinite(p->box[d])) {
+                why = "box lengths must be finite and >= 0";
+                return PIMD_ERR_ARG;
+            }
     }
     if (p->potential == PIMD_POT_HARMONIC && !std::isfinite(p->omega)) { why = "bad omega"; return PIMD_ERR_ARG; }
     if (is_pair(p->potential)) {
@@ -275,7 +300,8 @@ void cell_grid(const pimd_params *p, int n_active, double e_guess, Layout &L)
 bool use_mfma(const pimd_params *p)
 {
     const int P = p->n_beads;
-    if (!fused_mfma_supported(P) || (p->flags & PIMD_FLAG_VALU_TRANSFORMS) || is_npt(p)) return false;
+    if (!fused_mfma_supported(P) || (p->flags & PIMD_FLAG_VALU_TRANSFORMS) || is_npt(p) || p->bosonic)
+        return false;
     if (p->flags & PIMD_FLAG_MFMA_TRANSFORMS) return true;
     const int row = P == 16 ? 0 : (P == 32 ? 1 : 2);
     return (long long)p->n_atoms * P >= tuning::kMfmaMinBeadAtoms[row];
@@ -286,7 +312,8 @@ bool use_mfma(const pimd_params *p)
 bool use_clusters(const pimd_params *p, int n_active)
 {
     const int P = p->n_beads, N = p->n_atoms;
-    if (!is_pair(p->potential) || n_active == 0 || P < 8 || kBlock / P > 32 || is_npt(p)) return false;
+    if (!is_pair(p->potential) || n_active == 0 || P < 8 || kBlock / P > 32 || is_npt(p) || p->bosonic)
+        return false;
     if (p->flags & PIMD_FLAG_ATOM_PAIRS) return false;
     if (p->flags & PIMD_FLAG_CLUSTER_PAIRS) return true;
     const int row = P == 8 ? 0 : P == 16 ? 1 : P == 32 ? 2 : P == 64 ? 3 : -1;
@@ -335,7 +362,7 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.x = take(arr);
     L.yt = take(arr);
     L.v = take(arr);
-    L.f = take(forces_in_array(p->potential) ? arr : 0);
+    L.f = take(forces_in_array(p) ? arr : 0);
     L.stage = take(arr);
     L.cent = take(N * 3 * sizeof(double));
     L.cref = take(N * 3 * sizeof(double));
@@ -353,7 +380,8 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.mfma_tiles = fused_mfma_supported(p->n_beads) ? mfma_block_tiles(p->n_atoms, p->n_beads) : 0;
     const int nparts = std::max(std::max(L.fused_grid, L.mfma_grid), std::max(L.valu_tiles, L.mfma_tiles));
     L.partials = take((size_t)nparts * PF_COUNT * sizeof(double));
-    L.fpartials = take((size_t)2 * std::max(L.pair_grid, 1) * sizeof(double));
+    L.trap_grid = (p->bosonic && p->potential == PIMD_POT_HARMONIC) ? boson_trap_grid(p->n_atoms, p->n_beads) : 0;
+    L.fpartials = take((size_t)2 * std::max(std::max(L.pair_grid, L.trap_grid), 1) * sizeof(double));
     L.ctl = take(sizeof(Ctl));
     L.cell_ent = take((size_t)L.ncell * L.cell_cap * sizeof(CellEntry));
     L.cell_scnt = take((size_t)L.ncell * sizeof(int));
@@ -366,6 +394,9 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.npt_grid = is_npt(p) ? npt_grid(p->n_atoms, p->n_beads) : 0;
     L.nft = take(L.npt_grid ? arr : 0);
     L.npart = take((size_t)L.npt_grid * NP_COUNT * sizeof(double));
+    L.fs = take(p->bosonic ? arr : 0);
+    L.bscr = take(p->bosonic ? boson_scr_doubles(p->n_atoms) * sizeof(double) : 0);
+    L.bres = take(p->bosonic ? 2 * sizeof(double) : 0);
     L.total = o;
     return L;
 }
@@ -420,7 +451,8 @@ std::vector<double> mode_table(const pimd_params *p)
             r[MD_A00] = c; r[MD_A01] = s / wk; r[MD_A10] = -wk * s; r[MD_A11] = c;
         }
         if (thermostatted(p)) {
-            const double tau_k = (k == 0) ? p->tau : p->tau_scale / (2.0 * wk);
+            // bosons: Cartesian beads, one damping time for all (App. D)
+            const double tau_k = (k == 0 || p->bosonic) ? p->tau : p->tau_scale / (2.0 * wk);
             const double to = (p->integrator == PIMD_OBABO) ? 0.5 * p->dt : p->dt;
             r[MD_C1] = std::exp(-to / tau_k);
             r[MD_C2] = std::sqrt(-std::expm1(-2.0 * to / tau_k));
@@ -492,6 +524,23 @@ void enqueue_step_npt(pimd_ctx *c)
     prof_end(c, e);
 }
 
+// The forces of the current positions: the force pass (pair potentials) and,
+// for bosons, the trap's and the springs' (rings and exchange links).
+void enqueue_forces(pimd_ctx *c)
+{
+    if (c->lay.pair_grid > 0) {
+        size_t e = prof_begin(c, PIMD_KERNEL_PAIR);
+        launch_pair(c->pa, c->lay.pair_grid, c->stream);
+        prof_end(c, e);
+    }
+    if (c->p.bosonic) {
+        size_t e = prof_begin(c, PIMD_KERNEL_PAIR);
+        if (c->lay.trap_grid > 0) launch_boson_trap(c->fa, c->d_f, c->d_fpartials, c->stream);
+        launch_boson_springs(c->ba, c->stream);
+        prof_end(c, e);
+    }
+}
+
 void enqueue_step(pimd_ctx *c)
 {
     if (c->lay.npt_grid) {
@@ -503,11 +552,7 @@ void enqueue_step(pimd_ctx *c)
     // the start of the step pass) before the step's opening half-kick
     if (c->fa.fixcom && c->lay.pair_grid > 0) enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
     enqueue_fused(c, FUSED_STEP, PIMD_KERNEL_FUSED);
-    if (c->lay.pair_grid > 0) {
-        size_t e = prof_begin(c, PIMD_KERNEL_PAIR);
-        launch_pair(c->pa, c->lay.pair_grid, c->stream);
-        prof_end(c, e);
-    }
+    enqueue_forces(c);
 }
 
 }  // namespace
@@ -540,6 +585,9 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     if (!mass) return fail(nullptr, PIMD_ERR_ARG, "mass is NULL");
     for (int i = 0; i < p->n_atoms; ++i)
         if (!finite_pos(mass[i])) return fail(nullptr, PIMD_ERR_ARG, "masses must be finite and > 0");
+    if (p->bosonic)
+        for (int i = 1; i < p->n_atoms; ++i)
+            if (mass[i] != mass[0]) return fail(nullptr, PIMD_ERR_ARG, "bosons of one species: all masses equal");
 
     pimd_ctx *c = new (std::nothrow) pimd_ctx();
     if (!c) return fail(nullptr, PIMD_ERR_OOM, "host allocation failed");
@@ -585,7 +633,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     c->d_x = (double *)(w + L.x);
     c->d_v = (double *)(w + L.v);
     // forces live in d_f for the pair potentials and for the caller's forces
-    c->d_f = forces_in_array(p->potential) ? (double *)(w + L.f) : nullptr;
+    c->d_f = forces_in_array(p) ? (double *)(w + L.f) : nullptr;
     c->d_stage = (double *)(w + L.stage);
     c->d_cent = (double *)(w + L.cent);
     c->d_cref = (double *)(w + L.cref);
@@ -604,6 +652,11 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
 
     // tables in internal order
     std::vector<double> M = nm_matrix(P), modes = mode_table(p);
+    if (p->bosonic) {
+        // Cartesian bead velocities: the export's p = m M^T v needs M = 1
+        std::fill(M.begin(), M.end(), 0.0);
+        for (int k = 0; k < P; ++k) M[(size_t)k * P + k] = 1.0;
+    }
     std::vector<double> MT((size_t)P * P);
     for (int k = 0; k < P; ++k)
         for (int j = 0; j < P; ++j) MT[(size_t)j * P + k] = M[(size_t)k * P + j];
@@ -645,17 +698,24 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     if (e == hipSuccess) e = hipMemset(c->d_cent, 0, (size_t)N * 3 * sizeof(double));
     if (e == hipSuccess && pair) e = hipMemset(c->d_nbr_count, 0, (size_t)N * sizeof(int));
     if (e == hipSuccess) e = hipMemset(c->d_ctl, 0, sizeof(Ctl));
+    if (e == hipSuccess && p->bosonic) {
+        // no potential: the force array stays zero, one zero energy partial
+        e = hipMemset(c->d_f, 0, (size_t)N * 3 * P * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(c->d_fpartials, 0, 2 * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(w + L.fs, 0, (size_t)N * 3 * P * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(w + L.bres, 0, 2 * sizeof(double));
+    }
     if (e == hipSuccess && L.ncell)
         e = hipMemset(w + L.cell_scnt, 0, (size_t)L.ncell * sizeof(int));
     if (e != hipSuccess) return cleanup(PIMD_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
 
-    if (forces_in_array(p->potential) && !c->d_f)
+    if (forces_in_array(p) && !c->d_f)
         return cleanup(PIMD_ERR_DEVICE, "internal: no force array for a potential that needs one");
     if (L.n_clusters) set_pair_smem();
     FusedArgs &a = c->fa;
     a.N = N; a.P = P; a.n_active = n_active;
     a.mode = FUSED_STEP;
-    a.pair = forces_in_array(p->potential) ? 1 : 0;
+    a.pair = forces_in_array(p) ? 1 : 0;
     a.lists = pair ? 1 : 0;
     a.nvt = thermostatted(p) ? 1 : 0;
     a.obabo = p->integrator == PIMD_OBABO ? 1 : 0;
@@ -684,6 +744,27 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     a.fpartials = c->d_fpartials;
     // the force pass's energy partials; external forces bring one total
     a.n_fpartials = p->potential == PIMD_POT_EXTERNAL ? 1 : L.pair_grid;
+    a.boson = p->bosonic ? 1 : 0;
+    a.fs = p->bosonic ? (const double *)(w + L.fs) : nullptr;
+    a.bres = p->bosonic ? (const double *)(w + L.bres) : nullptr;
+    if (p->bosonic) {
+        a.n_fpartials = L.pair_grid > 0 ? L.pair_grid : (L.trap_grid > 0 ? L.trap_grid : 1);
+        a.inv_3v = 0.0;                 // no pressures for bosons
+        BosonArgs &ba = c->ba;
+        ba = BosonArgs{};
+        ba.x = c->d_x;
+        ba.N = N;
+        ba.P = P;
+        ba.layout = 1;
+        const double wn = (double)P * kT / p->hbar;
+        ba.ks = 0.5 * mass[0] * p->mvv2e * wn * wn;
+        ba.bn = 1.0 / ((double)P * kT);
+        for (int d = 0; d < 3; ++d) ba.box[d] = p->box[d] > 0.0 ? p->box[d] : 0.0;
+        ba.f = (double *)(w + L.fs);
+        ba.prob = nullptr;
+        ba.scr = (double *)(w + L.bscr);
+        ba.res = (double *)(w + L.bres);
+    }
     a.ctl = c->d_ctl;
     a.ncell = L.ncell;
     a.cell_cap = L.cell_cap;
@@ -777,8 +858,8 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
     if (c->lay.npt_grid) {
         launch_pair_npt(c->pa, c->lay.pair_grid, c->stream);
         launch_npt_a(c->na, NPT_EST, c->stream);
-    } else if (c->lay.pair_grid > 0) {
-        launch_pair(c->pa, c->lay.pair_grid, c->stream);
+    } else {
+        enqueue_forces(c);
     }
     if (!external && !c->lay.npt_grid) {
         // external forces: the estimators wait for the caller's forces
@@ -839,7 +920,8 @@ int pimd_step(pimd_ctx *c, int64_t nsteps)
         size_t e = prof_begin(c, PIMD_KERNEL_CLOSE);
         launch_npt_a(c->na, NPT_CLOSE, c->stream);
         prof_end(c, e);
-    } else if (c->lay.pair_grid > 0) {
+    } else if (c->lay.pair_grid > 0 || c->p.bosonic) {
+        // forces from arrays: the last step's closing kick and its estimators
         enqueue_fused(c, FUSED_CLOSE, PIMD_KERNEL_CLOSE);
     }
     // fixcom: the last step's centroid velocity is removed before the call ends
@@ -1262,6 +1344,7 @@ int pimd_batch_add(pimd_batch *b, const pimd_params *p, const double *mass, cons
         return bfail(b, PIMD_ERR_UNSUPPORTED, "external forces are not batched (the caller steps each system)");
     if (p->fixcom) return bfail(b, PIMD_ERR_UNSUPPORTED, "fixcom is not batched");
     if (is_npt(p)) return bfail(b, PIMD_ERR_UNSUPPORTED, "the barostat is not batched");
+    if (p->bosonic) return bfail(b, PIMD_ERR_UNSUPPORTED, "bosons are not batched");
     pimd_ctx *c = nullptr;
     int rc = pimd_create(p, mass, topo, nullptr, 0, (void *)b->stream, &c);
     if (rc != PIMD_OK) return bfail(b, rc, pimd_last_error(nullptr));

@@ -460,6 +460,203 @@ __global__ __launch_bounds__(kBlock) void k_boson_links(BosonArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The bosonic fix's step in a context (Sec. III.C: Cartesian coordinates,
+// since the normal modes change under exchange; the thermostat of Eq. D3 on
+// every bead with one damping time).  Thread = (atom, bead), A = kBlock/P
+// atoms per block, tiles strided over the grid.  The forces are the array f
+// (the potential's: force pass, trap kernel or caller) plus fs (the springs
+// inside the rings and the exchange links).  Modes as the distinguishable
+// pass: STEP (the pending closing kick, and OBABO's last O, then the
+// estimators' sums at that synchronized state, then the opening of the new
+// step: BAOAB B A O A, OBABO O B A A), CLOSE, EST, PREP (centroids only).
+// The partials are those of the distinguishable pass: PF_EKIN (Cartesian
+// kinetic energy), PF_VIR (sum of r . F over the potential's forces, for
+// K_VR), the excursion and displacement maxima for the neighbor lists, and
+// the non-finite flag.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bpass(FusedArgs a)
+{
+    __shared__ double sX[3 * kBlock];    // [A][3][P] positions of the tile
+    __shared__ double sC[3 * kBlock];    // [A][3] centroids
+    __shared__ double red[64];
+    const int P = a.P, N = a.N;
+    const int A = kBlock / P;
+    const int t = threadIdx.x, la = t / P, k = t - la * P;
+    const bool lane_ok = la < A;
+    const int mode = a.mode;
+    const long long budget = a.ctl->budget;
+    const unsigned long long step = a.ctl->step;
+    const int synced = a.ctl->synced;
+    const bool spent = (mode == FUSED_STEP && budget == 0);
+    const bool closing = (mode == FUSED_STEP || mode == FUSED_CLOSE) && !synced;
+    const bool est_now = closing || mode == FUSED_EST;
+    const bool moves = (mode == FUSED_STEP || mode == FUSED_PREP);
+    const double c1 = a.modes[MD_C1], c2 = a.modes[MD_C2];
+    const double h = a.hdt;
+    double acc_ekin = 0.0, acc_vir = 0.0, acc_emax = 0.0, acc_dmax = 0.0, acc_bad = 0.0;
+    const int ntiles = (N + A - 1) / A;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int i = tile * A + la;
+        const bool act = lane_ok && i < N;
+        double x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, fp[3] = {0.0, 0.0, 0.0};
+        double ft[3] = {0.0, 0.0, 0.0};
+        double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0, cref[3] = {0.0, 0.0, 0.0};
+        unsigned long long oi = 0;
+        const size_t b = (size_t)i * 3 * P + k;
+        if (act) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                x[d] = a.x[b + d * P];
+                v[d] = a.v[b + d * P];
+                if (mode != FUSED_PREP) {
+                    fp[d] = a.f[b + d * P];
+                    ft[d] = fp[d] + a.fs[b + d * P];
+                }
+            }
+            hm = a.atoms[i * 4 + AT_HALF_M];
+            im = a.atoms[i * 4 + AT_INV_M];
+            sg = a.atoms[i * 4 + AT_SIGMA];
+            active = a.atoms[i * 4 + AT_ACTIVE];
+            oi = (unsigned long long)a.orig[i];
+            if (k == 0 && moves) {
+                cref[0] = a.cref[i * 3]; cref[1] = a.cref[i * 3 + 1]; cref[2] = a.cref[i * 3 + 2];
+            }
+        }
+        if (spent) return;
+        if (act) {
+            // PILE on this bead's velocity over one O step, noise of step s_
+            // and O step q_ of that step, counter (atom, bead, s_, q_)
+            auto o_step = [&](unsigned long long s_, unsigned long long q_) {
+                double z[3];
+                gauss3(a.seed, oi, (unsigned long long)k, s_, z, q_);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) v[d] = c1 * v[d] + c2 * sg * z[d];
+            };
+            if (closing) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) v[d] += h * ft[d] * im;
+                if (a.obabo && a.nvt) o_step(step - 1, 1);
+            }
+            if (est_now) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    acc_ekin += hm * v[d] * v[d];
+                    acc_vir += x[d] * fp[d];
+                }
+            }
+            if (mode == FUSED_STEP) {
+                if (a.obabo) {
+                    if (a.nvt) o_step(step, 0);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        v[d] += h * ft[d] * im;
+                        x[d] += h * v[d];
+                        x[d] += h * v[d];
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        v[d] += h * ft[d] * im;
+                        x[d] += h * v[d];
+                    }
+                    if (a.nvt) o_step(step, 0);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) x[d] += h * v[d];
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) a.x[b + d * P] = x[d];
+            }
+            if (mode == FUSED_STEP || mode == FUSED_CLOSE) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) a.v[b + d * P] = v[d];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (!isfinite(x[d]) || !isfinite(v[d])) acc_bad = 1.0;
+        }
+        if (moves) {
+            // centroids, the beads' excursions and the centroids' displacement
+            // since the last list build (the rebuild criterion), cells
+            __syncthreads();   // the previous tile's reads of sX and sC are done
+            if (act) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sX[(la * 3 + d) * P + k] = x[d];
+            }
+            __syncthreads();
+            if (act && k == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double c = 0.0;
+                    for (int j = 0; j < P; ++j) c += sX[(la * 3 + d) * P + j];
+                    sC[la * 3 + d] = c / (double)P;
+                }
+            }
+            __syncthreads();
+            if (act) {
+                double e2 = 0.0, c[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    c[d] = sC[la * 3 + d];
+                    const double u = x[d] - c[d];
+                    e2 += u * u;
+                }
+                if (active != 0.0) acc_emax = fmax(acc_emax, e2);
+                if (k == 0) {
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        a.cent[i * 3 + d] = c[d];
+                        const double u = c[d] - cref[d];
+                        d2 += u * u;
+                    }
+                    if (active != 0.0) acc_dmax = fmax(acc_dmax, d2);
+                    if (a.ncell > 0 && i < a.n_active) (void)cell_of(a, i, c);
+                }
+            }
+        }
+    }
+    if (spent) return;
+    double s2[2] = {acc_ekin, acc_vir};
+    double m3[3] = {acc_emax, acc_dmax, acc_bad};
+    block_sum_max<2, 3>(s2, m3, red);
+    if (t == 0) {
+        double *pp = a.partials + (size_t)blockIdx.x * PF_COUNT;
+        for (int q = 0; q < PF_COUNT; ++q) pp[q] = 0.0;
+        pp[PF_EKIN] = s2[0];
+        pp[PF_VIR] = s2[1];
+        pp[PF_EMAX] = m3[0];
+        pp[PF_DMAX] = m3[1];
+        pp[PF_NONFINITE] = m3[2];
+    }
+}
+
+// Harmonic trap on Cartesian beads: f = -m mvv2e omega^2 x for every bead,
+// and per block the energy sum 1/2 m mvv2e omega^2 |x|^2 (fpartials, with a
+// zero virial).  Thread = (atom, bead) as in the step pass.
+__global__ __launch_bounds__(kBlock) void k_btrap(FusedArgs a, double *f, double *fpartials)
+{
+    __shared__ double red[64];
+    const int P = a.P, A = kBlock / P;
+    const int t = threadIdx.x, la = t / P, k = t - la * P;
+    const int i = blockIdx.x * A + la;
+    double e = 0.0;
+    if (!a.ctl->ran) return;   // the system took no step (uniform per block)
+    if (la < A && i < a.N) {
+        const double kk = 2.0 * a.atoms[i * 4 + AT_HALF_M] * a.omega2;
+        const size_t b = (size_t)i * 3 * P + k;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double xv = a.x[b + d * P];
+            f[b + d * P] = -kk * xv;
+            e += 0.5 * kk * xv * xv;
+        }
+    }
+    double e1[1] = {e};
+    block_sum<1>(e1, red);
+    if (t == 0) reinterpret_cast<double2 *>(fpartials)[blockIdx.x] = make_double2(e1[0], 0.0);
+}
+
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 double *g_scratch_ptr[kMaxDevices] = {};
@@ -513,6 +710,30 @@ int boson_args(const double *x, int32_t N, int32_t P, double kspring, double bet
 }
 
 }  // namespace
+
+int boson_pass_grid(int N, int P)
+{
+    const int A = kBlock / P;
+    const int ntiles = (N + A - 1) / A;
+    return ntiles < 2048 ? ntiles : 2048;
+}
+
+void launch_boson_pass(const FusedArgs &a, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bpass, dim3(grid), dim3(kBlock), 0, st, a);
+}
+
+int boson_trap_grid(int N, int P)
+{
+    const int A = kBlock / P;
+    return (N + A - 1) / A;
+}
+
+void launch_boson_trap(const FusedArgs &a, double *f, double *fpartials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_btrap, dim3(boson_trap_grid(a.N, a.P)), dim3(kBlock), 0, st, a, f,
+                       fpartials);
+}
 
 void launch_boson_springs(const BosonArgs &a, hipStream_t st)
 {

@@ -124,6 +124,11 @@ struct FusedArgs {
     CellEntry *cell_ent;      // [ncell][cell_cap] the same, increasing index, with centroids
     int *cell_scnt;           // [ncell] atoms per cell
     int4 *cinfo;              // [N] (cell, image index per dim) of each active atom's centroid
+    // bosonic exchange (the bosonic fix): Cartesian bead velocities in v, the
+    // step pass of pimd_boson.hip, and the springs' forces and energies apart
+    int boson;
+    const double *fs;         // [N][3][P] spring forces (rings and exchange links)
+    const double *bres;       // [2] V_B and EV_B of the current positions
 };
 
 // modes[k*8 + ...]
@@ -209,6 +214,13 @@ struct BosonArgs {
     double *res;         // [2]: V_B, EV_B (the primitive estimator's weighted ring energy)
 };
 void launch_boson_springs(const BosonArgs &a, hipStream_t st);
+
+// The bosonic step pass (all FusedModes) and the harmonic trap's forces on
+// Cartesian beads, with per-block energies in fpartials (pimd_boson.hip).
+int boson_pass_grid(int N, int P);
+void launch_boson_pass(const FusedArgs &a, int grid, hipStream_t st);
+int boson_trap_grid(int N, int P);
+void launch_boson_trap(const FusedArgs &a, double *f, double *fpartials, hipStream_t st);
 
 // Records the message that pimd_last_error(NULL) returns (pimd_api.hip).
 int report_error(int code, const char *msg);

@@ -585,15 +585,18 @@ __device__ void finalize_system(const FusedArgs &a, int nblocks, double *red, in
             c->ucom_pending = 0;        // the step pass removed it
         }
         if (est_now || est_after) {
-            const double ekin = tot[0] - dekin, esp = tot[1], vir = tot[2];
+            // bosons: the spring energy is V_B, the primitive estimator
+            // subtracts EV_B / P, and index 5 holds the virial estimator K_VR
+            // = -(1/2P) sum r . F (App. A, bosonic list)
+            const double ekin = tot[0] - dekin, esp = a.boson ? a.bres[0] : tot[1], vir = tot[2];
             const double epot = a.pair ? upair : tot[3];
             double v[kNumEst];
             v[0] = ekin;
             v[1] = esp;
             v[2] = epot;
             v[3] = ekin + esp + epot;
-            v[4] = a.kT15PN - esp / (double)P;
-            v[5] = a.kT15N - vir / (2.0 * (double)P);
+            v[4] = a.kT15PN - (a.boson ? a.bres[1] : esp) / (double)P;
+            v[5] = (a.boson ? 0.0 : a.kT15N) - vir / (2.0 * (double)P);
             v[6] = ekin * a.temp_norm;
             // pressures, with W = sum_k Tr Xi^k, the force pass's cell virial.
             // P_CV: the centroids' kinetic term (2 sum hm |v~0|^2, after the
@@ -697,6 +700,10 @@ int fused_grid(int N, int P)
 
 void launch_fused(const FusedArgs &a, int grid, hipStream_t s)
 {
+    if (a.boson) {
+        launch_boson_pass(a, grid, s);   // Cartesian beads (pimd_boson.hip)
+        return;
+    }
     if (a.fixcom)
         hipLaunchKernelGGL(k_fused<true>, dim3(grid), dim3(kBlock), fused_smem_bytes(a.P), s, a);
     else

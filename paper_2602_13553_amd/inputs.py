@@ -79,6 +79,7 @@ class SystemSpec:
     lj_active: np.ndarray | None = None   # [N] 0/1
     bonds: np.ndarray | None = None       # [n_bonds][2]
     nsteps: int = 0                 # length of the workload's run
+    bosonic: int = 0                # 1: identical bosons with exchange (Cartesian beads)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -134,6 +135,29 @@ def free_ring_polymer(seed: int = 7, n_atoms: int = 16, n_beads: int = 8, kT: fl
                       box=(0.0, 0.0, 0.0), seed=seed, potential=POT_NONE, mass=mass, x0=x0, v0=v0)
 
 
+def cartesian_tau(n_beads: int, kT: float, hbar: float) -> float:
+    """App. D's default damping time of the Cartesian thermostat, 1/(2 omega_n)
+    with omega_n = P kB T / hbar."""
+    return hbar / (2.0 * n_beads * kT)
+
+
+def trapped_bosons(n_atoms: int = 16, n_beads: int = 8, kT: float = 0.5, hbar: float = 1.0,
+                   omega: float = 1.0, dt: float = 0.02, seed: int = 20260213,
+                   spread: float = 0.8, ensemble: int = NVT, integrator: int = 0) -> SystemSpec:
+    """Identical bosons (m = 1) in a harmonic trap, reduced units, with the
+    Cartesian thermostat's default damping time: centers N(0, spread^2), bead
+    offsets N(0, 0.1^2), Maxwell-Boltzmann bead velocities at P*T."""
+    rng = np.random.default_rng(seed)
+    mass = np.ones(n_atoms)
+    x0 = spread * rng.standard_normal((1, n_atoms, 3)) + 0.1 * rng.standard_normal((n_beads, n_atoms, 3))
+    v0 = _mb_velocities(rng, n_beads, mass, kT, 1.0)
+    return SystemSpec(name="bosons trap N=%d P=%d" % (n_atoms, n_beads), n_atoms=n_atoms,
+                      n_beads=n_beads, temp=kT, kB=1.0, hbar=hbar, mvv2e=1.0, dt=dt,
+                      tau=cartesian_tau(n_beads, kT, hbar), tau_scale=1.0, ensemble=ensemble,
+                      box=(0.0, 0.0, 0.0), seed=seed, potential=POT_HARMONIC, mass=mass, x0=x0,
+                      v0=v0, omega=omega, integrator=integrator, bosonic=1)
+
+
 # --- Lennard-Jones quantum liquid ------------------------------------------------
 def lj_liquid(n_atoms: int = 4000, n_beads: int = 32, rho: float = 0.8, kT: float = 0.7,
               hbar: float = 0.1, dt: float = 0.002, tau: float = 0.5, rc: float = 2.5,
@@ -155,6 +179,19 @@ def lj_liquid(n_atoms: int = 4000, n_beads: int = 32, rho: float = 0.8, kT: floa
                       potential=POT_LJ, mass=mass, x0=x0, v0=v0, lj_eps=1.0, lj_sigma=1.0,
                       lj_rc=rc, skin=skin, nsteps=nsteps,
                       extra={"rho": rho, "bead_jitter": jitter})
+
+
+def lj_bosons(n_atoms: int = 108, n_beads: int = 8, rho: float = 0.8, kT: float = 1.0,
+              hbar: float = 0.5, dt: float = 0.002, seed: int = 20260213, skin: float = 0.2,
+              ensemble: int = NVT, integrator: int = 0) -> SystemSpec:
+    """An LJ liquid of identical bosons (a helium-like quantum liquid in
+    reduced units: thermal wavelength sqrt(2 pi hbar^2/(m kT)) = 1.25 sigma at
+    the defaults, above the spacing at rho = 0.8), FCC start, the Cartesian
+    thermostat's default damping time."""
+    s = lj_liquid(n_atoms=n_atoms, n_beads=n_beads, rho=rho, kT=kT, hbar=hbar, dt=dt,
+                  tau=cartesian_tau(n_beads, kT, hbar), seed=seed, ensemble=ensemble, skin=skin)
+    return replace(s, name="LJ bosons N=%d P=%d" % (n_atoms, n_beads), integrator=integrator,
+                   bosonic=1)
 
 
 # --- water-shaped system ----------------------------------------------------------

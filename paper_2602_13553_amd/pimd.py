@@ -66,6 +66,7 @@ class pimd_params(C.Structure):
         ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("nbr_capacity", C.c_int32), ("flags", C.c_int32), ("integrator", C.c_int32),
         ("fixcom", C.c_int32), ("p_ext", C.c_double), ("tau_p", C.c_double),
+        ("bosonic", C.c_int32), ("pad0", C.c_int32),
     ]
 
 
@@ -203,6 +204,7 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     p.fixcom = int(getattr(spec, "fixcom", 0))
     p.p_ext = float(getattr(spec, "p_ext", 0.0))
     p.tau_p = float(getattr(spec, "tau_p", 1.0))
+    p.bosonic = int(getattr(spec, "bosonic", 0))
     return p
 
 

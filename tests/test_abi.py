@@ -5,6 +5,7 @@ import ctypes as C
 import math
 import os
 import re
+from dataclasses import replace as dataclasses_replace
 
 import numpy as np
 import pytest
@@ -166,3 +167,38 @@ def test_barostat_validation_without_gpu():
     h.ensemble, h.integrator, h.tau_p = pimd.PIMD_NPT, pimd.PIMD_OBABO, 0.5
     hm = np.ascontiguousarray(inputs.harmonic_tiny().mass)
     assert lib.pimd_workspace_bytes(C.byref(h), pimd._dp(hm), None, C.byref(n)) == -6
+
+
+def test_bosonic_validation_without_gpu():
+    """The bosonic fix's limits are checked before any device call: NVT or
+    NVE, no water, no fixcom, no barostat, at most 1024 bosons; the trap, LJ,
+    no potential and the caller's forces are accepted, and the workspace holds
+    the spring forces and the exchange scratch."""
+    lib = pimd.load()
+    n = C.c_size_t()
+    spec = inputs.trapped_bosons(n_atoms=16, n_beads=8)
+    mass = np.ascontiguousarray(spec.mass)
+    p = pimd.params_from_spec(spec)
+    assert p.bosonic == 1
+    assert lib.pimd_workspace_bytes(C.byref(p), pimd._dp(mass), None, C.byref(n)) == 0
+    q = pimd.params_from_spec(dataclasses_replace(spec, bosonic=0))
+    n0 = C.c_size_t()
+    assert lib.pimd_workspace_bytes(C.byref(q), pimd._dp(mass), None, C.byref(n0)) == 0
+    assert n.value >= n0.value + 16 * 8 * 3 * 8 + 8 * (16 * 17)
+    for field, value, code in (("ensemble", pimd.PIMD_NPT, -6), ("potential", pimd.PIMD_POT_WATER, -6),
+                               ("fixcom", 1, -6), ("bosonic", 2, -1)):
+        bad = pimd.params_from_spec(spec)
+        setattr(bad, field, value)
+        assert lib.pimd_workspace_bytes(C.byref(bad), pimd._dp(mass), None, C.byref(n)) == code, field
+    big = inputs.trapped_bosons(n_atoms=1025, n_beads=2)
+    bp = pimd.params_from_spec(big)
+    assert lib.pimd_workspace_bytes(C.byref(bp), pimd._dp(np.ascontiguousarray(big.mass)), None,
+                                    C.byref(n)) == -6
+    lj = inputs.lj_bosons(n_atoms=108, n_beads=4)
+    lp = pimd.params_from_spec(lj)
+    assert lib.pimd_workspace_bytes(C.byref(lp), pimd._dp(np.ascontiguousarray(lj.mass)), None,
+                                    C.byref(n)) == 0
+    for pot in (pimd.PIMD_POT_NONE, pimd.PIMD_POT_EXTERNAL):
+        ok = pimd.params_from_spec(spec)
+        ok.potential = pot
+        assert lib.pimd_workspace_bytes(C.byref(ok), pimd._dp(mass), None, C.byref(n)) == 0, pot

@@ -9,6 +9,7 @@ the links alone (the inner-ring energies enter every term equally and are
 added at the end) with double-double chain sums and V', so the exponent of
 every ring weight carries the rounding of its own size, independent of
 V_B's."""
+import math
 import sys
 
 import numpy as np
@@ -88,3 +89,178 @@ def test_boson_spring_errors():
     assert ei.value.code == pimd.PIMD_ERR_ARG
     with pytest.raises(pimd.PimdError):
         pimd.boson_spring(np.zeros((2, 3, 3)), 1.0, 1.0, box=[1.0, -1.0, 1.0])
+
+
+# ----------------------------------------------------------- bosonic contexts
+from paper_2602_13553_amd import inputs  # noqa: E402
+
+EST_NAMES = ("ekin", "espring", "epot", "etot", "kprim", "kcv", "temp")
+
+
+def _boson_pair(spec, nsteps, chunks=None):
+    """The bosonic context on the GPU against the oracle's bosonic step from
+    the spec's state: positions, momenta (Cartesian m v), step and the
+    bosonic estimators."""
+    from paper_2602_13553_amd import pimd
+    _say("case %s nsteps=%d integrator=%d ensemble=%d" % (spec.name, nsteps, spec.integrator,
+                                                         spec.ensemble))
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    for c in (chunks or [nsteps]):
+        ctx.step(c)
+    ge = ctx.estimators()
+    gx, gp, gs = ctx.get_state()
+    ctx.close()
+    st = oracle.BosonState.from_spec(spec)
+    st.step(nsteps)
+    return gx, gp, gs, ge, st
+
+
+def _check_boson(g, tol=BAR, est_tol=1e-10):
+    gx, gp, gs, ge, st = g
+    oe = st.estimators()
+    ex = np.abs(gx - st.x).max() / np.abs(st.x).max()
+    ep = np.abs(gp - st.p).max() / np.abs(st.p).max()
+    _say("  x rel %.3e  p rel %.3e  V_B %.12e / %.12e  K_PR %.10e / %.10e  K_VR %.10e / %.10e"
+         % (ex, ep, ge["espring"], oe["espring"], ge["kprim"], oe["kprim"], ge["kcv"], oe["kcv"]))
+    assert gs == int(st.step_count[0])
+    assert ex <= tol and ep <= tol, (ex, ep)
+    scale = max(abs(oe["ekin"]), abs(oe["espring"]), abs(oe["epot"]), 1e-300)
+    for n in EST_NAMES:
+        s = abs(oe["temp"]) if n == "temp" else scale
+        assert abs(ge[n] - oe[n]) <= est_tol * s, (n, ge[n], oe[n])
+    for n in ("pcv", "ppr", "pmd"):
+        assert ge[n] == 0.0
+
+
+@pytest.mark.parametrize("N,P,integrator,ens", [(16, 8, 0, inputs.NVT), (16, 8, 1, inputs.NVT),
+                                                (33, 5, 0, inputs.NVE), (3, 64, 1, inputs.NVT),
+                                                (70, 1, 0, inputs.NVT)])
+def test_trapped_bosons_match_oracle(N, P, integrator, ens):
+    """Trapped bosons in a context: 20 steps (in graph-sized and ragged
+    chunks) against the oracle's bosonic step, both splittings, NVT and NVE,
+    ragged atom tiles, P = 1 and 64."""
+    spec = inputs.trapped_bosons(n_atoms=N, n_beads=P, integrator=integrator, ensemble=ens,
+                                 seed=N + P)
+    _check_boson(_boson_pair(spec, 45, chunks=[32, 13]))
+
+
+@pytest.mark.parametrize("N,P,integrator", [(108, 8, 0), (108, 8, 1), (500, 4, 0)])
+def test_lj_bosons_match_oracle(N, P, integrator):
+    """A bosonic LJ liquid (links under the minimum image, neighbor lists from
+    the all-pairs scan at N = 108 and from the centroid cells at N = 500):
+    10 steps against the oracle."""
+    spec = inputs.lj_bosons(n_atoms=N, n_beads=P, integrator=integrator, seed=N + 3 * P)
+    _check_boson(_boson_pair(spec, 10))
+
+
+def test_boson_running_sums_match_oracle():
+    """The context's running sums of the bosonic estimators over 30 steps
+    equal the sums of the oracle's per-step values."""
+    from paper_2602_13553_amd import pimd
+    spec = inputs.trapped_bosons(n_atoms=12, n_beads=6, seed=5)
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    ctx.step(30)
+    ge = ctx.estimators()
+    ctx.close()
+    st = oracle.BosonState.from_spec(spec)
+    acc = {n: 0.0 for n in EST_NAMES}
+    for _ in range(30):
+        st.step(1)
+        e = st.estimators()
+        for n in EST_NAMES:
+            acc[n] += e[n]
+    assert ge["count"] == 30
+    for n in EST_NAMES:
+        assert abs(ge["sum"][n] - acc[n]) <= 1e-10 * max(1.0, abs(acc[n])), (n, ge["sum"][n], acc[n])
+
+
+def test_boson_restart_and_determinism():
+    """get_state / set_state restarts a bosonic run where it stopped, and two
+    runs are identical bit for bit."""
+    from paper_2602_13553_amd import pimd
+    spec = inputs.lj_bosons(n_atoms=108, n_beads=4, seed=9)
+    outs = []
+    for _ in range(2):
+        a = pimd.Context.from_spec(spec)
+        a.set_state(spec.x0, spec.v0, 0)
+        a.step(40)
+        outs.append(a.get_state())
+        a.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    b = pimd.Context.from_spec(spec)
+    b.set_state(spec.x0, spec.v0, 0)
+    b.step(20)
+    x, p, s = b.get_state()
+    b.close()
+    c = pimd.Context.from_spec(spec)
+    c.set_state(x, p / spec.mass[None, :, None], s)
+    c.step(20)
+    xc, pc, sc = c.get_state()
+    c.close()
+    assert sc == 40
+    assert np.abs(xc - outs[0][0]).max() <= 1e-12 * np.abs(outs[0][0]).max()
+    assert np.abs(pc - outs[0][1]).max() <= 1e-11 * np.abs(outs[0][1]).max()
+
+
+def test_boson_nve_conserves_h():
+    """Without the thermostat the bosonic H = K + V_B + U is conserved to
+    second order in dt: its spread over a fixed time falls about fourfold when
+    dt halves."""
+    from paper_2602_13553_amd import pimd
+    spreads = []
+    for dt in (0.004, 0.002):
+        spec = inputs.trapped_bosons(n_atoms=8, n_beads=8, dt=dt, ensemble=inputs.NVE, seed=3)
+        ctx = pimd.Context.from_spec(spec)
+        ctx.set_state(spec.x0, spec.v0, 0)
+        h = []
+        for _ in range(int(round(2.0 / dt / 10))):
+            ctx.step(10)
+            h.append(ctx.estimators()["etot"])
+        ctx.close()
+        spreads.append(np.ptp(h))
+    _say("  H spread %.3e (dt 0.004), %.3e (dt 0.002)" % tuple(spreads))
+    assert 3.0 < spreads[0] / spreads[1] < 5.0
+
+
+def test_boson_trap_estimators_give_the_exact_energy():
+    """Three bosons in a harmonic trap at kB T = 0.5 hbar omega, P = 4: the
+    GPU's long-run averages of K_PR and K_VR both equal half the exact
+    finite-P energy, -(1/2) d ln Z / d beta, from the recursion's Gaussian
+    integrals (the same closed form that pins the oracle)."""
+    from paper_2602_13553_amd import pimd
+    import test_oracle_pins as pins
+    N, P, kT = 3, 4, 0.5
+    spec = inputs.trapped_bosons(n_atoms=N, n_beads=P, kT=kT, dt=0.05, seed=31, spread=0.5)
+    ex = 0.5 * pins._boson_trap_energy(N, P, 1.0 / kT)
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, 0)
+    ctx.step(2000)
+    kp, kv = [], []
+    for _ in range(40):
+        ctx.reset_averages()
+        ctx.step(5000)
+        e = ctx.estimators()
+        kp.append(e["sum"]["kprim"] / e["count"])
+        kv.append(e["sum"]["kcv"] / e["count"])
+    ctx.close()
+    kp, kv = np.array(kp), np.array(kv)
+    sp, sv = kp.std(ddof=1) / math.sqrt(len(kp)), kv.std(ddof=1) / math.sqrt(len(kv))
+    _say("  K_PR %.5f +- %.5f  K_VR %.5f +- %.5f  exact %.5f" % (kp.mean(), sp, kv.mean(), sv, ex))
+    assert abs(kp.mean() - ex) < 4 * sp + 2e-3 * ex
+    assert abs(kv.mean() - ex) < 4 * sv + 2e-3 * ex
+
+
+def test_boson_context_errors():
+    from paper_2602_13553_amd import pimd
+    spec = inputs.trapped_bosons(n_atoms=4, n_beads=4)
+    spec.mass = np.array([1.0, 1.0, 2.0, 1.0])
+    with pytest.raises(pimd.PimdError) as ei:
+        pimd.Context.from_spec(spec)
+    assert ei.value.code == pimd.PIMD_ERR_ARG
+    b = pimd.Batch()
+    with pytest.raises(pimd.PimdError) as ei:
+        b.add(inputs.trapped_bosons(n_atoms=4, n_beads=4))
+    assert ei.value.code == pimd.PIMD_ERR_UNSUPPORTED
+    b.close()
