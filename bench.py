@@ -66,6 +66,8 @@ PROFILE_FILES = {
     ("lj", "k_fused<false>"): "k_fused_lj_n4000_p32.txt",
     ("water64", "k_fused_mfma<64, false, false>"): "k_fused_mfma_water_n32766_p64.txt",
     ("water64", "k_pair"): "k_pair_water_n32766_p64.txt",
+    ("water64x4", "k_fused_mfma<64, false, false>"): "k_fused_mfma_water_n131070_p64.txt",
+    ("water64x4", "k_pair"): "k_fused_mfma_water_n131070_p64.txt",
 }
 
 
@@ -143,6 +145,20 @@ def bench_boson():
         for _ in range(n):
             pimd.boson_spring(x, 1.1, 0.9)
         out["N%d_P%d_us_per_call" % (N, P)] = (time.perf_counter() - t0) / n * 1e6
+    return out
+
+
+def bench_bosons():
+    """Bosonic contexts (the bosonic fix's Cartesian step with the exchange
+    springs in every step): 1024 trapped bosons at P = 32, and an LJ liquid
+    of 500 bosons at P = 32 (helium-like reduced units)."""
+    out = {}
+    for name, spec in (("trap_n1024_p32", inputs.trapped_bosons(n_atoms=1024, n_beads=32)),
+                       ("lj_n500_p32", inputs.lj_bosons(n_atoms=500, n_beads=32))):
+        ms, _, prof, _, _, _ = run_gpu(spec, 200, 20, 50)
+        out[name] = {"workload": spec.name, "ms_per_step": ms,
+                     "bead_atom_steps_per_s": spec.bead_atoms * 1e3 / ms,
+                     "kernels_ms": {k: v[0] for k, v in kernel_avgs(prof).items()}}
     return out
 
 
@@ -372,8 +388,19 @@ def bench_serving(n_jobs, seed=20260213):
     a 200 GB budget and stepped together, against one job at a time."""
     from paper_2602_13553_amd import serve
     tr = inputs.serving_trace(n_jobs=n_jobs, seed=seed)
-    rep = serve.serve(tr, hbm_budget=200e9, max_active=64, tick=32).summary()
-    seq = serve.serve_sequential(tr).summary()
+
+    def progress(tag):
+        state = {"last": 0}
+
+        def f(done):
+            if done >= state["last"] + 50 or done == n_jobs:
+                state["last"] = done
+                log("  %s: %d of %d jobs done" % (tag, done, n_jobs))
+        return f
+
+    rep = serve.serve(tr, hbm_budget=200e9, max_active=64, tick=32,
+                      progress=progress("continuous batching")).summary()
+    seq = serve.serve_sequential(tr, progress=progress("one at a time")).summary()
     offered = sum(j.n_atoms * j.n_beads * j.nsteps for j in tr) / max(tr[-1].arrival, 1e-9)
     return {"workload": "%d jobs, Poisson 20/s, harmonic/LJ/water, N in [256,32768], "
                         "P in {8,16,32,64}, 200-5000 steps" % n_jobs,
@@ -551,6 +578,8 @@ def main():
         out["npt"] = bench_npt(ljmake)
         log("bosonic exchange kernel")
         out["boson_spring"] = bench_boson()
+        log("bosonic contexts")
+        out["bosons"] = bench_bosons()
         log("external forces")
         out["external_forces"] = bench_external()
         log("batched: %d systems x %d steps" % (args.batch_systems, args.batch_steps))

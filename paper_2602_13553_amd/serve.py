@@ -93,7 +93,7 @@ def workspace_bytes(spec) -> int:
 
 def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32,
           keep_states: bool = False, realtime: bool = True,
-          max_active_bead_atoms: float = 2e6) -> ServeReport:
+          max_active_bead_atoms: float = 2e6, progress=None) -> ServeReport:
     """Replay ``trace`` (jobs with arrival times in seconds) through one batch.
 
     Admission is first-come first-served under three limits: the slot count,
@@ -102,7 +102,8 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
     is saturated: beyond it, another job only slows every running job down
     (shared throughput) instead of raising the aggregate rate, so waiting
     jobs start later but every job finishes sooner.  A job is always admitted
-    when nothing runs."""
+    when nothing runs.  progress: called with the number of finished jobs
+    each time a tick finishes some."""
     batch = pimd.Batch()
     pre = _Prefetch(sorted(trace, key=lambda j: j.arrival))
     report = ServeReport()
@@ -110,6 +111,7 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
     upcoming = None                        # next (job, spec) from the prefetcher
     exhausted = False
     running = {}                           # sid -> (job, bytes, admitted time)
+    left = {}                              # sid -> steps still in its budget
     used = 0.0
     active_ba = 0
     t0 = time.perf_counter()
@@ -142,6 +144,7 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
             batch.set_state(sid, spec.x0, spec.v0, 0)
             batch.set_budget(sid, job.nsteps)
             running[sid] = (job, nbytes, now())
+            left[sid] = job.nsteps
             used += nbytes
             active_ba += ba
         report.max_active = max(report.max_active, len(running))
@@ -151,16 +154,25 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
             if upcoming is not None and realtime:
                 time.sleep(max(0.0, min(0.01, upcoming[0].arrival - now())))
             continue
-        # one tick for every running job
+        # one tick for every running job.  A tick takes min(tick, budget left)
+        # steps of each job, so the host knows which jobs it finishes without
+        # reading the device; the tick is waited for (once) only when it
+        # finishes one, and each finished job's step count is checked then.
         batch.step(tick)
         report.ticks += 1
         done = []
-        for sid, (job, nbytes, adm) in running.items():
-            e = batch.estimators(sid)
-            if e["step"] >= job.nsteps:
+        for sid in running:
+            left[sid] -= tick
+            if left[sid] <= 0:
                 done.append(sid)
+        if not done:
+            continue
+        for sid in done:
+            e = batch.estimators(sid)
+            assert e["step"] == running[sid][0].nsteps, (e["step"], running[sid][0].nsteps)
         t_done = now()
         for sid in done:
+            left.pop(sid)
             job, nbytes, adm = running.pop(sid)
             r = JobResult(job.job_id, job.arrival, adm, t_done,
                           job.n_atoms * job.n_beads * job.nsteps)
@@ -170,13 +182,17 @@ def serve(trace, hbm_budget: float = 200e9, max_active: int = 64, tick: int = 32
             used -= nbytes
             active_ba -= job.n_atoms * job.n_beads
             report.results.append(r)
+        if progress is not None:
+            progress(len(report.results))
     report.wall = now()
     batch.close()
     return report
 
 
-def serve_sequential(trace, keep_states: bool = False, realtime: bool = True) -> ServeReport:
-    """One job at a time, in arrival order, each with its own context."""
+def serve_sequential(trace, keep_states: bool = False, realtime: bool = True,
+                     progress=None) -> ServeReport:
+    """One job at a time, in arrival order, each with its own context;
+    progress: called with the number of finished jobs after each."""
     report = ServeReport()
     pre = _Prefetch(sorted(trace, key=lambda j: j.arrival))
     t0 = time.perf_counter()
@@ -201,6 +217,8 @@ def serve_sequential(trace, keep_states: bool = False, realtime: bool = True) ->
         assert e["step"] == job.nsteps
         ctx.close()
         report.results.append(r)
+        if progress is not None:
+            progress(len(report.results))
     report.wall = time.perf_counter() - t0
     report.max_active = 1
     return report
