@@ -63,11 +63,12 @@ class _System(C.Structure):
         ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32)),
         ("atom_id", C.POINTER(C.c_int64)), ("integrator", C.c_int32), ("fixcom", C.c_int32),
         ("npt", C.c_int32), ("p_ext", C.c_double), ("tau_p", C.c_double),
+        ("aniso", C.c_int32),
     ]
 
 
 class _Baro(C.Structure):
-    _fields_ = [("vw", C.c_double), ("box", C.c_double * 3)]
+    _fields_ = [("vw", C.c_double), ("box", C.c_double * 3), ("vwa", C.c_double * 3)]
 
 
 class _Est(C.Structure):
@@ -110,6 +111,7 @@ def lib():
             "orc_baro_centroid_flow": (None, [C.c_double, C.c_double, d, d]),
             "orc_npt_step": (None, [S, C.POINTER(_Baro), d, d, d, d, u64, C.c_int32]),
             "orc_baro_energies": (None, [S, C.POINTER(_Baro), C.c_double, d]),
+            "orc_virial_bead_diag": (None, [S, d, d]),
             "orc_boson_spring": (C.c_double, [C.c_int32, C.c_int32, C.c_double, C.c_double, d, d,
                                               d, d, d]),
             "orc_boson_forces": (C.c_double, [S, d, d, d]),
@@ -217,6 +219,7 @@ class System:
     npt: int = 0                        # 1: isotropic BZP barostat (OBABO only); nve -> NpH
     p_ext: float = 0.0                  # target pressure
     tau_p: float = 1.0                  # barostat time, W = 3 P N kB T tau_p^2
+    aniso: int = 0                      # 1: anisotropic barostat (one v_W per dimension)
     _c: _System = field(default=None, init=False, repr=False)
 
     def cstruct(self) -> _System:
@@ -233,6 +236,7 @@ class System:
         s.integrator = int(self.integrator)
         s.fixcom = int(self.fixcom)
         s.npt, s.p_ext, s.tau_p = int(self.npt), float(self.p_ext), float(self.tau_p)
+        s.aniso = int(self.aniso)
         s.mass = _dp(self._mass)
         if self.lj_active is not None:
             self._act = np.ascontiguousarray(self.lj_active, dtype=np.int32)
@@ -263,7 +267,8 @@ class System:
                    bonds=spec.bonds, integrator=int(getattr(spec, "integrator", 0)),
                    fixcom=int(getattr(spec, "fixcom", 0)),
                    npt=int(spec.ensemble in (2, 3)), p_ext=float(getattr(spec, "p_ext", 0.0)),
-                   tau_p=float(getattr(spec, "tau_p", 1.0)))
+                   tau_p=float(getattr(spec, "tau_p", 1.0)),
+                   aniso=int(getattr(spec, "baro_aniso", 0)))
 
     # --- per-function wrappers -------------------------------------------
     def free_rp_matrix(self, k: int, h: float) -> np.ndarray:
@@ -291,6 +296,15 @@ class System:
         if xk.shape != (self.n_atoms, 3):
             raise ValueError("xk must be [n_atoms][3], got %s" % (xk.shape,))
         return lib().orc_virial_bead(C.byref(self.cstruct()), _dp(xk))
+
+    def virial_diag(self, xk: np.ndarray) -> np.ndarray:
+        """Diagonal (Xi_xx, Xi_yy, Xi_zz) of one bead's cell virial tensor."""
+        xk = np.ascontiguousarray(xk, dtype=np.float64)
+        if xk.shape != (self.n_atoms, 3):
+            raise ValueError("xk must be [n_atoms][3], got %s" % (xk.shape,))
+        w = np.zeros(3)
+        lib().orc_virial_bead_diag(C.byref(self.cstruct()), _dp(xk), _dp(w))
+        return w
 
     def spring_energy_nm(self, x: np.ndarray) -> float:
         x = np.ascontiguousarray(x, dtype=np.float64)
@@ -322,6 +336,7 @@ class State:
             self.baro = _Baro()
             self.baro.vw = 0.0
             self.baro.box = (C.c_double * 3)(*system.box)
+            self.baro.vwa = (C.c_double * 3)(0.0, 0.0, 0.0)
 
     @property
     def box(self) -> tuple:
@@ -358,7 +373,8 @@ class State:
         out = np.zeros(5)
         lib().orc_baro_energies(C.byref(self._cs()), C.byref(self.baro),
                                 self.estimators()["etot"], _dp(out))
-        return dict(zip(("volume", "kw", "uw", "jw", "enthalpy"), out.tolist()), vw=self.baro.vw)
+        vw = tuple(self.baro.vwa) if self.sys.aniso else self.baro.vw
+        return dict(zip(("volume", "kw", "uw", "jw", "enthalpy"), out.tolist()), vw=vw)
 
     # --- forces supplied by the caller (an external potential) -----------
     @classmethod

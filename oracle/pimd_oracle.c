@@ -422,6 +422,70 @@ double orc_virial_bead(const orc_system *sys, const double *xk)
     return w;
 }
 
+void orc_virial_bead_diag(const orc_system *sys, const double *xk, double w[3])
+{
+    const int32_t N = sys->n_atoms;
+    w[0] = w[1] = w[2] = 0.0;
+    if (sys->pot != ORC_POT_PAIR || !(sys->box[0] > 0.0)) return;
+    const double L[3] = {sys->box[0], sys->box[1], sys->box[2]};
+    const double rc = sys->lj_rc, rc2 = rc * rc;
+    const double eps = sys->lj_eps, sig = sys->lj_sigma;
+    double src2 = sig * sig / rc2, src6 = src2 * src2 * src2;
+    const double ushift = 4.0 * eps * (src6 * src6 - src6);
+    const int minimg = (L[0] >= 2.0 * rc) && (L[1] >= 2.0 * rc) && (L[2] >= 2.0 * rc);
+    const int n0 = minimg ? 0 : (int)ceil(rc / L[0]) + 1, n1 = minimg ? 0 : (int)ceil(rc / L[1]) + 1,
+              n2 = minimg ? 0 : (int)ceil(rc / L[2]) + 1;
+    /* every ordered pair (i, j, image) once, half each: (r_a)(F_a) = fr r_a^2
+     * (the nearest image alone when every box length is at least 2 rc);
+     * per atom, then summed in atom order */
+    double *wat = (double *)calloc(3 * (size_t)(N > 0 ? N : 1), sizeof(double));
+    if (eps != 0.0) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int32_t i = 0; i < N; ++i) {
+            if (sys->lj_active && !sys->lj_active[i]) continue;
+            double wi[3] = {0.0, 0.0, 0.0};
+            for (int32_t j = 0; j < N; ++j) {
+                if (sys->lj_active && !sys->lj_active[j]) continue;
+                double d0 = xk[3 * i] - xk[3 * j];
+                double d1 = xk[3 * i + 1] - xk[3 * j + 1];
+                double d2 = xk[3 * i + 2] - xk[3 * j + 2];
+                if (minimg) {
+                    d0 -= L[0] * nearbyint(d0 / L[0]);
+                    d1 -= L[1] * nearbyint(d1 / L[1]);
+                    d2 -= L[2] * nearbyint(d2 / L[2]);
+                }
+                for (int a = -n0; a <= n0; ++a)
+                    for (int b = -n1; b <= n1; ++b)
+                        for (int c = -n2; c <= n2; ++c) {
+                            if (j == i && a == 0 && b == 0 && c == 0) continue;
+                            const double e[3] = {d0 + a * L[0], d1 + b * L[1], d2 + c * L[2]};
+                            const double r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+                            if (r2 < rc2) {
+                                double u, fr;
+                                lj_pair(eps, sig, rc2, ushift, r2, &u, &fr);
+                                for (int q = 0; q < 3; ++q) wi[q] += 0.5 * fr * e[q] * e[q];
+                            }
+                        }
+            }
+            for (int q = 0; q < 3; ++q) wat[3 * (size_t)i + q] = wi[q];
+        }
+    }
+    for (int32_t i = 0; i < N; ++i)
+        for (int q = 0; q < 3; ++q) w[q] += wat[3 * (size_t)i + q];
+    free(wat);
+    for (int32_t b = 0; b < sys->n_bonds; ++b) {
+        int32_t i = sys->bonds[2 * b], j = sys->bonds[2 * b + 1];
+        double d[3];
+        for (int a = 0; a < 3; ++a) {
+            d[a] = xk[3 * i + a] - xk[3 * j + a];
+            d[a] -= sys->box[a] * nearbyint(d[a] / sys->box[a]);
+        }
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double fr = -2.0 * sys->bond_k * (r - sys->bond_r0) / r;
+        for (int a = 0; a < 3; ++a) w[a] += fr * d[a] * d[a];
+    }
+}
+
 void orc_forces(const orc_system *sys, const double *x, double *f, double *U)
 {
     const size_t stride = 3 * (size_t)sys->n_atoms;
@@ -785,6 +849,36 @@ void orc_baro_kick(const orc_system *sys0, orc_baro *b, const double *x, const d
                 vir += (x[e] - c) * f[e];
             }
         }
+    if (sys->aniso) {
+        /* one v_W per dimension, driven by the diagonal of the centroid-virial
+         * stress tensor: P V P_CV^aa = k0_a - vir_a + w_a */
+        double k0a[3] = {0.0, 0.0, 0.0}, fva[3] = {0.0, 0.0, 0.0}, f2a[3] = {0.0, 0.0, 0.0};
+        double vira[3] = {0.0, 0.0, 0.0}, wa[3] = {0.0, 0.0, 0.0};
+        for (int32_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                const double v = vt[(size_t)i * 3 + d], F = ft[(size_t)i * 3 + d];
+                k0a[d] += sys->mass[i] * sys->mvv2e * v * v;
+                fva[d] += F * v;
+                f2a[d] += F * F / (sys->mass[i] * sys->mvv2e);
+                double c = 0.0;
+                for (int32_t k = 0; k < P; ++k) c += x[((size_t)k * N + i) * 3 + d];
+                c /= (double)P;
+                for (int32_t k = 0; k < P; ++k) {
+                    const size_t e = ((size_t)k * N + i) * 3 + d;
+                    vira[d] += (x[e] - c) * f[e];
+                }
+            }
+        for (int32_t k = 0; k < P; ++k) {
+            double wk[3];
+            orc_virial_bead_diag(sys, x + (size_t)k * N * 3, wk);
+            for (int d = 0; d < 3; ++d) wa[d] += wk[d];
+        }
+        for (int d = 0; d < 3; ++d)
+            b->vwa[d] += h / W * (k0a[d] - vira[d] + wa[d] - (double)P * V * sys->p_ext + (double)P * kT) +
+                         h * h / W * fva[d] + h * h * h / (3.0 * W) * f2a[d];
+        free(ft);
+        return;
+    }
     for (int32_t k = 0; k < P; ++k) w += orc_virial_bead(sys, x + (size_t)k * N * 3);
     /* 3 P V P_CV = k0 - vir + w */
     b->vw += h / W * (k0 - vir + w - 3.0 * (double)P * V * sys->p_ext + 3.0 * (double)P * kT) +
@@ -809,7 +903,22 @@ static void orc_baro_o(const orc_system *sys, orc_baro *b, uint64_t s, uint64_t 
     const double sigma = sqrt((double)sys->n_beads * sys->kB * sys->temp / orc_baro_mass(sys));
     double z[3];
     orc_gaussians_q(sys->seed, 0, ~(uint64_t)0, 0, s, q, z);
-    b->vw = c1 * b->vw + c2 * sigma * z[0];
+    if (sys->aniso)
+        for (int d = 0; d < 3; ++d) b->vwa[d] = c1 * b->vwa[d] + c2 * sigma * z[d];
+    else
+        b->vw = c1 * b->vw + c2 * sigma * z[0];
+}
+
+/* the centroid modes under the barostat over t, and the box with them */
+static void orc_baro_flow_all(const orc_system *sys, orc_baro *b, double t, double *xt, double *vt)
+{
+    const int32_t N = sys->n_atoms;
+    for (int32_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const size_t e = (size_t)i * 3 + d;
+            orc_baro_centroid_flow(sys->aniso ? b->vwa[d] : b->vw, t, &xt[e], &vt[e]);
+        }
+    for (int d = 0; d < 3; ++d) b->box[d] *= exp(t * (sys->aniso ? b->vwa[d] : b->vw));
 }
 
 void orc_npt_step(const orc_system *sys0, orc_baro *b, double *x, double *vt, double *f,
@@ -842,10 +951,7 @@ void orc_npt_step(const orc_system *sys0, orc_baro *b, double *x, double *vt, do
                             vt[e] = Ah[2] * q + Ah[3] * p;
                         }
                 }
-                for (size_t e = 0; e < (size_t)N * 3; ++e)
-                    orc_baro_centroid_flow(b->vw, h, &xt[e], &vt[e]);
-                const double sc = exp(h * b->vw);
-                for (int d = 0; d < 3; ++d) b->box[d] *= sc;
+                orc_baro_flow_all(&sys, b, h, xt, vt);
                 if (half == 0 && !sys.nve) {
                     /* O(dt) on the beads' modes, then on v_W */
                     for (int32_t k = 0; k < P; ++k) {
@@ -894,10 +1000,8 @@ void orc_npt_step(const orc_system *sys0, orc_baro *b, double *x, double *vt, do
                     }
                 }
         }
-        for (size_t e = 0; e < (size_t)N * 3; ++e) orc_baro_centroid_flow(b->vw, sys.dt, &xt[e], &vt[e]);
+        orc_baro_flow_all(&sys, b, sys.dt, xt, vt);
         orc_from_normal(P, N, xt, x);
-        const double scale = exp(sys.dt * b->vw);
-        for (int d = 0; d < 3; ++d) b->box[d] *= scale;
         *step = s + 1;
         /* forces in the new box */
         sys = orc_in_box(sys0, b);
@@ -916,7 +1020,9 @@ void orc_baro_energies(const orc_system *sys, const orc_baro *b, double etot, do
 {
     const double P = (double)sys->n_beads, kT = sys->kB * sys->temp;
     const double V = b->box[0] * b->box[1] * b->box[2];
-    const double kw = 0.5 * orc_baro_mass(sys) * b->vw * b->vw;
+    const double kw = sys->aniso ? 0.5 * orc_baro_mass(sys) *
+                                       (b->vwa[0] * b->vwa[0] + b->vwa[1] * b->vwa[1] + b->vwa[2] * b->vwa[2])
+                                 : 0.5 * orc_baro_mass(sys) * b->vw * b->vw;
     const double uw = P * sys->p_ext * V;
     const double jw = -P * kT * log(V);
     out[0] = V;

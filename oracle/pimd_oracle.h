@@ -66,6 +66,7 @@ typedef struct orc_system {
                                nve = 1 the barostat's thermostat is off too (NpH) */
     double p_ext;           /* target pressure (energy per volume) */
     double tau_p;           /* barostat time: W = 3 P N kB T tau_p^2 */
+    int32_t aniso;          /* 1: anisotropic barostat (one v_W per dimension, App. E) */
 } orc_system;
 
 typedef struct orc_est {
@@ -113,6 +114,11 @@ double orc_forces_bead(const orc_system *sys, const double *xk, double *fk);
  * positions and the box, i.e. the sum of r_ij . F_ij over interacting pairs
  * (every image) and bonds.  0 without a periodic box. */
 double orc_virial_bead(const orc_system *sys, const double *xk);
+/* The diagonal Xi_aa of one bead's cell virial tensor: minus the derivative
+ * of U under the scaling of the a-components of the positions and of L_a
+ * alone, i.e. the sum of (r_ij)_a (F_ij)_a over interacting pairs (every
+ * image) and bonds.  Zeros without a periodic box. */
+void orc_virial_bead_diag(const orc_system *sys, const double *xk, double w[3]);
 /* x, f: [P][N][3]; U: [P] */
 void orc_forces(const orc_system *sys, const double *x, double *f, double *U);
 
@@ -130,8 +136,9 @@ void orc_step_kick(const orc_system *sys, double *vt, const double *f, uint64_t 
 
 /* --- BZP barostat (App. E, isotropic) ---------------------------------- */
 typedef struct orc_baro {
-    double vw;              /* barostat velocity v_W */
+    double vw;              /* barostat velocity v_W (isotropic) */
     double box[3];          /* current box lengths */
+    double vwa[3];          /* the per-dimension velocities v_Wx, v_Wy, v_Wz (anisotropic) */
 } orc_baro;
 /* W = 3 P N kB T tau_p^2 (App. A) */
 double orc_baro_mass(const orc_system *sys);

@@ -1285,3 +1285,168 @@ def test_boson_estimators_give_the_exact_trap_energy():
     # distinguishable particles in the same trap at the same P: a different energy
     ed = 0.5 * N * _boson_trap_energy(1, P, 1.0 / kT)
     assert abs(ed - ex) > 10 * max(sp, sv), (ed, ex)
+
+
+# ------------------------------------------------- anisotropic BZP barostat (App. E)
+def _scaled_energy_dim(s, xk, dim, lam):
+    """U of one bead configuration with the dim-components of the positions
+    and L_dim scaled by lam."""
+    box = list(s.box)
+    box[dim] *= lam
+    y = xk.copy()
+    y[:, dim] *= lam
+    s2 = dataclasses.replace(s, n_beads=1, box=tuple(box))
+    f, U = s2.forces(y[None])
+    return U[0]
+
+
+@pytest.mark.parametrize("case", ["lj_images", "lj_big", "water_wrapped"])
+def test_virial_diagonal_is_minus_the_one_dim_scaling_derivative(case):
+    """Xi_aa = -dU/d(lambda_a) when only the a-components of the positions and
+    L_a scale (central differences), for each a; the three sum to the trace."""
+    if case == "lj_images":
+        s, xk = _lj_box(N=12, L=4.2, seed=7)
+        s = dataclasses.replace(s, box=(4.2, 4.6, 3.9))
+    elif case == "lj_big":
+        s, xk = _lj_box(N=40, L=6.5, seed=9)
+        s = dataclasses.replace(s, box=(6.5, 7.0, 6.1))
+    else:
+        spec = inputs.water(n_atoms=96, n_beads=1, seed=4)
+        s = oracle.System.from_spec(spec)
+        xk = np.mod(spec.x0[0] + 0.45 * np.asarray(s.box), np.asarray(s.box))
+    w = s.virial_diag(xk)
+    h = 1e-6
+    for a in range(3):
+        d = (_scaled_energy_dim(s, xk, a, 1 + h) - _scaled_energy_dim(s, xk, a, 1 - h)) / (2 * h)
+        assert abs(w[a] + d) <= 1e-6 * max(1.0, abs(w[a])), (a, w[a], -d)
+    assert abs(w.sum() - s.virial(xk)) <= 1e-12 * max(1.0, abs(s.virial(xk)))
+
+
+def _nph_aniso(dt, integrator, t_total=1.0):
+    """_nph's system in a rectangular box under the anisotropic barostat
+    (one v_W per dimension) in NpH: the enthalpy every fifth step and the
+    box lengths."""
+    g, P, T = 5, 4, 2.0
+    box = (6.3, 6.6, 6.0)
+    N = g ** 3
+    pts = np.stack(np.meshgrid(*[np.arange(g)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.1, dt=dt,
+                      pot=oracle.POT_PAIR, box=box, lj_eps=1.0, lj_sigma=1.0, lj_rc=3.0,
+                      integrator=integrator, npt=1, nve=True, p_ext=1.0, tau_p=0.5, seed=3,
+                      aniso=1)
+    rng = np.random.default_rng(1)
+    x = (pts + 0.5) * (np.asarray(box) / g)
+    st = oracle.State(s, x[None] + 0.02 * rng.standard_normal((P, N, 3)),
+                      rng.standard_normal((P, N, 3)) * math.sqrt(P * T))
+    H, B = [], []
+    for _ in range(int(round(t_total / dt)) // 5):
+        st.step(5)
+        b = st.baro_energies()
+        H.append(b["enthalpy"])
+        B.append(st.box)
+    return np.array(H), np.array(B)
+
+
+@pytest.mark.parametrize("integrator", [1, 0])
+def test_bzp_aniso_nph_conserves_the_enthalpy_to_second_order(integrator):
+    """With one v_W per dimension, App. A's enthalpy H + sum_a K_Wa + U_W +
+    J_W is a constant of the NpH motion: its spread falls as dt^2 while the
+    three box lengths move by different amounts (so the box's shape
+    changes)."""
+    H1, B1 = _nph_aniso(0.002, integrator)
+    H2, B2 = _nph_aniso(0.001, integrator)
+    rel = B2 / B2[0]
+    assert np.ptp(rel[:, 0] - rel[:, 1]) > 0.01 or np.ptp(rel[:, 1] - rel[:, 2]) > 0.01
+    assert (B2.max(axis=0) / B2.min(axis=0)).max() > 1.1
+    r = np.ptp(H1) / np.ptp(H2)
+    assert 3.0 < r < 5.0, (np.ptp(H1), np.ptp(H2))
+
+
+def test_bzp_aniso_kick_is_the_exact_flow_of_the_kick():
+    """Each v_Wa after a kick of length h equals the integral of
+    (1/W)[P V (P_CV^aa(v~(t)) - P_ext) + P kT] along v~(t) = v~ + t f~/m, by
+    RK4, with P_CV^aa written out here from the centroid velocities, the
+    bead forces and the diagonal virial (App. E's stress tensor)."""
+    s, x = _lj_box(N=20, L=5.2, seed=21, P=3)
+    s = dataclasses.replace(s, box=(5.2, 5.5, 4.9), integrator=1, npt=1, p_ext=0.7, tau_p=0.3,
+                            hbar=0.3, aniso=1)
+    rng = np.random.default_rng(22)
+    st = oracle.State(s, x[None] + 0.03 * rng.standard_normal((3, 20, 3)),
+                      rng.standard_normal((3, 20, 3)) * 1.5)
+    h, P, N = 0.01, 3, 20
+    W = oracle.lib().orc_baro_mass(oracle.C.byref(s.cstruct()))
+    V = float(np.prod(s.box))
+    ft = oracle.to_normal(st.f)
+    vt0 = st.vt.copy()
+    xc = st.x.mean(axis=0)
+    vir = ((st.x - xc[None]) * st.f).sum(axis=(0, 1))
+    wd = sum(s.virial_diag(st.x[k]) for k in range(P))
+
+    def rate(t):
+        v0 = vt0[0] + t * ft[0] / s.mass[:, None]
+        k0 = (s.mass[:, None] * v0 * v0).sum(axis=0)
+        pcv = (k0 - vir + wd) / (P * V)
+        return (P * V * (pcv - s.p_ext) + P * s.kB * s.temp) / W
+
+    n, acc = 40, np.zeros(3)
+    dt = h / n
+    for j in range(n):
+        t = j * dt
+        acc += dt / 6 * (rate(t) + 4 * rate(t + dt / 2) + rate(t + dt))
+    st.baro.vwa = (oracle.C.c_double * 3)(0.25, -0.1, 0.05)
+    oracle.lib().orc_baro_kick(oracle.C.byref(s.cstruct()), oracle.C.byref(st.baro),
+                               oracle._dp(st.x), oracle._dp(st.vt), oracle._dp(st.f), h)
+    got = np.array(st.baro.vwa) - np.array([0.25, -0.1, 0.05])
+    assert np.abs(got - acc).max() <= 1e-10 * max(1.0, np.abs(acc).max()), (got, acc)
+
+
+def test_bzp_aniso_equal_dims_is_isotropic_under_symmetry():
+    """A system that is the same along x, y and z (a cubic lattice in a cubic
+    box at rest) gives the three v_Wa the same kicks.  App. E's isotropic
+    force on v_W carries 3 dt / W where each v_Wa's carries dt / W, so with a
+    barostat mass three times smaller (tau_p / sqrt(3)) each v_Wa follows the
+    isotropic v_W: the two barostats take the same steps without the
+    thermostats."""
+    g, P = 3, 2
+    N = g ** 3
+    L = 4.5
+    pts = np.stack(np.meshgrid(*[np.arange(g)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    x = (pts + 0.5) * (L / g)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.1, dt=0.002,
+                      pot=oracle.POT_PAIR, box=(L, L, L), lj_eps=1.0, lj_sigma=1.0, lj_rc=2.0,
+                      integrator=1, npt=1, nve=True, p_ext=0.5, tau_p=0.5, seed=3)
+    v = np.zeros((P, N, 3))
+    a = oracle.State(s, x[None].repeat(P, 0), v)
+    b = oracle.State(dataclasses.replace(s, aniso=1, tau_p=0.5 / math.sqrt(3.0)), x[None].repeat(P, 0), v)
+    a.step(20)
+    b.step(20)
+    vw = np.array(b.baro.vwa)
+    assert np.abs(vw - vw[0]).max() <= 1e-12 * max(1e-3, abs(vw[0]))
+    assert abs(vw[0] - a.baro.vw) <= 1e-10 * max(1e-3, abs(a.baro.vw)), (vw, a.baro.vw)
+    assert np.abs(a.x - b.x).max() <= 1e-12 * np.abs(a.x).max()
+
+
+def test_bzp_aniso_barostat_equipartition():
+    """NpT with one v_W per dimension: each v_Wa's marginal is Gaussian with
+    variance P kT / W (App. E's noise sqrt(P kB T / W) per dimension), so
+    <W v_Wa^2> = P kT for every a; a dilute ring-polymer gas in a
+    rectangular box, 6e4 steps, block-averaged error bars."""
+    N, P = 8, 4
+    box = (4.0, 4.4, 3.6)
+    rng = np.random.default_rng(5)
+    s = oracle.System(n_atoms=N, n_beads=P, mass=np.ones(N), temp=1.0, hbar=0.2, dt=0.01,
+                      pot=oracle.POT_PAIR, box=box, lj_eps=0.0, lj_rc=1.0, integrator=1, npt=1,
+                      p_ext=0.5, tau_p=0.2, tau=0.05, seed=9, aniso=1)
+    st = oracle.State(s, rng.uniform(0, 1, (1, N, 3)) * np.asarray(box) +
+                      0.01 * rng.standard_normal((P, N, 3)), rng.standard_normal((P, N, 3)) * 2)
+    W = oracle.lib().orc_baro_mass(oracle.C.byref(s.cstruct()))
+    st.step(1000)
+    acc = []
+    for _ in range(60000):
+        st.step(1)
+        acc.append(W * np.array(st.baro.vwa) ** 2)
+    blocks = np.array(acc).reshape(40, -1, 3).mean(axis=1)
+    m, se = blocks.mean(axis=0), blocks.std(axis=0) / math.sqrt(40)
+    want = P * s.kB * s.temp
+    assert np.all(np.abs(m - want) < 5 * se), (m, se, want)
+    assert np.all(se < 0.2)
