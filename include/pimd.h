@@ -13,7 +13,7 @@
  *   - unwrapped coordinates for transforms and estimators: Sec. IV.B
  *   - estimators K, S, U, H, K_PR, K_CV: App. A, Eqs. A4, A5, A7; the
  *     pressures P_CV, P_PR, P_MD and the barostat's enthalpy: App. A
- *   - isotropic BZP barostat (NpT, NpH): Sec. IV.A, App. E
+ *   - BZP barostat, isotropic or anisotropic (NpT, NpH): Sec. IV.A, App. E
  *
  * Conventions for every entry point:
  *   - Return 0 (PIMD_OK) or a negative PIMD_ERR_* code.  On error, out
@@ -51,7 +51,7 @@ extern "C" {
 #define PIMD_ERR_OVERFLOW (-7)    /* neighbor-list capacity exceeded */
 
 /* ensemble (Sec. III.C): NVT = PILE-L thermostat at P*T, NVE = no thermostat;
- * NPT = PILE-L and the isotropic BZP barostat (Sec. IV.A, App. E) with a
+ * NPT = PILE-L and the BZP barostat (Sec. IV.A, App. E) with a
  * thermostat on its velocity, NPH = the barostat with neither thermostat.
  * NPT and NPH need PIMD_POT_LJ or PIMD_POT_WATER and fixcom = 0; they are not
  * batched. */
@@ -102,7 +102,8 @@ typedef struct pimd_params {
                              (set nbr_capacity for more) */
     double tau_p;         /* NPT, NPH: barostat time > 0; mass W = 3 P N kB T tau_p^2 */
     int32_t bosonic;      /* 1: identical bosons with exchange (the bosonic fix; see below) */
-    int32_t pad0;
+    int32_t baro_aniso;   /* NPT, NPH: 1 = anisotropic barostat (one v_W per dimension;
+                             see below), 0 = isotropic; must be 0 otherwise */
 } pimd_params;
 
 /* bosonic = 1: the bosonic fix of Sec. III.C.  The N atoms are identical
@@ -127,7 +128,7 @@ typedef struct pimd_params {
  * -(1/2P) sum_k sum_i r_i^k . F_i^k with the potential's forces; the
  * pressures are 0.  pimd_get_state returns the Cartesian momenta m v. */
 
-/* The barostat (NPT, NPH; App. E, isotropic).  An OBABO step: O(dt/2) on the
+/* The barostat (NPT, NPH; App. E).  An OBABO step: O(dt/2) on the
  * beads and on v_W; B(dt/2) on v_W and the beads together; A(dt) with the
  * centroid modes under the barostat, x~0 <- e x~0 + t sinh(u)/u v~0,
  * v~0 <- v~0 / e (t = dt, u = t v_W, e = exp(u)), the other modes by the free
@@ -143,6 +144,18 @@ typedef struct pimd_params {
  * (2^64 - 1, 0, step, q) (q as for the beads' O steps).
  * pimd_set_state starts the box at params.box with v_W = 0, or at the values
  * given to pimd_set_barostat before it (a restart). */
+
+/* baro_aniso = 1: App. E's anisotropic barostat.  Each dimension a has its
+ * own v_Wa (same mass W), moves the centroid modes' component a and the box
+ * length L_a alone (u = t v_Wa in the flow above, L_a <- exp(t v_Wa) L_a),
+ * and is driven by that dimension's diagonal element of the centroid-virial
+ * stress tensor: force (1/W)[P V (P_CV^aa - p_ext) + P kB T], with
+ * P V P_CV^aa = sum_i m_i |v~0_ia|^2 - sum_k sum_i (x_ia^k - c_ia) F_ia^k +
+ * sum_k W_aa^k (W_aa^k bead k's pair virial along a), and the kick's h^2 and
+ * h^3 terms from that dimension's sums.  Its O step uses the three Gaussians
+ * of v_W's counter, one per dimension.  The box keeps no aspect ratio; the
+ * neighbor lists are rebuilt against the smallest scaling of any dimension;
+ * K_W = W sum_a v_Wa^2 / 2. */
 
 /* fixcom = 1: at the end of every step (after the closing B, and OBABO's
  * second O) the mass-weighted mean u = sum_i m_i v~0_i / sum_i m_i of the
@@ -223,9 +236,11 @@ typedef struct pimd_estimators {
     double rlist;        /* centroid cutoff of the current neighbor lists */
     /* NPT, NPH (0 otherwise), at the state's step: */
     double volume;       /* V of the current box */
-    double vw;           /* barostat velocity v_W */
+    double vw;           /* barostat velocity v_W (anisotropic: the mean of the three, the
+                            isotropic v_W with the same volume rate) */
     double enthalpy;     /* H + K_W + U_W + J_W (App. A): K_W = W v_W^2 / 2, U_W = P p_ext V,
                             J_W = -P kB T ln V */
+    double vwa[3];       /* anisotropic barostat: v_W of each dimension (0 otherwise) */
 } pimd_estimators;
 /* ekin    = sum_k sum_i 1/2 m_i |v~_i^(k)|^2 (App. A item 1)
  * espring = sum_k sum_i 1/2 m_i omega_n^2 lambda_k |x~_i^(k)|^2 (App. A item 2,
@@ -306,18 +321,19 @@ int pimd_get_estimators(pimd_ctx *ctx, pimd_estimators *out);
 int pimd_get_state(pimd_ctx *ctx, double *x, double *p, uint64_t *step);
 
 /* NPT, NPH: wait for the stream, then copy out the current box lengths
- * (box[3], may be NULL) and the barostat velocity (vw, may be NULL).
+ * (box[3], may be NULL) and the barostat velocity (vw, may be NULL: one
+ * double, or with baro_aniso the three v_Wa).
  * Errors: STATE, UNSUPPORTED (no barostat), DEVICE. */
 int pimd_get_barostat(pimd_ctx *ctx, double *box, double *vw);
 
-/* NPT, NPH: the box lengths (box[3], > 0, in the aspect ratio of params.box:
- * the barostat is isotropic) and barostat velocity that the next
- * pimd_set_state starts from,
- * e.g. those pimd_get_barostat returned with the state being restored; the
- * state's forces and estimators are then those of this box.  Host-side only
- * (no device work).  Errors: ARG (bad box or non-finite vw), UNSUPPORTED (no
- * barostat). */
-int pimd_set_barostat(pimd_ctx *ctx, const double *box, double vw);
+/* NPT, NPH: the box lengths (box[3], > 0; isotropic: in the aspect ratio of
+ * params.box, which that barostat keeps) and barostat velocity (vw: one
+ * double, or with baro_aniso three) that the next pimd_set_state starts
+ * from, e.g. those pimd_get_barostat returned with the state being restored;
+ * the state's forces and estimators are then those of this box.  Host-side
+ * only (no device work).  Errors: ARG (bad box, NULL or non-finite vw),
+ * UNSUPPORTED (no barostat). */
+int pimd_set_barostat(pimd_ctx *ctx, const double *box, const double *vw);
 
 /* Bosonic exchange springs (the bosonic fix of Sec. III.C; the exchange
  * potential of Hirshberg et al. 2019, evaluated in quadratic time as in

@@ -27,6 +27,7 @@ struct Layout {
     size_t x, yt, v, f, stage, cent, cref, M, MT, modes, atoms, mass, orig, bond_j, nbr_count, nbr,
         partials, fpartials, ctl, cell_ent, cell_scnt, cinfo, total;
     int cap, fused_grid, mfma_grid, pair_grid, pair_S, pair_active_tiles, n_active;
+    int n_forced;                 // atoms with lanes in the force pass (bond-owned ones last)
     int valu_tiles, mfma_tiles;
     int ncell, cell_cap, nc[3];   // centroid cells (ncell = 0: none)
     bool clusters;                // force pass on cluster lists
@@ -34,6 +35,7 @@ struct Layout {
     size_t clist, ccount, cframe, cmode;
     int npt_grid;                 // barostat passes' blocks (0: no barostat)
     size_t nft, npart;            // barostat: f~ and pass partials
+    size_t fdiag;                 // anisotropic barostat: per force-pass block, the cell virial's diagonal
     size_t fs, bscr, bres;        // bosons: spring forces, exchange scratch, (V_B, EV_B)
     int trap_grid;                // bosons in a trap: the trap kernel's blocks
 };
@@ -74,7 +76,7 @@ struct pimd_ctx {
     NptArgs na;                     // the barostat's passes (NPT, NPH)
     BosonArgs ba;                   // the exchange springs (bosonic)
     double start_box[3] = {0.0, 0.0, 0.0};   // the box and v_W the next set_state starts from
-    double start_vw = 0.0;
+    double start_vw[3] = {0.0, 0.0, 0.0};   // isotropic: [0]; anisotropic: per dimension
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_failed = false;
@@ -166,6 +168,10 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
             return PIMD_ERR_UNSUPPORTED;
         }
     }
+    if (p->baro_aniso != 0 && (p->baro_aniso != 1 || !is_npt(p))) {
+        why = "baro_aniso must be 0, or 1 with NPT or NPH";
+        return PIMD_ERR_ARG;
+    }
     if (p->bosonic != 0 && p->bosonic != 1) { why = "bosonic must be 0 or 1"; return PIMD_ERR_ARG; }
     if (p->bosonic) {
         if (p->ensemble != PIMD_NVT && p->ensemble != PIMD_NVE) {
@@ -220,8 +226,31 @@ int validate(const pimd_params *p, const pimd_topology *topo, std::string &why)
     return PIMD_OK;
 }
 
-// Active-first internal order; orig[internal] = caller index.
-std::vector<int> internal_order(const pimd_params *p, const pimd_topology *topo, int *n_active)
+// Atoms (caller index) outside the LJ whose only bond goes to an LJ-active
+// atom (water-shaped potential with a topology; none otherwise).
+std::vector<int> bond_owned(const pimd_params *p, const pimd_topology *topo)
+{
+    std::vector<int> owned(p->n_atoms, 0);
+    if (p->potential != PIMD_POT_WATER || !topo || !topo->lj_active) return owned;
+    std::vector<int> deg(p->n_atoms, 0), partner(p->n_atoms, -1);
+    for (int b = 0; b < topo->n_bonds; ++b) {
+        const int i = topo->bonds[2 * b], j = topo->bonds[2 * b + 1];
+        ++deg[i]; ++deg[j];
+        partner[i] = j; partner[j] = i;
+    }
+    for (int i = 0; i < p->n_atoms; ++i)
+        owned[i] = (!topo->lj_active[i] && deg[i] == 1 && topo->lj_active[partner[i]]) ? 1 : 0;
+    return owned;
+}
+
+// Internal order; orig[internal] = caller index.  LJ-active atoms first, then
+// the other atoms that need lanes of their own in the force pass, then the
+// bond-owned atoms: atoms outside the LJ with a single bond, to an LJ-active
+// atom, whose force the active atom's bond writes (the H atoms of the
+// water-shaped system).  Each group keeps the caller's order.  *n_forced is
+// the number of atoms before the bond-owned ones.
+std::vector<int> internal_order(const pimd_params *p, const pimd_topology *topo, int *n_active,
+                                int *n_forced)
 {
     std::vector<int> orig;
     orig.reserve(p->n_atoms);
@@ -230,9 +259,15 @@ std::vector<int> internal_order(const pimd_params *p, const pimd_topology *topo,
     for (int i = 0; i < p->n_atoms; ++i)
         if (!act || act[i]) orig.push_back(i);
     *n_active = is_pair(p->potential) ? (int)orig.size() : 0;
-    if (act)
+    *n_forced = (int)orig.size();
+    if (act) {
+        std::vector<int> owned = bond_owned(p, topo);
         for (int i = 0; i < p->n_atoms; ++i)
-            if (!act[i]) orig.push_back(i);
+            if (!act[i] && !owned[i]) orig.push_back(i);
+        *n_forced = (int)orig.size();
+        for (int i = 0; i < p->n_atoms; ++i)
+            if (!act[i] && owned[i]) orig.push_back(i);
+    }
     return orig;
 }
 
@@ -342,7 +377,7 @@ int choose_pair_subgroups(const pimd_params *p)
     return pair_subgroups(N, P);
 }
 
-Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
+Layout make_layout(const pimd_params *p, int n_active, int n_forced, int cap, double e_guess)
 {
     Layout L{};
     cell_grid(p, n_active, e_guess, L);
@@ -355,7 +390,8 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.mfma_grid = use_mfma(p) ? fused_mfma_grid(p->n_atoms, p->n_beads) : 0;
     L.clusters = pair && use_clusters(p, n_active);
     L.pair_S = pair ? (L.clusters ? 1 : choose_pair_subgroups(p)) : 1;
-    L.pair_grid = pair ? pair_grid(p->n_atoms, p->n_beads, L.pair_S) : 0;
+    L.n_forced = n_forced;
+    L.pair_grid = pair ? pair_grid(n_forced, p->n_beads, L.pair_S) : 0;
     L.pair_active_tiles = pair ? pair_active_tiles(n_active, p->n_beads, L.pair_S) : 0;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
@@ -393,7 +429,8 @@ Layout make_layout(const pimd_params *p, int n_active, int cap, double e_guess)
     L.cmode = take((size_t)L.n_clusters * sizeof(int));
     L.npt_grid = is_npt(p) ? npt_grid(p->n_atoms, p->n_beads) : 0;
     L.nft = take(L.npt_grid ? arr : 0);
-    L.npart = take((size_t)L.npt_grid * NP_COUNT * sizeof(double));
+    L.npart = take((size_t)L.npt_grid * NP_COUNT_ANISO * sizeof(double));
+    L.fdiag = take((L.npt_grid && p->baro_aniso) ? (size_t)L.pair_grid * 3 * sizeof(double) : 0);
     L.fs = take(p->bosonic ? arr : 0);
     L.bscr = take(p->bosonic ? boson_scr_doubles(p->n_atoms) * sizeof(double) : 0);
     L.bres = take(p->bosonic ? 2 * sizeof(double) : 0);
@@ -568,10 +605,10 @@ int pimd_workspace_bytes(const pimd_params *p, const double *mass, const pimd_to
     if (!bytes) return fail(nullptr, PIMD_ERR_ARG, "bytes is NULL");
     if (!mass && is_pair(p->potential) && p->nbr_capacity == 0)
         return fail(nullptr, PIMD_ERR_ARG, "mass is required to size neighbor lists");
-    int n_active = 0;
-    std::vector<int> orig = internal_order(p, topo, &n_active);
+    int n_active = 0, n_forced = 0;
+    std::vector<int> orig = internal_order(p, topo, &n_active, &n_forced);
     const int cap = is_pair(p->potential) ? neighbor_capacity(p, mass, orig, n_active) : 0;
-    *bytes = make_layout(p, n_active, cap, excursion_guess(p, mass, orig, n_active)).total;
+    *bytes = make_layout(p, n_active, n_forced, cap, excursion_guess(p, mass, orig, n_active)).total;
     return PIMD_OK;
 }
 
@@ -593,12 +630,12 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     if (!c) return fail(nullptr, PIMD_ERR_OOM, "host allocation failed");
     c->p = *p;
     c->graph_failed = (p->flags & PIMD_FLAG_NO_GRAPHS) != 0;
-    int n_active = 0;
-    c->orig = internal_order(p, topo, &n_active);
+    int n_active = 0, n_forced = 0;
+    c->orig = internal_order(p, topo, &n_active, &n_forced);
     const int N = p->n_atoms, P = p->n_beads;
     const bool pair = is_pair(p->potential);
     const int cap = pair ? neighbor_capacity(p, mass, c->orig, n_active) : 0;
-    c->lay = make_layout(p, n_active, cap, excursion_guess(p, mass, c->orig, n_active));
+    c->lay = make_layout(p, n_active, n_forced, cap, excursion_guess(p, mass, c->orig, n_active));
     const Layout &L = c->lay;
 
     auto cleanup = [&](int code, const std::string &msg) {
@@ -678,11 +715,13 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         for (int q = 0; q < N; ++q) inv[c->orig[q]] = q;
         bond_j.assign((size_t)N * kMaxBonds, -1);
         std::vector<int> deg(N, 0);
+        // a bond-owned atom (internal index >= n_forced) is flagged in its
+        // partner's entry: the partner's lanes write its force
         if (p->potential == PIMD_POT_WATER && topo)
             for (int b = 0; b < topo->n_bonds; ++b) {
                 const int i = inv[topo->bonds[2 * b]], j = inv[topo->bonds[2 * b + 1]];
-                bond_j[(size_t)i * kMaxBonds + deg[i]++] = j;
-                bond_j[(size_t)j * kMaxBonds + deg[j]++] = i;
+                bond_j[(size_t)i * kMaxBonds + deg[i]++] = j >= L.n_forced ? (j | kBondOwned) : j;
+                bond_j[(size_t)j * kMaxBonds + deg[j]++] = i >= L.n_forced ? (i | kBondOwned) : i;
             }
     }
     hipError_t e = hipSuccess;
@@ -779,6 +818,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
 
     PairArgs &q = c->pa;
     q.N = N; q.P = P; q.n_active = n_active; q.cap = L.cap;
+    q.n_forced = L.n_forced;
     q.S = L.pair_S;
     q.n_active_tiles = L.pair_active_tiles;
     for (int d = 0; d < 3; ++d) q.box[d] = p->box[d];
@@ -813,6 +853,9 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
         b.f = c->fa;
         b.ft = (double *)(w + L.nft);
         b.part = (double *)(w + L.npart);
+        b.aniso = p->baro_aniso;
+        b.fdiag = p->baro_aniso ? (double *)(w + L.fdiag) : nullptr;
+        q.fdiag = p->baro_aniso ? (double *)(w + L.fdiag) : nullptr;
         b.dt = p->dt;
         b.p_ext = p->p_ext;
         const double kT = p->kB * p->temp;
@@ -992,7 +1035,8 @@ int pimd_get_estimators(pimd_ctx *c, pimd_estimators *out)
     out->rlist = h.rlist;
     const bool baro = c->lay.npt_grid > 0;
     out->volume = baro ? h.volume : 0.0;
-    out->vw = baro ? h.vw : 0.0;
+    out->vw = baro ? (c->p.baro_aniso ? (h.vwa[0] + h.vwa[1] + h.vwa[2]) / 3.0 : h.vw) : 0.0;
+    for (int d = 0; d < 3; ++d) out->vwa[d] = (baro && c->p.baro_aniso) ? h.vwa[d] : 0.0;
     out->enthalpy = baro ? h.enthalpy : 0.0;
     if (h.nonfinite) return fail(c, PIMD_ERR_NONFINITE, "non-finite position or velocity");
     if (h.overflow) return fail(c, PIMD_ERR_OVERFLOW, "neighbor list capacity exceeded");
@@ -1013,24 +1057,37 @@ int pimd_get_barostat(pimd_ctx *c, double *box, double *vw)
     HIP_TRY(c, hipMemcpy(&h, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     if (box)
         for (int d = 0; d < 3; ++d) box[d] = h.box[d];
-    if (vw) *vw = h.vw;
+    if (vw) {
+        if (c->p.baro_aniso)
+            for (int d = 0; d < 3; ++d) vw[d] = h.vwa[d];
+        else
+            *vw = h.vw;
+    }
     return PIMD_OK;
 }
 
-int pimd_set_barostat(pimd_ctx *c, const double *box, double vw)
+int pimd_set_barostat(pimd_ctx *c, const double *box, const double *vw)
 {
     if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
     if (!c->lay.npt_grid) return fail(c, PIMD_ERR_UNSUPPORTED, "no barostat (ensemble is not NPT or NPH)");
-    // the barostat scales all three lengths together: the aspect ratio stays
-    // that of params.box
+    const bool an = c->p.baro_aniso != 0;
     bool ok = box != nullptr;
     for (int d = 0; ok && d < 3; ++d) ok = finite_pos(box[d]);
-    const double g = ok ? box[0] / c->p.box[0] : 0.0;
-    for (int d = 1; ok && d < 3; ++d) ok = std::fabs(box[d] / c->p.box[d] - g) <= 1e-9 * g;
-    if (!ok) return fail(c, PIMD_ERR_ARG, "box must hold lengths > 0 in the aspect ratio of params.box");
-    if (!std::isfinite(vw)) return fail(c, PIMD_ERR_ARG, "vw must be finite");
+    if (!an) {
+        // the isotropic barostat scales all three lengths together: the
+        // aspect ratio stays that of params.box
+        const double g = ok ? box[0] / c->p.box[0] : 0.0;
+        for (int d = 1; ok && d < 3; ++d) ok = std::fabs(box[d] / c->p.box[d] - g) <= 1e-9 * g;
+        if (!ok) return fail(c, PIMD_ERR_ARG, "box must hold lengths > 0 in the aspect ratio of params.box");
+    } else if (!ok) {
+        return fail(c, PIMD_ERR_ARG, "box must hold three lengths > 0");
+    }
+    const int nv = an ? 3 : 1;
+    bool okv = vw != nullptr;
+    for (int d = 0; okv && d < nv; ++d) okv = std::isfinite(vw[d]);
+    if (!okv) return fail(c, PIMD_ERR_ARG, "vw must be non-NULL and finite");
     for (int d = 0; d < 3; ++d) c->start_box[d] = box[d];
-    c->start_vw = vw;
+    for (int d = 0; d < 3; ++d) c->start_vw[d] = d < nv ? vw[d] : 0.0;
     return PIMD_OK;
 }
 

@@ -71,6 +71,7 @@ struct Ctl {
     double volume;             // V, K_W + U_W + J_W and the enthalpy at the estimator point
     double ebaro;
     double enthalpy;
+    double vwa[3];             // anisotropic barostat: v_W per dimension (vw unused)
 };
 
 // One atom of a centroid cell as the list build reads it: its centroid, its
@@ -136,8 +137,13 @@ enum { MD_A00 = 0, MD_A01, MD_A10, MD_A11, MD_C1, MD_C2, MD_SPRING, MD_NONCENTRO
 // atoms[i*4 + ...]
 enum { AT_HALF_M = 0, AT_INV_M, AT_SIGMA, AT_ACTIVE };
 
+// bond_j entries with this bit set name a partner whose force the atom's
+// bond writes (the partner has no lane of its own in the force pass)
+constexpr int kBondOwned = 1 << 30;
+
 struct PairArgs {
     int N, P, n_active, cap;
+    int n_forced;             // atoms 0..n_forced-1 have lanes; the rest are bond-owned
     int S;                    // sub-groups of lanes sharing one atom's list
     int n_active_tiles;       // tiles that hold LJ-active atoms (they come first)
     double box[3];
@@ -165,6 +171,8 @@ struct PairArgs {
     int *ccount;              // [n_clusters]
     int *cframe;              // [n_active] packed box offset of each atom in its cluster's frame
     int *cmode;               // [n_clusters] 0: cluster list, 1: per-atom lists (fallback)
+    double *fdiag;            // anisotropic barostat: [blocks][3] the diagonal of each
+                              // block's cell virial (nullptr: not needed)
 };
 
 // Barostat passes (pimd_npt.hip).  A step is: NPT_STEP pass A (pending
@@ -176,10 +184,15 @@ enum NptMode : int { NPT_STEP = 0, NPT_CLOSE = 1, NPT_EST = 2 };
 // per-block partials of pass A
 enum { NP_EKIN = 0, NP_ESPRING, NP_VIR, NP_K0, NP_K0A, NP_FVA, NP_F2, NP_K0B, NP_FVB, NP_BAD,
        NP_COUNT };
+// the anisotropic barostat's per-dimension sums, after those (3 each)
+enum { NP_K0A3 = NP_COUNT, NP_FVA3 = NP_COUNT + 3, NP_F23 = NP_COUNT + 6, NP_K0B3 = NP_COUNT + 9,
+       NP_FVB3 = NP_COUNT + 12, NP_VIR3 = NP_COUNT + 15, NP_COUNT_ANISO = NP_COUNT + 18 };
 struct NptArgs {
     FusedArgs f;              // the system (x, v, f, tables, control block, partials)
     double *ft;               // [N][3][P] f~ of the current forces (pass A -> pass B)
-    double *part;             // [gridDim][NP_COUNT] pass A partials; pass B: [gridDim][3]
+    double *part;             // [gridDim][NP_COUNT_ANISO] pass A partials; pass B: [gridDim][3]
+    int aniso;                // 1: one v_W per dimension (App. E's anisotropic barostat)
+    const double *fdiag;      // aniso: [force-pass blocks][3] diagonal of the cell virial
     double dt;
     double p_ext;
     double wmass;             // W = 3 P N kB T tau_p^2
@@ -187,7 +200,8 @@ struct NptArgs {
     double kTP;               // P kB T
 };
 int npt_grid(int N, int P);
-void launch_npt_init(Ctl *ctl, const double box[3], double vw, hipStream_t s);
+// vw: the isotropic v_W in [0]; anisotropic, the three v_Wa
+void launch_npt_init(Ctl *ctl, const double box[3], const double vw[3], hipStream_t s);
 void launch_npt_a(const NptArgs &a, int mode, hipStream_t s);
 void launch_npt_b(const NptArgs &a, hipStream_t s);
 void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s);

@@ -757,10 +757,14 @@ __device__ __forceinline__ void lj_energy_virial(double s12, double s6, int np, 
     w += 0.5 * eps24 * (2.0 * s12 - s6);
 }
 
+// DIAG: also the pair's r_a F_a per dimension into wd (the diagonal of the
+// cell virial, for the anisotropic barostat)
+template <bool DIAG = false>
 __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, double rc2,
                                               double sig2, double eps24,
                                               double &fx, double &fy, double &fz,
-                                              double &s12, double &s6, int &np)
+                                              double &s12, double &s6, int &np,
+                                              double *wd = nullptr)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
@@ -777,6 +781,52 @@ __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, d
         // are formed once per thread (lj_energy_virial)
         s12 += sr12; s6 += sr6; ++np;
         fx += fr * dx; fy += fr * dy; fz += fr * dz;
+        if constexpr (DIAG) {
+            wd[0] += fr * dx * dx; wd[1] += fr * dy * dy; wd[2] += fr * dz * dz;
+        }
+    }
+}
+
+// Harmonic bonds of atom i at bead k (minimum image), added to its force and
+// to the thread's energy and virial sums.  A partner flagged kBondOwned has
+// no lane of its own (an atom outside the LJ whose only bond is this one): its
+// force is minus this bond's force, written here, and the whole bond's energy
+// and virial are counted here (otherwise each side counts half).  The
+// partner's force is the exact negative of what its own lanes would compute,
+// since the minimum-image difference is antisymmetric.
+template <bool DIAG = false>
+__device__ __forceinline__ void bond_forces(const PairArgs &a, int i, int k, double xi, double yi,
+                                            double zi, double L0, double L1, double L2,
+                                            double &fx, double &fy, double &fz, double &e,
+                                            double &wv, double *wd = nullptr)
+{
+    const int P = a.P, P3 = 3 * P;
+    const double *__restrict__ X = a.x;
+    for (int bb = 0; bb < kMaxBonds; ++bb) {
+        const int jr = a.bond_j[i * kMaxBonds + bb];
+        if (jr < 0) break;
+        const bool owned = (jr & kBondOwned) != 0;
+        const int j = jr & ~kBondOwned;
+        const size_t jb = (size_t)j * P3 + k;
+        double dx = xi - X[jb], dy = yi - X[jb + P], dz = zi - X[jb + 2 * P];
+        dx -= L0 * rint(dx / L0);
+        dy -= L1 * rint(dy / L1);
+        dz -= L2 * rint(dz / L2);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double dr = r - a.bond_r0;
+        const double fr = -2.0 * a.bond_k * dr / r;
+        const double share = owned ? 1.0 : 0.5;   // each bond is seen from both atoms
+        e += share * a.bond_k * dr * dr;
+        wv += share * fr * r * r;
+        fx += fr * dx; fy += fr * dy; fz += fr * dz;
+        if constexpr (DIAG) {
+            wd[0] += share * fr * dx * dx; wd[1] += share * fr * dy * dy; wd[2] += share * fr * dz * dz;
+        }
+        if (owned) {
+            a.f[jb] = -(fr * dx);
+            a.f[jb + P] = -(fr * dy);
+            a.f[jb + 2 * P] = -(fr * dz);
+        }
     }
 }
 
@@ -785,7 +835,8 @@ __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, d
 // forces are combined in sub-group order through shared memory; S > 1 only
 // when the system alone would leave the GPU with few waves to hide latency.
 // BOXDEV: the box lengths come from the control block (a barostat moves them)
-template <bool BOXDEV = false>
+// DIAG: the block also writes the diagonal of its cell virial (a.fdiag)
+template <bool BOXDEV = false, bool DIAG = false>
 __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, double *s_f)
 {
     const int P = a.P, S = a.S;
@@ -795,7 +846,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     const int la = t / G, g = t - la * G;   // atom slot, lane within the atom's group
     const int sg = g / P, k = g - sg * P;   // sub-group, bead
     const int i = tile * A + la;
-    const bool act = (la < A) && (i < a.N);
+    const bool act = (la < A) && (i < a.n_forced);
     const double L0 = BOXDEV ? a.ctl->box[0] : a.box[0];
     const double L1 = BOXDEV ? a.ctl->box[1] : a.box[1];
     const double L2 = BOXDEV ? a.ctl->box[2] : a.box[2];
@@ -983,6 +1034,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     }
 
     double e = 0.0, wv = 0.0, s12 = 0.0, s6 = 0.0;
+    double wd[3] = {0.0, 0.0, 0.0};   // DIAG: sum of fr r_a^2 over the thread's pairs
     int np = 0;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int P3 = 3 * P;
@@ -1029,8 +1081,8 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
             for (int u = 0; u < 4; ++u) {
                 double sx, sy, sz;
                 unpack_shift(en[u].y, sx, sy, sz);
-                lj_accumulate(xi - xj[u] + sx * L0, yi - yj[u] + sy * L1, zi - zj[u] + sz * L2,
-                              rc2, sig2, eps24, fx, fy, fz, s12, s6, np);
+                lj_accumulate<DIAG>(xi - xj[u] + sx * L0, yi - yj[u] + sy * L1, zi - zj[u] + sz * L2,
+                                    rc2, sig2, eps24, fx, fy, fz, s12, s6, np, wd);
             }
         }
         for (; q < qend; q += S) {
@@ -1038,31 +1090,16 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
             double sx, sy, sz;
             unpack_shift(en.y, sx, sy, sz);
             const int jb = en.x + k;
-            lj_accumulate(xi - X[jb] + sx * L0, yi - X[jb + P] + sy * L1, zi - X[jb + 2 * P] + sz * L2,
-                          rc2, sig2, eps24, fx, fy, fz, s12, s6, np);
+            lj_accumulate<DIAG>(xi - X[jb] + sx * L0, yi - X[jb + P] + sy * L1,
+                                zi - X[jb + 2 * P] + sz * L2, rc2, sig2, eps24, fx, fy, fz, s12, s6,
+                                np, wd);
         }
         __syncthreads();
     }
     lj_energy_virial(s12, s6, np, eps4, eps24, ush, e, wv);
-    if (act) {
-        if (sg == 0) {
-            for (int bb = 0; bb < kMaxBonds; ++bb) {
-                const int j = a.bond_j[i * kMaxBonds + bb];
-                if (j < 0) break;
-                const size_t jb = (size_t)j * P3 + k;
-                double dx = xi - X[jb], dy = yi - X[jb + P], dz = zi - X[jb + 2 * P];
-                dx -= L0 * rint(dx / L0);
-                dy -= L1 * rint(dy / L1);
-                dz -= L2 * rint(dz / L2);
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                const double dr = r - a.bond_r0;
-                const double fr = -2.0 * a.bond_k * dr / r;
-                e += 0.5 * a.bond_k * dr * dr;
-                wv += 0.5 * fr * r * r;  // each bond is seen from both atoms
-                fx += fr * dx; fy += fr * dy; fz += fr * dz;
-            }
-        }
-    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) wd[d] *= 0.5;   // half of each ordered pair, as the trace
+    if (act && sg == 0) bond_forces<DIAG>(a, i, k, xi, yi, zi, L0, L1, L2, fx, fy, fz, e, wv, wd);
     if (S > 1) {
         s_f[t * 3] = fx; s_f[t * 3 + 1] = fy; s_f[t * 3 + 2] = fz;
         __syncthreads();
@@ -1077,9 +1114,20 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
     }
     // block sums (fixed order): energy, then the cell virial after all partials
-    double e1[2] = {e, wv};
-    block_sum<2>(e1, red);
-    if (t == 0) reinterpret_cast<double2 *>(a.fpartials)[tile] = make_double2(e1[0], e1[1]);
+    if constexpr (DIAG) {
+        double e5[5] = {e, wv, wd[0], wd[1], wd[2]};
+        block_sum<5>(e5, red);
+        if (t == 0) {
+            reinterpret_cast<double2 *>(a.fpartials)[tile] = make_double2(e5[0], e5[1]);
+            a.fdiag[(size_t)tile * 3] = e5[2];
+            a.fdiag[(size_t)tile * 3 + 1] = e5[3];
+            a.fdiag[(size_t)tile * 3 + 2] = e5[4];
+        }
+    } else {
+        double e1[2] = {e, wv};
+        block_sum<2>(e1, red);
+        if (t == 0) reinterpret_cast<double2 *>(a.fpartials)[tile] = make_double2(e1[0], e1[1]);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1104,7 +1152,7 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
     const int la = t / P, k = t - la * P;
     const int i0 = b * A;
     const int i = i0 + la;
-    const bool act = (la < A) && (i < a.N);
+    const bool act = (la < A) && (i < a.n_forced);
     const int na = min(A, a.n_active - i0);             // LJ-active atoms of the block (> 0)
     const bool lj = act && la < na;
     const double L0 = a.box[0], L1 = a.box[1], L2 = a.box[2];
@@ -1275,21 +1323,7 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
     }
     lj_energy_virial(s12, s6, np, eps4, eps24, ush, e, wv);
     if (act) {
-        for (int bb = 0; bb < kMaxBonds; ++bb) {
-            const int j = a.bond_j[i * kMaxBonds + bb];
-            if (j < 0) break;
-            const size_t jb = (size_t)j * P3 + k;
-            double dx = xi - X[jb], dy = yi - X[jb + P], dz = zi - X[jb + 2 * P];
-            dx -= L0 * rint(dx / L0);
-            dy -= L1 * rint(dy / L1);
-            dz -= L2 * rint(dz / L2);
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            const double dr = r - a.bond_r0;
-            const double fr = -2.0 * a.bond_k * dr / r;
-            e += 0.5 * a.bond_k * dr * dr;
-            wv += 0.5 * fr * r * r;  // each bond is seen from both atoms
-            fx += fr * dx; fy += fr * dy; fz += fr * dz;
-        }
+        bond_forces(a, i, k, xi, yi, zi, L0, L1, L2, fx, fy, fz, e, wv);
         a.f[ib] = fx; a.f[ib + P] = fy; a.f[ib + 2 * P] = fz;
     }
     double e1[2] = {e, wv};
@@ -1433,7 +1467,10 @@ __global__ __launch_bounds__(kBlock) void k_pair_npt(PairArgs a)
     __shared__ double s_f[kBlock * 3];
     const int b = blockIdx.x, nA = a.n_active_tiles;
     const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
-    pair_tile<true>(a, tile, s_cnt, red, s_f);
+    if (a.fdiag)
+        pair_tile<true, true>(a, tile, s_cnt, red, s_f);
+    else
+        pair_tile<true, false>(a, tile, s_cnt, red, s_f);
 }
 
 void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s)

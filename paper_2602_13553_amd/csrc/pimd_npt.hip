@@ -1,4 +1,7 @@
-// The isotropic BZP barostat (App. E): NpT, or NpH with both thermostats off.
+// The BZP barostat (App. E): NpT, or NpH with both thermostats off;
+// isotropic (one v_W) or anisotropic (one v_W per dimension, each driven by
+// the diagonal element of the centroid-virial stress tensor in its
+// dimension and scaling the centroids and the box in that dimension).
 // An OBABO step at a synchronized state is
 //   O(dt/2) on the beads and on v_W; B(dt/2) on v_W and the beads together;
 //   A(dt): the centroid mode under the barostat, the other modes by the free
@@ -48,12 +51,38 @@ __device__ double baro_kick(const NptArgs &a, double vw, double h, double k0x2, 
            h * h / W * fv + h * h * h / (3.0 * W) * f2;
 }
 
+// One dimension's v_W after a kick of length h (anisotropic): the sums are
+// that dimension's; k0x2 - vir + w = P V P_CV^aa.
+__device__ double baro_kick_dim(const NptArgs &a, double vw, double h, double k0x2, double vir,
+                                double w, double V, double fv, double f2)
+{
+    const double W = a.wmass;
+    return vw + h / W * (k0x2 - vir + w - (double)a.f.P * V * a.p_ext + a.kTP) + h * h / W * fv +
+           h * h * h / (3.0 * W) * f2;
+}
+
 // v_W's O step q of step s
 __device__ double baro_o(const NptArgs &a, double vw, unsigned long long s, unsigned long long q)
 {
     double z[3];
     gauss3(a.f.seed, ~0ULL, 0ULL, s, z, q);
     return a.bc1 * vw + a.bc2 * a.bsig * z[0];
+}
+
+// The three v_Wa's O step q of step s (anisotropic): the three Gaussians of
+// the barostat's counter, one per dimension
+__device__ void baro_o3(const NptArgs &a, double vw[3], unsigned long long s, unsigned long long q)
+{
+    double z[3];
+    gauss3(a.f.seed, ~0ULL, 0ULL, s, z, q);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vw[d] = a.bc1 * vw[d] + a.bc2 * a.bsig * z[d];
+}
+
+// v_W of dimension d: the isotropic one, or that dimension's
+__device__ __forceinline__ double vw_of(const NptArgs &a, const Ctl *c, int d)
+{
+    return a.aniso ? c->vwa[d] : c->vw;
 }
 
 // Pass A.  Thread = (atom, mode); a block holds kBlock/P whole atoms.
@@ -66,13 +95,14 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
     const int P = a.P, N = a.N, A = kBlock / P;
     __shared__ double sX[3 * kBlock];
     __shared__ double sF[3 * kBlock];
-    __shared__ double red[64];
+    __shared__ double red[NP_COUNT_ANISO * (kBlock / 64)];
     const int t = threadIdx.x, la = t / P, k = t - la * P;
     const int i = blockIdx.x * A + la;
     const bool act = la < A && i < N;
     const unsigned long long step = a.ctl->step;
     const bool closing = mode != NPT_EST && !a.ctl->synced;
     const bool opening = mode == NPT_STEP;
+    const bool an = na.aniso != 0;
     const size_t vb = (size_t)i * 3 * P + k;
     if (act) {
 #pragma unroll
@@ -82,9 +112,9 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
         }
     }
     __syncthreads();
-    double acc[NP_COUNT];
+    double acc[NP_COUNT_ANISO];
 #pragma unroll
-    for (int q = 0; q < NP_COUNT; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NP_COUNT_ANISO; ++q) acc[q] = 0.0;
     if (act) {
         const double *xr = sX + la * 3 * P, *fr = sF + la * 3 * P;
         const double *Mk = a.M + (size_t)k * P;
@@ -118,6 +148,10 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
                 for (int d = 0; d < 3; ++d) {
                     acc[NP_K0A] += hm * vt[d] * vt[d];
                     acc[NP_FVA] += ft[d] * vt[d];
+                    if (an) {
+                        acc[NP_K0A3 + d] += hm * vt[d] * vt[d];
+                        acc[NP_FVA3 + d] += ft[d] * vt[d];
+                    }
                 }
             }
 #pragma unroll
@@ -129,9 +163,11 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
             acc[NP_EKIN] += hm * vt[d] * vt[d];
             acc[NP_ESPRING] += hm * mk[MD_SPRING] * yt[d] * yt[d];
             acc[NP_VIR] += mk[MD_NONCENTROID] * yt[d] * ft[d];
+            if (an) acc[NP_VIR3 + d] += mk[MD_NONCENTROID] * yt[d] * ft[d];
             if (k == 0) {
                 acc[NP_K0] += hm * vt[d] * vt[d];
                 acc[NP_F2] += ft[d] * ft[d] * im;
+                if (an) acc[NP_F23 + d] += ft[d] * ft[d] * im;
             }
         }
         if (opening) {
@@ -141,6 +177,10 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
                 for (int d = 0; d < 3; ++d) {
                     acc[NP_K0B] += hm * vt[d] * vt[d];
                     acc[NP_FVB] += ft[d] * vt[d];
+                    if (an) {
+                        acc[NP_K0B3 + d] += hm * vt[d] * vt[d];
+                        acc[NP_FVB3 + d] += ft[d] * vt[d];
+                    }
                 }
             }
         }
@@ -150,11 +190,20 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
             if (!isfinite(vt[d])) acc[NP_BAD] = 1.0;
         }
     }
-    block_sum<NP_COUNT>(acc, red);
-    if (t == 0) {
-        double *pp = na.part + (size_t)blockIdx.x * NP_COUNT;
+    if (an) {
+        block_sum<NP_COUNT_ANISO>(acc, red);
+    } else {
+        double acc0[NP_COUNT];
 #pragma unroll
-        for (int q = 0; q < NP_COUNT; ++q) pp[q] = acc[q];
+        for (int q = 0; q < NP_COUNT; ++q) acc0[q] = acc[q];
+        block_sum<NP_COUNT>(acc0, red);
+#pragma unroll
+        for (int q = 0; q < NP_COUNT; ++q) acc[q] = acc0[q];
+    }
+    if (t == 0) {
+        double *pp = na.part + (size_t)blockIdx.x * NP_COUNT_ANISO;
+#pragma unroll
+        for (int q = 0; q < NP_COUNT_ANISO; ++q) pp[q] = acc[q];
     }
 }
 
@@ -164,37 +213,78 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_a(NptArgs na, int mode, int 
 {
     const FusedArgs &a = na.f;
     Ctl *c = a.ctl;
-    __shared__ double red[64];
+    // pass A's sums, then the force pass's energy and cell virial, then
+    // (anisotropic) the diagonal of the cell virial
+    constexpr int NT0 = NP_COUNT + 2;
+    constexpr int TE = NP_COUNT_ANISO, TW = TE + 1, TD = TE + 2, NT = TE + 5;
+    __shared__ double red[NT * (kBlock / 64)];
     const int t = threadIdx.x;
-    constexpr int NT = NP_COUNT + 2;     // + pair energy, cell virial
+    const bool an = na.aniso != 0;
     double tot[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) tot[q] = 0.0;
     for (int b = t; b < nblocks; b += kBlock) {
 #pragma unroll
-        for (int q = 0; q < NP_COUNT; ++q) tot[q] += na.part[(size_t)b * NP_COUNT + q];
+        for (int q = 0; q < NP_COUNT_ANISO; ++q)
+            if (an || q < NP_COUNT) tot[q] += na.part[(size_t)b * NP_COUNT_ANISO + q];
     }
     const double2 *fp = reinterpret_cast<const double2 *>(a.fpartials);
     for (int b = t; b < a.n_fpartials; b += kBlock) {
         const double2 e = fp[b];
-        tot[NP_COUNT] += e.x;
-        tot[NP_COUNT + 1] += e.y;
+        tot[TE] += e.x;
+        tot[TW] += e.y;
+        if (an) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) tot[TD + d] += na.fdiag[(size_t)b * 3 + d];
+        }
     }
-    block_sum<NT>(tot, red);
+    if (an) {
+        block_sum<NT>(tot, red);
+    } else {
+        // the isotropic barostat's sums alone, in the order they always had
+        double t0[NT0];
+#pragma unroll
+        for (int q = 0; q < NP_COUNT; ++q) t0[q] = tot[q];
+        t0[NP_COUNT] = tot[TE];
+        t0[NP_COUNT + 1] = tot[TW];
+        block_sum<NT0>(t0, red);
+#pragma unroll
+        for (int q = 0; q < NP_COUNT; ++q) tot[q] = t0[q];
+        tot[TE] = t0[NP_COUNT];
+        tot[TW] = t0[NP_COUNT + 1];
+    }
     if (t != 0) return;
     const unsigned long long step = c->step;
     const bool closing = mode != NPT_EST && !c->synced;
     const bool est_now = closing || mode == NPT_EST;
     const double h = a.hdt, P = (double)a.P;
     const double V = c->box[0] * c->box[1] * c->box[2];
-    const double vir = tot[NP_VIR], w = tot[NP_COUNT + 1], f2 = tot[NP_F2];
+    const double vir = tot[NP_VIR], w = tot[TW], f2 = tot[NP_F2];
     double vw = c->vw;
+    double vwa[3] = {c->vwa[0], c->vwa[1], c->vwa[2]};
+    // the kicks: one v_W, or each dimension's with that dimension's sums
+    auto kick = [&](int k0, int fv, int k03, int fv3) {
+        if (an) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                vwa[d] = baro_kick_dim(na, vwa[d], h, 2.0 * tot[k03 + d], tot[NP_VIR3 + d], tot[TD + d], V,
+                                       tot[fv3 + d], tot[NP_F23 + d]);
+        } else {
+            vw = baro_kick(na, vw, h, 2.0 * tot[k0], vir, w, V, tot[fv], f2);
+        }
+    };
+    auto o_step = [&](unsigned long long s_, unsigned long long q_) {
+        if (an)
+            baro_o3(na, vwa, s_, q_);
+        else
+            vw = baro_o(na, vw, s_, q_);
+    };
     if (closing) {
-        vw = baro_kick(na, vw, h, 2.0 * tot[NP_K0A], vir, w, V, tot[NP_FVA], f2);
-        if (a.obabo && a.nvt) vw = baro_o(na, vw, step - 1, 1);
+        kick(NP_K0A, NP_FVA, NP_K0A3, NP_FVA3);
+        if (a.obabo && a.nvt) o_step(step - 1, 1);
     }
     if (est_now) {
-        const double ekin = tot[NP_EKIN], esp = tot[NP_ESPRING], epot = tot[NP_COUNT];
+        const double ekin = tot[NP_EKIN], esp = tot[NP_ESPRING], epot = tot[TE];
         const double i3v = 1.0 / (3.0 * V), iP = 1.0 / P;
         double v[kNumEst];
         v[0] = ekin;
@@ -207,8 +297,11 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_a(NptArgs na, int mode, int 
         v[7] = (2.0 * tot[NP_K0] - vir + w) * iP * i3v;
         v[8] = (2.0 * a.kT15PN - (2.0 * esp - w) * iP) * i3v;
         v[9] = (2.0 * ekin + w) * i3v;
-        // K_W + U_W + J_W (App. A), with J_W = -P kB T ln V
-        const double eb = 0.5 * na.wmass * vw * vw + P * na.p_ext * V - na.kTP * log(V);
+        // K_W + U_W + J_W (App. A), with J_W = -P kB T ln V; anisotropic:
+        // the three barostat velocities' kinetic energies
+        const double kw = an ? 0.5 * na.wmass * (vwa[0] * vwa[0] + vwa[1] * vwa[1] + vwa[2] * vwa[2])
+                             : 0.5 * na.wmass * vw * vw;
+        const double eb = kw + P * na.p_ext * V - na.kTP * log(V);
         c->volume = V;
         c->ebaro = eb;
         c->enthalpy = v[3] + eb;
@@ -224,10 +317,12 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_a(NptArgs na, int mode, int 
     }
     if (closing) c->synced = 1;
     if (mode == NPT_STEP) {
-        if (a.obabo && a.nvt) vw = baro_o(na, vw, step, 0);
-        vw = baro_kick(na, vw, h, 2.0 * tot[NP_K0B], vir, w, V, tot[NP_FVB], f2);
+        if (a.obabo && a.nvt) o_step(step, 0);
+        kick(NP_K0B, NP_FVB, NP_K0B3, NP_FVB3);
     }
     c->vw = vw;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c->vwa[d] = vwa[d];
     if (tot[NP_BAD] != 0.0) c->nonfinite = 1;
     c->ran = 1;
 }
@@ -243,11 +338,22 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
     const int t = threadIdx.x, la = t / P, k = t - la * P;
     const int i = blockIdx.x * A + la;
     const bool act = la < A && i < N;
-    const double vw = a.ctl->vw;
     const unsigned long long step = a.ctl->step;
-    // BAOAB: v_W for the second A(dt/2), after its O(dt) (noise alone, so
-    // every thread forms it; the finalize forms the same value)
-    const double vw2 = (!a.obabo && a.nvt) ? baro_o(na, vw, step, 0) : vw;
+    // v_W per dimension (the isotropic one three times); BAOAB: v_W for the
+    // second A(dt/2), after its O(dt) (noise alone, so every thread forms it;
+    // the finalize forms the same value)
+    double vw[3], vw2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vw[d] = vw2[d] = vw_of(na, a.ctl, d);
+    if (!a.obabo && a.nvt) {
+        if (na.aniso) {
+            baro_o3(na, vw2, step, 0);
+        } else {
+            const double v2 = baro_o(na, vw[0], step, 0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) vw2[d] = v2;
+        }
+    }
     const size_t vb = (size_t)i * 3 * P + k;
     const double sqrtP = sqrt((double)P);
     if (act) {
@@ -277,12 +383,12 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
         // A over a time t_: the centroid under the barostat (velocity vw_),
         // in absolute coordinates x~0 = y~0 + sqrt(P) x_0; the other modes by
         // the free ring-polymer flow, A(dt/2) n_ times
-        auto a_flow = [&](double t_, double vw_, int n_) {
+        auto a_flow = [&](double t_, const double *vw_, int n_) {
             if (k == 0) {
-                const double u = t_ * vw_;
-                const double e = exp(u), ei = exp(-u), s = t_ * sinhc(u);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
+                    const double u = t_ * vw_[d];
+                    const double e = exp(u), ei = exp(-u), s = t_ * sinhc(u);
                     const double X = e * (yt[d] + sqrtP * x0[d]) + s * vt[d];
                     vt[d] *= ei;
                     yt[d] = X - sqrtP * x0[d];
@@ -343,12 +449,15 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
         if (active != 0.0) m3[1] = e2;
         if (k == 0) {
             // displacement from the last build's centroid carried along by the
-            // box scaling since that build
-            const double s = a.obabo ? exp(na.dt * vw) : exp(a.hdt * vw) * exp(a.hdt * vw2);
-            const double g = a.ctl->box[0] * s / a.ctl->box_build[0];
+            // box scaling (per dimension) since that build
+            double sd[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                sd[d] = a.obabo ? exp(na.dt * vw[d]) : exp(a.hdt * vw[d]) * exp(a.hdt * vw2[d]);
             double d2 = 0.0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
+                const double g = a.ctl->box[d] * sd[d] / a.ctl->box_build[d];
                 a.cent[i * 3 + d] = c[d];
                 const double dd = c[d] - g * a.cref[i * 3 + d];
                 d2 += dd * dd;
@@ -359,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
                 double bn[3], icw[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    bn[d] = a.ctl->box[d] * s;
+                    bn[d] = a.ctl->box[d] * sd[d];
                     icw[d] = (double)a.nc[d] / bn[d];
                 }
                 (void)cell_of_in(a, i, c, bn, icw);
@@ -396,7 +505,20 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
     }
     block_maxv<3>(m3, red);
     if (t == 0) {
-        if (a.obabo) {
+        if (na.aniso) {
+            double v1[3] = {c->vwa[0], c->vwa[1], c->vwa[2]}, v2[3] = {v1[0], v1[1], v1[2]};
+            if (a.obabo) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) c->box[d] *= exp(na.dt * v1[d]);
+            } else {
+                if (a.nvt) baro_o3(na, v2, c->step, 0);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    c->box[d] = c->box[d] * exp(a.hdt * v1[d]) * exp(a.hdt * v2[d]);
+                    c->vwa[d] = v2[d];
+                }
+            }
+        } else if (a.obabo) {
             const double s = exp(na.dt * c->vw);
 #pragma unroll
             for (int d = 0; d < 3; ++d) c->box[d] *= s;
@@ -413,7 +535,13 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
         c->synced = 0;
         if (c->budget > 0) c->budget = c->budget - 1;
         const double dmax = sqrt(m3[0]), emax = sqrt(m3[1]);
-        const double g = c->box[0] / c->box_build[0];
+        // the smallest scaling of any dimension since the build bounds a
+        // pair's distance then by its distance now over g
+        double g = c->box[0] / c->box_build[0];
+        if (na.aniso) {
+#pragma unroll
+            for (int d = 1; d < 3; ++d) g = fmin(g, c->box[d] / c->box_build[d]);
+        }
         const bool rebuild = a.rc + 2.0 * (emax + dmax) > g * c->rlist;
         const double rl = a.rc + a.skin + 2.0 * emax;
         if (rebuild) {
@@ -445,22 +573,27 @@ __global__ __launch_bounds__(kBlock) void k_npt_fin_b(NptArgs na, int nblocks)
     }
 }
 
-__global__ void k_npt_init(Ctl *c, double b0, double b1, double b2, double vw)
+__global__ void k_npt_init(Ctl *c, double b0, double b1, double b2, double vw, double vx,
+                           double vy, double vz)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->box[0] = c->box_build[0] = b0;
         c->box[1] = c->box_build[1] = b1;
         c->box[2] = c->box_build[2] = b2;
         c->vw = vw;
+        c->vwa[0] = vx;
+        c->vwa[1] = vy;
+        c->vwa[2] = vz;
         c->volume = b0 * b1 * b2;
         c->ebaro = 0.0;
         c->enthalpy = 0.0;
     }
 }
 
-void launch_npt_init(Ctl *ctl, const double box[3], double vw, hipStream_t s)
+void launch_npt_init(Ctl *ctl, const double box[3], const double vw[3], hipStream_t s)
 {
-    hipLaunchKernelGGL(k_npt_init, dim3(1), dim3(64), 0, s, ctl, box[0], box[1], box[2], vw);
+    hipLaunchKernelGGL(k_npt_init, dim3(1), dim3(64), 0, s, ctl, box[0], box[1], box[2], vw[0], vw[0],
+                       vw[1], vw[2]);
 }
 
 void launch_npt_a(const NptArgs &a, int mode, hipStream_t s)

@@ -80,6 +80,7 @@ class SystemSpec:
     bonds: np.ndarray | None = None       # [n_bonds][2]
     nsteps: int = 0                 # length of the workload's run
     bosonic: int = 0                # 1: identical bosons with exchange (Cartesian beads)
+    baro_aniso: int = 0             # NPT, NPH: 1 = one barostat velocity per dimension
     extra: dict = field(default_factory=dict)
 
     @property

@@ -66,7 +66,7 @@ class pimd_params(C.Structure):
         ("skin", C.c_double), ("bond_k", C.c_double), ("bond_r0", C.c_double),
         ("nbr_capacity", C.c_int32), ("flags", C.c_int32), ("integrator", C.c_int32),
         ("fixcom", C.c_int32), ("p_ext", C.c_double), ("tau_p", C.c_double),
-        ("bosonic", C.c_int32), ("pad0", C.c_int32),
+        ("bosonic", C.c_int32), ("baro_aniso", C.c_int32),
     ]
 
 
@@ -79,7 +79,8 @@ class pimd_estimators(C.Structure):
     _fields_ = [("step", C.c_uint64), ("value", C.c_double * NEST), ("count", C.c_uint64),
                 ("sum", C.c_double * NEST), ("sumsq", C.c_double * NEST), ("nonfinite", C.c_int32),
                 ("overflow", C.c_int32), ("n_rebuilds", C.c_uint64), ("rlist", C.c_double),
-                ("volume", C.c_double), ("vw", C.c_double), ("enthalpy", C.c_double)]
+                ("volume", C.c_double), ("vw", C.c_double), ("enthalpy", C.c_double),
+                ("vwa", C.c_double * 3)]
 
 
 class pimd_profile(C.Structure):
@@ -120,7 +121,7 @@ def load() -> C.CDLL:
                                           P(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p]
         lib.pimd_boson_spring_noalloc.argtypes = lib.pimd_boson_spring.argtypes
-        lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), C.c_double]
+        lib.pimd_set_barostat.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
         lib.pimd_reset_averages.argtypes = [C.c_void_p]
         lib.pimd_get_positions.argtypes = [C.c_void_p, C.c_void_p]
         lib.pimd_set_forces.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
@@ -167,6 +168,7 @@ def _estimators_dict(e) -> dict:
     out["nonfinite"], out["overflow"] = e.nonfinite, e.overflow
     out["n_rebuilds"], out["rlist"] = int(e.n_rebuilds), float(e.rlist)
     out["volume"], out["vw"], out["enthalpy"] = float(e.volume), float(e.vw), float(e.enthalpy)
+    out["vwa"] = tuple(float(v) for v in e.vwa)
     return out
 
 
@@ -205,6 +207,7 @@ def params_from_spec(spec, flags: int = 0) -> pimd_params:
     p.p_ext = float(getattr(spec, "p_ext", 0.0))
     p.tau_p = float(getattr(spec, "tau_p", 1.0))
     p.bosonic = int(getattr(spec, "bosonic", 0))
+    p.baro_aniso = int(getattr(spec, "baro_aniso", 0))
     return p
 
 
@@ -311,16 +314,23 @@ class Context:
         return x, p, int(s.value)
 
     def barostat(self):
-        """NPT, NPH: the current box lengths and barostat velocity v_W."""
+        """NPT, NPH: the current box lengths and barostat velocity: v_W (a
+        float), or with the anisotropic barostat the three v_Wa (a tuple)."""
         box = np.empty(3)
-        vw = C.c_double()
-        self._check(self._lib.pimd_get_barostat(self._h, _dp(box), C.byref(vw)), self._h)
-        return tuple(box.tolist()), float(vw.value)
+        vw = np.zeros(3)
+        self._check(self._lib.pimd_get_barostat(self._h, _dp(box), _dp(vw)), self._h)
+        if self.params.baro_aniso:
+            return tuple(box.tolist()), tuple(vw.tolist())
+        return tuple(box.tolist()), float(vw[0])
 
-    def set_barostat(self, box, vw: float) -> None:
-        """NPT, NPH: the box and v_W that the next set_state starts from."""
+    def set_barostat(self, box, vw) -> None:
+        """NPT, NPH: the box and v_W (a float, or three with the anisotropic
+        barostat) that the next set_state starts from."""
         b = np.ascontiguousarray(box, dtype=np.float64)
-        self._check(self._lib.pimd_set_barostat(self._h, _dp(b), float(vw)), self._h)
+        v = np.ascontiguousarray(np.atleast_1d(np.asarray(vw, dtype=np.float64)))
+        if v.size != (3 if self.params.baro_aniso else 1):
+            raise ValueError("vw: one value, or three with the anisotropic barostat")
+        self._check(self._lib.pimd_set_barostat(self._h, _dp(b), _dp(v)), self._h)
 
     def profile_begin(self) -> None:
         self._check(self._lib.pimd_profile_begin(self._h), self._h)

@@ -142,7 +142,7 @@ def test_workload_generators():
 def test_barostat_validation_without_gpu():
     """The barostat needs a pair potential, no fixcom, tau_p > 0 and a finite
     p_ext, takes either splitting, and neither the matrix-core nor the
-    cluster flags."""
+    cluster flags; baro_aniso is 0 or 1, and 1 only under a barostat."""
     lib = pimd.load()
     spec = inputs.lj_liquid(n_atoms=32, n_beads=4)
     mass = np.ascontiguousarray(spec.mass)
@@ -163,6 +163,15 @@ def test_barostat_validation_without_gpu():
     assert rc(p_ext=float("nan")) == -1
     assert rc(flags=pimd.PIMD_FLAG_MFMA_TRANSFORMS) == -6
     assert rc(ensemble=4) == -1
+    # the anisotropic barostat: 0 or 1, and only with a barostat; its
+    # workspace adds the force pass's per-block diagonal virials
+    assert rc() == 0
+    iso = n.value
+    assert rc(baro_aniso=1) == 0 and n.value > iso
+    assert rc(baro_aniso=1, ensemble=pimd.PIMD_NPH, integrator=pimd.PIMD_BAOAB) == 0
+    assert rc(baro_aniso=2) == -1
+    assert rc(baro_aniso=1, ensemble=pimd.PIMD_NVT) == -1
+    assert rc(baro_aniso=1, ensemble=pimd.PIMD_NVE) == -1
     h = pimd.params_from_spec(inputs.harmonic_tiny())
     h.ensemble, h.integrator, h.tau_p = pimd.PIMD_NPT, pimd.PIMD_OBABO, 0.5
     hm = np.ascontiguousarray(inputs.harmonic_tiny().mass)

@@ -49,18 +49,24 @@ def run_both(spec, chunks):
 
 def check(g, st, tol=TOL, est_tol=1e-10):
     gx, gp, gs, gest, gbox, gvw = g
+    an = bool(st.sys.aniso)
     oest = st.estimators()
     ob = st.baro_energies()
     assert gs == int(st.step_count[0])
     ex, ep = rel_err(gx, st.x), rel_err(gp, st.p)
     W = oracle.lib().orc_baro_mass(oracle.C.byref(st.sys.cstruct()))
     vscale = math.sqrt(st.sys.n_beads * st.sys.kB * st.sys.temp / W)
-    _say("  x rel %.3e  p rel %.3e  box %.12f / %.12f  vw %.6e / %.6e" %
-         (ex, ep, gbox[0], st.box[0], gvw, st.baro.vw))
+    ovw = np.array(list(st.baro.vwa) if an else [st.baro.vw])
+    gv = np.atleast_1d(np.asarray(gvw, dtype=np.float64))
+    _say("  x rel %.3e  p rel %.3e  box %s / %s  vw %s / %s" %
+         (ex, ep, np.array(gbox), np.array(st.box), gv, ovw))
     assert ex <= tol and ep <= tol, (ex, ep)
-    assert abs(gbox[0] / st.box[0] - 1) <= tol
-    assert gbox[0] == gbox[1] == gbox[2]
-    assert abs(gvw - st.baro.vw) <= est_tol * max(abs(st.baro.vw), vscale)
+    for d in range(3):
+        assert abs(gbox[d] / st.box[d] - 1) <= tol
+    if not an:
+        assert gbox[0] == gbox[1] == gbox[2]
+    assert gv.shape == ovw.shape
+    assert np.abs(gv - ovw).max() <= est_tol * max(np.abs(ovw).max(), vscale)
     scale = max(abs(oest["ekin"]), abs(oest["espring"]), abs(oest["epot"]))
     for name in ("ekin", "espring", "epot", "etot", "kprim", "kcv"):
         assert abs(gest[name] - oest[name]) <= est_tol * scale, (name, gest[name], oest[name])
@@ -70,7 +76,12 @@ def check(g, st, tol=TOL, est_tol=1e-10):
     assert abs(gest["volume"] - ob["volume"]) <= tol * ob["volume"]
     hscale = scale + abs(ob["uw"]) + abs(ob["jw"]) + abs(ob["kw"])
     assert abs(gest["enthalpy"] - ob["enthalpy"]) <= est_tol * hscale
-    assert abs(gest["vw"] - st.baro.vw) <= est_tol * max(abs(st.baro.vw), vscale)
+    if an:
+        assert np.abs(np.array(gest["vwa"]) - ovw).max() <= est_tol * max(np.abs(ovw).max(), vscale)
+        assert abs(gest["vw"] - ovw.mean()) <= est_tol * max(np.abs(ovw).max(), vscale)
+    else:
+        assert abs(gest["vw"] - st.baro.vw) <= est_tol * max(abs(st.baro.vw), vscale)
+        assert gest["vwa"] == (0.0, 0.0, 0.0)
 
 
 @pytest.mark.parametrize("ensemble", [2, 3])
@@ -238,3 +249,106 @@ def test_barostat_full_size_nph_conserves_the_enthalpy():
     assert vr > 1.2
     assert 3.0 < h1 / h2 < 5.0
     assert h2 < 5.0 * e2
+
+
+# ------------------------------------------- anisotropic barostat (App. E)
+
+def _stretch(spec, f):
+    """The same lattice in a rectangular box: coordinates and box lengths
+    scaled by f per dimension."""
+    spec.x0 = np.ascontiguousarray(spec.x0 * np.asarray(f)[None, None, :])
+    spec.box = tuple(b * s for b, s in zip(spec.box, f))
+    return spec
+
+
+def _aniso(spec, ensemble, p_ext, tau_p, integrator=1):
+    spec = _barostat(spec, ensemble, p_ext, tau_p, integrator)
+    spec.baro_aniso = 1
+    return spec
+
+
+@pytest.mark.parametrize("ensemble", [2, 3])
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_aniso_barostat_lj_matches_oracle(ensemble, integrator):
+    """One v_W per dimension in a rectangular box (the stress differs per
+    dimension, so the three lengths part): positions, momenta, the three
+    lengths and velocities, the estimators and the enthalpy."""
+    spec = _stretch(inputs.lj_liquid(n_atoms=256, n_beads=8, seed=60 + integrator), (1.0, 0.92, 1.12))
+    spec = _aniso(spec, ensemble, 2.0, 0.2, integrator)
+    g, st = run_both(spec, [1, 6, 3])
+    check(g, st)
+    assert len(set(g[4])) == 3
+
+
+def test_aniso_barostat_water_matches_oracle():
+    """Water-shaped N = 384, P = 8, BAOAB: the bonds' share of each
+    dimension's virial (an O atom's lanes also write its H atoms' forces)."""
+    spec = _aniso(inputs.water(n_atoms=384, n_beads=8, seed=62), 2, 0.5, 200.0, integrator=0)
+    g, st = run_both(spec, [4, 6])
+    check(g, st)
+
+
+@pytest.mark.parametrize("N,P", [(97, 3), (64, 1)])
+def test_aniso_barostat_ragged_and_odd(N, P):
+    spec = _stretch(inputs.lj_liquid(n_atoms=N, n_beads=P, seed=63 + P), (1.1, 1.0, 0.95))
+    spec = _aniso(spec, 2, 1.0, 0.3)
+    g, st = run_both(spec, [3, 7])
+    check(g, st)
+
+
+def test_aniso_barostat_cell_lists_and_rebuilds():
+    """N = 2916 in a rectangular box under a fast barostat: cells binned in a
+    box whose three lengths scale apart, rebuilds against the smallest
+    scaling; every pair inside rc must still be found (the oracle sums all
+    pairs)."""
+    from paper_2602_13553_amd import pimd
+    spec = _stretch(inputs.lj_liquid(n_atoms=2916, n_beads=4, seed=64), (1.0, 1.08, 0.94))
+    spec = _aniso(spec, 2, 1.0, 0.1)
+    ctx = pimd.Context.from_spec(spec)
+    assert ctx.launch_info()["cells"] > 0
+    ctx.close()
+    g, st = run_both(spec, [16, 24])
+    _say("  rebuilds %d" % g[3]["n_rebuilds"])
+    assert g[3]["n_rebuilds"] >= 2
+    check(g, st, tol=1e-10, est_tol=1e-9)
+
+
+def test_aniso_barostat_checkpoint_restart():
+    """20 steps in one go equal 10 steps, a checkpoint (state, three lengths,
+    three v_Wa) and 10 more in a new context; the anisotropic barostat takes
+    any box of positive lengths and exactly three velocities."""
+    from paper_2602_13553_amd import pimd
+    spec = _stretch(inputs.lj_liquid(n_atoms=256, n_beads=8, seed=65), (1.0, 1.0, 1.1))
+    spec = _aniso(spec, 2, 1.0, 0.2, integrator=0)
+    a = pimd.Context.from_spec(spec)
+    a.set_state(spec.x0, spec.v0, 0)
+    a.step(20)
+    xa, pa, sa = a.get_state()
+    boxa, vwa = a.barostat()
+    a.close()
+    b = pimd.Context.from_spec(spec)
+    b.set_state(spec.x0, spec.v0, 0)
+    b.step(10)
+    x, p, s = b.get_state()
+    box, vw = b.barostat()
+    b.close()
+    assert isinstance(vw, tuple) and len(vw) == 3
+    c = pimd.Context.from_spec(spec)
+    with pytest.raises(ValueError):
+        c.set_barostat(box, 0.0)
+    with pytest.raises(pimd.PimdError):
+        c.set_barostat(box, (0.0, float("nan"), 0.0))
+    with pytest.raises(pimd.PimdError):
+        c.set_barostat((box[0], -1.0, box[2]), vw)
+    c.set_barostat(box, vw)
+    c.set_state(x, p / spec.mass[None, :, None], s)
+    c.step(10)
+    xc, pc, sc = c.get_state()
+    boxc, vwc = c.barostat()
+    c.close()
+    _say("  restart x rel %.3e p rel %.3e box %s / %s" % (rel_err(xc, xa), rel_err(pc, pa), boxc, boxa))
+    assert sc == sa == 20
+    assert rel_err(xc, xa) <= TOL and rel_err(pc, pa) <= 1e-11
+    for d in range(3):
+        assert abs(boxc[d] / boxa[d] - 1) <= TOL
+        assert abs(vwc[d] - vwa[d]) <= 1e-10 * max(abs(vwa[d]), 1e-3)
