@@ -112,15 +112,28 @@ __device__ __forceinline__ void dma_tile(const double *src, double *dst, int nro
 {
     using L = Lds<P>;
     const int ln = opaque(lane);
+    if (nrows == 16 * L::T) {
+        // a whole tile (uniform): no per-lane test
 #pragma unroll
-    for (int j = 0; j < L::NDMA; ++j) {
-        const int base = (w * L::NDMA + j) * 64;
-        const int q = base + ln;
-        const int a = q / L::UNITS, up = q - a * L::UNITS;
-        const int u = up ^ (a & L::SWZ);
-        if (a < nrows)
+        for (int j = 0; j < L::NDMA; ++j) {
+            const int base = (w * L::NDMA + j) * 64;
+            const int q = base + ln;
+            const int a = q / L::UNITS, up = q - a * L::UNITS;
+            const int u = up ^ (a & L::SWZ);
             __builtin_amdgcn_global_load_lds((const void *)(src + 2 * (a * L::UNITS + u)),
                                              (lds_void *)(dst + 2 * base), 16, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < L::NDMA; ++j) {
+            const int base = (w * L::NDMA + j) * 64;
+            const int q = base + ln;
+            const int a = q / L::UNITS, up = q - a * L::UNITS;
+            const int u = up ^ (a & L::SWZ);
+            if (a < nrows)
+                __builtin_amdgcn_global_load_lds((const void *)(src + 2 * (a * L::UNITS + u)),
+                                                 (lds_void *)(dst + 2 * base), 16, 0, 0);
+        }
     }
 }
 
@@ -159,8 +172,26 @@ __device__ __forceinline__ int m_index(int k, int q)
 {
     constexpr int LG = (P == 16) ? 4 : (P == 32 ? 5 : 6);
     static_assert((1 << LG) == P, "P is a power of two");
-    return (k == 0) ? 2 * P : (2 * k == P) ? 2 * P + 1 + (q >> (LG - 1)) : (2 * k < P) ? q : P + q;
+    // selects rather than branches: k differs between lanes
+    int idx = (2 * k < P) ? q : P + q;
+    idx = (2 * k == P) ? 2 * P + 1 + (q >> (LG - 1)) : idx;
+    return (k == 0) ? 2 * P : idx;
 }
+
+// m_index for a fixed row k, as base + ((q & mask) >> shift): the forward
+// products' lanes keep one row for the whole pass.
+template <int P>
+struct MRow {
+    int base, mask, shift;
+    __device__ __forceinline__ MRow(int k)
+    {
+        constexpr int LG = (P == 16) ? 4 : (P == 32 ? 5 : 6);
+        base = (k == 0) ? 2 * P : (2 * k == P) ? 2 * P + 1 : (2 * k < P) ? 0 : P;
+        mask = (k == 0) ? 0 : P - 1;
+        shift = (2 * k == P) ? LG - 1 : 0;
+    }
+    __device__ __forceinline__ int at(int q) const { return base + ((q & mask) >> shift); }
+};
 
 // atom-table columns (per atom of a tile); TA_OA holds (orig, active) as two ints
 enum { TA_X0 = 0, TA_HM = 3, TA_IM = 4, TA_SG = 5, TA_OA = 6, TA_CREF = 7, TA_C = 10 };
@@ -284,7 +315,6 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
     // ---- forward products: f~ of mode block mb for the tile's 16 atoms
     // (the positions' modes are carried from the previous step)
     const int ra0 = tt * 16;          // this wave's first row in the tiles
-    const bool ok_op = (a0 + lr) < N;
     d4 af[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) af[d] = d4{0.0, 0.0, 0.0, 0.0};
@@ -292,17 +322,17 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
         const int lf = opaque(l), fr = lf & 15, fq = lf >> 4, fm = mb * 16 + fr;
         const double *frow = sm.f + (ra0 + fr) * L::ROW;
         const int fs = (ra0 + fr) & L::SWZ;
-        // B operand M^T[bead][mode] = M[fm][4 kb + fq]: phase fm (4 kb + fq) mod P
+        // B operand M^T[bead][mode] = M[fm][4 kb + fq]: phase fm (4 kb + fq) mod P.
+        // Rows of atoms past the end hold stale values: their products land in
+        // accumulator rows that are never used.
+        const MRow<P> mr(fm);
         const int q0 = (fm * fq) & (P - 1), dq = (4 * fm) & (P - 1);
 #pragma unroll 4
         for (int kb = 0; kb < NK4; ++kb) {
             const int cj = swc<P>(fs, 4 * kb + fq);
-            const double bm = sm.mt[m_index<P>(fm, (q0 + kb * dq) & (P - 1))];
+            const double bm = sm.mt[mr.at(q0 + kb * dq)];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double fv = ok_op ? frow[d * P + cj] : 0.0;
-                af[d] = mfma4(fv, bm, af[d]);
-            }
+            for (int d = 0; d < 3; ++d) af[d] = mfma4(frow[d * P + cj], bm, af[d]);
         }
     }
     lds_barrier();                    // every wave is done with the f tile
@@ -497,7 +527,7 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
 }
 
 template <int P, bool OB, bool FC>
-__device__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *partial_out)
+__device__ __forceinline__ void mfma_tiles(const FusedArgs &a, int first, int stride, double *partial_out)
 {
     using L = Lds<P>;
     constexpr int T = L::T;

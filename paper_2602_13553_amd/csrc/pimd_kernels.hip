@@ -730,6 +730,10 @@ __device__ __forceinline__ int pack_shift(int sx, int sy, int sz)
 {
     return (sx + 512) | ((sy + 512) << 10) | ((sz + 512) << 20);
 }
+constexpr int kNoShift = 512 | (512 << 10) | (512 << 20);   // pack_shift(0, 0, 0)
+// Word 3 of a raw buffer resource on gfx9-family parts (data format 32,
+// no swizzle, no index stride): offsets are plain byte offsets.
+constexpr int kBufferRsrcWord3 = 0x00020000;
 __device__ __forceinline__ void unpack_shift(int p, double &sx, double &sy, double &sz)
 {
     sx = (double)((p & 1023) - 512);
@@ -1056,6 +1060,10 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     const int C = kPairStage / A;
     const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
     const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
+    // (uniform per kernel: S = 1 with P a multiple of 64, and a position
+    // array that a buffer's 31-bit range covers)
+    const long long x_bytes = (long long)a.N * 3 * P * 8;
+    const bool uniform_entries = S == 1 && P % 64 == 0 && x_bytes < (1LL << 31);
     for (int c0 = 0; c0 < nmax; c0 += C) {
         const int span = min(C, nmax - c0);
         for (int e2 = t; e2 < A * span; e2 += kBlock) {
@@ -1066,6 +1074,45 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         const int2 *ls = s_lst + la * span;                 // entry q at ls[q - c0]
         const int qend = min(cnt, c0 + span);
         int q = c0 + sg;
+        if (uniform_entries) {
+            // One lane group per atom, and the atom's group is whole waves:
+            // every lane of a wave takes the same entry.  The entries are read
+            // as scalars and the gathers are buffer loads: scalar offset (the
+            // neighbor's rows) plus this lane's fixed bead offset, no vector
+            // address arithmetic.  The image shift costs vector work only
+            // where it is not zero.  (The buffer's range is the position
+            // array: an offset past it would read zeros, not fault.)
+            const __amdgpu_buffer_rsrc_t xr =
+                __builtin_amdgcn_make_buffer_rsrc((void *)X, (short)0, (int)x_bytes, kBufferRsrcWord3);
+            const unsigned kx = (unsigned)k * 8u, ky = kx + (unsigned)P * 8u, kz = ky + (unsigned)P * 8u;
+            for (; q + 3 < qend; q += 4) {
+                unsigned jo[4];
+                int js[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int2 en = ls[q - c0 + u];
+                    jo[u] = (unsigned)__builtin_amdgcn_readfirstlane(en.x) * 8u;
+                    js[u] = __builtin_amdgcn_readfirstlane(en.y);
+                }
+                double xj[4], yj[4], zj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xj[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, kx, jo[u], 0));
+                    yj[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, ky, jo[u], 0));
+                    zj[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, kz, jo[u], 0));
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
+                    if (js[u] != kNoShift) {
+                        double sx, sy, sz;
+                        unpack_shift(js[u], sx, sy, sz);
+                        dx += sx * L0; dy += sy * L1; dz += sz * L2;
+                    }
+                    lj_accumulate<DIAG>(dx, dy, dz, rc2, sig2, eps24, fx, fy, fz, s12, s6, np, wd);
+                }
+            }
+        }
         // four entries per iteration: all gathers issued before any use
         for (; q + 3 * S < qend; q += 4 * S) {
             int2 en[4];
@@ -1331,7 +1378,7 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
     if (t == 0) reinterpret_cast<double2 *>(a.fpartials)[b] = make_double2(e1[0], e1[1]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pair(PairArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_pair(PairArgs a)
 {
     __shared__ int s_cnt[kBlock];
     __shared__ double red[64];

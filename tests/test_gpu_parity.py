@@ -190,6 +190,26 @@ def test_water_full_size_p64():
     check_states(g, o)
 
 
+@pytest.mark.parametrize("kind,N,P", [("lj", 257, 64), ("lj_images", 64, 64), ("water", 387, 64),
+                                      ("lj", 130, 128)])
+def test_pair_one_group_per_atom(kind, N, P):
+    """The force pass with one lane group per atom and P a multiple of 64:
+    every lane of a wave takes the same list entry (entries read as scalars,
+    gathers as buffer loads, the image shift applied only where it is not
+    zero).  A ragged last tile, a box under 2 rc (every pair through images,
+    entries with several shifts), water's bonds, and P = 128 (two waves per
+    atom)."""
+    pimd = _pimd()
+    if kind == "water":
+        spec = inputs.water(n_atoms=N, n_beads=P, seed=N)
+    else:
+        spec = inputs.lj_liquid(n_atoms=N, n_beads=P, seed=N)
+        if kind == "lj_images":
+            assert spec.box[0] < 2 * spec.lj_rc
+    g, o = run_pair(spec, 6, chunks=[2, 4], flags=pimd.PIMD_PAIR_SUBGROUPS(1))
+    check_states(g, o)
+
+
 # ------------------------------------------------------------ transform variants
 @pytest.mark.parametrize("kind,N,P", [
     ("harmonic", 37, 16), ("harmonic", 50, 32), ("harmonic", 5, 64), ("harmonic", 333, 64),
