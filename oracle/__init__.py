@@ -84,6 +84,7 @@ def lib():
     if _lib is None:
         _lib = C.CDLL(os.environ.get("ORACLE_LIB") or build())
         d = C.POINTER(C.c_double)
+        u32 = C.POINTER(C.c_uint32)
         u64 = C.POINTER(C.c_uint64)
         S = C.POINTER(_System)
         sig = {
@@ -91,9 +92,10 @@ def lib():
             "orc_mode_lambda": (None, [C.c_int32, d]),
             "orc_to_normal": (None, [C.c_int32, C.c_int32, d, d]),
             "orc_from_normal": (None, [C.c_int32, C.c_int32, d, d]),
-            "orc_philox4x64_10": (None, [u64, u64, u64]),
-            "orc_gaussians": (None, [C.c_uint64] * 5 + [d]),
-            "orc_gaussians_q": (None, [C.c_uint64] * 6 + [d]),
+            "orc_philox4x32_10": (None, [u32, u32, u32]),
+            "orc_gaussians": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, d]),
+            "orc_gaussians_q": (None, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64,
+                                       C.c_uint32, d]),
             "orc_free_rp_matrix": (None, [S, C.c_int32, C.c_double, d]),
             "orc_pile_coeffs": (None, [S, C.c_int32, d, d]),
             "orc_forces_bead": (C.c_double, [S, d, d]),
@@ -158,11 +160,11 @@ def from_normal(at: np.ndarray) -> np.ndarray:
     return out
 
 
-def philox4x64_10(ctr, key) -> list[int]:
-    c = (C.c_uint64 * 4)(*[int(v) & (2**64 - 1) for v in ctr])
-    k = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
-    o = (C.c_uint64 * 4)()
-    lib().orc_philox4x64_10(c, k, o)
+def philox4x32_10(ctr, key) -> list[int]:
+    c = (C.c_uint32 * 4)(*[int(v) & (2**32 - 1) for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & (2**32 - 1) for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
     return [int(v) for v in o]
 
 
@@ -182,9 +184,9 @@ def boson_spring(x: np.ndarray, kspring: float, beta_n: float, with_ev: bool = F
     return (v, f, prob, float(ev[0])) if with_ev else (v, f, prob)
 
 
-def gaussians(seed: int, tag: int, i: int, k: int, s: int, q: int = 0) -> np.ndarray:
+def gaussians(seed: int, i: int, k: int, s: int, q: int = 0) -> np.ndarray:
     z = np.zeros(3)
-    lib().orc_gaussians_q(seed, tag, i, k, s, q, _dp(z))
+    lib().orc_gaussians_q(seed, i, k, s, q, _dp(z))
     return z
 
 

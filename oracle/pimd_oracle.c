@@ -129,60 +129,52 @@ void orc_from_normal(int32_t P, int32_t N, const double *at, double *a)
 }
 
 /* ------------------------------------------------------------------------
- * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
- *   (hi0, lo0) = M0 * c0, (hi1, lo1) = M1 * c2,
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+ *   (hi0, lo0) = M0 * c0, (hi1, lo1) = M1 * c2   (32 x 32 -> 64-bit products),
  *   c <- (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0),
  * with the key bumped by the Weyl constants between rounds.
- * Pinned against numpy.random.Philox (known answers).
+ * Pinned against the generator authors' published known answers.
  * --------------------------------------------------------------------- */
-static void mul_hilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 {
-    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
-    *lo = (uint64_t)p;
-    *hi = (uint64_t)(p >> 64);
-}
-
-void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
-    uint64_t k0 = key[0], k1 = key[1];
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
     for (int r = 0; r < 10; ++r) {
-        uint64_t hi0, lo0, hi1, lo1;
-        mul_hilo64(M0, c0, &hi0, &lo0);
-        mul_hilo64(M1, c2, &hi1, &lo1);
-        uint64_t n0 = hi1 ^ c1 ^ k0;
-        uint64_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += W0; k1 += W1;
     }
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Uniform on (0, 1]: the top 53 bits plus one, times 2^-53. */
-static double u01_open0(uint64_t w)
+/* Uniform on (0, 1]: the word plus one, times 2^-32. */
+static double u01_open0(uint32_t w)
 {
-    return ((double)(w >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    return ((double)w + 1.0) * (1.0 / 4294967296.0);
 }
 
 /* Box-Muller on the four words: (z0, z1) from (u0, u1), z2 from (u2, u3).
  * The paper leaves the generator unspecified (App. D only asks for
  * independent N(0,1) numbers); this keyed, counter-based stream is this
- * implementation's reading.  Pinned by moment tests. */
-void orc_gaussians(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s,
-                   double z[3])
+ * implementation's reading.  Counter (i, k, s mod 2^32, floor(s / 2^32) +
+ * q 2^31), key (seed mod 2^32, floor(seed / 2^32)): i < 2^32 (an atom, or
+ * 2^32 - 1 for the barostat's own noise), k < 2^32, s < 2^31 * 2^32.
+ * Pinned by moment tests. */
+void orc_gaussians(uint64_t seed, uint32_t i, uint32_t k, uint64_t s, double z[3])
 {
-    orc_gaussians_q(seed, tag, i, k, s, 0, z);
+    orc_gaussians_q(seed, i, k, s, 0, z);
 }
 
-void orc_gaussians_q(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s, uint64_t q,
-                     double z[3])
+void orc_gaussians_q(uint64_t seed, uint32_t i, uint32_t k, uint64_t s, uint32_t q, double z[3])
 {
-    uint64_t ctr[4] = {i, k, s, q};
-    uint64_t key[2] = {seed, tag};
-    uint64_t w[4];
-    orc_philox4x64_10(ctr, key, w);
+    const uint32_t ctr[4] = {i, k, (uint32_t)s, (uint32_t)(s >> 32) | (q << 31)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
     double u0 = u01_open0(w[0]), u1 = u01_open0(w[1]);
     double u2 = u01_open0(w[2]), u3 = u01_open0(w[3]);
     double r0 = sqrt(-2.0 * log(u0));
@@ -501,7 +493,7 @@ void orc_forces(const orc_system *sys, const double *x, double *f, double *U)
  *   A  (x~, v~) <- A(dt/2)
  *      x = M^T x~, f = F(x)
  *   B  v~ += (dt/2) f~/m        with f~ = M f
- * The noise eta for mode k, atom i, dim a at step s is orc_gaussians(seed, 0,
+ * The noise eta for mode k, atom i, dim a at step s is orc_gaussians(seed,
  * i, k, s)[a].
  * --------------------------------------------------------------------- */
 /* Half-kick B(h): v~ += h (M f) / m, f in energy/length, v~ in length/time. */
@@ -532,7 +524,7 @@ static void orc_o_step(const orc_system *sys, double *vt, uint64_t s, uint64_t q
             double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
             const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
             double z[3];
-            orc_gaussians_q(sys->seed, 0, id, (uint64_t)k, s, q, z);
+            orc_gaussians_q(sys->seed, (uint32_t)id, (uint32_t)k, s, (uint32_t)q, z);
             for (int d = 0; d < 3; ++d) {
                 size_t e = ((size_t)k * N + i) * 3 + d;
                 vt[e] = c1 * vt[e] + c2 * sigma * z[d];
@@ -604,7 +596,7 @@ void orc_step_positions(const orc_system *sys, double *x, double *vt, const doub
             double sigma = sqrt((double)P * sys->kB * sys->temp * ftm2v / sys->mass[i]);
             double z[3] = {0.0, 0.0, 0.0};
             const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
-            if (!sys->nve) orc_gaussians(sys->seed, 0, id, (uint64_t)k, s, z);
+            if (!sys->nve) orc_gaussians(sys->seed, (uint32_t)id, (uint32_t)k, s, z);
             for (int d = 0; d < 3; ++d) {
                 size_t e = ((size_t)k * N + i) * 3 + d;
                 double q = xt[e], p = vt[e];
@@ -902,7 +894,7 @@ static void orc_baro_o(const orc_system *sys, orc_baro *b, uint64_t s, uint64_t 
     const double c1 = exp(-h / sys->tau), c2 = sqrt(1.0 - c1 * c1);
     const double sigma = sqrt((double)sys->n_beads * sys->kB * sys->temp / orc_baro_mass(sys));
     double z[3];
-    orc_gaussians_q(sys->seed, 0, ~(uint64_t)0, 0, s, q, z);
+    orc_gaussians_q(sys->seed, 0xFFFFFFFFu, 0, s, (uint32_t)q, z);
     if (sys->aniso)
         for (int d = 0; d < 3; ++d) b->vwa[d] = c1 * b->vwa[d] + c2 * sigma * z[d];
     else
@@ -961,7 +953,7 @@ void orc_npt_step(const orc_system *sys0, orc_baro *b, double *x, double *vt, do
                                                       (1.0 / sys.mvv2e) / sys.mass[i]);
                             const uint64_t id = sys.atom_id ? (uint64_t)sys.atom_id[i] : (uint64_t)i;
                             double z[3];
-                            orc_gaussians(sys.seed, 0, id, (uint64_t)k, s, z);
+                            orc_gaussians(sys.seed, (uint32_t)id, (uint32_t)k, s, z);
                             for (int d = 0; d < 3; ++d) {
                                 const size_t e = ((size_t)k * N + i) * 3 + d;
                                 vt[e] = c1 * vt[e] + c2 * sigma * z[d];
@@ -1208,7 +1200,7 @@ void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, doub
                 const double sigma = sqrt((double)P * kT * im);
                 const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
                 double z[3] = {0.0, 0.0, 0.0};
-                if (!sys->nve) orc_gaussians_q(sys->seed, 0, id, (uint64_t)j, s, 0, z);
+                if (!sys->nve) orc_gaussians_q(sys->seed, (uint32_t)id, (uint32_t)j, s, 0, z);
                 for (int d = 0; d < 3; ++d) {
                     const size_t e = ((size_t)j * N + i) * 3 + d;
                     if (obabo) {
@@ -1231,7 +1223,7 @@ void orc_boson_step(const orc_system *sys, double *x, double *v, double *f, doub
                 const double sigma = sqrt((double)P * kT * im);
                 const uint64_t id = sys->atom_id ? (uint64_t)sys->atom_id[i] : (uint64_t)i;
                 double z[3] = {0.0, 0.0, 0.0};
-                if (obabo && !sys->nve) orc_gaussians_q(sys->seed, 0, id, (uint64_t)j, s, 1, z);
+                if (obabo && !sys->nve) orc_gaussians_q(sys->seed, (uint32_t)id, (uint32_t)j, s, 1, z);
                 for (int d = 0; d < 3; ++d) {
                     const size_t e = ((size_t)j * N + i) * 3 + d;
                     v[e] += h * f[e] * im;                 /* B */

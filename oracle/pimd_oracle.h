@@ -92,14 +92,11 @@ void orc_to_normal(int32_t P, int32_t N, const double *a, double *at);
 void orc_from_normal(int32_t P, int32_t N, const double *at, double *a);
 
 /* --- random numbers (App. D noise) ------------------------------------- */
-void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
-/* three standard normal deviates for (seed, tag) and counter (i, k, s, 0) */
-void orc_gaussians(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s,
-                   double z[3]);
-/* The same for O step q of step s (0, or 1 for OBABO's second O): counter
- * (i, k, s, q). */
-void orc_gaussians_q(uint64_t seed, uint64_t tag, uint64_t i, uint64_t k, uint64_t s, uint64_t q,
-                     double z[3]);
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* three standard normal deviates for key seed and counter (i, k, s, 0) */
+void orc_gaussians(uint64_t seed, uint32_t i, uint32_t k, uint64_t s, double z[3]);
+/* The same for O step q of step s (0, or 1 for OBABO's second O). */
+void orc_gaussians_q(uint64_t seed, uint32_t i, uint32_t k, uint64_t s, uint32_t q, double z[3]);
 
 /* --- free ring-polymer propagator and thermostat coefficients ---------- */
 /* A(h) for mode k: [[a00, a01], [a10, a11]] acting on (x~, v~) */

@@ -68,26 +68,35 @@ def test_nm_round_trip(P):
 
 
 # ---------------------------------------------------------------- random numbers
-def test_philox_known_answers_numpy():
-    """numpy.random.Philox(counter=c, key=k).random_raw(4) returns
-    Philox4x64-10(c + 1, k), the counter incrementing from word 0 upward."""
-    rng = np.random.default_rng(1)
-    cases = [((0, 0), (0, 0, 0, 0)), ((2**64 - 1, 2**64 - 1), (2**64 - 1,) * 3 + (2**64 - 2,))]
-    for _ in range(20):
-        cases.append((tuple(int(v) for v in rng.integers(0, 2**63, 2)),
-                      tuple(int(v) for v in rng.integers(0, 2**63, 4))))
-    for key, ctr in cases:
-        g = np.random.Philox(key=np.array(key, dtype=np.uint64),
-                             counter=np.array(ctr, dtype=np.uint64))
-        ref = [int(v) for v in g.random_raw(4)]
-        c = sum(int(ctr[i]) << (64 * i) for i in range(4)) + 1
-        c1 = [(c >> (64 * i)) & (2**64 - 1) for i in range(4)]
-        assert oracle.philox4x64_10(c1, key) == ref
+def test_philox4x32_known_answers():
+    """The known answers that the generator's authors publish with their
+    reference implementation (Random123) for Philox4x32-10: counter and key
+    all zeros, all ones, and the leading hexadecimal digits of pi."""
+    cases = [
+        ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+        ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+        ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+         (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+    ]
+    for ctr, key, ref in cases:
+        assert oracle.philox4x32_10(ctr, key) == list(ref)
+
+
+def test_gaussian_counter_fields_are_distinct():
+    """Each field of the counter (atom, mode, step's two halves, O step) and
+    each half of the key changes the draw; the barostat's own index
+    2^32 - 1 is not an atom's."""
+    base = oracle.gaussians(7, 3, 5, 11, 0)
+    for args in ((8, 3, 5, 11, 0), (7 + 2**32, 3, 5, 11, 0), (7, 4, 5, 11, 0), (7, 3, 6, 11, 0),
+                 (7, 3, 5, 12, 0), (7, 3, 5, 11 + 2**32, 0), (7, 3, 5, 11, 1),
+                 (7, 2**32 - 1, 5, 11, 0)):
+        assert not np.array_equal(oracle.gaussians(*args), base), args
+    assert np.array_equal(oracle.gaussians(7, 3, 5, 11, 0), base)
 
 
 def test_gaussian_moments_and_independence():
     n = 60000
-    z = np.array([oracle.gaussians(12345, 0, i % 300, i // 300, 7) for i in range(n)])
+    z = np.array([oracle.gaussians(12345, i % 300, i // 300, 7) for i in range(n)])
     se = 1 / math.sqrt(n)
     for d in range(3):
         assert abs(z[:, d].mean()) < 5 * se
@@ -101,8 +110,8 @@ def test_gaussian_moments_and_independence():
         q = z[:, a] ** 2 * z[:, b] ** 2
         assert abs(q.mean() - 1) < 5 * q.std() / math.sqrt(n)
     # distinct keys, steps and modes give uncorrelated streams
-    z2 = np.array([oracle.gaussians(12346, 0, i % 300, i // 300, 7) for i in range(n)])
-    z3 = np.array([oracle.gaussians(12345, 0, i % 300, i // 300, 8) for i in range(n)])
+    z2 = np.array([oracle.gaussians(12346, i % 300, i // 300, 7) for i in range(n)])
+    z3 = np.array([oracle.gaussians(12345, i % 300, i // 300, 8) for i in range(n)])
     assert abs(np.corrcoef(z[:, 0], z2[:, 0])[0, 1]) < 5 * se
     assert abs(np.corrcoef(z[:, 0], z3[:, 0])[0, 1]) < 5 * se
 
@@ -468,8 +477,8 @@ def test_obabo_one_step_by_hand():
     c2 = math.sqrt(1 - c1 * c1)
     sig = math.sqrt(kT / m)
     for i in range(N):
-        z0 = oracle.gaussians(seed, 0, i, 0, s0, 0)
-        z1 = oracle.gaussians(seed, 0, i, 0, s0, 1)
+        z0 = oracle.gaussians(seed, i, 0, s0, 0)
+        z1 = oracle.gaussians(seed, i, 0, s0, 1)
         vh = c1 * v[0, i] + c2 * sig * z0
         x1 = x[0, i] + 0.5 * dt * vh + 0.5 * dt * vh
         v1 = c1 * vh + c2 * sig * z1
@@ -1197,8 +1206,8 @@ def test_boson_obabo_one_step_by_hand():
     h = 0.5 * s.dt
     xx, vv = x[:, 0].copy(), v[:, 0].copy()
     f0 = force(xx)
-    z0 = np.array([oracle.gaussians(s.seed, 0, 0, j, 0, 0) for j in range(P)])
-    z1 = np.array([oracle.gaussians(s.seed, 0, 0, j, 0, 1) for j in range(P)])
+    z0 = np.array([oracle.gaussians(s.seed, 0, j, 0, 0) for j in range(P)])
+    z1 = np.array([oracle.gaussians(s.seed, 0, j, 0, 1) for j in range(P)])
     vv = c1 * vv + c2 * sig * z0
     vv = vv + h * f0 / m
     xx = xx + h * vv
