@@ -301,8 +301,10 @@ int pimd_set_state(pimd_ctx *ctx, const double *x, const double *v, uint64_t ste
 /* Enqueue nsteps >= 0 steps on the context's stream and return without
  * waiting.  Each BAOAB step: B(dt/2), A(dt/2), O(dt), A(dt/2), forces,
  * B(dt/2), in normal modes (OBABO: see the integrator field); the noise for
- * mode k, atom i, dim a at step s is the Philox4x64-10 stream keyed by
- * (seed, 0) at counter (i, k, s, 0) (and (i, k, s, 1) for OBABO's second O).
+ * mode k, atom i (the caller's index), dim a at step s is the Philox4x32-10
+ * stream keyed by (seed mod 2^32, seed / 2^32) at counter (i, k, s mod 2^32,
+ * s / 2^32) (with 2^31 added to the last word for OBABO's second O), through
+ * Box-Muller; steps below 2^63.
  * After the call's work completes the state is synchronized (full-step
  * velocities) and the estimators of every step are in the running sums.
  * External forces take one step per call (see pimd_set_forces).

@@ -502,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_bpass(FusedArgs a)
         double x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, fp[3] = {0.0, 0.0, 0.0};
         double ft[3] = {0.0, 0.0, 0.0};
         double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0, cref[3] = {0.0, 0.0, 0.0};
-        unsigned long long oi = 0;
+        unsigned oi = 0;
         const size_t b = (size_t)i * 3 * P + k;
         if (act) {
 #pragma unroll
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_bpass(FusedArgs a)
             im = a.atoms[i * 4 + AT_INV_M];
             sg = a.atoms[i * 4 + AT_SIGMA];
             active = a.atoms[i * 4 + AT_ACTIVE];
-            oi = (unsigned long long)a.orig[i];
+            oi = (unsigned)a.orig[i];
             if (k == 0 && moves) {
                 cref[0] = a.cref[i * 3]; cref[1] = a.cref[i * 3 + 1]; cref[2] = a.cref[i * 3 + 2];
             }
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_bpass(FusedArgs a)
             // and O step q_ of that step, counter (atom, bead, s_, q_)
             auto o_step = [&](unsigned long long s_, unsigned long long q_) {
                 double z[3];
-                gauss3(a.seed, oi, (unsigned long long)k, s_, z, q_);
+                gauss3(a.seed, oi, (unsigned)k, s_, z, (unsigned)q_);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) v[d] = c1 * v[d] + c2 * sg * z[d];
             };

@@ -8,49 +8,33 @@
 namespace pimd {
 
 // --------------------------------------------------------------------------
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
 // --------------------------------------------------------------------------
-// 64 x 64 -> 128-bit product from four 32 x 32 + 64 multiply-adds
-// (v_mad_u64_u32), the carries folded into the addends:
-//   a*b = t + (u_lo + ah*bl) 2^32 + (u_hi + ah*bh) 2^64,  t = al*bl,
-//   u = al*bh + t_hi,  v = ah*bl + u_lo,  lo = v_lo:t_lo,  hi = ah*bh + u_hi + v_hi.
-__device__ __forceinline__ void mulhilo64(unsigned long long a, unsigned long long b,
-                                          unsigned long long &lo, unsigned long long &hi)
+// Each round takes two 32 x 32 -> 64-bit products (one v_mad_u64_u32 each);
+// the key is wave-uniform, so its Weyl bumps stay in scalar registers.
+__device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1)
 {
-    const unsigned al = (unsigned)a, ah = (unsigned)(a >> 32);
-    const unsigned bl = (unsigned)b, bh = (unsigned)(b >> 32);
-    const unsigned long long t = (unsigned long long)al * bl;
-    const unsigned long long u = (unsigned long long)al * bh + (t >> 32);
-    const unsigned long long v = (unsigned long long)ah * bl + (unsigned)u;
-    lo = (v << 32) | (unsigned)t;
-    hi = (unsigned long long)ah * bh + ((u >> 32) + (v >> 32));
-}
-
-__device__ __forceinline__ void philox4x64_10(unsigned long long c[4], unsigned long long k0,
-                                              unsigned long long k1)
-{
-    const unsigned long long M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const unsigned W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        unsigned long long lo0, hi0, lo1, hi1;
-        mulhilo64(M0, c[0], lo0, hi0);
-        mulhilo64(M1, c[2], lo1, hi1);
-        const unsigned long long n0 = hi1 ^ c[1] ^ k0;
-        const unsigned long long n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        const unsigned long long p0 = (unsigned long long)M0 * c[0];
+        const unsigned long long p1 = (unsigned long long)M1 * c[2];
+        const unsigned n0 = (unsigned)(p1 >> 32) ^ c[1] ^ k0;
+        const unsigned n2 = (unsigned)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0; c[1] = (unsigned)p1; c[2] = n2; c[3] = (unsigned)p0;
         k0 += W0; k1 += W1;
     }
 }
 
-// The uniform of a word: n = (top 53 bits) + 1 in [1, 2^53], u = n 2^-53 on (0, 1].
+// The uniform of a word w: n = w + 1 in [1, 2^32], u = n 2^-32 on (0, 1].
 
-// -2 ln u for u = n 2^-53.  With n = 2^e m, m in [sqrt(1/2), sqrt(2)):
-// ln u = (e - 53) ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, and
+// -2 ln u for u = n 2^-32.  With n = 2^e m, m in [sqrt(1/2), sqrt(2)):
+// ln u = (e - 32) ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, and
 // atanh(s) = s (1 + s^2/3 + s^4/5 + ...) summed to s^22 (next term < 2^-60).
-__device__ __forceinline__ double neg2log_u(unsigned long long w)
+__device__ __forceinline__ double neg2log_u(unsigned w)
 {
-    const double n = (double)(w >> 11) + 1.0;                 // exact
+    const double n = (double)w + 1.0;                          // exact
     int e = __builtin_amdgcn_frexp_exp(n);                     // n = 2^e * m0, m0 in [0.5, 1)
     double m = __builtin_amdgcn_frexp_mant(n);
     if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }      // m in [sqrt(1/2), sqrt(2))
@@ -76,23 +60,23 @@ __device__ __forceinline__ double neg2log_u(unsigned long long w)
     // ln 2 = LN2_HI + LN2_LO, LN2_HI = ln 2 truncated to 40 fraction bits (so
     // that k LN2_HI is exact for |k| < 2^12)
     const double LN2_HI = 0x1.62e42fefa2p-1, LN2_LO = 0x1.9ef35793c7673p-41;
-    const double k = (double)(e - 53);
+    const double k = (double)(e - 32);
     const double lnu = fma(k, LN2_HI, fma(k, LN2_LO, lnm));
     return -2.0 * lnu;
 }
 
-// sin and cos of 2 pi u for u = n 2^-53.  The octant q = floor(8u) and the
+// sin and cos of 2 pi u for u = n 2^-32.  The octant q = floor(8u) and the
 // offset inside it come exactly from the integer n; the angle t in [0, pi/4]
 // (measured from the nearer octant edge) goes through Taylor series to t^19
 // and t^20 (truncation < 2^-64), then q maps (sin t, cos t) back.
-__device__ __forceinline__ void sincos_2pi_u(unsigned long long w, double &sn, double &cs)
+__device__ __forceinline__ void sincos_2pi_u(unsigned w, double &sn, double &cs)
 {
-    const unsigned long long n = (w >> 11) + 1ULL;              // [1, 2^53]
-    const unsigned q = (unsigned)(n >> 50);                     // 0..8
-    const unsigned long long rem = n & ((1ULL << 50) - 1ULL);
+    const unsigned long long n = (unsigned long long)w + 1ULL;  // [1, 2^32]
+    const unsigned q = (unsigned)(n >> 29);                     // 0..8
+    const unsigned rem = (unsigned)n & ((1u << 29) - 1u);
     const bool odd = (q & 1u) != 0u;
-    const unsigned long long tq = odd ? (1ULL << 50) - rem : rem;
-    const double t = (double)tq * (0.78539816339744830962 * 8.8817841970012523234e-16);
+    const unsigned tq = odd ? (1u << 29) - rem : rem;
+    const double t = (double)tq * (0.78539816339744830962 * 0x1p-29);
     const double t2 = t * t;
     double ps = -1.0 / 121645100408832000.0;                   // -1/19!
     ps = fma(ps, t2, 1.0 / 355687428096000.0);
@@ -122,15 +106,18 @@ __device__ __forceinline__ void sincos_2pi_u(unsigned long long w, double &sn, d
     cs = (p == 0u) ? bc : (p == 1u) ? -bs : (p == 2u) ? -bc : bs;
 }
 
+// The barostat's own noise takes this index in place of an atom's.
+constexpr unsigned kBaroNoiseIndex = 0xFFFFFFFFu;
+
 // Three N(0,1) deviates for atom i, mode k, step s and O step q of the step
-// (0, or 1 for OBABO's second): counter (i, k, s, q), key (seed, 0);
-// Box-Muller (z0, z1) from (u0, u1), z2 from (u2, u3).
-__device__ __forceinline__ void gauss3(unsigned long long seed, unsigned long long i,
-                                       unsigned long long k, unsigned long long s, double z[3],
-                                       unsigned long long q = 0ULL)
+// (0, or 1 for OBABO's second): counter (i, k, s mod 2^32, s / 2^32 + q 2^31),
+// key (seed mod 2^32, seed / 2^32); Box-Muller (z0, z1) from (u0, u1), z2
+// from (u2, u3).
+__device__ __forceinline__ void gauss3(unsigned long long seed, unsigned i, unsigned k,
+                                       unsigned long long s, double z[3], unsigned q = 0u)
 {
-    unsigned long long c[4] = {i, k, s, q};
-    philox4x64_10(c, seed, 0ULL);
+    unsigned c[4] = {i, k, (unsigned)s, (unsigned)(s >> 32) | (q << 31)};
+    philox4x32_10(c, (unsigned)seed, (unsigned)(seed >> 32));
     const double r0 = sqrt(neg2log_u(c[0]));
     const double r2 = sqrt(neg2log_u(c[2]));
     double s1, c1, s3, c3;

@@ -373,7 +373,7 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
         // of step s_ and O step q_ of that step
         auto o_step = [&](unsigned long long s_, unsigned long long q_) {
             double z[3];
-            gauss3(a.seed, (unsigned long long)orig, (unsigned long long)m, s_, z, q_);
+            gauss3(a.seed, (unsigned)orig, (unsigned)m, s_, z, (unsigned)q_);
 #pragma unroll
             for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1 * P] * vt[d] + mk[MD_C2 * P] * sg * z[d];
         };

@@ -125,13 +125,13 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
         double hm = 0.0, im = 0.0, sg = 0.0, active = 0.0;
         double vpre[3] = {0.0, 0.0, 0.0}, ypre[3] = {0.0, 0.0, 0.0}, xref[3] = {0.0, 0.0, 0.0};
         double cref[3] = {0.0, 0.0, 0.0};
-        unsigned long long oi = 0;
+        unsigned oi = 0;
         if (act) {
             hm = a.atoms[i * 4 + AT_HALF_M];
             im = a.atoms[i * 4 + AT_INV_M];
             sg = a.atoms[i * 4 + AT_SIGMA];
             active = a.atoms[i * 4 + AT_ACTIVE];
-            oi = (unsigned long long)a.orig[i];
+            oi = (unsigned)a.orig[i];
             const size_t vb = (size_t)i * 3 * P + k;
             if (mode != FUSED_PREP) {
                 vpre[0] = a.v[vb]; vpre[1] = a.v[vb + P]; vpre[2] = a.v[vb + 2 * P];
@@ -241,7 +241,7 @@ __device__ void fused_tiles(const FusedArgs &a, int t0, int tstride, double *sme
             // of step s_ and O step q_ of that step
             auto o_step = [&](unsigned long long s_, unsigned long long q_) {
                 double z[3];
-                gauss3(a.seed, oi, (unsigned long long)k, s_, z, q_);
+                gauss3(a.seed, oi, (unsigned)k, s_, z, (unsigned)q_);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
             };

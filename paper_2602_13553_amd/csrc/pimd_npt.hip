@@ -65,7 +65,7 @@ __device__ double baro_kick_dim(const NptArgs &a, double vw, double h, double k0
 __device__ double baro_o(const NptArgs &a, double vw, unsigned long long s, unsigned long long q)
 {
     double z[3];
-    gauss3(a.f.seed, ~0ULL, 0ULL, s, z, q);
+    gauss3(a.f.seed, kBaroNoiseIndex, 0u, s, z, (unsigned)q);
     return a.bc1 * vw + a.bc2 * a.bsig * z[0];
 }
 
@@ -74,7 +74,7 @@ __device__ double baro_o(const NptArgs &a, double vw, unsigned long long s, unsi
 __device__ void baro_o3(const NptArgs &a, double vw[3], unsigned long long s, unsigned long long q)
 {
     double z[3];
-    gauss3(a.f.seed, ~0ULL, 0ULL, s, z, q);
+    gauss3(a.f.seed, kBaroNoiseIndex, 0u, s, z, (unsigned)q);
 #pragma unroll
     for (int d = 0; d < 3; ++d) vw[d] = a.bc1 * vw[d] + a.bc2 * a.bsig * z[d];
 }
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
         }
         const double hm = a.atoms[i * 4 + AT_HALF_M], im = a.atoms[i * 4 + AT_INV_M];
         const double sg = a.atoms[i * 4 + AT_SIGMA];
-        const unsigned long long oi = (unsigned long long)a.orig[i];
+        const unsigned oi = (unsigned)a.orig[i];
         const double *mk = a.modes + k * 8;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_a(NptArgs na, int mode)
         }
         auto o_step = [&](unsigned long long s_, unsigned long long q_) {
             double z[3];
-            gauss3(a.seed, oi, (unsigned long long)k, s_, z, q_);
+            gauss3(a.seed, oi, (unsigned)k, s_, z, (unsigned)q_);
 #pragma unroll
             for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
         };
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_npt_b(NptArgs na)
             a_flow(a.hdt, vw, 1);
             if (a.nvt) {
                 double z[3];
-                gauss3(a.seed, (unsigned long long)a.orig[i], (unsigned long long)k, step, z, 0ULL);
+                gauss3(a.seed, (unsigned)a.orig[i], (unsigned)k, step, z, 0u);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) vt[d] = mk[MD_C1] * vt[d] + mk[MD_C2] * sg * z[d];
             }
