@@ -295,7 +295,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
  * Computes f(x), the neighbor lists and the estimators of this state (with
  * external forces: neither; they follow pimd_set_forces), and sets the
  * thermostat step counter to `step`.  Synchronizes.
- * Errors: ARG (NULL or non-finite input), DEVICE. */
+ * Errors: ARG (NULL or non-finite input, step >= 2^63), DEVICE. */
 int pimd_set_state(pimd_ctx *ctx, const double *x, const double *v, uint64_t step);
 
 /* Enqueue nsteps >= 0 steps on the context's stream and return without

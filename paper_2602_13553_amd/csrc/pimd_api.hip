@@ -876,6 +876,8 @@ int pimd_set_state(pimd_ctx *c, const double *x, const double *v, uint64_t step)
 {
     if (!c) return fail(nullptr, PIMD_ERR_ARG, "ctx is NULL");
     if (!x || !v) return fail(c, PIMD_ERR_ARG, "x and v must be non-NULL");
+    // the noise counter keeps the step in 63 bits (its top bit is the O step)
+    if (step >> 63) return fail(c, PIMD_ERR_ARG, "step must be below 2^63");
     const int N = c->p.n_atoms, P = c->p.n_beads;
     const size_t n = (size_t)N * 3 * P;
     for (size_t e = 0; e < n; ++e)

@@ -428,6 +428,10 @@ def test_error_paths():
     with pytest.raises(pimd.PimdError) as ei:
         ctx.set_state(bad, spec.v0)
     assert ei.value.code == -1
+    with pytest.raises(pimd.PimdError) as ei:
+        ctx.set_state(spec.x0, spec.v0, 2**63)
+    assert ei.value.code == -1
+    ctx.set_state(spec.x0, spec.v0, 2**63 - 1)
     ctx.set_state(spec.x0, spec.v0)
     with pytest.raises(pimd.PimdError):
         ctx.step(-1)
