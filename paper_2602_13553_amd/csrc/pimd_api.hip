@@ -820,6 +820,7 @@ int pimd_create(const pimd_params *p, const double *mass, const pimd_topology *t
     q.N = N; q.P = P; q.n_active = n_active; q.cap = L.cap;
     q.n_forced = L.n_forced;
     q.S = L.pair_S;
+    q.paired = pair_lanes_paired(N, P) ? 1 : 0;
     q.n_active_tiles = L.pair_active_tiles;
     for (int d = 0; d < 3; ++d) q.box[d] = p->box[d];
     q.rc2 = p->lj_rc * p->lj_rc;
@@ -1201,7 +1202,7 @@ struct pimd_batch {
         int off, n;   // items [off, off + n)
     };
     std::vector<Group> step_groups;
-    int pair_off = 0, pair_n = 0, close_off = 0, close_n = 0, n_sys_plan = 0;
+    int pair_off = 0, pair_n = 0, pair1_off = 0, pair1_n = 0, close_off = 0, close_n = 0, n_sys_plan = 0;
     int smem_valu = 0;   // dynamic LDS of the batched vector-ALU pass: max over its systems
     bool pair_clusters = false;   // some system's force pass uses cluster lists
     int ncu = 256;
@@ -1310,15 +1311,19 @@ int rebuild_plan(pimd_batch *b)
         g.n = (int)items.size() - g.off;
         if (g.n) b->step_groups.push_back(g);
     }
-    b->pair_off = (int)items.size();
+    // force items: the systems whose lanes take bead pairs, then the others
     b->pair_clusters = false;
-    for (int s = 0; s < n; ++s) {
-        pimd_ctx *c = b->sys[s];
-        if (!c || !b->active[s] || !c->fa.pair) continue;
-        for (int t = 0; t < c->lay.pair_grid; ++t) items.push_back(make_int2(s, t));
-        if (c->lay.n_clusters) b->pair_clusters = true;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int off = (int)items.size();
+        for (int s = 0; s < n; ++s) {
+            pimd_ctx *c = b->sys[s];
+            if (!c || !b->active[s] || !c->fa.pair || (c->pa.paired != 0) != (pass == 0)) continue;
+            for (int t = 0; t < c->lay.pair_grid; ++t) items.push_back(make_int2(s, t));
+            if (c->lay.n_clusters) b->pair_clusters = true;
+        }
+        (pass == 0 ? b->pair_off : b->pair1_off) = off;
+        (pass == 0 ? b->pair_n : b->pair1_n) = (int)items.size() - off;
     }
-    b->pair_n = (int)items.size() - b->pair_off;
     b->close_off = (int)items.size();
     for (int s = 0; s < n; ++s) {
         pimd_ctx *c = b->sys[s];
@@ -1369,7 +1374,10 @@ void enqueue_batch_step(pimd_batch *b)
     launch_finalize_batch(b->d_fa, b->d_nparts, b->n_sys_plan, FUSED_STEP, b->stream);
     if (b->pair_n)
         launch_pair_batch(b->d_pa, b->d_items + b->pair_off, b->pair_n, std::min(b->pair_n, 8 * ncu),
-                          b->pair_clusters, b->stream);
+                          b->pair_clusters, true, b->stream);
+    if (b->pair1_n)
+        launch_pair_batch(b->d_pa, b->d_items + b->pair1_off, b->pair1_n,
+                          std::min(b->pair1_n, 8 * ncu), b->pair_clusters, false, b->stream);
 }
 
 }  // namespace

@@ -145,6 +145,7 @@ struct PairArgs {
     int N, P, n_active, cap;
     int n_forced;             // atoms 0..n_forced-1 have lanes; the rest are bond-owned
     int S;                    // sub-groups of lanes sharing one atom's list
+    int paired;               // 1: lanes take bead pairs (pair_lanes_paired)
     int n_active_tiles;       // tiles that hold LJ-active atoms (they come first)
     double box[3];
     double rc2;
@@ -259,10 +260,17 @@ void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys,
                            hipStream_t s);
 void set_pair_smem();
 void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
-                       bool clusters, hipStream_t s);
+                       bool clusters, bool paired, hipStream_t s);
 int pair_subgroups(int N, int P);
 int pair_grid(int N, int P, int S);
 int pair_active_tiles(int n_active, int P, int S);
+// The force pass gives each lane two consecutive beads (16-byte gathers) when
+// P is even and the position array fits 32-bit buffer offsets; the rule is
+// the same for a system alone and in a batch, so both sum in the same order.
+inline bool pair_lanes_paired(int N, int P)
+{
+    return P % 2 == 0 && (long long)N * 3 * P * 8 < (1LL << 31);
+}
 void launch_pair(const PairArgs &a, int grid, hipStream_t s);
 void launch_import(const double *src, double *dst, const int *orig, int N, int P, hipStream_t s);
 void launch_export(const double *x, const double *v, const double *atoms_mass, const double *M,

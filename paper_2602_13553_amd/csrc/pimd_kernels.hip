@@ -840,7 +840,11 @@ __device__ __forceinline__ void bond_forces(const PairArgs &a, int i, int k, dou
 // when the system alone would leave the GPU with few waves to hide latency.
 // BOXDEV: the box lengths come from the control block (a barostat moves them)
 // DIAG: the block also writes the diagonal of its cell virial (a.fdiag)
-template <bool BOXDEV = false, bool DIAG = false>
+// PAIRED (even P, pair_lanes_paired): in the force loop each lane takes two
+// consecutive beads of 2S sub-groups of P/2 lanes, so every gather is a
+// 16-byte load: half the load instructions of one bead per lane, which is
+// what the loop's gathers are limited by when the rows come from L2.
+template <bool BOXDEV = false, bool DIAG = false, bool PAIRED = false>
 __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, double *s_f)
 {
     const int P = a.P, S = a.S;
@@ -1046,8 +1050,22 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     const double *__restrict__ X = a.x;
     double xi = 0.0, yi = 0.0, zi = 0.0;
     const int cnt = (act && i < a.n_active) ? a.nbr_count[i] : 0;
+    // PAIRED: lane = (atom, sub-group sg2 of 2S, bead pair kp) takes beads
+    // 2 kp and 2 kp + 1 of every 2S-th entry of the atom's list
+    const int P2 = P / 2, S2 = 2 * S;
+    const int sg2 = PAIRED ? g / P2 : 0, kp = PAIRED ? g - sg2 * P2 : 0;
+    double pxi[2] = {0.0, 0.0}, pyi[2] = {0.0, 0.0}, pzi[2] = {0.0, 0.0};
+    double pf[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (act) {
-        xi = X[ib]; yi = X[ib + P]; zi = X[ib + 2 * P];
+        if constexpr (PAIRED) {
+            const size_t pb = (size_t)i * P3 + 2 * kp;
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2) {
+                pxi[b2] = X[pb + b2]; pyi[b2] = X[pb + P + b2]; pzi[b2] = X[pb + 2 * P + b2];
+            }
+        } else {
+            xi = X[ib]; yi = X[ib + P]; zi = X[ib + 2 * P];
+        }
     }
     // The block's list entries pass through LDS, up to C = kPairStage/A per
     // atom at a time, in one coalesced copy: the loop then waits only on the
@@ -1060,10 +1078,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     const int C = kPairStage / A;
     const double eps4 = 4.0 * a.lj_eps, eps24 = 24.0 * a.lj_eps;
     const double rc2 = a.rc2, sig2 = a.lj_sig2, ush = a.lj_ushift;
-    // (uniform per kernel: S = 1 with P a multiple of 64, and a position
-    // array that a buffer's 31-bit range covers)
     const long long x_bytes = (long long)a.N * 3 * P * 8;
-    const bool uniform_entries = S == 1 && P % 64 == 0 && x_bytes < (1LL << 31);
     for (int c0 = 0; c0 < nmax; c0 += C) {
         const int span = min(C, nmax - c0);
         for (int e2 = t; e2 < A * span; e2 += kBlock) {
@@ -1074,47 +1089,58 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         const int2 *ls = s_lst + la * span;                 // entry q at ls[q - c0]
         const int qend = min(cnt, c0 + span);
         int q = c0 + sg;
-        if (uniform_entries) {
-            // One lane group per atom, and the atom's group is whole waves:
-            // every lane of a wave takes the same entry.  The entries are read
-            // as scalars and the gathers are buffer loads: scalar offset (the
-            // neighbor's rows) plus this lane's fixed bead offset, no vector
-            // address arithmetic.  The image shift costs vector work only
-            // where it is not zero.  (The buffer's range is the position
-            // array: an offset past it would read zeros, not fault.)
+        if constexpr (PAIRED) {
+            typedef double dbl2 __attribute__((ext_vector_type(2)));
+            // the buffer's range is the position array (pair_lanes_paired
+            // keeps it under 2 GiB)
             const __amdgpu_buffer_rsrc_t xr =
                 __builtin_amdgcn_make_buffer_rsrc((void *)X, (short)0, (int)x_bytes, kBufferRsrcWord3);
-            const unsigned kx = (unsigned)k * 8u, ky = kx + (unsigned)P * 8u, kz = ky + (unsigned)P * 8u;
-            for (; q + 3 < qend; q += 4) {
-                unsigned jo[4];
-                int js[4];
+            const unsigned kx = (unsigned)(2 * kp) * 8u, ky = kx + (unsigned)P * 8u,
+                           kz = ky + (unsigned)P * 8u;
+            // (the image shift costs vector work only where it is not zero)
+            auto pair2 = [&](const int2 en, const dbl2 xj, const dbl2 yj, const dbl2 zj) {
+                double dx[2], dy[2], dz[2];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int2 en = ls[q - c0 + u];
-                    jo[u] = (unsigned)__builtin_amdgcn_readfirstlane(en.x) * 8u;
-                    js[u] = __builtin_amdgcn_readfirstlane(en.y);
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    dx[b2] = pxi[b2] - xj[b2]; dy[b2] = pyi[b2] - yj[b2]; dz[b2] = pzi[b2] - zj[b2];
                 }
-                double xj[4], yj[4], zj[4];
+                if (en.y != kNoShift) {
+                    double sx, sy, sz;
+                    unpack_shift(en.y, sx, sy, sz);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    xj[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, kx, jo[u], 0));
-                    yj[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, ky, jo[u], 0));
-                    zj[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, kz, jo[u], 0));
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    double dx = xi - xj[u], dy = yi - yj[u], dz = zi - zj[u];
-                    if (js[u] != kNoShift) {
-                        double sx, sy, sz;
-                        unpack_shift(js[u], sx, sy, sz);
-                        dx += sx * L0; dy += sy * L1; dz += sz * L2;
+                    for (int b2 = 0; b2 < 2; ++b2) {
+                        dx[b2] += sx * L0; dy[b2] += sy * L1; dz[b2] += sz * L2;
                     }
-                    lj_accumulate<DIAG>(dx, dy, dz, rc2, sig2, eps24, fx, fy, fz, s12, s6, np, wd);
                 }
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2)
+                    lj_accumulate<DIAG>(dx[b2], dy[b2], dz[b2], rc2, sig2, eps24, pf[3 * b2],
+                                        pf[3 * b2 + 1], pf[3 * b2 + 2], s12, s6, np, wd);
+            };
+            auto rows = [&](const int2 en, dbl2 &xj, dbl2 &yj, dbl2 &zj) {
+                const unsigned jo = (unsigned)en.x * 8u;
+                xj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, jo + kx, 0, 0));
+                yj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, jo + ky, 0, 0));
+                zj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, jo + kz, 0, 0));
+            };
+            // two entries per iteration: all six gathers issued before any use
+            for (q = c0 + sg2; q + S2 < qend; q += 2 * S2) {
+                const int2 en0 = ls[q - c0], en1 = ls[q + S2 - c0];
+                dbl2 xj0, yj0, zj0, xj1, yj1, zj1;
+                rows(en0, xj0, yj0, zj0);
+                rows(en1, xj1, yj1, zj1);
+                pair2(en0, xj0, yj0, zj0);
+                pair2(en1, xj1, yj1, zj1);
+            }
+            if (q < qend) {
+                const int2 en = ls[q - c0];
+                dbl2 xj, yj, zj;
+                rows(en, xj, yj, zj);
+                pair2(en, xj, yj, zj);
             }
         }
         // four entries per iteration: all gathers issued before any use
-        for (; q + 3 * S < qend; q += 4 * S) {
+        if (!PAIRED) for (; q + 3 * S < qend; q += 4 * S) {
             int2 en[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) en[u] = ls[q - c0 + u * S];
@@ -1132,7 +1158,7 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                                     rc2, sig2, eps24, fx, fy, fz, s12, s6, np, wd);
             }
         }
-        for (; q < qend; q += S) {
+        if (!PAIRED) for (; q < qend; q += S) {
             const int2 en = ls[q - c0];
             double sx, sy, sz;
             unpack_shift(en.y, sx, sy, sz);
@@ -1143,11 +1169,33 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
         }
         __syncthreads();
     }
+    if constexpr (PAIRED) {
+        // back to one bead per lane: the sub-group 0 lanes sum the 2S
+        // sub-groups' forces of their bead in sub-group order (the staged
+        // entries are no longer needed, so their LDS holds the partials:
+        // A * 2S * 3P = 6 kBlock doubles)
+        double *s2 = reinterpret_cast<double *>(s_lst);
+        if (la < A) {
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s2[((la * S2 + sg2) * 3 + d) * P + 2 * kp + b2] = pf[3 * b2 + d];
+        }
+        __syncthreads();
+        if (act && sg == 0) {
+            for (int u = 0; u < S2; ++u) {
+                fx += s2[((la * S2 + u) * 3 + 0) * P + k];
+                fy += s2[((la * S2 + u) * 3 + 1) * P + k];
+                fz += s2[((la * S2 + u) * 3 + 2) * P + k];
+            }
+            xi = X[ib]; yi = X[ib + P]; zi = X[ib + 2 * P];
+        }
+    }
     lj_energy_virial(s12, s6, np, eps4, eps24, ush, e, wv);
 #pragma unroll
     for (int d = 0; d < 3; ++d) wd[d] *= 0.5;   // half of each ordered pair, as the trace
     if (act && sg == 0) bond_forces<DIAG>(a, i, k, xi, yi, zi, L0, L1, L2, fx, fy, fz, e, wv, wd);
-    if (S > 1) {
+    if (!PAIRED && S > 1) {
         s_f[t * 3] = fx; s_f[t * 3 + 1] = fy; s_f[t * 3 + 2] = fz;
         __syncthreads();
         if (act && sg == 0) {
@@ -1378,7 +1426,8 @@ __device__ void cluster_tile(const PairArgs &a, int b, double *smem, int *s_cnt,
     if (t == 0) reinterpret_cast<double2 *>(a.fpartials)[b] = make_double2(e1[0], e1[1]);
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_pair(PairArgs a)
+template <bool PAIRED>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PAIRED ? 5 : 6))) void k_pair(PairArgs a)
 {
     __shared__ int s_cnt[kBlock];
     __shared__ double red[64];
@@ -1387,7 +1436,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     // is laid out contiguously per XCD, so both are spread over all XCDs.
     const int b = blockIdx.x, nA = a.n_active_tiles;
     const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
-    pair_tile(a, tile, s_cnt, red, s_f);
+    pair_tile<false, false, PAIRED>(a, tile, s_cnt, red, s_f);
 }
 // The same pass with the active tiles on cluster lists (a kernel of its own,
 // so that the per-atom kernel keeps its register budget).
@@ -1406,7 +1455,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_clusters(PairArgs a)
 }
 
 // Batched: one (system, tile) item per block (grid = item count).  Per-atom
-// lists only, so that the kernel keeps the per-atom kernel's register budget.
+// lists only, so that the kernel keeps the per-atom kernel's register budget;
+// the systems with paired lanes and the others are two item lists.
+template <bool PAIRED>
 __global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *__restrict__ table,
                                                        const int2 *__restrict__ items, int n_items)
 {
@@ -1418,7 +1469,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batch(const PairArgs *__restric
     const int sys = __builtin_amdgcn_readfirstlane(items[blockIdx.x].x);
     const int tile = __builtin_amdgcn_readfirstlane(items[blockIdx.x].y);
     const PairArgs a = table[sys];
-    pair_tile(a, tile, s_cnt, red, s_f);
+    pair_tile<false, false, PAIRED>(a, tile, s_cnt, red, s_f);
 }
 
 // The same with cluster lists for the systems that use them.
@@ -1432,8 +1483,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_batch_clusters(const PairArgs *
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = items[it];
         const PairArgs a = table[item.x];
+        // (a system without cluster lists sums as it does alone: k_pair)
         if (item.y < a.n_clusters)
             cluster_tile(a, item.y, s_dyn, s_cnt, red, s_f);
+        else if (a.n_clusters == 0 && a.paired)
+            pair_tile<false, false, true>(a, item.y, s_cnt, red, s_f);
         else
             pair_tile(a, item.y, s_cnt, red, s_f);
         __syncthreads();
@@ -1481,13 +1535,15 @@ void launch_finalize_batch(const FusedArgs *table, const int *nparts, int n_sys,
 }
 
 void launch_pair_batch(const PairArgs *table, const int2 *items, int n_items, int grid,
-                       bool clusters, hipStream_t s)
+                       bool clusters, bool paired, hipStream_t s)
 {
     if (clusters)
         hipLaunchKernelGGL(k_pair_batch_clusters, dim3(grid), dim3(kBlock), kClusterSmem, s, table,
                            items, n_items);
+    else if (paired)
+        hipLaunchKernelGGL(k_pair_batch<true>, dim3(n_items), dim3(kBlock), 0, s, table, items, n_items);
     else
-        hipLaunchKernelGGL(k_pair_batch, dim3(n_items), dim3(kBlock), 0, s, table, items, n_items);
+        hipLaunchKernelGGL(k_pair_batch<false>, dim3(n_items), dim3(kBlock), 0, s, table, items, n_items);
 }
 
 void set_batch_smem(int smem_bytes)
@@ -1507,6 +1563,7 @@ void set_pair_smem()
 
 // The force pass of a system under a barostat (per-atom lists; cells binned
 // in the moving box).
+template <bool PAIRED>
 __global__ __launch_bounds__(kBlock) void k_pair_npt(PairArgs a)
 {
     __shared__ int s_cnt[kBlock];
@@ -1515,22 +1572,27 @@ __global__ __launch_bounds__(kBlock) void k_pair_npt(PairArgs a)
     const int b = blockIdx.x, nA = a.n_active_tiles;
     const int tile = (b < nA) ? xcd_tile(b, nA) : nA + xcd_tile(b - nA, gridDim.x - nA);
     if (a.fdiag)
-        pair_tile<true, true>(a, tile, s_cnt, red, s_f);
+        pair_tile<true, true, PAIRED>(a, tile, s_cnt, red, s_f);
     else
-        pair_tile<true, false>(a, tile, s_cnt, red, s_f);
+        pair_tile<true, false, PAIRED>(a, tile, s_cnt, red, s_f);
 }
 
 void launch_pair_npt(const PairArgs &a, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pair_npt, dim3(grid), dim3(kBlock), 0, s, a);
+    if (a.paired)
+        hipLaunchKernelGGL(k_pair_npt<true>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_pair_npt<false>, dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 void launch_pair(const PairArgs &a, int grid, hipStream_t s)
 {
     if (a.n_clusters)
         hipLaunchKernelGGL(k_pair_clusters, dim3(grid), dim3(kBlock), kClusterSmem, s, a);
+    else if (a.paired)
+        hipLaunchKernelGGL(k_pair<true>, dim3(grid), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_pair, dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_pair<false>, dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 // --------------------------------------------------------------------------
