@@ -416,10 +416,12 @@ def pair_roofline(workload, spec, x, avgs):
     npairs = pairs_inside_cutoff(x, spec.box, spec.lj_rc, spec.lj_active)
     flops = LJ_FLOPS_PER_PAIR * npairs
     ach = flops / (avgs["pair"][0] * 1e-3) / 1e12
-    return {"kernel": "k_pair", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+    # even P: the instantiation whose lanes take bead pairs
+    kname = "k_pair<true>" if spec.n_beads % 2 == 0 else "k_pair<false>"
+    return {"kernel": kname, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
             "traffic": profiled_traffic(PROFILE_FILES.get((workload, "k_pair"), ""),
-                                        "pimd::k_pair("),
+                                        _counter_name(kname)),
             "work_per_launch": "%d ordered bead pairs inside rc x %d flops" % (npairs, LJ_FLOPS_PER_PAIR),
             "launch_us": avgs["pair"][0] * 1e3}
 
