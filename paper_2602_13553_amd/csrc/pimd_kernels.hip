@@ -1095,8 +1095,10 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
             // keeps it under 2 GiB)
             const __amdgpu_buffer_rsrc_t xr =
                 __builtin_amdgcn_make_buffer_rsrc((void *)X, (short)0, (int)x_bytes, kBufferRsrcWord3);
-            const unsigned kx = (unsigned)(2 * kp) * 8u, ky = kx + (unsigned)P * 8u,
-                           kz = ky + (unsigned)P * 8u;
+            // (the lane's bead offset in the vector offset, the dim's row
+            // offset in the scalar one)
+            const unsigned kx = (unsigned)(2 * kp) * 8u;
+            const int ry = __builtin_amdgcn_readfirstlane(P * 8), rz = 2 * ry;
             // (the image shift costs vector work only where it is not zero)
             auto pair2 = [&](const int2 en, const dbl2 xj, const dbl2 yj, const dbl2 zj) {
                 double dx[2], dy[2], dz[2];
@@ -1118,10 +1120,10 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
                                         pf[3 * b2 + 1], pf[3 * b2 + 2], s12, s6, np, wd);
             };
             auto rows = [&](const int2 en, dbl2 &xj, dbl2 &yj, dbl2 &zj) {
-                const unsigned jo = (unsigned)en.x * 8u;
-                xj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, jo + kx, 0, 0));
-                yj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, jo + ky, 0, 0));
-                zj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, jo + kz, 0, 0));
+                const unsigned vo = (unsigned)en.x * 8u + kx;
+                xj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, vo, 0, 0));
+                yj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, vo, ry, 0));
+                zj = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(xr, vo, rz, 0));
             };
             // two entries per iteration: all six gathers issued before any use
             for (q = c0 + sg2; q + S2 < qend; q += 2 * S2) {
