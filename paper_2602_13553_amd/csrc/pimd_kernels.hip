@@ -772,11 +772,13 @@ __device__ __forceinline__ void lj_accumulate(double dx, double dy, double dz, d
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2) {
-        // 1/r2: hardware reciprocal refined by two Newton steps (a few ulp at
-        // most, far inside the FP64 parity bar) instead of the IEEE division
-        // sequence
+        // 1/r2: the hardware reciprocal (about 2^-24 relative) refined by one
+        // Newton step, instead of the IEEE division sequence.  Measured over
+        // 4e6 values in [0.5, 4096): at most 11 ulp from the correctly
+        // rounded 1/r2 (a second step makes it exact there); the pair force,
+        // a polynomial in 1/r2 of degree 7, then carries ~1e-14 relative,
+        // far inside the FP64 parity bar.
         double ir2 = __builtin_amdgcn_rcp(r2);
-        ir2 = fma(fma(-r2, ir2, 1.0), ir2, ir2);
         ir2 = fma(fma(-r2, ir2, 1.0), ir2, ir2);
         const double sr2 = sig2 * ir2;
         const double sr6 = sr2 * sr2 * sr2, sr12 = sr6 * sr6;
