@@ -21,6 +21,7 @@ reproducible, and a system in a batch matches its solo run bit for bit.
 Rebuild the library (``__graft_entry__.build()``) after writing.
 
     python -m paper_2602_13553_amd.autotune [--write] [--steps 40] [--json out.json]
+    python -m paper_2602_13553_amd.autotune --from-json out.json --write   (no GPU)
 """
 from __future__ import annotations
 
@@ -161,8 +162,13 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--write", action="store_true", help="rewrite csrc/pimd_tuning.h")
     ap.add_argument("--json", help="also save the raw timings here")
+    ap.add_argument("--from-json", help="take the timings from a saved sweep instead of the GPU")
     args = ap.parse_args(argv)
-    res = sweep(args.steps, args.warmup, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if args.from_json:
+        with open(args.from_json) as f:
+            res = json.load(f)
+    else:
+        res = sweep(args.steps, args.warmup, log=lambda m: print(m, file=sys.stderr, flush=True))
     mfma_min, table = choose(res)
     print(summary_text(res, mfma_min, table), flush=True)
     if args.json:

@@ -2,7 +2,7 @@
 // from kernel timings on the GPU; regenerate with
 //   python -m paper_2602_13553_amd.autotune --write
 // (the sweep, its workloads and the raw timings are described there).
-// Measured on AMD Radeon Graphics (gfx950:sramecc+:xnack-), 2026-12-02, 40 timed steps per point.
+// Measured on AMD Radeon Graphics (gfx950:sramecc+:xnack-), 2026-12-03, 40 timed steps per point.
 #pragma once
 
 namespace pimd {
@@ -10,14 +10,14 @@ namespace tuning {
 
 // Smallest N*P from which the matrix-core step pass is faster than the
 // vector-ALU one, for P = 16, 32, 64.
-constexpr long long kMfmaMinBeadAtoms[3] = {524288LL, 262144LL, 262144LL};
+constexpr long long kMfmaMinBeadAtoms[3] = {262144LL, 262144LL, 131072LL};
 
 // Force-pass lane sub-groups per atom for P = 8, 16, 32, 64 (rows) and N in
 // [2^6, 2^7), [2^7, 2^8), ..., [2^15, 2^16) (columns; clamped at both ends).
 // 0: the occupancy heuristic decides.
 constexpr int kPairSubgroups[4][10] = {
-    {16, 16, 16, 16, 16, 8, 4, 4, 2, 2},
-    {16, 16, 16, 16, 16, 8, 4, 2, 1, 1},
+    {16, 16, 16, 16, 16, 8, 4, 4, 2, 1},
+    {16, 8, 16, 8, 8, 4, 4, 2, 1, 1},
     {8, 8, 8, 8, 8, 4, 2, 1, 1, 1},
     {4, 4, 4, 4, 4, 2, 1, 1, 1, 1},
 };
