@@ -1071,7 +1071,8 @@ __device__ void pair_tile(const PairArgs &a, int tile, int *s_cnt, double *red, 
     }
     // The block's list entries pass through LDS, up to C = kPairStage/A per
     // atom at a time, in one coalesced copy: the loop then waits only on the
-    // bead-row gathers.  Entry q still goes to sub-group q mod S, in order.
+    // bead-row gathers.  Entry q still goes to sub-group q mod S (q mod 2S
+    // with bead pairs), in order.
     __shared__ int2 s_lst[kPairStage];
     if (g == 0) s_cnt[la] = cnt;
     __syncthreads();
