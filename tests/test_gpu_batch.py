@@ -23,6 +23,7 @@ def mixed_specs():
         inputs.water(n_atoms=192, n_beads=8, seed=5),                    # bonds + masked LJ
         inputs.lj_liquid(n_atoms=171, n_beads=6, seed=6),                # ragged P
         inputs.harmonic_tiny(n_atoms=20, n_beads=64, seed=7),            # MFMA P=64 trap
+        inputs.lj_liquid(n_atoms=108, n_beads=5, seed=8),                # odd P: one bead per lane
     ]
 
 
