@@ -439,7 +439,9 @@ int pimd_profile_end(pimd_ctx *ctx, pimd_profile *out);
  * of the step pass; pair_subgroups, pair_blocks: lane sub-groups per atom and
  * blocks of the force pass (0 without pair forces); cells: centroid cells of
  * the list build (0 = all-pairs scan); cluster_pairs: 1 when the force pass
- * runs on cluster lists.  Errors: ARG. */
+ * runs on cluster lists; bead_pairs: 1 when its lanes take two consecutive
+ * beads each (even P, per-atom lists; the pair_subgroups sub-groups of P
+ * lanes then work as twice as many of P/2 lanes).  Errors: ARG. */
 typedef struct pimd_launch_info {
     int32_t transforms;
     int32_t fused_blocks;
@@ -447,6 +449,7 @@ typedef struct pimd_launch_info {
     int32_t pair_blocks;
     int32_t cells;
     int32_t cluster_pairs;
+    int32_t bead_pairs;
 } pimd_launch_info;
 int pimd_get_launch_info(const pimd_ctx *ctx, pimd_launch_info *out);
 

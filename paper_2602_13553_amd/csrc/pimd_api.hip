@@ -985,6 +985,7 @@ int pimd_get_launch_info(const pimd_ctx *c, pimd_launch_info *out)
     out->pair_blocks = L.pair_grid;
     out->cells = L.ncell;
     out->cluster_pairs = L.n_clusters > 0 ? 1 : 0;
+    out->bead_pairs = (L.pair_grid > 0 && L.n_clusters == 0 && c->pa.paired) ? 1 : 0;
     return PIMD_OK;
 }
 

@@ -90,7 +90,7 @@ class pimd_profile(C.Structure):
 class pimd_launch_info(C.Structure):
     _fields_ = [("transforms", C.c_int32), ("fused_blocks", C.c_int32),
                 ("pair_subgroups", C.c_int32), ("pair_blocks", C.c_int32), ("cells", C.c_int32),
-                ("cluster_pairs", C.c_int32)]
+                ("cluster_pairs", C.c_int32), ("bead_pairs", C.c_int32)]
 
 
 _lib = None

@@ -193,12 +193,12 @@ def test_water_full_size_p64():
 @pytest.mark.parametrize("kind,N,P", [("lj", 257, 64), ("lj_images", 64, 64), ("water", 387, 64),
                                       ("lj", 130, 128)])
 def test_pair_one_group_per_atom(kind, N, P):
-    """The force pass with one lane group per atom and P a multiple of 64:
-    every lane of a wave takes the same list entry (entries read as scalars,
-    gathers as buffer loads, the image shift applied only where it is not
-    zero).  A ragged last tile, a box under 2 rc (every pair through images,
-    entries with several shifts), water's bonds, and P = 128 (two waves per
-    atom)."""
+    """The force pass with one lane group per atom (S = 1) at P = 64 and 128:
+    the lanes take bead pairs, in two sub-groups per atom of half a wave
+    (P = 64) or a whole wave (P = 128), with 16-byte gathers and the image
+    shift applied only where it is not zero.  A ragged last tile, a box under
+    2 rc (every pair through images, entries with several shifts), water's
+    bonds."""
     pimd = _pimd()
     if kind == "water":
         spec = inputs.water(n_atoms=N, n_beads=P, seed=N)
@@ -207,6 +207,28 @@ def test_pair_one_group_per_atom(kind, N, P):
         if kind == "lj_images":
             assert spec.box[0] < 2 * spec.lj_rc
     g, o = run_pair(spec, 6, chunks=[2, 4], flags=pimd.PIMD_PAIR_SUBGROUPS(1))
+    check_states(g, o)
+
+
+@pytest.mark.parametrize("kind,N,P,S", [("lj", 257, 32, 4), ("lj", 130, 16, 8), ("water", 387, 8, 2),
+                                        ("lj", 131, 7, 4), ("lj", 100, 33, 2), ("water", 99, 5, 1)])
+def test_pair_lane_layouts(kind, N, P, S):
+    """Both lane layouts of the force pass at several sub-group counts: bead
+    pairs for even P (2S sub-groups of P/2 lanes, summed per bead in
+    sub-group order) and one bead per lane for odd P, with ragged last tiles
+    and water's bonds; the context reports which one it runs."""
+    pimd = _pimd()
+    if kind == "water":
+        spec = inputs.water(n_atoms=N, n_beads=P, seed=N)
+    else:
+        spec = inputs.lj_liquid(n_atoms=N, n_beads=P, seed=N)
+    flags = pimd.PIMD_PAIR_SUBGROUPS(S)
+    ctx = pimd.Context.from_spec(spec, flags=flags)
+    info = ctx.launch_info()
+    ctx.close()
+    assert info["pair_subgroups"] == S
+    assert info["bead_pairs"] == (1 if P % 2 == 0 else 0)
+    g, o = run_pair(spec, 6, chunks=[2, 4], flags=flags)
     check_states(g, o)
 
 
