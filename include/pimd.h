@@ -457,7 +457,8 @@ int pimd_get_launch_info(const pimd_ctx *ctx, pimd_launch_info *out);
  * Many independent systems (each with its own N, P, T, potential, seed, ...)
  * advanced together: one step of the whole batch is a fixed handful of
  * launches (the fused pass per bead-count group, one finalize pass with a
- * block per system, one force pass), whatever the number of systems, and
+ * block per system, the force pass for the systems with even and with odd
+ * P), whatever the number of systems, and
  * chunks of steps are captured in a hipGraph.  Every system behaves exactly
  * as a pimd_ctx with the same parameters (same kernels, same noise stream);
  * its arithmetic does not depend on the other systems in the batch.
