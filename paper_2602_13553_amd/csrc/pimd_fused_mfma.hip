@@ -53,6 +53,18 @@ namespace {
 
 constexpr int kWaves = kBlock / 64;
 
+// Wave priority around the phases whose instructions should win issue
+// arbitration: the tile copies (3, so that the next tile's bytes are requested
+// as early as possible) and the matrix-core loops (2, so that the long MFMA
+// chains start while the other block's waves fill the vector ALUs); 0 for the
+// rest.  Measured on the water P = 64 state: 93.0 -> 89.8 us per launch.
+__device__ __forceinline__ void prio(int p)
+{
+    if (p == 3) __builtin_amdgcn_s_setprio(3);
+    else if (p == 2) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 __device__ __forceinline__ d4 mfma4(double a, double b, d4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -310,7 +322,7 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
         }
     }
     dma_barrier();
-    if (has_next) dma_tile<P>(a.yt + (size_t)nb0 * 3 * P, sYn, nnat, w, l);
+    if (has_next) { prio(3); dma_tile<P>(a.yt + (size_t)nb0 * 3 * P, sYn, nnat, w, l); prio(0); }
 
     // ---- forward products: f~ of mode block mb for the tile's 16 atoms
     // (the positions' modes are carried from the previous step)
@@ -327,6 +339,7 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
         // accumulator rows that are never used.
         const MRow<P> mr(fm);
         const int q0 = (fm * fq) & (P - 1), dq = (4 * fm) & (P - 1);
+        prio(2);
 #pragma unroll 4
         for (int kb = 0; kb < NK4; ++kb) {
             const int cj = swc<P>(fs, 4 * kb + fq);
@@ -334,9 +347,10 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
 #pragma unroll
             for (int d = 0; d < 3; ++d) af[d] = mfma4(frow[d * P + cj], bm, af[d]);
         }
+        prio(0);
     }
     lds_barrier();                    // every wave is done with the f tile
-    if (has_next && need_f) dma_tile<P>(a.f + (size_t)nb0 * 3 * P, sm.f, nnat, w, l);
+    if (has_next && need_f) { prio(3); dma_tile<P>(a.f + (size_t)nb0 * 3 * P, sm.f, nnat, w, l); prio(0); }
 
     // ---- per (atom, mode) update: lane l, register r: atom a0 + 4r + uq, mode m
     const int lu = opaque(l), uq = lu >> 4;
@@ -486,6 +500,7 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
         const int li = opaque(l), ir = li & 15, iq = li >> 4, ib = mb * 16 + ir;
         const double *irow = sY + (ra0 + ir) * L::ROW;
         const int is = (ra0 + ir) & L::SWZ;
+        prio(2);
 #pragma unroll 4
         for (int kb = 0; kb < NK4; ++kb) {
             // B operand M[mode][bead], mode 4 kb + iq: phase mode bead mod P
@@ -495,6 +510,7 @@ __device__ __forceinline__ void mfma_tile(const FusedArgs &a, const Smem<P> &sm,
 #pragma unroll
             for (int d = 0; d < 3; ++d) ax[d] = mfma4(irow[d * P + cj], bm, ax[d]);
         }
+        prio(0);
     }
     const int bead = mb * 16 + lr;
 #pragma unroll
@@ -574,8 +590,8 @@ __device__ __forceinline__ void mfma_tiles(const FusedArgs &a, int first, int st
     int rorig = 0;
     if (first < nbt) {
         const int b0 = first * 16 * T, nat = min(16 * T, N - b0);
-        dma_tile<P>(a.yt + (size_t)b0 * 3 * P, s_y0, nat, w, l);
-        if (a.pair) dma_tile<P>(a.f + (size_t)b0 * 3 * P, s_f, nat, w, l);
+        { prio(3); dma_tile<P>(a.yt + (size_t)b0 * 3 * P, s_y0, nat, w, l); prio(0); }
+        if (a.pair) { prio(3); dma_tile<P>(a.f + (size_t)b0 * 3 * P, s_f, nat, w, l); prio(0); }
         load_tile_regs<P>(a, b0, nat, tt, mb, l, t, rv, ratom, rorig);
     }
     // a system whose step budget is spent takes no step (uniform per block);
