@@ -437,6 +437,28 @@ def test_checkpoint_restart():
     assert rel_err(xc, xa) <= TOL and rel_err(pc, pa) <= 1e-11
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_noise_counter_across_the_32_bit_step_boundary(integrator):
+    """The noise counter holds the step in two 32-bit words (OBABO's second O
+    in the top bit of the upper one): a run from step 2^32 - 3 across 2^32,
+    BAOAB and OBABO, matches the oracle started at the same step."""
+    pimd = _pimd()
+    spec = inputs.lj_liquid(n_atoms=108, n_beads=8, seed=9)
+    spec.integrator = integrator
+    s0 = 2**32 - 3
+    _say("case %s integrator=%d from step %d" % (spec.name, integrator, s0))
+    ctx = pimd.Context.from_spec(spec)
+    ctx.set_state(spec.x0, spec.v0, s0)
+    ctx.step(6)
+    est = ctx.estimators()
+    gx, gp, gs = ctx.get_state()
+    ctx.close()
+    st = oracle.State.from_spec(spec, step=s0)
+    st.step(6)
+    assert gs == s0 + 6
+    check_states((gx, gp, gs, est), (st.x, st.p, int(st.step_count[0]), st.estimators(), st.sys))
+
+
 # ------------------------------------------------------------ errors
 def test_error_paths():
     pimd = _pimd()
