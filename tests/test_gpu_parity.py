@@ -211,6 +211,7 @@ def test_pair_one_group_per_atom(kind, N, P):
 
 
 @pytest.mark.parametrize("kind,N,P,S", [("lj", 257, 32, 4), ("lj", 130, 16, 8), ("water", 387, 8, 2),
+                                        ("lj", 60, 4, 16), ("lj", 50, 2, 16),
                                         ("lj", 131, 7, 4), ("lj", 100, 33, 2), ("water", 99, 5, 1)])
 def test_pair_lane_layouts(kind, N, P, S):
     """Both lane layouts of the force pass at several sub-group counts: bead
