@@ -28,24 +28,44 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles (the 'does it build' check); returns the library path."""
-    objs = []
+# The host-side debug build: the library's host code (parameter checks,
+# layouts, atom ordering, batch plans) under AddressSanitizer and
+# UndefinedBehaviorSanitizer; the device code is built as usual.  The
+# sanitizer runtime is not linked in: the process that loads the library
+# preloads clang's shared ASan runtime (which carries the UBSan handlers).
+LIB_HOST_SAN = os.path.join(HERE, "libpimd_hostsan.so")
+HOST_SAN_FLAGS = ["-Xarch_host", "-fsanitize=address,undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all",
+                  "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, host_sanitize: bool = False) -> str:
+    """Always recompiles (the 'does it build' check); returns the library path.
+    host_sanitize: build LIB_HOST_SAN instead (see HOST_SAN_FLAGS)."""
+    suffix = ".hostsan.o" if host_sanitize else ".o"
+    objs, cmds = [], []
     for s in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(s)[0] + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
-               os.path.join(CSRC, s), "-o", obj]
+        obj = os.path.join(CSRC, os.path.splitext(s)[0] + suffix)
+        cmds.append([hipcc(), *HIP_FLAGS, *(HOST_SAN_FLAGS if host_sanitize else []),
+                     "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, s), "-o", obj])
+        objs.append(obj)
+    # the translation units compile in parallel (one hipcc each)
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+        procs.append(subprocess.Popen(cmd))
+    failed = [c for c, pr in zip(cmds, procs) if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    out = LIB_HOST_SAN if host_sanitize else LIB
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":
