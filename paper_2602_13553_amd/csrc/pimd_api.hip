@@ -360,7 +360,7 @@ bool use_clusters(const pimd_params *p, int n_active)
 }
 
 // Lane sub-groups per atom in the force pass: the flags, else the tuning
-// table, else the occupancy heuristic.
+// table of the potential, else the occupancy heuristic.
 int choose_pair_subgroups(const pimd_params *p)
 {
     const int P = p->n_beads, N = p->n_atoms;
@@ -371,7 +371,8 @@ int choose_pair_subgroups(const pimd_params *p)
         int lg = 0;
         while ((2 << lg) <= N) ++lg;            // floor(log2 N)
         const int col = std::min(std::max(lg - 6, 0), 9);
-        const int S = tuning::kPairSubgroups[row][col];
+        const int S = p->potential == PIMD_POT_WATER ? tuning::kPairSubgroupsWater[row][col]
+                                                     : tuning::kPairSubgroups[row][col];
         if (S > 0 && S * P <= kBlock) return S;
     }
     return pair_subgroups(N, P);

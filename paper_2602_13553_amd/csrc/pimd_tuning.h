@@ -13,13 +13,21 @@ namespace tuning {
 constexpr long long kMfmaMinBeadAtoms[3] = {262144LL, 262144LL, 131072LL};
 
 // Force-pass lane sub-groups per atom for P = 8, 16, 32, 64 (rows) and N in
-// [2^6, 2^7), [2^7, 2^8), ..., [2^15, 2^16) (columns; clamped at both ends).
-// 0: the occupancy heuristic decides.
+// [2^6, 2^7), [2^7, 2^8), ..., [2^15, 2^16) (columns; clamped at both ends),
+// for LJ liquids.  0: the occupancy heuristic decides.
 constexpr int kPairSubgroups[4][10] = {
     {16, 16, 16, 16, 16, 8, 4, 4, 2, 1},
     {16, 8, 16, 8, 8, 4, 4, 2, 1, 1},
     {8, 8, 8, 8, 8, 4, 2, 1, 1, 1},
     {4, 4, 4, 4, 4, 2, 1, 1, 1, 1},
+};
+
+// The same for the water-shaped potential (O-O LJ plus O-H bonds).
+constexpr int kPairSubgroupsWater[4][10] = {
+    {16, 16, 16, 16, 16, 16, 16, 8, 4, 2},
+    {16, 16, 16, 16, 16, 8, 8, 4, 2, 2},
+    {8, 8, 8, 8, 8, 8, 4, 2, 2, 2},
+    {4, 4, 4, 4, 4, 4, 2, 2, 2, 1},
 };
 
 // Force pass on cluster lists (1) or per-atom lists (0), same rows and

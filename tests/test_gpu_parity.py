@@ -210,6 +210,31 @@ def test_pair_one_group_per_atom(kind, N, P):
     check_states(g, o)
 
 
+def _tuning_table(name):
+    import re
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "paper_2602_13553_amd", "csrc", "pimd_tuning.h")).read()
+    body = re.search(name + r"\[4\]\[10\] = \{(.*?)\};", src, re.S).group(1)
+    return [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
+
+
+def test_pair_subgroups_follow_the_tuning_table_of_the_potential():
+    """With no sub-group flag, the force pass takes its lane split from the
+    compiled table of its potential, indexed by P and floor(log2 N)."""
+    pimd = _pimd()
+    tables = {"lj": _tuning_table("kPairSubgroups"), "water": _tuning_table("kPairSubgroupsWater")}
+    for kind, N, P in (("water", 32766, 32), ("water", 32766, 64), ("water", 2049, 8),
+                       ("water", 300, 16), ("lj", 4000, 32), ("lj", 300, 16)):
+        spec = (inputs.water(n_atoms=N, n_beads=P) if kind == "water"
+                else inputs.lj_liquid(n_atoms=N, n_beads=P))
+        col = min(max(spec.n_atoms.bit_length() - 1 - 6, 0), 9)
+        want = tables[kind][(8, 16, 32, 64).index(P)][col]
+        ctx = pimd.Context.from_spec(spec)
+        info = ctx.launch_info()
+        ctx.close()
+        assert info["pair_subgroups"] == want, (kind, N, P)
+
+
 @pytest.mark.parametrize("kind,N,P,S", [("lj", 257, 32, 4), ("lj", 130, 16, 8), ("water", 387, 8, 2),
                                         ("lj", 60, 4, 16), ("lj", 50, 2, 16),
                                         ("lj", 131, 7, 4), ("lj", 100, 33, 2), ("water", 99, 5, 1)])
