@@ -232,6 +232,9 @@ def main(argv=None):
         return
     mfma_min, table, water = choose(res)
     print(summary_text(res, mfma_min, table, water), flush=True)
+    if args.write and not _rows(res, "water"):
+        # the header would give the water-shaped potential the LJ table
+        sys.exit("no water points: not writing %s (merge a water sweep with --from-json)" % HEADER)
     if args.write:
         with open(HEADER, "w") as f:
             f.write(header_text(res, mfma_min, table, water))

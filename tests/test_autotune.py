@@ -107,3 +107,26 @@ def test_committed_tables_are_within_limits():
         for P, r in zip(autotune.BEADS, rows):
             for S in r:
                 assert S in autotune.SUBGROUPS and S * P <= 256
+
+
+def test_write_needs_both_workloads(tmp_path, monkeypatch):
+    """--write from an LJ-only sweep would replace the water table with the
+    LJ one: it refuses, and the header is left alone."""
+    import json
+    import pytest
+    res = synthetic_result(lambda P, N, S: float(S), lambda P, N: (1.0, 1.0))
+    path = tmp_path / "lj.json"
+    path.write_text(json.dumps(res))
+    header = tmp_path / "pimd_tuning.h"
+    header.write_text("untouched")
+    monkeypatch.setattr(autotune, "HEADER", str(header))
+    with pytest.raises(SystemExit):
+        autotune.main(["--from-json", str(path), "--write"])
+    assert header.read_text() == "untouched"
+    water = synthetic_result(lambda P, N, S: 1.0, lambda P, N: (1.0, 1.0),
+                             water_pair_time=lambda P, N, S: 1.0 / S)
+    water["rows"] = [x for x in water["rows"] if x.get("potential") == "water"]
+    wpath = tmp_path / "water.json"
+    wpath.write_text(json.dumps(water))
+    autotune.main(["--from-json", str(path), "--from-json", str(wpath), "--write"])
+    assert "kPairSubgroupsWater[4][10]" in header.read_text()
